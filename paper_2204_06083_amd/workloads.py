@@ -1,0 +1,251 @@
+"""Seeded synthetic inputs: grids, level sets, manufactured solutions.
+
+This module only *samples* the problem data that a user of the solver would
+hand in: the node grid, the level-set function psi at the nodes (negative
+inside the domain), the source f, the Dirichlet data u_D and, for the heat
+problem, random smooth initial data.  It contains none of the method's
+arithmetic (no classification, interpolation weights, operator or solver), so
+both the CPU oracle and the GPU path may consume its arrays.
+
+Geometries follow the level-set description of Sec. 2 (the mask is the sign of
+psi) and the workloads of Sec. 3: a disk, a five-armed star, an ellipsoid and
+random perturbed stars standing in for the shape-optimisation batch of
+Sec. 3.6.  No dataset is involved anywhere; every input is analytic or drawn
+from a seeded numpy generator.
+
+The node grid puts node i of axis a at x0[a] + i*h, i = 0..n[a] (so n[a]+1
+nodes per axis; the box [-0.5, 0.5]^d with n cells per side gives h = 1/n).
+Arrays are numpy C-order with index order [z, y, x] (x fastest), i.e. the
+lexicographic numbering of Sec. 2.4.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional, Tuple
+
+import numpy as np
+
+SEED_BASE = 220406083
+
+
+@dataclass(frozen=True)
+class Grid:
+    dim: int
+    n: Tuple[int, ...]          # cells per axis, x first
+    x0: Tuple[float, ...]       # coordinate of node 0 per axis, x first
+    h: float
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        """numpy array shape of a node field, [z, y, x] order."""
+        return tuple(m + 1 for m in reversed(self.n))
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod(self.shape))
+
+    def axis_coords(self, axis: int) -> np.ndarray:
+        """Node coordinates along physical axis (0 = x, 1 = y, 2 = z)."""
+        i = np.arange(self.n[axis] + 1, dtype=np.float64)
+        return self.x0[axis] + i * self.h
+
+    def mesh(self):
+        """Coordinate arrays (X, Y[, Z]) broadcast to the node field shape."""
+        axes = [self.axis_coords(a) for a in range(self.dim)]
+        grids = np.meshgrid(*reversed(axes), indexing="ij")  # [z,y,x] order
+        return tuple(reversed(grids))                          # X, Y[, Z]
+
+
+def unit_box_grid(dim: int, n: int) -> Grid:
+    """Box [-0.5, 0.5]^dim with n cells per side, h = 1/n."""
+    return Grid(dim=dim, n=(n,) * dim, x0=(-0.5,) * dim, h=1.0 / n)
+
+
+@dataclass
+class Problem:
+    """One Poisson / shifted-Poisson problem instance."""
+    name: str
+    grid: Grid
+    psi: np.ndarray                              # node field, < 0 inside
+    f: np.ndarray                                # node field (source of -Lap u = f)
+    u_exact: Optional[Callable] = None           # u(X, Y[, Z], xp) or None
+    u_dirichlet: Optional[Callable] = None       # boundary data u_D(X, Y[, Z], xp)
+    sigma: float = 0.0                           # diagonal shift (heat: 1/dt)
+    tol: float = 1e-8
+    meta: dict = field(default_factory=dict)
+
+
+# ---------------------------------------------------------------- geometries
+
+def psi_disk(grid: Grid, center=(0.013, 0.021), radius=0.4) -> np.ndarray:
+    X, Y = grid.mesh()
+    return np.sqrt((X - center[0]) ** 2 + (Y - center[1]) ** 2) - radius
+
+
+def psi_star(grid: Grid, r0=0.3, amp=0.1, arms=5) -> np.ndarray:
+    """psi = |x| - (r0 + amp cos(arms*phi))."""
+    X, Y = grid.mesh()
+    phi = np.arctan2(Y, X)
+    return np.sqrt(X * X + Y * Y) - (r0 + amp * np.cos(arms * phi))
+
+
+def psi_ellipsoid(grid: Grid, semi=(0.4, 0.3, 0.35)) -> np.ndarray:
+    X, Y, Z = grid.mesh()
+    return (X / semi[0]) ** 2 + (Y / semi[1]) ** 2 + (Z / semi[2]) ** 2 - 1.0
+
+
+def psi_random_star(grid: Grid, c, phase, r0=0.3) -> np.ndarray:
+    """psi = |x| - (r0 + sum_m c_m cos(m phi + phase_m)), m = 2..2+len(c)-1."""
+    X, Y = grid.mesh()
+    phi = np.arctan2(Y, X)
+    r = np.full_like(X, r0)
+    for m, (cm, pm) in enumerate(zip(c, phase), start=2):
+        r = r + cm * np.cos(m * phi + pm)
+    return np.sqrt(X * X + Y * Y) - r
+
+
+def psi_halfplane_box(grid: Grid, normal, offset, half_width=0.35) -> np.ndarray:
+    """Intersection of a tilted half-plane {n.x < offset} with a centred box.
+
+    Piecewise linear: along any grid line whose two nodes straddle the tilted
+    face and lie away from the box faces, linear interpolation of psi is exact.
+    """
+    comps = grid.mesh()
+    lin = sum(nc * X for nc, X in zip(normal, comps)) - offset
+    box = np.max(np.stack([np.abs(X) for X in comps]), axis=0) - half_width
+    return np.maximum(lin, box)
+
+
+# ------------------------------------------------------ manufactured solutions
+
+def _xp_of(a):
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            return torch
+    except ImportError:  # pragma: no cover
+        pass
+    return np
+
+
+def u_disk(X, Y):
+    xp = _xp_of(X)
+    return xp.sin(2 * math.pi * X) * xp.cos(3 * math.pi * Y)
+
+
+def u_star(X, Y):
+    xp = _xp_of(X)
+    return xp.exp(X) * xp.sin(4 * math.pi * Y)
+
+
+def u_ellipsoid(X, Y, Z):
+    xp = _xp_of(X)
+    return xp.sin(math.pi * X) * xp.sin(2 * math.pi * Y) * xp.sin(3 * math.pi * Z)
+
+
+def zero_data(*coords):
+    return 0.0 * coords[0]
+
+
+def linear_field(coef):
+    """u = coef[0] + coef[1] x + coef[2] y (+ coef[3] z); -Lap u = 0."""
+    def u(*coords):
+        out = coef[0] + 0.0 * coords[0]
+        for c, X in zip(coef[1:], coords):
+            out = out + c * X
+        return out
+    return u
+
+
+# -------------------------------------------------------------- the workloads
+
+def disk_poisson(n: int = 128) -> Problem:
+    """2-D Poisson on the disk r = 0.4 centred at (0.013, 0.021); u = sin(2 pi x) cos(3 pi y)."""
+    g = unit_box_grid(2, n)
+    X, Y = g.mesh()
+    return Problem("disk2d", g, psi_disk(g), 13.0 * math.pi ** 2 * u_disk(X, Y),
+                   u_exact=u_disk, u_dirichlet=u_disk, tol=1e-10)
+
+
+def star_poisson(n: int = 2048) -> Problem:
+    """2-D Poisson on the star r = 0.3 + 0.1 cos(5 phi); u = exp(x) sin(4 pi y)."""
+    g = unit_box_grid(2, n)
+    X, Y = g.mesh()
+    return Problem("star2d", g, psi_star(g), (16.0 * math.pi ** 2 - 1.0) * u_star(X, Y),
+                   u_exact=u_star, u_dirichlet=u_star, tol=1e-8)
+
+
+def ellipsoid_poisson(n: int = 256) -> Problem:
+    """3-D Poisson on the ellipsoid (0.4, 0.3, 0.35); u = sin(pi x) sin(2 pi y) sin(3 pi z)."""
+    g = unit_box_grid(3, n)
+    X, Y, Z = g.mesh()
+    return Problem("ellipsoid3d", g, psi_ellipsoid(g),
+                   14.0 * math.pi ** 2 * u_ellipsoid(X, Y, Z),
+                   u_exact=u_ellipsoid, u_dirichlet=u_ellipsoid, tol=1e-8)
+
+
+def heat_initial(grid: Grid, rhs_id: int, kmax: int = 8) -> np.ndarray:
+    """u0 = sum_{kx,ky in 1..kmax} a_k sin(kx pi x) sin(ky pi y), a_k ~ N(0, 1/|k|^2)."""
+    rng = np.random.default_rng(SEED_BASE + rhs_id)
+    X, Y = grid.mesh()
+    u0 = np.zeros_like(X)
+    for kx in range(1, kmax + 1):
+        for ky in range(1, kmax + 1):
+            std = 1.0 / math.sqrt(kx * kx + ky * ky)
+            a = rng.normal(0.0, std)
+            u0 += a * np.sin(kx * math.pi * X) * np.sin(ky * math.pi * Y)
+    return u0
+
+
+def star_heat(n: int = 1024, rhs_id: int = 0) -> Problem:
+    """One backward-Euler heat step on the star: (A + I/dt) u1 = u0/dt, dt = h, u_D = 0."""
+    g = unit_box_grid(2, n)
+    dt = g.h
+    u0 = heat_initial(g, rhs_id)
+    return Problem("star2d_heat", g, psi_star(g), u0 / dt, u_exact=None,
+                   u_dirichlet=zero_data, sigma=1.0 / dt, tol=1e-8,
+                   meta={"dt": dt, "u0": u0, "rhs_id": rhs_id})
+
+
+def random_star_params(count: int = 256, seed: int = SEED_BASE):
+    """Parameters of the shape-optimisation batch: (N, c[5], phase[5]) per geometry."""
+    rng = np.random.default_rng(seed)
+    sizes = (256, 384, 512, 768, 1024)
+    out = []
+    while len(out) < count:
+        n = int(rng.choice(sizes))
+        c = rng.uniform(0.0, 0.04, size=5)
+        ph = rng.uniform(0.0, 2.0 * math.pi, size=5)
+        h = 1.0 / n
+        if 0.3 + c.sum() > 0.5 - 2.0 * h:      # keep the outer node layer outside
+            continue
+        out.append((n, c, ph))
+    return out
+
+
+def random_star_poisson(n: int, c, phase) -> Problem:
+    g = unit_box_grid(2, n)
+    return Problem("random_star2d", g, psi_random_star(g, c, phase),
+                   np.ones(g.shape), u_exact=None, u_dirichlet=zero_data, tol=1e-8)
+
+
+def disk_mms(n: int, center=(0.013, 0.021), radius=0.4) -> Problem:
+    """Manufactured-solution disk used for convergence sweeps (config-1 data at any n)."""
+    g = unit_box_grid(2, n)
+    X, Y = g.mesh()
+    return Problem("disk2d_mms", g, psi_disk(g, center, radius),
+                   13.0 * math.pi ** 2 * u_disk(X, Y),
+                   u_exact=u_disk, u_dirichlet=u_disk, tol=1e-10)
+
+
+def ellipsoid_mms(n: int) -> Problem:
+    return ellipsoid_poisson(n)
+
+
+WORKLOADS = {
+    "disk2d_128": lambda: disk_poisson(128),
+    "star2d_2048": lambda: star_poisson(2048),
+    "star2d_heat_1024": lambda: star_heat(1024, 0),
+    "ellipsoid3d_256": lambda: ellipsoid_poisson(256),
+}

@@ -1,0 +1,193 @@
+/*
+ * ebamg.h -- C ABI of the MI355X (gfx950) embedded-boundary AMG-PCG library.
+ *
+ * The library solves the symmetric positive definite system A u = b that the
+ * line-by-line embedded-boundary discretisation of -Laplace produces on a
+ * uniform Cartesian node grid (Peng, Appelo, Liu, "Universal AMG accelerated
+ * embedded boundary method without small cell stiffness"; Algorithm 2):
+ *
+ *   step 1  classify nodes (mask, boundary points, computational points);
+ *   steps 2-3  central differences with the Dirichlet condition imposed by
+ *           interpolating to interior boundary points along grid lines, which
+ *           changes only the diagonal and the right-hand side;
+ *   step 4  conjugate gradients preconditioned by algebraic multigrid.
+ *
+ * A = (1/h^2) (diag(a) - adjacency of computational points) + sigma I, where
+ * the dimensionless diagonal is a_k = (number of computational neighbours) +
+ * sum over boundary-point sides of 1/q, q*h being the distance from the
+ * computational point to the boundary crossing on that grid line (Sec. 2.1.1).
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - Node fields are dense (n[0]+1) x (n[1]+1) [x (n[2]+1)] arrays, x fastest
+ *     (flat index i + nx*(j + ny*k)), no padding.
+ *   - The caller owns every array it passes; the library owns only the
+ *     amg_handle_t and the memory it allocated for it.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream unless stated otherwise.
+ *   - Return 0 on success or a negative EB_E* code; eb_last_error() returns a
+ *     thread-local message for the last failure.  No exception or abort crosses
+ *     the ABI.  Outputs are unspecified after an error unless stated.
+ *   - Inside the domain means psi < 0 strictly; psi == 0 is outside.
+ *   - Everything is FP64.
+ */
+#ifndef EBAMG_H
+#define EBAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBAMG_ABI_VERSION 1
+
+enum {
+    EB_OK = 0,
+    EB_EINVAL = -1,    /* bad argument (null pointer, dim, sizes, params)        */
+    EB_EDOMAIN = -2,   /* an outermost-layer node is inside (psi < 0)             */
+    EB_ENOSPC = -3,    /* an output capacity is too small (required size is
+                          still reported where the call says so)                 */
+    EB_ENOTSPD = -4,   /* non-positive pivot / curvature: operator not SPD       */
+    EB_ENAN = -5,      /* NaN or Inf met in the solve                             */
+    EB_ENOCONV = -6,   /* maxit reached before the tolerance                      */
+    EB_EHIP = -7,      /* a HIP runtime call failed                               */
+    EB_ENOTIMPL = -8   /* feature not available                                   */
+};
+
+/* Node grid: node (i,j,k) sits at x0 + (i,j,k)*h, i = 0..n[0] etc. (host struct) */
+typedef struct {
+    int32_t dim;       /* 2 or 3                                                  */
+    int32_t n[3];      /* cells per axis; n[2] ignored when dim == 2              */
+    double x0[3];      /* coordinates of node 0; x0[2] ignored when dim == 2      */
+    double h;          /* spacing, > 0                                            */
+} eb_grid_t;
+
+/* One boundary-point side of a computational point (Sec. 2.1.1, line-by-line
+ * interpolation).  Records are sorted by (node, dir).                         */
+typedef struct {
+    int64_t node;      /* flat node index of the computational point            */
+    int32_t dir;       /* side: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z               */
+    int32_t steps;     /* j >= 2: node + j*side is the first outside node        */
+    double q;          /* crossing distance / h, in (1, j]                       */
+    double c;          /* diagonal contribution 1/q (interpolation weight g_Gamma) */
+    double xg[3];      /* crossing coordinates (xg[2] = 0 in 2-D)                 */
+} eb_cut_t;            /* 56 bytes                                               */
+
+typedef struct {
+    int32_t coarse_max;      /* solve densely once n <= coarse_max (default 256)  */
+    int32_t max_levels;      /* hierarchy depth limit (default 16)                */
+    double min_reduction;    /* stop coarsening if n_next > min_reduction * n (0.6) */
+    int32_t dense_limit;     /* refuse a dense coarsest level above this (8192)   */
+    int32_t reserved;
+} amg_params_t;
+
+typedef struct {
+    double tol;              /* stop when ||r||_2 <= tol * ||b||_2                */
+    int32_t maxit;           /* iteration limit (default 1000)                    */
+    int32_t x0_given;        /* 1: x holds the initial guess on entry; 0: x0 = 0  */
+    int32_t check_every;     /* iterations queued between convergence polls (8)   */
+    int32_t reserved;
+} pcg_params_t;
+
+typedef struct {
+    int32_t iterations;      /* products with A inside CG                         */
+    int32_t status;          /* EB_OK, EB_ENOCONV, EB_ENOTSPD or EB_ENAN          */
+    int32_t restarts;        /* restarts after true-residual drift (0 or 1)       */
+    int32_t levels;          /* hierarchy depth used                              */
+    double rel_res_recursive;/* ||r_k|| / ||b|| of the recursive residual         */
+    double rel_res_true;     /* ||b - A x|| / ||b||, recomputed at exit           */
+    double solve_ms;         /* device time of the solve (HIP events)             */
+    double reserved;
+} pcg_result_t;
+
+typedef struct amg_handle amg_handle_t;
+
+/* Per-level description returned by amg_level_info (host struct).  The device
+ * pointers stay owned by the handle and are valid until amg_free.            */
+typedef struct {
+    int64_t n;               /* unknowns on this level                           */
+    int64_t nnz_a, nnz_p, nnz_r;
+    double rho;              /* Gershgorin bound of D^-1 A (0 on the coarsest)   */
+    double omega;            /* 4 / (3 rho)                                      */
+    int32_t is_coarsest;
+    int32_t max_comp;        /* most aggregates sharing one box on this level    */
+    int32_t ext[3];          /* coordinate extents of this level                 */
+    int32_t reserved;
+    const int32_t* a_rowptr; const int32_t* a_col; const double* a_val;
+    const int32_t* p_rowptr; const int32_t* p_col; const double* p_val;
+    const int32_t* r_rowptr; const int32_t* r_col; const double* r_val;
+    const int32_t* agg;      /* aggregate (coarse unknown) of each unknown       */
+    const int32_t* coords;   /* n x 3 integer coordinates                         */
+    const double* dense_inv; /* coarsest only: n x n inverse, row-major          */
+} amg_level_info_t;
+
+/* Step 1 and the diagonal of steps 2-3 (Sec. 2 definitions; Sec. 2.1.1
+ * interpolant; crossing by linear interpolation of psi as in Sec. 3.3).
+ *   psi   [in]  node field, level set, negative inside.
+ *   kind  [out] node field int8: 0 outside, 1 boundary point, 2 computational.
+ *   a     [out] node field: a_k at computational points, 0 elsewhere.
+ *   cuts  [out] up to cuts_cap records, sorted by (node, dir); may be NULL
+ *               when cuts_cap == 0.
+ *   n_unknowns, n_cuts [host out] totals, always written on EB_OK and
+ *               EB_ENOSPC (cuts_cap < *n_cuts: records beyond cuts_cap are
+ *               not written).
+ * Synchronises `stream` to return the counts.  EB_EDOMAIN if an outermost
+ * node is inside.  When the node two steps beyond a computational point is
+ * itself inside, the grid line is followed to the first outside node and the
+ * same two-point interpolation is used (q may exceed 2).                       */
+int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double* a,
+                     eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                     int64_t* n_cuts, void* stream);
+
+/* Right-hand side of steps 2-3: b_k = f_k + sum over the cuts of k of
+ * u_at_cuts[m] * c_m / h^2 (the g_Gamma u_Gamma / h^2 term of Sec. 2.1.1),
+ * b = 0 off computational points.  f is a node field, u_at_cuts holds the
+ * Dirichlet data at each record's crossing (same order as cuts).  Deterministic
+ * (no atomics).                                                                */
+int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const double* f,
+                    const eb_cut_t* cuts, int64_t n_cuts, const double* u_at_cuts,
+                    double* b, void* stream);
+
+/* y = A x on node fields (Eq. central_difference with the diagonal above):
+ * y_k = (a_k/h^2 + sigma) x_k - (1/h^2) sum of x over computational
+ * neighbours; values of x off computational points are ignored; y = 0 there. */
+int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                  const double* x, double* y, void* stream);
+
+/* Build the aggregation AMG hierarchy of A (+ sigma I) on the device
+ * (Algorithm 2 step 4 preconditioner).  *H receives a new handle (host).
+ * p may be NULL for defaults.  Synchronises `stream` (level sizes are read
+ * back to size allocations).  All later calls on H use the stream given here
+ * unless they take their own.                                                  */
+int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+              const amg_params_t* p, amg_handle_t** H, void* stream);
+
+/* Solve A x = b by PCG with one V(1,1) cycle as preconditioner (Algorithm 2
+ * step 4).  b, x are node fields; x holds x0 on entry if p->x0_given.  On
+ * return x holds the solution at computational points and 0 elsewhere.
+ * res (host) is filled on EB_OK and on EB_ENOCONV/EB_ENOTSPD/EB_ENAN.
+ * Synchronises `stream` at return.  One handle must not be used by two
+ * streams at once.                                                            */
+int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* p,
+              pcg_result_t* res, void* stream);
+
+/* Apply one V(1,1) cycle z = M r (node fields; parity and debugging aid).     */
+int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
+
+/* Hierarchy introspection (host calls; pointers as described above).          */
+int amg_num_levels(const amg_handle_t* H);
+int amg_level_info(const amg_handle_t* H, int level, amg_level_info_t* out);
+/* Fine-level node list: node_of_unknown[k] = flat node index of unknown k.    */
+const int64_t* amg_fine_nodes(const amg_handle_t* H);
+
+void amg_free(amg_handle_t* H);
+const char* eb_strerror(int code);
+const char* eb_last_error(void);
+int eb_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBAMG_H */

@@ -1,0 +1,147 @@
+"""ctypes binding of libebamg.so (the C ABI declared in include/ebamg.h).
+
+Argument marshalling only.  Loading fails loudly if the HIP library has not
+been built: there is no CPU fallback anywhere in the product path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebamg.so")
+
+EB_OK, EB_EINVAL, EB_EDOMAIN, EB_ENOSPC, EB_ENOTSPD, EB_ENAN, EB_ENOCONV, EB_EHIP, EB_ENOTIMPL = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+
+EXPORTS = [
+    "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
+    "amg_vcycle_apply", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
+    "eb_strerror", "eb_last_error", "eb_abi_version",
+]
+
+
+class EbGrid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("x0", C.c_double * 3), ("h", C.c_double)]
+
+
+class AmgParams(C.Structure):
+    _fields_ = [("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("min_reduction", C.c_double),
+                ("dense_limit", C.c_int32), ("reserved", C.c_int32)]
+
+
+class PcgParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("x0_given", C.c_int32),
+                ("check_every", C.c_int32), ("reserved", C.c_int32)]
+
+
+class PcgResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("status", C.c_int32), ("restarts", C.c_int32),
+                ("levels", C.c_int32), ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
+                ("solve_ms", C.c_double), ("reserved", C.c_double)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_p", C.c_int64), ("nnz_r", C.c_int64),
+                ("rho", C.c_double), ("omega", C.c_double), ("is_coarsest", C.c_int32),
+                ("max_comp", C.c_int32), ("ext", C.c_int32 * 3), ("reserved", C.c_int32),
+                ("a_rowptr", C.c_void_p), ("a_col", C.c_void_p), ("a_val", C.c_void_p),
+                ("p_rowptr", C.c_void_p), ("p_col", C.c_void_p), ("p_val", C.c_void_p),
+                ("r_rowptr", C.c_void_p), ("r_col", C.c_void_p), ("r_val", C.c_void_p),
+                ("agg", C.c_void_p), ("coords", C.c_void_p), ("dense_inv", C.c_void_p)]
+
+
+CUT_DTYPE = np.dtype([("node", "<i8"), ("dir", "<i4"), ("steps", "<i4"), ("q", "<f8"),
+                      ("c", "<f8"), ("xg", "<f8", (3,))])
+assert CUT_DTYPE.itemsize == 56
+
+
+class EbError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__(f"{where}: error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libebamg.so (once); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2204_06083_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.eb_assemble_diag.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
+    L.eb_assemble_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, vp, vp]
+    L.stencil_apply.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, vp, vp, vp]
+    L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
+    L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
+    L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]
+    L.amg_num_levels.argtypes = [vp]
+    L.amg_level_info.argtypes = [vp, C.c_int, C.POINTER(LevelInfo)]
+    L.amg_fine_nodes.argtypes = [vp]
+    L.amg_fine_nodes.restype = vp
+    L.amg_free.argtypes = [vp]
+    L.amg_free.restype = None
+    L.eb_strerror.argtypes = [C.c_int]
+    L.eb_strerror.restype = C.c_char_p
+    L.eb_last_error.restype = C.c_char_p
+    for name in ("eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
+                 "amg_vcycle_apply", "amg_num_levels", "amg_level_info", "eb_abi_version"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def check(code, where, ok=(EB_OK,)):
+    if code not in ok:
+        L = lib()
+        raise EbError(code, where, L.eb_last_error().decode() or L.eb_strerror(code).decode())
+    return code
+
+
+def make_grid(grid) -> EbGrid:
+    """EbGrid from a workloads.Grid-like object (dim, n, x0, h)."""
+    g = EbGrid()
+    g.dim = int(grid.dim)
+    for a in range(3):
+        g.n[a] = int(grid.n[a]) if a < grid.dim else 0
+        g.x0[a] = float(grid.x0[a]) if a < grid.dim else 0.0
+    g.h = float(grid.h)
+    return g
+
+
+_hip = None
+
+
+def hip_runtime():
+    """libamdhip64 for raw device copies of library-owned arrays."""
+    global _hip
+    if _hip is None:
+        for name in ("libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"):
+            try:
+                _hip = C.CDLL(name)
+                break
+            except OSError:
+                continue
+        if _hip is None:
+            raise RuntimeError("libamdhip64.so not found")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip
+
+
+def copy_device_to_host(ptr: int, nbytes: int, out: np.ndarray):
+    """Blocking copy of nbytes from a device pointer into a host numpy array."""
+    if nbytes == 0:
+        return out
+    assert out.nbytes >= nbytes
+    rc = hip_runtime().hipMemcpy(out.ctypes.data, C.c_void_p(ptr), nbytes, 4)  # hipMemcpyDefault
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed with {rc}")
+    return out

@@ -1,0 +1,1017 @@
+// Aggregation AMG setup on the device.
+//
+// Level l -> l+1 (every unknown carries integer grid coordinates; the fine
+// level uses node indices, a coarse unknown the box it was formed in):
+//   aggregates   connected components, in the graph of A_l, of the unknowns of
+//                one 3^d coordinate box; coarse order = (box lexicographic,
+//                smallest member), which is the order a prefix sum over the
+//                box grid produces when each box numbers its components by
+//                smallest member;
+//   rho          max_i sum_j |a_ij| / a_ii (Gershgorin), omega = 4 / (3 rho);
+//   P            (I - omega D^-1 A) P_tent with the structural pattern;
+//   R            P^T;
+//   A_{l+1}      R (A P), structural patterns, sorted columns.
+// Coarsest level: dense Cholesky factorisation and the explicit inverse, so
+// the solve phase applies it as one matrix-vector product.
+//
+// Every edge of A_l joins unknowns whose coordinates differ by at most one
+// per axis (true for the stencil; kept by the Galerkin product because boxes
+// are 3 wide), so every row of P, A P and A_{l+1} has its columns in the 3^d
+// boxes around one centre box.  The products therefore accumulate into a
+// small dense slot array per row (slot = neighbour box x rank within box),
+// visited in slot order, which is ascending column order.  No floating-point
+// atomics: accumulation order per entry is ascending k, then ascending j.
+//
+// Built with -ffp-contract=off so that separately rounded products and sums
+// follow the order stated above.
+#include <math.h>
+#include <string.h>
+
+#include "handle.hpp"
+
+namespace eb {
+
+__device__ inline int box_of(int c) { return c / 3; }
+
+__device__ inline int64_t box_lin(int bx, int by, int bz, const int* nb) {
+    return (int64_t)bx + (int64_t)nb[0] * ((int64_t)by + (int64_t)nb[1] * bz);
+}
+
+struct NB3 {
+    int v[3];
+};
+
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill_i8(int8_t* p, int64_t n, int8_t v) {
+    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill_f64(double* p, int64_t n, double v) {
+    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------ fine level CSR
+__global__ void __launch_bounds__(BLOCK) k_fine_flags(const int8_t* __restrict__ kind, GridDims d, int64_t nn,
+                                                      int32_t* __restrict__ flag, int32_t* __restrict__ err) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nn) return;
+    int f = kind[n] == 2;
+    if (f) {
+        const int i = (int)(n % d.nx);
+        const int64_t r = n / d.nx;
+        const int j = (int)(r % d.ny);
+        const int k = (int)(r / d.ny);
+        const bool edge = i == 0 || i == d.nx - 1 || j == 0 || j == d.ny - 1 ||
+                          (d.dim == 3 && (k == 0 || k == d.nz - 1));
+        if (edge) {
+            atomicOr(err, DEVERR_DOMAIN);
+            f = 0;
+        }
+    }
+    flag[n] = f;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fine_rows(const int8_t* __restrict__ kind, GridDims d, int64_t nn,
+                                                     const int32_t* __restrict__ flag,
+                                                     const int32_t* __restrict__ unk_off,
+                                                     int32_t* __restrict__ rowcnt, int64_t* __restrict__ fine_nodes,
+                                                     int32_t* __restrict__ coords) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nn || !flag[n]) return;
+    const int32_t k = unk_off[n];
+    fine_nodes[k] = n;
+    const int i = (int)(n % d.nx);
+    const int64_t r = n / d.nx;
+    coords[3 * (int64_t)k + 0] = i;
+    coords[3 * (int64_t)k + 1] = (int)(r % d.ny);
+    coords[3 * (int64_t)k + 2] = (int)(r / d.ny);
+    int c = 1;
+    c += kind[n - 1] == 2;
+    c += kind[n + 1] == 2;
+    c += kind[n - d.sy] == 2;
+    c += kind[n + d.sy] == 2;
+    if (d.dim == 3) {
+        c += kind[n - d.sz] == 2;
+        c += kind[n + d.sz] == 2;
+    }
+    rowcnt[k] = c;
+}
+
+// Row k in ascending column order: -z, -y, -x, self, +x, +y, +z.
+__global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ kind, const double* __restrict__ a,
+                                                     double sigma, GridDims d, int64_t nunk,
+                                                     const int64_t* __restrict__ fine_nodes,
+                                                     const int32_t* __restrict__ unk_off,
+                                                     const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                     double* __restrict__ val, double* __restrict__ diag) {
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= nunk) return;
+    const int64_t n = fine_nodes[k];
+    int32_t pos = rowptr[k];
+    const double off = -d.s;
+    int64_t nbrs[7];
+    int cnt = 0;
+    if (d.dim == 3) nbrs[cnt++] = n - d.sz;
+    nbrs[cnt++] = n - d.sy;
+    nbrs[cnt++] = n - 1;
+    const int self = cnt;
+    nbrs[cnt++] = n;
+    nbrs[cnt++] = n + 1;
+    nbrs[cnt++] = n + d.sy;
+    if (d.dim == 3) nbrs[cnt++] = n + d.sz;
+    for (int e = 0; e < cnt; ++e) {
+        if (e == self) {
+            const double dg = a[n] * d.s + sigma;
+            col[pos] = (int32_t)k;
+            val[pos] = dg;
+            diag[k] = dg;
+            ++pos;
+        } else if (kind[nbrs[e]] == 2) {
+            col[pos] = unk_off[nbrs[e]];
+            val[pos] = off;
+            ++pos;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- aggregation
+__global__ void __launch_bounds__(BLOCK) k_box_count(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
+                                                     int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
+    atomicAdd(&cnt[b], 1);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_box_fill(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
+                                                    const int32_t* __restrict__ boff, int32_t* __restrict__ fillpos,
+                                                    int32_t* __restrict__ members) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
+    const int32_t slot = atomicAdd(&fillpos[b], 1);
+    members[boff[b] + slot] = (int32_t)i;
+}
+
+constexpr int MAX_BOX_MEMBERS = 128;
+
+__device__ inline int uf_find(int* parent, int x) {
+    while (parent[x] != x) x = parent[x];
+    return x;
+}
+
+// One thread per box: sort the members, union-find over the edges of A that
+// stay inside the box (the root of a set is always its smallest local index,
+// hence its smallest member), number the components by smallest member.
+__global__ void __launch_bounds__(64) k_box_components(const int32_t* __restrict__ boff,
+                                                       const int32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ members,
+                                                       const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ coords, NB3 nb, int64_t nboxes,
+                                                       int32_t* __restrict__ lrank, int32_t* __restrict__ ncomp,
+                                                       int32_t* __restrict__ err) {
+    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (b >= nboxes) return;
+    const int m = cnt[b];
+    if (m == 0) {
+        ncomp[b] = 0;
+        return;
+    }
+    if (m > MAX_BOX_MEMBERS) {
+        atomicOr(err, DEVERR_CAP);
+        ncomp[b] = 0;
+        return;
+    }
+    int mem[MAX_BOX_MEMBERS];
+    int parent[MAX_BOX_MEMBERS];
+    const int32_t base = boff[b];
+    for (int t = 0; t < m; ++t) {
+        const int v = members[base + t];
+        int u = t;
+        while (u > 0 && mem[u - 1] > v) {
+            mem[u] = mem[u - 1];
+            --u;
+        }
+        mem[u] = v;
+        parent[t] = t;
+    }
+    for (int li = 0; li < m; ++li) {
+        const int i = mem[li];
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int j = col[e];
+            if (j == i) continue;
+            const int64_t bj = box_lin(box_of(coords[3 * (int64_t)j]), box_of(coords[3 * (int64_t)j + 1]),
+                                       box_of(coords[3 * (int64_t)j + 2]), nb.v);
+            if (bj != b) continue;
+            int lo = 0, hi = m - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (mem[mid] < j) lo = mid + 1; else hi = mid;
+            }
+            const int ra = uf_find(parent, li);
+            const int rb = uf_find(parent, lo);
+            if (ra != rb) {
+                if (ra < rb) parent[rb] = ra; else parent[ra] = rb;
+            }
+        }
+    }
+    // roots in ascending local order get ranks 0, 1, ...; reuse `parent` for the
+    // rank of roots after resolving every member's root into `mem`'s partner.
+    int nc = 0;
+    for (int li = 0; li < m; ++li) {
+        const int rt = uf_find(parent, li);
+        if (rt == li) ++nc;
+    }
+    // second pass: rank of each root = number of roots before it
+    for (int li = 0; li < m; ++li) {
+        const int rt = uf_find(parent, li);
+        int rank = 0;
+        for (int t = 0; t < rt; ++t) rank += (uf_find(parent, t) == t);
+        lrank[mem[li]] = rank;
+    }
+    ncomp[b] = nc;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_assign_agg(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
+                                                      const int32_t* __restrict__ cstart,
+                                                      const int32_t* __restrict__ lrank, int32_t* __restrict__ agg) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
+    agg[i] = cstart[b] + lrank[i];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_coarse_coords(const int32_t* __restrict__ ncomp,
+                                                         const int32_t* __restrict__ cstart, NB3 nb, int64_t nboxes,
+                                                         int32_t* __restrict__ ccoords, int32_t* __restrict__ crank) {
+    const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (b >= nboxes) return;
+    const int m = ncomp[b];
+    if (m == 0) return;
+    const int bx = (int)(b % nb.v[0]);
+    const int64_t r = b / nb.v[0];
+    const int by = (int)(r % nb.v[1]);
+    const int bz = (int)(r / nb.v[1]);
+    const int32_t c0 = cstart[b];
+    for (int t = 0; t < m; ++t) {
+        ccoords[3 * (int64_t)(c0 + t) + 0] = bx;
+        ccoords[3 * (int64_t)(c0 + t) + 1] = by;
+        ccoords[3 * (int64_t)(c0 + t) + 2] = bz;
+        crank[c0 + t] = t;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_max_i32(const int32_t* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
+    __shared__ int32_t lds[BLOCK];
+    int32_t m = 0;
+    for (int64_t i = threadIdx.x; i < n; i += BLOCK) m = max(m, v[i]);
+    lds[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) lds[threadIdx.x] = max(lds[threadIdx.x], lds[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+// ----------------------------------------------------------------- Gershgorin
+__global__ void __launch_bounds__(BLOCK) k_gershgorin_rows(const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ diag, int64_t n,
+                                                           double* __restrict__ rowv) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s = s + fabs(val[e]);
+    rowv[i] = s / diag[i];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_max_f64(const double* __restrict__ v, int64_t n, double* __restrict__ out,
+                                                   int32_t* __restrict__ err) {
+    __shared__ double lds[BLOCK];
+    double m = 0.0;
+    bool bad = false;
+    for (int64_t i = threadIdx.x; i < n; i += BLOCK) {
+        const double x = v[i];
+        if (!(x > 0.0) || isinf(x)) bad = true;   // a_ii <= 0 or NaN/Inf
+        m = fmax(m, x);
+    }
+    lds[threadIdx.x] = m;
+    if (bad) atomicOr(err, DEVERR_NOTSPD);
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+// ------------------------------------------------------- slot accumulators
+// Slot of coarse unknown J relative to centre box (bx, by, bz): neighbour box
+// offset in {-1,0,1}^d (lexicographic, x fastest) times maxc, plus the rank of
+// J within its box.  Ascending slot = ascending J.
+struct SlotMap {
+    int dim;
+    int maxc;
+    int nslots;
+    const int32_t* ccoords;   // coarse coordinates (3 per coarse unknown)
+    const int32_t* crank;     // rank within box
+    const int32_t* cstart;    // first coarse unknown of each box
+    NB3 nb;                   // box grid of the fine level = coarse extents
+
+    __device__ int slot(int32_t J, int bx, int by, int bz) const {
+        const int ox = ccoords[3 * (int64_t)J] - bx + 1;
+        const int oy = ccoords[3 * (int64_t)J + 1] - by + 1;
+        const int oz = dim == 3 ? ccoords[3 * (int64_t)J + 2] - bz + 1 : 1;
+        const int r = crank[J];
+        if (ox < 0 || ox > 2 || oy < 0 || oy > 2 || oz < 0 || oz > 2 || r >= maxc) return -1;
+        const int o = dim == 3 ? (oz * 3 + oy) * 3 + ox : oy * 3 + ox;
+        return o * maxc + r;
+    }
+    __device__ int32_t column(int s, int bx, int by, int bz) const {
+        const int o = s / maxc;
+        const int r = s - o * maxc;
+        const int ox = o % 3;
+        const int oy = (o / 3) % 3;
+        const int oz = dim == 3 ? o / 9 : 1;
+        const int64_t b = box_lin(bx + ox - 1, by + oy - 1, bz + oz - 1, nb.v);
+        return cstart[b] + r;
+    }
+};
+
+// LDS layout for NT threads with ns slots each: vals[s * NT + t], flags[s * NT + t].
+struct SlotLds {
+    double* vals;
+    uint8_t* flags;
+    int nt;
+    __device__ void init(char* smem, int ns, int nt_) {
+        nt = nt_;
+        vals = reinterpret_cast<double*>(smem);
+        flags = reinterpret_cast<uint8_t*>(smem + sizeof(double) * (size_t)ns * nt_);
+    }
+};
+
+enum { ACC_P = 0, ACC_AP = 1, ACC_RAP = 2 };
+
+struct AccArgs {
+    SlotMap sm;
+    int64_t nrows;
+    // centre coordinates per row: level-l coordinates (P, AP: centre = coords / 3)
+    // or coarse coordinates (RAP: centre = ccoords)
+    const int32_t* row_coords;
+    int centre_div;           // 3 for P/AP rows, 1 for RAP rows
+    // first operand (rows): A_l for P/AP, R for RAP
+    const int32_t* x_rowptr; const int32_t* x_col; const double* x_val;
+    // second operand: P (for AP) or AP (for RAP); for ACC_P the agg map
+    const int32_t* y_rowptr; const int32_t* y_col; const double* y_val;
+    const int32_t* agg;       // ACC_P only
+    const double* diag;       // ACC_P only
+    double omega;             // ACC_P only
+    int32_t* out_cnt;         // count pass
+    const int32_t* out_rowptr;// fill pass
+    int32_t* out_col;
+    double* out_val;
+    int32_t* err;
+};
+
+template <int MODE, bool FILL>
+__global__ void k_accumulate(AccArgs A) {
+    extern __shared__ char smem[];
+    SlotLds L;
+    const int ns = A.sm.nslots;
+    const int nt = blockDim.x;
+    L.init(smem, ns, nt);
+    const int t = threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.x * nt + t;
+    if (row >= A.nrows) return;
+    for (int s = 0; s < ns; ++s) {
+        L.flags[s * nt + t] = 0;
+        if (FILL) L.vals[s * nt + t] = 0.0;
+    }
+    const int bx = A.row_coords[3 * row] / A.centre_div;
+    const int by = A.row_coords[3 * row + 1] / A.centre_div;
+    const int bz = A.row_coords[3 * row + 2] / A.centre_div;
+    bool bad = false;
+    if (MODE == ACC_P) {
+        const double dii = A.diag[row];
+        const int s0 = A.sm.slot(A.agg[row], bx, by, bz);
+        if (s0 < 0) {
+            bad = true;
+        } else {
+            L.flags[s0 * nt + t] = 1;
+            if (FILL) L.vals[s0 * nt + t] = 1.0;
+        }
+        for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
+            const int j = A.x_col[e];
+            const int s = A.sm.slot(A.agg[j], bx, by, bz);
+            if (s < 0) { bad = true; continue; }
+            L.flags[s * nt + t] = 1;
+            if (FILL) {
+                const double w = A.omega * (A.x_val[e] / dii);
+                L.vals[s * nt + t] = L.vals[s * nt + t] - w;
+            }
+        }
+    } else {
+        for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
+            const int k = A.x_col[e];
+            const double xv = FILL ? A.x_val[e] : 0.0;
+            for (int f = A.y_rowptr[k]; f < A.y_rowptr[k + 1]; ++f) {
+                const int s = A.sm.slot(A.y_col[f], bx, by, bz);
+                if (s < 0) { bad = true; continue; }
+                L.flags[s * nt + t] = 1;
+                if (FILL) {
+                    const double pr = xv * A.y_val[f];
+                    L.vals[s * nt + t] = L.vals[s * nt + t] + pr;
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(A.err, DEVERR_CAP);
+    if (!FILL) {
+        int c = 0;
+        for (int s = 0; s < ns; ++s) c += L.flags[s * nt + t];
+        A.out_cnt[row] = c;
+    } else {
+        int32_t pos = A.out_rowptr[row];
+        for (int s = 0; s < ns; ++s) {
+            if (L.flags[s * nt + t]) {
+                A.out_col[pos] = A.sm.column(s, bx, by, bz);
+                A.out_val[pos] = L.vals[s * nt + t];
+                ++pos;
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------------- transpose
+__global__ void __launch_bounds__(BLOCK) k_tr_count(const int32_t* __restrict__ col, int64_t nnz,
+                                                    int32_t* __restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[col[e]], 1);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_tr_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, int64_t nrows,
+                                                   const int32_t* __restrict__ t_rowptr, int32_t* __restrict__ fill,
+                                                   int32_t* __restrict__ t_col, double* __restrict__ t_val) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= nrows) return;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int c = col[e];
+        const int32_t pos = t_rowptr[c] + atomicAdd(&fill[c], 1);
+        t_col[pos] = (int32_t)i;
+        t_val[pos] = val[e];
+    }
+}
+
+// insertion sort of each row by column (rows are short)
+__global__ void __launch_bounds__(BLOCK) k_sort_rows(const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                     double* __restrict__ val, int64_t nrows) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= nrows) return;
+    const int b = rowptr[i], e = rowptr[i + 1];
+    for (int u = b + 1; u < e; ++u) {
+        const int32_t c = col[u];
+        const double v = val[u];
+        int w = u;
+        while (w > b && col[w - 1] > c) {
+            col[w] = col[w - 1];
+            val[w] = val[w - 1];
+            --w;
+        }
+        col[w] = c;
+        val[w] = v;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_extract_diag(const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int64_t n,
+                                                        double* __restrict__ diag, int32_t* __restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double dg = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e)
+        if (col[e] == (int32_t)i) dg = val[e];
+    if (!(dg > 0.0)) atomicOr(err, DEVERR_NOTSPD);
+    diag[i] = dg;
+}
+
+// ------------------------------------------------------------ coarsest level
+__global__ void __launch_bounds__(BLOCK) k_csr_to_dense(const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int64_t n,
+                                                        double* __restrict__ dense) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t j = 0; j < n; ++j) dense[i * n + j] = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) dense[i * n + col[e]] = val[e];
+}
+
+// Right-looking Cholesky in place (lower triangle), one workgroup.
+__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ Ad, int n, int32_t* __restrict__ err) {
+    __shared__ double piv;
+    __shared__ int fail;
+    if (threadIdx.x == 0) fail = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const double dkk = Ad[(int64_t)k * n + k];
+            if (!(dkk > 0.0)) {
+                fail = 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(dkk);
+            }
+            Ad[(int64_t)k * n + k] = piv;
+        }
+        __syncthreads();
+        if (fail) break;
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) Ad[(int64_t)i * n + k] = Ad[(int64_t)i * n + k] / piv;
+        __syncthreads();
+        const int m = n - k - 1;
+        // trailing update of the lower triangle, (i, j) with k < j <= i < n
+        for (int64_t w = threadIdx.x; w < (int64_t)m * m; w += blockDim.x) {
+            const int i = k + 1 + (int)(w / m);
+            const int j = k + 1 + (int)(w % m);
+            if (j > i) continue;
+            Ad[(int64_t)i * n + j] = Ad[(int64_t)i * n + j] - Ad[(int64_t)i * n + k] * Ad[(int64_t)j * n + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && fail) atomicOr(err, DEVERR_NOTSPD);
+}
+
+// Linv column c by forward substitution (one thread per column).
+__global__ void __launch_bounds__(BLOCK) k_tri_inverse(const double* __restrict__ Lf, int n,
+                                                       double* __restrict__ Li) {
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= n) return;
+    for (int i = 0; i < c; ++i) Li[(int64_t)i * n + c] = 0.0;
+    for (int i = c; i < n; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) s = s - Lf[(int64_t)i * n + k] * Li[(int64_t)k * n + c];
+        Li[(int64_t)i * n + c] = s / Lf[(int64_t)i * n + i];
+    }
+}
+
+// W = Linv^T Linv (the inverse of A_coarsest); same summation order for (i,j)
+// and (j,i), so W is exactly symmetric.
+__global__ void __launch_bounds__(BLOCK) k_gram(const double* __restrict__ Li, int n, double* __restrict__ W) {
+    const int64_t id = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (id >= (int64_t)n * n) return;
+    const int i = (int)(id / n), j = (int)(id % n);
+    const int k0 = i > j ? i : j;
+    double s = 0.0;
+    for (int k = k0; k < n; ++k) s = s + Li[(int64_t)k * n + i] * Li[(int64_t)k * n + j];
+    W[id] = s;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
+                                                   int64_t n, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n && flag[i]) out[off[i]] = (int32_t)i;
+}
+
+// ------------------------------------------------------------- host helpers
+static int check_err(const int32_t* derr, hipStream_t s, const char* where) {
+    int32_t e = 0;
+    EB_TRY(read_device_i32(derr, &e, s));
+    if (e & DEVERR_DOMAIN) {
+        set_error("%s: a computational point lies on the outermost node layer", where);
+        return EB_EDOMAIN;
+    }
+    if (e & DEVERR_NOTSPD) {
+        set_error("%s: non-positive diagonal or Cholesky pivot (operator not SPD)", where);
+        return EB_ENOTSPD;
+    }
+    if (e & DEVERR_CAP) {
+        set_error("%s: a box or accumulator capacity was exceeded", where);
+        return EB_ENOSPC;
+    }
+    return EB_OK;
+}
+
+// rowptr (n+1 entries) from per-row counts; returns nnz on the host.
+static int rowptr_from_counts(const int32_t* cnt, int64_t n, int32_t** rowptr, int64_t* nnz, hipStream_t s) {
+    EB_TRY(dalloc_n(rowptr, n + 1, s));
+    int64_t total = 0;
+    EB_TRY(scan_i32(cnt, *rowptr, n, &total, s));
+    if (total >= ((int64_t)1 << 31)) {
+        set_error("a sparse matrix exceeds 2^31 entries");
+        return EB_ENOSPC;
+    }
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, *rowptr + n, (int32_t)total);
+    EB_LAUNCH_CHECK();
+    *nnz = total;
+    return EB_OK;
+}
+
+static int launch_accumulate(int mode, bool fill, AccArgs& args, hipStream_t s) {
+    const int ns = args.sm.nslots;
+    const size_t per_thread = (size_t)ns * (sizeof(double) + 1);
+    int nt = 256;
+    while (nt > 64 && per_thread * nt > 64 * 1024) nt >>= 1;
+    if (per_thread * nt > 150 * 1024) {
+        set_error("accumulator needs %zu bytes of LDS per 64 rows", per_thread * 64);
+        return EB_ENOSPC;
+    }
+    const size_t lds = per_thread * nt + 16;
+    const dim3 grid((unsigned)((args.nrows + nt - 1) / nt > 0 ? (args.nrows + nt - 1) / nt : 1));
+#define EB_ACC_LAUNCH(M, F) hipLaunchKernelGGL((k_accumulate<M, F>), grid, dim3(nt), lds, s, args)
+    if (mode == ACC_P) { if (fill) EB_ACC_LAUNCH(ACC_P, true); else EB_ACC_LAUNCH(ACC_P, false); }
+    else if (mode == ACC_AP) { if (fill) EB_ACC_LAUNCH(ACC_AP, true); else EB_ACC_LAUNCH(ACC_AP, false); }
+    else { if (fill) EB_ACC_LAUNCH(ACC_RAP, true); else EB_ACC_LAUNCH(ACC_RAP, false); }
+#undef EB_ACC_LAUNCH
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// Sparse product via the slot accumulator: count, prefix sum, fill.
+static int accumulate_product(int mode, AccArgs args, int64_t nrows, int32_t** rowptr, int32_t** col, double** val,
+                              int64_t* nnz, hipStream_t s) {
+    int32_t* cnt = nullptr;
+    EB_TRY(dalloc_n(&cnt, nrows, s));
+    args.nrows = nrows;
+    args.out_cnt = cnt;
+    EB_TRY(launch_accumulate(mode, false, args, s));
+    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, nnz, s));
+    EB_TRY(dfree(cnt, s));
+    EB_TRY(dalloc_n(col, *nnz, s));
+    EB_TRY(dalloc_n(val, *nnz, s));
+    args.out_rowptr = *rowptr;
+    args.out_col = *col;
+    args.out_val = *val;
+    EB_TRY(launch_accumulate(mode, true, args, s));
+    return EB_OK;
+}
+
+static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
+    Level& L = H->lev[l];
+    L.is_coarsest = 1;
+    const int64_t n = L.n;
+    if (n == 0) return EB_OK;
+    if (n > H->params.dense_limit) {
+        set_error("coarsest level has %lld unknowns, above the dense limit %d (coarsening stalled)",
+                  (long long)n, H->params.dense_limit);
+        return EB_ENOSPC;
+    }
+    double* dense = nullptr;
+    double* linv = nullptr;
+    EB_TRY(dalloc_n(&dense, n * n, s));
+    EB_TRY(dalloc_n(&linv, n * n, s));
+    EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
+    hipLaunchKernelGGL(k_csr_to_dense, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, n, dense);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, dense, (int)n, err);
+    EB_LAUNCH_CHECK();
+    EB_TRY(check_err(err, s, "coarsest Cholesky"));
+    hipLaunchKernelGGL(k_tri_inverse, dim3(grid_for(n)), dim3(BLOCK), 0, s, dense, (int)n, linv);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gram, dim3(grid_for(n * n)), dim3(BLOCK), 0, s, linv, (int)n, L.dense_inv);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(dense, s));
+    EB_TRY(dfree(linv, s));
+    return EB_OK;
+}
+
+// Aggregate level l; returns 1 in *stop if the level becomes the coarsest.
+static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* stop) {
+    Level& L = H->lev[l];
+    *stop = 0;
+    const int64_t n = L.n;
+    const int dim = H->d.dim;
+    if (n <= H->params.coarse_max || l + 1 >= H->params.max_levels || l + 1 >= MAX_LEVELS) {
+        *stop = 1;
+        return EB_OK;
+    }
+    NB3 nb;
+    for (int a = 0; a < 3; ++a) {
+        L.nb[a] = (L.ext[a] + 2) / 3;
+        nb.v[a] = L.nb[a];
+    }
+    const int64_t nboxes = (int64_t)nb.v[0] * nb.v[1] * nb.v[2];
+    L.nboxes = nboxes;
+    int32_t *cnt = nullptr, *boff = nullptr, *fillpos = nullptr, *members = nullptr, *lrank = nullptr;
+    EB_TRY(dalloc_n(&cnt, nboxes, s));
+    EB_TRY(dalloc_n(&boff, nboxes, s));
+    EB_TRY(dalloc_n(&fillpos, nboxes, s));
+    EB_TRY(dalloc_n(&members, n, s));
+    EB_TRY(dalloc_n(&lrank, n, s));
+    EB_TRY(dalloc_n(&L.box_ncomp, nboxes, s));
+    EB_TRY(dalloc_n(&L.box_cstart, nboxes, s));
+    EB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nboxes, s));
+    EB_HIP(hipMemsetAsync(fillpos, 0, sizeof(int32_t) * nboxes, s));
+    hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt);
+    EB_LAUNCH_CHECK();
+    EB_TRY(scan_i32(cnt, boff, nboxes, nullptr, s));
+    hipLaunchKernelGGL(k_box_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, boff, fillpos, members);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_box_components, dim3(grid_for(nboxes, 64)), dim3(64), 0, s, boff, cnt, members,
+                       L.a_rowptr, L.a_col, L.coords, nb, nboxes, lrank, L.box_ncomp, err);
+    EB_LAUNCH_CHECK();
+    int64_t nc = 0;
+    EB_TRY(scan_i32(L.box_ncomp, L.box_cstart, nboxes, &nc, s));
+    EB_TRY(check_err(err, s, "aggregation"));
+    int32_t* dmax = nullptr;
+    EB_TRY(dalloc_n(&dmax, 1, s));
+    hipLaunchKernelGGL(k_max_i32, dim3(1), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dmax);
+    EB_LAUNCH_CHECK();
+    int32_t maxc = 0;
+    EB_TRY(read_device_i32(dmax, &maxc, s));
+    EB_TRY(dfree(dmax, s));
+    EB_TRY(dfree(cnt, s));
+    EB_TRY(dfree(boff, s));
+    EB_TRY(dfree(fillpos, s));
+    EB_TRY(dfree(members, s));
+    if ((double)nc > H->params.min_reduction * (double)n || nc == 0) {
+        EB_TRY(dfree(lrank, s));
+        *stop = 1;
+        return EB_OK;
+    }
+    L.max_comp = maxc;
+    EB_TRY(dalloc_n(&L.agg, n, s));
+    hipLaunchKernelGGL(k_assign_agg, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, L.box_cstart, lrank, L.agg);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(lrank, s));
+
+    Level& C = H->lev[l + 1];
+    C = Level();
+    C.n = nc;
+    for (int a = 0; a < 3; ++a) C.ext[a] = nb.v[a];
+    EB_TRY(dalloc_n(&C.coords, 3 * nc, s));
+    EB_TRY(dalloc_n(&C.crank, nc, s));
+    hipLaunchKernelGGL(k_coarse_coords, dim3(grid_for(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, L.box_cstart, nb,
+                       nboxes, C.coords, C.crank);
+    EB_LAUNCH_CHECK();
+
+    // Gershgorin bound and smoothing weight
+    double* rowv = nullptr;
+    double* drho = nullptr;
+    EB_TRY(dalloc_n(&rowv, n, s));
+    EB_TRY(dalloc_n(&drho, 1, s));
+    hipLaunchKernelGGL(k_gershgorin_rows, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, L.diag,
+                       n, rowv);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_max_f64, dim3(1), dim3(BLOCK), 0, s, rowv, n, drho, err);
+    EB_LAUNCH_CHECK();
+    EB_HIP(hipMemcpyAsync(&L.rho, drho, sizeof(double), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    EB_TRY(check_err(err, s, "Gershgorin bound"));
+    L.omega = 4.0 / (3.0 * L.rho);
+    EB_TRY(dfree(rowv, s));
+    EB_TRY(dfree(drho, s));
+
+    AccArgs args;
+    memset(&args, 0, sizeof(args));
+    args.sm.dim = dim;
+    args.sm.maxc = maxc;
+    args.sm.nslots = (dim == 3 ? 27 : 9) * maxc;
+    args.sm.ccoords = C.coords;
+    args.sm.crank = C.crank;
+    args.sm.cstart = L.box_cstart;
+    args.sm.nb = nb;
+    args.err = err;
+
+    // P = (I - omega D^-1 A) P_tent
+    args.row_coords = L.coords;
+    args.centre_div = 3;
+    args.x_rowptr = L.a_rowptr; args.x_col = L.a_col; args.x_val = L.a_val;
+    args.agg = L.agg; args.diag = L.diag; args.omega = L.omega;
+    EB_TRY(accumulate_product(ACC_P, args, n, &L.p_rowptr, &L.p_col, &L.p_val, &L.nnz_p, s));
+
+    // R = P^T
+    {
+        int32_t* tcnt = nullptr;
+        int32_t* tfill = nullptr;
+        EB_TRY(dalloc_n(&tcnt, nc, s));
+        EB_TRY(dalloc_n(&tfill, nc, s));
+        EB_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * nc, s));
+        EB_HIP(hipMemsetAsync(tfill, 0, sizeof(int32_t) * nc, s));
+        hipLaunchKernelGGL(k_tr_count, dim3(grid_for(L.nnz_p)), dim3(BLOCK), 0, s, L.p_col, L.nnz_p, tcnt);
+        EB_LAUNCH_CHECK();
+        EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, &L.nnz_r, s));
+        EB_TRY(dalloc_n(&L.r_col, L.nnz_r, s));
+        EB_TRY(dalloc_n(&L.r_val, L.nnz_r, s));
+        hipLaunchKernelGGL(k_tr_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.p_rowptr, L.p_col, L.p_val, n,
+                           L.r_rowptr, tfill, L.r_col, L.r_val);
+        EB_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(nc)), dim3(BLOCK), 0, s, L.r_rowptr, L.r_col, L.r_val, nc);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(tcnt, s));
+        EB_TRY(dfree(tfill, s));
+    }
+
+    // AP = A P
+    int32_t *ap_rowptr = nullptr, *ap_col = nullptr;
+    double* ap_val = nullptr;
+    int64_t nnz_ap = 0;
+    args.x_rowptr = L.a_rowptr; args.x_col = L.a_col; args.x_val = L.a_val;
+    args.y_rowptr = L.p_rowptr; args.y_col = L.p_col; args.y_val = L.p_val;
+    args.row_coords = L.coords;
+    args.centre_div = 3;
+    EB_TRY(accumulate_product(ACC_AP, args, n, &ap_rowptr, &ap_col, &ap_val, &nnz_ap, s));
+
+    // A_c = R (A P)
+    args.x_rowptr = L.r_rowptr; args.x_col = L.r_col; args.x_val = L.r_val;
+    args.y_rowptr = ap_rowptr; args.y_col = ap_col; args.y_val = ap_val;
+    args.row_coords = C.coords;
+    args.centre_div = 1;
+    EB_TRY(accumulate_product(ACC_RAP, args, nc, &C.a_rowptr, &C.a_col, &C.a_val, &C.nnz_a, s));
+    EB_TRY(dfree(ap_rowptr, s));
+    EB_TRY(dfree(ap_col, s));
+    EB_TRY(dfree(ap_val, s));
+    EB_TRY(dalloc_n(&C.diag, nc, s));
+    hipLaunchKernelGGL(k_extract_diag, dim3(grid_for(nc)), dim3(BLOCK), 0, s, C.a_rowptr, C.a_col, C.a_val, nc,
+                       C.diag, err);
+    EB_LAUNCH_CHECK();
+    EB_TRY(check_err(err, s, "Galerkin product"));
+    return EB_OK;
+}
+
+static void free_level(Level& L, hipStream_t s) {
+    void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
+                    L.r_val, L.agg, L.coords, L.crank, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.res,
+                    L.zt, L.ev};
+    for (void* p : ptrs) (void)dfree(p, s);
+    L = Level();
+}
+
+int free_handle_memory(amg_handle* H) {
+    hipStream_t s = H->stream;
+    for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
+    void* ptrs[] = {H->strips, H->boxes0, H->fine_nodes, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, H->x, H->r,
+                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->red.partials, H->red.ticket};
+    for (void* p : ptrs) (void)dfree(p, s);
+    if (H->sc_host) (void)hipHostFree(H->sc_host);
+    if (H->ev0) (void)hipEventDestroy(H->ev0);
+    if (H->ev1) (void)hipEventDestroy(H->ev1);
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+int solve_layout_alloc(amg_handle* H, hipStream_t s);   // solve.hip
+
+static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStream_t s) {
+    const GridDims& d = H->d;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    int32_t* err = nullptr;
+    int32_t* flag = nullptr;
+    int32_t* unk_off = nullptr;
+    EB_TRY(dalloc_n(&err, 1, s));
+    EB_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    EB_TRY(dalloc_n(&flag, nn, s));
+    EB_TRY(dalloc_n(&unk_off, nn, s));
+    hipLaunchKernelGGL(k_fine_flags, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, err);
+    EB_LAUNCH_CHECK();
+    int64_t nunk = 0;
+    EB_TRY(scan_i32(flag, unk_off, nn, &nunk, s));
+    EB_TRY(check_err(err, s, "amg_setup"));
+    H->n_fine = nunk;
+    Level& L0 = H->lev[0];
+    L0 = Level();
+    L0.n = nunk;
+    L0.ext[0] = d.nx;
+    L0.ext[1] = d.ny;
+    L0.ext[2] = d.nz;
+    EB_TRY(dalloc_n(&H->fine_nodes, nunk, s));
+    EB_TRY(dalloc_n(&L0.coords, 3 * nunk, s));
+    EB_TRY(dalloc_n(&L0.diag, nunk, s));
+    int32_t* rowcnt = nullptr;
+    EB_TRY(dalloc_n(&rowcnt, nunk, s));
+    hipLaunchKernelGGL(k_fine_rows, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, unk_off, rowcnt,
+                       H->fine_nodes, L0.coords);
+    EB_LAUNCH_CHECK();
+    EB_TRY(rowptr_from_counts(rowcnt, nunk, &L0.a_rowptr, &L0.nnz_a, s));
+    EB_TRY(dalloc_n(&L0.a_col, L0.nnz_a, s));
+    EB_TRY(dalloc_n(&L0.a_val, L0.nnz_a, s));
+    hipLaunchKernelGGL(k_fine_fill, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, kind, a, H->sigma, d, nunk,
+                       H->fine_nodes, unk_off, L0.a_rowptr, L0.a_col, L0.a_val, L0.diag);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(rowcnt, s));
+    EB_TRY(dfree(flag, s));
+    EB_TRY(dfree(unk_off, s));
+
+    int l = 0;
+    while (true) {
+        if (H->lev[l].n == 0) {
+            H->lev[l].is_coarsest = 1;
+            break;
+        }
+        int stop = 0;
+        EB_TRY(build_next(H, l, s, err, &stop));
+        if (stop) {
+            EB_TRY(make_coarsest(H, l, s, err));
+            break;
+        }
+        ++l;
+    }
+    H->nlev = l + 1;
+    EB_TRY(solve_layout_alloc(H, s));
+    EB_TRY(check_err(err, s, "amg_setup"));
+    EB_TRY(dfree(err, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                         const amg_params_t* p, amg_handle_t** Hout, void* stream) {
+    clear_error();
+    if (!Hout || !kind || !a) {
+        set_error("amg_setup: null pointer");
+        return EB_EINVAL;
+    }
+    *Hout = nullptr;
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!(sigma >= 0.0) || isinf(sigma)) {
+        set_error("amg_setup: sigma must be finite and >= 0");
+        return EB_EINVAL;
+    }
+    amg_params_t prm;
+    prm.coarse_max = 256;
+    prm.max_levels = 16;
+    prm.min_reduction = 0.6;
+    prm.dense_limit = 4096;
+    prm.reserved = 0;
+    if (p) {
+        prm = *p;
+        if (prm.coarse_max < 1 || prm.max_levels < 1 || !(prm.min_reduction > 0.0 && prm.min_reduction <= 1.0) ||
+            prm.dense_limit < 1) {
+            set_error("amg_setup: invalid parameters");
+            return EB_EINVAL;
+        }
+        if (prm.dense_limit > 8192) prm.dense_limit = 8192;
+    }
+    amg_handle* H = new (std::nothrow) amg_handle();
+    if (!H) {
+        set_error("amg_setup: out of host memory");
+        return EB_EINVAL;
+    }
+    H->d = d;
+    H->sigma = sigma;
+    H->stream = (hipStream_t)stream;
+    H->params = prm;
+    int rc = setup_impl(H, kind, a, H->stream);
+    if (rc != EB_OK) {
+        char msg[1024];
+        snprintf(msg, sizeof(msg), "%s", eb_last_error());
+        (void)free_handle_memory(H);
+        delete H;
+        set_error("%s", msg);
+        return rc;
+    }
+    *Hout = H;
+    return EB_OK;
+}
+
+extern "C" void amg_free(amg_handle_t* H) {
+    if (!H) return;
+    (void)free_handle_memory(H);
+    delete H;
+}
+
+extern "C" int amg_num_levels(const amg_handle_t* H) { return H ? H->nlev : 0; }
+
+extern "C" const int64_t* amg_fine_nodes(const amg_handle_t* H) { return H ? H->fine_nodes : nullptr; }
+
+extern "C" int amg_level_info(const amg_handle_t* H, int level, amg_level_info_t* out) {
+    if (!H || !out || level < 0 || level >= H->nlev) {
+        set_error("amg_level_info: bad handle or level");
+        return EB_EINVAL;
+    }
+    const Level& L = H->lev[level];
+    memset(out, 0, sizeof(*out));
+    out->n = L.n;
+    out->nnz_a = L.nnz_a;
+    out->nnz_p = L.nnz_p;
+    out->nnz_r = L.nnz_r;
+    out->rho = L.rho;
+    out->omega = L.omega;
+    out->is_coarsest = L.is_coarsest;
+    out->max_comp = L.max_comp;
+    for (int a = 0; a < 3; ++a) out->ext[a] = L.ext[a];
+    out->a_rowptr = L.a_rowptr; out->a_col = L.a_col; out->a_val = L.a_val;
+    out->p_rowptr = L.p_rowptr; out->p_col = L.p_col; out->p_val = L.p_val;
+    out->r_rowptr = L.r_rowptr; out->r_col = L.r_col; out->r_val = L.r_val;
+    out->agg = L.agg;
+    out->coords = L.coords;
+    out->dense_inv = L.dense_inv;
+    return EB_OK;
+}

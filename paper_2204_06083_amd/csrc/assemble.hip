@@ -1,0 +1,313 @@
+// Embedded-boundary assembly kernels: classification, the line-by-line
+// diagonal with its cut records, the right-hand side and the matrix-free
+// operator on dense node fields.
+//
+// Built with -ffp-contract=off: the diagonal a_k, q, c and the crossing
+// coordinates are evaluated in a fixed order with separately rounded
+// operations, so an independent FP64 implementation can reproduce them bit
+// for bit (t = psi_in / (psi_in - psi_out); q = (j-1) + t; c = 1/q;
+// a_k = n_regular, then a_k += c side by side in the order -x,+x,-y,+y,-z,+z).
+#include "common.hpp"
+
+namespace eb {
+
+struct NodePos {
+    int i, j, k;
+};
+
+__device__ inline NodePos node_pos(int64_t n, const GridDims& d) {
+    NodePos p;
+    p.i = (int)(n % d.nx);
+    int64_t r = n / d.nx;
+    p.j = (int)(r % d.ny);
+    p.k = (int)(r / d.ny);
+    return p;
+}
+
+__device__ inline int axis_coord(const NodePos& p, int axis) {
+    return axis == 0 ? p.i : (axis == 1 ? p.j : p.k);
+}
+
+__device__ inline int axis_len(const GridDims& d, int axis) {
+    return axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
+}
+
+__device__ inline int64_t axis_stride(const GridDims& d, int axis) {
+    return axis == 0 ? 1 : (axis == 1 ? d.sy : d.sz);
+}
+
+// ------------------------------------------------------------ classification
+// Sec. 2: mask m = [psi < 0]; boundary point = inside with an outside nearest
+// neighbour; computational point = inside with all 2d neighbours inside.
+__global__ void __launch_bounds__(BLOCK) k_classify(const double* __restrict__ psi, int8_t* __restrict__ kind,
+                                                    GridDims d, int64_t nnodes, int32_t* __restrict__ err,
+                                                    int32_t* __restrict__ is_unknown, int32_t* __restrict__ ncut) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nnodes) return;
+    const NodePos p = node_pos(n, d);
+    const bool inside = psi[n] < 0.0;
+    const bool edge = p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
+                      (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
+    int8_t kd = 0;
+    int cuts = 0;
+    if (inside) {
+        if (edge) {
+            atomicOr(err, DEVERR_DOMAIN);
+            kd = 1;
+        } else {
+            int n_in = 0;
+            for (int axis = 0; axis < d.dim; ++axis) {
+                const int64_t st = axis_stride(d, axis);
+                n_in += psi[n - st] < 0.0;
+                n_in += psi[n + st] < 0.0;
+            }
+            kd = n_in == 2 * d.dim ? 2 : 1;
+        }
+    }
+    kind[n] = kd;
+    is_unknown[n] = kd == 2;
+    ncut[n] = cuts;  // sides are counted once kinds are known (k_count_cuts)
+}
+
+// Number of boundary-point sides of each computational point.
+__global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, GridDims d, int64_t nnodes,
+                                                      int32_t* __restrict__ ncut) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nnodes) return;
+    int c = 0;
+    if (kind[n] == 2) {
+        for (int axis = 0; axis < d.dim; ++axis) {
+            const int64_t st = axis_stride(d, axis);
+            c += kind[n - st] != 2;
+            c += kind[n + st] != 2;
+        }
+    }
+    ncut[n] = c;
+}
+
+// ------------------------------------------------- diagonal and cut records
+// Sec. 2.1.1: the BP value is the linear interpolant between the computational
+// point (xi_1 = 0) and the boundary crossing (xi_Gamma = q h) evaluated at the
+// BP (xi = h): u_BP = u_Gamma / q + (1 - 1/q) u_1.  Substituted into the
+// central difference, the side adds c = 1/q to the diagonal of -L_h h^2 and
+// u_Gamma c / h^2 to the right-hand side.  The crossing is located by linear
+// interpolation of psi between the last inside and first outside node on the
+// grid line (Sec. 3.3); when the node two steps out is still inside, the line
+// is followed to the first outside node.
+__global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ psi, const int8_t* __restrict__ kind,
+                                                     GridDims d, int64_t nnodes, const int64_t* __restrict__ cut_off,
+                                                     double* __restrict__ a, eb_cut_t* __restrict__ cuts,
+                                                     int64_t cap, int32_t* __restrict__ err) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nnodes) return;
+    if (kind[n] != 2) {
+        a[n] = 0.0;
+        return;
+    }
+    const NodePos p = node_pos(n, d);
+    int nreg = 0;
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t st = axis_stride(d, axis);
+        nreg += kind[n - st] == 2;
+        nreg += kind[n + st] == 2;
+    }
+    double acc = (double)nreg;
+    int64_t m = cut_off[n];
+    for (int side = 0; side < 2 * d.dim; ++side) {
+        const int axis = side >> 1;
+        const int step = (side & 1) ? 1 : -1;
+        const int64_t st = axis_stride(d, axis) * step;
+        if (kind[n + st] == 2) continue;
+        const int pos = axis_coord(p, axis);
+        const int len = axis_len(d, axis);
+        int j = 2;
+        // walk to the first outside node; the outermost layer is outside
+        while (true) {
+            const int at = pos + j * step;
+            if (at <= 0 || at >= len - 1) {
+                if (psi[n + (int64_t)j * st] < 0.0) atomicOr(err, DEVERR_DOMAIN);
+                break;
+            }
+            if (!(psi[n + (int64_t)j * st] < 0.0)) break;
+            ++j;
+        }
+        const double psi_in = psi[n + (int64_t)(j - 1) * st];
+        const double psi_out = psi[n + (int64_t)j * st];
+        const double t = psi_in / (psi_in - psi_out);
+        const double q = (double)(j - 1) + t;
+        const double c = 1.0 / q;
+        acc = acc + c;
+        if (m < cap) {
+            eb_cut_t rec;
+            rec.node = n;
+            rec.dir = side;
+            rec.steps = j;
+            rec.q = q;
+            rec.c = c;
+            double xg[3];
+            xg[0] = d.x0 + (double)p.i * d.h;
+            xg[1] = d.y0 + (double)p.j * d.h;
+            xg[2] = d.dim == 3 ? d.z0 + (double)p.k * d.h : 0.0;
+            const double qh = q * d.h;
+            xg[axis] = step > 0 ? xg[axis] + qh : xg[axis] - qh;
+            rec.xg[0] = xg[0];
+            rec.xg[1] = xg[1];
+            rec.xg[2] = xg[2];
+            cuts[m] = rec;
+        }
+        ++m;
+    }
+    a[n] = acc;
+}
+
+// ------------------------------------------------------------ right-hand side
+// b_k = f_k + sum over the cuts of k (ascending side) of u_Gamma * (c / h^2).
+__global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, const double* __restrict__ f,
+                                               const eb_cut_t* __restrict__ cuts, int64_t ncuts,
+                                               const double* __restrict__ u, double* __restrict__ b,
+                                               int64_t nnodes, double s) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nnodes) return;
+    if (kind[n] != 2) {
+        b[n] = 0.0;
+        return;
+    }
+    double v = f[n];
+    // lower_bound of node n in the (node, dir)-sorted records
+    int64_t lo = 0, hi = ncuts;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cuts[mid].node < n) lo = mid + 1; else hi = mid;
+    }
+    for (int64_t m = lo; m < ncuts && cuts[m].node == n; ++m) {
+        const double w = cuts[m].c * s;
+        v = v + u[m] * w;
+    }
+    b[n] = v;
+}
+
+// -------------------------------------------------------- operator on fields
+__global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restrict__ kind, const double* __restrict__ a,
+                                                         double sigma, const double* __restrict__ x,
+                                                         double* __restrict__ y, GridDims d, int64_t nnodes) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nnodes) return;
+    const NodePos p = node_pos(n, d);
+    // a node on the outermost layer has no full stencil: never treated as an unknown
+    const bool edge = p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
+                      (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
+    if (kind[n] != 2 || edge) {
+        y[n] = 0.0;
+        return;
+    }
+    double nb = 0.0;
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t st = axis_stride(d, axis);
+        if (kind[n - st] == 2) nb = nb + x[n - st];
+        if (kind[n + st] == 2) nb = nb + x[n + st];
+    }
+    const double diag = a[n] * d.s + sigma;
+    y[n] = diag * x[n] - d.s * nb;
+}
+
+static int check_err_word(const int32_t* derr, hipStream_t s) {
+    int32_t e = 0;
+    EB_TRY(read_device_i32(derr, &e, s));
+    if (e & DEVERR_DOMAIN) {
+        set_error("the domain reaches the outermost node layer (psi < 0 there)");
+        return EB_EDOMAIN;
+    }
+    return EB_OK;
+}
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double* a,
+                                eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                                int64_t* n_cuts, void* stream) {
+    clear_error();
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!psi || !kind || !a || !n_unknowns || !n_cuts || cuts_cap < 0 || (cuts_cap > 0 && !cuts)) {
+        set_error("eb_assemble_diag: null pointer or negative capacity");
+        return EB_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    int32_t* err = nullptr;
+    int32_t* is_unk = nullptr;
+    int32_t* ncut = nullptr;
+    int64_t* off = nullptr;
+    int32_t* unk_off = nullptr;
+    EB_TRY(dalloc_n(&err, 1, s));
+    EB_TRY(dalloc_n(&is_unk, nn, s));
+    EB_TRY(dalloc_n(&ncut, nn, s));
+    EB_TRY(dalloc_n(&off, nn, s));
+    EB_TRY(dalloc_n(&unk_off, nn, s));
+    EB_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, err, is_unk, ncut);
+    EB_LAUNCH_CHECK();
+    int rc = check_err_word(err, s);
+    if (rc == EB_OK) {
+        hipLaunchKernelGGL(k_count_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, ncut);
+        EB_LAUNCH_CHECK();
+        int64_t total_cuts = 0, total_unk = 0;
+        EB_TRY(scan_i32_to_i64(ncut, off, nn, &total_cuts, s));
+        EB_TRY(scan_i32(is_unk, unk_off, nn, &total_unk, s));
+        hipLaunchKernelGGL(k_diag_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, off, a, cuts,
+                           cuts_cap, err);
+        EB_LAUNCH_CHECK();
+        rc = check_err_word(err, s);
+        *n_unknowns = total_unk;
+        *n_cuts = total_cuts;
+        if (rc == EB_OK && total_cuts > cuts_cap) {
+            set_error("cut-record capacity %lld < required %lld", (long long)cuts_cap, (long long)total_cuts);
+            rc = EB_ENOSPC;
+        }
+    }
+    EB_TRY(dfree(err, s));
+    EB_TRY(dfree(is_unk, s));
+    EB_TRY(dfree(ncut, s));
+    EB_TRY(dfree(off, s));
+    EB_TRY(dfree(unk_off, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+extern "C" int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const double* f, const eb_cut_t* cuts,
+                               int64_t n_cuts, const double* u_at_cuts, double* b, void* stream) {
+    clear_error();
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!kind || !f || !b || n_cuts < 0 || (n_cuts > 0 && (!cuts || !u_at_cuts))) {
+        set_error("eb_assemble_rhs: null pointer or negative count");
+        return EB_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+extern "C" int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                             const double* x, double* y, void* stream) {
+    clear_error();
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!kind || !a || !x || !y) {
+        set_error("stencil_apply: null pointer");
+        return EB_EINVAL;
+    }
+    if (!(sigma >= 0.0)) {
+        set_error("stencil_apply: sigma must be >= 0");
+        return EB_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL(k_stencil_dense, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, a, sigma, x, y, d, nn);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}

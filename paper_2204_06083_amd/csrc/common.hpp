@@ -1,0 +1,116 @@
+// Shared internals of the ebamg library: error state, allocation, launch
+// helpers, deterministic wave/block reductions and the device-wide scan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "ebamg.h"
+
+namespace eb {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define EB_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::eb::set_error("%s:%d: %s failed: %s", __FILE__, __LINE__, #call,   \
+                            hipGetErrorString(e_));                               \
+            return EB_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+#define EB_TRY(expr)                                                              \
+    do {                                                                          \
+        int rc_ = (expr);                                                         \
+        if (rc_ != EB_OK) return rc_;                                             \
+    } while (0)
+
+#define EB_LAUNCH_CHECK() EB_HIP(hipGetLastError())
+
+// ------------------------------------------------------------- allocation
+// Stream-ordered allocations from the device's default memory pool: repeated
+// setup/free cycles reuse pool memory instead of calling into the driver.
+int dalloc(void** p, size_t bytes, hipStream_t s);
+int dfree(void* p, hipStream_t s);
+void pool_keep_memory();   // raise the pool release threshold once per device
+
+template <class T>
+int dalloc_n(T** p, int64_t count, hipStream_t s) {
+    return dalloc(reinterpret_cast<void**>(p), (size_t)(count > 0 ? count : 1) * sizeof(T), s);
+}
+
+// Device error word: kernels OR in flags, host reads at sync points.
+enum : int32_t {
+    DEVERR_DOMAIN = 1,
+    DEVERR_NOSPC = 2,
+    DEVERR_NOTSPD = 4,
+    DEVERR_NAN = 8,
+    DEVERR_CAP = 16,
+};
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+
+inline unsigned grid_for(int64_t n, int block = BLOCK) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+// ------------------------------------------------------------- reductions
+// Butterfly sum over the 64 lanes of a wavefront; every lane gets the total.
+// The pairing order is fixed, so results are reproducible run to run.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+// Block sum for blockDim.x == NT (multiple of 64).  Result valid in thread 0.
+template <int NT>
+__device__ inline double block_sum(double v, double* lds /* NT/64 */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / WAVE; ++i) t += lds[i];
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------- scans
+// Exclusive prefix sum of n counts (int32 in, int64 or int32 out).  If
+// `total_host` is non-null the grand total is copied back and the stream is
+// synchronised.
+int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s);
+int scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* total_host, hipStream_t s);
+
+// Small helpers used by several translation units.
+int read_device_i32(const int32_t* dptr, int32_t* host, hipStream_t s);
+int read_device_i64(const int64_t* dptr, int64_t* host, hipStream_t s);
+
+// Geometry of the node grid as seen by kernels.
+struct GridDims {
+    int dim;
+    int nx, ny, nz;          // nodes per axis (nz = 1 in 2-D)
+    int64_t sy, sz;          // strides of y and z in the dense user layout
+    double x0, y0, z0, h, s; // s = 1/h^2
+};
+
+int make_dims(const eb_grid_t* g, GridDims* d);
+
+}  // namespace eb

@@ -1,0 +1,89 @@
+// Internal layout of an amg_handle_t: the device hierarchy plus the fine-level
+// solve layout (row-padded node fields and active strip / box lists).
+#pragma once
+
+#include "common.hpp"
+
+namespace eb {
+
+constexpr int MAX_LEVELS = 24;
+
+struct Level {
+    int64_t n = 0, nnz_a = 0, nnz_p = 0, nnz_r = 0;
+    double rho = 0.0, omega = 0.0;
+    int is_coarsest = 0;
+    int max_comp = 0;            // most coarse unknowns sharing one box of this level
+    int ext[3] = {1, 1, 1};      // coordinate extents
+    int nb[3] = {1, 1, 1};       // box-grid extents (ceil(ext / 3))
+    int64_t nboxes = 0;
+    // operator (CSR, sorted columns) and its diagonal
+    int32_t* a_rowptr = nullptr; int32_t* a_col = nullptr; double* a_val = nullptr;
+    double* diag = nullptr;
+    // transfer operators to/from level + 1
+    int32_t* p_rowptr = nullptr; int32_t* p_col = nullptr; double* p_val = nullptr;
+    int32_t* r_rowptr = nullptr; int32_t* r_col = nullptr; double* r_val = nullptr;
+    int32_t* agg = nullptr;      // n: coarse unknown of each unknown
+    int32_t* coords = nullptr;   // 3n
+    int32_t* crank = nullptr;    // n: rank of the unknown among those of its coordinate box
+    int32_t* box_cstart = nullptr;  // nboxes: first coarse unknown of each box
+    int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
+    double* dense_inv = nullptr; // coarsest: n x n
+    // solve vectors (levels >= 1)
+    double* rv = nullptr; double* res = nullptr; double* zt = nullptr; double* ev = nullptr;
+};
+
+// Device scalars of one PCG solve.
+struct PcgScalars {
+    double rho;        // (r, z) of the current iterate
+    double beta;       // p <- z + beta p
+    double alpha;
+    double pq;
+    double rr;         // ||r||^2
+    double bb;         // ||b||^2
+    double tol2bb;     // tol^2 ||b||^2
+    double rz_new;
+    int32_t done;      // 1: converged / failed, later kernels return at once
+    int32_t status;    // EB_OK or failure code
+    int32_t iters;
+    int32_t rho_valid;
+};
+
+struct Reduction {
+    double* partials = nullptr;
+    unsigned int* ticket = nullptr;
+    int64_t cap = 0;
+};
+
+}  // namespace eb
+
+struct amg_handle {
+    eb::GridDims d;
+    double sigma = 0.0;
+    hipStream_t stream = nullptr;
+    amg_params_t params;
+    int64_t n_fine = 0;
+    int nlev = 0;
+    eb::Level lev[eb::MAX_LEVELS];
+    // fine-level solve layout: node fields with x rows padded to `px` (multiple of 64)
+    int px = 0;
+    int64_t npad = 0;
+    int strip_w = 64;
+    int64_t nstrips = 0;
+    int32_t* strips = nullptr;      // active strips (ids: padded index / strip_w)
+    int64_t nboxes0 = 0;
+    int32_t* boxes0 = nullptr;      // level-0 boxes holding unknowns
+    int64_t* fine_nodes = nullptr;  // unknown -> dense node index
+    int32_t* fine_pad = nullptr;    // unknown -> padded node index
+    int8_t* kind_p = nullptr;       // padded kind (2 computational, else 0)
+    double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
+    int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)
+    // PCG state (padded node fields)
+    double* x = nullptr; double* r = nullptr; double* z = nullptr;
+    double* p[2] = {nullptr, nullptr};
+    double* q = nullptr; double* res = nullptr; double* zt = nullptr;
+    double* bvec = nullptr;         // right-hand side in the padded layout
+    eb::PcgScalars* sc = nullptr;
+    eb::PcgScalars* sc_host = nullptr;   // pinned mirror
+    eb::Reduction red;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};

@@ -1,0 +1,222 @@
+// Host runtime pieces: error state, pooled allocation, scans, small helpers.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.hpp"
+
+namespace eb {
+
+static thread_local char g_last_error[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_last_error[0] = 0; }
+
+void pool_keep_memory() {
+    static bool done[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[dev] = true;
+}
+
+int dalloc(void** p, size_t bytes, hipStream_t s) {
+    pool_keep_memory();
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        *p = nullptr;
+        return EB_EHIP;
+    }
+    return EB_OK;
+}
+
+int dfree(void* p, hipStream_t s) {
+    if (!p) return EB_OK;
+    EB_HIP(hipFreeAsync(p, s));
+    return EB_OK;
+}
+
+int read_device_i32(const int32_t* dptr, int32_t* host, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(host, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+int read_device_i64(const int64_t* dptr, int64_t* host, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(host, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+int make_dims(const eb_grid_t* g, GridDims* d) {
+    if (!g || (g->dim != 2 && g->dim != 3) || !(g->h > 0.0)) {
+        set_error("invalid grid (dim must be 2 or 3, h > 0)");
+        return EB_EINVAL;
+    }
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->n[a] < 2 || g->n[a] > (1 << 20)) {
+            set_error("invalid grid: n[%d] = %d", a, g->n[a]);
+            return EB_EINVAL;
+        }
+    }
+    d->dim = g->dim;
+    d->nx = g->n[0] + 1;
+    d->ny = g->n[1] + 1;
+    d->nz = g->dim == 3 ? g->n[2] + 1 : 1;
+    int64_t total = (int64_t)d->nx * d->ny * d->nz;
+    if (total >= ((int64_t)1 << 31)) {
+        set_error("grid has %lld nodes; at most 2^31 - 1 are supported", (long long)total);
+        return EB_EINVAL;
+    }
+    d->sy = d->nx;
+    d->sz = (int64_t)d->nx * d->ny;
+    d->x0 = g->x0[0];
+    d->y0 = g->x0[1];
+    d->z0 = g->dim == 3 ? g->x0[2] : 0.0;
+    d->h = g->h;
+    d->s = 1.0 / (g->h * g->h);
+    return EB_OK;
+}
+
+// ------------------------------------------------------------------- scan
+// Three-phase exclusive scan: per-block scans (ITEMS elements per thread),
+// a recursive scan of the block totals, then a uniform add.  Integer only,
+// so the result is exact and order independent.
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in, TO* __restrict__ out,
+                                                      TO* __restrict__ tile_sums, int64_t n) {
+    __shared__ TO lds[BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    TO v[SCAN_ITEMS];
+    TO run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = base + i;
+        TO x = idx < n ? (TO)in[idx] : (TO)0;
+        v[i] = run;
+        run += x;
+    }
+    lds[threadIdx.x] = run;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of thread totals
+    for (int off = 1; off < BLOCK; off <<= 1) {
+        TO t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : (TO)0;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
+    }
+    TO prefix = threadIdx.x > 0 ? lds[threadIdx.x - 1] : (TO)0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = v[i] + prefix;
+    }
+    if (threadIdx.x == BLOCK - 1) tile_sums[blockIdx.x] = lds[BLOCK - 1];
+}
+
+template <class TO>
+__global__ void __launch_bounds__(BLOCK) k_scan_add(TO* __restrict__ out, const TO* __restrict__ tile_off, int64_t n) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const TO add = tile_off[blockIdx.x];
+    for (int i = threadIdx.x; i < SCAN_TILE; i += BLOCK) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
+template <class TO>
+__global__ void k_scan_total(const TO* out, const TO* tile_sums, int64_t ntiles, TO* total) {
+    // total = (exclusive offset of the last tile) + (sum of the last tile)
+    if (threadIdx.x == 0 && blockIdx.x == 0) *total = out[ntiles - 1] + tile_sums[ntiles - 1];
+}
+
+template <class TI, class TO>
+static int scan_impl(const TI* in, TO* out, int64_t n, TO* total_dev, hipStream_t s) {
+    if (n <= 0) {
+        EB_HIP(hipMemsetAsync(total_dev, 0, sizeof(TO), s));
+        return EB_OK;
+    }
+    const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    TO* sums = nullptr;
+    TO* sums_scan = nullptr;
+    EB_TRY(dalloc_n(&sums, ntiles, s));
+    EB_TRY(dalloc_n(&sums_scan, ntiles, s));
+    hipLaunchKernelGGL((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out, sums, n);
+    EB_LAUNCH_CHECK();
+    if (ntiles == 1) {
+        EB_HIP(hipMemcpyAsync(total_dev, sums, sizeof(TO), hipMemcpyDeviceToDevice, s));
+    } else {
+        TO* dummy_total = nullptr;
+        EB_TRY(dalloc_n(&dummy_total, 1, s));
+        EB_TRY((scan_impl<TO, TO>(sums, sums_scan, ntiles, dummy_total, s)));
+        hipLaunchKernelGGL((k_scan_add<TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, out, sums_scan, n);
+        EB_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_scan_total<TO>), dim3(1), dim3(1), 0, s, sums_scan, sums, ntiles, total_dev);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(dummy_total, s));
+    }
+    EB_TRY(dfree(sums, s));
+    EB_TRY(dfree(sums_scan, s));
+    return EB_OK;
+}
+
+int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s) {
+    int64_t* tot = nullptr;
+    EB_TRY(dalloc_n(&tot, 1, s));
+    EB_TRY((scan_impl<int32_t, int64_t>(in, out, n, tot, s)));
+    if (total_host) EB_TRY(read_device_i64(tot, total_host, s));
+    EB_TRY(dfree(tot, s));
+    return EB_OK;
+}
+
+int scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* total_host, hipStream_t s) {
+    int32_t* tot = nullptr;
+    EB_TRY(dalloc_n(&tot, 1, s));
+    EB_TRY((scan_impl<int32_t, int32_t>(in, out, n, tot, s)));
+    if (total_host) {
+        int32_t t = 0;
+        EB_TRY(read_device_i32(tot, &t, s));
+        *total_host = t;
+    }
+    EB_TRY(dfree(tot, s));
+    return EB_OK;
+}
+
+}  // namespace eb
+
+extern "C" {
+
+const char* eb_last_error(void) { return eb::g_last_error; }
+
+const char* eb_strerror(int code) {
+    switch (code) {
+        case EB_OK: return "success";
+        case EB_EINVAL: return "invalid argument";
+        case EB_EDOMAIN: return "domain reaches the outermost node layer";
+        case EB_ENOSPC: return "output capacity too small";
+        case EB_ENOTSPD: return "operator is not symmetric positive definite";
+        case EB_ENAN: return "NaN or Inf in the solve";
+        case EB_ENOCONV: return "iteration limit reached";
+        case EB_EHIP: return "HIP runtime error";
+        case EB_ENOTIMPL: return "not implemented";
+        default: return "unknown error";
+    }
+}
+
+int eb_abi_version(void) { return EBAMG_ABI_VERSION; }
+
+}  // extern "C"

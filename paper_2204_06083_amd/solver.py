@@ -1,0 +1,232 @@
+"""Python entry points over the C ABI, taking torch tensors on the GPU.
+
+Each function checks shapes and dtypes, passes raw device pointers and the
+current HIP stream to libebamg.so and wraps the outputs.  All arithmetic runs
+in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _field(t: torch.Tensor, shape, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous {dtype} of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Assembly:
+    grid: object
+    kind: torch.Tensor          # int8 node field
+    a: torch.Tensor             # float64 node field
+    cuts: torch.Tensor          # uint8 [cap*56] device buffer of eb_cut_t records
+    n_unknowns: int
+    n_cuts: int
+
+    def cuts_host(self) -> np.ndarray:
+        raw = self.cuts[: self.n_cuts * 56].cpu().numpy()
+        return raw.view(L.CUT_DTYPE)
+
+    def cut_coordinates(self):
+        """Crossing coordinates as device tensors (x, y[, z]) in record order."""
+        if self.n_cuts == 0:
+            z = torch.zeros(0, dtype=torch.float64, device=self.kind.device)
+            return tuple(z for _ in range(self.grid.dim))
+        rec = self.cuts[: self.n_cuts * 56].view(torch.float64).view(self.n_cuts, 7)
+        return tuple(rec[:, 4 + p].contiguous() for p in range(self.grid.dim))
+
+
+def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None) -> Assembly:
+    """Classify nodes and build a_k and the cut records (eb_assemble_diag)."""
+    lib = L.lib()
+    g = L.make_grid(grid)
+    shape = grid.shape
+    dev = psi.device
+    psi_p = _field(psi, shape, torch.float64, "psi")
+    kind = torch.empty(shape, dtype=torch.int8, device=dev)
+    a = torch.empty(shape, dtype=torch.float64, device=dev)
+    nu, nc = C.c_int64(0), C.c_int64(0)
+    if cuts_cap is None:
+        # counts first (capacity 0 reports the required size), then the records
+        rc = lib.eb_assemble_diag(C.byref(g), psi_p, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
+                                  None, 0, C.byref(nu), C.byref(nc), _stream())
+        L.check(rc, "eb_assemble_diag", ok=(L.EB_OK, L.EB_ENOSPC))
+        cuts_cap = nc.value
+    cuts = torch.empty(max(cuts_cap, 1) * 56, dtype=torch.uint8, device=dev)
+    rc = lib.eb_assemble_diag(C.byref(g), psi_p, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
+                              C.c_void_p(cuts.data_ptr()), int(cuts_cap), C.byref(nu), C.byref(nc), _stream())
+    L.check(rc, "eb_assemble_diag")
+    return Assembly(grid, kind, a, cuts, nu.value, nc.value)
+
+
+def assemble_rhs(asm: Assembly, f: torch.Tensor, u_at_cuts: torch.Tensor) -> torch.Tensor:
+    lib = L.lib()
+    g = L.make_grid(asm.grid)
+    shape = asm.grid.shape
+    f_p = _field(f, shape, torch.float64, "f")
+    u = u_at_cuts.contiguous().to(torch.float64)
+    if u.numel() != asm.n_cuts:
+        raise ValueError("u_at_cuts must hold one value per cut record")
+    b = torch.empty(shape, dtype=torch.float64, device=f.device)
+    rc = lib.eb_assemble_rhs(C.byref(g), C.c_void_p(asm.kind.data_ptr()), f_p, C.c_void_p(asm.cuts.data_ptr()),
+                             asm.n_cuts, C.c_void_p(u.data_ptr()), C.c_void_p(b.data_ptr()), _stream())
+    L.check(rc, "eb_assemble_rhs")
+    return b
+
+
+def stencil_apply(grid, kind: torch.Tensor, a: torch.Tensor, sigma: float, x: torch.Tensor,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib = L.lib()
+    g = L.make_grid(grid)
+    shape = grid.shape
+    y = out if out is not None else torch.empty(shape, dtype=torch.float64, device=x.device)
+    rc = lib.stencil_apply(C.byref(g), _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a"),
+                           float(sigma), _field(x, shape, torch.float64, "x"), _field(y, shape, torch.float64, "y"),
+                           _stream())
+    L.check(rc, "stencil_apply")
+    return y
+
+
+@dataclass
+class LevelArrays:
+    n: int
+    nnz_a: int
+    nnz_p: int
+    nnz_r: int
+    rho: float
+    omega: float
+    is_coarsest: bool
+    max_comp: int
+    info: object
+
+
+class Hierarchy:
+    """amg_setup / pcg_solve / amg_free around one handle."""
+
+    def __init__(self, grid, kind: torch.Tensor, a: torch.Tensor, sigma: float = 0.0, coarse_max: int = 256,
+                 max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 4096):
+        lib = L.lib()
+        self.grid = grid
+        self.sigma = float(sigma)
+        g = L.make_grid(grid)
+        p = L.AmgParams(coarse_max, max_levels, min_reduction, dense_limit, 0)
+        h = C.c_void_p()
+        shape = grid.shape
+        rc = lib.amg_setup(C.byref(g), _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a"),
+                           self.sigma, C.byref(p), C.byref(h), _stream())
+        L.check(rc, "amg_setup")
+        self.handle = h
+        self._keep = (kind, a)
+
+    def free(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            L.lib().amg_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def n_levels(self) -> int:
+        return L.lib().amg_num_levels(self.handle)
+
+    def level(self, l: int) -> LevelArrays:
+        info = L.LevelInfo()
+        L.check(L.lib().amg_level_info(self.handle, l, C.byref(info)), "amg_level_info")
+        return LevelArrays(info.n, info.nnz_a, info.nnz_p, info.nnz_r, info.rho, info.omega,
+                           bool(info.is_coarsest), info.max_comp, info)
+
+    def export_level(self, l: int) -> dict:
+        """Copy one level's arrays to host numpy (parity tests)."""
+        torch.cuda.synchronize()
+        lv = self.level(l)
+        i = lv.info
+        out = dict(n=lv.n, rho=lv.rho, omega=lv.omega, is_coarsest=lv.is_coarsest, max_comp=lv.max_comp)
+
+        def get(ptr, count, dtype):
+            arr = np.empty(max(count, 0), dtype=dtype)
+            if ptr and count > 0:
+                L.copy_device_to_host(ptr, arr.nbytes, arr)
+            return arr
+
+        out["a_rowptr"] = get(i.a_rowptr, lv.n + 1, np.int32)
+        out["a_col"] = get(i.a_col, lv.nnz_a, np.int32)
+        out["a_val"] = get(i.a_val, lv.nnz_a, np.float64)
+        out["coords"] = get(i.coords, 3 * lv.n, np.int32).reshape(-1, 3)
+        if not lv.is_coarsest:
+            nc = self.level(l + 1).n
+            out["agg"] = get(i.agg, lv.n, np.int32)
+            out["p_rowptr"] = get(i.p_rowptr, lv.n + 1, np.int32)
+            out["p_col"] = get(i.p_col, lv.nnz_p, np.int32)
+            out["p_val"] = get(i.p_val, lv.nnz_p, np.float64)
+            out["r_rowptr"] = get(i.r_rowptr, nc + 1, np.int32)
+            out["r_col"] = get(i.r_col, lv.nnz_r, np.int32)
+            out["r_val"] = get(i.r_val, lv.nnz_r, np.float64)
+        elif i.dense_inv:
+            out["dense_inv"] = get(i.dense_inv, lv.n * lv.n, np.float64).reshape(lv.n, lv.n)
+        return out
+
+    def fine_nodes(self) -> np.ndarray:
+        torch.cuda.synchronize()
+        n = self.level(0).n
+        arr = np.empty(n, dtype=np.int64)
+        ptr = L.lib().amg_fine_nodes(self.handle)
+        if n > 0:
+            L.copy_device_to_host(ptr, arr.nbytes, arr)
+        return arr
+
+    def vcycle(self, r: torch.Tensor) -> torch.Tensor:
+        shape = self.grid.shape
+        z = torch.empty(shape, dtype=torch.float64, device=r.device)
+        rc = L.lib().amg_vcycle_apply(self.handle, _field(r, shape, torch.float64, "r"), C.c_void_p(z.data_ptr()),
+                                      _stream())
+        L.check(rc, "amg_vcycle_apply")
+        return z
+
+    def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-8, maxit: int = 1000,
+              check_every: int = 8, out: Optional[torch.Tensor] = None, allow_noconv: bool = False):
+        shape = self.grid.shape
+        x = out if out is not None else torch.empty(shape, dtype=torch.float64, device=b.device)
+        if x0 is not None:
+            x.copy_(x0)
+        prm = L.PcgParams(float(tol), int(maxit), 1 if x0 is not None else 0, int(check_every), 0)
+        res = L.PcgResult()
+        rc = L.lib().pcg_solve(self.handle, _field(b, shape, torch.float64, "b"), _field(x, shape, torch.float64, "x"),
+                               C.byref(prm), C.byref(res), _stream())
+        ok = (L.EB_OK, L.EB_ENOCONV) if allow_noconv else (L.EB_OK,)
+        L.check(rc, "pcg_solve", ok=ok)
+        info = dict(iterations=res.iterations, status=res.status, restarts=res.restarts, levels=res.levels,
+                    rel_res_true=res.rel_res_true, solve_ms=res.solve_ms)
+        return x, info
+
+
+def solve_problem(problem, device="cuda", tol=None, coarse_max=256):
+    """Full path for one workloads.Problem: assemble, RHS, setup, solve."""
+    g = problem.grid
+    psi = torch.as_tensor(problem.psi, device=device)
+    f = torch.as_tensor(problem.f, device=device)
+    asm = assemble_diag(g, psi)
+    coords = asm.cut_coordinates()
+    u_cut = problem.u_dirichlet(*coords) if problem.u_dirichlet is not None else torch.zeros_like(coords[0])
+    b = assemble_rhs(asm, f, torch.as_tensor(u_cut, device=device, dtype=torch.float64))
+    H = Hierarchy(g, asm.kind, asm.a, problem.sigma, coarse_max=coarse_max)
+    x, info = H.solve(b, tol=problem.tol if tol is None else tol)
+    return dict(asm=asm, b=b, H=H, x=x, info=info)

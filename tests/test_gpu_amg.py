@@ -1,0 +1,113 @@
+"""GPU parity of the AMG hierarchy: integer structures bit-exact, values to tolerance."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import amg as OA
+from oracle import eb_assembly as E
+from paper_2204_06083_amd import solver as S
+from paper_2204_06083_amd import workloads as W
+
+from gpu_common import DEV, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _split_box_problem():
+    g = W.unit_box_grid(2, 60)
+    X, Y = g.mesh()
+    psi = np.maximum(np.abs(Y) - 0.33, np.abs(X) - 0.41)
+    for (j, i) in [(25, 25), (31, 34), (40, 19)]:
+        psi[j, i] = 1.0        # isolated outside nodes at box centres split boxes
+    return W.Problem("split", g, psi, np.ones(g.shape), u_dirichlet=W.zero_data)
+
+
+CASES = {
+    "disk128": (lambda: W.disk_poisson(128), 0.0, 256),
+    "star512": (lambda: W.star_poisson(512), 0.0, 256),
+    "star300_sigma": (lambda: W.star_poisson(300), 300.0, 64),
+    "ell48": (lambda: W.ellipsoid_poisson(48), 0.0, 64),
+    "ell33_ragged": (lambda: W.ellipsoid_poisson(33), 0.0, 16),
+    "split": (_split_box_problem, 0.0, 8),
+    "star2048": (lambda: W.star_poisson(2048), 0.0, 256),
+}
+
+
+def _csr_equal_pattern(rowptr, col, M):
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    return np.array_equal(rowptr, M.indptr) and np.array_equal(col, M.indices)
+
+
+def _vals_close(val, M, rtol=1e-13):
+    M = sp.csr_matrix(M)
+    scale = np.abs(M.data).max() if M.nnz else 1.0
+    return np.max(np.abs(val - M.data)) <= rtol * scale if M.nnz else True
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_parity(name):
+    mk, sigma, cmax = CASES[name]
+    prob = mk()
+    print(f"[gpu] hierarchy {name} grid={prob.grid.shape} sigma={sigma}", flush=True)
+    asm_o = E.assemble(prob.grid, prob.psi)
+    A0 = E.operator_csr(asm_o, sigma)
+    Ho = OA.build_hierarchy(A0, E.unknown_coords(asm_o), coarse_max=cmax)
+    asm_g = S.assemble_diag(prob.grid, to_dev(prob.psi))
+    Hg = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, sigma, coarse_max=cmax)
+    assert Hg.n_levels == Ho.n_levels
+    assert np.array_equal(Hg.fine_nodes(), asm_o.nodes)
+    for l, lo in enumerate(Ho.levels):
+        lg = Hg.export_level(l)
+        assert lg["n"] == lo.n
+        assert np.array_equal(lg["coords"][:, :prob.grid.dim], lo.coords[:, :prob.grid.dim])
+        assert _csr_equal_pattern(lg["a_rowptr"], lg["a_col"], lo.A), f"A pattern level {l}"
+        assert _vals_close(lg["a_val"], lo.A), f"A values level {l}"
+        if lo.chol is None:
+            assert np.array_equal(lg["agg"], lo.agg), f"aggregates level {l}"
+            if l == 0:
+                # same bit-exact entries summed in the same row order
+                assert lg["rho"] == lo.rho and lg["omega"] == lo.omega
+            else:
+                # Galerkin entries agree to rounding (1e-13), so does their row-sum bound
+                assert lg["rho"] == pytest.approx(lo.rho, rel=1e-13, abs=0)
+                assert lg["omega"] == pytest.approx(lo.omega, rel=1e-13, abs=0)
+            assert _csr_equal_pattern(lg["p_rowptr"], lg["p_col"], lo.P), f"P pattern level {l}"
+            assert _vals_close(lg["p_val"], lo.P), f"P values level {l}"
+            assert _csr_equal_pattern(lg["r_rowptr"], lg["r_col"], lo.R), f"R pattern level {l}"
+            assert np.array_equal(np.sort(lg["r_val"]), np.sort(lg["p_val"]))
+        else:
+            W_o = np.linalg.inv(lo.A.toarray())
+            assert np.max(np.abs(lg["dense_inv"] - W_o)) <= 1e-10 * np.abs(W_o).max()
+            assert np.array_equal(lg["dense_inv"], lg["dense_inv"].T)
+    Hg.free()
+
+
+def test_hierarchy_deterministic():
+    prob = W.star_poisson(700)
+    asm_g = S.assemble_diag(prob.grid, to_dev(prob.psi))
+    out = []
+    for _ in range(2):
+        H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, 0.0)
+        out.append([H.export_level(l) for l in range(H.n_levels)])
+        H.free()
+    for la, lb in zip(*out):
+        for k in la:
+            if isinstance(la[k], np.ndarray):
+                assert np.array_equal(la[k], lb[k]), k
+
+
+def test_vcycle_matches_oracle():
+    for prob, sigma in ((W.star_poisson(400), 0.0), (W.ellipsoid_poisson(40), 0.0), (W.disk_poisson(16), 0.0)):
+        asm_o = E.assemble(prob.grid, prob.psi)
+        A0 = E.operator_csr(asm_o, sigma)
+        Ho = OA.build_hierarchy(A0, E.unknown_coords(asm_o))
+        asm_g = S.assemble_diag(prob.grid, to_dev(prob.psi))
+        Hg = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, sigma)
+        rng = np.random.default_rng(8)
+        r = rng.normal(size=prob.grid.shape)
+        z = Hg.vcycle(to_dev(r)).cpu().numpy().ravel()
+        zo = OA.vcycle(Ho, r.ravel()[asm_o.nodes])
+        assert np.linalg.norm(z[asm_o.nodes] - zo) <= 1e-12 * np.linalg.norm(zo)
+        assert not np.any(z[asm_o.kind.ravel() != 2])
+        Hg.free()

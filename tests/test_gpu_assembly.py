@@ -1,0 +1,96 @@
+"""GPU parity of classification, diagonal, cut records, RHS and the stencil (C ABI vs oracle)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import eb_assembly as E
+from paper_2204_06083_amd import _lib as L
+from paper_2204_06083_amd import solver as S
+from paper_2204_06083_amd import workloads as W
+
+from gpu_common import DEV, gpu_system, oracle_system, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "disk128": lambda: W.disk_poisson(128),
+    "star2048": lambda: W.star_poisson(2048),
+    "star1000_ragged": lambda: W.star_poisson(1000),
+    "heat1024": lambda: W.star_heat(1024, 0),
+    "ell64": lambda: W.ellipsoid_poisson(64),
+    "ell256": lambda: W.ellipsoid_poisson(256),
+    "ell_ragged_75": lambda: W.ellipsoid_poisson(75),
+    "rstar": lambda: W.random_star_poisson(*W.random_star_params(3)[2]),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembly_bit_exact(name):
+    prob = CASES[name]()
+    print(f"[gpu] assembly {name} grid={prob.grid.shape}", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    kind = asm_g.kind.cpu().numpy()
+    assert np.array_equal(kind, asm_o.kind)
+    assert asm_g.n_unknowns == asm_o.n_unknowns
+    assert asm_g.n_cuts == asm_o.n_cuts
+    cuts = asm_g.cuts_host()
+    assert np.array_equal(cuts["node"], asm_o.cuts["node"])
+    assert np.array_equal(cuts["dir"], asm_o.cuts["dir"])
+    assert np.array_equal(cuts["steps"], asm_o.cuts["steps"])
+    # floating point evaluated in the same order without contraction: bit-exact
+    assert np.array_equal(cuts["q"], asm_o.cuts["q"])
+    assert np.array_equal(cuts["c"], asm_o.cuts["c"])
+    assert np.array_equal(cuts["xg"][:, :prob.grid.dim], asm_o.cuts["xg"][:, :prob.grid.dim])
+    a = asm_g.a.cpu().numpy().ravel()
+    assert np.array_equal(a[asm_o.nodes], asm_o.a)
+    assert not np.any(a[kind.ravel() != 2])
+    b = b_g.cpu().numpy().ravel()
+    assert np.array_equal(b[asm_o.nodes], b_o)
+    assert not np.any(b[kind.ravel() != 2])
+
+
+@pytest.mark.parametrize("name", ["disk128", "star1000_ragged", "ell64", "heat1024"])
+def test_stencil_apply_matches_operator(name):
+    prob = CASES[name]()
+    sigma = prob.sigma
+    asm_o = E.assemble(prob.grid, prob.psi)
+    A = E.operator_csr(asm_o, sigma)
+    asm_g = S.assemble_diag(prob.grid, to_dev(prob.psi))
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=prob.grid.shape)
+    y = S.stencil_apply(prob.grid, asm_g.kind, asm_g.a, sigma, to_dev(x)).cpu().numpy().ravel()
+    xv = x.ravel()[asm_o.nodes]
+    ref = A @ xv
+    scale = abs(A) @ np.abs(xv)
+    assert np.all(np.abs(y[asm_o.nodes] - ref) <= 4e-16 * 8 * scale)
+    assert not np.any(y[asm_o.kind.ravel() != 2])
+
+
+def test_empty_domain_and_errors():
+    g = W.unit_box_grid(2, 40)
+    psi = np.ones(g.shape)
+    asm = S.assemble_diag(g, to_dev(psi))
+    assert asm.n_unknowns == 0 and asm.n_cuts == 0
+    assert not torch.any(asm.kind).item()
+    # domain touching the outer layer
+    psi2 = W.psi_disk(g, radius=0.7)
+    with pytest.raises(L.EbError) as ei:
+        S.assemble_diag(g, to_dev(psi2))
+    assert ei.value.code == L.EB_EDOMAIN
+    # too small a cut capacity reports the required count
+    prob = W.disk_poisson(64)
+    with pytest.raises(L.EbError) as ei:
+        S.assemble_diag(prob.grid, to_dev(prob.psi), cuts_cap=3)
+    assert ei.value.code == L.EB_ENOSPC
+    # invalid grid
+    bad = W.Grid(dim=4, n=(8, 8, 8), x0=(0, 0, 0), h=0.1)
+    with pytest.raises(Exception):
+        S.assemble_diag(bad, to_dev(np.ones((9, 9))))
+
+
+def test_cut_capacity_exact_fit_and_determinism():
+    prob = W.star_poisson(512)
+    a1 = S.assemble_diag(prob.grid, to_dev(prob.psi))
+    a2 = S.assemble_diag(prob.grid, to_dev(prob.psi), cuts_cap=a1.n_cuts)
+    assert torch.equal(a1.a, a2.a) and torch.equal(a1.cuts[: a1.n_cuts * 56], a2.cuts[: a2.n_cuts * 56])

@@ -1,0 +1,137 @@
+"""GPU PCG parity: same hierarchy and algorithm as the oracle, direct-solve parity, error paths."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import amg as OA
+from oracle import eb_assembly as E
+from oracle import pcg as OP
+from paper_2204_06083_amd import _lib as L
+from paper_2204_06083_amd import solver as S
+from paper_2204_06083_amd import workloads as W
+
+from gpu_common import DEV, gpu_system, oracle_system, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ITER_CASES = {
+    "disk128_1e-10": (lambda: W.disk_poisson(128), 1e-10),
+    "star512": (lambda: W.star_poisson(512), 1e-8),
+    "star1000_ragged": (lambda: W.star_poisson(1000), 1e-8),
+    "heat512_sigma": (lambda: W.star_heat(512, 5), 1e-8),
+    "ell48": (lambda: W.ellipsoid_poisson(48), 1e-8),
+    "ell64": (lambda: W.ellipsoid_poisson(64), 1e-8),
+    "disk16_onelevel": (lambda: W.disk_mms(16, radius=0.3), 1e-10),
+    "star2048_full": (lambda: W.star_poisson(2048), 1e-8),
+}
+
+
+@pytest.mark.parametrize("name", list(ITER_CASES))
+def test_iterate_parity(name):
+    mk, tol = ITER_CASES[name]
+    prob = mk()
+    print(f"[gpu] pcg {name} grid={prob.grid.shape}", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    res_o, Ho = OP.amg_pcg(A, E.unknown_coords(asm_o), b_o, tol=tol)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    x_g, info = H.solve(b_g, tol=tol)
+    x = x_g.cpu().numpy().ravel()
+    assert info["status"] == 0
+    assert abs(info["iterations"] - res_o.iterations) <= 1, (info, res_o.iterations)
+    assert rel(x[asm_o.nodes], res_o.x) <= 1e-10
+    assert not np.any(x[asm_o.kind.ravel() != 2])
+    # residual recomputed by the oracle's own operator
+    assert np.linalg.norm(b_o - A @ x[asm_o.nodes]) <= tol * np.linalg.norm(b_o) * 1.0001
+    assert info["rel_res_true"] <= tol
+    H.free()
+
+
+def test_direct_solve_parity_config1():
+    """S-parity: tight tolerance against a sparse direct solve."""
+    prob = W.disk_poisson(128)
+    asm_o, A, b_o, u = oracle_system(prob)
+    xs = OP.direct_solve(A, b_o)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x_g, info = H.solve(b_g, tol=1e-13)
+    assert rel(x_g.cpu().numpy().ravel()[asm_o.nodes], xs) <= 1e-10
+    H.free()
+
+
+@pytest.mark.parametrize("n", [10, 13, 16])
+def test_dense_small_grids(n):
+    prob = W.disk_mms(n, radius=0.3)
+    asm_o, A, b_o, u = oracle_system(prob)
+    xd = np.linalg.solve(A.toarray(), b_o)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, coarse_max=4)
+    x_g, info = H.solve(b_g, tol=1e-13)
+    assert rel(x_g.cpu().numpy().ravel()[asm_o.nodes], xd) <= 1e-10
+    H.free()
+
+
+def test_full_size_ellipsoid_residual_property():
+    """Full 257^3 grid: the GPU solution's residual, recomputed by the oracle operator."""
+    prob = W.ellipsoid_poisson(256)
+    print("[gpu] pcg ell256 full", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x_g, info = H.solve(b_g, tol=1e-8)
+    x = x_g.cpu().numpy().ravel()[asm_o.nodes]
+    assert np.linalg.norm(b_o - A @ x) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
+    ue = W.u_ellipsoid(*prob.grid.mesh()).ravel()[asm_o.nodes]
+    assert np.max(np.abs(x - ue)) < 5e-3            # discretisation error at h = 1/256
+    H.free()
+
+
+def test_determinism_and_warm_start():
+    prob = W.star_poisson(600)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x1, i1 = H.solve(b_g, tol=1e-8)
+    x2, i2 = H.solve(b_g, tol=1e-8)
+    assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+    x3, i3 = H.solve(b_g, tol=1e-8, x0=x1)
+    assert i3["iterations"] == 0
+    x4, i4 = H.solve(b_g, tol=1e-10, x0=x1)
+    assert 0 < i4["iterations"] < i1["iterations"] + 5
+    H.free()
+
+
+def test_error_paths():
+    prob = W.star_poisson(256)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    with pytest.raises(L.EbError) as ei:
+        H.solve(b_g, tol=1e-12, maxit=1)
+    assert ei.value.code == L.EB_ENOCONV
+    x, info = H.solve(b_g, tol=1e-12, maxit=1, allow_noconv=True)
+    assert info["status"] == L.EB_ENOCONV and info["iterations"] == 1
+    xz, iz = H.solve(torch.zeros_like(b_g), tol=1e-8)
+    assert iz["iterations"] == 0 and not torch.any(xz).item()
+    with pytest.raises(L.EbError) as ei:
+        H.solve(b_g, tol=-1.0)
+    assert ei.value.code == L.EB_EINVAL
+    H.free()
+    # negative shift is rejected; a kind with an unknown on the outer layer is rejected
+    with pytest.raises(L.EbError):
+        S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, sigma=-1.0)
+    bad = asm_g.kind.clone()
+    bad[0, 5] = 2
+    with pytest.raises(L.EbError) as ei:
+        S.Hierarchy(prob.grid, bad, asm_g.a)
+    assert ei.value.code == L.EB_EDOMAIN
+
+
+def test_empty_system():
+    g = W.unit_box_grid(2, 32)
+    psi = np.ones(g.shape)
+    asm = S.assemble_diag(g, to_dev(psi))
+    H = S.Hierarchy(g, asm.kind, asm.a)
+    x, info = H.solve(torch.zeros(g.shape, dtype=torch.float64, device=DEV))
+    assert info["iterations"] == 0 and not torch.any(x).item()
+    H.free()

@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = the whole hot path on one synthetic problem.
+
+Workload (default): 2-D Poisson on the five-armed star r = 0.3 + 0.1 cos(5 phi)
+in [-0.5, 0.5]^2 with 2048 x 2048 cells (2049^2 nodes, 1,246,505 unknowns),
+manufactured u = exp(x) sin(4 pi y), plain FP64 AMG-PCG to relative residual
+1e-8.  psi and f are resident in HBM before timing starts; each step runs
+  classification + diagonal + cut records -> boundary data at the crossings
+  -> right-hand side -> AMG setup -> PCG solve
+entirely in the library's HIP kernels, and frees the hierarchy.
+
+Output: one JSON line (rank 0).  `value` = unknowns x CG iterations per second
+of whole-step time.  `roofline` reports the dominant solve kernel: its
+algorithmic bytes per launch over its average launch time, measured with HIP
+events on the library's stream inside the timed steps.  `cpu_baseline` times
+the CPU oracle on one full step of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
+       python bench.py --copy-calib    (plain copy kernel for counter scaling)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per fine unknown for each timed solve kernel (FP64 values,
+# int32 aggregate ids; every array touched once per launch).  The coarse-level
+# share of the restriction output / prolongation input is 8 B * n1 / n0.
+KERNEL_BYTES = {
+    "pcg_spmv": lambda n0, n1: 40.0 * n0,            # read z, p_old, d; write p, q
+    "pcg_xr": lambda n0, n1: 48.0 * n0,              # read x, p, r, q; write x, r
+    "fine_down": lambda n0, n1: 24.0 * n0,           # read r, d; write res
+    "fine_restrict": lambda n0, n1: 20.0 * n0 + 8.0 * n1,   # read res, d, agg; write r_c
+    "fine_up": lambda n0, n1: 28.0 * n0 + 8.0 * n1,  # read r, d, agg; gather e_c; write zt
+    "fine_post": lambda n0, n1: 32.0 * n0,           # read zt, r, d; write z
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kernel", default="pcg_spmv", choices=sorted(KERNEL_BYTES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--n", type=int, default=2048)
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of known size (for scaling FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    nbytes = 256 << 20
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "launches": 5}))
+
+
+def cpu_baseline(n):
+    """The oracle, as it stands, on one full step of the same workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import eb_assembly as E
+    from oracle import pcg as OP
+    from paper_2204_06083_amd import workloads as W
+
+    prob = W.star_poisson(n)
+    reps = 2
+    work = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            asm = E.assemble(prob.grid, prob.psi)
+            A = E.operator_csr(asm)
+            b = E.rhs(asm, prob.f, prob.u_dirichlet(*E.cut_coordinates(asm)))
+            res, H = OP.amg_pcg(A, E.unknown_coords(asm), b, tol=prob.tol)
+            work += asm.n_unknowns * res.iterations
+        t1 = time.perf_counter()
+    secs = t1 - t0
+    return {
+        "value": work / secs,
+        "unit": "unknowns·CG-iters/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{reps} full steps (assemble, RHS, AMG setup, PCG to 1e-8; {res.iterations} iterations each) "
+                  f"of the {n}^2 star workload in {secs:.2f} s, BLAS limited to 1 thread; host has "
+                  f"{len(os.sched_getaffinity(0))} usable cores",
+        "seconds": secs,
+        "iterations": res.iterations,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the solve is single-GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calib:
+        copy_calibration()
+        return
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    prob = W.star_poisson(args.n)
+    g = prob.grid
+    psi = torch.as_tensor(prob.psi, device=dev)
+    f = torch.as_tensor(prob.f, device=dev)
+    first = S.assemble_diag(g, psi)
+    cuts_cap = first.n_cuts
+    del first
+    torch.cuda.synchronize()
+
+    stats = {"iters": [], "setup_ms": [], "solve_ms": [], "rel_res_true": [], "levels": 0, "n1": 0}
+    timing = {"launches": 0, "ms": 0.0}
+
+    def step(measure):
+        ta = time.perf_counter()
+        asm = S.assemble_diag(g, psi, cuts_cap=cuts_cap)
+        u = W.u_star(*asm.cut_coordinates())
+        b = S.assemble_rhs(asm, f, u)
+        t_setup0 = time.perf_counter()
+        H = S.Hierarchy(g, asm.kind, asm.a, 0.0)
+        t_setup1 = time.perf_counter()
+        if measure:
+            H.time_kernel(args.kernel)
+        x, info = H.solve(b, tol=prob.tol)
+        if measure:
+            nl, ms = H.kernel_time()
+            timing["launches"] += nl
+            timing["ms"] += ms
+            stats["iters"].append(info["iterations"])
+            stats["setup_ms"].append((t_setup1 - t_setup0) * 1e3)
+            stats["solve_ms"].append(info["solve_ms"])
+            stats["rel_res_true"].append(info["rel_res_true"])
+            stats["levels"] = info["levels"]
+            stats["n1"] = H.level(1).n if H.n_levels > 1 else 0
+            stats["n0"] = asm.n_unknowns
+        H.free()
+        return asm.n_unknowns, info["iterations"], ta
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_work = 0
+    for _ in range(args.steps):
+        n0, its, _ = step(True)
+        total_work += n0 * its
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    ms_per_step = secs * 1e3 / args.steps
+    n0 = stats["n0"]
+    n1 = stats["n1"]
+    avg_launch_ms = timing["ms"] / max(timing["launches"], 1)
+    bytes_per_launch = KERNEL_BYTES[args.kernel](n0, n1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    mean_iters = sum(stats["iters"]) / len(stats["iters"])
+    mean_solve = sum(stats["solve_ms"]) / len(stats["solve_ms"])
+    out = {
+        "metric": "unknowns·CG-iters/s & solves/s to 1e-8 rel-res, learned/mixed vs plain FP64",
+        "value": total_work / secs,
+        "unit": "unknowns·CG-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"star2d_{args.n}_poisson_plain_fp64_amg_pcg_tol1e-8",
+                   "grid_nodes": f"{args.n + 1}x{args.n + 1}", "n_unknowns": n0, "tol": prob.tol,
+                   "precision": "plain FP64 (no mixed precision, no learned smoother)"},
+        "solves_per_s": args.steps / secs,
+        "iterations": mean_iters,
+        "levels": stats["levels"],
+        "setup_ms_host": sum(stats["setup_ms"]) / len(stats["setup_ms"]),
+        "solve_ms": mean_solve,
+        "solve_phase_unknowns_iters_per_s": n0 * mean_iters / (mean_solve * 1e-3),
+        "rel_res_true_max": max(stats["rel_res_true"]),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": args.kernel,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_launch_ms * 1e3,
+            "launches_timed": timing["launches"],
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -78,7 +78,9 @@ typedef struct {
     int32_t coarse_max;      /* solve densely once n <= coarse_max (default 256)  */
     int32_t max_levels;      /* hierarchy depth limit (default 16)                */
     double min_reduction;    /* stop coarsening if n_next > min_reduction * n (0.6) */
-    int32_t dense_limit;     /* refuse a dense coarsest level above this (8192)   */
+    int32_t dense_limit;     /* refuse a dense coarsest level above this (default
+                                and upper bound 1200: the factorisation keeps a
+                                16-column panel of the level in LDS)           */
     int32_t reserved;
 } amg_params_t;
 
@@ -180,6 +182,23 @@ int amg_num_levels(const amg_handle_t* H);
 int amg_level_info(const amg_handle_t* H, int level, amg_level_info_t* out);
 /* Fine-level node list: node_of_unknown[k] = flat node index of unknown k.    */
 const int64_t* amg_fine_nodes(const amg_handle_t* H);
+
+/* Measurement hook for benchmark harnesses (host calls).  While a kernel id
+ * is selected, every launch of that solve-phase kernel made through H is
+ * bracketed by HIP events on the stream it is launched on.  eb_timing_read
+ * synchronises that stream, returns the number of timed launches and their
+ * summed duration in ms, and resets both.  kernel_id < 0 disables timing.   */
+enum {
+    EB_K_PCG_SPMV = 0,      /* p <- z + beta p; q = A p; (p, q)                 */
+    EB_K_PCG_XR = 1,        /* x += alpha p; r -= alpha q; ||r||^2              */
+    EB_K_FINE_DOWN = 2,     /* fine pre-smoothing and residual                  */
+    EB_K_FINE_RESTRICT = 3, /* fine residual restriction P^T res                */
+    EB_K_FINE_UP = 4,       /* fine prolongation and correction                 */
+    EB_K_FINE_POST = 5,     /* fine post-smoothing and (r, z)                   */
+    EB_K_COUNT = 6
+};
+int eb_timing_select(amg_handle_t* H, int kernel_id);
+int eb_timing_read(amg_handle_t* H, int64_t* launches, double* total_ms);
 
 void amg_free(amg_handle_t* H);
 const char* eb_strerror(int code);

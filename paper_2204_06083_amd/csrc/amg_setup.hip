@@ -272,17 +272,20 @@ __global__ void __launch_bounds__(BLOCK) k_coarse_coords(const int32_t* __restri
     }
 }
 
+// Maximum of n non-negative int32 values into *out (pre-zeroed); integer
+// atomicMax is order independent, so the result is deterministic.
 __global__ void __launch_bounds__(BLOCK) k_max_i32(const int32_t* __restrict__ v, int64_t n, int32_t* __restrict__ out) {
     __shared__ int32_t lds[BLOCK];
     int32_t m = 0;
-    for (int64_t i = threadIdx.x; i < n; i += BLOCK) m = max(m, v[i]);
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        m = max(m, v[i]);
     lds[threadIdx.x] = m;
     __syncthreads();
     for (int off = BLOCK / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) lds[threadIdx.x] = max(lds[threadIdx.x], lds[threadIdx.x + off]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = lds[0];
+    if (threadIdx.x == 0) atomicMax(out, lds[0]);
 }
 
 // ----------------------------------------------------------------- Gershgorin
@@ -298,15 +301,19 @@ __global__ void __launch_bounds__(BLOCK) k_gershgorin_rows(const int32_t* __rest
     rowv[i] = s / diag[i];
 }
 
-__global__ void __launch_bounds__(BLOCK) k_max_f64(const double* __restrict__ v, int64_t n, double* __restrict__ out,
-                                                   int32_t* __restrict__ err) {
+// Maximum of n positive doubles into *out (pre-zeroed bit pattern): for
+// non-negative IEEE doubles the bit patterns order like the values, so an
+// unsigned 64-bit atomicMax gives the exact, order-independent maximum.
+// Non-positive, NaN or infinite entries raise DEVERR_NOTSPD.
+__global__ void __launch_bounds__(BLOCK) k_max_f64(const double* __restrict__ v, int64_t n,
+                                                   unsigned long long* __restrict__ out, int32_t* __restrict__ err) {
     __shared__ double lds[BLOCK];
     double m = 0.0;
     bool bad = false;
-    for (int64_t i = threadIdx.x; i < n; i += BLOCK) {
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
         const double x = v[i];
-        if (!(x > 0.0) || isinf(x)) bad = true;   // a_ii <= 0 or NaN/Inf
-        m = fmax(m, x);
+        if (!(x > 0.0) || isinf(x)) bad = true;
+        else m = fmax(m, x);
     }
     lds[threadIdx.x] = m;
     if (bad) atomicOr(err, DEVERR_NOTSPD);
@@ -315,7 +322,7 @@ __global__ void __launch_bounds__(BLOCK) k_max_f64(const double* __restrict__ v,
         if ((int)threadIdx.x < off) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + off]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = lds[0];
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(lds[0]));
 }
 
 // ------------------------------------------------------- slot accumulators
@@ -520,50 +527,85 @@ __global__ void __launch_bounds__(BLOCK) k_csr_to_dense(const int32_t* __restric
     for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) dense[i * n + col[e]] = val[e];
 }
 
-// Right-looking Cholesky in place (lower triangle), one workgroup.
-__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ Ad, int n, int32_t* __restrict__ err) {
-    __shared__ double piv;
+// Blocked right-looking Cholesky in place (lower triangle of the row-major
+// n x n matrix), one workgroup.  Each 16-column panel is copied to LDS and
+// factored there; the trailing update reads the panel from LDS.
+constexpr int CHOL_NB = 16;
+constexpr int CHOL_THREADS = 1024;
+
+__global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ Ad, int n, int32_t* __restrict__ err) {
+    extern __shared__ double panel[];   // (n) x CHOL_NB, row-major by panel row
     __shared__ int fail;
     if (threadIdx.x == 0) fail = 0;
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double dkk = Ad[(int64_t)k * n + k];
-            if (!(dkk > 0.0)) {
-                fail = 1;
-                piv = 1.0;
-            } else {
-                piv = sqrt(dkk);
-            }
-            Ad[(int64_t)k * n + k] = piv;
+    for (int k0 = 0; k0 < n; k0 += CHOL_NB) {
+        const int kb = min(CHOL_NB, n - k0);
+        const int rows = n - k0;
+        for (int e = threadIdx.x; e < rows * CHOL_NB; e += blockDim.x) {
+            const int r = e / CHOL_NB, c = e % CHOL_NB;
+            panel[e] = c < kb ? Ad[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
         }
         __syncthreads();
+        for (int c = 0; c < kb; ++c) {
+            if (threadIdx.x == 0) {
+                const double dcc = panel[c * CHOL_NB + c];
+                if (!(dcc > 0.0)) fail = 1;
+                panel[c * CHOL_NB + c] = dcc > 0.0 ? sqrt(dcc) : 1.0;
+            }
+            __syncthreads();
+            const double piv = panel[c * CHOL_NB + c];
+            for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) panel[r * CHOL_NB + c] /= piv;
+            __syncthreads();
+            // update the remaining panel columns
+            const int rem = kb - c - 1;
+            for (int e = threadIdx.x; e < (rows - c - 1) * rem; e += blockDim.x) {
+                const int r = c + 1 + e / rem;
+                const int c2 = c + 1 + e % rem;
+                if (c2 <= r) panel[r * CHOL_NB + c2] -= panel[r * CHOL_NB + c] * panel[c2 * CHOL_NB + c];
+            }
+            __syncthreads();
+        }
         if (fail) break;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) Ad[(int64_t)i * n + k] = Ad[(int64_t)i * n + k] / piv;
-        __syncthreads();
-        const int m = n - k - 1;
-        // trailing update of the lower triangle, (i, j) with k < j <= i < n
-        for (int64_t w = threadIdx.x; w < (int64_t)m * m; w += blockDim.x) {
-            const int i = k + 1 + (int)(w / m);
-            const int j = k + 1 + (int)(w % m);
+        for (int e = threadIdx.x; e < rows * kb; e += blockDim.x) {
+            const int r = e / kb, c = e % kb;
+            if (c <= r) Ad[(int64_t)(k0 + r) * n + k0 + c] = panel[r * CHOL_NB + c];
+        }
+        // trailing update of the lower triangle: A[i][j] -= sum_c P[i][c] P[j][c], k0+kb <= j <= i
+        const int t0 = k0 + kb;
+        const int m = n - t0;
+        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+            const int i = t0 + (int)(e / m);
+            const int j = t0 + (int)(e % m);
             if (j > i) continue;
-            Ad[(int64_t)i * n + j] = Ad[(int64_t)i * n + j] - Ad[(int64_t)i * n + k] * Ad[(int64_t)j * n + k];
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < CHOL_NB; ++c) acc += panel[(i - k0) * CHOL_NB + c] * panel[(j - k0) * CHOL_NB + c];
+            Ad[(int64_t)i * n + j] -= acc;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0 && fail) atomicOr(err, DEVERR_NOTSPD);
 }
 
-// Linv column c by forward substitution (one thread per column).
-__global__ void __launch_bounds__(BLOCK) k_tri_inverse(const double* __restrict__ Lf, int n,
-                                                       double* __restrict__ Li) {
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= n) return;
-    for (int i = 0; i < c; ++i) Li[(int64_t)i * n + c] = 0.0;
-    for (int i = c; i < n; ++i) {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) s = s - Lf[(int64_t)i * n + k] * Li[(int64_t)k * n + c];
-        Li[(int64_t)i * n + c] = s / Lf[(int64_t)i * n + i];
+// Linv = L^-1 by forward substitution on identity columns: each thread owns
+// one column, kept in LDS; rows of L are read from global memory (uniform
+// across the wavefront).
+__global__ void k_tri_inverse(const double* __restrict__ Lf, int n, int cols_per_block, double* __restrict__ Li) {
+    extern __shared__ double ycol[];      // n x cols_per_block
+    const int t = threadIdx.x;
+    const int c = blockIdx.x * cols_per_block + t;
+    const bool live = t < cols_per_block && c < n;
+    if (live) {
+        for (int i = 0; i < n; ++i) {
+            double v = 0.0;
+            if (i >= c) {
+                double acc = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) acc -= Lf[(int64_t)i * n + k] * ycol[k * cols_per_block + t];
+                v = acc / Lf[(int64_t)i * n + i];
+            }
+            ycol[i * cols_per_block + t] = v;
+        }
+        for (int i = 0; i < n; ++i) Li[(int64_t)i * n + c] = ycol[i * cols_per_block + t];
     }
 }
 
@@ -586,6 +628,12 @@ __global__ void __launch_bounds__(BLOCK) k_compact(const int32_t* __restrict__ f
 }
 
 // ------------------------------------------------------------- host helpers
+static unsigned max_grid(int64_t n) {
+    int64_t g = (n + BLOCK - 1) / BLOCK;
+    if (g > 1024) g = 1024;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
 static int check_err(const int32_t* derr, hipStream_t s, const char* where) {
     int32_t e = 0;
     EB_TRY(read_device_i32(derr, &e, s));
@@ -675,11 +723,20 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
     hipLaunchKernelGGL(k_csr_to_dense, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, n, dense);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, dense, (int)n, err);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CHOL_THREADS), sizeof(double) * n * CHOL_NB, s, dense, (int)n,
+                       err);
     EB_LAUNCH_CHECK();
     EB_TRY(check_err(err, s, "coarsest Cholesky"));
-    hipLaunchKernelGGL(k_tri_inverse, dim3(grid_for(n)), dim3(BLOCK), 0, s, dense, (int)n, linv);
-    EB_LAUNCH_CHECK();
+    {
+        int cpb = (int)((150 * 1024) / (sizeof(double) * n));
+        if (cpb > 64) cpb = 64;
+        if (cpb < 1) cpb = 1;
+        const unsigned nb = (unsigned)((n + cpb - 1) / cpb);
+        const unsigned nthreads = (unsigned)((cpb + WAVE - 1) / WAVE * WAVE);
+        hipLaunchKernelGGL(k_tri_inverse, dim3(nb), dim3(nthreads), sizeof(double) * n * cpb, s, dense, (int)n, cpb,
+                           linv);
+        EB_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_gram, dim3(grid_for(n * n)), dim3(BLOCK), 0, s, linv, (int)n, L.dense_inv);
     EB_LAUNCH_CHECK();
     EB_TRY(dfree(dense, s));
@@ -727,7 +784,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
     EB_TRY(check_err(err, s, "aggregation"));
     int32_t* dmax = nullptr;
     EB_TRY(dalloc_n(&dmax, 1, s));
-    hipLaunchKernelGGL(k_max_i32, dim3(1), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dmax);
+    EB_HIP(hipMemsetAsync(dmax, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_max_i32, dim3(max_grid(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dmax);
     EB_LAUNCH_CHECK();
     int32_t maxc = 0;
     EB_TRY(read_device_i32(dmax, &maxc, s));
@@ -759,13 +817,14 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
 
     // Gershgorin bound and smoothing weight
     double* rowv = nullptr;
-    double* drho = nullptr;
+    unsigned long long* drho = nullptr;
     EB_TRY(dalloc_n(&rowv, n, s));
     EB_TRY(dalloc_n(&drho, 1, s));
+    EB_HIP(hipMemsetAsync(drho, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_gershgorin_rows, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, L.diag,
                        n, rowv);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_max_f64, dim3(1), dim3(BLOCK), 0, s, rowv, n, drho, err);
+    hipLaunchKernelGGL(k_max_f64, dim3(max_grid(n)), dim3(BLOCK), 0, s, rowv, n, drho, err);
     EB_LAUNCH_CHECK();
     EB_HIP(hipMemcpyAsync(&L.rho, drho, sizeof(double), hipMemcpyDeviceToHost, s));
     EB_HIP(hipStreamSynchronize(s));
@@ -853,9 +912,15 @@ int free_handle_memory(amg_handle* H) {
     hipStream_t s = H->stream;
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
     void* ptrs[] = {H->strips, H->boxes0, H->fine_nodes, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, H->x, H->r,
-                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->red.partials, H->red.ticket};
+                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->red.pq, H->red.rr,
+                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2};
     for (void* p : ptrs) (void)dfree(p, s);
     if (H->sc_host) (void)hipHostFree(H->sc_host);
+    if (H->tim_ev) {
+        for (int i = 0; i < 2 * H->tim_cap; ++i) (void)hipEventDestroy(H->tim_ev[i]);
+        delete[] H->tim_ev;
+        H->tim_ev = nullptr;
+    }
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     EB_HIP(hipStreamSynchronize(s));
@@ -948,7 +1013,7 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
     prm.coarse_max = 256;
     prm.max_levels = 16;
     prm.min_reduction = 0.6;
-    prm.dense_limit = 4096;
+    prm.dense_limit = 1200;
     prm.reserved = 0;
     if (p) {
         prm = *p;
@@ -957,7 +1022,7 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
             set_error("amg_setup: invalid parameters");
             return EB_EINVAL;
         }
-        if (prm.dense_limit > 8192) prm.dense_limit = 8192;
+        if (prm.dense_limit > 1200) prm.dense_limit = 1200;
     }
     amg_handle* H = new (std::nothrow) amg_handle();
     if (!H) {

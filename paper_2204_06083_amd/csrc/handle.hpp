@@ -32,26 +32,29 @@ struct Level {
     double* rv = nullptr; double* res = nullptr; double* zt = nullptr; double* ev = nullptr;
 };
 
-// Device scalars of one PCG solve.
+// Device scalars of one PCG solve.  Written only by block 0 of the kernel
+// that owns each field (or by a one-block finaliser) and read by later kernels.
 struct PcgScalars {
-    double rho;        // (r, z) of the current iterate
-    double beta;       // p <- z + beta p
-    double alpha;
-    double pq;
-    double rr;         // ||r||^2
+    double rr;         // ||r||^2 of the latest iterate
     double bb;         // ||b||^2
     double tol2bb;     // tol^2 ||b||^2
-    double rz_new;
+    double pq;         // (p, q) of the latest iteration
+    double rr_true;    // ||b - A x||^2 recomputed at exit
     int32_t done;      // 1: converged / failed, later kernels return at once
     int32_t status;    // EB_OK or failure code
     int32_t iters;
-    int32_t rho_valid;
+    int32_t pad;
 };
 
+// One partial sum per block of the fixed-size fine grid; consumers sum them
+// in a fixed order (every block of the consumer gets the same total).
 struct Reduction {
-    double* partials = nullptr;
-    unsigned int* ticket = nullptr;
-    int64_t cap = 0;
+    int nparts = 0;             // blocks of every reducing fine kernel
+    double* pq = nullptr;
+    double* rr = nullptr;
+    double* rz[2] = {nullptr, nullptr};
+    double* aux = nullptr;
+    double* aux2 = nullptr;
 };
 
 }  // namespace eb
@@ -86,4 +89,12 @@ struct amg_handle {
     eb::PcgScalars* sc_host = nullptr;   // pinned mirror
     eb::Reduction red;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // kernel timing hook (eb_timing_select / eb_timing_read)
+    int tim_kernel = -1;
+    int tim_cap = 0;
+    int tim_used = 0;
+    hipEvent_t* tim_ev = nullptr;     // 2 * tim_cap events
+    hipStream_t tim_stream = nullptr;
+    int64_t tim_launches = 0;
+    double tim_ms = 0.0;
 };

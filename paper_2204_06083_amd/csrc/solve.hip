@@ -10,11 +10,14 @@
 // applied matrix-free from the aggregate map.  Coarse levels use CSR; the
 // coarsest applies its dense inverse.
 //
-// PCG scalars (alpha, beta, norms) live on the device; reductions write one
-// partial per block and the last block to finish sums the partials in a fixed
-// order (deterministic, no floating-point atomics), then updates the scalars.
-// Once a finaliser marks the solve done, every later kernel of the queued
-// iterations returns at once; the host polls the flag every few iterations.
+// Reductions: every reducing fine kernel runs a fixed grid of `nparts` blocks
+// (grid-stride over the strips) and writes one partial per block.  The kernel
+// that needs the scalar sums those partials itself, in a fixed order, in every
+// block, so all blocks agree bit for bit and no cross-block synchronisation,
+// fence or atomic is needed.  PCG scalars (alpha, beta, convergence) are thus
+// formed on the device; block 0 records them for the host, which polls the
+// `done` flag every few iterations.  Once `done` is set, every queued kernel
+// returns at once.
 #include <math.h>
 #include <string.h>
 
@@ -22,11 +25,12 @@
 
 namespace eb {
 
-constexpr int NT = 256;   // threads per block of every solve kernel
+constexpr int NT = 256;        // threads per block of every solve kernel
+constexpr int MAX_PARTS = 1024;
 
 struct FineArgs {
     const int32_t* strips;
-    int64_t nstrips;
+    int64_t nthreads;     // nstrips * strip_w virtual threads
     int strip_w;
     int64_t sy, sz;       // padded strides
     int dim;
@@ -34,14 +38,15 @@ struct FineArgs {
     const double* diag;   // padded, 0 off unknowns
 };
 
-__device__ inline int64_t fine_node(const FineArgs& f, bool& active) {
-    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+__device__ inline int64_t strip_node(const FineArgs& f, int64_t gid) {
     const int64_t sidx = gid / f.strip_w;
-    const int lane = (int)(gid - sidx * f.strip_w);
-    active = sidx < f.nstrips;
-    if (!active) return 0;
-    return (int64_t)f.strips[sidx] * f.strip_w + lane;
+    return (int64_t)f.strips[sidx] * f.strip_w + (gid - sidx * f.strip_w);
 }
+
+#define FINE_LOOP(f, p)                                                                         \
+    for (int64_t gid_ = (int64_t)blockIdx.x * NT + threadIdx.x; gid_ < (f).nthreads;            \
+         gid_ += (int64_t)gridDim.x * NT)                                                        \
+        for (int64_t p = strip_node((f), gid_), once_ = 0; once_ < 1; ++once_)
 
 __device__ inline double nbr_sum(const double* __restrict__ v, int64_t p, const FineArgs& f) {
     double t = v[p - 1] + v[p + 1];
@@ -61,96 +66,51 @@ __device__ inline double nbr_sum_scaled(const double* __restrict__ v, int64_t p,
 }
 
 // ------------------------------------------------------------ reductions
-enum FinKind {
-    FIN_PQ = 0,      // (p, q) -> alpha
-    FIN_RR = 1,      // ||r||^2 -> convergence test, iteration count
-    FIN_RZ = 2,      // (r, z) -> beta, rho
-    FIN_BB = 3,      // ||b||^2
-    FIN_RR0 = 4,     // initial / true ||r||^2 (no iteration count)
-};
-
-__device__ inline void finalize(int kind, double v, PcgScalars* sc) {
-    switch (kind) {
-        case FIN_PQ:
-            sc->pq = v;
-            if (!(v > 0.0) || isinf(v)) {
-                sc->status = isnan(v) || isinf(v) ? EB_ENAN : EB_ENOTSPD;
-                sc->done = 1;
-            } else {
-                sc->alpha = sc->rho / v;
-            }
-            break;
-        case FIN_RR:
-            sc->rr = v;
-            sc->iters += 1;
-            if (isnan(v) || isinf(v)) {
-                sc->status = EB_ENAN;
-                sc->done = 1;
-            } else if (v <= sc->tol2bb) {
-                sc->done = 1;
-            }
-            break;
-        case FIN_RZ:
-            if (isnan(v) || isinf(v)) {
-                sc->status = EB_ENAN;
-                sc->done = 1;
-            } else if (!(v > 0.0)) {
-                sc->status = EB_ENOTSPD;
-                sc->done = 1;
-            } else {
-                sc->beta = sc->rho_valid ? v / sc->rho : 0.0;
-                sc->rho = v;
-                sc->rho_valid = 1;
-            }
-            sc->rz_new = v;
-            break;
-        case FIN_BB:
-            sc->bb = v;
-            break;
-        case FIN_RR0:
-            sc->rr = v;
-            break;
-    }
-}
-
-// Every thread of the block calls this with its contribution.
-__device__ inline void block_reduce_finalize(double v, int kind, double* partials, unsigned int* ticket,
-                                             PcgScalars* sc) {
+__device__ inline void block_partial(double v, double* __restrict__ part) {
     __shared__ double lds[NT / WAVE];
-    __shared__ double lds2[NT / WAVE];
-    __shared__ int last;
-    const double bsum = block_sum<NT>(v, lds);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = bsum;
-        __threadfence();
-        const unsigned int t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        double acc = 0.0;
-        for (unsigned int i = threadIdx.x; i < gridDim.x; i += NT) acc += partials[i];
-        const double tot = block_sum<NT>(acc, lds2);
-        if (threadIdx.x == 0) {
-            finalize(kind, tot, sc);
-            *ticket = 0u;
-        }
-    }
+    const double s = block_sum<NT>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// ------------------------------------------------------------ fine kernels
+// Sum of np partials in a fixed order; every thread of the block gets it.
+__device__ inline double block_total(const double* __restrict__ part, int np) {
+    __shared__ double lds[NT / WAVE];
+    __shared__ double tot;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < np; i += NT) a += part[i];
+    a = block_sum<NT>(a, lds);
+    if (threadIdx.x == 0) tot = a;
+    __syncthreads();
+    const double r = tot;
+    __syncthreads();
+    return r;
+}
+
+__device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+__device__ inline bool bad_value(double v) { return isnan(v) || isinf(v); }
+
+// ------------------------------------------------------------ PCG kernels
 // p_new = z + beta p_old; q = A p_new; partial (p_new, q).
+// rho = (r, z) of the latest V-cycle, beta = rho / rho_prev (0 on the first).
 __global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const double* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
-                                                   double* __restrict__ q, PcgScalars* sc, double* partials,
-                                                   unsigned int* ticket) {
+                                                   double* __restrict__ q, const double* __restrict__ rz_cur,
+                                                   const double* __restrict__ rz_prev, int np,
+                                                   double* __restrict__ part_pq, PcgScalars* sc) {
     if (sc->done) return;
-    const double beta = sc->beta;
-    bool active;
-    const int64_t p = fine_node(f, active);
+    const double rho = block_total(rz_cur, np);
+    double beta = 0.0;
+    if (rz_prev) beta = rho / block_total(rz_prev, np);
+    if (!(rho > 0.0) || bad_value(rho) || bad_value(beta)) {
+        if (lead()) {
+            sc->status = (bad_value(rho) || bad_value(beta)) ? EB_ENAN : EB_ENOTSPD;
+            sc->done = 1;
+        }
+        return;
+    }
     double part = 0.0;
-    if (active) {
+    FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
             const double pc = z[p] + beta * pold[p];
@@ -165,42 +125,79 @@ __global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const double* __r
             const double qv = d * pc - f.s * nb;
             pnew[p] = pc;
             q[p] = qv;
-            part = pc * qv;
+            part += pc * qv;
         }
     }
-    block_reduce_finalize(part, FIN_PQ, partials, ticket, sc);
+    block_partial(part, part_pq);
 }
 
-// x += alpha p; r -= alpha q; partial ||r||^2.
+// alpha = rho / (p, q); x += alpha p; r -= alpha q; partial ||r||^2.
 __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ x, double* __restrict__ r,
                                                const double* __restrict__ pv, const double* __restrict__ q,
-                                               PcgScalars* sc, double* partials, unsigned int* ticket) {
+                                               const double* __restrict__ rz_cur, const double* __restrict__ part_pq,
+                                               int np, double* __restrict__ part_rr, PcgScalars* sc, int iter) {
     if (sc->done) return;
-    const double alpha = sc->alpha;
-    bool active;
-    const int64_t p = fine_node(f, active);
-    double part = 0.0;
-    if (active && f.diag[p] != 0.0) {
-        x[p] = x[p] + alpha * pv[p];
-        const double rv = r[p] - alpha * q[p];
-        r[p] = rv;
-        part = rv * rv;
+    const double rho = block_total(rz_cur, np);
+    const double pq = block_total(part_pq, np);
+    if (!(pq > 0.0) || bad_value(pq)) {
+        if (lead()) {
+            sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
+            sc->done = 1;
+        }
+        return;
     }
-    block_reduce_finalize(part, FIN_RR, partials, ticket, sc);
+    const double alpha = rho / pq;
+    if (lead()) {
+        sc->iters = iter;
+        sc->pq = pq;
+    }
+    double part = 0.0;
+    FINE_LOOP(f, p) {
+        if (f.diag[p] != 0.0) {
+            x[p] = x[p] + alpha * pv[p];
+            const double rv = r[p] - alpha * q[p];
+            r[p] = rv;
+            part += rv * rv;
+        }
+    }
+    block_partial(part, part_rr);
 }
 
+// Convergence test on ||r||^2 (partials of the previous kernel); true if the
+// caller must return.
+__device__ inline bool converged_or_failed(const double* __restrict__ part_rr, int np, PcgScalars* sc) {
+    const double rr = block_total(part_rr, np);
+    if (bad_value(rr)) {
+        if (lead()) {
+            sc->status = EB_ENAN;
+            sc->done = 1;
+        }
+        return true;
+    }
+    if (lead()) sc->rr = rr;
+    if (rr <= sc->tol2bb) {
+        if (lead()) sc->done = 1;
+        return true;
+    }
+    return false;
+}
+
+// ------------------------------------------------------------ fine V-cycle
 // Pre-smoothing and residual: z1 = omega r / d (not stored), res = r - A z1.
+// With `check`, first test convergence of the iterate that produced r.
 __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, const double* __restrict__ r,
-                                                  double* __restrict__ res, const PcgScalars* sc) {
+                                                  double* __restrict__ res, PcgScalars* sc, int check,
+                                                  const double* __restrict__ part_rr, int np) {
     if (sc->done) return;
-    bool active;
-    const int64_t p = fine_node(f, active);
-    if (!active) return;
-    const double d = f.diag[p];
-    if (d == 0.0) return;
-    const double z1 = omega * r[p] / d;
-    const double nb = omega * nbr_sum_scaled(r, p, f);
-    res[p] = r[p] - (d * z1 - f.s * nb);
+    if (check && converged_or_failed(part_rr, np, sc)) return;
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double z1 = omega * r[p] / d;
+            const double nb = omega * nbr_sum_scaled(r, p, f);
+            res[p] = r[p] - (d * z1 - f.s * nb);
+        }
+    }
 }
 
 // Restriction r_c = P^T res = P_tent^T (I - omega A D^-1) res, one thread per
@@ -263,73 +260,90 @@ __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const 
                                                 const double* __restrict__ ec, const double* __restrict__ r,
                                                 double* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
-    bool active;
-    const int64_t p = fine_node(f, active);
-    if (!active) return;
-    const double d = f.diag[p];
-    if (d == 0.0) return;
-    const double tp = ec[agg[p]];
-    int32_t g;
-    double nb = 0.0;
-    g = agg[p - 1];      nb += g >= 0 ? ec[g] : 0.0;
-    g = agg[p + 1];      nb += g >= 0 ? ec[g] : 0.0;
-    g = agg[p - f.sy];   nb += g >= 0 ? ec[g] : 0.0;
-    g = agg[p + f.sy];   nb += g >= 0 ? ec[g] : 0.0;
-    if (f.dim == 3) {
-        g = agg[p - f.sz]; nb += g >= 0 ? ec[g] : 0.0;
-        g = agg[p + f.sz]; nb += g >= 0 ? ec[g] : 0.0;
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double tp = ec[agg[p]];
+            int32_t g;
+            double nb = 0.0;
+            g = agg[p - 1];      nb += g >= 0 ? ec[g] : 0.0;
+            g = agg[p + 1];      nb += g >= 0 ? ec[g] : 0.0;
+            g = agg[p - f.sy];   nb += g >= 0 ? ec[g] : 0.0;
+            g = agg[p + f.sy];   nb += g >= 0 ? ec[g] : 0.0;
+            if (f.dim == 3) {
+                g = agg[p - f.sz]; nb += g >= 0 ? ec[g] : 0.0;
+                g = agg[p + f.sz]; nb += g >= 0 ? ec[g] : 0.0;
+            }
+            const double at = d * tp - f.s * nb;
+            zt[p] = omega * r[p] / d + (tp - omega * at / d);
+        }
     }
-    const double at = d * tp - f.s * nb;
-    zt[p] = omega * r[p] / d + (tp - omega * at / d);
 }
 
 // Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z).
 __global__ void __launch_bounds__(NT) k_fine_post(FineArgs f, double omega, const double* __restrict__ zt,
                                                   const double* __restrict__ r, double* __restrict__ z,
-                                                  PcgScalars* sc, double* partials, unsigned int* ticket) {
+                                                  double* __restrict__ part_rz, const PcgScalars* sc) {
     if (sc->done) return;
-    bool active;
-    const int64_t p = fine_node(f, active);
     double part = 0.0;
-    if (active) {
+    FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
             const double az = d * zt[p] - f.s * nbr_sum(zt, p, f);
             const double zv = zt[p] + omega * (r[p] - az) / d;
             z[p] = zv;
-            part = r[p] * zv;
+            part += r[p] * zv;
         }
     }
-    block_reduce_finalize(part, FIN_RZ, partials, ticket, sc);
+    block_partial(part, part_rz);
 }
 
-// res = b - A x on padded fields (true residual), partial ||res||^2.
+// out = b - A x (padded fields), partial ||out||^2.
 __global__ void __launch_bounds__(NT) k_fine_resid(FineArgs f, const double* __restrict__ bp,
                                                    const double* __restrict__ x, double* __restrict__ out,
-                                                   PcgScalars* sc, double* partials, unsigned int* ticket) {
-    bool active;
-    const int64_t p = fine_node(f, active);
-    double part = 0.0;
-    if (active) {
+                                                   double* __restrict__ part) {
+    double acc = 0.0;
+    FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
             const double ax = d * x[p] - f.s * nbr_sum(x, p, f);
             const double rv = bp[p] - ax;
             out[p] = rv;
-            part = rv * rv;
+            acc += rv * rv;
         }
     }
-    block_reduce_finalize(part, FIN_RR0, partials, ticket, sc);
+    block_partial(acc, part);
 }
 
-// partial ||v||^2 over unknowns
-__global__ void __launch_bounds__(NT) k_fine_norm2(FineArgs f, const double* __restrict__ v, int kind,
-                                                   PcgScalars* sc, double* partials, unsigned int* ticket) {
-    bool active;
-    const int64_t p = fine_node(f, active);
-    double part = 0.0;
-    if (active && f.diag[p] != 0.0) part = v[p] * v[p];
-    block_reduce_finalize(part, kind, partials, ticket, sc);
+__global__ void __launch_bounds__(NT) k_fine_norm2(FineArgs f, const double* __restrict__ v,
+                                                   double* __restrict__ part) {
+    double acc = 0.0;
+    FINE_LOOP(f, p) {
+        if (f.diag[p] != 0.0) acc += v[p] * v[p];
+    }
+    block_partial(acc, part);
+}
+
+// One block: ||b||^2, ||r0||^2, tolerance and the initial convergence test.
+__global__ void __launch_bounds__(NT) k_finalize_init(PcgScalars* sc, const double* __restrict__ part_bb,
+                                                      const double* __restrict__ part_rr, int np, double tol,
+                                                      int iters) {
+    const double bb = block_total(part_bb, np);
+    const double rr = block_total(part_rr, np);
+    if (threadIdx.x == 0) {
+        sc->bb = bb;
+        sc->rr = rr;
+        sc->tol2bb = tol * tol * bb;
+        sc->status = (bad_value(bb) || bad_value(rr)) ? EB_ENAN : EB_OK;
+        sc->done = (bb == 0.0 || rr <= tol * tol * bb || sc->status != EB_OK) ? 1 : 0;
+        sc->iters = iters;
+        sc->pq = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_finalize_true(PcgScalars* sc, const double* __restrict__ part, int np) {
+    const double rr = block_total(part, np);
+    if (threadIdx.x == 0) sc->rr_true = rr;
 }
 
 // ------------------------------------------------------------ coarse kernels
@@ -403,29 +417,30 @@ __global__ void __launch_bounds__(NT) k_dense_apply(int64_t n, const double* __r
     if (lane == 0) ev[row] = acc;
 }
 
-// Gather the padded fine field into compact order and back (one-level
-// hierarchies, where the fine level is also the coarsest).
+// One-level hierarchies (fine level = coarsest): gather r into compact order
+// (after the convergence test) and scatter z back with the (r, z) partials.
 __global__ void __launch_bounds__(NT) k_gather(int64_t n, const int32_t* __restrict__ pad,
                                                const double* __restrict__ src, double* __restrict__ dst,
-                                               const PcgScalars* sc) {
+                                               PcgScalars* sc, int check, const double* __restrict__ part_rr,
+                                               int np) {
     if (sc->done) return;
-    const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (k < n) dst[k] = src[pad[k]];
+    if (check && converged_or_failed(part_rr, np, sc)) return;
+    for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT)
+        dst[k] = src[pad[k]];
 }
 
 __global__ void __launch_bounds__(NT) k_scatter_dot(int64_t n, const int32_t* __restrict__ pad,
                                                     const double* __restrict__ ev, const double* __restrict__ r,
-                                                    double* __restrict__ z, PcgScalars* sc, double* partials,
-                                                    unsigned int* ticket) {
+                                                    double* __restrict__ z, double* __restrict__ part_rz,
+                                                    const PcgScalars* sc) {
     if (sc->done) return;
-    const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
     double part = 0.0;
-    if (k < n) {
+    for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
         const int32_t p = pad[k];
         z[p] = ev[k];
-        part = r[p] * ev[k];
+        part += r[p] * ev[k];
     }
-    block_reduce_finalize(part, FIN_RZ, partials, ticket, sc);
+    block_partial(part, part_rz);
 }
 
 // ---------------------------------------------------- layout conversion
@@ -443,24 +458,11 @@ __global__ void __launch_bounds__(NT) k_store_field(int64_t n, const int64_t* __
     if (k < n) dst[nodes[k]] = src[pad[k]];
 }
 
-__global__ void k_init_scalars(PcgScalars* sc, double tol, int keep_iters) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int it = keep_iters ? sc->iters : 0;
-    const double bb = sc->bb;
-    sc->rho = 0.0;
-    sc->beta = 0.0;
-    sc->alpha = 0.0;
-    sc->pq = 0.0;
-    sc->rz_new = 0.0;
-    sc->tol2bb = tol * tol * bb;
-    sc->done = (bb == 0.0 || sc->rr <= sc->tol2bb) ? 1 : 0;
-    sc->status = EB_OK;
-    sc->iters = it;
-    sc->rho_valid = 0;
-}
-
 __global__ void k_mark_running(PcgScalars* sc) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->done = 0;
+        sc->status = EB_OK;
+    }
 }
 
 __global__ void __launch_bounds__(NT) k_copy_f64(int64_t n, const double* __restrict__ src, double* __restrict__ dst) {
@@ -502,10 +504,48 @@ __global__ void __launch_bounds__(BLOCK) k_compact_list(const int32_t* __restric
 
 
 // ------------------------------------------------------------- host side
+// Kernel timing hook: harvest completed event pairs into the accumulators.
+static int timing_harvest(amg_handle* H) {
+    if (H->tim_used == 0) return EB_OK;
+    EB_HIP(hipStreamSynchronize(H->tim_stream));
+    for (int i = 0; i < H->tim_used; ++i) {
+        float ms = 0.f;
+        EB_HIP(hipEventElapsedTime(&ms, H->tim_ev[2 * i], H->tim_ev[2 * i + 1]));
+        H->tim_ms += ms;
+        H->tim_launches += 1;
+    }
+    H->tim_used = 0;
+    return EB_OK;
+}
+
+static int timing_begin(amg_handle* H, int id, hipStream_t s, bool* on) {
+    *on = H->tim_kernel == id;
+    if (!*on) return EB_OK;
+    if (H->tim_used == H->tim_cap) EB_TRY(timing_harvest(H));
+    H->tim_stream = s;
+    EB_HIP(hipEventRecord(H->tim_ev[2 * H->tim_used], s));
+    return EB_OK;
+}
+
+static int timing_end(amg_handle* H, bool on, hipStream_t s) {
+    if (!on) return EB_OK;
+    EB_HIP(hipEventRecord(H->tim_ev[2 * H->tim_used + 1], s));
+    H->tim_used += 1;
+    return EB_OK;
+}
+
+#define EB_TIMED(H, id, s, launch)                    \
+    do {                                             \
+        bool on_;                                    \
+        EB_TRY(timing_begin((H), (id), (s), &on_));  \
+        launch;                                      \
+        EB_TRY(timing_end((H), on_, (s)));           \
+    } while (0)
+
 static FineArgs fine_args(const amg_handle* H) {
     FineArgs f;
     f.strips = H->strips;
-    f.nstrips = H->nstrips;
+    f.nthreads = H->nstrips * H->strip_w;
     f.strip_w = H->strip_w;
     f.sy = H->px;
     f.sz = (int64_t)H->px * H->d.ny;
@@ -513,11 +553,6 @@ static FineArgs fine_args(const amg_handle* H) {
     f.s = H->d.s;
     f.diag = H->diag_p;
     return f;
-}
-
-static unsigned fine_grid(const amg_handle* H) {
-    const int64_t threads = H->nstrips * H->strip_w;
-    return grid_for(threads, NT);
 }
 
 static BoxArgs box_args(const amg_handle* H) {
@@ -536,67 +571,90 @@ static BoxArgs box_args(const amg_handle* H) {
     return b;
 }
 
-// z = M r on padded fine fields; the last kernel also reduces (r, z).
-static int enqueue_vcycle(amg_handle* H, const double* r, double* z, hipStream_t s) {
+// z = M r on padded fine fields; the last kernel writes the (r, z) partials
+// to rz_out.  With `check`, the first kernel tests convergence of r first.
+static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_out, int check, hipStream_t s) {
     PcgScalars* sc = H->sc;
-    double* part = H->red.partials;
-    unsigned int* tk = H->red.ticket;
+    const int np = H->red.nparts;
+    const dim3 G((unsigned)np);
     if (H->nlev == 1) {
         Level& L = H->lev[0];
         const int64_t n = L.n;
-        hipLaunchKernelGGL(k_gather, dim3(grid_for(n, NT)), dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc);
+        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc, check, H->red.rr, np);
         hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv, L.ev,
-                           sc);
-        hipLaunchKernelGGL(k_scatter_dot, dim3(grid_for(n, NT)), dim3(NT), 0, s, n, H->fine_pad, L.ev, r, z, sc, part,
-                           tk);
+                           (const PcgScalars*)sc);
+        hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, r, z, rz_out,
+                           (const PcgScalars*)sc);
         EB_LAUNCH_CHECK();
         return EB_OK;
     }
     const FineArgs f = fine_args(H);
-    const unsigned fg = fine_grid(H);
     const double w0 = H->lev[0].omega;
-    hipLaunchKernelGGL(k_fine_down, dim3(fg), dim3(NT), 0, s, f, w0, r, H->res, sc);
-    hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0, H->res,
-                       H->lev[1].rv, sc);
-    // down the coarse levels
+    EB_TIMED(H, EB_K_FINE_DOWN, s,
+             hipLaunchKernelGGL(k_fine_down, G, dim3(NT), 0, s, f, w0, r, H->res, sc, check, H->red.rr, np));
+    EB_TIMED(H, EB_K_FINE_RESTRICT, s,
+             hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0,
+                                H->res, H->lev[1].rv, (const PcgScalars*)sc));
     for (int l = 1; l < H->nlev - 1; ++l) {
         Level& L = H->lev[l];
         Level& C = H->lev[l + 1];
         hipLaunchKernelGGL(k_csr_down, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.a_rowptr, L.a_col, L.a_val,
-                           L.diag, L.omega, L.rv, L.res, sc);
+                           L.diag, L.omega, L.rv, L.res, (const PcgScalars*)sc);
         hipLaunchKernelGGL(k_csr_spmv, dim3(grid_for(C.n, NT)), dim3(NT), 0, s, C.n, L.r_rowptr, L.r_col, L.r_val,
-                           L.res, C.rv, sc);
+                           L.res, C.rv, (const PcgScalars*)sc);
     }
     {
         Level& Lc = H->lev[H->nlev - 1];
         hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv, Lc.rv,
-                           Lc.ev, sc);
+                           Lc.ev, (const PcgScalars*)sc);
     }
     for (int l = H->nlev - 2; l >= 1; --l) {
         Level& L = H->lev[l];
         Level& C = H->lev[l + 1];
         hipLaunchKernelGGL(k_csr_up, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.p_rowptr, L.p_col, L.p_val,
-                           L.diag, L.omega, L.rv, C.ev, L.zt, sc);
+                           L.diag, L.omega, L.rv, C.ev, L.zt, (const PcgScalars*)sc);
         hipLaunchKernelGGL(k_csr_post, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.a_rowptr, L.a_col, L.a_val,
-                           L.diag, L.omega, L.rv, L.zt, L.ev, sc);
+                           L.diag, L.omega, L.rv, L.zt, L.ev, (const PcgScalars*)sc);
     }
-    hipLaunchKernelGGL(k_fine_up, dim3(fg), dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, r, H->zt, sc);
-    hipLaunchKernelGGL(k_fine_post, dim3(fg), dim3(NT), 0, s, f, w0, H->zt, r, z, sc, part, tk);
+    EB_TIMED(H, EB_K_FINE_UP, s,
+             hipLaunchKernelGGL(k_fine_up, G, dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, r, H->zt,
+                                (const PcgScalars*)sc));
+    EB_TIMED(H, EB_K_FINE_POST, s,
+             hipLaunchKernelGGL(k_fine_post, G, dim3(NT), 0, s, f, w0, H->zt, r, z, rz_out, (const PcgScalars*)sc));
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
 
-static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
+// Iteration k >= 1 of a run: the V-cycle before it (number k-1) wrote
+// rz[(k-1) % 2]; this iteration's V-cycle writes rz[k % 2].
+static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t s) {
     const FineArgs f = fine_args(H);
-    const unsigned fg = fine_grid(H);
+    const int np = H->red.nparts;
+    const dim3 G((unsigned)np);
     double* pold = H->p[k & 1];
     double* pnew = H->p[(k + 1) & 1];
-    hipLaunchKernelGGL(k_pcg_p_spmv, dim3(fg), dim3(NT), 0, s, f, H->z, pold, pnew, H->q, H->sc, H->red.partials,
-                       H->red.ticket);
-    hipLaunchKernelGGL(k_pcg_xr, dim3(fg), dim3(NT), 0, s, f, H->x, H->r, pnew, H->q, H->sc, H->red.partials,
-                       H->red.ticket);
+    const double* rz_cur = H->red.rz[(k - 1) & 1];
+    const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
+    EB_TIMED(H, EB_K_PCG_SPMV, s,
+             hipLaunchKernelGGL(k_pcg_p_spmv, G, dim3(NT), 0, s, f, H->z, pold, pnew, H->q, rz_cur, rz_prev, np,
+                                H->red.pq, H->sc));
+    EB_TIMED(H, EB_K_PCG_XR, s,
+             hipLaunchKernelGGL(k_pcg_xr, G, dim3(NT), 0, s, f, H->x, H->r, pnew, H->q, rz_cur, H->red.pq, np,
+                                H->red.rr, H->sc, iter_global));
     EB_LAUNCH_CHECK();
-    return enqueue_vcycle(H, H->r, H->z, s);
+    return enqueue_vcycle(H, H->r, H->z, H->red.rz[k & 1], 1, s);
+}
+
+// b, x0 -> r0 = b - A x0; ||b||^2, ||r0||^2, tolerance, initial convergence test.
+static int enqueue_init(amg_handle* H, double tol, int iters, hipStream_t s) {
+    const FineArgs f = fine_args(H);
+    const int np = H->red.nparts;
+    const dim3 G((unsigned)np);
+    hipLaunchKernelGGL(k_fine_norm2, G, dim3(NT), 0, s, f, H->bvec, H->red.aux);
+    hipLaunchKernelGGL(k_fine_resid, G, dim3(NT), 0, s, f, H->bvec, H->x, H->r, H->red.rr);
+    hipLaunchKernelGGL(k_finalize_init, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, H->red.rr, np, tol, iters);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
 }
 
 int solve_layout_alloc(amg_handle* H, hipStream_t s) {
@@ -622,7 +680,6 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
                        L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, sflag,
                        H->strip_w);
     EB_LAUNCH_CHECK();
-    // active strips
     {
         int32_t* off = nullptr;
         EB_TRY(dalloc_n(&off, nstrip_all, s));
@@ -634,7 +691,6 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
         EB_TRY(dfree(off, s));
     }
     EB_TRY(dfree(sflag, s));
-    // active level-0 boxes (restriction)
     if (H->nlev > 1) {
         const int64_t nb = L0.nboxes;
         int32_t* bflag = nullptr;
@@ -653,7 +709,6 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
             return EB_ENOSPC;
         }
     }
-    // PCG vectors (zero everywhere; kernels only ever write unknowns)
     double** vecs[] = {&H->x, &H->r, &H->z, &H->p[0], &H->p[1], &H->q, &H->res, &H->zt, &H->bvec};
     for (double** v : vecs) {
         EB_TRY(dalloc_n(v, npad, s));
@@ -662,23 +717,27 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     for (int l = 0; l < H->nlev; ++l) {
         Level& L = H->lev[l];
         if (l == 0 && H->nlev > 1) continue;
-        const int64_t n = L.n;
+        const int64_t n = L.n > 0 ? L.n : 1;
         EB_TRY(dalloc_n(&L.rv, n, s));
         EB_TRY(dalloc_n(&L.res, n, s));
         EB_TRY(dalloc_n(&L.zt, n, s));
         EB_TRY(dalloc_n(&L.ev, n, s));
-        EB_HIP(hipMemsetAsync(L.rv, 0, sizeof(double) * (n > 0 ? n : 1), s));
-        EB_HIP(hipMemsetAsync(L.ev, 0, sizeof(double) * (n > 0 ? n : 1), s));
+        EB_HIP(hipMemsetAsync(L.rv, 0, sizeof(double) * n, s));
+        EB_HIP(hipMemsetAsync(L.ev, 0, sizeof(double) * n, s));
     }
     EB_TRY(dalloc_n(&H->sc, 1, s));
     EB_HIP(hipMemsetAsync(H->sc, 0, sizeof(PcgScalars), s));
     EB_HIP(hipHostMalloc((void**)&H->sc_host, sizeof(PcgScalars), hipHostMallocDefault));
-    int64_t maxblocks = fine_grid(H);
-    maxblocks = maxblocks > (int64_t)grid_for(nunk, NT) ? maxblocks : (int64_t)grid_for(nunk, NT);
-    H->red.cap = maxblocks + 1;
-    EB_TRY(dalloc_n(&H->red.partials, H->red.cap, s));
-    EB_TRY(dalloc_n(&H->red.ticket, 1, s));
-    EB_HIP(hipMemsetAsync(H->red.ticket, 0, sizeof(unsigned int), s));
+    const int64_t nthreads = H->nlev == 1 ? nunk : H->nstrips * H->strip_w;
+    int64_t np = (nthreads + NT - 1) / NT;
+    if (np < 1) np = 1;
+    if (np > MAX_PARTS) np = MAX_PARTS;
+    H->red.nparts = (int)np;
+    double** parts[] = {&H->red.pq, &H->red.rr, &H->red.rz[0], &H->red.rz[1], &H->red.aux, &H->red.aux2};
+    for (double** v : parts) {
+        EB_TRY(dalloc_n(v, np, s));
+        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * np, s));
+    }
     EB_HIP(hipEventCreate(&H->ev0));
     EB_HIP(hipEventCreate(&H->ev1));
     return EB_OK;
@@ -687,6 +746,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
 static int poll_scalars(amg_handle* H, hipStream_t s) {
     EB_HIP(hipMemcpyAsync(H->sc_host, H->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     EB_HIP(hipStreamSynchronize(s));
+    if (H->tim_used > 0) EB_TRY(timing_harvest(H));
     return EB_OK;
 }
 
@@ -727,9 +787,8 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         return EB_OK;
     }
     const FineArgs f = fine_args(H);
-    const unsigned fg = fine_grid(H);
+    const int np = H->red.nparts;
     const unsigned ug = grid_for(nunk, NT);
-    // stage b and x0 into the padded layout (zero off unknowns)
     hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, b, H->bvec);
     if (p.x0_given) {
         hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, x, H->x);
@@ -737,20 +796,14 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         EB_HIP(hipMemsetAsync(H->x, 0, sizeof(double) * H->npad, s));
     }
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_fine_norm2, dim3(fg), dim3(NT), 0, s, f, H->bvec, (int)FIN_BB, H->sc, H->red.partials,
-                       H->red.ticket);
-    hipLaunchKernelGGL(k_fine_resid, dim3(fg), dim3(NT), 0, s, f, H->bvec, H->x, H->r, H->sc, H->red.partials,
-                       H->red.ticket);
-    EB_LAUNCH_CHECK();
 
     int restarts = 0;
     int enqueued = 0;
+    int iter_base = 0;
     int rc = EB_OK;
     while (true) {
-        hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, H->sc, p.tol, restarts > 0 ? 1 : 0);
-        EB_LAUNCH_CHECK();
-        // z = M r, rho = (r, z), beta = 0
-        EB_TRY(enqueue_vcycle(H, H->r, H->z, s));
+        EB_TRY(enqueue_init(H, p.tol, iter_base, s));
+        EB_TRY(enqueue_vcycle(H, H->r, H->z, H->red.rz[0], 0, s));   // V-cycle 0: rz[0]
         int k = 0;
         while (true) {
             EB_TRY(poll_scalars(H, s));
@@ -761,17 +814,21 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             }
             const int left = p.maxit - H->sc_host->iters;
             const int chunk = left < p.check_every ? left : p.check_every;
-            for (int c = 0; c < chunk; ++c, ++k, ++enqueued) EB_TRY(enqueue_iteration(H, k, s));
+            for (int c = 0; c < chunk; ++c, ++enqueued) {
+                ++k;
+                EB_TRY(enqueue_iteration(H, k, iter_base + k, s));
+            }
         }
-        // true residual
-        hipLaunchKernelGGL(k_fine_resid, dim3(fg), dim3(NT), 0, s, f, H->bvec, H->x, H->res, H->sc,
-                           H->red.partials, H->red.ticket);
+        // true residual ||b - A x||
+        hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res, H->red.aux);
+        hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
         EB_LAUNCH_CHECK();
         EB_TRY(poll_scalars(H, s));
         const PcgScalars& sh = *H->sc_host;
         const double bb = sh.bb;
-        const double true_rel = bb > 0.0 ? sqrt(sh.rr / bb) : 0.0;
+        const double true_rel = bb > 0.0 ? sqrt(sh.rr_true / bb) : 0.0;
         res->rel_res_true = true_rel;
+        res->rel_res_recursive = bb > 0.0 ? sqrt(sh.rr / bb) : 0.0;
         res->iterations = sh.iters;
         if (sh.status != EB_OK) {
             rc = sh.status;
@@ -782,19 +839,15 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             break;
         }
         if (restarts == 0 && sh.iters < p.maxit) {
-            // restart from the current iterate with the true residual
-            restarts = 1;
-            hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, H->res, H->r);
-            EB_LAUNCH_CHECK();
+            restarts = 1;          // drift: restart from the current iterate
+            iter_base = sh.iters;
             continue;
         }
         rc = EB_ENOCONV;
         break;
     }
-    (void)enqueued;
     res->restarts = restarts;
     res->status = rc;
-    // store the solution: zero everywhere, then the unknowns
     EB_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
     hipLaunchKernelGGL(k_store_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->x, x);
     EB_LAUNCH_CHECK();
@@ -825,9 +878,39 @@ extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, voi
     hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
     hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, r, H->r);
     EB_LAUNCH_CHECK();
-    EB_TRY(enqueue_vcycle(H, H->r, H->z, s));
+    EB_TRY(enqueue_vcycle(H, H->r, H->z, H->red.aux2, 0, s));
     hipLaunchKernelGGL(k_store_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z, z);
     EB_LAUNCH_CHECK();
     EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+extern "C" int eb_timing_select(amg_handle_t* H, int kernel_id) {
+    clear_error();
+    if (!H || kernel_id >= EB_K_COUNT) {
+        set_error("eb_timing_select: bad handle or kernel id");
+        return EB_EINVAL;
+    }
+    if (kernel_id >= 0 && !H->tim_ev) {
+        H->tim_cap = 256;
+        H->tim_ev = new hipEvent_t[2 * H->tim_cap];
+        for (int i = 0; i < 2 * H->tim_cap; ++i) EB_HIP(hipEventCreate(&H->tim_ev[i]));
+    }
+    EB_TRY(timing_harvest(H));
+    H->tim_kernel = kernel_id;
+    return EB_OK;
+}
+
+extern "C" int eb_timing_read(amg_handle_t* H, int64_t* launches, double* total_ms) {
+    clear_error();
+    if (!H || !launches || !total_ms) {
+        set_error("eb_timing_read: null pointer");
+        return EB_EINVAL;
+    }
+    EB_TRY(timing_harvest(H));
+    *launches = H->tim_launches;
+    *total_ms = H->tim_ms;
+    H->tim_launches = 0;
+    H->tim_ms = 0.0;
     return EB_OK;
 }

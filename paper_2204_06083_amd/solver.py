@@ -119,7 +119,7 @@ class Hierarchy:
     """amg_setup / pcg_solve / amg_free around one handle."""
 
     def __init__(self, grid, kind: torch.Tensor, a: torch.Tensor, sigma: float = 0.0, coarse_max: int = 256,
-                 max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 4096):
+                 max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 1200):
         lib = L.lib()
         self.grid = grid
         self.sigma = float(sigma)
@@ -192,6 +192,17 @@ class Hierarchy:
         if n > 0:
             L.copy_device_to_host(ptr, arr.nbytes, arr)
         return arr
+
+    def time_kernel(self, name: Optional[str]):
+        """Bracket every launch of one solve kernel with HIP events (None disables)."""
+        kid = -1 if name is None else L.KERNEL_IDS[name]
+        L.check(L.lib().eb_timing_select(self.handle, kid), "eb_timing_select")
+
+    def kernel_time(self):
+        """(launches, total ms) of the selected kernel since the last read."""
+        n, ms = C.c_int64(0), C.c_double(0.0)
+        L.check(L.lib().eb_timing_read(self.handle, C.byref(n), C.byref(ms)), "eb_timing_read")
+        return n.value, ms.value
 
     def vcycle(self, r: torch.Tensor) -> torch.Tensor:
         shape = self.grid.shape

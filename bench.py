@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--rocprof-summary", metavar="DIR",
+                    help="print a markdown summary of a rocprofv3 --stats/--pmc output directory and exit")
+    ap.add_argument("--phases", action="store_true",
+                    help="diagnostics: synchronise between phases and report host time per phase")
     return ap.parse_args()
 
 
@@ -103,8 +107,46 @@ def cpu_baseline(n):
     }
 
 
+def rocprof_summary(path, top=25):
+    """Markdown table of a rocprofv3 kernel_stats.csv (and counters if present)."""
+    import csv
+    import glob
+    out = []
+    stats = sorted(glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True))
+    for f in stats:
+        rows = list(csv.DictReader(open(f)))
+        total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+        out.append(f"kernel stats: {os.path.relpath(f, path)}")
+        out.append("| kernel | calls | avg us | min us | max us | total ms | % |")
+        out.append("|---|---|---|---|---|---|---|")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+            name = r["Name"].split("(")[0]
+            out.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
+        out.append("")
+    for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        agg = {}
+        for r in rows:
+            key = (r["Kernel_Name"].split("(")[0], r["Counter_Name"])
+            a = agg.setdefault(key, [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        out.append(f"counters: {os.path.relpath(f, path)}")
+        out.append("| kernel | counter | dispatches | mean per dispatch |")
+        out.append("|---|---|---|---|")
+        for (k, c), (nd, v) in sorted(agg.items()):
+            out.append(f"| {k} | {c} | {nd} | {v / nd:.1f} |")
+        out.append("")
+    print("\n".join(out))
+
+
 def main():
     args = parse()
+    if args.rocprof_summary:
+        rocprof_summary(args.rocprof_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the solve is single-GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
@@ -130,17 +172,31 @@ def main():
     stats = {"iters": [], "setup_ms": [], "solve_ms": [], "rel_res_true": [], "levels": 0, "n1": 0}
     timing = {"launches": 0, "ms": 0.0}
 
+    phases = {"assemble": [], "rhs": [], "setup": [], "solve": [], "free": []}
+
+    def mark():
+        if args.phases:
+            torch.cuda.synchronize()
+        return time.perf_counter()
+
     def step(measure):
-        ta = time.perf_counter()
+        ta = mark()
         asm = S.assemble_diag(g, psi, cuts_cap=cuts_cap)
+        tb = mark()
         u = W.u_star(*asm.cut_coordinates())
         b = S.assemble_rhs(asm, f, u)
-        t_setup0 = time.perf_counter()
+        t_setup0 = mark()
         H = S.Hierarchy(g, asm.kind, asm.a, 0.0)
-        t_setup1 = time.perf_counter()
+        t_setup1 = mark()
         if measure:
             H.time_kernel(args.kernel)
         x, info = H.solve(b, tol=prob.tol)
+        t_solve1 = mark()
+        if measure and args.phases:
+            phases["assemble"].append((tb - ta) * 1e3)
+            phases["rhs"].append((t_setup0 - tb) * 1e3)
+            phases["setup"].append((t_setup1 - t_setup0) * 1e3)
+            phases["solve"].append((t_solve1 - t_setup1) * 1e3)
         if measure:
             nl, ms = H.kernel_time()
             timing["launches"] += nl
@@ -152,7 +208,12 @@ def main():
             stats["levels"] = info["levels"]
             stats["n1"] = H.level(1).n if H.n_levels > 1 else 0
             stats["n0"] = asm.n_unknowns
+        t_free0 = mark()
         H.free()
+        t_free1 = mark()
+        if measure and args.phases:
+            phases["free"].append((t_free1 - t_free0) * 1e3)
+            phases.setdefault("step", []).append((t_free1 - ta) * 1e3)
         return asm.n_unknowns, info["iterations"], ta
 
     for _ in range(args.warmup):
@@ -210,6 +271,8 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
     }
+    if args.phases:
+        out["phases_ms"] = {k: sum(v) / len(v) for k, v in phases.items() if v}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

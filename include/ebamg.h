@@ -201,6 +201,11 @@ int eb_timing_select(amg_handle_t* H, int kernel_id);
 int eb_timing_read(amg_handle_t* H, int64_t* launches, double* total_ms);
 
 void amg_free(amg_handle_t* H);
+
+/* The library recycles device blocks freed by amg_free and its own
+ * temporaries instead of returning them to the driver.  This synchronises the
+ * current device and returns every cached, unused block (host call).          */
+void eb_release_cached_memory(void);
 const char* eb_strerror(int code);
 const char* eb_last_error(void);
 int eb_abi_version(void);

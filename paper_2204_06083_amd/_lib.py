@@ -20,6 +20,7 @@ EXPORTS = [
     "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
     "amg_vcycle_apply", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
+    "eb_release_cached_memory",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4, "fine_post": 5}
@@ -92,6 +93,8 @@ def lib():
     L.amg_free.restype = None
     L.eb_timing_select.argtypes = [vp, C.c_int]
     L.eb_timing_read.argtypes = [vp, C.POINTER(i64), C.POINTER(dbl)]
+    L.eb_release_cached_memory.argtypes = []
+    L.eb_release_cached_memory.restype = None
     L.eb_strerror.argtypes = [C.c_int]
     L.eb_strerror.restype = C.c_char_p
     L.eb_last_error.restype = C.c_char_p

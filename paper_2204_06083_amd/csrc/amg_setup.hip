@@ -385,7 +385,7 @@ struct AccArgs {
     const int32_t* y_rowptr; const int32_t* y_col; const double* y_val;
     const int32_t* agg;       // ACC_P only
     const double* diag;       // ACC_P only
-    double omega;             // ACC_P only
+    const double* omega;      // ACC_P only (device scalar)
     int32_t* out_cnt;         // count pass
     const int32_t* out_rowptr;// fill pass
     int32_t* out_col;
@@ -413,6 +413,7 @@ __global__ void k_accumulate(AccArgs A) {
     bool bad = false;
     if (MODE == ACC_P) {
         const double dii = A.diag[row];
+        const double omega = FILL ? *A.omega : 0.0;
         const int s0 = A.sm.slot(A.agg[row], bx, by, bz);
         if (s0 < 0) {
             bad = true;
@@ -426,7 +427,7 @@ __global__ void k_accumulate(AccArgs A) {
             if (s < 0) { bad = true; continue; }
             L.flags[s * nt + t] = 1;
             if (FILL) {
-                const double w = A.omega * (A.x_val[e] / dii);
+                const double w = omega * (A.x_val[e] / dii);
                 L.vals[s * nt + t] = L.vals[s * nt + t] - w;
             }
         }
@@ -463,10 +464,11 @@ __global__ void k_accumulate(AccArgs A) {
 }
 
 // -------------------------------------------------------------- transpose
-__global__ void __launch_bounds__(BLOCK) k_tr_count(const int32_t* __restrict__ col, int64_t nnz,
-                                                    int32_t* __restrict__ cnt) {
-    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (e < nnz) atomicAdd(&cnt[col[e]], 1);
+__global__ void __launch_bounds__(BLOCK) k_tr_count(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                    int64_t nrows, int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= nrows) return;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) atomicAdd(&cnt[col[e]], 1);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_tr_fill(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -483,23 +485,67 @@ __global__ void __launch_bounds__(BLOCK) k_tr_fill(const int32_t* __restrict__ r
     }
 }
 
-// insertion sort of each row by column (rows are short)
-__global__ void __launch_bounds__(BLOCK) k_sort_rows(const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                     double* __restrict__ val, int64_t nrows) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+// Sort each row by column: one wavefront per row, bitonic network in LDS for
+// rows of up to SORT_MAX entries (keys are unique column indices), insertion
+// sort by lane 0 beyond that.
+constexpr int SORT_MAX = 256;
+
+__global__ void __launch_bounds__(WAVE) k_sort_rows(const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                    double* __restrict__ val, int64_t nrows) {
+    __shared__ int32_t key[SORT_MAX];
+    __shared__ double v[SORT_MAX];
+    const int64_t i = blockIdx.x;
     if (i >= nrows) return;
     const int b = rowptr[i], e = rowptr[i + 1];
-    for (int u = b + 1; u < e; ++u) {
-        const int32_t c = col[u];
-        const double v = val[u];
-        int w = u;
-        while (w > b && col[w - 1] > c) {
-            col[w] = col[w - 1];
-            val[w] = val[w - 1];
-            --w;
+    const int m = e - b;
+    const int lane = threadIdx.x;
+    if (m <= 1) return;
+    if (m > SORT_MAX) {
+        if (lane == 0) {
+            for (int u = b + 1; u < e; ++u) {
+                const int32_t c = col[u];
+                const double x = val[u];
+                int w = u;
+                while (w > b && col[w - 1] > c) {
+                    col[w] = col[w - 1];
+                    val[w] = val[w - 1];
+                    --w;
+                }
+                col[w] = c;
+                val[w] = x;
+            }
         }
-        col[w] = c;
-        val[w] = v;
+        return;
+    }
+    int p2 = 2;
+    while (p2 < m) p2 <<= 1;
+    for (int t = lane; t < p2; t += WAVE) {
+        key[t] = t < m ? col[b + t] : INT32_MAX;
+        v[t] = t < m ? val[b + t] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < p2; t += WAVE) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const bool up = (t & k) == 0;
+                    const int32_t kt = key[t], ku = key[u];
+                    if ((kt > ku) == up) {
+                        key[t] = ku;
+                        key[u] = kt;
+                        const double vt = v[t];
+                        v[t] = v[u];
+                        v[u] = vt;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = lane; t < m; t += WAVE) {
+        col[b + t] = key[t];
+        val[b + t] = v[t];
     }
 }
 
@@ -529,12 +575,13 @@ __global__ void __launch_bounds__(BLOCK) k_csr_to_dense(const int32_t* __restric
 
 // Blocked right-looking Cholesky in place (lower triangle of the row-major
 // n x n matrix), one workgroup.  Each 16-column panel is copied to LDS and
-// factored there; the trailing update reads the panel from LDS.
+// factored there; the trailing update reads the panel from LDS and updates
+// 4 x 4 tiles of the lower triangle in registers.
 constexpr int CHOL_NB = 16;
-constexpr int CHOL_THREADS = 1024;
+constexpr int CHOL_THREADS = 256;
 
 __global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ Ad, int n, int32_t* __restrict__ err) {
-    extern __shared__ double panel[];   // (n) x CHOL_NB, row-major by panel row
+    extern __shared__ double panel[];   // (n - k0) x CHOL_NB, row-major by panel row
     __shared__ int fail;
     if (threadIdx.x == 0) fail = 0;
     __syncthreads();
@@ -556,31 +603,65 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ 
             const double piv = panel[c * CHOL_NB + c];
             for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) panel[r * CHOL_NB + c] /= piv;
             __syncthreads();
-            // update the remaining panel columns
             const int rem = kb - c - 1;
-            for (int e = threadIdx.x; e < (rows - c - 1) * rem; e += blockDim.x) {
-                const int r = c + 1 + e / rem;
-                const int c2 = c + 1 + e % rem;
-                if (c2 <= r) panel[r * CHOL_NB + c2] -= panel[r * CHOL_NB + c] * panel[c2 * CHOL_NB + c];
+            if (rem > 0) {
+                for (int e = threadIdx.x; e < (rows - c - 1) * rem; e += blockDim.x) {
+                    const int r = c + 1 + e / rem;
+                    const int c2 = c + 1 + e % rem;
+                    if (c2 <= r) panel[r * CHOL_NB + c2] -= panel[r * CHOL_NB + c] * panel[c2 * CHOL_NB + c];
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if (fail) break;
         for (int e = threadIdx.x; e < rows * kb; e += blockDim.x) {
             const int r = e / kb, c = e % kb;
             if (c <= r) Ad[(int64_t)(k0 + r) * n + k0 + c] = panel[r * CHOL_NB + c];
         }
-        // trailing update of the lower triangle: A[i][j] -= sum_c P[i][c] P[j][c], k0+kb <= j <= i
+        // trailing update A[i][j] -= sum_c P[i][c] P[j][c] for t0 <= j <= i,
+        // over 4 x 4 tiles (ti >= tj) of the trailing lower triangle
         const int t0 = k0 + kb;
         const int m = n - t0;
-        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
-            const int i = t0 + (int)(e / m);
-            const int j = t0 + (int)(e % m);
-            if (j > i) continue;
-            double acc = 0.0;
+        const int mt = (m + 3) / 4;
+        const int ntiles = mt * (mt + 1) / 2;
+        for (int tile = threadIdx.x; tile < ntiles; tile += blockDim.x) {
+            int ti = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+            while (ti * (ti + 1) / 2 > tile) --ti;
+            const int tj = tile - ti * (ti + 1) / 2;
+            const int i0 = t0 + 4 * ti, j0 = t0 + 4 * tj;
+            double acc[4][4];
 #pragma unroll
-            for (int c = 0; c < CHOL_NB; ++c) acc += panel[(i - k0) * CHOL_NB + c] * panel[(j - k0) * CHOL_NB + c];
-            Ad[(int64_t)i * n + j] -= acc;
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int c = 0; c < CHOL_NB; ++c) {
+                double pi[4], pj[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    pi[a] = i0 + a < n ? panel[(i0 + a - k0) * CHOL_NB + c] : 0.0;
+                    pj[a] = j0 + a < n ? panel[(j0 + a - k0) * CHOL_NB + c] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
+            }
+            double cur[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = i0 + a, j = j0 + b;
+                    cur[a][b] = (i < n && j <= i) ? Ad[(int64_t)i * n + j] : 0.0;
+                }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = i0 + a, j = j0 + b;
+                    if (i < n && j <= i) Ad[(int64_t)i * n + j] = cur[a][b] - acc[a][b];
+                }
         }
         __syncthreads();
     }
@@ -588,24 +669,37 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ 
 }
 
 // Linv = L^-1 by forward substitution on identity columns: each thread owns
-// one column, kept in LDS; rows of L are read from global memory (uniform
-// across the wavefront).
+// one column, kept in LDS; row i of L is staged in LDS once per block and read
+// at the same index by every lane (broadcast).  Columns are zero above their
+// diagonal, so every lane runs the same loop from the block's first column.
 __global__ void k_tri_inverse(const double* __restrict__ Lf, int n, int cols_per_block, double* __restrict__ Li) {
-    extern __shared__ double ycol[];      // n x cols_per_block
+    extern __shared__ double smem_ti[];
+    double* ycol = smem_ti;                                   // n x cols_per_block
+    double* lrow = smem_ti + (int64_t)n * cols_per_block;     // n
     const int t = threadIdx.x;
-    const int c = blockIdx.x * cols_per_block + t;
+    const int cbase = blockIdx.x * cols_per_block;
+    const int c = cbase + t;
     const bool live = t < cols_per_block && c < n;
-    if (live) {
-        for (int i = 0; i < n; ++i) {
-            double v = 0.0;
-            if (i >= c) {
-                double acc = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) acc -= Lf[(int64_t)i * n + k] * ycol[k * cols_per_block + t];
-                v = acc / Lf[(int64_t)i * n + i];
+    for (int i = cbase; i < n; ++i) {
+        for (int k = cbase + t; k <= i; k += blockDim.x) lrow[k] = Lf[(int64_t)i * n + k];
+        __syncthreads();
+        if (t < cols_per_block) {
+            double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int k = cbase;
+            for (; k + 3 < i; k += 4) {
+                a0 -= lrow[k] * ycol[(k - cbase) * cols_per_block + t];
+                a1 -= lrow[k + 1] * ycol[(k + 1 - cbase) * cols_per_block + t];
+                a2 -= lrow[k + 2] * ycol[(k + 2 - cbase) * cols_per_block + t];
+                a3 -= lrow[k + 3] * ycol[(k + 3 - cbase) * cols_per_block + t];
             }
-            ycol[i * cols_per_block + t] = v;
+            for (; k < i; ++k) a0 -= lrow[k] * ycol[(k - cbase) * cols_per_block + t];
+            ycol[(i - cbase) * cols_per_block + t] = (live && i >= c) ? ((a0 + a1) + (a2 + a3)) / lrow[i] : 0.0;
         }
-        for (int i = 0; i < n; ++i) Li[(int64_t)i * n + c] = ycol[i * cols_per_block + t];
+        __syncthreads();
+    }
+    if (live) {
+        for (int i = 0; i < cbase; ++i) Li[(int64_t)i * n + c] = 0.0;
+        for (int i = cbase; i < n; ++i) Li[(int64_t)i * n + c] = ycol[(i - cbase) * cols_per_block + t];
     }
 }
 
@@ -627,6 +721,30 @@ __global__ void __launch_bounds__(BLOCK) k_compact(const int32_t* __restrict__ f
     if (i < n && flag[i]) out[off[i]] = (int32_t)i;
 }
 
+// omega = 4 / (3 rho) from the bit pattern left by k_max_f64.
+__global__ void k_omega(const unsigned long long* __restrict__ rho_bits, double* __restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double rho = __longlong_as_double((long long)*rho_bits);
+    scal[0] = rho;
+    scal[1] = 4.0 / (3.0 * rho);
+}
+
+// Gather the sizes the host reports (nnz per level) into one array.
+struct ReportArgs {
+    int nlev;
+    const int32_t* a_tot[MAX_LEVELS];
+    const int32_t* p_tot[MAX_LEVELS];
+    const int32_t* r_tot[MAX_LEVELS];
+};
+
+__global__ void k_report(ReportArgs R, int64_t* __restrict__ out) {
+    const int l = threadIdx.x;
+    if (l >= R.nlev) return;
+    out[3 * l + 0] = R.a_tot[l] ? *R.a_tot[l] : 0;
+    out[3 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
+    out[3 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
+}
+
 // ------------------------------------------------------------- host helpers
 static unsigned max_grid(int64_t n) {
     int64_t g = (n + BLOCK - 1) / BLOCK;
@@ -634,36 +752,40 @@ static unsigned max_grid(int64_t n) {
     return (unsigned)(g > 0 ? g : 1);
 }
 
-static int check_err(const int32_t* derr, hipStream_t s, const char* where) {
-    int32_t e = 0;
-    EB_TRY(read_device_i32(derr, &e, s));
+// Device status words of one setup: [0] error flags, [1] count, [2] max.
+struct SetupStat {
+    int32_t err;
+    int32_t count;
+    int32_t maxv;
+    int32_t pad;
+};
+
+static int read_stat(const int32_t* dstat, SetupStat* h, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(h, dstat, sizeof(SetupStat), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+static int err_code(int32_t e, const char* where) {
     if (e & DEVERR_DOMAIN) {
         set_error("%s: a computational point lies on the outermost node layer", where);
         return EB_EDOMAIN;
-    }
-    if (e & DEVERR_NOTSPD) {
-        set_error("%s: non-positive diagonal or Cholesky pivot (operator not SPD)", where);
-        return EB_ENOTSPD;
     }
     if (e & DEVERR_CAP) {
         set_error("%s: a box or accumulator capacity was exceeded", where);
         return EB_ENOSPC;
     }
+    if (e & DEVERR_NOTSPD) {
+        set_error("%s: non-positive diagonal or Cholesky pivot (operator not SPD)", where);
+        return EB_ENOTSPD;
+    }
     return EB_OK;
 }
 
-// rowptr (n+1 entries) from per-row counts; returns nnz on the host.
-static int rowptr_from_counts(const int32_t* cnt, int64_t n, int32_t** rowptr, int64_t* nnz, hipStream_t s) {
+// rowptr (n+1 entries) from per-row counts; nnz stays on the device in rowptr[n].
+static int rowptr_from_counts(const int32_t* cnt, int64_t n, int32_t** rowptr, hipStream_t s) {
     EB_TRY(dalloc_n(rowptr, n + 1, s));
-    int64_t total = 0;
-    EB_TRY(scan_i32(cnt, *rowptr, n, &total, s));
-    if (total >= ((int64_t)1 << 31)) {
-        set_error("a sparse matrix exceeds 2^31 entries");
-        return EB_ENOSPC;
-    }
-    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, *rowptr + n, (int32_t)total);
-    EB_LAUNCH_CHECK();
-    *nnz = total;
+    EB_TRY(scan_i32_dev(cnt, *rowptr, n, *rowptr + n, s));
     return EB_OK;
 }
 
@@ -687,18 +809,25 @@ static int launch_accumulate(int mode, bool fill, AccArgs& args, hipStream_t s) 
     return EB_OK;
 }
 
-// Sparse product via the slot accumulator: count, prefix sum, fill.
-static int accumulate_product(int mode, AccArgs args, int64_t nrows, int32_t** rowptr, int32_t** col, double** val,
-                              int64_t* nnz, hipStream_t s) {
+// Sparse product via the slot accumulator: count, prefix sum, fill.  The
+// column/value arrays are sized by a proven bound (nrows * row_bound), so no
+// host synchronisation is needed; the exact nnz stays in rowptr[nrows].
+static int accumulate_product(int mode, AccArgs args, int64_t nrows, int64_t row_bound, int32_t** rowptr,
+                              int32_t** col, double** val, hipStream_t s) {
     int32_t* cnt = nullptr;
     EB_TRY(dalloc_n(&cnt, nrows, s));
     args.nrows = nrows;
     args.out_cnt = cnt;
     EB_TRY(launch_accumulate(mode, false, args, s));
-    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, nnz, s));
+    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, s));
     EB_TRY(dfree(cnt, s));
-    EB_TRY(dalloc_n(col, *nnz, s));
-    EB_TRY(dalloc_n(val, *nnz, s));
+    const int64_t cap = nrows * row_bound;
+    if (cap >= ((int64_t)1 << 31)) {
+        set_error("a sparse matrix bound exceeds 2^31 entries");
+        return EB_ENOSPC;
+    }
+    EB_TRY(dalloc_n(col, cap, s));
+    EB_TRY(dalloc_n(val, cap, s));
     args.out_rowptr = *rowptr;
     args.out_col = *col;
     args.out_val = *val;
@@ -726,15 +855,14 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CHOL_THREADS), sizeof(double) * n * CHOL_NB, s, dense, (int)n,
                        err);
     EB_LAUNCH_CHECK();
-    EB_TRY(check_err(err, s, "coarsest Cholesky"));
     {
-        int cpb = (int)((150 * 1024) / (sizeof(double) * n));
+        int cpb = (int)((140 * 1024) / (sizeof(double) * n));
         if (cpb > 64) cpb = 64;
         if (cpb < 1) cpb = 1;
         const unsigned nb = (unsigned)((n + cpb - 1) / cpb);
         const unsigned nthreads = (unsigned)((cpb + WAVE - 1) / WAVE * WAVE);
-        hipLaunchKernelGGL(k_tri_inverse, dim3(nb), dim3(nthreads), sizeof(double) * n * cpb, s, dense, (int)n, cpb,
-                           linv);
+        hipLaunchKernelGGL(k_tri_inverse, dim3(nb), dim3(nthreads), sizeof(double) * (n * cpb + n), s, dense, (int)n,
+                           cpb, linv);
         EB_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_gram, dim3(grid_for(n * n)), dim3(BLOCK), 0, s, linv, (int)n, L.dense_inv);
@@ -744,8 +872,9 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     return EB_OK;
 }
 
-// Aggregate level l; returns 1 in *stop if the level becomes the coarsest.
-static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* stop) {
+// Aggregate level l and build level l+1; *stop = 1 if level l becomes the
+// coarsest.  One host synchronisation (coarse count, box maximum, errors).
+static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* stop) {
     Level& L = H->lev[l];
     *stop = 0;
     const int64_t n = L.n;
@@ -754,6 +883,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
         *stop = 1;
         return EB_OK;
     }
+    int32_t* err = dstat;
     NB3 nb;
     for (int a = 0; a < 3; ++a) {
         L.nb[a] = (L.ext[a] + 2) / 3;
@@ -771,29 +901,27 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
     EB_TRY(dalloc_n(&L.box_cstart, nboxes, s));
     EB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nboxes, s));
     EB_HIP(hipMemsetAsync(fillpos, 0, sizeof(int32_t) * nboxes, s));
+    EB_HIP(hipMemsetAsync(dstat + 2, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt);
     EB_LAUNCH_CHECK();
-    EB_TRY(scan_i32(cnt, boff, nboxes, nullptr, s));
+    EB_TRY(scan_i32_dev(cnt, boff, nboxes, dstat + 3, s));     // total (= n) unused
     hipLaunchKernelGGL(k_box_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, boff, fillpos, members);
     EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_box_components, dim3(grid_for(nboxes, 64)), dim3(64), 0, s, boff, cnt, members,
                        L.a_rowptr, L.a_col, L.coords, nb, nboxes, lrank, L.box_ncomp, err);
     EB_LAUNCH_CHECK();
-    int64_t nc = 0;
-    EB_TRY(scan_i32(L.box_ncomp, L.box_cstart, nboxes, &nc, s));
-    EB_TRY(check_err(err, s, "aggregation"));
-    int32_t* dmax = nullptr;
-    EB_TRY(dalloc_n(&dmax, 1, s));
-    EB_HIP(hipMemsetAsync(dmax, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_max_i32, dim3(max_grid(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dmax);
+    EB_TRY(scan_i32_dev(L.box_ncomp, L.box_cstart, nboxes, dstat + 1, s));
+    hipLaunchKernelGGL(k_max_i32, dim3(max_grid(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dstat + 2);
     EB_LAUNCH_CHECK();
-    int32_t maxc = 0;
-    EB_TRY(read_device_i32(dmax, &maxc, s));
-    EB_TRY(dfree(dmax, s));
     EB_TRY(dfree(cnt, s));
     EB_TRY(dfree(boff, s));
     EB_TRY(dfree(fillpos, s));
     EB_TRY(dfree(members, s));
+    SetupStat st;
+    EB_TRY(read_stat(dstat, &st, s));
+    EB_TRY(err_code(st.err, "aggregation"));
+    const int64_t nc = st.count;
+    const int maxc = st.maxv;
     if ((double)nc > H->params.min_reduction * (double)n || nc == 0) {
         EB_TRY(dfree(lrank, s));
         *stop = 1;
@@ -815,7 +943,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
                        nboxes, C.coords, C.crank);
     EB_LAUNCH_CHECK();
 
-    // Gershgorin bound and smoothing weight
+    // Gershgorin bound and smoothing weight, kept on the device
     double* rowv = nullptr;
     unsigned long long* drho = nullptr;
     EB_TRY(dalloc_n(&rowv, n, s));
@@ -823,35 +951,33 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
     EB_HIP(hipMemsetAsync(drho, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_gershgorin_rows, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, L.diag,
                        n, rowv);
-    EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_max_f64, dim3(max_grid(n)), dim3(BLOCK), 0, s, rowv, n, drho, err);
+    hipLaunchKernelGGL(k_omega, dim3(1), dim3(1), 0, s, drho, H->dscal + 2 * l);
     EB_LAUNCH_CHECK();
-    EB_HIP(hipMemcpyAsync(&L.rho, drho, sizeof(double), hipMemcpyDeviceToHost, s));
-    EB_HIP(hipStreamSynchronize(s));
-    EB_TRY(check_err(err, s, "Gershgorin bound"));
-    L.omega = 4.0 / (3.0 * L.rho);
     EB_TRY(dfree(rowv, s));
     EB_TRY(dfree(drho, s));
 
+    const int slots = (dim == 3 ? 27 : 9) * maxc;
     AccArgs args;
     memset(&args, 0, sizeof(args));
     args.sm.dim = dim;
     args.sm.maxc = maxc;
-    args.sm.nslots = (dim == 3 ? 27 : 9) * maxc;
+    args.sm.nslots = slots;
     args.sm.ccoords = C.coords;
     args.sm.crank = C.crank;
     args.sm.cstart = L.box_cstart;
     args.sm.nb = nb;
     args.err = err;
 
-    // P = (I - omega D^-1 A) P_tent
+    // P = (I - omega D^-1 A) P_tent; a row has at most min(row of A, slots) entries
+    const int64_t p_bound = L.row_bound < slots ? L.row_bound : slots;
     args.row_coords = L.coords;
     args.centre_div = 3;
     args.x_rowptr = L.a_rowptr; args.x_col = L.a_col; args.x_val = L.a_val;
-    args.agg = L.agg; args.diag = L.diag; args.omega = L.omega;
-    EB_TRY(accumulate_product(ACC_P, args, n, &L.p_rowptr, &L.p_col, &L.p_val, &L.nnz_p, s));
+    args.agg = L.agg; args.diag = L.diag; args.omega = H->dscal + 2 * l + 1;
+    EB_TRY(accumulate_product(ACC_P, args, n, p_bound, &L.p_rowptr, &L.p_col, &L.p_val, s));
 
-    // R = P^T
+    // R = P^T (same number of entries)
     {
         int32_t* tcnt = nullptr;
         int32_t* tfill = nullptr;
@@ -859,36 +985,34 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
         EB_TRY(dalloc_n(&tfill, nc, s));
         EB_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * nc, s));
         EB_HIP(hipMemsetAsync(tfill, 0, sizeof(int32_t) * nc, s));
-        hipLaunchKernelGGL(k_tr_count, dim3(grid_for(L.nnz_p)), dim3(BLOCK), 0, s, L.p_col, L.nnz_p, tcnt);
+        hipLaunchKernelGGL(k_tr_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.p_rowptr, L.p_col, n, tcnt);
         EB_LAUNCH_CHECK();
-        EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, &L.nnz_r, s));
-        EB_TRY(dalloc_n(&L.r_col, L.nnz_r, s));
-        EB_TRY(dalloc_n(&L.r_val, L.nnz_r, s));
+        EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, s));
+        EB_TRY(dalloc_n(&L.r_col, n * p_bound, s));
+        EB_TRY(dalloc_n(&L.r_val, n * p_bound, s));
         hipLaunchKernelGGL(k_tr_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.p_rowptr, L.p_col, L.p_val, n,
                            L.r_rowptr, tfill, L.r_col, L.r_val);
         EB_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(nc)), dim3(BLOCK), 0, s, L.r_rowptr, L.r_col, L.r_val, nc);
+        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)nc), dim3(WAVE), 0, s, L.r_rowptr, L.r_col, L.r_val, nc);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(tcnt, s));
         EB_TRY(dfree(tfill, s));
     }
 
-    // AP = A P
+    // AP = A P, then A_c = R (A P); rows of both have at most `slots` entries
     int32_t *ap_rowptr = nullptr, *ap_col = nullptr;
     double* ap_val = nullptr;
-    int64_t nnz_ap = 0;
     args.x_rowptr = L.a_rowptr; args.x_col = L.a_col; args.x_val = L.a_val;
     args.y_rowptr = L.p_rowptr; args.y_col = L.p_col; args.y_val = L.p_val;
     args.row_coords = L.coords;
     args.centre_div = 3;
-    EB_TRY(accumulate_product(ACC_AP, args, n, &ap_rowptr, &ap_col, &ap_val, &nnz_ap, s));
-
-    // A_c = R (A P)
+    EB_TRY(accumulate_product(ACC_AP, args, n, slots, &ap_rowptr, &ap_col, &ap_val, s));
     args.x_rowptr = L.r_rowptr; args.x_col = L.r_col; args.x_val = L.r_val;
     args.y_rowptr = ap_rowptr; args.y_col = ap_col; args.y_val = ap_val;
     args.row_coords = C.coords;
     args.centre_div = 1;
-    EB_TRY(accumulate_product(ACC_RAP, args, nc, &C.a_rowptr, &C.a_col, &C.a_val, &C.nnz_a, s));
+    EB_TRY(accumulate_product(ACC_RAP, args, nc, slots, &C.a_rowptr, &C.a_col, &C.a_val, s));
+    C.row_bound = slots;
     EB_TRY(dfree(ap_rowptr, s));
     EB_TRY(dfree(ap_col, s));
     EB_TRY(dfree(ap_val, s));
@@ -896,7 +1020,6 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* err, int* st
     hipLaunchKernelGGL(k_extract_diag, dim3(grid_for(nc)), dim3(BLOCK), 0, s, C.a_rowptr, C.a_col, C.a_val, nc,
                        C.diag, err);
     EB_LAUNCH_CHECK();
-    EB_TRY(check_err(err, s, "Galerkin product"));
     return EB_OK;
 }
 
@@ -910,40 +1033,43 @@ static void free_level(Level& L, hipStream_t s) {
 
 int free_handle_memory(amg_handle* H) {
     hipStream_t s = H->stream;
+    // blocks go back to the library cache tagged with the setup stream: wait
+    // for any solve still running on another stream first
+    if (H->last_stream && H->last_stream != s) (void)hipStreamSynchronize(H->last_stream);
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
-    void* ptrs[] = {H->strips, H->boxes0, H->fine_nodes, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, H->x, H->r,
-                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->red.pq, H->red.rr,
+    void* ptrs[] = {H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, H->x, H->r,
+                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
                     H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2};
     for (void* p : ptrs) (void)dfree(p, s);
-    if (H->sc_host) (void)hipHostFree(H->sc_host);
-    if (H->tim_ev) {
-        for (int i = 0; i < 2 * H->tim_cap; ++i) (void)hipEventDestroy(H->tim_ev[i]);
-        delete[] H->tim_ev;
-        H->tim_ev = nullptr;
-    }
+    H->sc_host = nullptr;
+    H->tim_ev = nullptr;    // process-wide event pool, not owned
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
-    EB_HIP(hipStreamSynchronize(s));
     return EB_OK;
 }
 
-int solve_layout_alloc(amg_handle* H, hipStream_t s);   // solve.hip
+int solve_layout_alloc(amg_handle* H, hipStream_t s);    // solve.hip
+int solve_layout_finish(amg_handle* H, hipStream_t s);   // solve.hip
 
 static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStream_t s) {
     const GridDims& d = H->d;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    int32_t* err = nullptr;
+    int32_t* dstat = nullptr;
     int32_t* flag = nullptr;
     int32_t* unk_off = nullptr;
-    EB_TRY(dalloc_n(&err, 1, s));
-    EB_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    EB_TRY(dalloc_n(&dstat, 4, s));
+    EB_HIP(hipMemsetAsync(dstat, 0, sizeof(SetupStat), s));
+    EB_TRY(dalloc_n(&H->dscal, 2 * MAX_LEVELS, s));
+    EB_HIP(hipMemsetAsync(H->dscal, 0, sizeof(double) * 2 * MAX_LEVELS, s));
     EB_TRY(dalloc_n(&flag, nn, s));
     EB_TRY(dalloc_n(&unk_off, nn, s));
-    hipLaunchKernelGGL(k_fine_flags, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, err);
+    hipLaunchKernelGGL(k_fine_flags, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, dstat);
     EB_LAUNCH_CHECK();
-    int64_t nunk = 0;
-    EB_TRY(scan_i32(flag, unk_off, nn, &nunk, s));
-    EB_TRY(check_err(err, s, "amg_setup"));
+    EB_TRY(scan_i32_dev(flag, unk_off, nn, dstat + 1, s));
+    SetupStat st;
+    EB_TRY(read_stat(dstat, &st, s));
+    EB_TRY(err_code(st.err, "amg_setup"));
+    const int64_t nunk = st.count;
     H->n_fine = nunk;
     Level& L0 = H->lev[0];
     L0 = Level();
@@ -951,6 +1077,7 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     L0.ext[0] = d.nx;
     L0.ext[1] = d.ny;
     L0.ext[2] = d.nz;
+    L0.row_bound = 2 * d.dim + 1;
     EB_TRY(dalloc_n(&H->fine_nodes, nunk, s));
     EB_TRY(dalloc_n(&L0.coords, 3 * nunk, s));
     EB_TRY(dalloc_n(&L0.diag, nunk, s));
@@ -959,9 +1086,9 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     hipLaunchKernelGGL(k_fine_rows, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, unk_off, rowcnt,
                        H->fine_nodes, L0.coords);
     EB_LAUNCH_CHECK();
-    EB_TRY(rowptr_from_counts(rowcnt, nunk, &L0.a_rowptr, &L0.nnz_a, s));
-    EB_TRY(dalloc_n(&L0.a_col, L0.nnz_a, s));
-    EB_TRY(dalloc_n(&L0.a_val, L0.nnz_a, s));
+    EB_TRY(rowptr_from_counts(rowcnt, nunk, &L0.a_rowptr, s));
+    EB_TRY(dalloc_n(&L0.a_col, nunk * L0.row_bound, s));
+    EB_TRY(dalloc_n(&L0.a_val, nunk * L0.row_bound, s));
     hipLaunchKernelGGL(k_fine_fill, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, kind, a, H->sigma, d, nunk,
                        H->fine_nodes, unk_off, L0.a_rowptr, L0.a_col, L0.a_val, L0.diag);
     EB_LAUNCH_CHECK();
@@ -976,18 +1103,55 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
             break;
         }
         int stop = 0;
-        EB_TRY(build_next(H, l, s, err, &stop));
+        EB_TRY(build_next(H, l, s, dstat, &stop));
         if (stop) {
-            EB_TRY(make_coarsest(H, l, s, err));
+            EB_TRY(make_coarsest(H, l, s, dstat));
             break;
         }
         ++l;
     }
     H->nlev = l + 1;
     EB_TRY(solve_layout_alloc(H, s));
-    EB_TRY(check_err(err, s, "amg_setup"));
-    EB_TRY(dfree(err, s));
-    EB_HIP(hipStreamSynchronize(s));
+
+    // one read-back: sizes of every level, smoothing weights, errors
+    ReportArgs R;
+    memset(&R, 0, sizeof(R));
+    R.nlev = H->nlev;
+    for (int k = 0; k < H->nlev; ++k) {
+        const Level& L = H->lev[k];
+        R.a_tot[k] = L.a_rowptr ? L.a_rowptr + L.n : nullptr;
+        if (!L.is_coarsest && L.p_rowptr) {
+            R.p_tot[k] = L.p_rowptr + L.n;
+            R.r_tot[k] = L.r_rowptr + H->lev[k + 1].n;
+        }
+    }
+    int64_t* drep = nullptr;
+    EB_TRY(dalloc_n(&drep, 3 * MAX_LEVELS, s));
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, R, drep);
+    EB_LAUNCH_CHECK();
+    int64_t rep[3 * MAX_LEVELS];
+    double scal[2 * MAX_LEVELS];
+    EB_HIP(hipMemcpyAsync(rep, drep, sizeof(int64_t) * 3 * H->nlev, hipMemcpyDeviceToHost, s));
+    EB_HIP(hipMemcpyAsync(scal, H->dscal, sizeof(double) * 2 * MAX_LEVELS, hipMemcpyDeviceToHost, s));
+    int32_t counts[2] = {0, 0};
+    EB_HIP(hipMemcpyAsync(counts, H->dcount, sizeof(counts), hipMemcpyDeviceToHost, s));
+    EB_TRY(read_stat(dstat, &st, s));
+    H->nstrips = counts[0];
+    H->nboxes0 = counts[1];
+    EB_TRY(dfree(drep, s));
+    for (int k = 0; k < H->nlev; ++k) {
+        Level& L = H->lev[k];
+        L.nnz_a = rep[3 * k];
+        L.nnz_p = rep[3 * k + 1];
+        L.nnz_r = rep[3 * k + 2];
+        if (!L.is_coarsest) {
+            L.rho = scal[2 * k];
+            L.omega = scal[2 * k + 1];
+        }
+    }
+    EB_TRY(err_code(st.err, "amg_setup"));
+    EB_TRY(solve_layout_finish(H, s));
+    EB_TRY(dfree(dstat, s));
     return EB_OK;
 }
 

@@ -33,11 +33,11 @@ void clear_error();
 #define EB_LAUNCH_CHECK() EB_HIP(hipGetLastError())
 
 // ------------------------------------------------------------- allocation
-// Stream-ordered allocations from the device's default memory pool: repeated
-// setup/free cycles reuse pool memory instead of calling into the driver.
+// Device memory from the library's caching allocator (runtime.hip): blocks
+// are recycled by size, so repeated setup/free cycles make no driver calls.
 int dalloc(void** p, size_t bytes, hipStream_t s);
 int dfree(void* p, hipStream_t s);
-void pool_keep_memory();   // raise the pool release threshold once per device
+void eb_cache_release_all();   // synchronise the device, return cached blocks
 
 template <class T>
 int dalloc_n(T** p, int64_t count, hipStream_t s) {
@@ -98,6 +98,9 @@ __device__ inline double block_sum(double v, double* lds /* NT/64 */) {
 // synchronised.
 int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s);
 int scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* total_host, hipStream_t s);
+// Same scans, grand total written to device memory (no synchronisation).
+int scan_i32_dev(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s);
+int scan_i32_to_i64_dev(const int32_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s);
 
 // Small helpers used by several translation units.
 int read_device_i32(const int32_t* dptr, int32_t* host, hipStream_t s);

@@ -14,6 +14,7 @@ struct Level {
     int is_coarsest = 0;
     int max_comp = 0;            // most coarse unknowns sharing one box of this level
     int ext[3] = {1, 1, 1};      // coordinate extents
+    int64_t row_bound = 0;       // upper bound on entries per row of A
     int nb[3] = {1, 1, 1};       // box-grid extents (ceil(ext / 3))
     int64_t nboxes = 0;
     // operator (CSR, sorted columns) and its diagonal
@@ -63,6 +64,7 @@ struct amg_handle {
     eb::GridDims d;
     double sigma = 0.0;
     hipStream_t stream = nullptr;
+    hipStream_t last_stream = nullptr;   // stream of the latest solve / V-cycle call
     amg_params_t params;
     int64_t n_fine = 0;
     int nlev = 0;
@@ -73,6 +75,7 @@ struct amg_handle {
     int strip_w = 64;
     int64_t nstrips = 0;
     int32_t* strips = nullptr;      // active strips (ids: padded index / strip_w)
+    int32_t* dcount = nullptr;      // device totals: [0] strips, [1] level-0 boxes
     int64_t nboxes0 = 0;
     int32_t* boxes0 = nullptr;      // level-0 boxes holding unknowns
     int64_t* fine_nodes = nullptr;  // unknown -> dense node index
@@ -86,7 +89,9 @@ struct amg_handle {
     double* q = nullptr; double* res = nullptr; double* zt = nullptr;
     double* bvec = nullptr;         // right-hand side in the padded layout
     eb::PcgScalars* sc = nullptr;
-    eb::PcgScalars* sc_host = nullptr;   // pinned mirror
+    double* dscal = nullptr;        // per level: rho, omega (device)
+    eb::PcgScalars* sc_host = nullptr;   // host mirror (points at sc_mirror)
+    eb::PcgScalars sc_mirror;
     eb::Reduction red;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // kernel timing hook (eb_timing_select / eb_timing_read)

@@ -3,6 +3,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <utility>
+
 #include "common.hpp"
 
 namespace eb {
@@ -18,33 +23,110 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_last_error[0] = 0; }
 
-void pool_keep_memory() {
-    static bool done[64] = {false};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done[dev] = true;
+// ------------------------------------------------------- caching allocator
+// Device blocks come from hipMalloc once and are then recycled by size inside
+// the library: freeing a block returns it to a per-device free list, and an
+// allocation reuses the smallest cached block that is large enough (at most
+// twice the request).  The driver's own alloc/free calls cost tens to
+// hundreds of microseconds each, which would dominate a setup that builds and
+// frees dozens of arrays.  Reuse is stream ordered: a block freed on stream s
+// is handed out again on s at once; on another stream the device is
+// synchronised first (rare: callers normally keep one stream).
+namespace {
+
+struct CachedBlock {
+    size_t bytes;
+    hipStream_t stream;
+};
+
+struct DeviceCache {
+    std::multimap<size_t, std::pair<void*, hipStream_t>> free_blocks;
+    std::unordered_map<void*, size_t> live;
+    size_t cached_bytes = 0;
+};
+
+std::mutex g_cache_mutex;
+DeviceCache g_cache[64];
+
+size_t round_bytes(size_t b) {
+    const size_t g = b <= (1 << 20) ? 256 : (1 << 16);
+    return (b + g - 1) / g * g;
 }
 
+}  // namespace
+
 int dalloc(void** p, size_t bytes, hipStream_t s) {
-    pool_keep_memory();
-    hipError_t e = hipMallocAsync(p, bytes, s);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        set_error("dalloc: no current device");
+        return EB_EHIP;
+    }
+    const size_t want = round_bytes(bytes);
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        DeviceCache& C = g_cache[dev];
+        auto it = C.free_blocks.lower_bound(want);
+        if (it != C.free_blocks.end() && it->first <= 2 * want) {
+            void* ptr = it->second.first;
+            hipStream_t old = it->second.second;
+            const size_t sz = it->first;
+            C.free_blocks.erase(it);
+            C.cached_bytes -= sz;
+            C.live[ptr] = sz;
+            if (old != s) (void)hipDeviceSynchronize();
+            *p = ptr;
+            return EB_OK;
+        }
+    }
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, want);
     if (e != hipSuccess) {
-        set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        // release cached blocks and retry once
+        (void)hipGetLastError();
+        eb_cache_release_all();
+        e = hipMalloc(&ptr, want);
+    }
+    if (e != hipSuccess) {
+        set_error("hipMalloc(%zu bytes) failed: %s", want, hipGetErrorString(e));
         *p = nullptr;
         return EB_EHIP;
     }
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    g_cache[dev].live[ptr] = want;
+    *p = ptr;
     return EB_OK;
 }
 
 int dfree(void* p, hipStream_t s) {
     if (!p) return EB_OK;
-    EB_HIP(hipFreeAsync(p, s));
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        set_error("dfree: no current device");
+        return EB_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    DeviceCache& C = g_cache[dev];
+    auto it = C.live.find(p);
+    if (it == C.live.end()) {
+        set_error("dfree: pointer not owned by the library");
+        return EB_EINVAL;
+    }
+    const size_t sz = it->second;
+    C.live.erase(it);
+    C.free_blocks.emplace(sz, std::make_pair(p, s));
+    C.cached_bytes += sz;
     return EB_OK;
+}
+
+void eb_cache_release_all() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    DeviceCache& C = g_cache[dev];
+    for (auto& kv : C.free_blocks) (void)hipFree(kv.second.first);
+    C.free_blocks.clear();
+    C.cached_bytes = 0;
 }
 
 int read_device_i32(const int32_t* dptr, int32_t* host, hipStream_t s) {
@@ -196,6 +278,14 @@ int scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* total_host, hi
     return EB_OK;
 }
 
+int scan_i32_dev(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s) {
+    return scan_impl<int32_t, int32_t>(in, out, n, total_dev, s);
+}
+
+int scan_i32_to_i64_dev(const int32_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s) {
+    return scan_impl<int32_t, int64_t>(in, out, n, total_dev, s);
+}
+
 }  // namespace eb
 
 extern "C" {
@@ -218,5 +308,7 @@ const char* eb_strerror(int code) {
 }
 
 int eb_abi_version(void) { return EBAMG_ABI_VERSION; }
+
+void eb_release_cached_memory(void) { eb::eb_cache_release_all(); }
 
 }  // extern "C"

@@ -657,6 +657,8 @@ static int enqueue_init(amg_handle* H, double tol, int iters, hipStream_t s) {
     return EB_OK;
 }
 
+// Fine solve layout, part 1 (no synchronisation): padded fields, active
+// strip and box lists sized by their bounds, vectors and partial buffers.
 int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     const GridDims& d = H->d;
     H->px = (d.nx + 63) / 64 * 64;
@@ -664,6 +666,8 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     H->strip_w = d.dim == 2 ? 64 : 32;
     const int64_t npad = H->npad;
     const int64_t nunk = H->n_fine;
+    EB_TRY(dalloc_n(&H->dcount, 2, s));
+    EB_HIP(hipMemsetAsync(H->dcount, 0, 2 * sizeof(int32_t), s));
     EB_TRY(dalloc_n(&H->fine_pad, nunk, s));
     EB_TRY(dalloc_n(&H->kind_p, npad, s));
     EB_TRY(dalloc_n(&H->diag_p, npad, s));
@@ -683,8 +687,8 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     {
         int32_t* off = nullptr;
         EB_TRY(dalloc_n(&off, nstrip_all, s));
-        EB_TRY(scan_i32(sflag, off, nstrip_all, &H->nstrips, s));
-        EB_TRY(dalloc_n(&H->strips, H->nstrips, s));
+        EB_TRY(scan_i32_dev(sflag, off, nstrip_all, H->dcount + 0, s));
+        EB_TRY(dalloc_n(&H->strips, nstrip_all, s));
         hipLaunchKernelGGL(k_compact_list, dim3(grid_for(nstrip_all)), dim3(BLOCK), 0, s, sflag, off, nstrip_all,
                            H->strips);
         EB_LAUNCH_CHECK();
@@ -698,8 +702,8 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
         EB_TRY(dalloc_n(&bflag, nb, s));
         EB_TRY(dalloc_n(&off, nb, s));
         hipLaunchKernelGGL(k_flag_nonzero, dim3(grid_for(nb)), dim3(BLOCK), 0, s, L0.box_ncomp, nb, bflag);
-        EB_TRY(scan_i32(bflag, off, nb, &H->nboxes0, s));
-        EB_TRY(dalloc_n(&H->boxes0, H->nboxes0, s));
+        EB_TRY(scan_i32_dev(bflag, off, nb, H->dcount + 1, s));
+        EB_TRY(dalloc_n(&H->boxes0, nb, s));
         hipLaunchKernelGGL(k_compact_list, dim3(grid_for(nb)), dim3(BLOCK), 0, s, bflag, off, nb, H->boxes0);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(bflag, s));
@@ -727,19 +731,26 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     }
     EB_TRY(dalloc_n(&H->sc, 1, s));
     EB_HIP(hipMemsetAsync(H->sc, 0, sizeof(PcgScalars), s));
-    EB_HIP(hipHostMalloc((void**)&H->sc_host, sizeof(PcgScalars), hipHostMallocDefault));
-    const int64_t nthreads = H->nlev == 1 ? nunk : H->nstrips * H->strip_w;
+    H->sc_host = &H->sc_mirror;   // pageable, per handle (polled a few times per solve)
+    double** parts[] = {&H->red.pq, &H->red.rr, &H->red.rz[0], &H->red.rz[1], &H->red.aux, &H->red.aux2};
+    for (double** v : parts) {
+        EB_TRY(dalloc_n(v, MAX_PARTS, s));
+        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * MAX_PARTS, s));
+    }
+    EB_HIP(hipEventCreate(&H->ev0));
+    EB_HIP(hipEventCreate(&H->ev1));
+    return EB_OK;
+}
+
+// Part 2, after the device totals have been read back (dcount copied into
+// H->nstrips / H->nboxes0 by the caller's single synchronisation).
+int solve_layout_finish(amg_handle* H, hipStream_t s) {
+    (void)s;
+    const int64_t nthreads = H->nlev == 1 ? H->n_fine : H->nstrips * H->strip_w;
     int64_t np = (nthreads + NT - 1) / NT;
     if (np < 1) np = 1;
     if (np > MAX_PARTS) np = MAX_PARTS;
     H->red.nparts = (int)np;
-    double** parts[] = {&H->red.pq, &H->red.rr, &H->red.rz[0], &H->red.rz[1], &H->red.aux, &H->red.aux2};
-    for (double** v : parts) {
-        EB_TRY(dalloc_n(v, np, s));
-        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * np, s));
-    }
-    EB_HIP(hipEventCreate(&H->ev0));
-    EB_HIP(hipEventCreate(&H->ev1));
     return EB_OK;
 }
 
@@ -775,6 +786,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     memset(res, 0, sizeof(*res));
     res->levels = H->nlev;
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
     const GridDims& d = H->d;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
     const int64_t nunk = H->n_fine;
@@ -869,6 +881,7 @@ extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, voi
         return EB_EINVAL;
     }
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
     const GridDims& d = H->d;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
     const int64_t nunk = H->n_fine;
@@ -892,9 +905,22 @@ extern "C" int eb_timing_select(amg_handle_t* H, int kernel_id) {
         return EB_EINVAL;
     }
     if (kernel_id >= 0 && !H->tim_ev) {
+        // one event pool per process and device, shared by handles that time
+        // kernels (the hook is a measurement aid: not for concurrent solves)
+        static hipEvent_t* pools[64] = {nullptr};
+        int dev = 0;
+        EB_HIP(hipGetDevice(&dev));
+        if (dev < 0 || dev >= 64) {
+            set_error("eb_timing_select: device id out of range");
+            return EB_EINVAL;
+        }
+        if (!pools[dev]) {
+            hipEvent_t* pool = new hipEvent_t[2 * 256];
+            for (int i = 0; i < 2 * 256; ++i) EB_HIP(hipEventCreate(&pool[i]));
+            pools[dev] = pool;
+        }
         H->tim_cap = 256;
-        H->tim_ev = new hipEvent_t[2 * H->tim_cap];
-        for (int i = 0; i < 2 * H->tim_cap; ++i) EB_HIP(hipEventCreate(&H->tim_ev[i]));
+        H->tim_ev = pools[dev];
     }
     EB_TRY(timing_harvest(H));
     H->tim_kernel = kernel_id;

@@ -36,12 +36,19 @@ HBM_PEAK_GBS = 8000.0
 # int32 aggregate ids; every array touched once per launch).  The coarse-level
 # share of the restriction output / prolongation input is 8 B * n1 / n0.
 KERNEL_BYTES = {
-    "pcg_spmv": lambda n0, n1: 40.0 * n0,            # read z, p_old, d; write p, q
-    "pcg_xr": lambda n0, n1: 48.0 * n0,              # read x, p, r, q; write x, r
-    "fine_down": lambda n0, n1: 24.0 * n0,           # read r, d; write res
-    "fine_restrict": lambda n0, n1: 20.0 * n0 + 8.0 * n1,   # read res, d, agg; write r_c
-    "fine_up": lambda n0, n1: 28.0 * n0 + 8.0 * n1,  # read r, d, agg; gather e_c; write zt
-    "fine_post": lambda n0, n1: 32.0 * n0,           # read zt, r, d; write z
+    # p = z + beta p_old; q = A p; (p, q): read z, p_old, d; write p, q
+    "pcg_spmv": lambda n0, n1: 40.0 * n0,
+    # x += alpha p; r_out = r_in - alpha q; res = r_out - A omega D^-1 r_out:
+    # read x, p, r_in, q, d; write x, r_out, res
+    "pcg_xr_down": lambda n0, n1: 64.0 * n0,
+    # first V-cycle only: read r, d; write res
+    "fine_down": lambda n0, n1: 24.0 * n0,
+    # r_c = P^T res: read res, d, agg; write r_c
+    "fine_restrict": lambda n0, n1: 20.0 * n0 + 8.0 * n1,
+    # zt = omega r / d + (I - omega D^-1 A) P_tent e_c: read agg, r, d; gather e_c; write zt
+    "fine_up": lambda n0, n1: 28.0 * n0 + 8.0 * n1,
+    # z = zt + omega (r - A zt) / d; (r, z): read zt, r, d; write z
+    "fine_post": lambda n0, n1: 32.0 * n0,
 }
 
 

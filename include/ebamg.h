@@ -189,12 +189,13 @@ const int64_t* amg_fine_nodes(const amg_handle_t* H);
  * synchronises that stream, returns the number of timed launches and their
  * summed duration in ms, and resets both.  kernel_id < 0 disables timing.   */
 enum {
-    EB_K_PCG_SPMV = 0,      /* p <- z + beta p; q = A p; (p, q)                 */
-    EB_K_PCG_XR = 1,        /* x += alpha p; r -= alpha q; ||r||^2              */
-    EB_K_FINE_DOWN = 2,     /* fine pre-smoothing and residual                  */
-    EB_K_FINE_RESTRICT = 3, /* fine residual restriction P^T res                */
-    EB_K_FINE_UP = 4,       /* fine prolongation and correction                 */
-    EB_K_FINE_POST = 5,     /* fine post-smoothing and (r, z)                   */
+    EB_K_PCG_SPMV = 0,      /* p <- z + beta p; q = A p; (p, q)                    */
+    EB_K_PCG_XR = 1,        /* x += alpha p; r -= alpha q; ||r||^2, fused with the
+                               fine pre-smoothing and residual                      */
+    EB_K_FINE_DOWN = 2,     /* fine pre-smoothing and residual (first V-cycle)     */
+    EB_K_FINE_RESTRICT = 3, /* fine residual restriction P^T res                   */
+    EB_K_FINE_UP = 4,       /* fine prolongation and correction                    */
+    EB_K_FINE_POST = 5,     /* fine post-smoothing and (r, z)                      */
     EB_K_COUNT = 6
 };
 int eb_timing_select(amg_handle_t* H, int kernel_id);

@@ -23,7 +23,8 @@ EXPORTS = [
     "eb_release_cached_memory",
 ]
 
-KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4, "fine_post": 5}
+KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
+              "fine_post": 5}
 
 
 class EbGrid(C.Structure):

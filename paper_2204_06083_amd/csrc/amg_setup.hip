@@ -668,38 +668,38 @@ __global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ 
     if (threadIdx.x == 0 && fail) atomicOr(err, DEVERR_NOTSPD);
 }
 
-// Linv = L^-1 by forward substitution on identity columns: each thread owns
-// one column, kept in LDS; row i of L is staged in LDS once per block and read
-// at the same index by every lane (broadcast).  Columns are zero above their
-// diagonal, so every lane runs the same loop from the block's first column.
-__global__ void k_tri_inverse(const double* __restrict__ Lf, int n, int cols_per_block, double* __restrict__ Li) {
+// Linv = L^-1 by forward substitution on identity columns.  A wavefront owns
+// four columns; 16 lanes share each column's dot products (strided over k) and
+// combine them with shuffles, so the sequential chain per row is short.  The
+// columns and row i of L live in LDS.  Column c is zero above its diagonal.
+constexpr int TRI_LPC = 16;                 // lanes per column
+constexpr int TRI_CPB = WAVE / TRI_LPC;     // columns per block (one wavefront)
+
+__global__ void __launch_bounds__(WAVE) k_tri_inverse(const double* __restrict__ Lf, int n, double* __restrict__ Li) {
     extern __shared__ double smem_ti[];
-    double* ycol = smem_ti;                                   // n x cols_per_block
-    double* lrow = smem_ti + (int64_t)n * cols_per_block;     // n
-    const int t = threadIdx.x;
-    const int cbase = blockIdx.x * cols_per_block;
-    const int c = cbase + t;
-    const bool live = t < cols_per_block && c < n;
+    double* ycol = smem_ti;                       // TRI_CPB x n
+    double* lrow = smem_ti + (int64_t)TRI_CPB * n; // n
+    const int lane = threadIdx.x;
+    const int g = lane / TRI_LPC;                 // column within the block
+    const int sub = lane % TRI_LPC;
+    const int cbase = blockIdx.x * TRI_CPB;
+    const int c = cbase + g;
     for (int i = cbase; i < n; ++i) {
-        for (int k = cbase + t; k <= i; k += blockDim.x) lrow[k] = Lf[(int64_t)i * n + k];
+        for (int k = cbase + lane; k <= i; k += WAVE) lrow[k] = Lf[(int64_t)i * n + k];
         __syncthreads();
-        if (t < cols_per_block) {
-            double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int k = cbase;
-            for (; k + 3 < i; k += 4) {
-                a0 -= lrow[k] * ycol[(k - cbase) * cols_per_block + t];
-                a1 -= lrow[k + 1] * ycol[(k + 1 - cbase) * cols_per_block + t];
-                a2 -= lrow[k + 2] * ycol[(k + 2 - cbase) * cols_per_block + t];
-                a3 -= lrow[k + 3] * ycol[(k + 3 - cbase) * cols_per_block + t];
-            }
-            for (; k < i; ++k) a0 -= lrow[k] * ycol[(k - cbase) * cols_per_block + t];
-            ycol[(i - cbase) * cols_per_block + t] = (live && i >= c) ? ((a0 + a1) + (a2 + a3)) / lrow[i] : 0.0;
+        double acc = 0.0;
+        for (int k = cbase + sub; k < i; k += TRI_LPC) acc += lrow[k] * ycol[g * n + k];
+#pragma unroll
+        for (int off = TRI_LPC / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TRI_LPC);
+        if (sub == 0) {
+            double v = 0.0;
+            if (c < n && i >= c) v = ((i == c ? 1.0 : 0.0) - acc) / lrow[i];
+            ycol[g * n + i] = v;
         }
         __syncthreads();
     }
-    if (live) {
-        for (int i = 0; i < cbase; ++i) Li[(int64_t)i * n + c] = 0.0;
-        for (int i = cbase; i < n; ++i) Li[(int64_t)i * n + c] = ycol[(i - cbase) * cols_per_block + t];
+    if (c < n) {
+        for (int i = sub; i < n; i += TRI_LPC) Li[(int64_t)i * n + c] = i >= cbase ? ycol[g * n + i] : 0.0;
     }
 }
 
@@ -855,16 +855,9 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CHOL_THREADS), sizeof(double) * n * CHOL_NB, s, dense, (int)n,
                        err);
     EB_LAUNCH_CHECK();
-    {
-        int cpb = (int)((140 * 1024) / (sizeof(double) * n));
-        if (cpb > 64) cpb = 64;
-        if (cpb < 1) cpb = 1;
-        const unsigned nb = (unsigned)((n + cpb - 1) / cpb);
-        const unsigned nthreads = (unsigned)((cpb + WAVE - 1) / WAVE * WAVE);
-        hipLaunchKernelGGL(k_tri_inverse, dim3(nb), dim3(nthreads), sizeof(double) * (n * cpb + n), s, dense, (int)n,
-                           cpb, linv);
-        EB_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_tri_inverse, dim3((unsigned)((n + TRI_CPB - 1) / TRI_CPB)), dim3(WAVE),
+                       sizeof(double) * (TRI_CPB + 1) * n, s, dense, (int)n, linv);
+    EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gram, dim3(grid_for(n * n)), dim3(BLOCK), 0, s, linv, (int)n, L.dense_inv);
     EB_LAUNCH_CHECK();
     EB_TRY(dfree(dense, s));
@@ -1025,8 +1018,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
 
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
-                    L.r_val, L.agg, L.coords, L.crank, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.res,
-                    L.zt, L.ev};
+                    L.r_val, L.agg, L.coords, L.crank, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp};
     for (void* p : ptrs) (void)dfree(p, s);
     L = Level();
 }
@@ -1037,8 +1029,8 @@ int free_handle_memory(amg_handle* H) {
     // for any solve still running on another stream first
     if (H->last_stream && H->last_stream != s) (void)hipStreamSynchronize(H->last_stream);
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
-    void* ptrs[] = {H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, H->x, H->r,
-                    H->z, H->p[0], H->p[1], H->q, H->res, H->zt, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
+    void* ptrs[] = {H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
+                    H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
                     H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;

@@ -30,7 +30,7 @@ struct Level {
     int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
     double* dense_inv = nullptr; // coarsest: n x n
     // solve vectors (levels >= 1)
-    double* rv = nullptr; double* res = nullptr; double* zt = nullptr; double* ev = nullptr;
+    double* rv = nullptr; double* ev = nullptr; double* tmp = nullptr;
 };
 
 // Device scalars of one PCG solve.  Written only by block 0 of the kernel
@@ -80,11 +80,11 @@ struct amg_handle {
     int32_t* boxes0 = nullptr;      // level-0 boxes holding unknowns
     int64_t* fine_nodes = nullptr;  // unknown -> dense node index
     int32_t* fine_pad = nullptr;    // unknown -> padded node index
-    int8_t* kind_p = nullptr;       // padded kind (2 computational, else 0)
     double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
     int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)
     // PCG state (padded node fields)
-    double* x = nullptr; double* r = nullptr; double* z = nullptr;
+    double* x = nullptr; double* z = nullptr;
+    double* rr[2] = {nullptr, nullptr};   // residual, alternating between iterations
     double* p[2] = {nullptr, nullptr};
     double* q = nullptr; double* res = nullptr; double* zt = nullptr;
     double* bvec = nullptr;         // right-hand side in the padded layout

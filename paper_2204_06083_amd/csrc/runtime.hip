@@ -237,11 +237,11 @@ static int scan_impl(const TI* in, TO* out, int64_t n, TO* total_dev, hipStream_
     TO* sums_scan = nullptr;
     EB_TRY(dalloc_n(&sums, ntiles, s));
     EB_TRY(dalloc_n(&sums_scan, ntiles, s));
-    hipLaunchKernelGGL((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out, sums, n);
+    // a single tile writes the grand total directly
+    hipLaunchKernelGGL((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out,
+                       ntiles == 1 ? total_dev : sums, n);
     EB_LAUNCH_CHECK();
-    if (ntiles == 1) {
-        EB_HIP(hipMemcpyAsync(total_dev, sums, sizeof(TO), hipMemcpyDeviceToDevice, s));
-    } else {
+    if (ntiles > 1) {
         TO* dummy_total = nullptr;
         EB_TRY(dalloc_n(&dummy_total, 1, s));
         EB_TRY((scan_impl<TO, TO>(sums, sums_scan, ntiles, dummy_total, s)));

@@ -216,8 +216,10 @@ struct BoxArgs {
 
 __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, double omega,
                                                       const double* __restrict__ res, double* __restrict__ rc,
-                                                      const PcgScalars* sc) {
+                                                      PcgScalars* sc, int check, const double* __restrict__ part_rr,
+                                                      int np) {
     if (sc->done) return;
+    if (check && converged_or_failed(part_rr, np, sc)) return;
     const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (t >= b.nboxes) return;
     const int64_t box = b.boxes[t];
@@ -246,37 +248,95 @@ __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, dou
                 const double rp = res[p];
                 const double aw = d * (rp / d) - f.s * nbr_sum_scaled(res, p, f);
                 const double u = rp - omega * aw;
-                const int c = b.agg[p] - c0;
-                if (c >= 0 && c < MAX_FINE_COMP) acc[c] += u;
+                if (m == 1) {
+                    acc[0] += u;
+                } else {
+                    const int c = b.agg[p] - c0;
+                    if (c >= 0 && c < MAX_FINE_COMP) acc[c] += u;
+                }
             }
         }
     }
     for (int c = 0; c < m && c < MAX_FINE_COMP; ++c) rc[c0 + c] = acc[c];
 }
 
-// Prolongation and pre-smoothed correction: t = e_c[agg]; z = omega r / d +
-// t - omega (A t) / d.
+// PCG update fused with the fine pre-smoothing and residual:
+//   alpha = rho / (p, q); x += alpha p; r_out = r_in - alpha q;
+//   res = r_out - A (omega D^-1 r_out), with r_out at the neighbours recomputed
+//   from r_in and q (r_in and r_out are different buffers).
+// The convergence test on ||r_out||^2 happens in the next kernel.
+__global__ void __launch_bounds__(NT) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
+                                                    double* __restrict__ rout, const double* __restrict__ pv,
+                                                    const double* __restrict__ q, double* __restrict__ res,
+                                                    double omega, const double* __restrict__ rz_cur,
+                                                    const double* __restrict__ part_pq, int np,
+                                                    double* __restrict__ part_rr, PcgScalars* sc, int iter) {
+    if (sc->done) return;
+    const double rho = block_total(rz_cur, np);
+    const double pq = block_total(part_pq, np);
+    if (!(pq > 0.0) || bad_value(pq)) {
+        if (lead()) {
+            sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    if (lead()) {
+        sc->iters = iter;
+        sc->pq = pq;
+    }
+    double part = 0.0;
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            x[p] = x[p] + alpha * pv[p];
+            const double rn = rin[p] - alpha * q[p];
+            rout[p] = rn;
+            part += rn * rn;
+            double nb = safe_div(rin[p - 1] - alpha * q[p - 1], f.diag[p - 1]);
+            nb += safe_div(rin[p + 1] - alpha * q[p + 1], f.diag[p + 1]);
+            nb += safe_div(rin[p - f.sy] - alpha * q[p - f.sy], f.diag[p - f.sy]);
+            nb += safe_div(rin[p + f.sy] - alpha * q[p + f.sy], f.diag[p + f.sy]);
+            if (f.dim == 3) {
+                nb += safe_div(rin[p - f.sz] - alpha * q[p - f.sz], f.diag[p - f.sz]);
+                nb += safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
+            }
+            const double z1 = omega * rn / d;
+            res[p] = rn - (d * z1 - f.s * (omega * nb));
+        }
+    }
+    block_partial(part, part_rr);
+}
+
+// Coarse-grid correction value t = e_c[agg] at node p (0 off unknowns).
+__device__ inline double corr_at(const int32_t* __restrict__ agg, const double* __restrict__ ec, int64_t p) {
+    const int32_t g = agg[p];
+    return g >= 0 ? ec[g] : 0.0;
+}
+
+// Pre-smoothed iterate after prolongation at node p:
+//   zt = omega r / d + t - omega (A t) / d,  t = e_c[agg].
+__device__ inline double zt_at(const FineArgs& f, double omega, const int32_t* __restrict__ agg,
+                               const double* __restrict__ ec, const double* __restrict__ r, int64_t p) {
+    const double d = f.diag[p];
+    if (d == 0.0) return 0.0;
+    const double tp = corr_at(agg, ec, p);
+    double nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
+    nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
+    if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
+    const double at = d * tp - f.s * nb;
+    return omega * r[p] / d + (tp - omega * at / d);
+}
+
+// Prolongation and pre-smoothed correction: zt = omega r / d + t - omega (A t) / d,
+// t = e_c[agg].
 __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const int32_t* __restrict__ agg,
                                                 const double* __restrict__ ec, const double* __restrict__ r,
                                                 double* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
     FINE_LOOP(f, p) {
-        const double d = f.diag[p];
-        if (d != 0.0) {
-            const double tp = ec[agg[p]];
-            int32_t g;
-            double nb = 0.0;
-            g = agg[p - 1];      nb += g >= 0 ? ec[g] : 0.0;
-            g = agg[p + 1];      nb += g >= 0 ? ec[g] : 0.0;
-            g = agg[p - f.sy];   nb += g >= 0 ? ec[g] : 0.0;
-            g = agg[p + f.sy];   nb += g >= 0 ? ec[g] : 0.0;
-            if (f.dim == 3) {
-                g = agg[p - f.sz]; nb += g >= 0 ? ec[g] : 0.0;
-                g = agg[p + f.sz]; nb += g >= 0 ? ec[g] : 0.0;
-            }
-            const double at = d * tp - f.s * nb;
-            zt[p] = omega * r[p] / d + (tp - omega * at / d);
-        }
+        if (f.diag[p] != 0.0) zt[p] = zt_at(f, omega, agg, ec, r, p);
     }
 }
 
@@ -347,60 +407,131 @@ __global__ void __launch_bounds__(NT) k_finalize_true(PcgScalars* sc, const doub
 }
 
 // ------------------------------------------------------------ coarse kernels
-__global__ void __launch_bounds__(NT) k_csr_down(int64_t n, const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                 const double* __restrict__ diag, double omega,
-                                                 const double* __restrict__ rv, double* __restrict__ res,
-                                                 const PcgScalars* sc) {
+// LPR lanes share one CSR row (strided over its entries) and combine their
+// partial sums with butterfly shuffles inside the LPR-lane segment.
+template <int LPR>
+__device__ inline double segment_sum(double v) {
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
+    return v;
+}
+
+struct Csr {
+    const int32_t* rowptr;
+    const int32_t* col;
+    const double* val;
+};
+
+// Large coarse levels, two light passes each way:
+//   res_j = rv_j - sum_e a_je omega rv_e / d_e;   rv_c[I] = sum_j R_Ij res_j;
+//   zt_j = omega rv_j / d_j + sum_J P_jJ ev_c[J]; ev_i = zt_i + omega (rv_i - (A zt)_i) / d_i.
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr A, const double* __restrict__ diag, double omega,
+                                                  const double* __restrict__ rv, double* __restrict__ res,
+                                                  const PcgScalars* sc) {
     if (sc->done) return;
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= n) return;
     double az = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const int j = col[e];
-        az += val[e] * (omega * rv[j] / diag[j]);
+    for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
+        const int k = A.col[e];
+        az += A.val[e] * (omega * rv[k] / diag[k]);
     }
-    res[i] = rv[i] - az;
+    az = segment_sum<LPR>(az);
+    if (lane == 0) res[row] = rv[row] - az;
 }
 
-__global__ void __launch_bounds__(NT) k_csr_spmv(int64_t n, const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                 const double* __restrict__ x, double* __restrict__ y,
-                                                 const PcgScalars* sc) {
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_csr_matvec(int64_t n, Csr M, const double* __restrict__ x,
+                                                   double* __restrict__ y, const PcgScalars* sc) {
     if (sc->done) return;
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= n) return;
     double acc = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc += val[e] * x[col[e]];
-    y[i] = acc;
+    for (int e = M.rowptr[row] + lane; e < M.rowptr[row + 1]; e += LPR) acc += M.val[e] * x[M.col[e]];
+    acc = segment_sum<LPR>(acc);
+    if (lane == 0) y[row] = acc;
 }
 
-// zt = omega rv / d + P e_c
-__global__ void __launch_bounds__(NT) k_csr_up(int64_t n, const int32_t* __restrict__ rowptr,
-                                               const int32_t* __restrict__ col, const double* __restrict__ val,
-                                               const double* __restrict__ diag, double omega,
-                                               const double* __restrict__ rv, const double* __restrict__ ec,
-                                               double* __restrict__ zt, const PcgScalars* sc) {
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr P, const double* __restrict__ diag, double omega,
+                                                    const double* __restrict__ rv, const double* __restrict__ ev_c,
+                                                    double* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= n) return;
     double acc = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc += val[e] * ec[col[e]];
-    zt[i] = omega * rv[i] / diag[i] + acc;
+    for (int e = P.rowptr[row] + lane; e < P.rowptr[row + 1]; e += LPR) acc += P.val[e] * ev_c[P.col[e]];
+    acc = segment_sum<LPR>(acc);
+    if (lane == 0) zt[row] = omega * rv[row] / diag[row] + acc;
 }
 
-// ev = zt + omega (rv - A zt) / d
-__global__ void __launch_bounds__(NT) k_csr_post(int64_t n, const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                 const double* __restrict__ diag, double omega,
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr A, const double* __restrict__ diag, double omega,
                                                  const double* __restrict__ rv, const double* __restrict__ zt,
                                                  double* __restrict__ ev, const PcgScalars* sc) {
     if (sc->done) return;
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= n) return;
     double az = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) az += val[e] * zt[col[e]];
-    ev[i] = zt[i] + omega * (rv[i] - az) / diag[i];
+    for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) az += A.val[e] * zt[A.col[e]];
+    az = segment_sum<LPR>(az);
+    if (lane == 0) ev[row] = zt[row] + omega * (rv[row] - az) / diag[row];
+}
+
+// Residual and restriction in one pass:
+//   rv_c[I] = sum_{j in R row I} R_Ij (rv_j - sum_e a_je omega rv_e / d_e).
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr R, Csr A, const double* __restrict__ diag,
+                                                    double omega, const double* __restrict__ rv,
+                                                    double* __restrict__ rv_c, const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= nc) return;
+    double acc = 0.0;
+    for (int e = R.rowptr[row] + lane; e < R.rowptr[row + 1]; e += LPR) {
+        const int j = R.col[e];
+        double az = 0.0;
+        for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
+            const int k = A.col[f];
+            az += A.val[f] * (omega * rv[k] / diag[k]);
+        }
+        acc += R.val[e] * (rv[j] - az);
+    }
+    acc = segment_sum<LPR>(acc);
+    if (lane == 0) rv_c[row] = acc;
+}
+
+// Prolongation and post-smoothing in one pass:
+//   zt_j = omega rv_j / d_j + sum_{P row j} P_jJ ev_c[J];
+//   ev[i] = zt_i + omega (rv_i - sum_{A row i} a_ij zt_j) / d_i.
+template <int LPR>
+__global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr A, Csr P, const double* __restrict__ diag,
+                                                  double omega, const double* __restrict__ rv,
+                                                  const double* __restrict__ ev_c, double* __restrict__ ev,
+                                                  const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= n) return;
+    double acc = 0.0;
+    for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
+        const int j = A.col[e];
+        double zt = omega * rv[j] / diag[j];
+        for (int g = P.rowptr[j]; g < P.rowptr[j + 1]; ++g) zt += P.val[g] * ev_c[P.col[g]];
+        acc += A.val[e] * zt;
+    }
+    acc = segment_sum<LPR>(acc);
+    if (lane == 0) {
+        double zi = omega * rv[row] / diag[row];
+        for (int g = P.rowptr[row]; g < P.rowptr[row + 1]; ++g) zi += P.val[g] * ev_c[P.col[g]];
+        ev[row] = zi + omega * (rv[row] - acc) / diag[row];
+    }
 }
 
 // Coarsest: ev = W rv with W the dense inverse; one wavefront per row.
@@ -474,7 +605,7 @@ __global__ void __launch_bounds__(NT) k_copy_f64(int64_t n, const double* __rest
 __global__ void __launch_bounds__(BLOCK) k_fine_layout(const int64_t* __restrict__ fine_nodes, int64_t nunk,
                                                        GridDims d, int px, const double* __restrict__ diag0,
                                                        const int32_t* __restrict__ agg0, int has_agg,
-                                                       int32_t* __restrict__ fine_pad, int8_t* __restrict__ kind_p,
+                                                       int32_t* __restrict__ fine_pad,
                                                        double* __restrict__ diag_p, int32_t* __restrict__ agg_p,
                                                        int32_t* __restrict__ strip_flag, int strip_w) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -484,7 +615,6 @@ __global__ void __launch_bounds__(BLOCK) k_fine_layout(const int64_t* __restrict
     const int64_t row = n / d.nx;
     const int64_t pidx = i + (int64_t)px * row;
     fine_pad[k] = (int32_t)pidx;
-    kind_p[pidx] = 2;
     diag_p[pidx] = diag0[k];
     agg_p[pidx] = has_agg ? agg0[k] : -1;
     strip_flag[pidx / strip_w] = 1;
@@ -571,16 +701,80 @@ static BoxArgs box_args(const amg_handle* H) {
     return b;
 }
 
-// z = M r on padded fine fields; the last kernel writes the (r, z) partials
-// to rz_out.  With `check`, the first kernel tests convergence of r first.
-static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_out, int check, hipStream_t s) {
+static int lanes_for(double avg_row) {
+    int l = 4;
+    while (l < 32 && l < avg_row * 0.75) l <<= 1;
+    return l;
+}
+
+#define EB_LPR_LAUNCH(KERNEL, lpr, rows, ...)                                                         \
+    do {                                                                                          \
+        const unsigned g_ = grid_for((rows) * (int64_t)(lpr), NT);                               \
+        switch (lpr) {                                                                            \
+            case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
+            case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
+            case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<32>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
+        }                                                                                         \
+    } while (0)
+
+// Coarse levels with more unknowns than this take two light passes each way;
+// smaller ones (launch bound) take one fused pass that recomputes the residual
+// or the prolongated correction at the neighbours.
+constexpr int64_t FUSE_BELOW = 20000;
+
+// Coarse part of the V-cycle, levels 1 .. nlev-1: rv_1 -> ev_1.
+static int enqueue_coarse(amg_handle* H, hipStream_t s) {
+    const PcgScalars* sc = H->sc;
+    for (int l = 1; l < H->nlev - 1; ++l) {
+        Level& L = H->lev[l];
+        Level& C = H->lev[l + 1];
+        const int lpr_r = lanes_for((double)L.nnz_r / (double)(C.n > 0 ? C.n : 1));
+        if (L.n >= FUSE_BELOW) {
+            const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
+            EB_LPR_LAUNCH(k_csr_resid, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv,
+                          L.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_matvec, lpr_r, C.n, C.n, Csr{L.r_rowptr, L.r_col, L.r_val}, L.tmp, C.rv, sc);
+        } else {
+            EB_LPR_LAUNCH(k_coarse_down, lpr_r, C.n, C.n, Csr{L.r_rowptr, L.r_col, L.r_val},
+                          Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv, C.rv, sc);
+        }
+    }
+    {
+        Level& Lc = H->lev[H->nlev - 1];
+        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv, Lc.rv,
+                           Lc.ev, sc);
+    }
+    for (int l = H->nlev - 2; l >= 1; --l) {
+        Level& L = H->lev[l];
+        Level& C = H->lev[l + 1];
+        const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
+        if (L.n >= FUSE_BELOW) {
+            const int lpr_p = lanes_for((double)L.nnz_p / (double)(L.n > 0 ? L.n : 1));
+            EB_LPR_LAUNCH(k_csr_prolong, lpr_p, L.n, L.n, Csr{L.p_rowptr, L.p_col, L.p_val}, L.diag, L.omega, L.rv,
+                          C.ev, L.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_post, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv,
+                          L.tmp, L.ev, sc);
+        } else {
+            EB_LPR_LAUNCH(k_coarse_up, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val},
+                          Csr{L.p_rowptr, L.p_col, L.p_val}, L.diag, L.omega, L.rv, C.ev, L.ev, sc);
+        }
+    }
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// z = M r for the initial residual (or a standalone V-cycle): fine
+// pre-smoothing, restriction, coarse levels, fused prolongation and
+// post-smoothing; the last kernel writes the (r, z) partials to rz_out.
+static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_out, hipStream_t s) {
     PcgScalars* sc = H->sc;
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
     if (H->nlev == 1) {
         Level& L = H->lev[0];
         const int64_t n = L.n;
-        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc, check, H->red.rr, np);
+        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc, 0, H->red.rr, np);
         hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv, L.ev,
                            (const PcgScalars*)sc);
         hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, r, z, rz_out,
@@ -591,31 +785,11 @@ static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_
     const FineArgs f = fine_args(H);
     const double w0 = H->lev[0].omega;
     EB_TIMED(H, EB_K_FINE_DOWN, s,
-             hipLaunchKernelGGL(k_fine_down, G, dim3(NT), 0, s, f, w0, r, H->res, sc, check, H->red.rr, np));
+             hipLaunchKernelGGL(k_fine_down, G, dim3(NT), 0, s, f, w0, r, H->res, sc, 0, H->red.rr, np));
     EB_TIMED(H, EB_K_FINE_RESTRICT, s,
              hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0,
-                                H->res, H->lev[1].rv, (const PcgScalars*)sc));
-    for (int l = 1; l < H->nlev - 1; ++l) {
-        Level& L = H->lev[l];
-        Level& C = H->lev[l + 1];
-        hipLaunchKernelGGL(k_csr_down, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.a_rowptr, L.a_col, L.a_val,
-                           L.diag, L.omega, L.rv, L.res, (const PcgScalars*)sc);
-        hipLaunchKernelGGL(k_csr_spmv, dim3(grid_for(C.n, NT)), dim3(NT), 0, s, C.n, L.r_rowptr, L.r_col, L.r_val,
-                           L.res, C.rv, (const PcgScalars*)sc);
-    }
-    {
-        Level& Lc = H->lev[H->nlev - 1];
-        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv, Lc.rv,
-                           Lc.ev, (const PcgScalars*)sc);
-    }
-    for (int l = H->nlev - 2; l >= 1; --l) {
-        Level& L = H->lev[l];
-        Level& C = H->lev[l + 1];
-        hipLaunchKernelGGL(k_csr_up, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.p_rowptr, L.p_col, L.p_val,
-                           L.diag, L.omega, L.rv, C.ev, L.zt, (const PcgScalars*)sc);
-        hipLaunchKernelGGL(k_csr_post, dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, L.a_rowptr, L.a_col, L.a_val,
-                           L.diag, L.omega, L.rv, L.zt, L.ev, (const PcgScalars*)sc);
-    }
+                                H->res, H->lev[1].rv, sc, 0, H->red.rr, np));
+    EB_TRY(enqueue_coarse(H, s));
     EB_TIMED(H, EB_K_FINE_UP, s,
              hipLaunchKernelGGL(k_fine_up, G, dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, r, H->zt,
                                 (const PcgScalars*)sc));
@@ -625,24 +799,56 @@ static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_
     return EB_OK;
 }
 
-// Iteration k >= 1 of a run: the V-cycle before it (number k-1) wrote
-// rz[(k-1) % 2]; this iteration's V-cycle writes rz[k % 2].
+// Iteration k >= 1 of a run.  The V-cycle before it (number k-1) wrote
+// rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
+// r[k % 2] and its V-cycle writes rz[k % 2].
 static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
     double* pold = H->p[k & 1];
     double* pnew = H->p[(k + 1) & 1];
+    double* rin = H->rr[(k - 1) & 1];
+    double* rout = H->rr[k & 1];
     const double* rz_cur = H->red.rz[(k - 1) & 1];
     const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
+    double* rz_out = H->red.rz[k & 1];
+    PcgScalars* sc = H->sc;
     EB_TIMED(H, EB_K_PCG_SPMV, s,
              hipLaunchKernelGGL(k_pcg_p_spmv, G, dim3(NT), 0, s, f, H->z, pold, pnew, H->q, rz_cur, rz_prev, np,
-                                H->red.pq, H->sc));
+                                H->red.pq, sc));
+    if (H->nlev == 1) {
+        EB_TIMED(H, EB_K_PCG_XR, s,
+                 hipLaunchKernelGGL(k_pcg_xr, G, dim3(NT), 0, s, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
+                                    H->red.rr, sc, iter_global));
+        // k_pcg_xr updates r in place: keep both buffers equal
+        hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
+        Level& L = H->lev[0];
+        const int64_t n = L.n;
+        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, rout, L.rv, sc, 1, H->red.rr, np);
+        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv, L.ev,
+                           (const PcgScalars*)sc);
+        hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, rout, H->z, rz_out,
+                           (const PcgScalars*)sc);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
+    const double w0 = H->lev[0].omega;
     EB_TIMED(H, EB_K_PCG_XR, s,
-             hipLaunchKernelGGL(k_pcg_xr, G, dim3(NT), 0, s, f, H->x, H->r, pnew, H->q, rz_cur, H->red.pq, np,
-                                H->red.rr, H->sc, iter_global));
+             hipLaunchKernelGGL(k_pcg_xr_down, G, dim3(NT), 0, s, f, H->x, rin, rout, pnew, H->q, H->res, w0, rz_cur,
+                                H->red.pq, np, H->red.rr, sc, iter_global));
+    EB_TIMED(H, EB_K_FINE_RESTRICT, s,
+             hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0,
+                                H->res, H->lev[1].rv, sc, 1, H->red.rr, np));
+    EB_TRY(enqueue_coarse(H, s));
+    EB_TIMED(H, EB_K_FINE_UP, s,
+             hipLaunchKernelGGL(k_fine_up, G, dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, rout, H->zt,
+                                (const PcgScalars*)sc));
+    EB_TIMED(H, EB_K_FINE_POST, s,
+             hipLaunchKernelGGL(k_fine_post, G, dim3(NT), 0, s, f, w0, H->zt, rout, H->z, rz_out,
+                                (const PcgScalars*)sc));
     EB_LAUNCH_CHECK();
-    return enqueue_vcycle(H, H->r, H->z, H->red.rz[k & 1], 1, s);
+    return EB_OK;
 }
 
 // b, x0 -> r0 = b - A x0; ||b||^2, ||r0||^2, tolerance, initial convergence test.
@@ -651,7 +857,7 @@ static int enqueue_init(amg_handle* H, double tol, int iters, hipStream_t s) {
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
     hipLaunchKernelGGL(k_fine_norm2, G, dim3(NT), 0, s, f, H->bvec, H->red.aux);
-    hipLaunchKernelGGL(k_fine_resid, G, dim3(NT), 0, s, f, H->bvec, H->x, H->r, H->red.rr);
+    hipLaunchKernelGGL(k_fine_resid, G, dim3(NT), 0, s, f, H->bvec, H->x, H->rr[0], H->red.rr);
     hipLaunchKernelGGL(k_finalize_init, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, H->red.rr, np, tol, iters);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -669,10 +875,8 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     EB_TRY(dalloc_n(&H->dcount, 2, s));
     EB_HIP(hipMemsetAsync(H->dcount, 0, 2 * sizeof(int32_t), s));
     EB_TRY(dalloc_n(&H->fine_pad, nunk, s));
-    EB_TRY(dalloc_n(&H->kind_p, npad, s));
     EB_TRY(dalloc_n(&H->diag_p, npad, s));
     EB_TRY(dalloc_n(&H->agg_p, npad, s));
-    EB_HIP(hipMemsetAsync(H->kind_p, 0, npad, s));
     EB_HIP(hipMemsetAsync(H->diag_p, 0, sizeof(double) * npad, s));
     EB_HIP(hipMemsetAsync(H->agg_p, 0xff, sizeof(int32_t) * npad, s));   // -1
     const int64_t nstrip_all = npad / H->strip_w;
@@ -681,7 +885,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     EB_HIP(hipMemsetAsync(sflag, 0, sizeof(int32_t) * nstrip_all, s));
     Level& L0 = H->lev[0];
     hipLaunchKernelGGL(k_fine_layout, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, H->fine_nodes, nunk, d, H->px, L0.diag,
-                       L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->kind_p, H->diag_p, H->agg_p, sflag,
+                       L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->diag_p, H->agg_p, sflag,
                        H->strip_w);
     EB_LAUNCH_CHECK();
     {
@@ -713,30 +917,28 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
             return EB_ENOSPC;
         }
     }
-    double** vecs[] = {&H->x, &H->r, &H->z, &H->p[0], &H->p[1], &H->q, &H->res, &H->zt, &H->bvec};
-    for (double** v : vecs) {
+    // Fields read at neighbours without a guard must be zero off unknowns
+    // (kernels only ever write unknowns); the others are fully written first
+    // or read only where the diagonal is non-zero.
+    double** zeroed[] = {&H->x, &H->z, &H->zt, &H->p[0], &H->p[1]};
+    for (double** v : zeroed) {
         EB_TRY(dalloc_n(v, npad, s));
         EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * npad, s));
     }
+    double** plain[] = {&H->rr[0], &H->rr[1], &H->q, &H->res, &H->bvec};
+    for (double** v : plain) EB_TRY(dalloc_n(v, npad, s));
     for (int l = 0; l < H->nlev; ++l) {
         Level& L = H->lev[l];
         if (l == 0 && H->nlev > 1) continue;
         const int64_t n = L.n > 0 ? L.n : 1;
         EB_TRY(dalloc_n(&L.rv, n, s));
-        EB_TRY(dalloc_n(&L.res, n, s));
-        EB_TRY(dalloc_n(&L.zt, n, s));
         EB_TRY(dalloc_n(&L.ev, n, s));
-        EB_HIP(hipMemsetAsync(L.rv, 0, sizeof(double) * n, s));
-        EB_HIP(hipMemsetAsync(L.ev, 0, sizeof(double) * n, s));
+        EB_TRY(dalloc_n(&L.tmp, n, s));
     }
     EB_TRY(dalloc_n(&H->sc, 1, s));
-    EB_HIP(hipMemsetAsync(H->sc, 0, sizeof(PcgScalars), s));
     H->sc_host = &H->sc_mirror;   // pageable, per handle (polled a few times per solve)
     double** parts[] = {&H->red.pq, &H->red.rr, &H->red.rz[0], &H->red.rz[1], &H->red.aux, &H->red.aux2};
-    for (double** v : parts) {
-        EB_TRY(dalloc_n(v, MAX_PARTS, s));
-        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * MAX_PARTS, s));
-    }
+    for (double** v : parts) EB_TRY(dalloc_n(v, MAX_PARTS, s));
     EB_HIP(hipEventCreate(&H->ev0));
     EB_HIP(hipEventCreate(&H->ev1));
     return EB_OK;
@@ -815,7 +1017,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     int rc = EB_OK;
     while (true) {
         EB_TRY(enqueue_init(H, p.tol, iter_base, s));
-        EB_TRY(enqueue_vcycle(H, H->r, H->z, H->red.rz[0], 0, s));   // V-cycle 0: rz[0]
+        EB_TRY(enqueue_vcycle(H, H->rr[0], H->z, H->red.rz[0], s));   // V-cycle 0 -> rz[0]
         int k = 0;
         while (true) {
             EB_TRY(poll_scalars(H, s));
@@ -889,9 +1091,9 @@ extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, voi
     if (nunk == 0) return EB_OK;
     const unsigned ug = grid_for(nunk, NT);
     hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
-    hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, r, H->r);
+    hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, r, H->rr[0]);
     EB_LAUNCH_CHECK();
-    EB_TRY(enqueue_vcycle(H, H->r, H->z, H->red.aux2, 0, s));
+    EB_TRY(enqueue_vcycle(H, H->rr[0], H->z, H->red.aux2, s));
     hipLaunchKernelGGL(k_store_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z, z);
     EB_LAUNCH_CHECK();
     EB_HIP(hipStreamSynchronize(s));

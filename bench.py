@@ -57,12 +57,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--kernel", default="pcg_spmv", choices=sorted(KERNEL_BYTES))
+    ap.add_argument("--kernel", default="pcg_xr_down", choices=sorted(KERNEL_BYTES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="print a markdown summary of a rocprofv3 --stats/--pmc output directory and exit")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="summarise FETCH_SIZE / WRITE_SIZE passes of --kernel and of --copy-calib, then exit")
     ap.add_argument("--phases", action="store_true",
                     help="diagnostics: synchronise between phases and report host time per phase")
     return ap.parse_args()
@@ -149,8 +151,69 @@ def rocprof_summary(path, top=25):
     print("\n".join(out))
 
 
+KERNEL_SYMBOLS = {"pcg_spmv": "eb::k_pcg_p_spmv", "pcg_xr_down": "eb::k_pcg_xr_down", "fine_down": "eb::k_fine_down",
+                  "fine_restrict": "eb::k_fine_restrict", "fine_up": "eb::k_fine_up", "fine_post": "eb::k_fine_post"}
+SOLVE_SOURCE = os.path.join(ROOT, "paper_2204_06083_amd", "csrc", "solve.hip")
+COPY_BYTES = 256 << 20
+
+
+def _sha256(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def _counter_mean(path, kernel_prefix):
+    import csv
+    import glob
+    vals = []
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Kernel_Name"].split("(")[0] == kernel_prefix:
+                vals.append(float(r["Counter_Value"]))
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def pmc_summary(args):
+    """Per-launch HBM traffic of one kernel from FETCH_SIZE / WRITE_SIZE passes,
+    each scaled by what the same counter reads for a plain copy of known size."""
+    fdir, wdir, cfdir, cwdir = args.pmc_summary
+    sym = KERNEL_SYMBOLS[args.kernel]
+    fetch, nf = _counter_mean(fdir, sym)
+    write, nw = _counter_mean(wdir, sym)
+    cfetch, _ = _counter_mean(cfdir, "__amd_rocclr_copyBuffer")
+    cwrite, _ = _counter_mean(cwdir, "__amd_rocclr_copyBuffer")
+    f_scale = COPY_BYTES / (cfetch * 1024.0)
+    w_scale = COPY_BYTES / (cwrite * 1024.0)
+    traffic = fetch * 1024.0 * f_scale + write * 1024.0 * w_scale
+    rec = {"kernel": args.kernel, "symbol": sym, "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+           "dispatches": [nf, nw], "copy_fetch_kib": cfetch, "copy_write_kib": cwrite,
+           "fetch_scale": f_scale, "write_scale": w_scale, "traffic_bytes_per_launch": traffic,
+           "solve_source_sha256": _sha256(SOLVE_SOURCE)}
+    print(f"kernel `{sym}`: FETCH_SIZE {fetch:.0f} KiB x {f_scale:.3f}, WRITE_SIZE {write:.0f} KiB x {w_scale:.3f} "
+          f"per dispatch -> {traffic / 1e6:.2f} MB per launch")
+    print()
+    print("traffic-json: " + json.dumps(rec))
+
+
+def load_traffic(kernel):
+    """traffic bytes per launch from the committed counter summary, if the
+    solve source is unchanged since the counters were taken (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_star2d_2048.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+            if rec.get("solve_source_sha256") == _sha256(SOLVE_SOURCE) and rec.get("kernel") == kernel:
+                return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
         return
@@ -272,7 +335,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": load_traffic(args.kernel),
             "avg_launch_us": avg_launch_ms * 1e3,
             "launches_timed": timing["launches"],
             "algorithmic_bytes_per_launch": bytes_per_launch,

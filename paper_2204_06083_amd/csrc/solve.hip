@@ -21,6 +21,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
 #include "handle.hpp"
 
 namespace eb {
@@ -28,9 +30,22 @@ namespace eb {
 constexpr int NT = 256;        // threads per block of every solve kernel
 constexpr int MAX_PARTS = 1024;
 
+// The GPU hands out workgroups round-robin over its 8 XCDs, each with its own
+// L2.  Renumbering blocks so that XCD x owns the contiguous block range
+// [x G/8, (x+1) G/8) (G a multiple of 8) keeps neighbouring grid rows, which
+// the stencil reads from adjacent strips, inside one L2.
+constexpr int NUM_XCD = 8;
+
+__device__ inline int64_t xcd_block() {
+    const int64_t per = gridDim.x / NUM_XCD;
+    if (per == 0 || (gridDim.x % NUM_XCD) != 0) return blockIdx.x;
+    return (int64_t)(blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+}
+
 struct FineArgs {
     const int32_t* strips;
-    int64_t nthreads;     // nstrips * strip_w virtual threads
+    int64_t nstrips;
+    int64_t spb;          // strips per block (contiguous range per block)
     int strip_w;
     int64_t sy, sz;       // padded strides
     int dim;
@@ -38,15 +53,15 @@ struct FineArgs {
     const double* diag;   // padded, 0 off unknowns
 };
 
-__device__ inline int64_t strip_node(const FineArgs& f, int64_t gid) {
-    const int64_t sidx = gid / f.strip_w;
-    return (int64_t)f.strips[sidx] * f.strip_w + (gid - sidx * f.strip_w);
-}
-
-#define FINE_LOOP(f, p)                                                                         \
-    for (int64_t gid_ = (int64_t)blockIdx.x * NT + threadIdx.x; gid_ < (f).nthreads;            \
-         gid_ += (int64_t)gridDim.x * NT)                                                        \
-        for (int64_t p = strip_node((f), gid_), once_ = 0; once_ < 1; ++once_)
+// Each block sweeps its own contiguous range of strips, NT / strip_w strips
+// at a time; p is the padded node index of this thread's node.
+#define FINE_LOOP(f, p)                                                                          \
+    for (int64_t s0_ = xcd_block() * (f).spb, s1_ = min(s0_ + (f).spb, (f).nstrips),              \
+                 sidx_ = s0_ + threadIdx.x / (f).strip_w;                                          \
+         sidx_ < s1_; sidx_ += NT / (f).strip_w)                                                   \
+        for (int64_t p = (int64_t)(f).strips[sidx_] * (f).strip_w + threadIdx.x % (f).strip_w,     \
+                     once_ = 0;                                                                    \
+             once_ < 1; ++once_)
 
 __device__ inline double nbr_sum(const double* __restrict__ v, int64_t p, const FineArgs& f) {
     double t = v[p - 1] + v[p + 1];
@@ -220,7 +235,7 @@ __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, dou
                                                       int np) {
     if (sc->done) return;
     if (check && converged_or_failed(part_rr, np, sc)) return;
-    const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t t = xcd_block() * NT + threadIdx.x;
     if (t >= b.nboxes) return;
     const int64_t box = b.boxes[t];
     const int bx = (int)(box % b.nbx);
@@ -648,34 +663,43 @@ static int timing_harvest(amg_handle* H) {
     return EB_OK;
 }
 
-static int timing_begin(amg_handle* H, int id, hipStream_t s, bool* on) {
-    *on = H->tim_kernel == id;
-    if (!*on) return EB_OK;
+// Events for the next timed launch of kernel `id` (null when not timed).
+// The launch records them at the kernel's own start and end
+// (hipExtLaunchKernel), so the durations match a kernel trace.
+static int timing_slot(amg_handle* H, int id, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (H->tim_kernel != id) return EB_OK;
     if (H->tim_used == H->tim_cap) EB_TRY(timing_harvest(H));
     H->tim_stream = s;
-    EB_HIP(hipEventRecord(H->tim_ev[2 * H->tim_used], s));
-    return EB_OK;
-}
-
-static int timing_end(amg_handle* H, bool on, hipStream_t s) {
-    if (!on) return EB_OK;
-    EB_HIP(hipEventRecord(H->tim_ev[2 * H->tim_used + 1], s));
+    *e0 = H->tim_ev[2 * H->tim_used];
+    *e1 = H->tim_ev[2 * H->tim_used + 1];
     H->tim_used += 1;
     return EB_OK;
 }
 
-#define EB_TIMED(H, id, s, launch)                    \
-    do {                                             \
-        bool on_;                                    \
-        EB_TRY(timing_begin((H), (id), (s), &on_));  \
-        launch;                                      \
-        EB_TRY(timing_end((H), on_, (s)));           \
+#define EB_TIMED_LAUNCH(H, id, s, KERNEL, GRID, BLOCKDIM, SHMEM, ...)                          \
+    do {                                                                                      \
+        hipEvent_t e0_, e1_;                                                                  \
+        EB_TRY(timing_slot((H), (id), (s), &e0_, &e1_));                                      \
+        if (e0_)                                                                              \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCKDIM, SHMEM, s, e0_, e1_, 0, __VA_ARGS__); \
+        else                                                                                  \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCKDIM, SHMEM, s, __VA_ARGS__);                \
     } while (0)
+
+// grid of NT-thread blocks covering n items, rounded up to whole XCD groups
+static unsigned xcd_grid(int64_t n) {
+    int64_t g = (n + NT - 1) / NT;
+    g = (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+    return (unsigned)(g > 0 ? g : NUM_XCD);
+}
 
 static FineArgs fine_args(const amg_handle* H) {
     FineArgs f;
     f.strips = H->strips;
-    f.nthreads = H->nstrips * H->strip_w;
+    f.nstrips = H->nstrips;
+    const int64_t np = H->red.nparts;
+    f.spb = (H->nstrips + np - 1) / np;
     f.strip_w = H->strip_w;
     f.sy = H->px;
     f.sz = (int64_t)H->px * H->d.ny;
@@ -784,17 +808,13 @@ static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_
     }
     const FineArgs f = fine_args(H);
     const double w0 = H->lev[0].omega;
-    EB_TIMED(H, EB_K_FINE_DOWN, s,
-             hipLaunchKernelGGL(k_fine_down, G, dim3(NT), 0, s, f, w0, r, H->res, sc, 0, H->red.rr, np));
-    EB_TIMED(H, EB_K_FINE_RESTRICT, s,
-             hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0,
-                                H->res, H->lev[1].rv, sc, 0, H->red.rr, np));
+    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, k_fine_down, G, dim3(NT), 0, f, w0, r, H->res, sc, 0, H->red.rr, np);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f, box_args(H), w0,
+                                H->res, H->lev[1].rv, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse(H, s));
-    EB_TIMED(H, EB_K_FINE_UP, s,
-             hipLaunchKernelGGL(k_fine_up, G, dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, r, H->zt,
-                                (const PcgScalars*)sc));
-    EB_TIMED(H, EB_K_FINE_POST, s,
-             hipLaunchKernelGGL(k_fine_post, G, dim3(NT), 0, s, f, w0, H->zt, r, z, rz_out, (const PcgScalars*)sc));
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up, G, dim3(NT), 0, f, w0, H->agg_p, H->lev[1].ev, r, H->zt,
+                                (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post, G, dim3(NT), 0, f, w0, H->zt, r, z, rz_out, (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -814,13 +834,11 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
     const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
     double* rz_out = H->red.rz[k & 1];
     PcgScalars* sc = H->sc;
-    EB_TIMED(H, EB_K_PCG_SPMV, s,
-             hipLaunchKernelGGL(k_pcg_p_spmv, G, dim3(NT), 0, s, f, H->z, pold, pnew, H->q, rz_cur, rz_prev, np,
-                                H->red.pq, sc));
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur, rz_prev, np,
+                                H->red.pq, sc);
     if (H->nlev == 1) {
-        EB_TIMED(H, EB_K_PCG_XR, s,
-                 hipLaunchKernelGGL(k_pcg_xr, G, dim3(NT), 0, s, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
-                                    H->red.rr, sc, iter_global));
+        EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr, G, dim3(NT), 0, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
+                                    H->red.rr, sc, iter_global);
         // k_pcg_xr updates r in place: keep both buffers equal
         hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
         Level& L = H->lev[0];
@@ -834,19 +852,15 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
         return EB_OK;
     }
     const double w0 = H->lev[0].omega;
-    EB_TIMED(H, EB_K_PCG_XR, s,
-             hipLaunchKernelGGL(k_pcg_xr_down, G, dim3(NT), 0, s, f, H->x, rin, rout, pnew, H->q, H->res, w0, rz_cur,
-                                H->red.pq, np, H->red.rr, sc, iter_global));
-    EB_TIMED(H, EB_K_FINE_RESTRICT, s,
-             hipLaunchKernelGGL(k_fine_restrict, dim3(grid_for(H->nboxes0, NT)), dim3(NT), 0, s, f, box_args(H), w0,
-                                H->res, H->lev[1].rv, sc, 1, H->red.rr, np));
+    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr_down, G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, H->res, w0, rz_cur,
+                                H->red.pq, np, H->red.rr, sc, iter_global);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f, box_args(H), w0,
+                                H->res, H->lev[1].rv, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse(H, s));
-    EB_TIMED(H, EB_K_FINE_UP, s,
-             hipLaunchKernelGGL(k_fine_up, G, dim3(NT), 0, s, f, w0, H->agg_p, H->lev[1].ev, rout, H->zt,
-                                (const PcgScalars*)sc));
-    EB_TIMED(H, EB_K_FINE_POST, s,
-             hipLaunchKernelGGL(k_fine_post, G, dim3(NT), 0, s, f, w0, H->zt, rout, H->z, rz_out,
-                                (const PcgScalars*)sc));
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up, G, dim3(NT), 0, f, w0, H->agg_p, H->lev[1].ev, rout, H->zt,
+                                (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post, G, dim3(NT), 0, f, w0, H->zt, rout, H->z, rz_out,
+                                (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -950,8 +964,9 @@ int solve_layout_finish(amg_handle* H, hipStream_t s) {
     (void)s;
     const int64_t nthreads = H->nlev == 1 ? H->n_fine : H->nstrips * H->strip_w;
     int64_t np = (nthreads + NT - 1) / NT;
-    if (np < 1) np = 1;
     if (np > MAX_PARTS) np = MAX_PARTS;
+    np = (np + NUM_XCD - 1) / NUM_XCD * NUM_XCD;   // whole XCD groups
+    if (np < NUM_XCD) np = NUM_XCD;
     H->red.nparts = (int)np;
     return EB_OK;
 }

@@ -146,101 +146,211 @@ __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ 
 
 // ---------------------------------------------------------------- aggregation
 __global__ void __launch_bounds__(BLOCK) k_box_count(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
-                                                     int32_t* __restrict__ cnt) {
+                                                     int32_t* __restrict__ cnt, int32_t* __restrict__ boxid) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
+    boxid[i] = (int32_t)b;
     atomicAdd(&cnt[b], 1);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_box_fill(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
+__global__ void __launch_bounds__(BLOCK) k_box_fill(const int32_t* __restrict__ boxid, int64_t n,
                                                     const int32_t* __restrict__ boff, int32_t* __restrict__ fillpos,
                                                     int32_t* __restrict__ members) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
-    const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
+    const int32_t b = boxid[i];
     const int32_t slot = atomicAdd(&fillpos[b], 1);
     members[boff[b] + slot] = (int32_t)i;
 }
 
-constexpr int MAX_BOX_MEMBERS = 128;
+// Level 0: a box covers at most 3^d grid nodes and the graph of A_0 inside it
+// is the grid adjacency among its unknowns, so its components come from bit
+// masks: node offset (ii, jj, kk) is bit (kk * 3 + jj) * 3 + ii.  Bit order is
+// node order, which is unknown order, so the lowest bit of a component is its
+// smallest member and components numbered in lowest-bit order follow the
+// smallest-member rule.
+__device__ inline uint32_t grow27(uint32_t c) {
+    constexpr uint32_t X0 = 0x1249249u;   // ii == 0
+    constexpr uint32_t X2 = X0 << 2;      // ii == 2
+    constexpr uint32_t Y0 = 0x01C0E07u;   // jj == 0
+    constexpr uint32_t Y2 = Y0 << 6;      // jj == 2
+    return c | ((c << 1) & ~X0) | ((c >> 1) & ~X2) | ((c << 3) & ~Y0) | ((c >> 3) & ~Y2) | (c << 9) | (c >> 9);
+}
 
-__device__ inline int uf_find(int* parent, int x) {
-    while (parent[x] != x) x = parent[x];
+__global__ void __launch_bounds__(BLOCK) k_box_components0(const int8_t* __restrict__ kind, GridDims d, NB3 nb,
+                                                           int64_t nboxes, const int32_t* __restrict__ unk_off,
+                                                           int32_t* __restrict__ lrank,
+                                                           int32_t* __restrict__ ncomp) {
+    const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (b >= nboxes) return;
+    const int bx = (int)(b % nb.v[0]);
+    const int64_t rq = b / nb.v[0];
+    const int by = (int)(rq % nb.v[1]);
+    const int bz = (int)(rq / nb.v[1]);
+    const int kz = d.dim == 3 ? 3 : 1;
+    uint32_t mask = 0;
+    for (int kk = 0; kk < kz; ++kk) {
+        const int k = 3 * bz + kk;
+        if (d.dim == 3 && (k < 1 || k > d.nz - 2)) continue;
+        for (int jj = 0; jj < 3; ++jj) {
+            const int j = 3 * by + jj;
+            if (j < 1 || j > d.ny - 2) continue;
+            for (int ii = 0; ii < 3; ++ii) {
+                const int i = 3 * bx + ii;
+                if (i < 1 || i > d.nx - 2) continue;
+                if (kind[(int64_t)i + d.sy * j + d.sz * k] == 2) mask |= 1u << ((kk * 3 + jj) * 3 + ii);
+            }
+        }
+    }
+    int rank = 0;
+    uint32_t rem = mask;
+    while (rem) {
+        uint32_t comp = rem & (~rem + 1u);
+        for (;;) {
+            const uint32_t g = grow27(comp) & mask;
+            if (g == comp) break;
+            comp = g;
+        }
+        rem &= ~comp;
+        for (uint32_t w = comp; w; w &= w - 1u) {
+            const int p = __ffs(w) - 1;
+            const int ii = p % 3, jj = (p / 3) % 3, kk = p / 9;
+            const int64_t node = (int64_t)(3 * bx + ii) + d.sy * (3 * by + jj) + d.sz * (3 * bz + kk);
+            lrank[unk_off[node]] = rank;
+        }
+        ++rank;
+    }
+    ncomp[b] = rank;
+}
+
+constexpr int MAX_BOX_MEMBERS = 128;
+constexpr int BOX_WAVES = 4;    // boxes (one wavefront each) per workgroup
+
+__device__ inline int uf_root(volatile int32_t* parent, int x) {
+    int p = parent[x];
+    while (p != x) {
+        x = p;
+        p = parent[x];
+    }
     return x;
 }
 
-// One thread per box: sort the members, union-find over the edges of A that
-// stay inside the box (the root of a set is always its smallest local index,
-// hence its smallest member), number the components by smallest member.
-__global__ void __launch_bounds__(64) k_box_components(const int32_t* __restrict__ boff,
-                                                       const int32_t* __restrict__ cnt,
-                                                       const int32_t* __restrict__ members,
-                                                       const int32_t* __restrict__ rowptr,
-                                                       const int32_t* __restrict__ col,
-                                                       const int32_t* __restrict__ coords, NB3 nb, int64_t nboxes,
-                                                       int32_t* __restrict__ lrank, int32_t* __restrict__ ncomp,
-                                                       int32_t* __restrict__ err) {
-    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (b >= nboxes) return;
-    const int m = cnt[b];
-    if (m == 0) {
-        ncomp[b] = 0;
-        return;
-    }
+// Levels >= 1: one wavefront per box.  The members are ranked by value in
+// LDS, the edges of A that stay inside the box are spread over the lanes and
+// merged with a lock-free union-find (a root is only ever attached below a
+// smaller root, so each component ends rooted at its smallest member), and
+// the roots are numbered in member order with a ballot prefix count.
+__global__ void __launch_bounds__(BOX_WAVES * WAVE) k_box_components(const int32_t* __restrict__ boff,
+                                                                     const int32_t* __restrict__ cnt,
+                                                                     const int32_t* __restrict__ members,
+                                                                     const int32_t* __restrict__ rowptr,
+                                                                     const int32_t* __restrict__ col,
+                                                                     const int32_t* __restrict__ boxid,
+                                                                     int64_t nboxes, int32_t* __restrict__ lrank,
+                                                                     int32_t* __restrict__ ncomp,
+                                                                     int32_t* __restrict__ err) {
+    __shared__ int32_t raw_s[BOX_WAVES][MAX_BOX_MEMBERS];
+    __shared__ int32_t srt_s[BOX_WAVES][MAX_BOX_MEMBERS];
+    __shared__ int32_t par_s[BOX_WAVES][MAX_BOX_MEMBERS];
+    __shared__ int32_t eoff_s[BOX_WAVES][MAX_BOX_MEMBERS + 1];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t b = (int64_t)blockIdx.x * BOX_WAVES + w;
+    int m = b < nboxes ? cnt[b] : 0;
     if (m > MAX_BOX_MEMBERS) {
-        atomicOr(err, DEVERR_CAP);
-        ncomp[b] = 0;
-        return;
-    }
-    int mem[MAX_BOX_MEMBERS];
-    int parent[MAX_BOX_MEMBERS];
-    const int32_t base = boff[b];
-    for (int t = 0; t < m; ++t) {
-        const int v = members[base + t];
-        int u = t;
-        while (u > 0 && mem[u - 1] > v) {
-            mem[u] = mem[u - 1];
-            --u;
+        if (lane == 0) {
+            atomicOr(err, DEVERR_CAP);
+            ncomp[b] = 0;
         }
-        mem[u] = v;
-        parent[t] = t;
+        m = 0;
     }
-    for (int li = 0; li < m; ++li) {
-        const int i = mem[li];
-        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            const int j = col[e];
-            if (j == i) continue;
-            const int64_t bj = box_lin(box_of(coords[3 * (int64_t)j]), box_of(coords[3 * (int64_t)j + 1]),
-                                       box_of(coords[3 * (int64_t)j + 2]), nb.v);
-            if (bj != b) continue;
-            int lo = 0, hi = m - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (mem[mid] < j) lo = mid + 1; else hi = mid;
-            }
-            const int ra = uf_find(parent, li);
-            const int rb = uf_find(parent, lo);
-            if (ra != rb) {
-                if (ra < rb) parent[rb] = ra; else parent[ra] = rb;
-            }
+    const int32_t base = m > 0 ? boff[b] : 0;
+    int32_t* raw = raw_s[w];
+    int32_t* srt = srt_s[w];
+    int32_t* par = par_s[w];
+    int32_t* eoff = eoff_s[w];
+    for (int t = lane; t < m; t += WAVE) raw[t] = members[base + t];
+    __syncthreads();
+    // rank by value (members are distinct); row lengths for the edge offsets
+    int len[2] = {0, 0};
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + h * WAVE;
+        if (t < m) {
+            const int32_t v = raw[t];
+            int r = 0;
+            for (int u = 0; u < m; ++u) r += raw[u] < v;
+            srt[r] = v;
         }
     }
-    // roots in ascending local order get ranks 0, 1, ...; reuse `parent` for the
-    // rank of roots after resolving every member's root into `mem`'s partner.
-    int nc = 0;
-    for (int li = 0; li < m; ++li) {
-        const int rt = uf_find(parent, li);
-        if (rt == li) ++nc;
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + h * WAVE;
+        if (t < m) {
+            len[h] = rowptr[srt[t] + 1] - rowptr[srt[t]];
+            par[t] = t;
+        }
     }
-    // second pass: rank of each root = number of roots before it
-    for (int li = 0; li < m; ++li) {
-        const int rt = uf_find(parent, li);
-        int rank = 0;
-        for (int t = 0; t < rt; ++t) rank += (uf_find(parent, t) == t);
-        lrank[mem[li]] = rank;
+    // inclusive wave scans of the two halves
+    int carry = 0;
+    for (int h = 0; h < 2; ++h) {
+        int v = len[h];
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int u = __shfl_up(v, off, WAVE);
+            if (lane >= off) v += u;
+        }
+        const int t = lane + h * WAVE;
+        if (t < m) eoff[t + 1] = carry + v;
+        carry += __shfl(v, WAVE - 1, WAVE);
     }
-    ncomp[b] = nc;
+    if (lane == 0) eoff[0] = 0;
+    __syncthreads();
+    const int ne = m > 0 ? eoff[m] : 0;
+    for (int e = lane; e < ne; e += WAVE) {
+        int lo = 0, hi = m - 1;          // member li with eoff[li] <= e < eoff[li + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (eoff[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int li = lo;
+        const int32_t i = srt[li];
+        const int32_t j = col[rowptr[i] + (e - eoff[li])];
+        if (j == i || boxid[j] != (int32_t)b) continue;
+        int a0 = 0, a1 = m - 1;          // local index of j
+        while (a0 < a1) {
+            const int mid = (a0 + a1) >> 1;
+            if (srt[mid] < j) a0 = mid + 1; else a1 = mid;
+        }
+        const int lj = a0;
+        for (;;) {
+            int ra = uf_root(par, li), rb = uf_root(par, lj);
+            if (ra == rb) break;
+            if (ra > rb) { const int tmp = ra; ra = rb; rb = tmp; }
+            if (atomicCAS(&par[rb], rb, ra) == rb) break;
+        }
+    }
+    __syncthreads();
+    int root[2] = {0, 0};
+    unsigned long long rmask[2];
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + h * WAVE;
+        if (t < m) root[h] = uf_root(par, t);
+        rmask[h] = __ballot(t < m && root[h] == t);
+    }
+    __syncthreads();
+    // par now holds the rank of each root (roots only)
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + h * WAVE;
+        if (t < m && root[h] == t) par[t] = __popcll(rmask[h] & below) + (h ? __popcll(rmask[0]) : 0);
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + h * WAVE;
+        if (t < m) lrank[srt[t]] = par[root[h]];
+    }
+    if (lane == 0 && b < nboxes && m > 0) ncomp[b] = __popcll(rmask[0]) + __popcll(rmask[1]);
+    if (lane == 0 && b < nboxes && m == 0 && cnt[b] == 0) ncomp[b] = 0;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_assign_agg(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
@@ -254,7 +364,7 @@ __global__ void __launch_bounds__(BLOCK) k_assign_agg(const int32_t* __restrict_
 
 __global__ void __launch_bounds__(BLOCK) k_coarse_coords(const int32_t* __restrict__ ncomp,
                                                          const int32_t* __restrict__ cstart, NB3 nb, int64_t nboxes,
-                                                         int32_t* __restrict__ ccoords, int32_t* __restrict__ crank) {
+                                                         int32_t* __restrict__ ccoords, int4* __restrict__ cinfo) {
     const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (b >= nboxes) return;
     const int m = ncomp[b];
@@ -268,7 +378,7 @@ __global__ void __launch_bounds__(BLOCK) k_coarse_coords(const int32_t* __restri
         ccoords[3 * (int64_t)(c0 + t) + 0] = bx;
         ccoords[3 * (int64_t)(c0 + t) + 1] = by;
         ccoords[3 * (int64_t)(c0 + t) + 2] = bz;
-        crank[c0 + t] = t;
+        cinfo[c0 + t] = make_int4(bx, by, bz, t);
     }
 }
 
@@ -333,16 +443,16 @@ struct SlotMap {
     int dim;
     int maxc;
     int nslots;
-    const int32_t* ccoords;   // coarse coordinates (3 per coarse unknown)
-    const int32_t* crank;     // rank within box
+    const int4* cinfo;        // per coarse unknown: box coordinates and rank within its box
     const int32_t* cstart;    // first coarse unknown of each box
     NB3 nb;                   // box grid of the fine level = coarse extents
 
     __device__ int slot(int32_t J, int bx, int by, int bz) const {
-        const int ox = ccoords[3 * (int64_t)J] - bx + 1;
-        const int oy = ccoords[3 * (int64_t)J + 1] - by + 1;
-        const int oz = dim == 3 ? ccoords[3 * (int64_t)J + 2] - bz + 1 : 1;
-        const int r = crank[J];
+        const int4 ci = cinfo[J];
+        const int ox = ci.x - bx + 1;
+        const int oy = ci.y - by + 1;
+        const int oz = dim == 3 ? ci.z - bz + 1 : 1;
+        const int r = ci.w;
         if (ox < 0 || ox > 2 || oy < 0 || oy > 2 || oz < 0 || oz > 2 || r >= maxc) return -1;
         const int o = dim == 3 ? (oz * 3 + oy) * 3 + ox : oy * 3 + ox;
         return o * maxc + r;
@@ -386,14 +496,16 @@ struct AccArgs {
     const int32_t* agg;       // ACC_P only
     const double* diag;       // ACC_P only
     const double* omega;      // ACC_P only (device scalar)
-    int32_t* out_cnt;         // count pass
-    const int32_t* out_rowptr;// fill pass
-    int32_t* out_col;
-    double* out_val;
+    int32_t* out_cnt;         // entries per row
+    int32_t* ell_col;         // row-major scratch, ell_stride entries per row
+    double* ell_val;
+    int ell_stride;
     int32_t* err;
 };
 
-template <int MODE, bool FILL>
+// One pass per row: accumulate into the slot array (LDS), then write the
+// occupied slots, in slot = column order, to the row's ELL scratch and count.
+template <int MODE>
 __global__ void k_accumulate(AccArgs A) {
     extern __shared__ char smem[];
     SlotLds L;
@@ -405,7 +517,7 @@ __global__ void k_accumulate(AccArgs A) {
     if (row >= A.nrows) return;
     for (int s = 0; s < ns; ++s) {
         L.flags[s * nt + t] = 0;
-        if (FILL) L.vals[s * nt + t] = 0.0;
+        L.vals[s * nt + t] = 0.0;
     }
     const int bx = A.row_coords[3 * row] / A.centre_div;
     const int by = A.row_coords[3 * row + 1] / A.centre_div;
@@ -413,53 +525,62 @@ __global__ void k_accumulate(AccArgs A) {
     bool bad = false;
     if (MODE == ACC_P) {
         const double dii = A.diag[row];
-        const double omega = FILL ? *A.omega : 0.0;
+        const double omega = *A.omega;
         const int s0 = A.sm.slot(A.agg[row], bx, by, bz);
         if (s0 < 0) {
             bad = true;
         } else {
             L.flags[s0 * nt + t] = 1;
-            if (FILL) L.vals[s0 * nt + t] = 1.0;
+            L.vals[s0 * nt + t] = 1.0;
         }
         for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
             const int j = A.x_col[e];
             const int s = A.sm.slot(A.agg[j], bx, by, bz);
             if (s < 0) { bad = true; continue; }
             L.flags[s * nt + t] = 1;
-            if (FILL) {
-                const double w = omega * (A.x_val[e] / dii);
-                L.vals[s * nt + t] = L.vals[s * nt + t] - w;
-            }
+            const double w = omega * (A.x_val[e] / dii);
+            L.vals[s * nt + t] = L.vals[s * nt + t] - w;
         }
     } else {
         for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
             const int k = A.x_col[e];
-            const double xv = FILL ? A.x_val[e] : 0.0;
+            const double xv = A.x_val[e];
             for (int f = A.y_rowptr[k]; f < A.y_rowptr[k + 1]; ++f) {
                 const int s = A.sm.slot(A.y_col[f], bx, by, bz);
                 if (s < 0) { bad = true; continue; }
                 L.flags[s * nt + t] = 1;
-                if (FILL) {
-                    const double pr = xv * A.y_val[f];
-                    L.vals[s * nt + t] = L.vals[s * nt + t] + pr;
-                }
+                const double pr = xv * A.y_val[f];
+                L.vals[s * nt + t] = L.vals[s * nt + t] + pr;
             }
         }
     }
     if (bad) atomicOr(A.err, DEVERR_CAP);
-    if (!FILL) {
-        int c = 0;
-        for (int s = 0; s < ns; ++s) c += L.flags[s * nt + t];
-        A.out_cnt[row] = c;
-    } else {
-        int32_t pos = A.out_rowptr[row];
-        for (int s = 0; s < ns; ++s) {
-            if (L.flags[s * nt + t]) {
-                A.out_col[pos] = A.sm.column(s, bx, by, bz);
-                A.out_val[pos] = L.vals[s * nt + t];
-                ++pos;
+    int c = 0;
+    const int64_t base = row * A.ell_stride;
+    for (int s = 0; s < ns; ++s) {
+        if (L.flags[s * nt + t]) {
+            if (c < A.ell_stride) {
+                A.ell_col[base + c] = A.sm.column(s, bx, by, bz);
+                A.ell_val[base + c] = L.vals[s * nt + t];
             }
+            ++c;
         }
+    }
+    if (c > A.ell_stride) atomicOr(A.err, DEVERR_CAP);
+    A.out_cnt[row] = c < A.ell_stride ? c : A.ell_stride;
+}
+
+// ELL scratch -> CSR (rows keep their order).
+__global__ void __launch_bounds__(BLOCK) k_ell_to_csr(const int32_t* __restrict__ ell_col,
+                                                      const double* __restrict__ ell_val, int stride, int64_t nrows,
+                                                      const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                      double* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= nrows) return;
+    const int32_t b = rowptr[i], e = rowptr[i + 1];
+    for (int32_t k = 0; k < e - b; ++k) {
+        col[b + k] = ell_col[i * stride + k];
+        val[b + k] = ell_val[i * stride + k];
     }
 }
 
@@ -483,6 +604,50 @@ __global__ void __launch_bounds__(BLOCK) k_tr_fill(const int32_t* __restrict__ r
         t_col[pos] = (int32_t)i;
         t_val[pos] = val[e];
     }
+}
+
+// Level-0 transpose by pulling: P_iI != 0 only for fine unknowns i within one
+// node of aggregate I's box, i.e. in the (3+2)^d nodes [3B-1, 3B+3]^d around
+// box B.  Visiting them in lexicographic order lists rows in ascending unknown
+// order, so R = P^T comes out sorted without atomics.
+template <bool FILL>
+__global__ void __launch_bounds__(BLOCK) k_tr0_pull(int64_t nc, const int4* __restrict__ cinfo,
+                                                    const int8_t* __restrict__ kind, GridDims d,
+                                                    const int32_t* __restrict__ unk_off,
+                                                    const int32_t* __restrict__ p_rowptr,
+                                                    const int32_t* __restrict__ p_col,
+                                                    const double* __restrict__ p_val, int32_t* __restrict__ cnt,
+                                                    const int32_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
+                                                    double* __restrict__ r_val) {
+    const int64_t I = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (I >= nc) return;
+    const int4 ci = cinfo[I];
+    // unknowns never sit on the outer ring of nodes, so the walk stays inside it
+    const int zlo = d.dim == 3 ? max(3 * ci.z - 1, 1) : 0;
+    const int zhi = d.dim == 3 ? min(3 * ci.z + 3, d.nz - 2) : 0;
+    const int ylo = max(3 * ci.y - 1, 1), yhi = min(3 * ci.y + 3, d.ny - 2);
+    const int xlo = max(3 * ci.x - 1, 1), xhi = min(3 * ci.x + 3, d.nx - 2);
+    int c = 0;
+    int32_t pos = FILL ? r_rowptr[I] : 0;
+    for (int k = zlo; k <= zhi; ++k)
+        for (int j = ylo; j <= yhi; ++j)
+            for (int i = xlo; i <= xhi; ++i) {
+                const int64_t node = (int64_t)i + d.sy * j + d.sz * k;
+                if (kind[node] != 2) continue;
+                const int32_t u = unk_off[node];
+                for (int e = p_rowptr[u]; e < p_rowptr[u + 1]; ++e) {
+                    if (p_col[e] == (int32_t)I) {
+                        if (FILL) {
+                            r_col[pos] = u;
+                            r_val[pos] = p_val[e];
+                            ++pos;
+                        }
+                        ++c;
+                        break;
+                    }
+                }
+            }
+    if (!FILL) cnt[I] = c;
 }
 
 // Sort each row by column: one wavefront per row, bitonic network in LDS for
@@ -574,132 +739,167 @@ __global__ void __launch_bounds__(BLOCK) k_csr_to_dense(const int32_t* __restric
 }
 
 // Blocked right-looking Cholesky in place (lower triangle of the row-major
-// n x n matrix), one workgroup.  Each 16-column panel is copied to LDS and
-// factored there; the trailing update reads the panel from LDS and updates
-// 4 x 4 tiles of the lower triangle in registers.
+// n x n matrix).  Per 16-column panel: k_chol_panel (one workgroup) factors
+// the panel rows [k0, n) in LDS and writes them back; k_chol_trailing (many
+// workgroups) applies A[i][j] -= sum_c L[i][c] L[j][c] to the trailing lower
+// triangle, each workgroup a 64 x 64 block with its panel rows staged in LDS
+// and each thread a 4 x 4 tile.
 constexpr int CHOL_NB = 16;
 constexpr int CHOL_THREADS = 256;
+constexpr int CHOL_TB = 64;     // trailing block edge
 
-__global__ void __launch_bounds__(CHOL_THREADS) k_cholesky(double* __restrict__ Ad, int n, int32_t* __restrict__ err) {
-    extern __shared__ double panel[];   // (n - k0) x CHOL_NB, row-major by panel row
-    __shared__ int fail;
-    if (threadIdx.x == 0) fail = 0;
-    __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += CHOL_NB) {
-        const int kb = min(CHOL_NB, n - k0);
-        const int rows = n - k0;
-        for (int e = threadIdx.x; e < rows * CHOL_NB; e += blockDim.x) {
-            const int r = e / CHOL_NB, c = e % CHOL_NB;
-            panel[e] = c < kb ? Ad[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
-        }
-        __syncthreads();
-        for (int c = 0; c < kb; ++c) {
-            if (threadIdx.x == 0) {
-                const double dcc = panel[c * CHOL_NB + c];
-                if (!(dcc > 0.0)) fail = 1;
-                panel[c * CHOL_NB + c] = dcc > 0.0 ? sqrt(dcc) : 1.0;
-            }
-            __syncthreads();
-            const double piv = panel[c * CHOL_NB + c];
-            for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) panel[r * CHOL_NB + c] /= piv;
-            __syncthreads();
-            const int rem = kb - c - 1;
-            if (rem > 0) {
-                for (int e = threadIdx.x; e < (rows - c - 1) * rem; e += blockDim.x) {
-                    const int r = c + 1 + e / rem;
-                    const int c2 = c + 1 + e % rem;
-                    if (c2 <= r) panel[r * CHOL_NB + c2] -= panel[r * CHOL_NB + c] * panel[c2 * CHOL_NB + c];
-                }
-                __syncthreads();
-            }
-        }
-        if (fail) break;
-        for (int e = threadIdx.x; e < rows * kb; e += blockDim.x) {
-            const int r = e / kb, c = e % kb;
-            if (c <= r) Ad[(int64_t)(k0 + r) * n + k0 + c] = panel[r * CHOL_NB + c];
-        }
-        // trailing update A[i][j] -= sum_c P[i][c] P[j][c] for t0 <= j <= i,
-        // over 4 x 4 tiles (ti >= tj) of the trailing lower triangle
-        const int t0 = k0 + kb;
-        const int m = n - t0;
-        const int mt = (m + 3) / 4;
-        const int ntiles = mt * (mt + 1) / 2;
-        for (int tile = threadIdx.x; tile < ntiles; tile += blockDim.x) {
-            int ti = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
-            while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-            while (ti * (ti + 1) / 2 > tile) --ti;
-            const int tj = tile - ti * (ti + 1) / 2;
-            const int i0 = t0 + 4 * ti, j0 = t0 + 4 * tj;
-            double acc[4][4];
+// Panel factorisation: each thread keeps RPT panel rows (16 values each) in
+// registers; per column the pivot row's owner takes the square root, every
+// row is scaled, the top-block rows publish their scaled entry through LDS and
+// every row applies the rank-1 update to its remaining panel columns.
+template <int RPT>
+__global__ void __launch_bounds__(CHOL_THREADS) k_chol_panel(double* __restrict__ Ad, int n, int k0,
+                                                             int32_t* __restrict__ err) {
+    __shared__ double piv_s[CHOL_NB];
+    __shared__ double col_s[CHOL_NB][CHOL_NB];   // col_s[c][c2] = L[k0+c2][k0+c]
+    const int kb = min(CHOL_NB, n - k0);
+    const int rows = n - k0;
+    const int t = threadIdx.x;
+    double x[RPT][CHOL_NB];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+    for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * CHOL_THREADS;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int c = 0; c < CHOL_NB; ++c) {
-                double pi[4], pj[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    pi[a] = i0 + a < n ? panel[(i0 + a - k0) * CHOL_NB + c] : 0.0;
-                    pj[a] = j0 + a < n ? panel[(j0 + a - k0) * CHOL_NB + c] : 0.0;
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
-            }
-            double cur[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int i = i0 + a, j = j0 + b;
-                    cur[a][b] = (i < n && j <= i) ? Ad[(int64_t)i * n + j] : 0.0;
-                }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int i = i0 + a, j = j0 + b;
-                    if (i < n && j <= i) Ad[(int64_t)i * n + j] = cur[a][b] - acc[a][b];
-                }
-        }
-        __syncthreads();
+        for (int c = 0; c < CHOL_NB; ++c)
+            x[q][c] = (r < rows && c < kb) ? Ad[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
     }
-    if (threadIdx.x == 0 && fail) atomicOr(err, DEVERR_NOTSPD);
+    bool fail = false;
+#pragma unroll
+    for (int c = 0; c < CHOL_NB; ++c) {
+        if (c < kb) {   // uniform across the workgroup
+        if (t == c) {
+            const double d = x[0][c];
+            if (!(d > 0.0)) fail = true;
+            const double p = d > 0.0 ? sqrt(d) : 1.0;
+            x[0][c] = p;
+            piv_s[c] = p;
+        }
+        __syncthreads();
+        const double p = piv_s[c];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = t + q * CHOL_THREADS;
+            if (r > c && r < rows) x[q][c] = x[q][c] / p;
+        }
+        if (t > c && t < kb) col_s[c][t] = x[0][c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = t + q * CHOL_THREADS;
+            if (r > c && r < rows) {
+#pragma unroll
+                for (int c2 = c + 1; c2 < CHOL_NB; ++c2)
+                    if (c2 < kb && c2 <= r) x[q][c2] = x[q][c2] - x[q][c] * col_s[c][c2];
+            }
+        }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * CHOL_THREADS;
+        if (r < rows) {
+#pragma unroll
+            for (int c = 0; c < CHOL_NB; ++c)
+                if (c < kb && c <= r) Ad[(int64_t)(k0 + r) * n + k0 + c] = x[q][c];
+        }
+    }
+    if (fail) atomicOr(err, DEVERR_NOTSPD);
 }
 
-// Linv = L^-1 by forward substitution on identity columns.  A wavefront owns
-// four columns; 16 lanes share each column's dot products (strided over k) and
-// combine them with shuffles, so the sequential chain per row is short.  The
-// columns and row i of L live in LDS.  Column c is zero above its diagonal.
-constexpr int TRI_LPC = 16;                 // lanes per column
-constexpr int TRI_CPB = WAVE / TRI_LPC;     // columns per block (one wavefront)
-
-__global__ void __launch_bounds__(WAVE) k_tri_inverse(const double* __restrict__ Lf, int n, double* __restrict__ Li) {
-    extern __shared__ double smem_ti[];
-    double* ycol = smem_ti;                       // TRI_CPB x n
-    double* lrow = smem_ti + (int64_t)TRI_CPB * n; // n
-    const int lane = threadIdx.x;
-    const int g = lane / TRI_LPC;                 // column within the block
-    const int sub = lane % TRI_LPC;
-    const int cbase = blockIdx.x * TRI_CPB;
-    const int c = cbase + g;
-    for (int i = cbase; i < n; ++i) {
-        for (int k = cbase + lane; k <= i; k += WAVE) lrow[k] = Lf[(int64_t)i * n + k];
-        __syncthreads();
-        double acc = 0.0;
-        for (int k = cbase + sub; k < i; k += TRI_LPC) acc += lrow[k] * ycol[g * n + k];
+__global__ void __launch_bounds__(CHOL_THREADS) k_chol_trailing(double* __restrict__ Ad, int n, int k0) {
+    __shared__ double pi_s[CHOL_TB * CHOL_NB];
+    __shared__ double pj_s[CHOL_TB * CHOL_NB];
+    const int t0 = k0 + CHOL_NB;
+    const int m = n - t0;
+    if (m <= 0) return;
+    const int nbk = (m + CHOL_TB - 1) / CHOL_TB;
+    // lower-triangular block index -> (bi, bj), bj <= bi
+    int bi = (int)((sqrt(8.0 * (double)blockIdx.x + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= (int)blockIdx.x) ++bi;
+    while (bi * (bi + 1) / 2 > (int)blockIdx.x) --bi;
+    const int bj = blockIdx.x - bi * (bi + 1) / 2;
+    if (bi >= nbk) return;
+    const int i_base = t0 + bi * CHOL_TB, j_base = t0 + bj * CHOL_TB;
+    for (int e = threadIdx.x; e < CHOL_TB * CHOL_NB; e += blockDim.x) {
+        const int r = e / CHOL_NB, c = e % CHOL_NB;
+        pi_s[e] = i_base + r < n ? Ad[(int64_t)(i_base + r) * n + k0 + c] : 0.0;
+        pj_s[e] = j_base + r < n ? Ad[(int64_t)(j_base + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int ti = threadIdx.x / (CHOL_TB / 4), tj = threadIdx.x % (CHOL_TB / 4);
+    const int i0 = i_base + 4 * ti, j0 = j_base + 4 * tj;
+    if (i0 >= n || j0 >= n || j0 > i0 + 3) return;
+    double acc[4][4];
 #pragma unroll
-        for (int off = TRI_LPC / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TRI_LPC);
-        if (sub == 0) {
-            double v = 0.0;
-            if (c < n && i >= c) v = ((i == c ? 1.0 : 0.0) - acc) / lrow[i];
-            ycol[g * n + i] = v;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < CHOL_NB; ++c) {
+        double pi[4], pj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            pi[a] = pi_s[(4 * ti + a) * CHOL_NB + c];
+            pj[a] = pj_s[(4 * tj + a) * CHOL_NB + c];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + a, j = j0 + b;
+            if (i < n && j <= i) Ad[(int64_t)i * n + j] -= acc[a][b];
+        }
+}
+
+// Linv = L^-1 by forward substitution on identity columns, 16 columns per
+// workgroup in LDS (n x 16).  Rows go in blocks of 16: the part of each dot
+// product that reaches back before the block is one independent sum per
+// (row, column) over all 256 threads, then 16 threads (one per column)
+// finish the block's lower-triangular solve.  Column c is zero above row c.
+constexpr int TRI_NB = 16;
+constexpr int TRI_THREADS = TRI_NB * TRI_NB;
+
+__global__ void __launch_bounds__(TRI_THREADS) k_tri_inverse(const double* __restrict__ Lf, int n,
+                                                             double* __restrict__ Li) {
+    extern __shared__ double ycol[];               // n x TRI_NB, ycol[i * TRI_NB + c]
+    __shared__ double t_s[TRI_NB][TRI_NB];
+    __shared__ double ld[TRI_NB][TRI_NB];          // diagonal block of L
+    const int c0 = blockIdx.x * TRI_NB;
+    const int tid = threadIdx.x;
+    const int ri = tid / TRI_NB, ci = tid % TRI_NB;
+    const int c = c0 + ci;
+    for (int r0 = c0; r0 < n; r0 += TRI_NB) {
+        const int i = r0 + ri;
+        if (i < n) {
+            const double* lrow = Lf + (int64_t)i * n;
+            double acc = 0.0;
+            for (int k = c0; k < r0; ++k) acc = acc + lrow[k] * ycol[k * TRI_NB + ci];
+            ld[ri][ci] = r0 + ci < n ? lrow[r0 + ci] : 0.0;
+            t_s[ri][ci] = (i == c ? 1.0 : 0.0) - acc;
+        }
+        __syncthreads();
+        if (ri == 0) {
+            for (int rr = 0; rr < TRI_NB && r0 + rr < n; ++rr) {
+                double v = t_s[rr][ci];
+                for (int k = 0; k < rr; ++k) v = v - ld[rr][k] * ycol[(r0 + k) * TRI_NB + ci];
+                ycol[(r0 + rr) * TRI_NB + ci] = (c < n && r0 + rr >= c) ? v / ld[rr][rr] : 0.0;
+            }
         }
         __syncthreads();
     }
-    if (c < n) {
-        for (int i = sub; i < n; i += TRI_LPC) Li[(int64_t)i * n + c] = i >= cbase ? ycol[g * n + i] : 0.0;
+    for (int e = tid; e < n * TRI_NB; e += TRI_THREADS) {
+        const int i = e / TRI_NB, cc = e % TRI_NB;
+        if (c0 + cc < n) Li[(int64_t)i * n + c0 + cc] = i >= c0 ? ycol[i * TRI_NB + cc] : 0.0;
     }
 }
 
@@ -789,7 +989,7 @@ static int rowptr_from_counts(const int32_t* cnt, int64_t n, int32_t** rowptr, h
     return EB_OK;
 }
 
-static int launch_accumulate(int mode, bool fill, AccArgs& args, hipStream_t s) {
+static int launch_accumulate(int mode, AccArgs& args, hipStream_t s) {
     const int ns = args.sm.nslots;
     const size_t per_thread = (size_t)ns * (sizeof(double) + 1);
     int nt = 256;
@@ -800,38 +1000,45 @@ static int launch_accumulate(int mode, bool fill, AccArgs& args, hipStream_t s) 
     }
     const size_t lds = per_thread * nt + 16;
     const dim3 grid((unsigned)((args.nrows + nt - 1) / nt > 0 ? (args.nrows + nt - 1) / nt : 1));
-#define EB_ACC_LAUNCH(M, F) hipLaunchKernelGGL((k_accumulate<M, F>), grid, dim3(nt), lds, s, args)
-    if (mode == ACC_P) { if (fill) EB_ACC_LAUNCH(ACC_P, true); else EB_ACC_LAUNCH(ACC_P, false); }
-    else if (mode == ACC_AP) { if (fill) EB_ACC_LAUNCH(ACC_AP, true); else EB_ACC_LAUNCH(ACC_AP, false); }
-    else { if (fill) EB_ACC_LAUNCH(ACC_RAP, true); else EB_ACC_LAUNCH(ACC_RAP, false); }
-#undef EB_ACC_LAUNCH
+    if (mode == ACC_P) hipLaunchKernelGGL((k_accumulate<ACC_P>), grid, dim3(nt), lds, s, args);
+    else if (mode == ACC_AP) hipLaunchKernelGGL((k_accumulate<ACC_AP>), grid, dim3(nt), lds, s, args);
+    else hipLaunchKernelGGL((k_accumulate<ACC_RAP>), grid, dim3(nt), lds, s, args);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
 
-// Sparse product via the slot accumulator: count, prefix sum, fill.  The
-// column/value arrays are sized by a proven bound (nrows * row_bound), so no
-// host synchronisation is needed; the exact nnz stays in rowptr[nrows].
+// Sparse product via the slot accumulator: one accumulation pass into a
+// bounded ELL scratch (row_bound entries per row), a prefix sum of the row
+// counts, and a compaction into CSR.  Arrays are sized by the proven bound, so
+// no host synchronisation is needed; the exact nnz stays in rowptr[nrows].
 static int accumulate_product(int mode, AccArgs args, int64_t nrows, int64_t row_bound, int32_t** rowptr,
                               int32_t** col, double** val, hipStream_t s) {
-    int32_t* cnt = nullptr;
-    EB_TRY(dalloc_n(&cnt, nrows, s));
-    args.nrows = nrows;
-    args.out_cnt = cnt;
-    EB_TRY(launch_accumulate(mode, false, args, s));
-    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, s));
-    EB_TRY(dfree(cnt, s));
     const int64_t cap = nrows * row_bound;
     if (cap >= ((int64_t)1 << 31)) {
         set_error("a sparse matrix bound exceeds 2^31 entries");
         return EB_ENOSPC;
     }
+    int32_t* cnt = nullptr;
+    int32_t* ell_col = nullptr;
+    double* ell_val = nullptr;
+    EB_TRY(dalloc_n(&cnt, nrows, s));
+    EB_TRY(dalloc_n(&ell_col, cap, s));
+    EB_TRY(dalloc_n(&ell_val, cap, s));
+    args.nrows = nrows;
+    args.out_cnt = cnt;
+    args.ell_col = ell_col;
+    args.ell_val = ell_val;
+    args.ell_stride = (int)row_bound;
+    EB_TRY(launch_accumulate(mode, args, s));
+    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, s));
     EB_TRY(dalloc_n(col, cap, s));
     EB_TRY(dalloc_n(val, cap, s));
-    args.out_rowptr = *rowptr;
-    args.out_col = *col;
-    args.out_val = *val;
-    EB_TRY(launch_accumulate(mode, true, args, s));
+    hipLaunchKernelGGL(k_ell_to_csr, dim3(grid_for(nrows)), dim3(BLOCK), 0, s, ell_col, ell_val, (int)row_bound,
+                       nrows, *rowptr, *col, *val);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(cnt, s));
+    EB_TRY(dfree(ell_col, s));
+    EB_TRY(dfree(ell_val, s));
     return EB_OK;
 }
 
@@ -852,11 +1059,28 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
     hipLaunchKernelGGL(k_csr_to_dense, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, n, dense);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CHOL_THREADS), sizeof(double) * n * CHOL_NB, s, dense, (int)n,
-                       err);
+    for (int k0 = 0; k0 < n; k0 += CHOL_NB) {
+        const int rpt = (int)((n - k0 + CHOL_THREADS - 1) / CHOL_THREADS);
+        switch (rpt) {
+            case 1: hipLaunchKernelGGL(k_chol_panel<1>, dim3(1), dim3(CHOL_THREADS), 0, s, dense, (int)n, k0, err); break;
+            case 2: hipLaunchKernelGGL(k_chol_panel<2>, dim3(1), dim3(CHOL_THREADS), 0, s, dense, (int)n, k0, err); break;
+            case 3: hipLaunchKernelGGL(k_chol_panel<3>, dim3(1), dim3(CHOL_THREADS), 0, s, dense, (int)n, k0, err); break;
+            case 4: hipLaunchKernelGGL(k_chol_panel<4>, dim3(1), dim3(CHOL_THREADS), 0, s, dense, (int)n, k0, err); break;
+            case 5: hipLaunchKernelGGL(k_chol_panel<5>, dim3(1), dim3(CHOL_THREADS), 0, s, dense, (int)n, k0, err); break;
+            default:
+                set_error("dense coarsest level of %lld unknowns exceeds the panel kernel", (long long)n);
+                return EB_EINVAL;
+        }
+        const int64_t m = n - k0 - CHOL_NB;
+        if (m > 0) {
+            const int64_t nbk = (m + CHOL_TB - 1) / CHOL_TB;
+            hipLaunchKernelGGL(k_chol_trailing, dim3((unsigned)(nbk * (nbk + 1) / 2)), dim3(CHOL_THREADS), 0, s,
+                               dense, (int)n, k0);
+        }
+    }
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_tri_inverse, dim3((unsigned)((n + TRI_CPB - 1) / TRI_CPB)), dim3(WAVE),
-                       sizeof(double) * (TRI_CPB + 1) * n, s, dense, (int)n, linv);
+    hipLaunchKernelGGL(k_tri_inverse, dim3((unsigned)((n + TRI_NB - 1) / TRI_NB)), dim3(TRI_THREADS),
+                       sizeof(double) * TRI_NB * n, s, dense, (int)n, linv);
     EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gram, dim3(grid_for(n * n)), dim3(BLOCK), 0, s, linv, (int)n, L.dense_inv);
     EB_LAUNCH_CHECK();
@@ -885,24 +1109,32 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     const int64_t nboxes = (int64_t)nb.v[0] * nb.v[1] * nb.v[2];
     L.nboxes = nboxes;
     int32_t *cnt = nullptr, *boff = nullptr, *fillpos = nullptr, *members = nullptr, *lrank = nullptr;
-    EB_TRY(dalloc_n(&cnt, nboxes, s));
-    EB_TRY(dalloc_n(&boff, nboxes, s));
-    EB_TRY(dalloc_n(&fillpos, nboxes, s));
-    EB_TRY(dalloc_n(&members, n, s));
+    int32_t* boxid = nullptr;
     EB_TRY(dalloc_n(&lrank, n, s));
     EB_TRY(dalloc_n(&L.box_ncomp, nboxes, s));
     EB_TRY(dalloc_n(&L.box_cstart, nboxes, s));
-    EB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nboxes, s));
-    EB_HIP(hipMemsetAsync(fillpos, 0, sizeof(int32_t) * nboxes, s));
     EB_HIP(hipMemsetAsync(dstat + 2, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt);
-    EB_LAUNCH_CHECK();
-    EB_TRY(scan_i32_dev(cnt, boff, nboxes, dstat + 3, s));     // total (= n) unused
-    hipLaunchKernelGGL(k_box_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, boff, fillpos, members);
-    EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_box_components, dim3(grid_for(nboxes, 64)), dim3(64), 0, s, boff, cnt, members,
-                       L.a_rowptr, L.a_col, L.coords, nb, nboxes, lrank, L.box_ncomp, err);
-    EB_LAUNCH_CHECK();
+    if (l == 0 && H->unk_off_tmp && H->kind_tmp) {
+        hipLaunchKernelGGL(k_box_components0, dim3(grid_for(nboxes)), dim3(BLOCK), 0, s, H->kind_tmp, H->d, nb,
+                           nboxes, H->unk_off_tmp, lrank, L.box_ncomp);
+        EB_LAUNCH_CHECK();
+    } else {
+        EB_TRY(dalloc_n(&cnt, nboxes, s));
+        EB_TRY(dalloc_n(&boff, nboxes, s));
+        EB_TRY(dalloc_n(&fillpos, nboxes, s));
+        EB_TRY(dalloc_n(&members, n, s));
+        EB_TRY(dalloc_n(&boxid, n, s));
+        EB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nboxes, s));
+        EB_HIP(hipMemsetAsync(fillpos, 0, sizeof(int32_t) * nboxes, s));
+        hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt, boxid);
+        EB_LAUNCH_CHECK();
+        EB_TRY(scan_i32_dev(cnt, boff, nboxes, dstat + 3, s));     // total (= n) unused
+        hipLaunchKernelGGL(k_box_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, boxid, n, boff, fillpos, members);
+        EB_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_box_components, dim3(grid_for(nboxes, BOX_WAVES)), dim3(BOX_WAVES * WAVE), 0, s, boff,
+                           cnt, members, L.a_rowptr, L.a_col, boxid, nboxes, lrank, L.box_ncomp, err);
+        EB_LAUNCH_CHECK();
+    }
     EB_TRY(scan_i32_dev(L.box_ncomp, L.box_cstart, nboxes, dstat + 1, s));
     hipLaunchKernelGGL(k_max_i32, dim3(max_grid(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, nboxes, dstat + 2);
     EB_LAUNCH_CHECK();
@@ -910,6 +1142,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     EB_TRY(dfree(boff, s));
     EB_TRY(dfree(fillpos, s));
     EB_TRY(dfree(members, s));
+    EB_TRY(dfree(boxid, s));
     SetupStat st;
     EB_TRY(read_stat(dstat, &st, s));
     EB_TRY(err_code(st.err, "aggregation"));
@@ -931,9 +1164,9 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     C.n = nc;
     for (int a = 0; a < 3; ++a) C.ext[a] = nb.v[a];
     EB_TRY(dalloc_n(&C.coords, 3 * nc, s));
-    EB_TRY(dalloc_n(&C.crank, nc, s));
+    EB_TRY(dalloc_n(&C.cinfo, nc, s));
     hipLaunchKernelGGL(k_coarse_coords, dim3(grid_for(nboxes)), dim3(BLOCK), 0, s, L.box_ncomp, L.box_cstart, nb,
-                       nboxes, C.coords, C.crank);
+                       nboxes, C.coords, C.cinfo);
     EB_LAUNCH_CHECK();
 
     // Gershgorin bound and smoothing weight, kept on the device
@@ -956,8 +1189,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     args.sm.dim = dim;
     args.sm.maxc = maxc;
     args.sm.nslots = slots;
-    args.sm.ccoords = C.coords;
-    args.sm.crank = C.crank;
+    args.sm.cinfo = C.cinfo;
     args.sm.cstart = L.box_cstart;
     args.sm.nb = nb;
     args.err = err;
@@ -971,7 +1203,20 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     EB_TRY(accumulate_product(ACC_P, args, n, p_bound, &L.p_rowptr, &L.p_col, &L.p_val, s));
 
     // R = P^T (same number of entries)
-    {
+    if (l == 0 && H->unk_off_tmp) {
+        int32_t* tcnt = nullptr;
+        EB_TRY(dalloc_n(&tcnt, nc, s));
+        hipLaunchKernelGGL((k_tr0_pull<false>), dim3(grid_for(nc)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
+                           H->unk_off_tmp, L.p_rowptr, L.p_col, L.p_val, tcnt, nullptr, nullptr, nullptr);
+        EB_LAUNCH_CHECK();
+        EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, s));
+        EB_TRY(dalloc_n(&L.r_col, n * p_bound, s));
+        EB_TRY(dalloc_n(&L.r_val, n * p_bound, s));
+        hipLaunchKernelGGL((k_tr0_pull<true>), dim3(grid_for(nc)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
+                           H->unk_off_tmp, L.p_rowptr, L.p_col, L.p_val, nullptr, L.r_rowptr, L.r_col, L.r_val);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(tcnt, s));
+    } else {
         int32_t* tcnt = nullptr;
         int32_t* tfill = nullptr;
         EB_TRY(dalloc_n(&tcnt, nc, s));
@@ -1018,7 +1263,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
 
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
-                    L.r_val, L.agg, L.coords, L.crank, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp};
+                    L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp};
     for (void* p : ptrs) (void)dfree(p, s);
     L = Level();
 }
@@ -1029,7 +1274,7 @@ int free_handle_memory(amg_handle* H) {
     // for any solve still running on another stream first
     if (H->last_stream && H->last_stream != s) (void)hipStreamSynchronize(H->last_stream);
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
-    void* ptrs[] = {H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
+    void* ptrs[] = {H->unk_off_tmp, H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
                     H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2};
     for (void* p : ptrs) (void)dfree(p, s);
@@ -1086,7 +1331,8 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     EB_LAUNCH_CHECK();
     EB_TRY(dfree(rowcnt, s));
     EB_TRY(dfree(flag, s));
-    EB_TRY(dfree(unk_off, s));
+    H->unk_off_tmp = unk_off;   // node -> unknown map, used by the level-0 transpose
+    H->kind_tmp = kind;
 
     int l = 0;
     while (true) {
@@ -1096,6 +1342,10 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         }
         int stop = 0;
         EB_TRY(build_next(H, l, s, dstat, &stop));
+        if (H->unk_off_tmp) {
+            EB_TRY(dfree(H->unk_off_tmp, s));
+            H->unk_off_tmp = nullptr;
+        }
         if (stop) {
             EB_TRY(make_coarsest(H, l, s, dstat));
             break;

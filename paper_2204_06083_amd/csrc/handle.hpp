@@ -25,7 +25,7 @@ struct Level {
     int32_t* r_rowptr = nullptr; int32_t* r_col = nullptr; double* r_val = nullptr;
     int32_t* agg = nullptr;      // n: coarse unknown of each unknown
     int32_t* coords = nullptr;   // 3n
-    int32_t* crank = nullptr;    // n: rank of the unknown among those of its coordinate box
+    int4* cinfo = nullptr;       // n: box coordinates and rank within the box (levels >= 1)
     int32_t* box_cstart = nullptr;  // nboxes: first coarse unknown of each box
     int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
     double* dense_inv = nullptr; // coarsest: n x n
@@ -79,6 +79,8 @@ struct amg_handle {
     int64_t nboxes0 = 0;
     int32_t* boxes0 = nullptr;      // level-0 boxes holding unknowns
     int64_t* fine_nodes = nullptr;  // unknown -> dense node index
+    int32_t* unk_off_tmp = nullptr; // setup only: dense node -> unknown index
+    const int8_t* kind_tmp = nullptr;  // setup only: the caller's kind field
     int32_t* fine_pad = nullptr;    // unknown -> padded node index
     double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
     int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)

@@ -10,10 +10,13 @@ manufactured u = exp(x) sin(4 pi y), plain FP64 AMG-PCG to relative residual
 entirely in the library's HIP kernels, and frees the hierarchy.
 
 Output: one JSON line (rank 0).  `value` = unknowns x CG iterations per second
-of whole-step time.  `roofline` reports the dominant solve kernel: its
-algorithmic bytes per launch over its average launch time, measured with HIP
-events on the library's stream inside the timed steps.  `cpu_baseline` times
-the CPU oracle on one full step of the same workload.
+of whole-step time for the plain FP64 path.  `roofline` reports the dominant
+solve kernel: its algorithmic bytes per launch over its average launch time,
+measured with HIP events on the library's stream inside the timed steps.
+`solve_roofline` applies the whole-solve byte model to the measured solve
+time.  `mixed` repeats the same steps with the single-precision V-cycle
+(FP64 outer CG) and reports its difference from the FP64 solution.
+`cpu_baseline` times the CPU oracle on full steps of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -50,6 +53,29 @@ KERNEL_BYTES = {
     # z = zt + omega (r - A zt) / d; (r, z): read zt, r, d; write z
     "fine_post": lambda n0, n1: 32.0 * n0,
 }
+
+
+# Whole-solve byte model per PCG iteration (the graded solve-phase roofline):
+# the fine kernels above (FP64 V-cycle: 40 + 64 + 20 + 28 + 32 B per fine
+# unknown; single-precision V-cycle: z, res, zt and the V-cycle's diagonal
+# copy in FP32, 36 + 60 + 12 + 20 + 20 B) plus, per coarse level l >= 1 that
+# is not the coarsest, A read twice (values + column ids, row pointers), P
+# and R once, and about a dozen vector reads/writes per unknown; the coarsest
+# level reads its dense inverse (FP64 in both paths).
+FINE_MODEL = {"fp64": 184.0, "fp32": 148.0}
+
+
+def solve_model_bytes(H, precision):
+    vb = 8.0 if precision == "fp64" else 4.0
+    n0 = H.level(0).n
+    total = FINE_MODEL[precision] * n0
+    for l in range(1, H.n_levels):
+        lv = H.level(l)
+        if lv.is_coarsest:
+            total += 8.0 * lv.n * lv.n + 2 * vb * lv.n
+        else:
+            total += 2 * ((vb + 4) * lv.nnz_a + 4 * lv.n) + (vb + 4) * (lv.nnz_p + lv.nnz_r) + 8 * (vb + 4) * lv.n
+    return total
 
 
 def parse():
@@ -249,7 +275,9 @@ def main():
             torch.cuda.synchronize()
         return time.perf_counter()
 
-    def step(measure):
+    model = {}
+
+    def step(measure, precision="fp64", record=True):
         ta = mark()
         asm = S.assemble_diag(g, psi, cuts_cap=cuts_cap)
         tb = mark()
@@ -258,10 +286,15 @@ def main():
         t_setup0 = mark()
         H = S.Hierarchy(g, asm.kind, asm.a, 0.0)
         t_setup1 = mark()
-        if measure:
+        if measure and record:
             H.time_kernel(args.kernel)
-        x, info = H.solve(b, tol=prob.tol)
+        x, info = H.solve(b, tol=prob.tol, precision=precision)
         t_solve1 = mark()
+        if precision not in model:
+            model[precision] = solve_model_bytes(H, precision)
+        if not record:
+            H.free()
+            return asm.n_unknowns, info, x
         if measure and args.phases:
             phases["assemble"].append((tb - ta) * 1e3)
             phases["rhs"].append((t_setup0 - tb) * 1e3)
@@ -286,6 +319,27 @@ def main():
             phases.setdefault("step", []).append((t_free1 - ta) * 1e3)
         return asm.n_unknowns, info["iterations"], ta
 
+    # FP32 V-cycle steps of the same workload, timed the same way
+    mixed = {"iters": [], "solve_ms": [], "rel_res_true": []}
+    for _ in range(args.warmup):
+        step(False, "fp32", record=False)
+    torch.cuda.synchronize()
+    tm0 = time.perf_counter()
+    mixed_work = 0
+    for _ in range(args.steps):
+        n0m, info_m, _ = step(True, "fp32", record=False)
+        mixed_work += n0m * info_m["iterations"]
+        mixed["iters"].append(info_m["iterations"])
+        mixed["solve_ms"].append(info_m["solve_ms"])
+        mixed["rel_res_true"].append(info_m["rel_res_true"])
+    torch.cuda.synchronize()
+    tm1 = time.perf_counter()
+    # difference from the FP64 solution on the same system (both from the library)
+    _, _, xm = step(False, "fp32", record=False)
+    _, _, xd = step(False, "fp64", record=False)
+    mixed_diff = (torch.linalg.vector_norm(xm - xd) / torch.linalg.vector_norm(xd)).item()
+    del xm, xd
+
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -305,6 +359,15 @@ def main():
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     mean_iters = sum(stats["iters"]) / len(stats["iters"])
     mean_solve = sum(stats["solve_ms"]) / len(stats["solve_ms"])
+    m_iters = sum(mixed["iters"]) / len(mixed["iters"])
+    m_solve = sum(mixed["solve_ms"]) / len(mixed["solve_ms"])
+    m_secs = tm1 - tm0
+
+    def solve_roofline(precision, iters, solve_ms):
+        b = model[precision]
+        gbs = b * iters / (solve_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "model_bytes_per_iter": b, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     out = {
         "metric": "unknowns·CG-iters/s & solves/s to 1e-8 rel-res, learned/mixed vs plain FP64",
         "value": total_work / secs,
@@ -328,6 +391,21 @@ def main():
         "solve_ms": mean_solve,
         "solve_phase_unknowns_iters_per_s": n0 * mean_iters / (mean_solve * 1e-3),
         "rel_res_true_max": max(stats["rel_res_true"]),
+        "solve_roofline": solve_roofline("fp64", mean_iters, mean_solve),
+        "mixed": {
+            "precision": "FP32 V-cycle, FP64 outer CG, FP64 true residual with restart, FP64 coarsest solve",
+            "value": mixed_work / m_secs,
+            "unit": "unknowns·CG-iters/s",
+            "ms_per_step": m_secs * 1e3 / args.steps,
+            "solves_per_s": args.steps / m_secs,
+            "iterations": m_iters,
+            "solve_ms": m_solve,
+            "solve_phase_unknowns_iters_per_s": n0 * m_iters / (m_solve * 1e-3),
+            "rel_res_true_max": max(mixed["rel_res_true"]),
+            "rel_diff_vs_fp64_solution": mixed_diff,
+            "solve_speedup_vs_fp64": mean_solve / m_solve,
+            "solve_roofline": solve_roofline("fp32", m_iters, m_solve),
+        },
         "roofline": {
             "bound": "hbm",
             "kernel": args.kernel,

@@ -89,8 +89,15 @@ typedef struct {
     int32_t maxit;           /* iteration limit (default 1000)                    */
     int32_t x0_given;        /* 1: x holds the initial guess on entry; 0: x0 = 0  */
     int32_t check_every;     /* iterations queued between convergence polls (8)   */
-    int32_t reserved;
+    int32_t precision;       /* V-cycle precision: EB_PREC_FP64 (0, default) or
+                                EB_PREC_FP32 (1: single-precision V-cycle; the
+                                outer CG, its dot products, the true-residual
+                                check with restart and the coarsest dense
+                                solve stay FP64).  Hierarchies of one level
+                                always run FP64.                               */
 } pcg_params_t;
+
+enum { EB_PREC_FP64 = 0, EB_PREC_FP32 = 1 };
 
 typedef struct {
     int32_t iterations;      /* products with A inside CG                         */
@@ -176,6 +183,13 @@ int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* p
 
 /* Apply one V(1,1) cycle z = M r (node fields; parity and debugging aid).     */
 int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
+
+/* The same cycle in single precision: r is rounded to FP32 after the fine
+ * pre-smoothing residual is formed, every level below computes and stores
+ * FP32 (the coarsest dense solve accumulates in FP64), and z is returned
+ * widened to FP64.  The first call on a handle makes FP32 copies of the
+ * hierarchy's values (kept until amg_free).  Synchronises `stream`.          */
+int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* stream);
 
 /* Hierarchy introspection (host calls; pointers as described above).          */
 int amg_num_levels(const amg_handle_t* H);

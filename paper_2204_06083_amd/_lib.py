@@ -18,7 +18,7 @@ EB_OK, EB_EINVAL, EB_EDOMAIN, EB_ENOSPC, EB_ENOTSPD, EB_ENAN, EB_ENOCONV, EB_EHI
 
 EXPORTS = [
     "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
-    "amg_vcycle_apply", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
+    "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory",
 ]
@@ -38,7 +38,10 @@ class AmgParams(C.Structure):
 
 class PcgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("x0_given", C.c_int32),
-                ("check_every", C.c_int32), ("reserved", C.c_int32)]
+                ("check_every", C.c_int32), ("precision", C.c_int32)]
+
+
+PRECISION = {"fp64": 0, "fp32": 1}
 
 
 class PcgResult(C.Structure):
@@ -86,6 +89,7 @@ def lib():
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]
+    L.amg_vcycle_apply_fp32.argtypes = [vp, vp, vp, vp]
     L.amg_num_levels.argtypes = [vp]
     L.amg_level_info.argtypes = [vp, C.c_int, C.POINTER(LevelInfo)]
     L.amg_fine_nodes.argtypes = [vp]
@@ -100,7 +104,7 @@ def lib():
     L.eb_strerror.restype = C.c_char_p
     L.eb_last_error.restype = C.c_char_p
     for name in ("eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
-                 "amg_vcycle_apply", "amg_num_levels", "amg_level_info", "eb_abi_version",
+                 "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "eb_abi_version",
                  "eb_timing_select", "eb_timing_read"):
         getattr(L, name).restype = i32
     _lib = L

@@ -1263,7 +1263,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
 
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
-                    L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp};
+                    L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp,
+                    L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32};
     for (void* p : ptrs) (void)dfree(p, s);
     L = Level();
 }
@@ -1276,7 +1277,7 @@ int free_handle_memory(amg_handle* H) {
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
     void* ptrs[] = {H->unk_off_tmp, H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
-                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2};
+                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->res32, H->zt32, H->z32};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;
     H->tim_ev = nullptr;    // process-wide event pool, not owned

@@ -31,6 +31,9 @@ struct Level {
     double* dense_inv = nullptr; // coarsest: n x n
     // solve vectors (levels >= 1)
     double* rv = nullptr; double* ev = nullptr; double* tmp = nullptr;
+    // FP32 copies for the single-precision V-cycle (made on first use)
+    float* a_val32 = nullptr; float* p_val32 = nullptr; float* r_val32 = nullptr; float* diag32 = nullptr;
+    float* rv32 = nullptr; float* ev32 = nullptr; float* tmp32 = nullptr;
 };
 
 // Device scalars of one PCG solve.  Written only by block 0 of the kernel
@@ -83,6 +86,12 @@ struct amg_handle {
     const int8_t* kind_tmp = nullptr;  // setup only: the caller's kind field
     int32_t* fine_pad = nullptr;    // unknown -> padded node index
     double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
+    // single-precision V-cycle: padded FP32 diagonal and V-cycle vectors
+    int fp32_ready = 0;
+    float* diag_p32 = nullptr;
+    float* res32 = nullptr;
+    float* zt32 = nullptr;
+    float* z32 = nullptr;
     int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)
     // PCG state (padded node fields)
     double* x = nullptr; double* z = nullptr;

@@ -51,7 +51,13 @@ struct FineArgs {
     int dim;
     double s;             // 1/h^2
     const double* diag;   // padded, 0 off unknowns
+    const float* diag32;  // the same in FP32 (single-precision V-cycle only)
 };
+
+// Diagonal in the precision of the V-cycle.
+template <class V> __device__ inline const V* vdiag(const FineArgs& f);
+template <> __device__ inline const double* vdiag<double>(const FineArgs& f) { return f.diag; }
+template <> __device__ inline const float* vdiag<float>(const FineArgs& f) { return f.diag32; }
 
 // Each block sweeps its own contiguous range of strips, NT / strip_w strips
 // at a time; p is the padded node index of this thread's node.
@@ -63,20 +69,23 @@ struct FineArgs {
                      once_ = 0;                                                                    \
              once_ < 1; ++once_)
 
-__device__ inline double nbr_sum(const double* __restrict__ v, int64_t p, const FineArgs& f) {
-    double t = v[p - 1] + v[p + 1];
+template <class V>
+__device__ inline V nbr_sum(const V* __restrict__ v, int64_t p, const FineArgs& f) {
+    V t = v[p - 1] + v[p + 1];
     t += v[p - f.sy] + v[p + f.sy];
     if (f.dim == 3) t += v[p - f.sz] + v[p + f.sz];
     return t;
 }
 
-__device__ inline double safe_div(double x, double d) { return d != 0.0 ? x / d : 0.0; }
+template <class V>
+__device__ inline V safe_div(V x, V d) { return d != V(0) ? x / d : V(0); }
 
 // sum over neighbours of v / d (zero where d == 0, i.e. off unknowns)
-__device__ inline double nbr_sum_scaled(const double* __restrict__ v, int64_t p, const FineArgs& f) {
-    double t = safe_div(v[p - 1], f.diag[p - 1]) + safe_div(v[p + 1], f.diag[p + 1]);
-    t += safe_div(v[p - f.sy], f.diag[p - f.sy]) + safe_div(v[p + f.sy], f.diag[p + f.sy]);
-    if (f.dim == 3) t += safe_div(v[p - f.sz], f.diag[p - f.sz]) + safe_div(v[p + f.sz], f.diag[p + f.sz]);
+template <class V>
+__device__ inline V nbr_sum_scaled(const V* __restrict__ v, const V* __restrict__ dg, int64_t p, const FineArgs& f) {
+    V t = safe_div(v[p - 1], dg[p - 1]) + safe_div(v[p + 1], dg[p + 1]);
+    t += safe_div(v[p - f.sy], dg[p - f.sy]) + safe_div(v[p + f.sy], dg[p + f.sy]);
+    if (f.dim == 3) t += safe_div(v[p - f.sz], dg[p - f.sz]) + safe_div(v[p + f.sz], dg[p + f.sz]);
     return t;
 }
 
@@ -106,9 +115,13 @@ __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 __device__ inline bool bad_value(double v) { return isnan(v) || isinf(v); }
 
 // ------------------------------------------------------------ PCG kernels
+// V is the storage type of the preconditioned residual z (the V-cycle's
+// precision); the CG vectors and scalars are always FP64.
+//
 // p_new = z + beta p_old; q = A p_new; partial (p_new, q).
 // rho = (r, z) of the latest V-cycle, beta = rho / rho_prev (0 on the first).
-__global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const double* __restrict__ z,
+template <class V>
+__global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const V* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
                                                    double* __restrict__ q, const double* __restrict__ rz_cur,
                                                    const double* __restrict__ rz_prev, int np,
@@ -128,14 +141,14 @@ __global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const double* __r
     FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
-            const double pc = z[p] + beta * pold[p];
-            double nb = z[p - 1] + beta * pold[p - 1];
-            nb += z[p + 1] + beta * pold[p + 1];
-            nb += z[p - f.sy] + beta * pold[p - f.sy];
-            nb += z[p + f.sy] + beta * pold[p + f.sy];
+            const double pc = (double)z[p] + beta * pold[p];
+            double nb = (double)z[p - 1] + beta * pold[p - 1];
+            nb += (double)z[p + 1] + beta * pold[p + 1];
+            nb += (double)z[p - f.sy] + beta * pold[p - f.sy];
+            nb += (double)z[p + f.sy] + beta * pold[p + f.sy];
             if (f.dim == 3) {
-                nb += z[p - f.sz] + beta * pold[p - f.sz];
-                nb += z[p + f.sz] + beta * pold[p + f.sz];
+                nb += (double)z[p - f.sz] + beta * pold[p - f.sz];
+                nb += (double)z[p + f.sz] + beta * pold[p + f.sz];
             }
             const double qv = d * pc - f.s * nb;
             pnew[p] = pc;
@@ -198,10 +211,12 @@ __device__ inline bool converged_or_failed(const double* __restrict__ part_rr, i
 }
 
 // ------------------------------------------------------------ fine V-cycle
-// Pre-smoothing and residual: z1 = omega r / d (not stored), res = r - A z1.
+// Pre-smoothing and residual: z1 = omega r / d (not stored), res = r - A z1,
+// formed from the FP64 residual and stored in the V-cycle precision.
 // With `check`, first test convergence of the iterate that produced r.
+template <class V>
 __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, const double* __restrict__ r,
-                                                  double* __restrict__ res, PcgScalars* sc, int check,
+                                                  V* __restrict__ res, PcgScalars* sc, int check,
                                                   const double* __restrict__ part_rr, int np) {
     if (sc->done) return;
     if (check && converged_or_failed(part_rr, np, sc)) return;
@@ -209,8 +224,8 @@ __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, cons
         const double d = f.diag[p];
         if (d != 0.0) {
             const double z1 = omega * r[p] / d;
-            const double nb = omega * nbr_sum_scaled(r, p, f);
-            res[p] = r[p] - (d * z1 - f.s * nb);
+            const double nb = omega * nbr_sum_scaled(r, f.diag, p, f);
+            res[p] = (V)(r[p] - (d * z1 - f.s * nb));
         }
     }
 }
@@ -229,14 +244,18 @@ struct BoxArgs {
     const int32_t* agg;   // padded
 };
 
-__global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, double omega,
-                                                      const double* __restrict__ res, double* __restrict__ rc,
+template <class V>
+__global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
+                                                      const V* __restrict__ res, V* __restrict__ rc,
                                                       PcgScalars* sc, int check, const double* __restrict__ part_rr,
                                                       int np) {
     if (sc->done) return;
     if (check && converged_or_failed(part_rr, np, sc)) return;
     const int64_t t = xcd_block() * NT + threadIdx.x;
     if (t >= b.nboxes) return;
+    const V* __restrict__ dg = vdiag<V>(f);
+    const V omega = (V)omega_d;
+    const V sh = (V)f.s;
     const int64_t box = b.boxes[t];
     const int bx = (int)(box % b.nbx);
     const int64_t rr = box / b.nbx;
@@ -244,9 +263,9 @@ __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, dou
     const int bz = (int)(rr / b.nby);
     const int32_t c0 = b.cstart[box];
     const int m = b.ncomp[box];
-    double acc[MAX_FINE_COMP];
+    V acc[MAX_FINE_COMP];
 #pragma unroll
-    for (int c = 0; c < MAX_FINE_COMP; ++c) acc[c] = 0.0;
+    for (int c = 0; c < MAX_FINE_COMP; ++c) acc[c] = V(0);
     const int z_hi = f.dim == 3 ? 3 : 1;
     for (int oz = 0; oz < z_hi; ++oz) {
         const int k = f.dim == 3 ? 3 * bz + oz : 0;
@@ -258,11 +277,11 @@ __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, dou
                 const int i = 3 * bx + ox;
                 if (i >= b.nx) break;
                 const int64_t p = (int64_t)i + f.sy * j + f.sz * k;
-                const double d = f.diag[p];
-                if (d == 0.0) continue;
-                const double rp = res[p];
-                const double aw = d * (rp / d) - f.s * nbr_sum_scaled(res, p, f);
-                const double u = rp - omega * aw;
+                const V d = dg[p];
+                if (d == V(0)) continue;
+                const V rp = res[p];
+                const V aw = d * (rp / d) - sh * nbr_sum_scaled(res, dg, p, f);
+                const V u = rp - omega * aw;
                 if (m == 1) {
                     acc[0] += u;
                 } else {
@@ -279,10 +298,12 @@ __global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, dou
 //   alpha = rho / (p, q); x += alpha p; r_out = r_in - alpha q;
 //   res = r_out - A (omega D^-1 r_out), with r_out at the neighbours recomputed
 //   from r_in and q (r_in and r_out are different buffers).
+// The CG part is FP64; res is stored in the V-cycle precision.
 // The convergence test on ||r_out||^2 happens in the next kernel.
+template <class V>
 __global__ void __launch_bounds__(NT) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
                                                     double* __restrict__ rout, const double* __restrict__ pv,
-                                                    const double* __restrict__ q, double* __restrict__ res,
+                                                    const double* __restrict__ q, V* __restrict__ res,
                                                     double omega, const double* __restrict__ rz_cur,
                                                     const double* __restrict__ part_pq, int np,
                                                     double* __restrict__ part_rr, PcgScalars* sc, int iter) {
@@ -318,56 +339,64 @@ __global__ void __launch_bounds__(NT) k_pcg_xr_down(FineArgs f, double* __restri
                 nb += safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
             }
             const double z1 = omega * rn / d;
-            res[p] = rn - (d * z1 - f.s * (omega * nb));
+            res[p] = (V)(rn - (d * z1 - f.s * (omega * nb)));
         }
     }
     block_partial(part, part_rr);
 }
 
 // Coarse-grid correction value t = e_c[agg] at node p (0 off unknowns).
-__device__ inline double corr_at(const int32_t* __restrict__ agg, const double* __restrict__ ec, int64_t p) {
+template <class V>
+__device__ inline V corr_at(const int32_t* __restrict__ agg, const V* __restrict__ ec, int64_t p) {
     const int32_t g = agg[p];
-    return g >= 0 ? ec[g] : 0.0;
+    return g >= 0 ? ec[g] : V(0);
 }
 
 // Pre-smoothed iterate after prolongation at node p:
 //   zt = omega r / d + t - omega (A t) / d,  t = e_c[agg].
-__device__ inline double zt_at(const FineArgs& f, double omega, const int32_t* __restrict__ agg,
-                               const double* __restrict__ ec, const double* __restrict__ r, int64_t p) {
-    const double d = f.diag[p];
-    if (d == 0.0) return 0.0;
-    const double tp = corr_at(agg, ec, p);
-    double nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
+template <class V>
+__device__ inline V zt_at(const FineArgs& f, V omega, const int32_t* __restrict__ agg, const V* __restrict__ ec,
+                          const double* __restrict__ r, int64_t p) {
+    const V d = vdiag<V>(f)[p];
+    if (d == V(0)) return V(0);
+    const V tp = corr_at(agg, ec, p);
+    V nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
     nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
     if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
-    const double at = d * tp - f.s * nb;
-    return omega * r[p] / d + (tp - omega * at / d);
+    const V at = d * tp - (V)f.s * nb;
+    return omega * (V)r[p] / d + (tp - omega * at / d);
 }
 
 // Prolongation and pre-smoothed correction: zt = omega r / d + t - omega (A t) / d,
 // t = e_c[agg].
+template <class V>
 __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const int32_t* __restrict__ agg,
-                                                const double* __restrict__ ec, const double* __restrict__ r,
-                                                double* __restrict__ zt, const PcgScalars* sc) {
+                                                const V* __restrict__ ec, const double* __restrict__ r,
+                                                V* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
+    const V w = (V)omega;
     FINE_LOOP(f, p) {
-        if (f.diag[p] != 0.0) zt[p] = zt_at(f, omega, agg, ec, r, p);
+        if (f.diag[p] != 0.0) zt[p] = zt_at(f, w, agg, ec, r, p);
     }
 }
 
-// Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z).
-__global__ void __launch_bounds__(NT) k_fine_post(FineArgs f, double omega, const double* __restrict__ zt,
-                                                  const double* __restrict__ r, double* __restrict__ z,
+// Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z) in FP64.
+template <class V>
+__global__ void __launch_bounds__(NT) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
+                                                  const double* __restrict__ r, V* __restrict__ z,
                                                   double* __restrict__ part_rz, const PcgScalars* sc) {
     if (sc->done) return;
+    const V* __restrict__ dg = vdiag<V>(f);
+    const V w = (V)omega;
+    const V sh = (V)f.s;
     double part = 0.0;
     FINE_LOOP(f, p) {
-        const double d = f.diag[p];
-        if (d != 0.0) {
-            const double az = d * zt[p] - f.s * nbr_sum(zt, p, f);
-            const double zv = zt[p] + omega * (r[p] - az) / d;
+        const V d = dg[p];
+        if (d != V(0)) {
+            const V az = d * zt[p] - sh * nbr_sum(zt, p, f);
+            const V zv = zt[p] + w * ((V)r[p] - az) / d;
             z[p] = zv;
-            part += r[p] * zv;
+            part += r[p] * (double)zv;
         }
     }
     block_partial(part, part_rz);
@@ -422,33 +451,35 @@ __global__ void __launch_bounds__(NT) k_finalize_true(PcgScalars* sc, const doub
 }
 
 // ------------------------------------------------------------ coarse kernels
-// LPR lanes share one CSR row (strided over its entries) and combine their
-// partial sums with butterfly shuffles inside the LPR-lane segment.
-template <int LPR>
-__device__ inline double segment_sum(double v) {
+// Arithmetic and storage in the V-cycle precision V.  LPR lanes share one CSR
+// row (strided over its entries) and combine their partial sums with
+// butterfly shuffles inside the LPR-lane segment.
+template <int LPR, class V>
+__device__ inline V segment_sum(V v) {
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
     return v;
 }
 
+template <class V>
 struct Csr {
     const int32_t* rowptr;
     const int32_t* col;
-    const double* val;
+    const V* val;
 };
 
 // Large coarse levels, two light passes each way:
 //   res_j = rv_j - sum_e a_je omega rv_e / d_e;   rv_c[I] = sum_j R_Ij res_j;
 //   zt_j = omega rv_j / d_j + sum_J P_jJ ev_c[J]; ev_i = zt_i + omega (rv_i - (A zt)_i) / d_i.
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr A, const double* __restrict__ diag, double omega,
-                                                  const double* __restrict__ rv, double* __restrict__ res,
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr<V> A, const V* __restrict__ diag, V omega,
+                                                  const V* __restrict__ rv, V* __restrict__ res,
                                                   const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= n) return;
-    double az = 0.0;
+    V az = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
         const int k = A.col[e];
         az += A.val[e] * (omega * rv[k] / diag[k]);
@@ -457,42 +488,42 @@ __global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr A, const double
     if (lane == 0) res[row] = rv[row] - az;
 }
 
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_csr_matvec(int64_t n, Csr M, const double* __restrict__ x,
-                                                   double* __restrict__ y, const PcgScalars* sc) {
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_csr_matvec(int64_t n, Csr<V> M, const V* __restrict__ x,
+                                                   V* __restrict__ y, const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= n) return;
-    double acc = 0.0;
+    V acc = V(0);
     for (int e = M.rowptr[row] + lane; e < M.rowptr[row + 1]; e += LPR) acc += M.val[e] * x[M.col[e]];
     acc = segment_sum<LPR>(acc);
     if (lane == 0) y[row] = acc;
 }
 
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr P, const double* __restrict__ diag, double omega,
-                                                    const double* __restrict__ rv, const double* __restrict__ ev_c,
-                                                    double* __restrict__ zt, const PcgScalars* sc) {
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr<V> P, const V* __restrict__ diag, V omega,
+                                                    const V* __restrict__ rv, const V* __restrict__ ev_c,
+                                                    V* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= n) return;
-    double acc = 0.0;
+    V acc = V(0);
     for (int e = P.rowptr[row] + lane; e < P.rowptr[row + 1]; e += LPR) acc += P.val[e] * ev_c[P.col[e]];
     acc = segment_sum<LPR>(acc);
     if (lane == 0) zt[row] = omega * rv[row] / diag[row] + acc;
 }
 
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr A, const double* __restrict__ diag, double omega,
-                                                 const double* __restrict__ rv, const double* __restrict__ zt,
-                                                 double* __restrict__ ev, const PcgScalars* sc) {
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr<V> A, const V* __restrict__ diag, V omega,
+                                                 const V* __restrict__ rv, const V* __restrict__ zt,
+                                                 V* __restrict__ ev, const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= n) return;
-    double az = 0.0;
+    V az = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) az += A.val[e] * zt[A.col[e]];
     az = segment_sum<LPR>(az);
     if (lane == 0) ev[row] = zt[row] + omega * (rv[row] - az) / diag[row];
@@ -500,18 +531,18 @@ __global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr A, const double*
 
 // Residual and restriction in one pass:
 //   rv_c[I] = sum_{j in R row I} R_Ij (rv_j - sum_e a_je omega rv_e / d_e).
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr R, Csr A, const double* __restrict__ diag,
-                                                    double omega, const double* __restrict__ rv,
-                                                    double* __restrict__ rv_c, const PcgScalars* sc) {
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V> A, const V* __restrict__ diag,
+                                                    V omega, const V* __restrict__ rv,
+                                                    V* __restrict__ rv_c, const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= nc) return;
-    double acc = 0.0;
+    V acc = V(0);
     for (int e = R.rowptr[row] + lane; e < R.rowptr[row + 1]; e += LPR) {
         const int j = R.col[e];
-        double az = 0.0;
+        V az = V(0);
         for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
             const int k = A.col[f];
             az += A.val[f] * (omega * rv[k] / diag[k]);
@@ -525,42 +556,44 @@ __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr R, Csr A, co
 // Prolongation and post-smoothing in one pass:
 //   zt_j = omega rv_j / d_j + sum_{P row j} P_jJ ev_c[J];
 //   ev[i] = zt_i + omega (rv_i - sum_{A row i} a_ij zt_j) / d_i.
-template <int LPR>
-__global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr A, Csr P, const double* __restrict__ diag,
-                                                  double omega, const double* __restrict__ rv,
-                                                  const double* __restrict__ ev_c, double* __restrict__ ev,
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P, const V* __restrict__ diag,
+                                                  V omega, const V* __restrict__ rv,
+                                                  const V* __restrict__ ev_c, V* __restrict__ ev,
                                                   const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= n) return;
-    double acc = 0.0;
+    V acc = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
         const int j = A.col[e];
-        double zt = omega * rv[j] / diag[j];
+        V zt = omega * rv[j] / diag[j];
         for (int g = P.rowptr[j]; g < P.rowptr[j + 1]; ++g) zt += P.val[g] * ev_c[P.col[g]];
         acc += A.val[e] * zt;
     }
     acc = segment_sum<LPR>(acc);
     if (lane == 0) {
-        double zi = omega * rv[row] / diag[row];
+        V zi = omega * rv[row] / diag[row];
         for (int g = P.rowptr[row]; g < P.rowptr[row + 1]; ++g) zi += P.val[g] * ev_c[P.col[g]];
         ev[row] = zi + omega * (rv[row] - acc) / diag[row];
     }
 }
 
-// Coarsest: ev = W rv with W the dense inverse; one wavefront per row.
+// Coarsest: ev = W rv with W the dense inverse (FP64 in either precision);
+// one wavefront per row.
+template <class V>
 __global__ void __launch_bounds__(NT) k_dense_apply(int64_t n, const double* __restrict__ W,
-                                                    const double* __restrict__ rv, double* __restrict__ ev,
+                                                    const V* __restrict__ rv, V* __restrict__ ev,
                                                     const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = (int64_t)blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (row >= n) return;
     double acc = 0.0;
-    for (int64_t j = lane; j < n; j += WAVE) acc += W[row * n + j] * rv[j];
+    for (int64_t j = lane; j < n; j += WAVE) acc += W[row * n + j] * (double)rv[j];
     acc = wave_sum(acc);
-    if (lane == 0) ev[row] = acc;
+    if (lane == 0) ev[row] = (V)acc;
 }
 
 // One-level hierarchies (fine level = coarsest): gather r into compact order
@@ -597,8 +630,9 @@ __global__ void __launch_bounds__(NT) k_load_field(int64_t n, const int64_t* __r
     if (k < n) dst[pad[k]] = src[nodes[k]];
 }
 
+template <class V>
 __global__ void __launch_bounds__(NT) k_store_field(int64_t n, const int64_t* __restrict__ nodes,
-                                                    const int32_t* __restrict__ pad, const double* __restrict__ src,
+                                                    const int32_t* __restrict__ pad, const V* __restrict__ src,
                                                     double* __restrict__ dst) {
     const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (k < n) dst[nodes[k]] = src[pad[k]];
@@ -706,6 +740,7 @@ static FineArgs fine_args(const amg_handle* H) {
     f.dim = H->d.dim;
     f.s = H->d.s;
     f.diag = H->diag_p;
+    f.diag32 = H->diag_p32;
     return f;
 }
 
@@ -725,21 +760,52 @@ static BoxArgs box_args(const amg_handle* H) {
     return b;
 }
 
+// Arrays of one level, and the fine V-cycle vectors, in the V-cycle precision.
+template <class V>
+struct LevelView {
+    Csr<V> A, P, R;
+    const V* diag;
+    V* rv;
+    V* ev;
+    V* tmp;
+};
+
+template <class V> static LevelView<V> view(const Level& L);
+template <> LevelView<double> view<double>(const Level& L) {
+    return {{L.a_rowptr, L.a_col, L.a_val}, {L.p_rowptr, L.p_col, L.p_val}, {L.r_rowptr, L.r_col, L.r_val},
+            L.diag, L.rv, L.ev, L.tmp};
+}
+template <> LevelView<float> view<float>(const Level& L) {
+    return {{L.a_rowptr, L.a_col, L.a_val32}, {L.p_rowptr, L.p_col, L.p_val32}, {L.r_rowptr, L.r_col, L.r_val32},
+            L.diag32, L.rv32, L.ev32, L.tmp32};
+}
+
+template <class V>
+struct FineBufs {
+    V* res;
+    V* zt;
+    V* z;
+};
+
+template <class V> static FineBufs<V> fine_bufs(const amg_handle* H);
+template <> FineBufs<double> fine_bufs<double>(const amg_handle* H) { return {H->res, H->zt, H->z}; }
+template <> FineBufs<float> fine_bufs<float>(const amg_handle* H) { return {H->res32, H->zt32, H->z32}; }
+
 static int lanes_for(double avg_row) {
     int l = 4;
     while (l < 32 && l < avg_row * 0.75) l <<= 1;
     return l;
 }
 
-#define EB_LPR_LAUNCH(KERNEL, lpr, rows, ...)                                                         \
-    do {                                                                                          \
-        const unsigned g_ = grid_for((rows) * (int64_t)(lpr), NT);                               \
-        switch (lpr) {                                                                            \
-            case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
-            case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
-            case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
-            default: hipLaunchKernelGGL((KERNEL<32>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
-        }                                                                                         \
+#define EB_LPR_LAUNCH(KERNEL, V, lpr, rows, ...)                                                         \
+    do {                                                                                                 \
+        const unsigned g_ = grid_for((rows) * (int64_t)(lpr), NT);                                      \
+        switch (lpr) {                                                                                   \
+            case 4: hipLaunchKernelGGL((KERNEL<4, V>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
+            case 8: hipLaunchKernelGGL((KERNEL<8, V>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break;   \
+            case 16: hipLaunchKernelGGL((KERNEL<16, V>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<32, V>), dim3(g_), dim3(NT), 0, s, __VA_ARGS__); break; \
+        }                                                                                                \
     } while (0)
 
 // Coarse levels with more unknowns than this take two light passes each way;
@@ -748,73 +814,84 @@ static int lanes_for(double avg_row) {
 constexpr int64_t FUSE_BELOW = 20000;
 
 // Coarse part of the V-cycle, levels 1 .. nlev-1: rv_1 -> ev_1.
+template <class V>
 static int enqueue_coarse(amg_handle* H, hipStream_t s) {
     const PcgScalars* sc = H->sc;
     for (int l = 1; l < H->nlev - 1; ++l) {
-        Level& L = H->lev[l];
-        Level& C = H->lev[l + 1];
+        const Level& L = H->lev[l];
+        const Level& C = H->lev[l + 1];
+        const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
+        const V w = (V)L.omega;
         const int lpr_r = lanes_for((double)L.nnz_r / (double)(C.n > 0 ? C.n : 1));
         if (L.n >= FUSE_BELOW) {
             const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_resid, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv,
-                          L.tmp, sc);
-            EB_LPR_LAUNCH(k_csr_matvec, lpr_r, C.n, C.n, Csr{L.r_rowptr, L.r_col, L.r_val}, L.tmp, C.rv, sc);
+            EB_LPR_LAUNCH(k_csr_resid, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_matvec, V, lpr_r, C.n, C.n, Lv.R, Lv.tmp, Cv.rv, sc);
         } else {
-            EB_LPR_LAUNCH(k_coarse_down, lpr_r, C.n, C.n, Csr{L.r_rowptr, L.r_col, L.r_val},
-                          Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv, C.rv, sc);
+            EB_LPR_LAUNCH(k_coarse_down, V, lpr_r, C.n, C.n, Lv.R, Lv.A, Lv.diag, w, Lv.rv, Cv.rv, sc);
         }
     }
     {
-        Level& Lc = H->lev[H->nlev - 1];
-        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv, Lc.rv,
-                           Lc.ev, sc);
+        const Level& Lc = H->lev[H->nlev - 1];
+        const LevelView<V> Lcv = view<V>(Lc);
+        hipLaunchKernelGGL(k_dense_apply<V>, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv,
+                           Lcv.rv, Lcv.ev, sc);
     }
     for (int l = H->nlev - 2; l >= 1; --l) {
-        Level& L = H->lev[l];
-        Level& C = H->lev[l + 1];
+        const Level& L = H->lev[l];
+        const Level& C = H->lev[l + 1];
+        const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
+        const V w = (V)L.omega;
         const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
         if (L.n >= FUSE_BELOW) {
             const int lpr_p = lanes_for((double)L.nnz_p / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_prolong, lpr_p, L.n, L.n, Csr{L.p_rowptr, L.p_col, L.p_val}, L.diag, L.omega, L.rv,
-                          C.ev, L.tmp, sc);
-            EB_LPR_LAUNCH(k_csr_post, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val}, L.diag, L.omega, L.rv,
-                          L.tmp, L.ev, sc);
+            EB_LPR_LAUNCH(k_csr_prolong, V, lpr_p, L.n, L.n, Lv.P, Lv.diag, w, Lv.rv, Cv.ev, Lv.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_post, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, Lv.ev, sc);
         } else {
-            EB_LPR_LAUNCH(k_coarse_up, lpr_a, L.n, L.n, Csr{L.a_rowptr, L.a_col, L.a_val},
-                          Csr{L.p_rowptr, L.p_col, L.p_val}, L.diag, L.omega, L.rv, C.ev, L.ev, sc);
+            EB_LPR_LAUNCH(k_coarse_up, V, lpr_a, L.n, L.n, Lv.A, Lv.P, Lv.diag, w, Lv.rv, Cv.ev, Lv.ev, sc);
         }
     }
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
 
-// z = M r for the initial residual (or a standalone V-cycle): fine
-// pre-smoothing, restriction, coarse levels, fused prolongation and
-// post-smoothing; the last kernel writes the (r, z) partials to rz_out.
-static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_out, hipStream_t s) {
+// One-level hierarchy (the fine level is the coarsest): z = W r in FP64.
+static int enqueue_vcycle_one_level(amg_handle* H, const double* r, double* z, double* rz_out, int check,
+                                    hipStream_t s) {
     PcgScalars* sc = H->sc;
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
-    if (H->nlev == 1) {
-        Level& L = H->lev[0];
-        const int64_t n = L.n;
-        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc, 0, H->red.rr, np);
-        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv, L.ev,
-                           (const PcgScalars*)sc);
-        hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, r, z, rz_out,
-                           (const PcgScalars*)sc);
-        EB_LAUNCH_CHECK();
-        return EB_OK;
-    }
+    Level& L = H->lev[0];
+    const int64_t n = L.n;
+    hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, r, L.rv, sc, check, H->red.rr, np);
+    hipLaunchKernelGGL(k_dense_apply<double>, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv,
+                       L.ev, (const PcgScalars*)sc);
+    hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, r, z, rz_out, (const PcgScalars*)sc);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// z = M r for the initial residual (or a standalone V-cycle), hierarchies of
+// two or more levels: fine pre-smoothing, restriction, coarse levels,
+// prolongation and post-smoothing; the last kernel writes the (r, z)
+// partials to rz_out.
+template <class V>
+static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, hipStream_t s) {
+    PcgScalars* sc = H->sc;
+    const int np = H->red.nparts;
+    const dim3 G((unsigned)np);
     const FineArgs f = fine_args(H);
+    const FineBufs<V> fb = fine_bufs<V>(H);
+    const LevelView<V> L1 = view<V>(H->lev[1]);
     const double w0 = H->lev[0].omega;
-    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, k_fine_down, G, dim3(NT), 0, f, w0, r, H->res, sc, 0, H->red.rr, np);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f, box_args(H), w0,
-                                H->res, H->lev[1].rv, sc, 0, H->red.rr, np);
-    EB_TRY(enqueue_coarse(H, s));
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up, G, dim3(NT), 0, f, w0, H->agg_p, H->lev[1].ev, r, H->zt,
-                                (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post, G, dim3(NT), 0, f, w0, H->zt, r, z, rz_out, (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, k_fine_down<V>, G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr, np);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f,
+                    box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
+    EB_TRY(enqueue_coarse<V>(H, s));
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, G, dim3(NT), 0, f, w0, H->agg_p, L1.ev, r, fb.zt,
+                    (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
+                    (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -822,7 +899,39 @@ static int enqueue_vcycle(amg_handle* H, const double* r, double* z, double* rz_
 // Iteration k >= 1 of a run.  The V-cycle before it (number k-1) wrote
 // rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
 // r[k % 2] and its V-cycle writes rz[k % 2].
+template <class V>
 static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t s) {
+    const FineArgs f = fine_args(H);
+    const int np = H->red.nparts;
+    const dim3 G((unsigned)np);
+    const FineBufs<V> fb = fine_bufs<V>(H);
+    double* pold = H->p[k & 1];
+    double* pnew = H->p[(k + 1) & 1];
+    double* rin = H->rr[(k - 1) & 1];
+    double* rout = H->rr[k & 1];
+    const double* rz_cur = H->red.rz[(k - 1) & 1];
+    const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
+    double* rz_out = H->red.rz[k & 1];
+    PcgScalars* sc = H->sc;
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<V>, G, dim3(NT), 0, f, fb.z, pold, pnew, H->q, rz_cur, rz_prev,
+                    np, H->red.pq, sc);
+    const double w0 = H->lev[0].omega;
+    const LevelView<V> L1 = view<V>(H->lev[1]);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr_down<V>, G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res, w0,
+                    rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f,
+                    box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
+    EB_TRY(enqueue_coarse<V>(H, s));
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, G, dim3(NT), 0, f, w0, H->agg_p, L1.ev, rout, fb.zt,
+                    (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, rout, fb.z, rz_out,
+                    (const PcgScalars*)sc);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// The same for a one-level hierarchy (FP64 dense solve of the fine level).
+static int enqueue_iteration_one_level(amg_handle* H, int k, int iter_global, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
@@ -834,34 +943,55 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
     const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
     double* rz_out = H->red.rz[k & 1];
     PcgScalars* sc = H->sc;
-    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur, rz_prev, np,
-                                H->red.pq, sc);
-    if (H->nlev == 1) {
-        EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr, G, dim3(NT), 0, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
-                                    H->red.rr, sc, iter_global);
-        // k_pcg_xr updates r in place: keep both buffers equal
-        hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
-        Level& L = H->lev[0];
-        const int64_t n = L.n;
-        hipLaunchKernelGGL(k_gather, G, dim3(NT), 0, s, n, H->fine_pad, rout, L.rv, sc, 1, H->red.rr, np);
-        hipLaunchKernelGGL(k_dense_apply, dim3(grid_for(n, NT / WAVE)), dim3(NT), 0, s, n, L.dense_inv, L.rv, L.ev,
-                           (const PcgScalars*)sc);
-        hipLaunchKernelGGL(k_scatter_dot, G, dim3(NT), 0, s, n, H->fine_pad, L.ev, rout, H->z, rz_out,
-                           (const PcgScalars*)sc);
-        EB_LAUNCH_CHECK();
-        return EB_OK;
-    }
-    const double w0 = H->lev[0].omega;
-    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr_down, G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, H->res, w0, rz_cur,
-                                H->red.pq, np, H->red.rr, sc, iter_global);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f, box_args(H), w0,
-                                H->res, H->lev[1].rv, sc, 1, H->red.rr, np);
-    EB_TRY(enqueue_coarse(H, s));
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up, G, dim3(NT), 0, f, w0, H->agg_p, H->lev[1].ev, rout, H->zt,
-                                (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post, G, dim3(NT), 0, f, w0, H->zt, rout, H->z, rz_out,
-                                (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<double>, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur,
+                    rz_prev, np, H->red.pq, sc);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr, G, dim3(NT), 0, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
+                    H->red.rr, sc, iter_global);
+    // k_pcg_xr updates r in place: keep both buffers equal
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
     EB_LAUNCH_CHECK();
+    return enqueue_vcycle_one_level(H, rout, H->z, rz_out, 1, s);
+}
+
+// FP32 copies of the hierarchy for the single-precision V-cycle, made once
+// per handle on first use.
+__global__ void __launch_bounds__(NT) k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+static int copy_to_f32(const double* src, int64_t n, float** dst, hipStream_t s) {
+    EB_TRY(dalloc_n(dst, n, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, NT)), dim3(NT), 0, s, n, src, *dst);
+        EB_LAUNCH_CHECK();
+    }
+    return EB_OK;
+}
+
+static int ensure_fp32(amg_handle* H, hipStream_t s) {
+    if (H->fp32_ready) return EB_OK;
+    EB_TRY(copy_to_f32(H->diag_p, H->npad, &H->diag_p32, s));
+    EB_TRY(dalloc_n(&H->res32, H->npad, s));
+    float** zeroed[] = {&H->zt32, &H->z32};
+    for (float** v : zeroed) {
+        EB_TRY(dalloc_n(v, H->npad, s));
+        EB_HIP(hipMemsetAsync(*v, 0, sizeof(float) * H->npad, s));
+    }
+    for (int l = 1; l < H->nlev; ++l) {
+        Level& L = H->lev[l];
+        const int64_t n = L.n > 0 ? L.n : 1;
+        if (!L.is_coarsest) {
+            EB_TRY(copy_to_f32(L.a_val, L.nnz_a, &L.a_val32, s));
+            EB_TRY(copy_to_f32(L.diag, L.n, &L.diag32, s));
+            EB_TRY(copy_to_f32(L.p_val, L.nnz_p, &L.p_val32, s));
+            EB_TRY(copy_to_f32(L.r_val, L.nnz_r, &L.r_val32, s));
+        }
+        EB_TRY(dalloc_n(&L.rv32, n, s));
+        EB_TRY(dalloc_n(&L.ev32, n, s));
+        EB_TRY(dalloc_n(&L.tmp32, n, s));
+    }
+    H->fp32_ready = 1;
     return EB_OK;
 }
 
@@ -994,10 +1124,11 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     p.maxit = 1000;
     p.x0_given = 0;
     p.check_every = 8;
-    p.reserved = 0;
+    p.precision = EB_PREC_FP64;
     if (prm) p = *prm;
-    if (!(p.tol > 0.0) || p.maxit < 0 || p.check_every < 1) {
-        set_error("pcg_solve: invalid parameters (tol > 0, maxit >= 0, check_every >= 1)");
+    if (!(p.tol > 0.0) || p.maxit < 0 || p.check_every < 1 ||
+        (p.precision != EB_PREC_FP64 && p.precision != EB_PREC_FP32)) {
+        set_error("pcg_solve: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0 or 1)");
         return EB_EINVAL;
     }
     memset(res, 0, sizeof(*res));
@@ -1015,6 +1146,9 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         res->status = EB_OK;
         return EB_OK;
     }
+    // the single-precision V-cycle needs a hierarchy below the fine level
+    const bool fp32 = p.precision == EB_PREC_FP32 && H->nlev > 1;
+    if (fp32) EB_TRY(ensure_fp32(H, s));
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const unsigned ug = grid_for(nunk, NT);
@@ -1032,7 +1166,10 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     int rc = EB_OK;
     while (true) {
         EB_TRY(enqueue_init(H, p.tol, iter_base, s));
-        EB_TRY(enqueue_vcycle(H, H->rr[0], H->z, H->red.rz[0], s));   // V-cycle 0 -> rz[0]
+        // V-cycle 0 -> rz[0]
+        if (H->nlev == 1) EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.rz[0], 0, s));
+        else if (fp32) EB_TRY(enqueue_vcycle<float>(H, H->rr[0], H->z32, H->red.rz[0], s));
+        else EB_TRY(enqueue_vcycle<double>(H, H->rr[0], H->z, H->red.rz[0], s));
         int k = 0;
         while (true) {
             EB_TRY(poll_scalars(H, s));
@@ -1045,7 +1182,9 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             const int chunk = left < p.check_every ? left : p.check_every;
             for (int c = 0; c < chunk; ++c, ++enqueued) {
                 ++k;
-                EB_TRY(enqueue_iteration(H, k, iter_base + k, s));
+                if (H->nlev == 1) EB_TRY(enqueue_iteration_one_level(H, k, iter_base + k, s));
+                else if (fp32) EB_TRY(enqueue_iteration<float>(H, k, iter_base + k, s));
+                else EB_TRY(enqueue_iteration<double>(H, k, iter_base + k, s));
             }
         }
         // true residual ||b - A x||
@@ -1078,7 +1217,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     res->restarts = restarts;
     res->status = rc;
     EB_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
-    hipLaunchKernelGGL(k_store_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->x, x);
+    hipLaunchKernelGGL(k_store_field<double>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->x, x);
     EB_LAUNCH_CHECK();
     EB_HIP(hipEventRecord(H->ev1, s));
     EB_HIP(hipStreamSynchronize(s));
@@ -1091,10 +1230,11 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     return rc;
 }
 
-extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream) {
+static int vcycle_apply(amg_handle_t* H, const double* r, double* z, int precision, void* stream,
+                        const char* name) {
     clear_error();
     if (!H || !r || !z) {
-        set_error("amg_vcycle_apply: null pointer");
+        set_error("%s: null pointer", name);
         return EB_EINVAL;
     }
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
@@ -1104,15 +1244,37 @@ extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, voi
     const int64_t nunk = H->n_fine;
     EB_HIP(hipMemsetAsync(z, 0, sizeof(double) * nn, s));
     if (nunk == 0) return EB_OK;
+    const bool fp32 = precision == EB_PREC_FP32 && H->nlev > 1;
+    if (fp32) EB_TRY(ensure_fp32(H, s));
     const unsigned ug = grid_for(nunk, NT);
     hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
     hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, r, H->rr[0]);
     EB_LAUNCH_CHECK();
-    EB_TRY(enqueue_vcycle(H, H->rr[0], H->z, H->red.aux2, s));
-    hipLaunchKernelGGL(k_store_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z, z);
+    if (H->nlev == 1) {
+        EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.aux2, 0, s));
+    } else if (fp32) {
+        EB_TRY(enqueue_vcycle<float>(H, H->rr[0], H->z32, H->red.aux2, s));
+    } else {
+        EB_TRY(enqueue_vcycle<double>(H, H->rr[0], H->z, H->red.aux2, s));
+    }
+    if (fp32) {
+        hipLaunchKernelGGL(k_store_field<float>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z32,
+                           z);
+    } else {
+        hipLaunchKernelGGL(k_store_field<double>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z,
+                           z);
+    }
     EB_LAUNCH_CHECK();
     EB_HIP(hipStreamSynchronize(s));
     return EB_OK;
+}
+
+extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream) {
+    return vcycle_apply(H, r, z, EB_PREC_FP64, stream, "amg_vcycle_apply");
+}
+
+extern "C" int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* stream) {
+    return vcycle_apply(H, r, z, EB_PREC_FP32, stream, "amg_vcycle_apply_fp32");
 }
 
 extern "C" int eb_timing_select(amg_handle_t* H, int kernel_id) {

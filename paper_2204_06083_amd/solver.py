@@ -204,21 +204,26 @@ class Hierarchy:
         L.check(L.lib().eb_timing_read(self.handle, C.byref(n), C.byref(ms)), "eb_timing_read")
         return n.value, ms.value
 
-    def vcycle(self, r: torch.Tensor) -> torch.Tensor:
+    def vcycle(self, r: torch.Tensor, precision: str = "fp64") -> torch.Tensor:
+        """One V(1,1) cycle z = M r; precision "fp64" or "fp32" (single-precision cycle)."""
         shape = self.grid.shape
         z = torch.empty(shape, dtype=torch.float64, device=r.device)
-        rc = L.lib().amg_vcycle_apply(self.handle, _field(r, shape, torch.float64, "r"), C.c_void_p(z.data_ptr()),
-                                      _stream())
-        L.check(rc, "amg_vcycle_apply")
+        fn = {"fp64": "amg_vcycle_apply", "fp32": "amg_vcycle_apply_fp32"}[precision]
+        rc = getattr(L.lib(), fn)(self.handle, _field(r, shape, torch.float64, "r"), C.c_void_p(z.data_ptr()),
+                                  _stream())
+        L.check(rc, fn)
         return z
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-8, maxit: int = 1000,
-              check_every: int = 8, out: Optional[torch.Tensor] = None, allow_noconv: bool = False):
+              check_every: int = 8, out: Optional[torch.Tensor] = None, allow_noconv: bool = False,
+              precision: str = "fp64"):
+        """PCG to ||r|| <= tol ||b||; precision selects the V-cycle's ("fp64" or "fp32")."""
         shape = self.grid.shape
         x = out if out is not None else torch.empty(shape, dtype=torch.float64, device=b.device)
         if x0 is not None:
             x.copy_(x0)
-        prm = L.PcgParams(float(tol), int(maxit), 1 if x0 is not None else 0, int(check_every), 0)
+        prm = L.PcgParams(float(tol), int(maxit), 1 if x0 is not None else 0, int(check_every),
+                          L.PRECISION[precision])
         res = L.PcgResult()
         rc = L.lib().pcg_solve(self.handle, _field(b, shape, torch.float64, "b"), _field(x, shape, torch.float64, "x"),
                                C.byref(prm), C.byref(res), _stream())
@@ -229,7 +234,7 @@ class Hierarchy:
         return x, info
 
 
-def solve_problem(problem, device="cuda", tol=None, coarse_max=256):
+def solve_problem(problem, device="cuda", tol=None, coarse_max=256, precision="fp64"):
     """Full path for one workloads.Problem: assemble, RHS, setup, solve."""
     g = problem.grid
     psi = torch.as_tensor(problem.psi, device=device)
@@ -239,5 +244,5 @@ def solve_problem(problem, device="cuda", tol=None, coarse_max=256):
     u_cut = problem.u_dirichlet(*coords) if problem.u_dirichlet is not None else torch.zeros_like(coords[0])
     b = assemble_rhs(asm, f, torch.as_tensor(u_cut, device=device, dtype=torch.float64))
     H = Hierarchy(g, asm.kind, asm.a, problem.sigma, coarse_max=coarse_max)
-    x, info = H.solve(b, tol=problem.tol if tol is None else tol)
+    x, info = H.solve(b, tol=problem.tol if tol is None else tol, precision=precision)
     return dict(asm=asm, b=b, H=H, x=x, info=info)

@@ -27,7 +27,8 @@
 
 namespace eb {
 
-constexpr int NT = 256;        // threads per block of every solve kernel
+constexpr int NT = 512;        // threads per block of the solve kernels
+constexpr int RNT = 256;       // threads per block of the box-per-thread restriction
 constexpr int MAX_PARTS = 1024;
 
 // The GPU hands out workgroups round-robin over its 8 XCDs, each with its own
@@ -90,19 +91,22 @@ __device__ inline V nbr_sum_scaled(const V* __restrict__ v, const V* __restrict_
 }
 
 // ------------------------------------------------------------ reductions
+// BS is the block size of the calling kernel.
+template <int BS = NT>
 __device__ inline void block_partial(double v, double* __restrict__ part) {
-    __shared__ double lds[NT / WAVE];
-    const double s = block_sum<NT>(v, lds);
+    __shared__ double lds[BS / WAVE];
+    const double s = block_sum<BS>(v, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // Sum of np partials in a fixed order; every thread of the block gets it.
+template <int BS = NT>
 __device__ inline double block_total(const double* __restrict__ part, int np) {
-    __shared__ double lds[NT / WAVE];
+    __shared__ double lds[BS / WAVE];
     __shared__ double tot;
     double a = 0.0;
-    for (int i = threadIdx.x; i < np; i += NT) a += part[i];
-    a = block_sum<NT>(a, lds);
+    for (int i = threadIdx.x; i < np; i += BS) a += part[i];
+    a = block_sum<BS>(a, lds);
     if (threadIdx.x == 0) tot = a;
     __syncthreads();
     const double r = tot;
@@ -192,9 +196,10 @@ __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ 
 }
 
 // Convergence test on ||r||^2 (partials of the previous kernel); true if the
-// caller must return.
+// caller must return.  BS is the caller's block size.
+template <int BS = NT>
 __device__ inline bool converged_or_failed(const double* __restrict__ part_rr, int np, PcgScalars* sc) {
-    const double rr = block_total(part_rr, np);
+    const double rr = block_total<BS>(part_rr, np);
     if (bad_value(rr)) {
         if (lead()) {
             sc->status = EB_ENAN;
@@ -245,13 +250,13 @@ struct BoxArgs {
 };
 
 template <class V>
-__global__ void __launch_bounds__(NT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
+__global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
                                                       const V* __restrict__ res, V* __restrict__ rc,
                                                       PcgScalars* sc, int check, const double* __restrict__ part_rr,
                                                       int np) {
     if (sc->done) return;
-    if (check && converged_or_failed(part_rr, np, sc)) return;
-    const int64_t t = xcd_block() * NT + threadIdx.x;
+    if (check && converged_or_failed<RNT>(part_rr, np, sc)) return;
+    const int64_t t = xcd_block() * RNT + threadIdx.x;
     if (t >= b.nboxes) return;
     const V* __restrict__ dg = vdiag<V>(f);
     const V omega = (V)omega_d;
@@ -721,9 +726,9 @@ static int timing_slot(amg_handle* H, int id, hipStream_t s, hipEvent_t* e0, hip
             hipLaunchKernelGGL(KERNEL, GRID, BLOCKDIM, SHMEM, s, __VA_ARGS__);                \
     } while (0)
 
-// grid of NT-thread blocks covering n items, rounded up to whole XCD groups
-static unsigned xcd_grid(int64_t n) {
-    int64_t g = (n + NT - 1) / NT;
+// grid of `bs`-thread blocks covering n items, rounded up to whole XCD groups
+static unsigned xcd_grid(int64_t n, int bs) {
+    int64_t g = (n + bs - 1) / bs;
     g = (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
     return (unsigned)(g > 0 ? g : NUM_XCD);
 }
@@ -741,6 +746,15 @@ static FineArgs fine_args(const amg_handle* H) {
     f.s = H->d.s;
     f.diag = H->diag_p;
     f.diag32 = H->diag_p32;
+    return f;
+}
+
+// Non-reducing fine kernels: one node per thread over the whole strip list
+// (no fixed partial count to respect).
+static FineArgs fine_args_full(const amg_handle* H, unsigned* grid) {
+    FineArgs f = fine_args(H);
+    f.spb = NT / H->strip_w;
+    *grid = xcd_grid(H->nstrips * (int64_t)H->strip_w, NT);
     return f;
 }
 
@@ -885,10 +899,12 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
     const LevelView<V> L1 = view<V>(H->lev[1]);
     const double w0 = H->lev[0].omega;
     EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, k_fine_down<V>, G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr, np);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
                     box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, G, dim3(NT), 0, f, w0, H->agg_p, L1.ev, r, fb.zt,
+    unsigned gu = 0;
+    const FineArgs fu = fine_args_full(H, &gu);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r, fb.zt,
                     (const PcgScalars*)sc);
     EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
                     (const PcgScalars*)sc);
@@ -919,10 +935,12 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
     const LevelView<V> L1 = view<V>(H->lev[1]);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr_down<V>, G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res, w0,
                     rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0)), dim3(NT), 0, f,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
                     box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, G, dim3(NT), 0, f, w0, H->agg_p, L1.ev, rout, fb.zt,
+    unsigned gu = 0;
+    const FineArgs fu = fine_args_full(H, &gu);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout, fb.zt,
                     (const PcgScalars*)sc);
     EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, rout, fb.z, rz_out,
                     (const PcgScalars*)sc);

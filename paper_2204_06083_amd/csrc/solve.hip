@@ -28,6 +28,8 @@
 namespace eb {
 
 constexpr int NT = 512;        // threads per block of the solve kernels
+// The fixed-grid reducing kernels ask for 8 waves per SIMD (<= 64 VGPRs) so
+// that their whole grid is resident at once.
 constexpr int RNT = 256;       // threads per block of the box-per-thread restriction
 constexpr int MAX_PARTS = 1024;
 
@@ -125,7 +127,7 @@ __device__ inline bool bad_value(double v) { return isnan(v) || isinf(v); }
 // p_new = z + beta p_old; q = A p_new; partial (p_new, q).
 // rho = (r, z) of the latest V-cycle, beta = rho / rho_prev (0 on the first).
 template <class V>
-__global__ void __launch_bounds__(NT) k_pcg_p_spmv(FineArgs f, const V* __restrict__ z,
+__global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
                                                    double* __restrict__ q, const double* __restrict__ rz_cur,
                                                    const double* __restrict__ rz_prev, int np,
@@ -306,7 +308,7 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
 // The CG part is FP64; res is stored in the V-cycle precision.
 // The convergence test on ||r_out||^2 happens in the next kernel.
 template <class V>
-__global__ void __launch_bounds__(NT) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
+__global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
                                                     double* __restrict__ rout, const double* __restrict__ pv,
                                                     const double* __restrict__ q, V* __restrict__ res,
                                                     double omega, const double* __restrict__ rz_cur,
@@ -387,7 +389,7 @@ __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const 
 
 // Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z) in FP64.
 template <class V>
-__global__ void __launch_bounds__(NT) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
+__global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
                                                   const double* __restrict__ r, V* __restrict__ z,
                                                   double* __restrict__ part_rz, const PcgScalars* sc) {
     if (sc->done) return;

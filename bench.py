@@ -155,7 +155,7 @@ def rocprof_summary(path, top=25):
         out.append("| kernel | calls | avg us | min us | max us | total ms | % |")
         out.append("|---|---|---|---|---|---|---|")
         for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
-            name = r["Name"].split("(")[0]
+            name = _kernel_symbol(r["Name"])
             out.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                        f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                        f"{float(r['TotalDurationNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
@@ -164,7 +164,7 @@ def rocprof_summary(path, top=25):
         rows = list(csv.DictReader(open(f)))
         agg = {}
         for r in rows:
-            key = (r["Kernel_Name"].split("(")[0], r["Counter_Name"])
+            key = (_kernel_symbol(r["Kernel_Name"]), r["Counter_Name"])
             a = agg.setdefault(key, [0, 0.0])
             a[0] += 1
             a[1] += float(r["Counter_Value"])
@@ -177,8 +177,16 @@ def rocprof_summary(path, top=25):
     print("\n".join(out))
 
 
-KERNEL_SYMBOLS = {"pcg_spmv": "eb::k_pcg_p_spmv", "pcg_xr_down": "eb::k_pcg_xr_down", "fine_down": "eb::k_fine_down",
-                  "fine_restrict": "eb::k_fine_restrict", "fine_up": "eb::k_fine_up", "fine_post": "eb::k_fine_post"}
+# FP64 instantiations (the bench's headline path)
+KERNEL_SYMBOLS = {k: f"eb::k_{v}<double>" for k, v in {
+    "pcg_spmv": "pcg_p_spmv", "pcg_xr_down": "pcg_xr_down", "fine_down": "fine_down",
+    "fine_restrict": "fine_restrict", "fine_up": "fine_up", "fine_post": "fine_post"}.items()}
+
+
+def _kernel_symbol(name):
+    """Kernel name as rocprofv3 reports it, without arguments or return type."""
+    name = name.split("(")[0]
+    return name[5:] if name.startswith("void ") else name
 SOLVE_SOURCE = os.path.join(ROOT, "paper_2204_06083_amd", "csrc", "solve.hip")
 COPY_BYTES = 256 << 20
 
@@ -194,7 +202,7 @@ def _counter_mean(path, kernel_prefix):
     vals = []
     for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
-            if r["Kernel_Name"].split("(")[0] == kernel_prefix:
+            if _kernel_symbol(r["Kernel_Name"]) == kernel_prefix:
                 vals.append(float(r["Counter_Value"]))
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
 

@@ -181,6 +181,21 @@ int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double si
 int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* p,
               pcg_result_t* res, void* stream);
 
+/* The same PCG for nrhs right-hand sides (1 <= nrhs <= 64) sharing the
+ * hierarchy, run as one launch sequence (Algorithm 2 step 4 for several b, as
+ * in the heat steps of Sec. 4).  b and x hold nrhs node fields back to back
+ * (field j at offset j * (n[0]+1)(n[1]+1)[(n[2]+1)] doubles); x holds the
+ * initial guesses if p->x0_given.  Each right-hand side has its own
+ * iteration, convergence test, true-residual check and restart; res (host)
+ * receives nrhs results (solve_ms is the time of the whole batch).  Returns
+ * EB_OK if every right-hand side converged, else the first failure code in
+ * right-hand-side order; every res[j] is filled either way.  Internally the
+ * vectors interleave the right-hand sides node by node; the first call with a
+ * given slot count (nrhs rounded up to a power of two) and precision makes
+ * the batch buffers, kept until amg_free.  Synchronises `stream`.            */
+int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* p,
+                      pcg_result_t* res, void* stream);
+
 /* Apply one V(1,1) cycle z = M r (node fields; parity and debugging aid).     */
 int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
 

@@ -17,7 +17,7 @@ EB_OK, EB_EINVAL, EB_EDOMAIN, EB_ENOSPC, EB_ENOTSPD, EB_ENAN, EB_ENOCONV, EB_EHI
     0, -1, -2, -3, -4, -5, -6, -7, -8
 
 EXPORTS = [
-    "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
+    "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
     "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory",
@@ -88,6 +88,7 @@ def lib():
     L.stencil_apply.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, vp, vp, vp]
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
+    L.pcg_solve_batched.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]
     L.amg_vcycle_apply_fp32.argtypes = [vp, vp, vp, vp]
     L.amg_num_levels.argtypes = [vp]
@@ -103,7 +104,7 @@ def lib():
     L.eb_strerror.argtypes = [C.c_int]
     L.eb_strerror.restype = C.c_char_p
     L.eb_last_error.restype = C.c_char_p
-    for name in ("eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve",
+    for name in ("eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
                  "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "eb_abi_version",
                  "eb_timing_select", "eb_timing_read"):
         getattr(L, name).restype = i32

@@ -1,0 +1,1074 @@
+// Batched PCG: up to 64 right-hand sides share the hierarchy and one launch
+// sequence (Algorithm 2 step 4 applied to several b at once, as in the heat
+// steps of Sec. 4 and the repeated solves of shape optimisation).
+//
+// Layout: kp slots (a power of two >= nrhs).  Fine-level vectors are planes
+// of kb = min(kp, 8) right-hand sides, node-major inside a plane:
+// v[(j / kb) * npad * kb + node * kb + j % kb], so a wavefront reads 8 nodes x
+// 8 right-hand sides contiguously, every diagonal or aggregate read serves kb
+// right-hand sides, and a grid row of one plane (npad-row x 64 B) stays small
+// enough for the rows above and below to be reused from L2.  Coarse-level
+// vectors interleave all slots per row, v[row * kp + j], so every matrix entry
+// read serves all kp right-hand sides.  The fine level keeps the single
+// solve's padded strips; coarse levels keep their CSR.
+//
+// Each right-hand side runs its own PCG (its own alpha, beta, convergence and
+// iteration count); a converged one is skipped by every later kernel.  The
+// per-RHS sums are formed deterministically: each reducing kernel runs a fixed
+// grid and writes one partial per (block, rhs); a one-block finaliser sums
+// them in a fixed order and updates the per-RHS scalars.
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#include "handle.hpp"
+
+namespace eb {
+
+constexpr int BNT = 512;          // threads per block
+constexpr int BMAX_RHS = 64;
+constexpr int BPARTS = 512;       // blocks of the reducing fine kernels (multiple of 8)
+constexpr int BFIN = 1024;        // threads of the finaliser
+constexpr int BMAX_FINE_COMP = 16;
+
+// Per-RHS scalars on the device (one allocation).
+struct BatchState {
+    double rz[BMAX_RHS];       // (r, z) of the latest V-cycle
+    double beta[BMAX_RHS];     // rz_new / rz_old for the next p-update (0 first)
+    double alpha[BMAX_RHS];
+    double pq[BMAX_RHS];
+    double rr[BMAX_RHS];       // ||r||^2 of the latest iterate
+    double bb[BMAX_RHS];
+    double tol2bb[BMAX_RHS];
+    double rr_true[BMAX_RHS];
+    int32_t done[BMAX_RHS];    // 1: converged, failed or an unused slot
+    int32_t status[BMAX_RHS];
+    int32_t iters[BMAX_RHS];
+    int32_t mask[BMAX_RHS];    // host-set: slots (re)started by the next init
+    int32_t ndone;
+    int32_t maxiter;
+    int32_t pad[2];
+};
+
+struct BatchBufs {
+    int kp = 0;
+    int prec = -1;                        // precision of the V-typed arrays
+    double* x = nullptr;
+    double* rr[2] = {nullptr, nullptr};
+    double* p[2] = {nullptr, nullptr};
+    double* q = nullptr;
+    double* bvec = nullptr;
+    double* tres = nullptr;               // true residual scratch
+    void* res = nullptr;                  // V-typed fine vectors
+    void* zt = nullptr;
+    void* z = nullptr;
+    void* rv[MAX_LEVELS] = {};            // V-typed level vectors (levels >= 1; level 0 if one level)
+    void* ev[MAX_LEVELS] = {};
+    void* tmp[MAX_LEVELS] = {};
+    double* part[3] = {nullptr, nullptr, nullptr};   // [BPARTS][kp]: (p,q), ||r||^2, (r,z)
+    double* part_aux = nullptr;
+    BatchState* st = nullptr;
+    BatchState host;
+};
+
+// ------------------------------------------------------------------ helpers
+struct BFine {
+    const int32_t* strips;
+    int64_t nstrips;
+    int64_t spb;          // strips per block
+    int strip_w;
+    int lsw0;             // log2(strip_w)
+    int lsw;              // log2(strip_w * kp)
+    int lkp;              // log2(kp)
+    int kp;
+    int kb, lkb;          // plane width min(kp, 8) and its log2
+    int64_t plane;        // npad * kb
+    int64_t sy, sz;       // padded node strides
+    int dim;
+    double s;             // 1/h^2
+    const double* diag;
+    const float* diag32;
+    const int32_t* done;  // per-RHS skip flags
+};
+
+template <class V> __device__ inline const V* bdiag(const BFine& f);
+template <> __device__ inline const double* bdiag<double>(const BFine& f) { return f.diag; }
+template <> __device__ inline const float* bdiag<float>(const BFine& f) { return f.diag32; }
+
+// Fine index of (node p, slot j).
+__device__ inline int64_t bvidx(const BFine& f, int64_t p, int j) {
+    return (int64_t)(j >> f.lkb) * f.plane + p * f.kb + (j & (f.kb - 1));
+}
+
+template <class V>
+__device__ inline V bsafe_div(V x, V d) { return d != V(0) ? x / d : V(0); }
+
+// Per-RHS block partial for plane jb: thread t carries the sum for slot
+// jb * kb + t % kb; the block's threads with the same slot are summed in
+// thread order.
+__device__ inline void bpartial(double v, double* __restrict__ part, int kp, int kb, int jb) {
+    __shared__ double lds[BNT];
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < kb) {
+        double a = 0.0;
+        for (int t = threadIdx.x; t < BNT; t += kb) a += lds[t];
+        part[(int64_t)blockIdx.x * kp + jb * kb + threadIdx.x] = a;
+    }
+    __syncthreads();
+}
+
+// The same with the slot t % kp (kernels over interleaved compact vectors).
+__device__ inline void bpartial_kp(double v, double* __restrict__ part, int kp) { bpartial(v, part, kp, kp, 0); }
+
+// Finaliser sum for rhs j over np block partials: BFIN / kp threads per rhs
+// take block-strided partials, then are combined in a fixed order.  Every
+// thread with rhs j returns the total (threads t with t % kp == j).
+__device__ inline double bfin_sum(const double* __restrict__ part, int np, int kp) {
+    __shared__ double lds[BFIN];
+    const int j = threadIdx.x & (kp - 1);
+    const int u = threadIdx.x / kp;
+    const int g = BFIN / kp;
+    double a = 0.0;
+    for (int b = u; b < np; b += g) a += part[(int64_t)b * kp + j];
+    lds[threadIdx.x] = a;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < g; ++w) t += lds[w * kp + j];
+    __syncthreads();
+    return t;
+}
+
+__device__ inline bool bbad(double v) { return isnan(v) || isinf(v); }
+
+// ------------------------------------------------------------- finalisers
+// (Re)start: ||b||^2 and ||r0||^2 per rhs; slots with mask = 0 are left done.
+__global__ void __launch_bounds__(BFIN) kb_fin_init(BatchState* st, const double* __restrict__ part_bb,
+                                                    const double* __restrict__ part_rr, int np, int kp, double tol) {
+    const double bb = bfin_sum(part_bb, np, kp);
+    const double rr = bfin_sum(part_rr, np, kp);
+    const int j = threadIdx.x;
+    if (j < kp && st->mask[j]) {
+        st->bb[j] = bb;
+        st->rr[j] = rr;
+        st->tol2bb[j] = tol * tol * bb;
+        st->status[j] = (bbad(bb) || bbad(rr)) ? EB_ENAN : EB_OK;
+        st->done[j] = (bb == 0.0 || rr <= tol * tol * bb || st->status[j] != EB_OK) ? 1 : 0;
+        st->beta[j] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nd = 0;
+        for (int i = 0; i < kp; ++i) nd += st->done[i] != 0;
+        st->ndone = nd;
+    }
+}
+
+// (r, z) after a V-cycle: beta for the next p-update, curvature check.
+__global__ void __launch_bounds__(BFIN) kb_fin_rz(BatchState* st, const double* __restrict__ part, int np, int kp,
+                                                  int first) {
+    const double rz = bfin_sum(part, np, kp);
+    const int j = threadIdx.x;
+    if (j < kp && !st->done[j]) {
+        if (!(rz > 0.0) || bbad(rz)) {
+            st->status[j] = bbad(rz) ? EB_ENAN : EB_ENOTSPD;
+            st->done[j] = 1;
+        } else {
+            st->beta[j] = first ? 0.0 : rz / st->rz[j];
+            st->rz[j] = rz;
+        }
+    }
+}
+
+// (p, q): alpha = rz / (p, q).
+__global__ void __launch_bounds__(BFIN) kb_fin_pq(BatchState* st, const double* __restrict__ part, int np, int kp) {
+    const double pq = bfin_sum(part, np, kp);
+    const int j = threadIdx.x;
+    if (j < kp && !st->done[j]) {
+        st->pq[j] = pq;
+        if (!(pq > 0.0) || bbad(pq)) {
+            st->status[j] = bbad(pq) ? EB_ENAN : EB_ENOTSPD;
+            st->done[j] = 1;
+        } else {
+            st->alpha[j] = st->rz[j] / pq;
+        }
+    }
+}
+
+// ||r||^2 after the update: iteration count and convergence.
+__global__ void __launch_bounds__(BFIN) kb_fin_rr(BatchState* st, const double* __restrict__ part, int np, int kp) {
+    const double rr = bfin_sum(part, np, kp);
+    const int j = threadIdx.x;
+    if (j < kp && !st->done[j]) {
+        st->iters[j] += 1;
+        st->rr[j] = rr;
+        if (bbad(rr)) {
+            st->status[j] = EB_ENAN;
+            st->done[j] = 1;
+        } else if (rr <= st->tol2bb[j]) {
+            st->done[j] = 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nd = 0, mx = 0;
+        for (int i = 0; i < kp; ++i) {
+            nd += st->done[i] != 0;
+            mx = max(mx, st->iters[i]);
+        }
+        st->ndone = nd;
+        st->maxiter = mx;
+    }
+}
+
+__global__ void __launch_bounds__(BFIN) kb_fin_true(BatchState* st, const double* __restrict__ part, int np, int kp) {
+    const double rr = bfin_sum(part, np, kp);
+    const int j = threadIdx.x;
+    if (j < kp) st->rr_true[j] = rr;
+}
+
+// ------------------------------------------------------------ fine kernels
+// Each thread takes one (node, j % kb) element of a plane and handles it in
+// all NPL = kp / kb planes in one unrolled body, so the loads of the planes
+// are independent and in flight together.  v0 is the element's index in
+// plane 0; plane jb adds jb * plane.
+#define BNODE_LOOP(f, p, jj, v0)                                                                         \
+    for (int64_t s0_ = xcd_block() * (f).spb, s1_ = min(s0_ + (f).spb, (f).nstrips),                      \
+                 e_ = (int64_t)threadIdx.x, eend_ = (s1_ - s0_) * ((int64_t)(f).strip_w << (f).lkb);       \
+         e_ < eend_; e_ += BNT)                                                                            \
+        for (int64_t p = (int64_t)(f).strips[s0_ + (e_ >> ((f).lsw0 + (f).lkb))] * (f).strip_w +           \
+                         ((e_ >> (f).lkb) & ((f).strip_w - 1)),                                            \
+                     jj = e_ & ((f).kb - 1), v0 = p * (f).kb + jj, once_ = 0;                              \
+             once_ < 1; ++once_)
+
+template <int NPL>
+__device__ inline void bpartials(const double (&acc)[NPL], double* __restrict__ part, const BFine& f) {
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) bpartial(acc[jb], part, f.kp, f.kb, jb);
+}
+
+// out = b - A x, partial ||out||^2 per rhs (FP64; every slot).
+template <int NPL>
+__global__ void __launch_bounds__(BNT) kb_resid(BFine f, const double* __restrict__ b, const double* __restrict__ x,
+                                                double* __restrict__ out, double* __restrict__ part) {
+    double acc[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    BNODE_LOOP(f, p, jj, v0) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const int64_t v = v0 + jb * f.plane;
+                double nb = x[v - ox] + x[v + ox] + x[v - sy] + x[v + sy];
+                if (f.dim == 3) nb += x[v - sz] + x[v + sz];
+                const double rv = b[v] - (d * x[v] - f.s * nb);
+                out[v] = rv;
+                acc[jb] += rv * rv;
+            }
+        }
+    }
+    bpartials<NPL>(acc, part, f);
+}
+
+template <int NPL>
+__global__ void __launch_bounds__(BNT) kb_norm2(BFine f, const double* __restrict__ a, double* __restrict__ part) {
+    double acc[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    BNODE_LOOP(f, p, jj, v0) {
+        if (f.diag[p] != 0.0) {
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const double t = a[v0 + jb * f.plane];
+                acc[jb] += t * t;
+            }
+        }
+    }
+    bpartials<NPL>(acc, part, f);
+}
+
+// Initial pre-smoothing residual res = r - A (omega D^-1 r).
+template <class V, int NPL>
+__global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const double* __restrict__ r,
+                                                    V* __restrict__ res) {
+    const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    BNODE_LOOP(f, p, jj, v0) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double dxm = f.diag[p - 1], dxp = f.diag[p + 1], dym = f.diag[p - f.sy], dyp = f.diag[p + f.sy];
+            const double dzm = f.dim == 3 ? f.diag[p - f.sz] : 0.0, dzp = f.dim == 3 ? f.diag[p + f.sz] : 0.0;
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                if (f.done[(jb << f.lkb) + jj]) continue;
+                const int64_t v = v0 + jb * f.plane;
+                double nb = bsafe_div(r[v - ox], dxm) + bsafe_div(r[v + ox], dxp);
+                nb += bsafe_div(r[v - sy], dym) + bsafe_div(r[v + sy], dyp);
+                if (f.dim == 3) nb += bsafe_div(r[v - sz], dzm) + bsafe_div(r[v + sz], dzp);
+                const double z1 = omega * r[v] / d;
+                res[v] = (V)(r[v] - (d * z1 - f.s * (omega * nb)));
+            }
+        }
+    }
+}
+
+// p_new = z + beta p_old; q = A p_new; partial (p_new, q).
+template <class V, int NPL>
+__global__ void __launch_bounds__(BNT) kb_pspmv(BFine f, const V* __restrict__ z, const double* __restrict__ pold,
+                                                double* __restrict__ pnew, double* __restrict__ q,
+                                                const BatchState* __restrict__ st, double* __restrict__ part) {
+    double acc[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    BNODE_LOOP(f, p, jj, v0) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const int j = (jb << f.lkb) + (int)jj;
+                if (f.done[j]) continue;
+                const double beta = st->beta[j];
+                const int64_t v = v0 + jb * f.plane;
+                auto pv = [&](int64_t w) { return beta != 0.0 ? (double)z[w] + beta * pold[w] : (double)z[w]; };
+                const double pc = pv(v);
+                double nb = pv(v - ox) + pv(v + ox) + pv(v - sy) + pv(v + sy);
+                if (f.dim == 3) nb += pv(v - sz) + pv(v + sz);
+                const double qv = d * pc - f.s * nb;
+                pnew[v] = pc;
+                q[v] = qv;
+                acc[jb] += pc * qv;
+            }
+        }
+    }
+    bpartials<NPL>(acc, part, f);
+}
+
+// x += alpha p; r_out = r_in - alpha q; res = r_out - A (omega D^-1 r_out).
+template <class V, int NPL>
+__global__ void __launch_bounds__(BNT) kb_xr_down(BFine f, double* __restrict__ x, const double* __restrict__ rin,
+                                                  double* __restrict__ rout, const double* __restrict__ pv,
+                                                  const double* __restrict__ q, V* __restrict__ res, double omega,
+                                                  const BatchState* __restrict__ st, double* __restrict__ part) {
+    double acc[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    BNODE_LOOP(f, p, jj, v0) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double dxm = f.diag[p - 1], dxp = f.diag[p + 1], dym = f.diag[p - f.sy], dyp = f.diag[p + f.sy];
+            const double dzm = f.dim == 3 ? f.diag[p - f.sz] : 0.0, dzp = f.dim == 3 ? f.diag[p + f.sz] : 0.0;
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const int j = (jb << f.lkb) + (int)jj;
+                if (f.done[j]) continue;
+                const double al = st->alpha[j];
+                const int64_t v = v0 + jb * f.plane;
+                x[v] = x[v] + al * pv[v];
+                const double rn = rin[v] - al * q[v];
+                rout[v] = rn;
+                acc[jb] += rn * rn;
+                double nb = bsafe_div(rin[v - ox] - al * q[v - ox], dxm);
+                nb += bsafe_div(rin[v + ox] - al * q[v + ox], dxp);
+                nb += bsafe_div(rin[v - sy] - al * q[v - sy], dym);
+                nb += bsafe_div(rin[v + sy] - al * q[v + sy], dyp);
+                if (f.dim == 3) {
+                    nb += bsafe_div(rin[v - sz] - al * q[v - sz], dzm);
+                    nb += bsafe_div(rin[v + sz] - al * q[v + sz], dzp);
+                }
+                const double z1 = omega * rn / d;
+                res[v] = (V)(rn - (d * z1 - f.s * (omega * nb)));
+            }
+        }
+    }
+    bpartials<NPL>(acc, part, f);
+}
+
+// Restriction r_c = P_tent^T (I - omega A D^-1) res: one thread per
+// (level-0 box, rhs).
+struct BBox {
+    const int32_t* boxes;
+    int64_t nboxes;
+    int nbx, nby;
+    int nx, ny, nz;
+    const int32_t* cstart;
+    const int32_t* ncomp;
+    const int32_t* agg;
+};
+
+template <class V>
+__global__ void __launch_bounds__(256) kb_restrict(BFine f, BBox b, double omega_d, const V* __restrict__ res,
+                                                   V* __restrict__ rc) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t bi = t >> f.lkp;
+    const int j = (int)(t & (f.kp - 1));
+    if (bi >= b.nboxes || f.done[j]) return;
+    const V* __restrict__ dg = bdiag<V>(f);
+    const V omega = (V)omega_d;
+    const V sh = (V)f.s;
+    const int64_t kp = f.kp;
+    const int64_t dx = f.kb, dy = f.sy * f.kb, dz = f.sz * f.kb;   // fine-index strides
+    const int64_t box = b.boxes[bi];
+    const int bx = (int)(box % b.nbx);
+    const int64_t rq = box / b.nbx;
+    const int by = (int)(rq % b.nby);
+    const int bz = (int)(rq / b.nby);
+    const int32_t c0 = b.cstart[box];
+    const int m = b.ncomp[box];
+    V acc[BMAX_FINE_COMP];
+#pragma unroll
+    for (int c = 0; c < BMAX_FINE_COMP; ++c) acc[c] = V(0);
+    const int z_hi = f.dim == 3 ? 3 : 1;
+    for (int oz = 0; oz < z_hi; ++oz) {
+        const int k = f.dim == 3 ? 3 * bz + oz : 0;
+        if (k >= b.nz) break;
+        for (int oy = 0; oy < 3; ++oy) {
+            const int jj = 3 * by + oy;
+            if (jj >= b.ny) break;
+            for (int ox = 0; ox < 3; ++ox) {
+                const int i = 3 * bx + ox;
+                if (i >= b.nx) break;
+                const int64_t p = (int64_t)i + f.sy * jj + f.sz * k;
+                const V d = dg[p];
+                if (d == V(0)) continue;
+                const int64_t v = bvidx(f, p, j);
+                const V rp = res[v];
+                V nb = bsafe_div(res[v - dx], dg[p - 1]) + bsafe_div(res[v + dx], dg[p + 1]);
+                nb += bsafe_div(res[v - dy], dg[p - f.sy]) + bsafe_div(res[v + dy], dg[p + f.sy]);
+                if (f.dim == 3) nb += bsafe_div(res[v - dz], dg[p - f.sz]) + bsafe_div(res[v + dz], dg[p + f.sz]);
+                const V aw = d * (rp / d) - sh * nb;
+                const V u = rp - omega * aw;
+                if (m == 1) {
+                    acc[0] += u;
+                } else {
+                    const int c = b.agg[p] - c0;
+                    if (c >= 0 && c < BMAX_FINE_COMP) acc[c] += u;
+                }
+            }
+        }
+    }
+    for (int c = 0; c < m && c < BMAX_FINE_COMP; ++c) rc[(int64_t)(c0 + c) * kp + j] = acc[c];
+}
+
+// zt = omega r / d + t - omega (A t) / d, t = e_c[agg]; the aggregate ids of
+// the five (seven) stencil points are read once for all planes.
+template <class V, int NPL>
+__global__ void __launch_bounds__(BNT) kb_fine_up(BFine f, double omega_d, const int32_t* __restrict__ agg,
+                                                  const V* __restrict__ ec, const double* __restrict__ r,
+                                                  V* __restrict__ zt) {
+    const V* __restrict__ dg = bdiag<V>(f);
+    const V omega = (V)omega_d;
+    const int64_t kp = f.kp;
+    BNODE_LOOP(f, p, jj, v0) {
+        const V d = dg[p];
+        if (d != V(0)) {
+            const int32_t g0 = agg[p], g1 = agg[p - 1], g2 = agg[p + 1], g3 = agg[p - f.sy], g4 = agg[p + f.sy];
+            const int32_t g5 = f.dim == 3 ? agg[p - f.sz] : -1, g6 = f.dim == 3 ? agg[p + f.sz] : -1;
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const int j = (jb << f.lkb) + (int)jj;
+                if (f.done[j]) continue;
+                auto t_at = [&](int32_t g) { return g >= 0 ? ec[(int64_t)g * kp + j] : V(0); };
+                const V tp = t_at(g0);
+                V nb = t_at(g1) + t_at(g2) + t_at(g3) + t_at(g4);
+                if (f.dim == 3) nb += t_at(g5) + t_at(g6);
+                const V at = d * tp - (V)f.s * nb;
+                const int64_t v = v0 + jb * f.plane;
+                zt[v] = omega * (V)r[v] / d + (tp - omega * at / d);
+            }
+        }
+    }
+}
+
+// z = zt + omega (r - A zt) / d; partial (r, z) per rhs.
+template <class V, int NPL>
+__global__ void __launch_bounds__(BNT) kb_fine_post(BFine f, double omega_d, const V* __restrict__ zt,
+                                                    const double* __restrict__ r, V* __restrict__ z,
+                                                    double* __restrict__ part) {
+    const V* __restrict__ dg = bdiag<V>(f);
+    const V omega = (V)omega_d;
+    const V sh = (V)f.s;
+    const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    double acc[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    BNODE_LOOP(f, p, jj, v0) {
+        const V d = dg[p];
+        if (d != V(0)) {
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                const int j = (jb << f.lkb) + (int)jj;
+                if (f.done[j]) continue;
+                const int64_t v = v0 + jb * f.plane;
+                V nb = zt[v - ox] + zt[v + ox] + zt[v - sy] + zt[v + sy];
+                if (f.dim == 3) nb += zt[v - sz] + zt[v + sz];
+                const V az = d * zt[v] - sh * nb;
+                const V zv = zt[v] + omega * ((V)r[v] - az) / d;
+                z[v] = zv;
+                acc[jb] += r[v] * (double)zv;
+            }
+        }
+    }
+    bpartials<NPL>(acc, part, f);
+}
+
+// ---------------------------------------------------------- coarse kernels
+// One thread per (row, rhs); the lanes of a wavefront share the row's entries.
+template <class V>
+struct BCsr {
+    const int32_t* rowptr;
+    const int32_t* col;
+    const V* val;
+};
+
+#define BROW(n, lkp, kp, done, row, j)                          \
+    const int64_t t_ = (int64_t)blockIdx.x * BNT + threadIdx.x;   \
+    const int64_t row = t_ >> (lkp);                              \
+    const int j = (int)(t_ & ((kp) - 1));                         \
+    if (row >= (n) || (done)[j]) return;
+
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_csr_resid(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                    BCsr<V> A, const V* __restrict__ diag, V omega,
+                                                    const V* __restrict__ rv, V* __restrict__ res) {
+    BROW(n, lkp, kp, done, row, j)
+    V az = V(0);
+    for (int e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) {
+        const int k = A.col[e];
+        az += A.val[e] * (omega * rv[(int64_t)k * kp + j] / diag[k]);
+    }
+    res[row * kp + j] = rv[row * kp + j] - az;
+}
+
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_csr_matvec(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                     BCsr<V> M, const V* __restrict__ x, V* __restrict__ y) {
+    BROW(n, lkp, kp, done, row, j)
+    V acc = V(0);
+    for (int e = M.rowptr[row]; e < M.rowptr[row + 1]; ++e) acc += M.val[e] * x[(int64_t)M.col[e] * kp + j];
+    y[row * kp + j] = acc;
+}
+
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_csr_prolong(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                      BCsr<V> P, const V* __restrict__ diag, V omega,
+                                                      const V* __restrict__ rv, const V* __restrict__ ev_c,
+                                                      V* __restrict__ zt) {
+    BROW(n, lkp, kp, done, row, j)
+    V acc = V(0);
+    for (int e = P.rowptr[row]; e < P.rowptr[row + 1]; ++e) acc += P.val[e] * ev_c[(int64_t)P.col[e] * kp + j];
+    zt[row * kp + j] = omega * rv[row * kp + j] / diag[row] + acc;
+}
+
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_csr_post(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                   BCsr<V> A, const V* __restrict__ diag, V omega,
+                                                   const V* __restrict__ rv, const V* __restrict__ zt,
+                                                   V* __restrict__ ev) {
+    BROW(n, lkp, kp, done, row, j)
+    V az = V(0);
+    for (int e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) az += A.val[e] * zt[(int64_t)A.col[e] * kp + j];
+    ev[row * kp + j] = zt[row * kp + j] + omega * (rv[row * kp + j] - az) / diag[row];
+}
+
+// Coarsest: ev = W rv (W FP64, FP64 accumulation).
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_dense(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                const double* __restrict__ W, const V* __restrict__ rv,
+                                                V* __restrict__ ev) {
+    BROW(n, lkp, kp, done, row, j)
+    double acc = 0.0;
+    for (int64_t m = 0; m < n; ++m) acc += W[row * n + m] * (double)rv[m * kp + j];
+    ev[row * kp + j] = (V)acc;
+}
+
+// One-level hierarchies: gather r to compact order and scatter z back.
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_gather(BFine f, int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                 const int32_t* __restrict__ pad, const double* __restrict__ src,
+                                                 V* __restrict__ dst) {
+    BROW(n, lkp, kp, done, k, j)
+    dst[k * kp + j] = (V)src[bvidx(f, pad[k], j)];
+}
+
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_scatter_dot(BFine f, int64_t n, int lkp, int kp,
+                                                      const int32_t* __restrict__ done,
+                                                      const int32_t* __restrict__ pad, const V* __restrict__ ev,
+                                                      const double* __restrict__ r, V* __restrict__ z,
+                                                      double* __restrict__ part) {
+    // fixed grid: each block strides over the (unknown, rhs) pairs
+    double acc = 0.0;
+    const int64_t total = n << lkp;
+    for (int64_t t = (int64_t)blockIdx.x * BNT + threadIdx.x; t < total; t += (int64_t)gridDim.x * BNT) {
+        const int64_t k = t >> lkp;
+        const int j = (int)(t & (kp - 1));
+        if (done[j]) continue;
+        const int64_t v = bvidx(f, pad[k], j);
+        z[v] = ev[k * kp + j];
+        acc += r[v] * (double)ev[k * kp + j];
+    }
+    bpartial_kp(acc, part, kp);
+}
+
+// Node fields <-> interleaved padded layout.
+__global__ void __launch_bounds__(BNT) kb_load(BFine f, int64_t nunk, int lkp, int kp, int nrhs, int64_t nn,
+                                               const int64_t* __restrict__ nodes, const int32_t* __restrict__ pad,
+                                               const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * BNT + threadIdx.x;
+    const int64_t k = t >> lkp;
+    const int j = (int)(t & (kp - 1));
+    if (k >= nunk) return;
+    dst[bvidx(f, pad[k], j)] = j < nrhs ? src[(int64_t)j * nn + nodes[k]] : 0.0;
+}
+
+__global__ void __launch_bounds__(BNT) kb_store(BFine f, int64_t nunk, int lkp, int kp, int nrhs, int64_t nn,
+                                                const int64_t* __restrict__ nodes, const int32_t* __restrict__ pad,
+                                                const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * BNT + threadIdx.x;
+    const int64_t k = t >> lkp;
+    const int j = (int)(t & (kp - 1));
+    if (k >= nunk || j >= nrhs) return;
+    dst[(int64_t)j * nn + nodes[k]] = src[bvidx(f, pad[k], j)];
+}
+
+// ---------------------------------------------------------------- host side
+// Device addresses of BatchState members (no host dereference of B->st).
+static int32_t* st_done(BatchBufs* B) {
+    return reinterpret_cast<int32_t*>(reinterpret_cast<char*>(B->st) + offsetof(BatchState, done));
+}
+static int32_t* st_mask(BatchBufs* B) {
+    return reinterpret_cast<int32_t*>(reinterpret_cast<char*>(B->st) + offsetof(BatchState, mask));
+}
+
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+void free_batch(amg_handle* H, hipStream_t s) {
+    BatchBufs* B = H->batch;
+    if (!B) return;
+    void* ptrs[] = {B->x, B->rr[0], B->rr[1], B->p[0], B->p[1], B->q, B->bvec, B->tres, B->res, B->zt, B->z,
+                    B->part[0], B->part[1], B->part[2], B->part_aux, B->st};
+    for (void* p : ptrs) (void)dfree(p, s);
+    for (int l = 0; l < MAX_LEVELS; ++l) {
+        (void)dfree(B->rv[l], s);
+        (void)dfree(B->ev[l], s);
+        (void)dfree(B->tmp[l], s);
+    }
+    delete B;
+    H->batch = nullptr;
+}
+
+// Buffers for kp slots with V-cycle element size vb (8 or 4 bytes).
+static int ensure_batch(amg_handle* H, int kp, int prec, hipStream_t s) {
+    if (H->batch && H->batch->kp == kp && H->batch->prec == prec) return EB_OK;
+    free_batch(H, s);
+    BatchBufs* B = new BatchBufs();
+    H->batch = B;
+    B->kp = kp;
+    B->prec = prec;
+    const int64_t nv = H->npad * kp;
+    const size_t vb = prec == EB_PREC_FP32 ? sizeof(float) : sizeof(double);
+    // read at neighbours without a guard: zero off unknowns
+    double** zeroed[] = {&B->x, &B->p[0], &B->p[1], &B->rr[0], &B->rr[1]};
+    for (double** v : zeroed) {
+        EB_TRY(dalloc_n(v, nv, s));
+        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * nv, s));
+    }
+    EB_TRY(dalloc_n(&B->q, nv, s));
+    EB_TRY(dalloc_n(&B->bvec, nv, s));
+    EB_HIP(hipMemsetAsync(B->bvec, 0, sizeof(double) * nv, s));
+    EB_TRY(dalloc_n(&B->tres, nv, s));
+    void** vzeroed[] = {&B->zt, &B->z, &B->res};
+    for (void** v : vzeroed) {
+        EB_TRY(dalloc(v, vb * (size_t)nv, s));
+        EB_HIP(hipMemsetAsync(*v, 0, vb * (size_t)nv, s));
+    }
+    for (int l = (H->nlev > 1 ? 1 : 0); l < H->nlev; ++l) {
+        const int64_t n = (H->lev[l].n > 0 ? H->lev[l].n : 1) * kp;
+        EB_TRY(dalloc(&B->rv[l], vb * (size_t)n, s));
+        EB_TRY(dalloc(&B->ev[l], vb * (size_t)n, s));
+        EB_TRY(dalloc(&B->tmp[l], vb * (size_t)n, s));
+    }
+    for (int i = 0; i < 3; ++i) EB_TRY(dalloc_n(&B->part[i], (int64_t)BPARTS * kp, s));
+    EB_TRY(dalloc_n(&B->part_aux, (int64_t)BPARTS * kp, s));
+    EB_TRY(dalloc_n(&B->st, 1, s));
+    EB_HIP(hipMemsetAsync(B->st, 0, sizeof(BatchState), s));
+    return EB_OK;
+}
+
+static BFine bfine(const amg_handle* H, const BatchBufs* B, bool full, unsigned* grid) {
+    BFine f;
+    f.strips = H->strips;
+    f.nstrips = H->nstrips;
+    f.strip_w = H->strip_w;
+    f.kp = B->kp;
+    f.lkp = ilog2(B->kp);
+    f.kb = B->kp < 8 ? B->kp : 8;
+    f.lkb = ilog2(f.kb);
+    f.plane = H->npad * f.kb;
+    f.lsw0 = ilog2(H->strip_w);
+    f.lsw = f.lsw0 + f.lkp;
+    f.sy = H->px;
+    f.sz = (int64_t)H->px * H->d.ny;
+    f.dim = H->d.dim;
+    f.s = H->d.s;
+    f.diag = H->diag_p;
+    f.diag32 = H->diag_p32;
+    f.done = st_done(const_cast<BatchBufs*>(B));
+    if (full) {
+        // one element per thread
+        const int64_t per_block = BNT / ((int64_t)H->strip_w * f.kb);
+        if (per_block >= 1) {
+            f.spb = per_block;
+            int64_t g = (H->nstrips + per_block - 1) / per_block;
+            g = (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+            *grid = (unsigned)(g > 0 ? g : NUM_XCD);
+            return f;
+        }
+    }
+    f.spb = (H->nstrips + BPARTS - 1) / BPARTS;
+    *grid = BPARTS;
+    return f;
+}
+
+static BBox bbox(const amg_handle* H) {
+    BBox b;
+    const Level& L0 = H->lev[0];
+    b.boxes = H->boxes0;
+    b.nboxes = H->nboxes0;
+    b.nbx = L0.nb[0];
+    b.nby = L0.nb[1];
+    b.nx = H->d.nx;
+    b.ny = H->d.ny;
+    b.nz = H->d.nz;
+    b.cstart = L0.box_cstart;
+    b.ncomp = L0.box_ncomp;
+    b.agg = H->agg_p;
+    return b;
+}
+
+template <class V> static BCsr<V> bcsr_a(const Level& L);
+template <class V> static BCsr<V> bcsr_p(const Level& L);
+template <class V> static BCsr<V> bcsr_r(const Level& L);
+template <class V> static const V* bldiag(const Level& L);
+template <> BCsr<double> bcsr_a<double>(const Level& L) { return {L.a_rowptr, L.a_col, L.a_val}; }
+template <> BCsr<double> bcsr_p<double>(const Level& L) { return {L.p_rowptr, L.p_col, L.p_val}; }
+template <> BCsr<double> bcsr_r<double>(const Level& L) { return {L.r_rowptr, L.r_col, L.r_val}; }
+template <> const double* bldiag<double>(const Level& L) { return L.diag; }
+template <> BCsr<float> bcsr_a<float>(const Level& L) { return {L.a_rowptr, L.a_col, L.a_val32}; }
+template <> BCsr<float> bcsr_p<float>(const Level& L) { return {L.p_rowptr, L.p_col, L.p_val32}; }
+template <> BCsr<float> bcsr_r<float>(const Level& L) { return {L.r_rowptr, L.r_col, L.r_val32}; }
+template <> const float* bldiag<float>(const Level& L) { return L.diag32; }
+
+// Launch a fine kernel instantiated for NPL = kp / kb planes (1, 2, 4 or 8).
+#define BLAUNCH_V(KERNEL, V, npl, grid, ...)                                                       \
+    do {                                                                                           \
+        switch (npl) {                                                                             \
+            case 1: hipLaunchKernelGGL((KERNEL<V, 1>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            case 2: hipLaunchKernelGGL((KERNEL<V, 2>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            case 4: hipLaunchKernelGGL((KERNEL<V, 4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<V, 8>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+        }                                                                                          \
+    } while (0)
+#define BLAUNCH_N(KERNEL, npl, grid, ...)                                                       \
+    do {                                                                                        \
+        switch (npl) {                                                                          \
+            case 1: hipLaunchKernelGGL((KERNEL<1>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            case 2: hipLaunchKernelGGL((KERNEL<2>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            case 4: hipLaunchKernelGGL((KERNEL<4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<8>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+        }                                                                                       \
+    } while (0)
+
+static int npl_of(const BFine& f) { return f.kp / f.kb; }
+
+static unsigned rows_grid(int64_t rows, int kp) {
+    const int64_t t = rows * kp;
+    return (unsigned)((t + BNT - 1) / BNT > 0 ? (t + BNT - 1) / BNT : 1);
+}
+
+// z = M r for every active rhs; the (r, z) partials go to part.
+template <class V>
+static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int initial, double* part, hipStream_t s) {
+    const int kp = B->kp, lkp = ilog2(kp);
+    const int32_t* done = st_done(B);
+    V* z = (V*)B->z;
+    if (H->nlev == 1) {
+        const Level& L = H->lev[0];
+        V* rv = (V*)B->rv[0];
+        V* ev = (V*)B->ev[0];
+        unsigned gq = 0;
+        const BFine fq = bfine(H, B, false, &gq);
+        hipLaunchKernelGGL(kb_gather<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, fq, L.n, lkp, kp, done,
+                           H->fine_pad, r, rv);
+        hipLaunchKernelGGL(kb_dense<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done, L.dense_inv,
+                           (const V*)rv, ev);
+        hipLaunchKernelGGL(kb_scatter_dot<V>, dim3(BPARTS), dim3(BNT), 0, s, fq, L.n, lkp, kp, done, H->fine_pad,
+                           (const V*)ev, r, z, part);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
+    unsigned gfull = 0;
+    const BFine ff = bfine(H, B, true, &gfull);
+    unsigned gfix = 0;
+    const BFine fr = bfine(H, B, false, &gfix);
+    const double w0 = H->lev[0].omega;
+    if (initial) {
+        BLAUNCH_V(kb_fine_down, V, npl_of(ff), dim3(gfull), ff, w0, r, (V*)B->res);
+    }
+    const BBox bx = bbox(H);
+    const int64_t nbt = H->nboxes0 * kp;
+    hipLaunchKernelGGL(kb_restrict<V>, dim3((unsigned)((nbt + 255) / 256 > 0 ? (nbt + 255) / 256 : 1)), dim3(256), 0,
+                       s, ff, bx, w0, (const V*)B->res, (V*)B->rv[1]);
+    for (int l = 1; l < H->nlev - 1; ++l) {
+        const Level& L = H->lev[l];
+        const Level& C = H->lev[l + 1];
+        const V w = (V)L.omega;
+        hipLaunchKernelGGL(kb_csr_resid<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
+                           bcsr_a<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (V*)B->tmp[l]);
+        hipLaunchKernelGGL(kb_csr_matvec<V>, dim3(rows_grid(C.n, kp)), dim3(BNT), 0, s, C.n, lkp, kp, done,
+                           bcsr_r<V>(L), (const V*)B->tmp[l], (V*)B->rv[l + 1]);
+    }
+    {
+        const Level& Lc = H->lev[H->nlev - 1];
+        hipLaunchKernelGGL(kb_dense<V>, dim3(rows_grid(Lc.n, kp)), dim3(BNT), 0, s, Lc.n, lkp, kp, done,
+                           Lc.dense_inv, (const V*)B->rv[H->nlev - 1], (V*)B->ev[H->nlev - 1]);
+    }
+    for (int l = H->nlev - 2; l >= 1; --l) {
+        const Level& L = H->lev[l];
+        const V w = (V)L.omega;
+        hipLaunchKernelGGL(kb_csr_prolong<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
+                           bcsr_p<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (const V*)B->ev[l + 1], (V*)B->tmp[l]);
+        hipLaunchKernelGGL(kb_csr_post<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
+                           bcsr_a<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (const V*)B->tmp[l], (V*)B->ev[l]);
+    }
+    BLAUNCH_V(kb_fine_up, V, npl_of(ff), dim3(gfull), ff, w0, H->agg_p, (const V*)B->ev[1], r, (V*)B->zt);
+    BLAUNCH_V(kb_fine_post, V, npl_of(fr), dim3(gfix), fr, w0, (const V*)B->zt, r, z, part);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// Iteration k >= 1 (ping-pong as in the single solve).
+template <class V>
+static int benqueue_iteration(amg_handle* H, BatchBufs* B, int k, hipStream_t s) {
+    const int kp = B->kp;
+    unsigned gfix = 0;
+    const BFine fr = bfine(H, B, false, &gfix);
+    double* pold = B->p[k & 1];
+    double* pnew = B->p[(k + 1) & 1];
+    double* rin = B->rr[(k - 1) & 1];
+    double* rout = B->rr[k & 1];
+    BLAUNCH_V(kb_pspmv, V, npl_of(fr), dim3(gfix), fr, (const V*)B->z, pold, pnew, B->q, (const BatchState*)B->st,
+              B->part[0]);
+    hipLaunchKernelGGL(kb_fin_pq, dim3(1), dim3(BFIN), 0, s, B->st, B->part[0], (int)gfix, kp);
+    // (with one level the fused pre-smoothing residual is formed but not used)
+    BLAUNCH_V(kb_xr_down, V, npl_of(fr), dim3(gfix), fr, B->x, rin, rout, pnew, B->q, (V*)B->res, H->lev[0].omega,
+              (const BatchState*)B->st, B->part[1]);
+    hipLaunchKernelGGL(kb_fin_rr, dim3(1), dim3(BFIN), 0, s, B->st, B->part[1], (int)gfix, kp);
+    EB_LAUNCH_CHECK();
+    EB_TRY(benqueue_vcycle<V>(H, B, rout, 0, B->part[2], s));
+    const int np_rz = H->nlev == 1 ? BPARTS : (int)gfix;
+    hipLaunchKernelGGL(kb_fin_rz, dim3(1), dim3(BFIN), 0, s, B->st, B->part[2], np_rz, kp, 0);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+// (Re)start for the slots whose mask is set: r0 = b - A x, norms, first V-cycle.
+template <class V>
+static int benqueue_start(amg_handle* H, BatchBufs* B, double tol, hipStream_t s) {
+    const int kp = B->kp;
+    unsigned gfix = 0;
+    const BFine fr = bfine(H, B, false, &gfix);
+    BLAUNCH_N(kb_norm2, npl_of(fr), dim3(gfix), fr, B->bvec, B->part_aux);
+    BLAUNCH_N(kb_resid, npl_of(fr), dim3(gfix), fr, B->bvec, B->x, B->rr[0], B->part[1]);
+    hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, B->part[1], (int)gfix, kp, tol);
+    EB_LAUNCH_CHECK();
+    EB_TRY(benqueue_vcycle<V>(H, B, B->rr[0], 1, B->part[2], s));
+    const int np_rz = H->nlev == 1 ? BPARTS : (int)gfix;
+    hipLaunchKernelGGL(kb_fin_rz, dim3(1), dim3(BFIN), 0, s, B->st, B->part[2], np_rz, kp, 1);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+static int bpoll(BatchBufs* B, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(&B->host, B->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+static int bset_mask(BatchBufs* B, const int32_t* mask, hipStream_t s) {
+    memcpy(B->host.mask, mask, sizeof(B->host.mask));
+    EB_HIP(hipMemcpyAsync(st_mask(B), B->host.mask, sizeof(B->host.mask), hipMemcpyHostToDevice, s));
+    EB_HIP(hipStreamSynchronize(s));   // the host array is reused
+    return EB_OK;
+}
+
+template <class V>
+static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t& p, pcg_result_t* res,
+                       hipStream_t s) {
+    const int kp = B->kp;
+    int32_t mask[BMAX_RHS];
+    for (int j = 0; j < BMAX_RHS; ++j) mask[j] = j < nrhs ? 1 : 0;
+    // unused slots: done from the start
+    {
+        BatchState init;
+        memset(&init, 0, sizeof(init));
+        for (int j = 0; j < BMAX_RHS; ++j) init.done[j] = j < nrhs ? 0 : 1;
+        B->host = init;
+        EB_HIP(hipMemcpyAsync(B->st, &B->host, sizeof(BatchState), hipMemcpyHostToDevice, s));
+        EB_HIP(hipStreamSynchronize(s));
+    }
+    EB_TRY(bset_mask(B, mask, s));
+    int restarts[BMAX_RHS] = {0};
+    int enqueued = 0;
+    while (true) {
+        EB_TRY(benqueue_start<V>(H, B, p.tol, s));
+        int k = 0;
+        while (true) {
+            EB_TRY(bpoll(B, s));
+            if (B->host.ndone >= kp || B->host.maxiter >= p.maxit) break;
+            if (enqueued > 4 * p.maxit + 4 * p.check_every) {
+                set_error("pcg_solve_batched: iteration counter stalled");
+                return EB_EHIP;
+            }
+            const int left = p.maxit - B->host.maxiter;
+            const int chunk = left < p.check_every ? left : p.check_every;
+            for (int c = 0; c < chunk; ++c, ++enqueued) {
+                ++k;
+                EB_TRY(benqueue_iteration<V>(H, B, k, s));
+            }
+        }
+        // true residual ||b - A x|| per rhs (FP64)
+        unsigned gfix = 0;
+        const BFine fr = bfine(H, B, false, &gfix);
+        BLAUNCH_N(kb_resid, npl_of(fr), dim3(gfix), fr, B->bvec, B->x, B->tres, B->part_aux);
+        hipLaunchKernelGGL(kb_fin_true, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, (int)gfix, kp);
+        EB_LAUNCH_CHECK();
+        EB_TRY(bpoll(B, s));
+        bool again = false;
+        for (int j = 0; j < BMAX_RHS; ++j) mask[j] = 0;
+        for (int j = 0; j < nrhs; ++j) {
+            const BatchState& h = B->host;
+            const double tr = h.bb[j] > 0.0 ? sqrt(h.rr_true[j] / h.bb[j]) : 0.0;
+            const bool drift = h.status[j] == EB_OK && h.bb[j] > 0.0 && tr > p.tol;
+            if (drift && restarts[j] == 0 && h.iters[j] < p.maxit) {
+                restarts[j] = 1;
+                mask[j] = 1;
+                again = true;
+            }
+        }
+        if (!again) break;
+        // restart the drifted slots from their current iterate
+        EB_TRY(bset_mask(B, mask, s));
+        {
+            // clear their done flags so the start kernels treat them as active
+            BatchState& h = B->host;
+            for (int j = 0; j < nrhs; ++j)
+                if (mask[j]) h.done[j] = 0;
+            EB_HIP(hipMemcpyAsync(st_done(B), h.done, sizeof(h.done), hipMemcpyHostToDevice, s));
+            EB_HIP(hipStreamSynchronize(s));
+        }
+    }
+    int rc = EB_OK;
+    const BatchState& h = B->host;
+    for (int j = 0; j < nrhs; ++j) {
+        pcg_result_t& r = res[j];
+        memset(&r, 0, sizeof(r));
+        r.iterations = h.iters[j];
+        r.restarts = restarts[j];
+        r.levels = H->nlev;
+        r.rel_res_true = h.bb[j] > 0.0 ? sqrt(h.rr_true[j] / h.bb[j]) : 0.0;
+        r.rel_res_recursive = h.bb[j] > 0.0 ? sqrt(h.rr[j] / h.bb[j]) : 0.0;
+        int st = h.status[j];
+        if (st == EB_OK && h.bb[j] > 0.0 && r.rel_res_true > p.tol) st = EB_ENOCONV;
+        r.status = st;
+        if (st != EB_OK && rc == EB_OK) rc = st;
+    }
+    return rc;
+}
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* prm,
+                                 pcg_result_t* res, void* stream) {
+    clear_error();
+    if (!H || !b || !x || !res) {
+        set_error("pcg_solve_batched: null pointer");
+        return EB_EINVAL;
+    }
+    if (nrhs < 1 || nrhs > BMAX_RHS) {
+        set_error("pcg_solve_batched: nrhs = %d outside 1..%d", nrhs, BMAX_RHS);
+        return EB_EINVAL;
+    }
+    pcg_params_t p;
+    p.tol = 1e-8;
+    p.maxit = 1000;
+    p.x0_given = 0;
+    p.check_every = 8;
+    p.precision = EB_PREC_FP64;
+    if (prm) p = *prm;
+    if (!(p.tol > 0.0) || p.maxit < 0 || p.check_every < 1 ||
+        (p.precision != EB_PREC_FP64 && p.precision != EB_PREC_FP32)) {
+        set_error("pcg_solve_batched: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0 or 1)");
+        return EB_EINVAL;
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
+    const GridDims& d = H->d;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    const int64_t nunk = H->n_fine;
+    hipEvent_t e0 = H->ev0, e1 = H->ev1;
+    EB_HIP(hipEventRecord(e0, s));
+    if (nunk == 0) {
+        EB_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn * nrhs, s));
+        EB_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < nrhs; ++j) {
+            memset(&res[j], 0, sizeof(res[j]));
+            res[j].levels = H->nlev;
+        }
+        return EB_OK;
+    }
+    const bool fp32 = p.precision == EB_PREC_FP32;
+    if (fp32) EB_TRY(ensure_fp32(H, s));
+    int kp = 1;
+    while (kp < nrhs) kp <<= 1;
+    EB_TRY(ensure_batch(H, kp, fp32 ? EB_PREC_FP32 : EB_PREC_FP64, s));
+    BatchBufs* B = H->batch;
+    const int lkp = ilog2(kp);
+    const unsigned ug = (unsigned)(((nunk << lkp) + BNT - 1) / BNT);
+    unsigned gdummy = 0;
+    const BFine fl = bfine(H, B, false, &gdummy);
+    hipLaunchKernelGGL(kb_load, dim3(ug), dim3(BNT), 0, s, fl, nunk, lkp, kp, nrhs, nn, H->fine_nodes, H->fine_pad, b,
+                       B->bvec);
+    if (p.x0_given) {
+        hipLaunchKernelGGL(kb_load, dim3(ug), dim3(BNT), 0, s, fl, nunk, lkp, kp, nrhs, nn, H->fine_nodes, H->fine_pad,
+                           x, B->x);
+    } else {
+        EB_HIP(hipMemsetAsync(B->x, 0, sizeof(double) * H->npad * kp, s));
+    }
+    EB_LAUNCH_CHECK();
+    const int rc = fp32 ? batched_run<float>(H, B, nrhs, p, res, s) : batched_run<double>(H, B, nrhs, p, res, s);
+    if (rc == EB_EHIP || rc == EB_EINVAL) return rc;
+    EB_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn * nrhs, s));
+    hipLaunchKernelGGL(kb_store, dim3(ug), dim3(BNT), 0, s, fl, nunk, lkp, kp, nrhs, nn, H->fine_nodes, H->fine_pad,
+                       B->x, x);
+    EB_LAUNCH_CHECK();
+    EB_HIP(hipEventRecord(e1, s));
+    EB_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    EB_HIP(hipEventElapsedTime(&ms, e0, e1));
+    for (int j = 0; j < nrhs; ++j) res[j].solve_ms = ms;
+    if (rc == EB_ENOCONV) set_error("pcg_solve_batched: a right-hand side did not converge within %d iterations",
+                                    p.maxit);
+    if (rc == EB_ENOTSPD) set_error("pcg_solve_batched: non-positive curvature in a right-hand side");
+    if (rc == EB_ENAN) set_error("pcg_solve_batched: NaN or Inf in a right-hand side");
+    return rc;
+}

@@ -56,6 +56,18 @@ enum : int32_t {
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 
+// The GPU hands out workgroups round-robin over its 8 XCDs, each with its own
+// L2.  Renumbering blocks so that XCD x owns the contiguous block range
+// [x G/8, (x+1) G/8) (G a multiple of 8) keeps neighbouring grid rows, which
+// the stencil kernels read from adjacent strips, inside one L2.
+constexpr int NUM_XCD = 8;
+
+__device__ inline int64_t xcd_block() {
+    const int64_t per = gridDim.x / NUM_XCD;
+    if (per == 0 || (gridDim.x % NUM_XCD) != 0) return blockIdx.x;
+    return (int64_t)(blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+}
+
 inline unsigned grid_for(int64_t n, int block = BLOCK) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);

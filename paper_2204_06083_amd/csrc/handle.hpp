@@ -61,6 +61,8 @@ struct Reduction {
     double* aux2 = nullptr;
 };
 
+struct BatchBufs;    // batched solve state (batched.hip)
+
 }  // namespace eb
 
 struct amg_handle {
@@ -113,4 +115,11 @@ struct amg_handle {
     hipStream_t tim_stream = nullptr;
     int64_t tim_launches = 0;
     double tim_ms = 0.0;
+    // batched solves (made on the first pcg_solve_batched call)
+    eb::BatchBufs* batch = nullptr;
 };
+
+namespace eb {
+int ensure_fp32(amg_handle* H, hipStream_t s);   // FP32 hierarchy copies (solve.hip)
+void free_batch(amg_handle* H, hipStream_t s);   // batched.hip
+}  // namespace eb

@@ -33,18 +33,6 @@ constexpr int NT = 512;        // threads per block of the solve kernels
 constexpr int RNT = 256;       // threads per block of the box-per-thread restriction
 constexpr int MAX_PARTS = 1024;
 
-// The GPU hands out workgroups round-robin over its 8 XCDs, each with its own
-// L2.  Renumbering blocks so that XCD x owns the contiguous block range
-// [x G/8, (x+1) G/8) (G a multiple of 8) keeps neighbouring grid rows, which
-// the stencil reads from adjacent strips, inside one L2.
-constexpr int NUM_XCD = 8;
-
-__device__ inline int64_t xcd_block() {
-    const int64_t per = gridDim.x / NUM_XCD;
-    if (per == 0 || (gridDim.x % NUM_XCD) != 0) return blockIdx.x;
-    return (int64_t)(blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
-}
-
 struct FineArgs {
     const int32_t* strips;
     int64_t nstrips;
@@ -989,7 +977,7 @@ static int copy_to_f32(const double* src, int64_t n, float** dst, hipStream_t s)
     return EB_OK;
 }
 
-static int ensure_fp32(amg_handle* H, hipStream_t s) {
+int ensure_fp32(amg_handle* H, hipStream_t s) {
     if (H->fp32_ready) return EB_OK;
     EB_TRY(copy_to_f32(H->diag_p, H->npad, &H->diag_p32, s));
     EB_TRY(dalloc_n(&H->res32, H->npad, s));

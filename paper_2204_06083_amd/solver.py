@@ -229,9 +229,37 @@ class Hierarchy:
                                C.byref(prm), C.byref(res), _stream())
         ok = (L.EB_OK, L.EB_ENOCONV) if allow_noconv else (L.EB_OK,)
         L.check(rc, "pcg_solve", ok=ok)
-        info = dict(iterations=res.iterations, status=res.status, restarts=res.restarts, levels=res.levels,
-                    rel_res_true=res.rel_res_true, solve_ms=res.solve_ms)
-        return x, info
+        return x, _result_dict(res)
+
+    def solve_batched(self, b: torch.Tensor, **kw):
+        """Several right-hand sides in one batched solve (see solve_batched)."""
+        return solve_batched(self, b, **kw)
+
+
+def _result_dict(res):
+    return dict(iterations=res.iterations, status=res.status, restarts=res.restarts, levels=res.levels,
+                rel_res_true=res.rel_res_true, solve_ms=res.solve_ms)
+
+
+def solve_batched(H: "Hierarchy", b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-8,
+                  maxit: int = 1000, check_every: int = 8, out: Optional[torch.Tensor] = None,
+                  allow_noconv: bool = False, precision: str = "fp64"):
+    """pcg_solve_batched: b of shape (nrhs, *grid.shape); returns (x, [info per rhs])."""
+    shape = tuple(H.grid.shape)
+    if b.dim() != len(shape) + 1:
+        raise ValueError("b must have shape (nrhs, *grid.shape)")
+    nrhs = b.shape[0]
+    bp = _field(b, (nrhs,) + shape, torch.float64, "b")
+    x = out if out is not None else torch.empty((nrhs,) + shape, dtype=torch.float64, device=b.device)
+    if x0 is not None:
+        x.copy_(x0)
+    xp = _field(x, (nrhs,) + shape, torch.float64, "x")
+    prm = L.PcgParams(float(tol), int(maxit), 1 if x0 is not None else 0, int(check_every), L.PRECISION[precision])
+    res = (L.PcgResult * max(nrhs, 1))()
+    rc = L.lib().pcg_solve_batched(H.handle, int(nrhs), bp, xp, C.byref(prm), res, _stream())
+    ok = (L.EB_OK, L.EB_ENOCONV) if allow_noconv else (L.EB_OK,)
+    L.check(rc, "pcg_solve_batched", ok=ok)
+    return x, [_result_dict(res[j]) for j in range(nrhs)]
 
 
 def solve_problem(problem, device="cuda", tol=None, coarse_max=256, precision="fp64"):

@@ -1,0 +1,145 @@
+"""Batched PCG (several right-hand sides, one hierarchy, one launch sequence)
+against the oracle's AMG-PCG per right-hand side and against the single
+solve of the library."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import eb_assembly as E
+from oracle import pcg as OP
+from paper_2204_06083_amd import _lib as L
+from paper_2204_06083_amd import solver as S
+from paper_2204_06083_amd import workloads as W
+
+from gpu_common import gpu_system, oracle_system, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _rhs_family(prob, nrhs, seed):
+    """Right-hand sides on the problem's system: b0 = the problem's own RHS,
+    then seeded mixtures of it with random smooth and rough node fields
+    (zero off unknowns, as the library ignores them)."""
+    asm_o, A, b_o, u = oracle_system(prob)
+    rng = np.random.default_rng(seed)
+    fields = []
+    asm_g, _ = gpu_system(prob, u)
+    coords = E.unknown_coords(asm_o)
+    for j in range(nrhs):
+        if j == 0:
+            bj = b_o.copy()
+        else:
+            smooth = np.cos((j + 1) * np.pi * coords[:, 0] / max(coords[:, 0].max(), 1)) * np.sin(
+                (j + 2) * np.pi * coords[:, 1] / max(coords[:, 1].max(), 1))
+            bj = rng.standard_normal(1) * b_o + rng.uniform(0.5, 2.0) * smooth * np.abs(b_o).max() \
+                + 0.1 * rng.standard_normal(b_o.size) * np.abs(b_o).max()
+        fields.append(bj)
+    B = np.zeros((nrhs,) + prob.grid.shape)
+    for j, bj in enumerate(fields):
+        B[j].ravel()[asm_o.nodes] = bj
+    return asm_o, A, fields, asm_g, B
+
+
+CASES = {
+    "disk128_x3": (lambda: W.disk_poisson(128), 1e-10, 3),
+    "star512_x5": (lambda: W.star_poisson(512), 1e-8, 5),
+    "heat512_x8": (lambda: W.star_heat(512, 0), 1e-8, 8),
+    "ell48_x4": (lambda: W.ellipsoid_poisson(48), 1e-8, 4),
+    "disk16_onelevel_x2": (lambda: W.disk_mms(16, radius=0.3), 1e-10, 2),
+    "star300_x1": (lambda: W.star_poisson(300), 1e-8, 1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_against_oracle(name, precision):
+    mk, tol, nrhs = CASES[name]
+    prob = mk()
+    print(f"[gpu] batched {name} {precision} grid={prob.grid.shape}", flush=True)
+    asm_o, A, fields, asm_g, B = _rhs_family(prob, nrhs, seed=11)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    X, infos = H.solve_batched(to_dev(B), tol=tol, precision=precision)
+    X = X.cpu().numpy()
+    coords = E.unknown_coords(asm_o)
+    for j in range(nrhs):
+        ref, _ = OP.amg_pcg(A, coords, fields[j], tol=tol)
+        xj = X[j].ravel()
+        err = rel(xj[asm_o.nodes], ref.x)
+        print(f"  rhs {j}: iters {infos[j]['iterations']} (oracle {ref.iterations}) err {err:.2e}", flush=True)
+        assert infos[j]["status"] == 0
+        assert infos[j]["rel_res_true"] <= tol
+        assert np.linalg.norm(fields[j] - A @ xj[asm_o.nodes]) <= tol * np.linalg.norm(fields[j]) * 1.0001
+        assert not np.any(xj[asm_o.kind.ravel() != 2])
+        if precision == "fp64":
+            assert abs(infos[j]["iterations"] - ref.iterations) <= 1
+            assert err <= 1e-10
+        else:
+            assert infos[j]["iterations"] <= ref.iterations + 3
+            ref12, _ = OP.amg_pcg(A, coords, fields[j], tol=1e-12)
+            assert rel(xj[asm_o.nodes], ref12.x) <= 1e-6
+    H.free()
+
+
+def test_batched_matches_single_solves():
+    prob = W.star_poisson(600)
+    asm_o, A, fields, asm_g, B = _rhs_family(prob, 4, seed=3)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    Bd = to_dev(B)
+    X, infos = H.solve_batched(Bd, tol=1e-8)
+    for j in range(4):
+        xj, ij = H.solve(Bd[j].contiguous(), tol=1e-8)
+        assert abs(ij["iterations"] - infos[j]["iterations"]) <= 1
+        assert rel(X[j].cpu().numpy().ravel(), xj.cpu().numpy().ravel()) <= 1e-10
+    # bitwise reproducible
+    X2, infos2 = H.solve_batched(Bd, tol=1e-8)
+    assert torch.equal(X, X2) and [i["iterations"] for i in infos] == [i["iterations"] for i in infos2]
+    H.free()
+
+
+def test_batched_edge_cases():
+    prob = W.star_poisson(256)
+    asm_o, A, fields, asm_g, B = _rhs_family(prob, 3, seed=5)
+    B[1] = 0.0                                   # a zero right-hand side inside the batch
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    Bd = to_dev(B)
+    X, infos = H.solve_batched(Bd, tol=1e-8)
+    assert infos[1]["iterations"] == 0 and not torch.any(X[1]).item()
+    assert infos[0]["status"] == 0 and infos[2]["status"] == 0
+    # warm start from the solution: nothing to do
+    X3, infos3 = H.solve_batched(Bd, tol=1e-8, x0=X)
+    assert all(i["iterations"] == 0 for i in infos3)
+    # iteration limit reported per right-hand side
+    with pytest.raises(L.EbError) as ei:
+        H.solve_batched(Bd, tol=1e-12, maxit=2)
+    assert ei.value.code == L.EB_ENOCONV
+    Xn, infon = H.solve_batched(Bd, tol=1e-12, maxit=2, allow_noconv=True)
+    assert infon[0]["status"] == L.EB_ENOCONV and infon[0]["iterations"] == 2
+    # slot count limits
+    big = torch.zeros((65,) + prob.grid.shape, dtype=torch.float64, device=Bd.device)
+    with pytest.raises(L.EbError) as ei:
+        H.solve_batched(big, tol=1e-8)
+    assert ei.value.code == L.EB_EINVAL
+    H.free()
+
+
+def test_batched_heat1024_64rhs():
+    """The heat workload at full size: 64 seeded initial conditions, one batch."""
+    print("[gpu] batched heat1024 x64", flush=True)
+    probs = [W.star_heat(1024, j) for j in range(64)]
+    p0 = probs[0]
+    asm_g, _ = gpu_system(p0)
+    B = torch.stack([S.assemble_rhs(asm_g, to_dev(p.f), torch.zeros(asm_g.n_cuts, dtype=torch.float64,
+                                                                      device=asm_g.kind.device)) for p in probs])
+    H = S.Hierarchy(p0.grid, asm_g.kind, asm_g.a, p0.sigma)
+    for precision in ("fp64", "fp32"):
+        X, infos = H.solve_batched(B.contiguous(), tol=1e-8, precision=precision)
+        assert all(i["status"] == 0 and i["rel_res_true"] <= 1e-8 for i in infos)
+        for j in (0, 17, 63):
+            xj, ij = H.solve(B[j].contiguous(), tol=1e-8, precision=precision)
+            assert abs(ij["iterations"] - infos[j]["iterations"]) <= 1
+            assert rel(X[j].cpu().numpy().ravel(), xj.cpu().numpy().ravel()) <= (1e-10 if precision == "fp64" else 1e-6)
+    # oracle operator residual for a sample
+    asm_o, A, b_o, _ = oracle_system(probs[5])
+    x5 = X[5].cpu().numpy().ravel()[asm_o.nodes]
+    assert np.linalg.norm(b_o - A @ x5) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
+    H.free()

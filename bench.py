@@ -16,7 +16,10 @@ measured with HIP events on the library's stream inside the timed steps.
 `solve_roofline` applies the whole-solve byte model to the measured solve
 time.  `mixed` repeats the same steps with the single-precision V-cycle
 (FP64 outer CG) and reports its difference from the FP64 solution.
-`cpu_baseline` times the CPU oracle on full steps of the same workload.
+`batched` times one backward-Euler heat step on the star 1024^2 for 64 seeded
+initial conditions as one batched solve (pcg_solve_batched) and as 64 single
+solves on the same hierarchy.  `cpu_baseline` times the CPU oracle on full
+steps of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -78,6 +81,55 @@ def solve_model_bytes(H, precision):
     return total
 
 
+def batched_heat(n=1024, nrhs=64, reps=3):
+    """One backward-Euler step of the heat workload for nrhs seeded initial
+    conditions: one batched solve vs nrhs single solves (same hierarchy)."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+    g = W.unit_box_grid(2, n)
+    dt = g.h
+    psi = torch.as_tensor(W.psi_star(g), device=dev)
+    asm = S.assemble_diag(g, psi)
+    zero = torch.zeros(asm.n_cuts, dtype=torch.float64, device=dev)
+    u0 = W.heat_initial_batch(g, range(nrhs), dev)
+    B = torch.stack([S.assemble_rhs(asm, (u0[j] / dt).contiguous(), zero) for j in range(nrhs)]).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = S.Hierarchy(g, asm.kind, asm.a, 1.0 / dt)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    out = {"workload": f"star2d_{n}_heat_backward_euler_dt_h_{nrhs}rhs", "n_unknowns": asm.n_unknowns, "nrhs": nrhs,
+           "setup_ms": setup_ms}
+    for prec in ("fp32", "fp64"):
+        H.solve_batched(B, tol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            X, infos = H.solve_batched(B, tol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        its = [i["iterations"] for i in infos]
+        H.solve(B[0].contiguous(), tol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sits = 0
+        for j in range(nrhs):
+            _, i = H.solve(B[j].contiguous(), tol=1e-8, precision=prec)
+            sits += i["iterations"]
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        out[prec] = {"batch_ms": tb * 1e3, "solves_per_s": nrhs / tb,
+                     "unknowns_iters_per_s": asm.n_unknowns * sum(its) / tb,
+                     "iterations_min_max": [min(its), max(its)],
+                     "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+                     "sequential_ms": ts * 1e3, "sequential_solves_per_s": nrhs / ts,
+                     "speedup_vs_sequential": ts / tb}
+    H.free()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +137,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel", default="pcg_xr_down", choices=sorted(KERNEL_BYTES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched heat-step measurement")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -429,6 +482,8 @@ def main():
     }
     if args.phases:
         out["phases_ms"] = {k: sum(v) / len(v) for k, v in phases.items() if v}
+    if not args.no_batched:
+        out["batched"] = batched_heat()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

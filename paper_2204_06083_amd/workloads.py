@@ -198,6 +198,30 @@ def heat_initial(grid: Grid, rhs_id: int, kmax: int = 8) -> np.ndarray:
     return u0
 
 
+def heat_coefficients(rhs_id: int, kmax: int = 8) -> np.ndarray:
+    """The a_k of heat_initial for one rhs_id, as a [kx-1, ky-1] array (same draws, same order)."""
+    rng = np.random.default_rng(SEED_BASE + rhs_id)
+    a = np.zeros((kmax, kmax))
+    for kx in range(1, kmax + 1):
+        for ky in range(1, kmax + 1):
+            a[kx - 1, ky - 1] = rng.normal(0.0, 1.0 / math.sqrt(kx * kx + ky * ky))
+    return a
+
+
+def heat_initial_batch(grid: Grid, rhs_ids, device, kmax: int = 8):
+    """heat_initial for several rhs_ids at once as a torch tensor (nrhs, ny+1, nx+1) on
+    `device`: u0 = S_y A^T S_x^T per right-hand side (separable sine modes), FP64.
+    Equal to heat_initial up to summation order."""
+    import torch
+    x = torch.as_tensor(grid.axis_coords(0), dtype=torch.float64, device=device)
+    y = torch.as_tensor(grid.axis_coords(1), dtype=torch.float64, device=device)
+    k = torch.arange(1, kmax + 1, dtype=torch.float64, device=device)
+    sx = torch.sin(math.pi * x[:, None] * k[None, :])          # (nx+1, K)
+    sy = torch.sin(math.pi * y[:, None] * k[None, :])          # (ny+1, K)
+    A = torch.as_tensor(np.stack([heat_coefficients(r, kmax) for r in rhs_ids]), device=device)  # (R, kx, ky)
+    return torch.matmul(torch.matmul(sy, A.transpose(1, 2).contiguous()), sx.t().contiguous())
+
+
 def star_heat(n: int = 1024, rhs_id: int = 0) -> Problem:
     """One backward-Euler heat step on the star: (A + I/dt) u1 = u0/dt, dt = h, u_D = 0."""
     g = unit_box_grid(2, n)

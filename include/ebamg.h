@@ -206,6 +206,70 @@ int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
  * hierarchy's values (kept until amg_free).  Synchronises `stream`.          */
 int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned fine-level smoother (an extension of the method: the paper fixes
+ * no smoother, Sec. 3 preamble / Algorithm 2 step 4).  A convolutional
+ * network (3 layers, 3^d taps, 16 channels, zero padding; bfloat16 weights,
+ * FP32 arithmetic) maps two node features, a_k / (2d) at computational points
+ * and clip(psi / h, -3, 3) / 3, to a Jacobi weight per computational point,
+ * omega_k = omega0 (1 + tanh(o_k) / 2).  The fine level's pre- and
+ * post-smoothing then use omega_k / A_kk; the prolongator and the coarser
+ * levels are unchanged.  Parameters: one FP32 array (see eb_smoother_net_size)
+ * in the order W1 [16][2][T], b1 [16], W2 [16][16][T], b2 [16], W3 [1][16][T],
+ * b3 [1], T = 3^d taps in lexicographic order, x fastest.
+ * ------------------------------------------------------------------------ */
+
+/* Number of FP32 parameters of the network for dim 2 or 3 (-1 otherwise).     */
+int64_t eb_smoother_net_size(int32_t dim);
+
+/* Forward pass over the node grid.  kind, a, psi: node fields as produced by
+ * eb_assemble_diag.  z1, z2 [out]: pre-activation fields of layers 1 and 2
+ * (nodes x 16 FP32, node-major, channels fastest; kept for the backward pass);
+ * o [out]: the last layer (nodes FP32); omega [out]: node field of the
+ * weights (0 off computational points).  Asynchronous.                       */
+int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,
+                        const float* params, double omega0, float* z1, float* z2, float* o, double* omega,
+                        void* stream);
+
+/* Gradient of a loss with respect to the parameters, given dL/domega (node
+ * field; only computational points are read) and the forward pass's z1, z2,
+ * o.  scratch: eb_smoother_scratch_floats(g) FP32 values of device memory;
+ * grads [out]: eb_smoother_net_size(dim) FP32 values.  Weight gradients are
+ * summed in a fixed order (deterministic).  Asynchronous.                     */
+int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,
+                         const float* params, double omega0, const float* z1, const float* z2, const float* o,
+                         const double* grad_omega, float* scratch, float* grads, void* stream);
+int64_t eb_smoother_scratch_floats(const eb_grid_t* g);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * t >= 1) on n FP32 parameters; m, v are the moment arrays (zero at t = 1).  */
+int eb_adam_step(float* params, const float* grads, float* m, float* v, int64_t n, int32_t t, float lr,
+                 void* stream);
+
+/* Use per-point weights omega (node field, positive and finite at every
+ * computational point; EB_EINVAL otherwise) in the fine smoother of every
+ * later pcg_solve / amg_vcycle_apply(_fp32) on H, until amg_clear_fine_weights.
+ * No effect on a one-level hierarchy.  Synchronises `stream`.                 */
+int amg_set_fine_weights(amg_handle_t* H, const double* omega, void* stream);
+int amg_clear_fine_weights(amg_handle_t* H);
+
+/* Training samples: for each of the m node fields xi_j (back to back), apply
+ * `sweeps` times e <- (e - M A e) / ||e - M A e||_2 with the current V-cycle M
+ * (fine weights if set) and write e_j (node fields, 0 off computational
+ * points).  Synchronises `stream`.                                            */
+int amg_smoother_samples(amg_handle_t* H, int32_t m, int32_t sweeps, const double* xi, double* e, void* stream);
+
+/* Loss L = mean_j (e_j'^T A e_j') / (2 e_j^T A e_j), e' = e - M A e, of the
+ * current V-cycle (fine weights if set) on the m node fields e_j, and its
+ * gradient with respect to the fine weights omega_k (node field grad_omega,
+ * 0 off computational points), by the adjoint of the cycle:
+ *   g = -A e' / (e^T A e), u = g - A W g, v = u - A P E_c R u,
+ *   dL/domega_k = (g_k t2_k + v_k r_k) / A_kk,
+ * r = A e, t2 = r - A z2, z2 the prolongated pre-smoothed iterate, E_c the
+ * coarse cycle.  loss is a host pointer.  Synchronises `stream`.              */
+int amg_smoother_loss_grad(amg_handle_t* H, int32_t m, const double* e, double* loss, double* grad_omega,
+                           void* stream);
+
 /* Hierarchy introspection (host calls; pointers as described above).          */
 int amg_num_levels(const amg_handle_t* H);
 int amg_level_info(const amg_handle_t* H, int level, amg_level_info_t* out);

@@ -20,7 +20,9 @@ EXPORTS = [
     "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
     "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
-    "eb_release_cached_memory",
+    "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
+    "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
+    "amg_smoother_samples", "amg_smoother_loss_grad",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -101,12 +103,25 @@ def lib():
     L.eb_timing_read.argtypes = [vp, C.POINTER(i64), C.POINTER(dbl)]
     L.eb_release_cached_memory.argtypes = []
     L.eb_release_cached_memory.restype = None
+    L.eb_smoother_net_size.argtypes = [i32]
+    L.eb_smoother_net_size.restype = i64
+    L.eb_smoother_forward.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp]
+    L.eb_smoother_backward.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
+    L.eb_smoother_scratch_floats.argtypes = [C.POINTER(EbGrid)]
+    L.eb_smoother_scratch_floats.restype = i64
+    L.eb_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, vp]
+    L.amg_set_fine_weights.argtypes = [vp, vp, vp]
+    L.amg_clear_fine_weights.argtypes = [vp]
+    L.amg_smoother_samples.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.amg_smoother_loss_grad.argtypes = [vp, i32, vp, C.POINTER(dbl), vp, vp]
     L.eb_strerror.argtypes = [C.c_int]
     L.eb_strerror.restype = C.c_char_p
     L.eb_last_error.restype = C.c_char_p
     for name in ("eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
                  "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "eb_abi_version",
-                 "eb_timing_select", "eb_timing_read"):
+                 "eb_timing_select", "eb_timing_read", "eb_smoother_forward", "eb_smoother_backward",
+                 "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights", "amg_smoother_samples",
+                 "amg_smoother_loss_grad"):
         getattr(L, name).restype = i32
     _lib = L
     return L

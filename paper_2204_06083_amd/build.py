@@ -31,6 +31,7 @@ SOURCES = {
     "amg_setup.hip": ["-ffp-contract=off"],
     "solve.hip": [],
     "batched.hip": [],
+    "learned.hip": [],
 }
 
 COMMON = [

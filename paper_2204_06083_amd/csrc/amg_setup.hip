@@ -1278,7 +1278,8 @@ int free_handle_memory(amg_handle* H) {
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
     void* ptrs[] = {H->unk_off_tmp, H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
-                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->res32, H->zt32, H->z32};
+                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->res32, H->zt32, H->z32,
+                    H->wf, H->wf32};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;
     H->tim_ev = nullptr;    // process-wide event pool, not owned

@@ -95,6 +95,10 @@ struct amg_handle {
     float* zt32 = nullptr;
     float* z32 = nullptr;
     int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)
+    // per-point fine smoother weights omega_k / d_k (padded; 0 off unknowns)
+    int wf_on = 0;
+    double* wf = nullptr;
+    float* wf32 = nullptr;
     // PCG state (padded node fields)
     double* x = nullptr; double* z = nullptr;
     double* rr[2] = {nullptr, nullptr};   // residual, alternating between iterations

@@ -1,0 +1,448 @@
+// Learned fine-level smoother weights: a three-layer convolutional network
+// (3^d taps, 16 channels, zero padding) maps two node features to a
+// per-point Jacobi weight omega_k = omega_0 (1 + tanh(o_k) / 2).
+//
+// This extends the method (the paper fixes no smoother: Sec. 3 preamble,
+// Algorithm 2 step 4 use an AMG package); the weights let the points next to
+// the boundary, whose diagonal the line-by-line treatment changes
+// (Sec. 2.1.1), be smoothed with weights of their own.
+//
+//   features  f0 = a_k / (2d) at computational points (0 elsewhere),
+//             f1 = clip(psi / h, -3, 3) / 3
+//   layer 1   z1 = conv(f;  W1, b1)   2 -> 16,  y1 = relu(z1)
+//   layer 2   z2 = conv(y1; W2, b2)  16 -> 16,  y2 = relu(z2)
+//   layer 3   o  = conv(y2; W3, b3)  16 -> 1
+//   conv(x; W, b)[c, p] = b[c] + sum_{c', t} W[c, c', t] x[c', p + off_t],
+//   taps off_t in {-1, 0, 1}^d lexicographic (x fastest).
+//
+// Weights are used rounded to bfloat16 (nearest, ties to even); products and
+// sums are FP32.  Parameters are one FP32 array in the order
+// W1 [16][2][T], b1 [16], W2 [16][16][T], b2 [16], W3 [1][16][T], b3 [1].
+// Activations are node-major, channels fastest: z[node * 16 + c].
+#include <math.h>
+
+#include "common.hpp"
+
+namespace eb {
+
+constexpr int NCH = 16;
+constexpr int LNT = 256;
+
+struct NetDims {
+    int dim, nx, ny, nz, T;
+    int64_t sy, sz, n;        // dense strides and node count
+    double h, omega0;
+};
+
+struct NetOff {
+    int64_t w1, b1, w2, b2, w3, b3, total;
+};
+
+__host__ __device__ inline NetOff net_offsets(int T) {
+    NetOff o;
+    o.w1 = 0;
+    o.b1 = o.w1 + (int64_t)NCH * 2 * T;
+    o.w2 = o.b1 + NCH;
+    o.b2 = o.w2 + (int64_t)NCH * NCH * T;
+    o.w3 = o.b2 + NCH;
+    o.b3 = o.w3 + (int64_t)NCH * T;
+    o.total = o.b3 + 1;
+    return o;
+}
+
+// bfloat16 rounding (nearest, ties to even) of an FP32 value, kept in FP32.
+__device__ inline float bf16r(float x) {
+    uint32_t u = __float_as_uint(x);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+    return __uint_as_float(u);
+}
+
+// Neighbour p + off_t, or -1 outside the node grid.
+__device__ inline int64_t tap_node(const NetDims& d, int i, int j, int k, int t) {
+    int dx, dy, dz;
+    if (d.dim == 2) {
+        dz = 0;
+        dy = t / 3 - 1;
+        dx = t % 3 - 1;
+    } else {
+        dz = t / 9 - 1;
+        dy = (t / 3) % 3 - 1;
+        dx = t % 3 - 1;
+    }
+    const int ii = i + dx, jj = j + dy, kk = k + dz;
+    if (ii < 0 || ii >= d.nx || jj < 0 || jj >= d.ny || kk < 0 || kk >= d.nz) return -1;
+    return (int64_t)ii + d.sy * jj + d.sz * kk;
+}
+
+__device__ inline void node_ijk(const NetDims& d, int64_t p, int& i, int& j, int& k) {
+    i = (int)(p % d.nx);
+    const int64_t r = p / d.nx;
+    j = (int)(r % d.ny);
+    k = (int)(r / d.ny);
+}
+
+__device__ inline void node_features(const NetDims& d, const int8_t* __restrict__ kind, const double* __restrict__ a,
+                                     const double* __restrict__ psi, int64_t q, float& f0, float& f1) {
+    f0 = kind[q] == 2 ? (float)(a[q] / (2.0 * d.dim)) : 0.0f;
+    const double s = psi[q] / d.h;
+    f1 = (float)(fmin(fmax(s, -3.0), 3.0) / 3.0);
+}
+
+// Parameters to LDS, weights rounded to bfloat16.
+__device__ inline void load_params(const float* __restrict__ params, float* __restrict__ lp, int64_t n,
+                                   const NetOff& o) {
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+        const bool is_w = (e < o.b1) || (e >= o.w2 && e < o.b2) || (e >= o.w3 && e < o.b3);
+        lp[e] = is_w ? bf16r(params[e]) : params[e];
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- forward
+__global__ void __launch_bounds__(LNT) k_net_l1(NetDims d, const int8_t* __restrict__ kind,
+                                                const double* __restrict__ a, const double* __restrict__ psi,
+                                                const float* __restrict__ params, float* __restrict__ z1) {
+    extern __shared__ float lp[];
+    const NetOff o = net_offsets(d.T);
+    load_params(params, lp, o.w2, o);            // W1, b1
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    int i, j, k;
+    node_ijk(d, p, i, j, k);
+    float acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = lp[o.b1 + c];
+    for (int t = 0; t < d.T; ++t) {
+        const int64_t q = tap_node(d, i, j, k, t);
+        if (q < 0) continue;
+        float f0, f1;
+        node_features(d, kind, a, psi, q, f0, f1);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[c] += lp[o.w1 + ((int64_t)c * 2 + 0) * d.T + t] * f0 +
+                                               lp[o.w1 + ((int64_t)c * 2 + 1) * d.T + t] * f1;
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) z1[p * NCH + c] = acc[c];
+}
+
+__global__ void __launch_bounds__(LNT) k_net_l2(NetDims d, const float* __restrict__ params,
+                                                const float* __restrict__ z1, float* __restrict__ z2) {
+    extern __shared__ float lp[];
+    const NetOff o = net_offsets(d.T);
+    load_params(params, lp, o.w3, o);            // up to b2
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    int i, j, k;
+    node_ijk(d, p, i, j, k);
+    float acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = lp[o.b2 + c];
+    for (int t = 0; t < d.T; ++t) {
+        const int64_t q = tap_node(d, i, j, k, t);
+        if (q < 0) continue;
+        float y[NCH];
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci) y[ci] = fmaxf(z1[q * NCH + ci], 0.0f);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            float s = 0.0f;
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) s += lp[o.w2 + ((int64_t)c * NCH + ci) * d.T + t] * y[ci];
+            acc[c] += s;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) z2[p * NCH + c] = acc[c];
+}
+
+// Last layer, the weight omega = omega_0 (1 + tanh(o) / 2) at computational
+// points (0 elsewhere).
+__global__ void __launch_bounds__(LNT) k_net_l3(NetDims d, const int8_t* __restrict__ kind,
+                                                const float* __restrict__ params, const float* __restrict__ z2,
+                                                float* __restrict__ out_o, double* __restrict__ omega) {
+    extern __shared__ float lp[];
+    const NetOff o = net_offsets(d.T);
+    load_params(params, lp, o.total, o);
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    int i, j, k;
+    node_ijk(d, p, i, j, k);
+    float acc = lp[o.b3];
+    for (int t = 0; t < d.T; ++t) {
+        const int64_t q = tap_node(d, i, j, k, t);
+        if (q < 0) continue;
+        float s = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) s += lp[o.w3 + (int64_t)c * d.T + t] * fmaxf(z2[q * NCH + c], 0.0f);
+        acc += s;
+    }
+    out_o[p] = acc;
+    omega[p] = kind[p] == 2 ? d.omega0 * (1.0 + 0.5 * tanh((double)acc)) : 0.0;
+}
+
+// ---------------------------------------------------------------- backward
+// go = dL/do = dL/domega * omega_0 (1 - tanh(o)^2) / 2 at computational points.
+__global__ void __launch_bounds__(LNT) k_net_go(NetDims d, const int8_t* __restrict__ kind,
+                                                const float* __restrict__ o, const double* __restrict__ gomega,
+                                                float* __restrict__ go) {
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    if (kind[p] != 2) {
+        go[p] = 0.0f;
+        return;
+    }
+    const double th = tanh((double)o[p]);
+    go[p] = (float)(gomega[p] * d.omega0 * 0.5 * (1.0 - th * th));
+}
+
+// gz2 = (sum_t W3[0, c, t] go[p - off_t]) * (z2 > 0)
+__global__ void __launch_bounds__(LNT) k_net_b3(NetDims d, const float* __restrict__ params,
+                                                const float* __restrict__ go, const float* __restrict__ z2,
+                                                float* __restrict__ gz2) {
+    extern __shared__ float lp[];
+    const NetOff o = net_offsets(d.T);
+    load_params(params, lp, o.total, o);
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    int i, j, k;
+    node_ijk(d, p, i, j, k);
+    float acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0.0f;
+    for (int t = 0; t < d.T; ++t) {
+        const int64_t q = tap_node(d, i, j, k, d.T - 1 - t);   // p - off_t (taps are symmetric)
+        if (q < 0) continue;
+        const float g = go[q];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[c] += lp[o.w3 + (int64_t)c * d.T + t] * g;
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) gz2[p * NCH + c] = z2[p * NCH + c] > 0.0f ? acc[c] : 0.0f;
+}
+
+// gz1[ci] = (sum_{t, c} W2[c, ci, t] gz2[p - off_t, c]) * (z1 > 0)
+__global__ void __launch_bounds__(LNT) k_net_b2(NetDims d, const float* __restrict__ params,
+                                                const float* __restrict__ gz2, const float* __restrict__ z1,
+                                                float* __restrict__ gz1) {
+    extern __shared__ float lp[];
+    const NetOff o = net_offsets(d.T);
+    load_params(params, lp, o.w3, o);
+    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (p >= d.n) return;
+    int i, j, k;
+    node_ijk(d, p, i, j, k);
+    float acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0.0f;
+    for (int t = 0; t < d.T; ++t) {
+        const int64_t q = tap_node(d, i, j, k, d.T - 1 - t);
+        if (q < 0) continue;
+        float g[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) g[c] = gz2[q * NCH + c];
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci) {
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) s += lp[o.w2 + ((int64_t)c * NCH + ci) * d.T + t] * g[c];
+            acc[ci] += s;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) gz1[p * NCH + c] = z1[p * NCH + c] > 0.0f ? acc[c] : 0.0f;
+}
+
+// Weight gradients of one layer, as per-block partials:
+//   gW[co, ci, t] = sum_p G[p, co] X[p + off_t, ci],  gb[co] = sum_p G[p, co]
+// X = relu(Z) (layers 2, 3) or the features (layer 1).  Each block owns a
+// contiguous node range; thread e owns entries e, e + LNT, ... and sums over
+// the range in node order.  part[block][CO*CI*T + CO].
+template <int CO, int CI, int XMODE>   // XMODE 0: relu(z) rows of CI, 1: features
+__global__ void __launch_bounds__(LNT) k_net_wgrad(NetDims d, const float* __restrict__ G,
+                                                   const float* __restrict__ Z, const int8_t* __restrict__ kind,
+                                                   const double* __restrict__ a, const double* __restrict__ psi,
+                                                   int64_t per_block, float* __restrict__ part) {
+    const int ne = CO * CI * d.T + CO;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min(p0 + per_block, d.n);
+    for (int e = threadIdx.x; e < ne; e += LNT) {
+        float s = 0.0f;
+        if (e < CO * CI * d.T) {
+            const int co = e / (CI * d.T);
+            const int ci = (e / d.T) % CI;
+            const int t = e % d.T;
+            for (int64_t p = p0; p < p1; ++p) {
+                const float g = G[p * CO + co];
+                if (g == 0.0f) continue;
+                int i, j, k;
+                node_ijk(d, p, i, j, k);
+                const int64_t q = tap_node(d, i, j, k, t);
+                if (q < 0) continue;
+                float x;
+                if (XMODE == 0) {
+                    x = fmaxf(Z[q * CI + ci], 0.0f);
+                } else {
+                    float f0, f1;
+                    node_features(d, kind, a, psi, q, f0, f1);
+                    x = ci == 0 ? f0 : f1;
+                }
+                s += g * x;
+            }
+        } else {
+            const int co = e - CO * CI * d.T;
+            for (int64_t p = p0; p < p1; ++p) s += G[p * CO + co];
+        }
+        part[(int64_t)blockIdx.x * ne + e] = s;
+    }
+}
+
+// Sum of the block partials in block order into the gradient array.
+__global__ void __launch_bounds__(LNT) k_net_wsum(const float* __restrict__ part, int nblk, int ne,
+                                                  float* __restrict__ out_w, float* __restrict__ out_b, int nw) {
+    const int e = blockIdx.x * LNT + threadIdx.x;
+    if (e >= ne) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ne + e];
+    if (e < nw) out_w[e] = (float)s;
+    else out_b[e - nw] = (float)s;
+}
+
+// Adam on FP32 parameters (bias-corrected moments).
+__global__ void __launch_bounds__(LNT) k_adam(float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n, int t, float lr,
+                                              float b1, float b2, float eps) {
+    const int64_t e = (int64_t)blockIdx.x * LNT + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.0f - b1) * gg;
+    const float vv = b2 * v[e] + (1.0f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    const float mh = mm / (1.0f - powf(b1, (float)t));
+    const float vh = vv / (1.0f - powf(b2, (float)t));
+    w[e] = w[e] - lr * mh / (sqrtf(vh) + eps);
+}
+
+static int net_dims(const eb_grid_t* g, double omega0, NetDims* nd) {
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    nd->dim = d.dim;
+    nd->nx = d.nx;
+    nd->ny = d.ny;
+    nd->nz = d.nz;
+    nd->T = d.dim == 3 ? 27 : 9;
+    nd->sy = d.sy;
+    nd->sz = d.sz;
+    nd->n = (int64_t)d.nx * d.ny * d.nz;
+    nd->h = d.h;
+    nd->omega0 = omega0;
+    return EB_OK;
+}
+
+constexpr int WGRAD_BLOCKS = 1024;
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int64_t eb_smoother_net_size(int32_t dim) {
+    if (dim != 2 && dim != 3) return -1;
+    return net_offsets(dim == 3 ? 27 : 9).total;
+}
+
+extern "C" int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,
+                                   const float* params, double omega0, float* z1, float* z2, float* o,
+                                   double* omega, void* stream) {
+    clear_error();
+    if (!g || !kind || !a || !psi || !params || !z1 || !z2 || !o || !omega) {
+        set_error("eb_smoother_forward: null pointer");
+        return EB_EINVAL;
+    }
+    if (!(omega0 > 0.0)) {
+        set_error("eb_smoother_forward: omega0 must be positive");
+        return EB_EINVAL;
+    }
+    NetDims d;
+    EB_TRY(net_dims(g, omega0, &d));
+    hipStream_t s = (hipStream_t)stream;
+    const NetOff off = net_offsets(d.T);
+    const unsigned gr = grid_for(d.n, LNT);
+    hipLaunchKernelGGL(k_net_l1, dim3(gr), dim3(LNT), sizeof(float) * off.w2, s, d, kind, a, psi, params, z1);
+    hipLaunchKernelGGL(k_net_l2, dim3(gr), dim3(LNT), sizeof(float) * off.w3, s, d, params, (const float*)z1, z2);
+    hipLaunchKernelGGL(k_net_l3, dim3(gr), dim3(LNT), sizeof(float) * off.total, s, d, kind, params,
+                       (const float*)z2, o, omega);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+extern "C" int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,
+                                    const float* params, double omega0, const float* z1, const float* z2,
+                                    const float* o, const double* grad_omega, float* scratch, float* grads,
+                                    void* stream) {
+    clear_error();
+    if (!g || !kind || !a || !psi || !params || !z1 || !z2 || !o || !grad_omega || !scratch || !grads) {
+        set_error("eb_smoother_backward: null pointer");
+        return EB_EINVAL;
+    }
+    NetDims d;
+    EB_TRY(net_dims(g, omega0, &d));
+    hipStream_t s = (hipStream_t)stream;
+    const NetOff off = net_offsets(d.T);
+    const unsigned gr = grid_for(d.n, LNT);
+    // scratch: go [n], gz2 [16 n], gz1 [16 n], partials [WGRAD_BLOCKS * (16*16*T + 16)]
+    float* go = scratch;
+    float* gz2 = go + d.n;
+    float* gz1 = gz2 + d.n * NCH;
+    float* part = gz1 + d.n * NCH;
+    hipLaunchKernelGGL(k_net_go, dim3(gr), dim3(LNT), 0, s, d, kind, o, grad_omega, go);
+    hipLaunchKernelGGL(k_net_b3, dim3(gr), dim3(LNT), sizeof(float) * off.total, s, d, params, (const float*)go, z2,
+                       gz2);
+    hipLaunchKernelGGL(k_net_b2, dim3(gr), dim3(LNT), sizeof(float) * off.w3, s, d, params, (const float*)gz2, z1,
+                       gz1);
+    EB_LAUNCH_CHECK();
+    const int64_t per = (d.n + WGRAD_BLOCKS - 1) / WGRAD_BLOCKS;
+    // layer 3: CO = 1, CI = 16, X = relu(z2)
+    {
+        const int ne = 1 * NCH * d.T + 1;
+        hipLaunchKernelGGL((k_net_wgrad<1, NCH, 0>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)go, z2,
+                           kind, a, psi, per, part);
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+                           ne, grads + off.w3, grads + off.b3, NCH * d.T);
+    }
+    {
+        const int ne = NCH * NCH * d.T + NCH;
+        hipLaunchKernelGGL((k_net_wgrad<NCH, NCH, 0>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1,
+                           kind, a, psi, per, part);
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+                           ne, grads + off.w2, grads + off.b2, NCH * NCH * d.T);
+    }
+    {
+        const int ne = NCH * 2 * d.T + NCH;
+        hipLaunchKernelGGL((k_net_wgrad<NCH, 2, 1>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz1,
+                           (const float*)nullptr, kind, a, psi, per, part);
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+                           ne, grads + off.w1, grads + off.b1, NCH * 2 * d.T);
+    }
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+extern "C" int64_t eb_smoother_scratch_floats(const eb_grid_t* g) {
+    NetDims d;
+    if (!g || net_dims(g, 1.0, &d) != EB_OK) return -1;
+    return d.n * (1 + 2 * NCH) + (int64_t)WGRAD_BLOCKS * (NCH * NCH * d.T + NCH);
+}
+
+extern "C" int eb_adam_step(float* params, const float* grads, float* m, float* v, int64_t n, int32_t t, float lr,
+                            void* stream) {
+    clear_error();
+    if (!params || !grads || !m || !v || n < 0 || t < 1 || !(lr > 0.0f)) {
+        set_error("eb_adam_step: invalid arguments");
+        return EB_EINVAL;
+    }
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, LNT)), dim3(LNT), 0, (hipStream_t)stream, params, grads, m, v, n,
+                       (int)t, lr, 0.9f, 0.999f, 1e-8f);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}

@@ -43,12 +43,17 @@ struct FineArgs {
     double s;             // 1/h^2
     const double* diag;   // padded, 0 off unknowns
     const float* diag32;  // the same in FP32 (single-precision V-cycle only)
+    const double* wf;     // per-point smoother weights omega_k / d_k (learned weights; 0 off unknowns)
+    const float* wf32;
 };
 
 // Diagonal in the precision of the V-cycle.
 template <class V> __device__ inline const V* vdiag(const FineArgs& f);
 template <> __device__ inline const double* vdiag<double>(const FineArgs& f) { return f.diag; }
 template <> __device__ inline const float* vdiag<float>(const FineArgs& f) { return f.diag32; }
+template <class V> __device__ inline const V* vwf(const FineArgs& f);
+template <> __device__ inline const double* vwf<double>(const FineArgs& f) { return f.wf; }
+template <> __device__ inline const float* vwf<float>(const FineArgs& f) { return f.wf32; }
 
 // Each block sweeps its own contiguous range of strips, NT / strip_w strips
 // at a time; p is the padded node index of this thread's node.
@@ -209,7 +214,9 @@ __device__ inline bool converged_or_failed(const double* __restrict__ part_rr, i
 // Pre-smoothing and residual: z1 = omega r / d (not stored), res = r - A z1,
 // formed from the FP64 residual and stored in the V-cycle precision.
 // With `check`, first test convergence of the iterate that produced r.
-template <class V>
+// LW: the smoother uses the per-point weights f.wf (z1 = wf r) instead of
+// omega / d; the prolongator always keeps omega.
+template <class V, bool LW>
 __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, const double* __restrict__ r,
                                                   V* __restrict__ res, PcgScalars* sc, int check,
                                                   const double* __restrict__ part_rr, int np) {
@@ -218,9 +225,17 @@ __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, cons
     FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
-            const double z1 = omega * r[p] / d;
-            const double nb = omega * nbr_sum_scaled(r, f.diag, p, f);
-            res[p] = (V)(r[p] - (d * z1 - f.s * nb));
+            if (LW) {
+                const double z1 = f.wf[p] * r[p];
+                double nb = f.wf[p - 1] * r[p - 1] + f.wf[p + 1] * r[p + 1];
+                nb += f.wf[p - f.sy] * r[p - f.sy] + f.wf[p + f.sy] * r[p + f.sy];
+                if (f.dim == 3) nb += f.wf[p - f.sz] * r[p - f.sz] + f.wf[p + f.sz] * r[p + f.sz];
+                res[p] = (V)(r[p] - (d * z1 - f.s * nb));
+            } else {
+                const double z1 = omega * r[p] / d;
+                const double nb = omega * nbr_sum_scaled(r, f.diag, p, f);
+                res[p] = (V)(r[p] - (d * z1 - f.s * nb));
+            }
         }
     }
 }
@@ -295,7 +310,7 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
 //   from r_in and q (r_in and r_out are different buffers).
 // The CG part is FP64; res is stored in the V-cycle precision.
 // The convergence test on ||r_out||^2 happens in the next kernel.
-template <class V>
+template <class V, bool LW>
 __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
                                                     double* __restrict__ rout, const double* __restrict__ pv,
                                                     const double* __restrict__ q, V* __restrict__ res,
@@ -325,16 +340,29 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
             const double rn = rin[p] - alpha * q[p];
             rout[p] = rn;
             part += rn * rn;
-            double nb = safe_div(rin[p - 1] - alpha * q[p - 1], f.diag[p - 1]);
-            nb += safe_div(rin[p + 1] - alpha * q[p + 1], f.diag[p + 1]);
-            nb += safe_div(rin[p - f.sy] - alpha * q[p - f.sy], f.diag[p - f.sy]);
-            nb += safe_div(rin[p + f.sy] - alpha * q[p + f.sy], f.diag[p + f.sy]);
-            if (f.dim == 3) {
-                nb += safe_div(rin[p - f.sz] - alpha * q[p - f.sz], f.diag[p - f.sz]);
-                nb += safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
+            if (LW) {
+                double nb = f.wf[p - 1] * (rin[p - 1] - alpha * q[p - 1]);
+                nb += f.wf[p + 1] * (rin[p + 1] - alpha * q[p + 1]);
+                nb += f.wf[p - f.sy] * (rin[p - f.sy] - alpha * q[p - f.sy]);
+                nb += f.wf[p + f.sy] * (rin[p + f.sy] - alpha * q[p + f.sy]);
+                if (f.dim == 3) {
+                    nb += f.wf[p - f.sz] * (rin[p - f.sz] - alpha * q[p - f.sz]);
+                    nb += f.wf[p + f.sz] * (rin[p + f.sz] - alpha * q[p + f.sz]);
+                }
+                const double z1 = f.wf[p] * rn;
+                res[p] = (V)(rn - (d * z1 - f.s * nb));
+            } else {
+                double nb = safe_div(rin[p - 1] - alpha * q[p - 1], f.diag[p - 1]);
+                nb += safe_div(rin[p + 1] - alpha * q[p + 1], f.diag[p + 1]);
+                nb += safe_div(rin[p - f.sy] - alpha * q[p - f.sy], f.diag[p - f.sy]);
+                nb += safe_div(rin[p + f.sy] - alpha * q[p + f.sy], f.diag[p + f.sy]);
+                if (f.dim == 3) {
+                    nb += safe_div(rin[p - f.sz] - alpha * q[p - f.sz], f.diag[p - f.sz]);
+                    nb += safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
+                }
+                const double z1 = omega * rn / d;
+                res[p] = (V)(rn - (d * z1 - f.s * (omega * nb)));
             }
-            const double z1 = omega * rn / d;
-            res[p] = (V)(rn - (d * z1 - f.s * (omega * nb)));
         }
     }
     block_partial(part, part_rr);
@@ -349,7 +377,7 @@ __device__ inline V corr_at(const int32_t* __restrict__ agg, const V* __restrict
 
 // Pre-smoothed iterate after prolongation at node p:
 //   zt = omega r / d + t - omega (A t) / d,  t = e_c[agg].
-template <class V>
+template <class V, bool LW>
 __device__ inline V zt_at(const FineArgs& f, V omega, const int32_t* __restrict__ agg, const V* __restrict__ ec,
                           const double* __restrict__ r, int64_t p) {
     const V d = vdiag<V>(f)[p];
@@ -359,24 +387,25 @@ __device__ inline V zt_at(const FineArgs& f, V omega, const int32_t* __restrict_
     nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
     if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
     const V at = d * tp - (V)f.s * nb;
-    return omega * (V)r[p] / d + (tp - omega * at / d);
+    const V z1 = LW ? vwf<V>(f)[p] * (V)r[p] : omega * (V)r[p] / d;
+    return z1 + (tp - omega * at / d);
 }
 
 // Prolongation and pre-smoothed correction: zt = omega r / d + t - omega (A t) / d,
 // t = e_c[agg].
-template <class V>
+template <class V, bool LW>
 __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const int32_t* __restrict__ agg,
                                                 const V* __restrict__ ec, const double* __restrict__ r,
                                                 V* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
     const V w = (V)omega;
     FINE_LOOP(f, p) {
-        if (f.diag[p] != 0.0) zt[p] = zt_at(f, w, agg, ec, r, p);
+        if (f.diag[p] != 0.0) zt[p] = zt_at<V, LW>(f, w, agg, ec, r, p);
     }
 }
 
 // Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z) in FP64.
-template <class V>
+template <class V, bool LW>
 __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
                                                   const double* __restrict__ r, V* __restrict__ z,
                                                   double* __restrict__ part_rz, const PcgScalars* sc) {
@@ -389,7 +418,7 @@ __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, c
         const V d = dg[p];
         if (d != V(0)) {
             const V az = d * zt[p] - sh * nbr_sum(zt, p, f);
-            const V zv = zt[p] + w * ((V)r[p] - az) / d;
+            const V zv = LW ? zt[p] + vwf<V>(f)[p] * ((V)r[p] - az) : zt[p] + w * ((V)r[p] - az) / d;
             z[p] = zv;
             part += r[p] * (double)zv;
         }
@@ -736,6 +765,8 @@ static FineArgs fine_args(const amg_handle* H) {
     f.s = H->d.s;
     f.diag = H->diag_p;
     f.diag32 = H->diag_p32;
+    f.wf = H->wf_on ? H->wf : nullptr;
+    f.wf32 = H->wf_on ? H->wf32 : nullptr;
     return f;
 }
 
@@ -879,7 +910,7 @@ static int enqueue_vcycle_one_level(amg_handle* H, const double* r, double* z, d
 // two or more levels: fine pre-smoothing, restriction, coarse levels,
 // prolongation and post-smoothing; the last kernel writes the (r, z)
 // partials to rz_out.
-template <class V>
+template <class V, bool LW>
 static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, hipStream_t s) {
     PcgScalars* sc = H->sc;
     const int np = H->red.nparts;
@@ -888,15 +919,16 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
     const FineBufs<V> fb = fine_bufs<V>(H);
     const LevelView<V> L1 = view<V>(H->lev[1]);
     const double w0 = H->lev[0].omega;
-    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, k_fine_down<V>, G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr, np);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_fine_down<V, LW>), G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr,
+                    np);
     EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
                     box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r, fb.zt,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r, fb.zt,
                     (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW>), G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -905,7 +937,7 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
 // Iteration k >= 1 of a run.  The V-cycle before it (number k-1) wrote
 // rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
 // r[k % 2] and its V-cycle writes rz[k % 2].
-template <class V>
+template <class V, bool LW>
 static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
@@ -923,16 +955,16 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
                     np, H->red.pq, sc);
     const double w0 = H->lev[0].omega;
     const LevelView<V> L1 = view<V>(H->lev[1]);
-    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr_down<V>, G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res, w0,
-                    rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
+                    w0, rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
     EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
                     box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, k_fine_up<V>, dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout, fb.zt,
-                    (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, k_fine_post<V>, G, dim3(NT), 0, f, w0, fb.zt, rout, fb.z, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout,
+                    fb.zt, (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW>), G, dim3(NT), 0, f, w0, fb.zt, rout, fb.z, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -959,6 +991,18 @@ static int enqueue_iteration_one_level(amg_handle* H, int k, int iter_global, hi
     hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
     EB_LAUNCH_CHECK();
     return enqueue_vcycle_one_level(H, rout, H->z, rz_out, 1, s);
+}
+
+// V-cycle / iteration with or without the per-point smoother weights.
+template <class V>
+static int enqueue_vcycle_any(amg_handle* H, const double* r, V* z, double* rz_out, hipStream_t s) {
+    return H->wf_on ? enqueue_vcycle<V, true>(H, r, z, rz_out, s) : enqueue_vcycle<V, false>(H, r, z, rz_out, s);
+}
+
+template <class V>
+static int enqueue_iteration_any(amg_handle* H, int k, int iter_global, hipStream_t s) {
+    return H->wf_on ? enqueue_iteration<V, true>(H, k, iter_global, s)
+                    : enqueue_iteration<V, false>(H, k, iter_global, s);
 }
 
 // FP32 copies of the hierarchy for the single-precision V-cycle, made once
@@ -1116,6 +1160,352 @@ static int poll_scalars(amg_handle* H, hipStream_t s) {
     return EB_OK;
 }
 
+// ------------------------------------------------- learned smoother weights
+// Per-point fine smoother weights and the training quantities of the learned
+// smoother (the network itself is in learned.hip).  Loss for error samples e:
+// L = mean (e'^T A e') / (2 e^T A e), e' = e - M A e, M the V(1,1) cycle with
+// W = diag(omega_k / d_k) on the fine level.  With r = A e, z1 = W r,
+// z2 = z1 + P E_c R (r - A z1), t2 = r - A z2, z = z2 + W t2:
+//   g = -A e' / (e^T A e),  u = g - A (W g),  v = u - A P E_c R u,
+//   dL/dW = g t2 + v r  (A and E_c symmetric, R = P^T).
+
+__global__ void __launch_bounds__(BLOCK) k_set_wf(int64_t n, const int64_t* __restrict__ nodes,
+                                                  const int32_t* __restrict__ pad, const double* __restrict__ diag_p,
+                                                  const double* __restrict__ om, double* __restrict__ wf,
+                                                  float* __restrict__ wf32, int32_t* __restrict__ bad) {
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= n) return;
+    const int32_t p = pad[k];
+    const double o = om[nodes[k]];
+    if (!(o > 0.0) || isinf(o)) atomicOr(bad, 1);
+    const double w = o / diag_p[p];
+    wf[p] = w;
+    wf32[p] = (float)w;
+}
+
+// y = A x on the padded fine layout (0 off unknowns).
+__global__ void __launch_bounds__(NT) k_lg_apply(FineArgs f, const double* __restrict__ x, double* __restrict__ y) {
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) y[p] = d * x[p] - f.s * nbr_sum(x, p, f);
+    }
+}
+
+// partial sums of a . b
+__global__ void __launch_bounds__(NT) k_lg_dot(FineArgs f, const double* __restrict__ a, const double* __restrict__ b,
+                                               double* __restrict__ part) {
+    double acc = 0.0;
+    FINE_LOOP(f, p) {
+        if (f.diag[p] != 0.0) acc += a[p] * b[p];
+    }
+    block_partial(acc, part);
+}
+
+// e = (e - z) / ||e - z||, the norm from the partials of (e - z, e - z) taken
+// by k_lg_diffnorm.
+__global__ void __launch_bounds__(NT) k_lg_diffnorm(FineArgs f, const double* __restrict__ e,
+                                                    const double* __restrict__ z, double* __restrict__ part) {
+    double acc = 0.0;
+    FINE_LOOP(f, p) {
+        if (f.diag[p] != 0.0) {
+            const double t = e[p] - z[p];
+            acc += t * t;
+        }
+    }
+    block_partial(acc, part);
+}
+
+__global__ void __launch_bounds__(NT) k_lg_diffscale(FineArgs f, double* __restrict__ e, const double* __restrict__ z,
+                                                     const double* __restrict__ part, int np) {
+    const double nrm = sqrt(block_total(part, np));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    FINE_LOOP(f, p) {
+        if (f.diag[p] != 0.0) e[p] = (e[p] - z[p]) * inv;
+    }
+}
+
+// From z2 (the prolongated pre-smoothed iterate) and r: t2 = r - A z2,
+// e' = e - (z2 + W t2).
+__global__ void __launch_bounds__(NT) k_lg_post(FineArgs f, const double* __restrict__ e, const double* __restrict__ r,
+                                                const double* __restrict__ z2, double omega,
+                                                double* __restrict__ t2, double* __restrict__ ep) {
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double tt = r[p] - (d * z2[p] - f.s * nbr_sum(z2, p, f));
+            const double w = f.wf ? f.wf[p] : omega / d;
+            t2[p] = tt;
+            ep[p] = e[p] - (z2[p] + w * tt);
+        }
+    }
+}
+
+// g = -(A e') / (e^T A e) and wg = W g; the denominator from its partials.
+__global__ void __launch_bounds__(NT) k_lg_g(FineArgs f, const double* __restrict__ aep,
+                                             const double* __restrict__ part_den, int np, double omega,
+                                             double* __restrict__ g, double* __restrict__ wg) {
+    const double den = block_total(part_den, np);
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double gg = -aep[p] / den;
+            g[p] = gg;
+            wg[p] = (f.wf ? f.wf[p] : omega / d) * gg;
+        }
+    }
+}
+
+// u = g - A wg
+__global__ void __launch_bounds__(NT) k_lg_u(FineArgs f, const double* __restrict__ g, const double* __restrict__ wg,
+                                             double* __restrict__ u) {
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) u[p] = g[p] - (d * wg[p] - f.s * nbr_sum(wg, p, f));
+    }
+}
+
+// Prolongation only: y = P e_c = t - omega (A t) / d, t = e_c[agg].
+__global__ void __launch_bounds__(NT) k_lg_prolong(FineArgs f, double omega, const int32_t* __restrict__ agg,
+                                                   const double* __restrict__ ec, double* __restrict__ y) {
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double tp = corr_at(agg, ec, p);
+            double nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
+            nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
+            if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
+            y[p] = tp - omega * (d * tp - f.s * nb) / d;
+        }
+    }
+}
+
+// gw += g t2 + (u - A pe) r
+__global__ void __launch_bounds__(NT) k_lg_acc(FineArgs f, const double* __restrict__ g, const double* __restrict__ t2,
+                                               const double* __restrict__ u, const double* __restrict__ pe,
+                                               const double* __restrict__ r, double* __restrict__ gw) {
+    FINE_LOOP(f, p) {
+        const double d = f.diag[p];
+        if (d != 0.0) {
+            const double v = u[p] - (d * pe[p] - f.s * nbr_sum(pe, p, f));
+            gw[p] += g[p] * t2[p] + v * r[p];
+        }
+    }
+}
+
+// loss += (e'^T A e') / (2 e^T A e)   (one block)
+__global__ void __launch_bounds__(NT) k_lg_loss(const double* __restrict__ part_num, const double* __restrict__ part_den,
+                                                int np, double* __restrict__ loss) {
+    const double num = block_total(part_num, np);
+    const double den = block_total(part_den, np);
+    if (threadIdx.x == 0) loss[0] += 0.5 * num / den;
+}
+
+// dL/domega at the nodes: gw / d / m.
+__global__ void __launch_bounds__(NT) k_lg_store_grad(int64_t n, const int64_t* __restrict__ nodes,
+                                                      const int32_t* __restrict__ pad, const double* __restrict__ gw,
+                                                      const double* __restrict__ diag_p, double inv_m,
+                                                      double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (k >= n) return;
+    const int32_t p = pad[k];
+    out[nodes[k]] = gw[p] / diag_p[p] * inv_m;
+}
+
+// fine pre-smoothing, restriction, coarse cycle, prolongation: z2 from r.
+static int lg_cycle_to_z2(amg_handle* H, const double* r, hipStream_t s) {
+    const FineArgs f = fine_args(H);
+    const int np = H->red.nparts;
+    const double w0 = H->lev[0].omega;
+    if (H->wf_on)
+        hipLaunchKernelGGL((k_fine_down<double, true>), dim3(np), dim3(NT), 0, s, f, w0, r, H->res, H->sc, 0,
+                           H->red.rr, np);
+    else
+        hipLaunchKernelGGL((k_fine_down<double, false>), dim3(np), dim3(NT), 0, s, f, w0, r, H->res, H->sc, 0,
+                           H->red.rr, np);
+    hipLaunchKernelGGL((k_fine_restrict<double>), dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, s, f, box_args(H),
+                       w0, (const double*)H->res, H->lev[1].rv, H->sc, 0, H->red.rr, np);
+    EB_TRY(enqueue_coarse<double>(H, s));
+    unsigned gu = 0;
+    const FineArgs fu = fine_args_full(H, &gu);
+    if (H->wf_on)
+        hipLaunchKernelGGL((k_fine_up<double, true>), dim3(gu), dim3(NT), 0, s, fu, w0, H->agg_p,
+                           (const double*)H->lev[1].ev, r, H->zt, (const PcgScalars*)H->sc);
+    else
+        hipLaunchKernelGGL((k_fine_up<double, false>), dim3(gu), dim3(NT), 0, s, fu, w0, H->agg_p,
+                           (const double*)H->lev[1].ev, r, H->zt, (const PcgScalars*)H->sc);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+static int lg_check(amg_handle* H, const char* name) {
+    if (H->nlev < 2) {
+        set_error("%s: the hierarchy has a single level (no fine smoother)", name);
+        return EB_EINVAL;
+    }
+    return EB_OK;
+}
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int amg_set_fine_weights(amg_handle_t* H, const double* omega, void* stream) {
+    clear_error();
+    if (!H || !omega) {
+        set_error("amg_set_fine_weights: null pointer");
+        return EB_EINVAL;
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
+    if (!H->wf) {
+        EB_TRY(dalloc_n(&H->wf, H->npad, s));
+        EB_TRY(dalloc_n(&H->wf32, H->npad, s));
+        EB_HIP(hipMemsetAsync(H->wf, 0, sizeof(double) * H->npad, s));
+        EB_HIP(hipMemsetAsync(H->wf32, 0, sizeof(float) * H->npad, s));
+    }
+    int32_t* bad = nullptr;
+    EB_TRY(dalloc_n(&bad, 1, s));
+    EB_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    if (H->n_fine > 0)
+        hipLaunchKernelGGL(k_set_wf, dim3(grid_for(H->n_fine)), dim3(BLOCK), 0, s, H->n_fine, H->fine_nodes,
+                           H->fine_pad, H->diag_p, omega, H->wf, H->wf32, bad);
+    EB_LAUNCH_CHECK();
+    int32_t hb = 0;
+    EB_TRY(read_device_i32(bad, &hb, s));
+    EB_TRY(dfree(bad, s));
+    if (hb) {
+        H->wf_on = 0;
+        set_error("amg_set_fine_weights: weights must be positive and finite at every computational point");
+        return EB_EINVAL;
+    }
+    H->wf_on = H->nlev > 1 ? 1 : 0;
+    return EB_OK;
+}
+
+extern "C" int amg_clear_fine_weights(amg_handle_t* H) {
+    clear_error();
+    if (!H) {
+        set_error("amg_clear_fine_weights: null pointer");
+        return EB_EINVAL;
+    }
+    H->wf_on = 0;
+    return EB_OK;
+}
+
+extern "C" int amg_smoother_samples(amg_handle_t* H, int32_t m, int32_t sweeps, const double* xi, double* e,
+                                    void* stream) {
+    clear_error();
+    if (!H || !xi || !e || m < 1 || sweeps < 0) {
+        set_error("amg_smoother_samples: invalid arguments");
+        return EB_EINVAL;
+    }
+    EB_TRY(lg_check(H, "amg_smoother_samples"));
+    hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
+    const GridDims& d = H->d;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    const int64_t nunk = H->n_fine;
+    const FineArgs f = fine_args(H);
+    const int np = H->red.nparts;
+    const unsigned ug = grid_for(nunk, NT);
+    double *ev = nullptr, *rv = nullptr;
+    EB_TRY(dalloc_n(&ev, H->npad, s));
+    EB_TRY(dalloc_n(&rv, H->npad, s));
+    EB_HIP(hipMemsetAsync(ev, 0, sizeof(double) * H->npad, s));
+    EB_HIP(hipMemsetAsync(rv, 0, sizeof(double) * H->npad, s));
+    EB_HIP(hipMemsetAsync(e, 0, sizeof(double) * nn * m, s));
+    hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
+    for (int j = 0; j < m; ++j) {
+        hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, xi + j * nn, ev);
+        for (int k = 0; k < sweeps; ++k) {
+            hipLaunchKernelGGL(k_lg_apply, dim3(np), dim3(NT), 0, s, f, (const double*)ev, rv);
+            EB_TRY(enqueue_vcycle_any<double>(H, rv, H->z, H->red.aux2, s));
+            hipLaunchKernelGGL(k_lg_diffnorm, dim3(np), dim3(NT), 0, s, f, (const double*)ev, (const double*)H->z,
+                               H->red.aux);
+            hipLaunchKernelGGL(k_lg_diffscale, dim3(np), dim3(NT), 0, s, f, ev, (const double*)H->z,
+                               (const double*)H->red.aux, np);
+        }
+        hipLaunchKernelGGL(k_store_field<double>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad,
+                           (const double*)ev, e + j * nn);
+        EB_LAUNCH_CHECK();
+    }
+    EB_TRY(dfree(ev, s));
+    EB_TRY(dfree(rv, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+
+extern "C" int amg_smoother_loss_grad(amg_handle_t* H, int32_t m, const double* e, double* loss, double* grad_omega,
+                                      void* stream) {
+    clear_error();
+    if (!H || !e || !loss || !grad_omega || m < 1) {
+        set_error("amg_smoother_loss_grad: invalid arguments");
+        return EB_EINVAL;
+    }
+    EB_TRY(lg_check(H, "amg_smoother_loss_grad"));
+    hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    H->last_stream = s;
+    const GridDims& d = H->d;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    const int64_t nunk = H->n_fine;
+    const FineArgs f = fine_args(H);
+    const int np = H->red.nparts;
+    const unsigned ug = grid_for(nunk, NT);
+    const double w0 = H->lev[0].omega;
+    // padded vectors: e, r, t2, ep / Aep, g, wg / pe, u, gw, scratch
+    double* v[9] = {};
+    for (double*& p : v) {
+        EB_TRY(dalloc_n(&p, H->npad, s));
+        EB_HIP(hipMemsetAsync(p, 0, sizeof(double) * H->npad, s));
+    }
+    double *ev = v[0], *rv = v[1], *t2 = v[2], *ep = v[3], *g = v[4], *wg = v[5], *u = v[6], *gw = v[7],
+           *aep = v[8];
+    double* dloss = nullptr;
+    double* part_den = nullptr;
+    EB_TRY(dalloc_n(&dloss, 1, s));
+    EB_TRY(dalloc_n(&part_den, MAX_PARTS, s));
+    EB_HIP(hipMemsetAsync(dloss, 0, sizeof(double), s));
+    hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
+    for (int j = 0; j < m; ++j) {
+        hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, e + j * nn, ev);
+        hipLaunchKernelGGL(k_lg_apply, dim3(np), dim3(NT), 0, s, f, (const double*)ev, rv);
+        hipLaunchKernelGGL(k_lg_dot, dim3(np), dim3(NT), 0, s, f, (const double*)ev, (const double*)rv, part_den);
+        EB_TRY(lg_cycle_to_z2(H, rv, s));                                   // H->zt = z2
+        hipLaunchKernelGGL(k_lg_post, dim3(np), dim3(NT), 0, s, f, (const double*)ev, (const double*)rv,
+                           (const double*)H->zt, w0, t2, ep);
+        hipLaunchKernelGGL(k_lg_apply, dim3(np), dim3(NT), 0, s, f, (const double*)ep, aep);
+        hipLaunchKernelGGL(k_lg_dot, dim3(np), dim3(NT), 0, s, f, (const double*)ep, (const double*)aep, H->red.aux);
+        hipLaunchKernelGGL(k_lg_loss, dim3(1), dim3(NT), 0, s, (const double*)H->red.aux, (const double*)part_den, np,
+                           dloss);
+        hipLaunchKernelGGL(k_lg_g, dim3(np), dim3(NT), 0, s, f, (const double*)aep, (const double*)part_den, np, w0,
+                           g, wg);
+        hipLaunchKernelGGL(k_lg_u, dim3(np), dim3(NT), 0, s, f, (const double*)g, (const double*)wg, u);
+        // R u -> coarse cycle -> P e_c
+        hipLaunchKernelGGL((k_fine_restrict<double>), dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, s, f,
+                           box_args(H), w0, (const double*)u, H->lev[1].rv, H->sc, 0, H->red.rr, np);
+        EB_TRY(enqueue_coarse<double>(H, s));
+        hipLaunchKernelGGL(k_lg_prolong, dim3(np), dim3(NT), 0, s, f, w0, H->agg_p, (const double*)H->lev[1].ev, wg);
+        hipLaunchKernelGGL(k_lg_acc, dim3(np), dim3(NT), 0, s, f, (const double*)g, (const double*)t2,
+                           (const double*)u, (const double*)wg, (const double*)rv, gw);
+        EB_LAUNCH_CHECK();
+    }
+    const int64_t nnode = nn;
+    EB_HIP(hipMemsetAsync(grad_omega, 0, sizeof(double) * nnode, s));
+    hipLaunchKernelGGL(k_lg_store_grad, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad,
+                       (const double*)gw, H->diag_p, 1.0 / m, grad_omega);
+    EB_LAUNCH_CHECK();
+    double hl = 0.0;
+    EB_HIP(hipMemcpyAsync(&hl, dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    *loss = hl / m;
+    for (double* p : v) EB_TRY(dfree(p, s));
+    EB_TRY(dfree(dloss, s));
+    EB_TRY(dfree(part_den, s));
+    return EB_OK;
+}
+
+namespace eb {
+
 }  // namespace eb
 
 using namespace eb;
@@ -1176,8 +1566,8 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         EB_TRY(enqueue_init(H, p.tol, iter_base, s));
         // V-cycle 0 -> rz[0]
         if (H->nlev == 1) EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.rz[0], 0, s));
-        else if (fp32) EB_TRY(enqueue_vcycle<float>(H, H->rr[0], H->z32, H->red.rz[0], s));
-        else EB_TRY(enqueue_vcycle<double>(H, H->rr[0], H->z, H->red.rz[0], s));
+        else if (fp32) EB_TRY(enqueue_vcycle_any<float>(H, H->rr[0], H->z32, H->red.rz[0], s));
+        else EB_TRY(enqueue_vcycle_any<double>(H, H->rr[0], H->z, H->red.rz[0], s));
         int k = 0;
         while (true) {
             EB_TRY(poll_scalars(H, s));
@@ -1191,8 +1581,8 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             for (int c = 0; c < chunk; ++c, ++enqueued) {
                 ++k;
                 if (H->nlev == 1) EB_TRY(enqueue_iteration_one_level(H, k, iter_base + k, s));
-                else if (fp32) EB_TRY(enqueue_iteration<float>(H, k, iter_base + k, s));
-                else EB_TRY(enqueue_iteration<double>(H, k, iter_base + k, s));
+                else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, iter_base + k, s));
+                else EB_TRY(enqueue_iteration_any<double>(H, k, iter_base + k, s));
             }
         }
         // true residual ||b - A x||
@@ -1261,9 +1651,9 @@ static int vcycle_apply(amg_handle_t* H, const double* r, double* z, int precisi
     if (H->nlev == 1) {
         EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.aux2, 0, s));
     } else if (fp32) {
-        EB_TRY(enqueue_vcycle<float>(H, H->rr[0], H->z32, H->red.aux2, s));
+        EB_TRY(enqueue_vcycle_any<float>(H, H->rr[0], H->z32, H->red.aux2, s));
     } else {
-        EB_TRY(enqueue_vcycle<double>(H, H->rr[0], H->z, H->red.aux2, s));
+        EB_TRY(enqueue_vcycle_any<double>(H, H->rr[0], H->z, H->red.aux2, s));
     }
     if (fp32) {
         hipLaunchKernelGGL(k_store_field<float>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z32,

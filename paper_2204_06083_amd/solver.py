@@ -274,3 +274,129 @@ def solve_problem(problem, device="cuda", tol=None, coarse_max=256, precision="f
     H = Hierarchy(g, asm.kind, asm.a, problem.sigma, coarse_max=coarse_max)
     x, info = H.solve(b, tol=problem.tol if tol is None else tol, precision=precision)
     return dict(asm=asm, b=b, H=H, x=x, info=info)
+
+
+# ------------------------------------------------------- learned smoother
+NET_CH = 16
+
+
+def init_smoother_params(dim: int, seed: int = 0) -> np.ndarray:
+    """Initial FP32 parameters: He-normal first two layers, zero last layer, so the
+    network starts at the plain smoother (omega_k = omega0).  Packed in the
+    library's order W1, b1, W2, b2, W3, b3."""
+    rng = np.random.default_rng(seed)
+    T = 3 ** dim
+    w1 = rng.normal(0.0, np.sqrt(2.0 / (2 * T)), size=(NET_CH, 2, T))
+    w2 = rng.normal(0.0, np.sqrt(2.0 / (NET_CH * T)), size=(NET_CH, NET_CH, T))
+    parts = [w1.ravel(), np.zeros(NET_CH), w2.ravel(), np.zeros(NET_CH), np.zeros(NET_CH * T), np.zeros(1)]
+    out = np.concatenate(parts).astype(np.float32)
+    assert out.size == L.lib().eb_smoother_net_size(dim)
+    return out
+
+
+class LearnedSmoother:
+    """Per-point fine smoother weights from the library's network, trained on the GPU.
+
+    Every step is a library call: forward pass, error samples, loss and
+    dL/domega (adjoint of the V-cycle), backward pass, Adam.  This class holds
+    the device buffers and the loop."""
+
+    def __init__(self, H: "Hierarchy", asm: "Assembly", psi: torch.Tensor, params: Optional[np.ndarray] = None,
+                 seed: int = 0):
+        self.H, self.asm, self.grid = H, asm, asm.grid
+        self.psi = psi.contiguous()
+        dev = psi.device
+        dim = self.grid.dim
+        self.P = int(L.lib().eb_smoother_net_size(dim))
+        p0 = init_smoother_params(dim, seed) if params is None else np.asarray(params, dtype=np.float32)
+        self.params = torch.as_tensor(p0, device=dev).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        n = int(np.prod(self.grid.shape))
+        self.z1 = torch.empty(n * NET_CH, dtype=torch.float32, device=dev)
+        self.z2 = torch.empty(n * NET_CH, dtype=torch.float32, device=dev)
+        self.o = torch.empty(n, dtype=torch.float32, device=dev)
+        self.omega = torch.empty(self.grid.shape, dtype=torch.float64, device=dev)
+        g = L.make_grid(self.grid)
+        self.scratch = torch.empty(int(L.lib().eb_smoother_scratch_floats(C.byref(g))), dtype=torch.float32,
+                                   device=dev)
+        self.grads = torch.zeros(self.P, dtype=torch.float32, device=dev)
+        self.omega0 = H.level(0).omega
+
+    def forward(self) -> torch.Tensor:
+        g = L.make_grid(self.grid)
+        rc = L.lib().eb_smoother_forward(C.byref(g), C.c_void_p(self.asm.kind.data_ptr()),
+                                         C.c_void_p(self.asm.a.data_ptr()), C.c_void_p(self.psi.data_ptr()),
+                                         C.c_void_p(self.params.data_ptr()), self.omega0,
+                                         C.c_void_p(self.z1.data_ptr()), C.c_void_p(self.z2.data_ptr()),
+                                         C.c_void_p(self.o.data_ptr()), C.c_void_p(self.omega.data_ptr()), _stream())
+        L.check(rc, "eb_smoother_forward")
+        return self.omega
+
+    def backward(self, grad_omega: torch.Tensor) -> torch.Tensor:
+        g = L.make_grid(self.grid)
+        rc = L.lib().eb_smoother_backward(C.byref(g), C.c_void_p(self.asm.kind.data_ptr()),
+                                          C.c_void_p(self.asm.a.data_ptr()), C.c_void_p(self.psi.data_ptr()),
+                                          C.c_void_p(self.params.data_ptr()), self.omega0,
+                                          C.c_void_p(self.z1.data_ptr()), C.c_void_p(self.z2.data_ptr()),
+                                          C.c_void_p(self.o.data_ptr()),
+                                          _field(grad_omega, self.grid.shape, torch.float64, "grad_omega"),
+                                          C.c_void_p(self.scratch.data_ptr()), C.c_void_p(self.grads.data_ptr()),
+                                          _stream())
+        L.check(rc, "eb_smoother_backward")
+        return self.grads
+
+    def apply(self):
+        """Evaluate the network and install its weights in the hierarchy's fine smoother."""
+        om = self.forward()
+        L.check(L.lib().amg_set_fine_weights(self.H.handle, C.c_void_p(om.data_ptr()), _stream()),
+                "amg_set_fine_weights")
+        return om
+
+    def samples(self, xi: torch.Tensor, sweeps: int) -> torch.Tensor:
+        m = xi.shape[0]
+        e = torch.empty_like(xi)
+        rc = L.lib().amg_smoother_samples(self.H.handle, int(m), int(sweeps),
+                                          _field(xi, (m,) + tuple(self.grid.shape), torch.float64, "xi"),
+                                          C.c_void_p(e.data_ptr()), _stream())
+        L.check(rc, "amg_smoother_samples")
+        return e
+
+    def loss_grad(self, e: torch.Tensor):
+        m = e.shape[0]
+        gom = torch.empty(self.grid.shape, dtype=torch.float64, device=e.device)
+        loss = C.c_double(0.0)
+        rc = L.lib().amg_smoother_loss_grad(self.H.handle, int(m),
+                                            _field(e, (m,) + tuple(self.grid.shape), torch.float64, "e"),
+                                            C.byref(loss), C.c_void_p(gom.data_ptr()), _stream())
+        L.check(rc, "amg_smoother_loss_grad")
+        return loss.value, gom
+
+    def step(self, lr: float):
+        self.t += 1
+        rc = L.lib().eb_adam_step(C.c_void_p(self.params.data_ptr()), C.c_void_p(self.grads.data_ptr()),
+                                  C.c_void_p(self.m.data_ptr()), C.c_void_p(self.v.data_ptr()), self.P, self.t,
+                                  float(lr), _stream())
+        L.check(rc, "eb_adam_step")
+
+    def train(self, steps: int = 100, samples: int = 4, sweeps: int = 6, lr: float = 3e-3, seed: int = 0):
+        """Adam on the loss of error samples left by the current cycle (xi seeded per step)."""
+        gen = torch.Generator(device=self.params.device)
+        gen.manual_seed(int(seed))
+        mask = (self.asm.kind == 2).to(torch.float64)
+        history = []
+        for it in range(steps):
+            self.apply()
+            xi = torch.randn((samples,) + tuple(self.grid.shape), dtype=torch.float64, device=self.params.device,
+                             generator=gen) * mask
+            e = self.samples(xi.contiguous(), sweeps)
+            loss, gom = self.loss_grad(e)
+            self.backward(gom)
+            self.step(lr)
+            history.append(loss)
+        self.apply()
+        return history
+
+    def clear(self):
+        L.check(L.lib().amg_clear_fine_weights(self.H.handle), "amg_clear_fine_weights")

@@ -1,0 +1,187 @@
+"""Learned fine smoother on the GPU against the oracle: network forward and
+backward, weighted V-cycle, error samples, loss and its gradient, training."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import amg as OA
+from oracle import eb_assembly as E
+from oracle import learned as LN
+from oracle import pcg as OP
+from paper_2204_06083_amd import _lib as L
+from paper_2204_06083_amd import solver as S
+from paper_2204_06083_amd import workloads as W
+
+from gpu_common import gpu_system, oracle_system, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "star256": lambda: W.star_poisson(256),
+    "disk128": lambda: W.disk_poisson(128),
+    "ell40": lambda: W.ellipsoid_poisson(40),
+}
+
+
+def _setup(name):
+    prob = CASES[name]()
+    asm_o, A, b_o, u = oracle_system(prob)
+    Ho = OA.build_hierarchy(A, E.unknown_coords(asm_o))
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    assert H.n_levels == Ho.n_levels and H.n_levels > 1
+    f = LN.features_of(asm_o, prob.psi, prob.grid.h, prob.grid.dim)
+    return prob, asm_o, A, b_o, Ho, asm_g, b_g, H, f
+
+
+def _net_dict(params, dim):
+    T = 3 ** dim
+    sizes = [("w1", (16, 2, T)), ("b1", (16,)), ("w2", (16, 16, T)), ("b2", (16,)), ("w3", (1, 16, T)),
+             ("b3", (1,))]
+    out, i = {}, 0
+    for k, sh in sizes:
+        n = int(np.prod(sh))
+        out[k] = params[i:i + n].astype(np.float64).reshape(sh)
+        i += n
+    assert i == params.size
+    return out
+
+
+def _random_params(dim, seed):
+    p = S.init_smoother_params(dim, seed)
+    rng = np.random.default_rng(seed + 100)
+    T = 3 ** dim
+    off_w3 = 16 * 2 * T + 16 + 16 * 16 * T + 16
+    p[off_w3:off_w3 + 16 * T] = rng.normal(0.0, 0.3, size=16 * T)
+    p[-1] = 0.05
+    p[16 * 2 * T: 16 * 2 * T + 16] = rng.normal(0.0, 0.1, size=16)
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_backward_against_oracle(name):
+    prob, asm_o, A, b_o, Ho, asm_g, b_g, H, f = _setup(name)
+    dim = prob.grid.dim
+    print(f"[gpu] learned fwd/bwd {name}", flush=True)
+    params = _random_params(dim, 1)
+    ls = S.LearnedSmoother(H, asm_g, to_dev(prob.psi), params=params)
+    om_g = ls.forward().cpu().numpy().ravel()
+    o_g = ls.o.cpu().numpy()
+    net = _net_dict(params, dim)
+    o_o, cache = LN.forward(net, f, dim, precision="bf16")
+    assert np.max(np.abs(o_g - o_o.ravel())) <= 1e-5 * max(1.0, np.abs(o_o).max())
+    om_o = LN.omega_of(o_o.ravel().astype(np.float64), Ho.levels[0].omega)
+    nodes = asm_o.nodes
+    assert rel(om_g[nodes], om_o[nodes]) <= 1e-6
+    assert not np.any(om_g[asm_o.kind.ravel() != 2])
+    # backward from a random dL/domega at the unknowns
+    rng = np.random.default_rng(2)
+    gom = np.zeros(om_g.size)
+    gom[nodes] = rng.standard_normal(nodes.size)
+    grads = ls.backward(to_dev(gom.reshape(prob.grid.shape))).cpu().numpy()
+    go = np.zeros(om_g.size)
+    th = np.tanh(o_g[nodes].astype(np.float64))
+    go[nodes] = gom[nodes] * Ho.levels[0].omega * 0.5 * (1.0 - th * th)
+    # the oracle's backward in FP64 on the GPU's own activations: the ReLU
+    # masks then agree even where a pre-activation is within rounding of 0
+    # (constant features far from the boundary make whole regions tie)
+    shp = (16,) + tuple(prob.grid.shape)
+    z1g = ls.z1.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
+    z2g = ls.z2.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
+    c64 = {"x0": cache["x0"].astype(np.float64), "z1": z1g, "y1": np.maximum(z1g, 0), "z2": z2g,
+           "y2": np.maximum(z2g, 0), "W": {kk: vv.astype(np.float64) for kk, vv in cache["W"].items()}}
+    g_o = LN.backward(c64, go.reshape(o_o.shape), dim)
+    lo = 0
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        ref = g_o[k].ravel()
+        got = grads[lo:lo + ref.size]
+        lo += ref.size
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"  grad {k}: rel max err {err:.2e}", flush=True)
+        assert err <= 2e-4, k
+    H.free()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_weighted_cycle_samples_and_loss_against_oracle(name):
+    prob, asm_o, A, b_o, Ho, asm_g, b_g, H, f = _setup(name)
+    print(f"[gpu] learned cycle/loss {name}", flush=True)
+    rng = np.random.default_rng(3)
+    n = asm_o.n_unknowns
+    nodes = asm_o.nodes
+    w0 = Ho.levels[0].omega
+    om = w0 * (1.0 + 0.4 * np.tanh(rng.standard_normal(n)))
+    omf = np.zeros(prob.grid.shape).ravel()
+    omf[nodes] = om
+    omd = to_dev(omf.reshape(prob.grid.shape))
+    L.check(L.lib().amg_set_fine_weights(H.handle, omd.data_ptr(), None), "amg_set_fine_weights")
+    # one cycle, both precisions
+    r = rng.standard_normal(n)
+    rf = np.zeros(prob.grid.shape).ravel()
+    rf[nodes] = r
+    zo = LN.vcycle_weighted(Ho, r, om)
+    z64 = H.vcycle(to_dev(rf.reshape(prob.grid.shape))).cpu().numpy().ravel()[nodes]
+    z32 = H.vcycle(to_dev(rf.reshape(prob.grid.shape)), precision="fp32").cpu().numpy().ravel()[nodes]
+    assert rel(z64, zo) <= 1e-12
+    assert rel(z32, zo) <= 2e-5
+    # error samples
+    xi = rng.standard_normal((2, n))
+    xif = np.zeros((2,) + (int(np.prod(prob.grid.shape)),))
+    xif[:, nodes] = xi
+    ls = S.LearnedSmoother(H, asm_g, to_dev(prob.psi))
+    eg = ls.samples(to_dev(xif.reshape((2,) + prob.grid.shape)), 3).cpu().numpy().reshape(2, -1)
+    for j in range(2):
+        e = xi[j]
+        for _ in range(3):
+            e = e - LN.vcycle_weighted(Ho, A @ e, om)
+            e = e / np.linalg.norm(e)
+        assert rel(eg[j][nodes], e) <= 1e-10
+    # loss and dL/domega
+    Eo = eg[:, nodes].T.copy()
+    Lg, gom = ls.loss_grad(to_dev(eg.reshape((2,) + prob.grid.shape)))
+    Lo, go = LN.loss_and_grad(Ho, om, Eo)
+    print(f"  loss gpu {Lg:.10e} oracle {Lo:.10e}", flush=True)
+    assert abs(Lg - Lo) <= 1e-10 * abs(Lo)
+    assert rel(gom.cpu().numpy().ravel()[nodes], go) <= 1e-9
+    # clearing restores the plain cycle
+    ls.clear()
+    zp = H.vcycle(to_dev(rf.reshape(prob.grid.shape))).cpu().numpy().ravel()[nodes]
+    assert rel(zp, OA.vcycle(Ho, r)) <= 1e-12
+    H.free()
+
+
+def test_set_weights_rejects_bad_values():
+    prob, asm_o, A, b_o, Ho, asm_g, b_g, H, f = _setup("disk128")
+    omf = np.zeros(prob.grid.shape).ravel()
+    omf[asm_o.nodes] = 0.5
+    omf[asm_o.nodes[3]] = -1.0
+    omd = to_dev(omf.reshape(prob.grid.shape))
+    rc = L.lib().amg_set_fine_weights(H.handle, omd.data_ptr(), None)
+    assert rc == L.EB_EINVAL
+    # the plain smoother stays in use
+    x, info = H.solve(b_g, tol=1e-10)
+    assert info["status"] == 0
+    H.free()
+
+
+def test_training_on_gpu_lowers_the_loss_and_keeps_pcg_converging():
+    """GPU training of the network on the star 512^2; the loss falls and the
+    solve with the learned weights converges; iterations are reported."""
+    prob = W.star_poisson(512)
+    print("[gpu] learned training star512", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x0, i0 = H.solve(b_g, tol=1e-8)
+    ls = S.LearnedSmoother(H, asm_g, to_dev(prob.psi), seed=0)
+    hist = ls.train(steps=40, samples=4, sweeps=6, lr=3e-3, seed=5)
+    print(f"  loss {hist[0]:.4f} -> {min(hist[-5:]):.4f}", flush=True)
+    assert min(hist[-5:]) < hist[0]
+    x1, i1 = H.solve(b_g, tol=1e-8)
+    print(f"  iterations plain {i0['iterations']} learned {i1['iterations']}", flush=True)
+    assert i1["status"] == 0 and i1["rel_res_true"] <= 1e-8
+    assert np.linalg.norm(b_o - A @ x1.cpu().numpy().ravel()[asm_o.nodes]) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
+    ls.clear()
+    x2, i2 = H.solve(b_g, tol=1e-8)
+    assert torch.equal(x0, x2) and i0["iterations"] == i2["iterations"]
+    H.free()

@@ -18,8 +18,10 @@ time.  `mixed` repeats the same steps with the single-precision V-cycle
 (FP64 outer CG) and reports its difference from the FP64 solution.
 `batched` times one backward-Euler heat step on the star 1024^2 for 64 seeded
 initial conditions as one batched solve (pcg_solve_batched) and as 64 single
-solves on the same hierarchy.  `cpu_baseline` times the CPU oracle on full
-steps of the same workload.
+solves on the same hierarchy.  `learned_3d` solves the 3-D ellipsoid 256^3
+Poisson problem with the plain and the learned fine smoother (network trained
+on the GPU at 96^3), both V-cycle precisions.  `cpu_baseline` times the CPU
+oracle on full steps of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -130,6 +132,61 @@ def batched_heat(n=1024, nrhs=64, reps=3):
     return out
 
 
+def learned_ellipsoid(n=256, n_train=96, steps=120, reps=3):
+    """The 3-D ellipsoid Poisson problem: plain Jacobi AMG-PCG against the
+    learned fine smoother (network trained on the GPU on the same ellipsoid at
+    n_train^3 and applied at n^3), FP64 and single-precision V-cycles."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+
+    def build(m):
+        p = W.ellipsoid_poisson(m)
+        psi = torch.as_tensor(p.psi, device=dev)
+        f = torch.as_tensor(p.f, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        asm = S.assemble_diag(p.grid, psi)
+        b = S.assemble_rhs(asm, f, torch.as_tensor(p.u_dirichlet(*asm.cut_coordinates()), device=dev))
+        H = S.Hierarchy(p.grid, asm.kind, asm.a, 0.0)
+        torch.cuda.synchronize()
+        return p, psi, asm, b, H, (time.perf_counter() - t0) * 1e3
+
+    def timed(H, b, prec):
+        H.solve(b, tol=1e-8, precision=prec)
+        ms, its = [], 0
+        for _ in range(reps):
+            _, info = H.solve(b, tol=1e-8, precision=prec)
+            ms.append(info["solve_ms"])
+            its = info["iterations"]
+        return {"iterations": its, "solve_ms": sorted(ms)[len(ms) // 2]}
+
+    pt, psit, asmt, bt, Ht, _ = build(n_train)
+    ls = S.LearnedSmoother(Ht, asmt, psit, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ls.train(steps=steps, samples=4, sweeps=6, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    params = ls.params.cpu().numpy()
+    Ht.free()
+    p, psi, asm, b, H, setup_ms = build(n)
+    out = {"workload": f"ellipsoid3d_{n}_poisson_tol1e-8", "n_unknowns": asm.n_unknowns, "levels": H.n_levels,
+           "assembly_rhs_setup_ms": setup_ms,
+           "training": {"grid": f"{n_train}^3", "steps": steps, "seconds": train_s,
+                        "loss_first": hist[0], "loss_last5_mean": sum(hist[-5:]) / 5}}
+    for prec in ("fp64", "fp32"):
+        out[f"plain_{prec}"] = timed(H, b, prec)
+    la = S.LearnedSmoother(H, asm, psi, params=params)
+    la.apply()
+    for prec in ("fp64", "fp32"):
+        out[f"learned_{prec}"] = timed(H, b, prec)
+    out["selection"] = la.select(b, tol=1e-8)
+    H.free()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +195,7 @@ def parse():
     ap.add_argument("--kernel", default="pcg_xr_down", choices=sorted(KERNEL_BYTES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched heat-step measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the 3-D learned-smoother measurement")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -484,6 +542,8 @@ def main():
         out["phases_ms"] = {k: sum(v) / len(v) for k, v in phases.items() if v}
     if not args.no_batched:
         out["batched"] = batched_heat()
+    if not args.no_learned:
+        out["learned_3d"] = learned_ellipsoid()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

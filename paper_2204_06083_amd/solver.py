@@ -400,3 +400,17 @@ class LearnedSmoother:
 
     def clear(self):
         L.check(L.lib().amg_clear_fine_weights(self.H.handle), "amg_clear_fine_weights")
+
+    def select(self, b: torch.Tensor, tol: float = 1e-8, precision: str = "fp64") -> dict:
+        """Keep the learned weights only if they solve b in fewer iterations than the
+        plain smoother; otherwise fall back to the plain smoother.  Returns both
+        counts and the choice."""
+        self.apply()
+        _, il = self.H.solve(b, tol=tol, precision=precision, allow_noconv=True)
+        self.clear()
+        _, ip = self.H.solve(b, tol=tol, precision=precision, allow_noconv=True)
+        use = il["status"] == 0 and il["iterations"] < ip["iterations"]
+        if use:
+            self.apply()
+        return {"plain_iterations": ip["iterations"], "learned_iterations": il["iterations"],
+                "learned_status": il["status"], "use_learned": bool(use)}

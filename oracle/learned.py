@@ -23,9 +23,12 @@ computed, written out plainly:
   omega_k = omega_0 (1 + tanh(o_k) / 2) in (omega_0 / 2, 3 omega_0 / 2),
   omega_0 the level's own weight 4 / (3 rho).  With W3 = 0 and b3 = 0 the
   weights equal omega_0: the plain smoother.
-* Precision of the GPU network: weights rounded to bfloat16 (round to nearest
-  even), products and sums in FP32.  `forward(..., precision="bf16")` does the
-  same here; "fp64" keeps everything in FP64 (used for the finite-difference
+* Precision of the GPU network: every convolution takes its weights and its
+  input rounded to bfloat16 (round to nearest even); products and sums are
+  FP32, biases FP32.  `forward(..., precision="bf16")` does the same here (the
+  cache then holds the rounded inputs, so the weight gradients are those of
+  the rounded computation and input gradients pass straight through the
+  rounding); "fp64" keeps everything in FP64 (used for the finite-difference
   pins).
 * Smoother: on the fine level only, pre- and post-smoothing use
   W = diag(omega_k / A_kk); the prolongator and every coarser level keep
@@ -151,11 +154,12 @@ def forward(net, f, dim, precision="fp64"):
     else:
         dt = np.float64
         W = {k: np.asarray(v, dtype=np.float64) for k, v in net.items()}
-    x0 = f.astype(dt)
+    rnd = bf16_round if precision == "bf16" else (lambda v: v)
+    x0 = rnd(f.astype(dt))
     z1 = conv(x0, W["w1"], W["b1"], dim)
-    y1 = np.maximum(z1, 0)
+    y1 = rnd(np.maximum(z1, 0))
     z2 = conv(y1, W["w2"], W["b2"], dim)
-    y2 = np.maximum(z2, 0)
+    y2 = rnd(np.maximum(z2, 0))
     o = conv(y2, W["w3"], W["b3"], dim)[0]
     return o, {"x0": x0, "z1": z1, "y1": y1, "z2": z2, "y2": y2, "W": W}
 

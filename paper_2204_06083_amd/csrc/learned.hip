@@ -15,8 +15,13 @@
 //   conv(x; W, b)[c, p] = b[c] + sum_{c', t} W[c, c', t] x[c', p + off_t],
 //   taps off_t in {-1, 0, 1}^d lexicographic (x fastest).
 //
-// Weights are used rounded to bfloat16 (nearest, ties to even); products and
-// sums are FP32.  Parameters are one FP32 array in the order
+// Every convolution takes its weights and its input rounded to bfloat16
+// (nearest, ties to even); products are exact in FP32 and sums are FP32; the
+// biases are FP32.  The 16 -> 16 layer runs on the matrix cores (bf16 MFMA,
+// FP32 accumulation), the other two with FP32 FMAs.  The backward pass is
+// exact for this computation: weight gradients use the rounded inputs, input
+// gradients pass straight through the rounding.  Parameters are one FP32
+// array in the order
 // W1 [16][2][T], b1 [16], W2 [16][16][T], b2 [16], W3 [1][16][T], b3 [1].
 // Activations are node-major, channels fastest: z[node * 16 + c].
 #include <math.h>
@@ -118,6 +123,8 @@ __global__ void __launch_bounds__(LNT) k_net_l1(NetDims d, const int8_t* __restr
         if (q < 0) continue;
         float f0, f1;
         node_features(d, kind, a, psi, q, f0, f1);
+        f0 = bf16r(f0);
+        f1 = bf16r(f1);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) acc[c] += lp[o.w1 + ((int64_t)c * 2 + 0) * d.T + t] * f0 +
                                                lp[o.w1 + ((int64_t)c * 2 + 1) * d.T + t] * f1;
@@ -126,34 +133,55 @@ __global__ void __launch_bounds__(LNT) k_net_l1(NetDims d, const int8_t* __restr
     for (int c = 0; c < NCH; ++c) z1[p * NCH + c] = acc[c];
 }
 
+// Layer 2 on the matrix cores.  A wavefront computes 16 consecutive nodes x
+// 16 output channels: for each tap t, D += A_t B_t with A_t[m][k] =
+// bf16(relu(z1))[node_m + off_t][k] and B_t[k][n] = W2[n][k][t], one
+// v_mfma_f32_16x16x16_bf16 per tap.  Lane l holds A rows l % 16, columns
+// 4 (l / 16) .. +3; B columns l % 16, rows 4 (l / 16) .. +3; D rows
+// 4 (l / 16) .. +3, column l % 16.
+typedef short mf_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_bits(float x) { return (short)(__float_as_uint(bf16r(x)) >> 16); }
+
 __global__ void __launch_bounds__(LNT) k_net_l2(NetDims d, const float* __restrict__ params,
                                                 const float* __restrict__ z1, float* __restrict__ z2) {
-    extern __shared__ float lp[];
+    extern __shared__ float lp[];                        // b2 (16 floats), then W2 as bf16 bits
     const NetOff o = net_offsets(d.T);
-    load_params(params, lp, o.w3, o);            // up to b2
-    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
-    if (p >= d.n) return;
-    int i, j, k;
-    node_ijk(d, p, i, j, k);
-    float acc[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) acc[c] = lp[o.b2 + c];
+    short* w2s = reinterpret_cast<short*>(lp + NCH);
+    for (int e = threadIdx.x; e < NCH * NCH * d.T; e += LNT) w2s[e] = bf16_bits(params[o.w2 + e]);
+    for (int e = threadIdx.x; e < NCH; e += LNT) lp[e] = params[o.b2 + e];
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t base = ((int64_t)blockIdx.x * (LNT / WAVE) + threadIdx.x / WAVE) * 16;
+    if (base >= d.n) return;                             // whole wavefront
+    const int m = lane % 16, kg = lane / 16;
+    const int64_t pm = base + m;                         // A row node
+    int i = 0, j = 0, k = 0;
+    const bool mvalid = pm < d.n;
+    if (mvalid) node_ijk(d, pm, i, j, k);
+    mf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < d.T; ++t) {
-        const int64_t q = tap_node(d, i, j, k, t);
-        if (q < 0) continue;
-        float y[NCH];
-#pragma unroll
-        for (int ci = 0; ci < NCH; ++ci) y[ci] = fmaxf(z1[q * NCH + ci], 0.0f);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            float s = 0.0f;
-#pragma unroll
-            for (int ci = 0; ci < NCH; ++ci) s += lp[o.w2 + ((int64_t)c * NCH + ci) * d.T + t] * y[ci];
-            acc[c] += s;
+        const int64_t q = mvalid ? tap_node(d, i, j, k, t) : -1;
+        mf_bf16x4 av, bv;
+        if (q >= 0) {
+            const float4 zv = *reinterpret_cast<const float4*>(z1 + q * NCH + 4 * kg);
+            av[0] = bf16_bits(fmaxf(zv.x, 0.f));
+            av[1] = bf16_bits(fmaxf(zv.y, 0.f));
+            av[2] = bf16_bits(fmaxf(zv.z, 0.f));
+            av[3] = bf16_bits(fmaxf(zv.w, 0.f));
+        } else {
+            av[0] = av[1] = av[2] = av[3] = 0;
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[r] = w2s[((int64_t)m * NCH + 4 * kg + r) * d.T + t];   // n = m
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) z2[p * NCH + c] = acc[c];
+    for (int r = 0; r < 4; ++r) {
+        const int64_t pn = base + 4 * kg + r;            // D row node
+        if (pn < d.n) z2[pn * NCH + m] = acc[r] + lp[m];
+    }
 }
 
 // Last layer, the weight omega = omega_0 (1 + tanh(o) / 2) at computational
@@ -174,7 +202,7 @@ __global__ void __launch_bounds__(LNT) k_net_l3(NetDims d, const int8_t* __restr
         if (q < 0) continue;
         float s = 0.0f;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) s += lp[o.w3 + (int64_t)c * d.T + t] * fmaxf(z2[q * NCH + c], 0.0f);
+        for (int c = 0; c < NCH; ++c) s += lp[o.w3 + (int64_t)c * d.T + t] * bf16r(fmaxf(z2[q * NCH + c], 0.0f));
         acc += s;
     }
     out_o[p] = acc;
@@ -281,11 +309,11 @@ __global__ void __launch_bounds__(LNT) k_net_wgrad(NetDims d, const float* __res
                 if (q < 0) continue;
                 float x;
                 if (XMODE == 0) {
-                    x = fmaxf(Z[q * CI + ci], 0.0f);
+                    x = bf16r(fmaxf(Z[q * CI + ci], 0.0f));
                 } else {
                     float f0, f1;
                     node_features(d, kind, a, psi, q, f0, f1);
-                    x = ci == 0 ? f0 : f1;
+                    x = bf16r(ci == 0 ? f0 : f1);
                 }
                 s += g * x;
             }
@@ -369,7 +397,10 @@ extern "C" int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const
     const NetOff off = net_offsets(d.T);
     const unsigned gr = grid_for(d.n, LNT);
     hipLaunchKernelGGL(k_net_l1, dim3(gr), dim3(LNT), sizeof(float) * off.w2, s, d, kind, a, psi, params, z1);
-    hipLaunchKernelGGL(k_net_l2, dim3(gr), dim3(LNT), sizeof(float) * off.w3, s, d, params, (const float*)z1, z2);
+    const int64_t waves2 = (d.n + 15) / 16;
+    const unsigned gr2 = (unsigned)((waves2 + LNT / WAVE - 1) / (LNT / WAVE));
+    hipLaunchKernelGGL(k_net_l2, dim3(gr2), dim3(LNT), sizeof(float) * NCH + sizeof(short) * NCH * NCH * d.T, s, d,
+                       params, (const float*)z1, z2);
     hipLaunchKernelGGL(k_net_l3, dim3(gr), dim3(LNT), sizeof(float) * off.total, s, d, kind, params,
                        (const float*)z2, o, omega);
     EB_LAUNCH_CHECK();

@@ -69,10 +69,26 @@ def test_forward_backward_against_oracle(name):
     o_g = ls.o.cpu().numpy()
     net = _net_dict(params, dim)
     o_o, cache = LN.forward(net, f, dim, precision="bf16")
-    assert np.max(np.abs(o_g - o_o.ravel())) <= 1e-5 * max(1.0, np.abs(o_o).max())
-    om_o = LN.omega_of(o_o.ravel().astype(np.float64), Ho.levels[0].omega)
+    # Layer by layer from the GPU's own previous layer: a layer's bf16 input
+    # rounding can land on the other side of a rounding boundary when the
+    # FP32 sums differ in order, so whole-network agreement is only to the
+    # bf16 step; each layer on the same input agrees to FP32 rounding.
+    shp = (16,) + tuple(prob.grid.shape)
+    Wd = {k: v.astype(np.float64) for k, v in cache["W"].items()}
+    z1g = ls.z1.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
+    z2g = ls.z2.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
+    z1o = LN.conv(cache["x0"].astype(np.float64), Wd["w1"], Wd["b1"], dim)
+    z2o = LN.conv(LN.bf16_round(np.maximum(z1g, 0)).astype(np.float64), Wd["w2"], Wd["b2"], dim)
+    oo = LN.conv(LN.bf16_round(np.maximum(z2g, 0)).astype(np.float64), Wd["w3"], Wd["b3"], dim)[0]
+    for got, ref, nm in ((z1g, z1o, "layer 1"), (z2g, z2o, "layer 2 (MFMA)"), (o_g.reshape(oo.shape), oo, "layer 3")):
+        err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+        print(f"  {nm}: max err {err:.2e}", flush=True)
+        assert err <= 2e-6, nm
+    # whole network: within a few bf16 steps of the oracle's own forward
+    assert np.abs(o_g - o_o.ravel()).max() <= 2e-2 * max(1.0, np.abs(o_o).max())
+    om_o = LN.omega_of(o_g.astype(np.float64), Ho.levels[0].omega)
     nodes = asm_o.nodes
-    assert rel(om_g[nodes], om_o[nodes]) <= 1e-6
+    assert rel(om_g[nodes], om_o[nodes]) <= 1e-12
     assert not np.any(om_g[asm_o.kind.ravel() != 2])
     # backward from a random dL/domega at the unknowns
     rng = np.random.default_rng(2)
@@ -88,8 +104,10 @@ def test_forward_backward_against_oracle(name):
     shp = (16,) + tuple(prob.grid.shape)
     z1g = ls.z1.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
     z2g = ls.z2.cpu().numpy().reshape(-1, 16).T.reshape(shp).astype(np.float64)
-    c64 = {"x0": cache["x0"].astype(np.float64), "z1": z1g, "y1": np.maximum(z1g, 0), "z2": z2g,
-           "y2": np.maximum(z2g, 0), "W": {kk: vv.astype(np.float64) for kk, vv in cache["W"].items()}}
+    c64 = {"x0": cache["x0"].astype(np.float64), "z1": z1g,
+           "y1": LN.bf16_round(np.maximum(z1g, 0)).astype(np.float64), "z2": z2g,
+           "y2": LN.bf16_round(np.maximum(z2g, 0)).astype(np.float64),
+           "W": {kk: vv.astype(np.float64) for kk, vv in cache["W"].items()}}
     g_o = LN.backward(c64, go.reshape(o_o.shape), dim)
     lo = 0
     for k in ("w1", "b1", "w2", "b2", "w3", "b3"):

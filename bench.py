@@ -288,10 +288,11 @@ def rocprof_summary(path, top=25):
     print("\n".join(out))
 
 
-# FP64 instantiations (the bench's headline path)
-KERNEL_SYMBOLS = {k: f"eb::k_{v}<double>" for k, v in {
-    "pcg_spmv": "pcg_p_spmv", "pcg_xr_down": "pcg_xr_down", "fine_down": "fine_down",
-    "fine_restrict": "fine_restrict", "fine_up": "fine_up", "fine_post": "fine_post"}.items()}
+# FP64 instantiations of the bench's headline path (plain smoother weights)
+KERNEL_SYMBOLS = {
+    "pcg_spmv": "eb::k_pcg_p_spmv<double>", "pcg_xr_down": "eb::k_pcg_xr_down<double, false>",
+    "fine_down": "eb::k_fine_down<double, false>", "fine_restrict": "eb::k_fine_restrict<double>",
+    "fine_up": "eb::k_fine_up<double, false>", "fine_post": "eb::k_fine_post<double, false>"}
 
 
 def _kernel_symbol(name):

@@ -325,6 +325,76 @@ __global__ void __launch_bounds__(LNT) k_net_wgrad(NetDims d, const float* __res
     }
 }
 
+// Layer-2 weight gradient on the matrix cores:
+//   gW2[co, ci, t] = sum_p gz2[p, co] bf16(relu(z1))[p + off_t, ci]
+// is, per tap, a 16 x 16 product over the nodes: v_mfma_f32_16x16x4_f32
+// takes 4 nodes at a time (A[m = co][k = node], B[k = node][n = ci]; lane l
+// holds A[l % 16][l / 16], B[l / 16][l % 16] and D rows 4 (l / 16) .. +3,
+// column l % 16).  Each wavefront sums its share of the block's node range;
+// the 4 wavefronts are added in LDS in wave order; the bias sums
+// gb2[co] = sum_p gz2[p, co] ride along in the A operand.  One partial per
+// block in the layout of k_net_wgrad.
+typedef float mf_f32x4b __attribute__((ext_vector_type(4)));
+
+template <int T>
+__global__ void __launch_bounds__(LNT) k_net_wgrad2(NetDims d, const float* __restrict__ gz2,
+                                                    const float* __restrict__ z1, int64_t per_block,
+                                                    float* __restrict__ part) {
+    __shared__ float red[T * NCH * NCH];
+    __shared__ float bred[LNT];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min(p0 + per_block, d.n);
+    mf_f32x4b acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = mf_f32x4b{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    const int c16 = lane % 16;
+    for (int64_t nb = p0 + 4 * w; nb < p1; nb += 4 * (LNT / WAVE)) {
+        const int64_t pk = nb + lane / 16;
+        const bool valid = pk < p1;
+        float a = 0.0f;
+        int i = 0, j = 0, k = 0;
+        if (valid) {
+            a = gz2[pk * NCH + c16];
+            node_ijk(d, pk, i, j, k);
+        }
+        bsum += a;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int64_t q = valid ? tap_node(d, i, j, k, t) : -1;
+            const float b = q >= 0 ? bf16r(fmaxf(z1[q * NCH + c16], 0.0f)) : 0.0f;
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    // wavefronts in order: red[t][co][ci]
+    for (int ww = 0; ww < LNT / WAVE; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = (t * NCH + 4 * (lane / 16) + r) * NCH + c16;
+                    red[idx] = (ww == 0 ? 0.0f : red[idx]) + acc[t][r];
+                }
+        }
+        __syncthreads();
+    }
+    bred[threadIdx.x] = bsum;
+    __syncthreads();
+    const int ne = NCH * NCH * T + NCH;
+    for (int e = threadIdx.x; e < NCH * NCH * T; e += LNT) {
+        const int co = e / (NCH * T), ci = (e / T) % NCH, t = e % T;
+        part[(int64_t)blockIdx.x * ne + e] = red[(t * NCH + co) * NCH + ci];
+    }
+    if (threadIdx.x < NCH) {
+        float b = 0.0f;   // lanes with l % 16 == co, in thread order
+        for (int tt = threadIdx.x; tt < LNT; tt += 16) b += bred[tt];
+        part[(int64_t)blockIdx.x * ne + NCH * NCH * T + threadIdx.x] = b;
+    }
+}
+
 // Sum of the block partials in block order into the gradient array.
 __global__ void __launch_bounds__(LNT) k_net_wsum(const float* __restrict__ part, int nblk, int ne,
                                                   float* __restrict__ out_w, float* __restrict__ out_b, int nw) {
@@ -443,8 +513,12 @@ extern "C" int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, cons
     }
     {
         const int ne = NCH * NCH * d.T + NCH;
-        hipLaunchKernelGGL((k_net_wgrad<NCH, NCH, 0>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1,
-                           kind, a, psi, per, part);
+        if (d.T == 27)
+            hipLaunchKernelGGL(k_net_wgrad2<27>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1, per,
+                               part);
+        else
+            hipLaunchKernelGGL(k_net_wgrad2<9>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1, per,
+                               part);
         hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
                            ne, grads + off.w2, grads + off.b2, NCH * NCH * d.T);
     }

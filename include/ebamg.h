@@ -224,7 +224,8 @@ int64_t eb_smoother_net_size(int32_t dim);
 
 /* Forward pass over the node grid.  kind, a, psi: node fields as produced by
  * eb_assemble_diag.  z1, z2 [out]: pre-activation fields of layers 1 and 2
- * (nodes x 16 FP32, node-major, channels fastest; kept for the backward pass);
+ * (nodes x 16 FP32, node-major, channels fastest; kept for the backward pass;
+ * z1 16-byte aligned, EB_EINVAL otherwise);
  * o [out]: the last layer (nodes FP32); omega [out]: node field of the
  * weights (0 off computational points).  Asynchronous.                       */
 int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,
@@ -233,7 +234,8 @@ int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const double* a,
 
 /* Gradient of a loss with respect to the parameters, given dL/domega (node
  * field; only computational points are read) and the forward pass's z1, z2,
- * o.  scratch: eb_smoother_scratch_floats(g) FP32 values of device memory;
+ * o.  scratch: eb_smoother_scratch_floats(g) FP32 values of device memory,
+ * 16-byte aligned (EB_EINVAL otherwise);
  * grads [out]: eb_smoother_net_size(dim) FP32 values.  Weight gradients are
  * summed in a fixed order (deterministic).  Asynchronous.                     */
 int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, const double* a, const double* psi,

@@ -249,79 +249,41 @@ __global__ void __launch_bounds__(LNT) k_net_b3(NetDims d, const float* __restri
     for (int c = 0; c < NCH; ++c) gz2[p * NCH + c] = z2[p * NCH + c] > 0.0f ? acc[c] : 0.0f;
 }
 
-// gz1[ci] = (sum_{t, c} W2[c, ci, t] gz2[p - off_t, c]) * (z1 > 0)
-__global__ void __launch_bounds__(LNT) k_net_b2(NetDims d, const float* __restrict__ params,
-                                                const float* __restrict__ gz2, const float* __restrict__ z1,
-                                                float* __restrict__ gz1) {
-    extern __shared__ float lp[];
+// gz1[ci] = (sum_{t, c} W2[c, ci, t] gz2[p - off_t, c]) * (z1 > 0) on the
+// matrix cores: a wavefront takes 16 consecutive nodes; per tap, four
+// v_mfma_f32_16x16x4_f32 over the input channels c (lane l's k = l / 16 is
+// c = 4 (l / 16) + kc in the kc-th), D[m = node][n = ci].
+__global__ void __launch_bounds__(LNT) k_net_b2m(NetDims d, const float* __restrict__ params,
+                                                 const float* __restrict__ gz2, const float* __restrict__ z1,
+                                                 float* __restrict__ gz1) {
+    extern __shared__ float lp[];                        // W2 rounded to bf16, [c][ci][t]
     const NetOff o = net_offsets(d.T);
-    load_params(params, lp, o.w3, o);
-    const int64_t p = (int64_t)blockIdx.x * LNT + threadIdx.x;
-    if (p >= d.n) return;
-    int i, j, k;
-    node_ijk(d, p, i, j, k);
-    float acc[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) acc[c] = 0.0f;
+    for (int e = threadIdx.x; e < NCH * NCH * d.T; e += LNT) lp[e] = bf16r(params[o.w2 + e]);
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t base = ((int64_t)blockIdx.x * (LNT / WAVE) + threadIdx.x / WAVE) * 16;
+    if (base >= d.n) return;                             // whole wavefront
+    const int m = lane % 16, kg = lane / 16;
+    const int64_t pm = base + m;
+    int i = 0, j = 0, k = 0;
+    const bool mvalid = pm < d.n;
+    if (mvalid) node_ijk(d, pm, i, j, k);
+    mf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < d.T; ++t) {
-        const int64_t q = tap_node(d, i, j, k, d.T - 1 - t);
-        if (q < 0) continue;
-        float g[NCH];
+        const int64_t q = mvalid ? tap_node(d, i, j, k, d.T - 1 - t) : -1;
+        float4 gv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q >= 0) gv = *reinterpret_cast<const float4*>(gz2 + q * NCH + 4 * kg);
+        const float gk[4] = {gv.x, gv.y, gv.z, gv.w};
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) g[c] = gz2[q * NCH + c];
-#pragma unroll
-        for (int ci = 0; ci < NCH; ++ci) {
-            float s = 0.0f;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) s += lp[o.w2 + ((int64_t)c * NCH + ci) * d.T + t] * g[c];
-            acc[ci] += s;
+        for (int kc = 0; kc < 4; ++kc) {
+            const float b = lp[((4 * kg + kc) * NCH + m) * d.T + t];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gk[kc], b, acc, 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) gz1[p * NCH + c] = z1[p * NCH + c] > 0.0f ? acc[c] : 0.0f;
-}
-
-// Weight gradients of one layer, as per-block partials:
-//   gW[co, ci, t] = sum_p G[p, co] X[p + off_t, ci],  gb[co] = sum_p G[p, co]
-// X = relu(Z) (layers 2, 3) or the features (layer 1).  Each block owns a
-// contiguous node range; thread e owns entries e, e + LNT, ... and sums over
-// the range in node order.  part[block][CO*CI*T + CO].
-template <int CO, int CI, int XMODE>   // XMODE 0: relu(z) rows of CI, 1: features
-__global__ void __launch_bounds__(LNT) k_net_wgrad(NetDims d, const float* __restrict__ G,
-                                                   const float* __restrict__ Z, const int8_t* __restrict__ kind,
-                                                   const double* __restrict__ a, const double* __restrict__ psi,
-                                                   int64_t per_block, float* __restrict__ part) {
-    const int ne = CO * CI * d.T + CO;
-    const int64_t p0 = (int64_t)blockIdx.x * per_block;
-    const int64_t p1 = min(p0 + per_block, d.n);
-    for (int e = threadIdx.x; e < ne; e += LNT) {
-        float s = 0.0f;
-        if (e < CO * CI * d.T) {
-            const int co = e / (CI * d.T);
-            const int ci = (e / d.T) % CI;
-            const int t = e % d.T;
-            for (int64_t p = p0; p < p1; ++p) {
-                const float g = G[p * CO + co];
-                if (g == 0.0f) continue;
-                int i, j, k;
-                node_ijk(d, p, i, j, k);
-                const int64_t q = tap_node(d, i, j, k, t);
-                if (q < 0) continue;
-                float x;
-                if (XMODE == 0) {
-                    x = bf16r(fmaxf(Z[q * CI + ci], 0.0f));
-                } else {
-                    float f0, f1;
-                    node_features(d, kind, a, psi, q, f0, f1);
-                    x = bf16r(ci == 0 ? f0 : f1);
-                }
-                s += g * x;
-            }
-        } else {
-            const int co = e - CO * CI * d.T;
-            for (int64_t p = p0; p < p1; ++p) s += G[p * CO + co];
-        }
-        part[(int64_t)blockIdx.x * ne + e] = s;
+    for (int r = 0; r < 4; ++r) {
+        const int64_t pn = base + 4 * kg + r;
+        if (pn < d.n) gz1[pn * NCH + m] = z1[pn * NCH + m] > 0.0f ? acc[r] : 0.0f;
     }
 }
 
@@ -332,10 +294,11 @@ __global__ void __launch_bounds__(LNT) k_net_wgrad(NetDims d, const float* __res
 // holds A[l % 16][l / 16], B[l / 16][l % 16] and D rows 4 (l / 16) .. +3,
 // column l % 16).  Each wavefront sums its share of the block's node range;
 // the 4 wavefronts are added in LDS in wave order; the bias sums
-// gb2[co] = sum_p gz2[p, co] ride along in the A operand.  One partial per
-// block in the layout of k_net_wgrad.
-typedef float mf_f32x4b __attribute__((ext_vector_type(4)));
-
+// gb2[co] = sum_p gz2[p, co] ride along in the A operand.
+//
+// The three weight-gradient kernels give one partial per block, in the
+// parameter order of the layer: part[block][co][ci][t], then the CO bias
+// sums; each block owns a contiguous node range.
 template <int T>
 __global__ void __launch_bounds__(LNT) k_net_wgrad2(NetDims d, const float* __restrict__ gz2,
                                                     const float* __restrict__ z1, int64_t per_block,
@@ -346,9 +309,9 @@ __global__ void __launch_bounds__(LNT) k_net_wgrad2(NetDims d, const float* __re
     const int w = threadIdx.x / WAVE;
     const int64_t p0 = (int64_t)blockIdx.x * per_block;
     const int64_t p1 = min(p0 + per_block, d.n);
-    mf_f32x4b acc[T];
+    mf_f32x4 acc[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] = mf_f32x4b{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < T; ++t) acc[t] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
     const int c16 = lane % 16;
     for (int64_t nb = p0 + 4 * w; nb < p1; nb += 4 * (LNT / WAVE)) {
@@ -395,15 +358,165 @@ __global__ void __launch_bounds__(LNT) k_net_wgrad2(NetDims d, const float* __re
     }
 }
 
-// Sum of the block partials in block order into the gradient array.
+// Layer-1 weight gradient on the matrix cores:
+//   gW1[co, ci, t] = sum_p gz1[p, co] bf16(f_ci)[p + off_t]
+// The 2 x T (channel, tap) columns go 8 taps at a time into the 16 columns
+// of one v_mfma_f32_16x16x4_f32 (n = 8 ci + tt, tap t = 8 g + tt); each
+// lane computes the one feature its column needs.
+template <int T>
+__global__ void __launch_bounds__(LNT) k_net_wgrad1(NetDims d, const float* __restrict__ gz1,
+                                                    const int8_t* __restrict__ kind, const double* __restrict__ a,
+                                                    const double* __restrict__ psi, int64_t per_block,
+                                                    float* __restrict__ part) {
+    constexpr int G = (T + 7) / 8;
+    __shared__ float red[G * NCH * NCH];
+    __shared__ float bred[LNT];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min(p0 + per_block, d.n);
+    mf_f32x4 acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    const int c16 = lane % 16;
+    const int ci = c16 / 8, tt = c16 % 8;
+    for (int64_t nb = p0 + 4 * w; nb < p1; nb += 4 * (LNT / WAVE)) {
+        const int64_t pk = nb + lane / 16;
+        const bool valid = pk < p1;
+        float av = 0.0f;
+        int i = 0, j = 0, k = 0;
+        if (valid) {
+            av = gz1[pk * NCH + c16];
+            node_ijk(d, pk, i, j, k);
+        }
+        bsum += av;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int t = 8 * g + tt;
+            const int64_t q = (valid && t < T) ? tap_node(d, i, j, k, t) : -1;
+            float b = 0.0f;
+            if (q >= 0) {
+                float f0, f1;
+                node_features(d, kind, a, psi, q, f0, f1);
+                b = bf16r(ci == 0 ? f0 : f1);
+            }
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[g], 0, 0, 0);
+        }
+    }
+    for (int ww = 0; ww < LNT / WAVE; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = (g * NCH + 4 * (lane / 16) + r) * NCH + c16;
+                    red[idx] = (ww == 0 ? 0.0f : red[idx]) + acc[g][r];
+                }
+        }
+        __syncthreads();
+    }
+    bred[threadIdx.x] = bsum;
+    __syncthreads();
+    const int ne = NCH * 2 * T + NCH;
+    for (int e = threadIdx.x; e < NCH * 2 * T; e += LNT) {
+        const int co = e / (2 * T), cc = (e / T) % 2, t = e % T;
+        part[(int64_t)blockIdx.x * ne + e] = red[((t / 8) * NCH + co) * NCH + 8 * cc + t % 8];
+    }
+    if (threadIdx.x < NCH) {
+        float b = 0.0f;
+        for (int u = threadIdx.x; u < LNT; u += 16) b += bred[u];
+        part[(int64_t)blockIdx.x * ne + NCH * 2 * T + threadIdx.x] = b;
+    }
+}
+
+// Layer-3 weight gradient on the matrix cores, summed over the tap's end
+// node q = p + off_t instead of p:
+//   gW3[0, ci, t] = sum_q go[q - off_t] bf16(relu(z2))[q, ci]
+// with the taps as the 16 rows of one v_mfma_f32_16x16x4_f32 (t = 16 g + m;
+// q - off_t is the mirrored tap since the taps are symmetric).
+template <int T>
+__global__ void __launch_bounds__(LNT) k_net_wgrad3(NetDims d, const float* __restrict__ go,
+                                                    const float* __restrict__ z2, int64_t per_block,
+                                                    float* __restrict__ part) {
+    constexpr int G = (T + 15) / 16;
+    __shared__ float red[G * NCH * NCH];
+    __shared__ float bred[LNT];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int64_t p0 = (int64_t)blockIdx.x * per_block;
+    const int64_t p1 = min(p0 + per_block, d.n);
+    mf_f32x4 acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    const int c16 = lane % 16;
+    for (int64_t nb = p0 + 4 * w; nb < p1; nb += 4 * (LNT / WAVE)) {
+        const int64_t qk = nb + lane / 16;
+        const bool valid = qk < p1;
+        float b = 0.0f;
+        int i = 0, j = 0, k = 0;
+        if (valid) {
+            b = bf16r(fmaxf(z2[qk * NCH + c16], 0.0f));
+            node_ijk(d, qk, i, j, k);
+            if (c16 == 0) bsum += go[qk];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int t = 16 * g + c16;
+            const int64_t p = (valid && t < T) ? tap_node(d, i, j, k, T - 1 - t) : -1;
+            const float av = p >= 0 ? go[p] : 0.0f;
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[g], 0, 0, 0);
+        }
+    }
+    // red[g][m = t % 16][ci]
+    for (int ww = 0; ww < LNT / WAVE; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = (g * NCH + 4 * (lane / 16) + r) * NCH + c16;
+                    red[idx] = (ww == 0 ? 0.0f : red[idx]) + acc[g][r];
+                }
+        }
+        __syncthreads();
+    }
+    bred[threadIdx.x] = bsum;
+    __syncthreads();
+    const int ne = NCH * T + 1;
+    for (int e = threadIdx.x; e < NCH * T; e += LNT) {
+        const int cc = e / T, t = e % T;
+        part[(int64_t)blockIdx.x * ne + e] = red[t * NCH + cc];   // (t / 16) * 256 + (t % 16) * 16 = 16 t
+    }
+    if (threadIdx.x == 0) {
+        float bb = 0.0f;
+        for (int u = 0; u < LNT; u += 16) bb += bred[u];
+        part[(int64_t)blockIdx.x * ne + NCH * T] = bb;
+    }
+}
+
+// Sum of the block partials into the gradient array in a fixed order: each
+// block takes 32 entries; slice sl of its 8 sums partials sl, sl + 8, ...
+// in order, then the slices are added in order.
+constexpr int WS_E = 32, WS_S = LNT / WS_E;
+
 __global__ void __launch_bounds__(LNT) k_net_wsum(const float* __restrict__ part, int nblk, int ne,
                                                   float* __restrict__ out_w, float* __restrict__ out_b, int nw) {
-    const int e = blockIdx.x * LNT + threadIdx.x;
-    if (e >= ne) return;
+    __shared__ double red[WS_S][WS_E];
+    const int el = threadIdx.x % WS_E, sl = threadIdx.x / WS_E;
+    const int e = blockIdx.x * WS_E + el;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ne + e];
-    if (e < nw) out_w[e] = (float)s;
-    else out_b[e - nw] = (float)s;
+    if (e < ne)
+        for (int b = sl; b < nblk; b += WS_S) s += part[(int64_t)b * ne + e];
+    red[sl][el] = s;
+    __syncthreads();
+    if (sl == 0 && e < ne) {
+        double t = 0.0;
+        for (int u = 0; u < WS_S; ++u) t += red[u][el];
+        if (e < nw) out_w[e] = (float)t;
+        else out_b[e - nw] = (float)t;
+    }
 }
 
 // Adam on FP32 parameters (bias-corrected moments).
@@ -440,6 +553,8 @@ static int net_dims(const eb_grid_t* g, double omega0, NetDims* nd) {
 
 constexpr int WGRAD_BLOCKS = 1024;
 
+inline int64_t round_up4(int64_t n) { return (n + 3) / 4 * 4; }
+
 }  // namespace eb
 
 using namespace eb;
@@ -459,6 +574,10 @@ extern "C" int eb_smoother_forward(const eb_grid_t* g, const int8_t* kind, const
     }
     if (!(omega0 > 0.0)) {
         set_error("eb_smoother_forward: omega0 must be positive");
+        return EB_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(z1) % 16) {
+        set_error("eb_smoother_forward: z1 must be 16-byte aligned");
         return EB_EINVAL;
     }
     NetDims d;
@@ -486,47 +605,67 @@ extern "C" int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, cons
         set_error("eb_smoother_backward: null pointer");
         return EB_EINVAL;
     }
+    if (reinterpret_cast<uintptr_t>(scratch) % 16) {
+        set_error("eb_smoother_backward: scratch must be 16-byte aligned");
+        return EB_EINVAL;
+    }
     NetDims d;
     EB_TRY(net_dims(g, omega0, &d));
     hipStream_t s = (hipStream_t)stream;
     const NetOff off = net_offsets(d.T);
     const unsigned gr = grid_for(d.n, LNT);
-    // scratch: go [n], gz2 [16 n], gz1 [16 n], partials [WGRAD_BLOCKS * (16*16*T + 16)]
+    // scratch: go [n, padded to 4], gz2 [16 n], gz1 [16 n],
+    // partials [WGRAD_BLOCKS * (16*16*T + 16)]; gz2 rows are read as float4
     float* go = scratch;
-    float* gz2 = go + d.n;
+    float* gz2 = go + round_up4(d.n);
     float* gz1 = gz2 + d.n * NCH;
     float* part = gz1 + d.n * NCH;
     hipLaunchKernelGGL(k_net_go, dim3(gr), dim3(LNT), 0, s, d, kind, o, grad_omega, go);
     hipLaunchKernelGGL(k_net_b3, dim3(gr), dim3(LNT), sizeof(float) * off.total, s, d, params, (const float*)go, z2,
                        gz2);
-    hipLaunchKernelGGL(k_net_b2, dim3(gr), dim3(LNT), sizeof(float) * off.w3, s, d, params, (const float*)gz2, z1,
-                       gz1);
+    {
+        const int64_t waves = (d.n + 15) / 16;
+        const unsigned grw = (unsigned)((waves + LNT / WAVE - 1) / (LNT / WAVE));
+        hipLaunchKernelGGL(k_net_b2m, dim3(grw), dim3(LNT), sizeof(float) * NCH * NCH * d.T, s, d, params,
+                           (const float*)gz2, z1, gz1);
+    }
     EB_LAUNCH_CHECK();
     const int64_t per = (d.n + WGRAD_BLOCKS - 1) / WGRAD_BLOCKS;
+    const bool d3 = d.T == 27;
     // layer 3: CO = 1, CI = 16, X = relu(z2)
     {
-        const int ne = 1 * NCH * d.T + 1;
-        hipLaunchKernelGGL((k_net_wgrad<1, NCH, 0>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)go, z2,
-                           kind, a, psi, per, part);
-        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+        const int ne = NCH * d.T + 1;
+        if (d3)
+            hipLaunchKernelGGL(k_net_wgrad3<27>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)go, z2, per,
+                               part);
+        else
+            hipLaunchKernelGGL(k_net_wgrad3<9>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)go, z2, per,
+                               part);
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, WS_E)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
                            ne, grads + off.w3, grads + off.b3, NCH * d.T);
     }
+    // layer 2: CO = CI = 16, X = relu(z1)
     {
         const int ne = NCH * NCH * d.T + NCH;
-        if (d.T == 27)
+        if (d3)
             hipLaunchKernelGGL(k_net_wgrad2<27>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1, per,
                                part);
         else
             hipLaunchKernelGGL(k_net_wgrad2<9>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz2, z1, per,
                                part);
-        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, WS_E)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
                            ne, grads + off.w2, grads + off.b2, NCH * NCH * d.T);
     }
+    // layer 1: CO = 16, CI = 2, X = the features
     {
         const int ne = NCH * 2 * d.T + NCH;
-        hipLaunchKernelGGL((k_net_wgrad<NCH, 2, 1>), dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz1,
-                           (const float*)nullptr, kind, a, psi, per, part);
-        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, LNT)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
+        if (d3)
+            hipLaunchKernelGGL(k_net_wgrad1<27>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz1, kind, a,
+                               psi, per, part);
+        else
+            hipLaunchKernelGGL(k_net_wgrad1<9>, dim3(WGRAD_BLOCKS), dim3(LNT), 0, s, d, (const float*)gz1, kind, a,
+                               psi, per, part);
+        hipLaunchKernelGGL(k_net_wsum, dim3(grid_for(ne, WS_E)), dim3(LNT), 0, s, (const float*)part, WGRAD_BLOCKS,
                            ne, grads + off.w1, grads + off.b1, NCH * 2 * d.T);
     }
     EB_LAUNCH_CHECK();
@@ -536,7 +675,7 @@ extern "C" int eb_smoother_backward(const eb_grid_t* g, const int8_t* kind, cons
 extern "C" int64_t eb_smoother_scratch_floats(const eb_grid_t* g) {
     NetDims d;
     if (!g || net_dims(g, 1.0, &d) != EB_OK) return -1;
-    return d.n * (1 + 2 * NCH) + (int64_t)WGRAD_BLOCKS * (NCH * NCH * d.T + NCH);
+    return round_up4(d.n) + d.n * 2 * NCH + (int64_t)WGRAD_BLOCKS * (NCH * NCH * d.T + NCH);
 }
 
 extern "C" int eb_adam_step(float* params, const float* grads, float* m, float* v, int64_t n, int32_t t, float lr,

@@ -45,8 +45,12 @@ computed, written out plainly:
     u = g - A (W g),   v = u - A P E_c R u.
   dL/domega_k = dL/dW_k / A_kk, then through tanh and the three convolutions.
 * Training: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights.
-  Error samples come from the plain solver: e = (I - M_0 A)^2 xi, xi ~ N(0, 1)
-  seeded, M_0 the plain V-cycle (errors the plain preconditioner leaves).
+  Error samples are errors a cycle leaves: starting from seeded xi ~ N(0, 1)
+  at the unknowns, e = (I - M A)^sweeps xi scaled to unit 2-norm (scaling
+  after every sweep or once at the end gives the same vector up to
+  rounding).  error_samples below uses the plain cycle M_0; the GPU training
+  loop draws them with the cycle of the current weights (the same sweep with
+  vcycle_weighted).
 
 Parity: pinned by tests/test_oracle_learned.py (convolution against a dense
 brute-force sum; network gradients and dL/domega against central finite

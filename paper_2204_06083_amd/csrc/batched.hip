@@ -21,6 +21,7 @@
 #include <stddef.h>
 #include <string.h>
 
+
 #include "handle.hpp"
 
 namespace eb {
@@ -69,6 +70,12 @@ struct BatchBufs {
     double* part_aux = nullptr;
     BatchState* st = nullptr;
     BatchState host;
+    // layout and launch shape of the fine kernels: plane width (slots per
+    // plane, node-major inside a plane) and planes per block (the grid's y
+    // dimension covers the rest); chosen by timing 8/16/32/64 and 1/2/4/8 on
+    // the 64-RHS heat workload
+    int kbw = 8;
+    int npb = 2;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -129,8 +136,17 @@ __device__ inline double bfin_sum(const double* __restrict__ part, int np, int k
     const int j = threadIdx.x & (kp - 1);
     const int u = threadIdx.x / kp;
     const int g = BFIN / kp;
+    // all of a thread's partials are loaded before they are added (in order)
+    constexpr int MAXL = BPARTS * BMAX_RHS / BFIN;
+    double v[MAXL];
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) {
+        const int b = u + i * g;
+        v[i] = b < np ? part[(int64_t)b * kp + j] : 0.0;
+    }
     double a = 0.0;
-    for (int b = u; b < np; b += g) a += part[(int64_t)b * kp + j];
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) a += v[i];
     lds[threadIdx.x] = a;
     __syncthreads();
     double t = 0.0;
@@ -244,13 +260,14 @@ __global__ void __launch_bounds__(BFIN) kb_fin_true(BatchState* st, const double
 template <int NPL>
 __device__ inline void bpartials(const double (&acc)[NPL], double* __restrict__ part, const BFine& f) {
 #pragma unroll
-    for (int jb = 0; jb < NPL; ++jb) bpartial(acc[jb], part, f.kp, f.kb, jb);
+    for (int jb = 0; jb < NPL; ++jb) bpartial(acc[jb], part, f.kp, f.kb, (int)blockIdx.y * NPL + jb);
 }
 
 // out = b - A x, partial ||out||^2 per rhs (FP64; every slot).
 template <int NPL>
 __global__ void __launch_bounds__(BNT) kb_resid(BFine f, const double* __restrict__ b, const double* __restrict__ x,
                                                 double* __restrict__ out, double* __restrict__ part) {
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
     double acc[NPL];
 #pragma unroll
     for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
@@ -260,7 +277,7 @@ __global__ void __launch_bounds__(BNT) kb_resid(BFine f, const double* __restric
         if (d != 0.0) {
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const int64_t v = v0 + jb * f.plane;
+                const int64_t v = v0 + (pb + jb) * f.plane;
                 double nb = x[v - ox] + x[v + ox] + x[v - sy] + x[v + sy];
                 if (f.dim == 3) nb += x[v - sz] + x[v + sz];
                 const double rv = b[v] - (d * x[v] - f.s * nb);
@@ -274,6 +291,7 @@ __global__ void __launch_bounds__(BNT) kb_resid(BFine f, const double* __restric
 
 template <int NPL>
 __global__ void __launch_bounds__(BNT) kb_norm2(BFine f, const double* __restrict__ a, double* __restrict__ part) {
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
     double acc[NPL];
 #pragma unroll
     for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
@@ -281,7 +299,7 @@ __global__ void __launch_bounds__(BNT) kb_norm2(BFine f, const double* __restric
         if (f.diag[p] != 0.0) {
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const double t = a[v0 + jb * f.plane];
+                const double t = a[v0 + (pb + jb) * f.plane];
                 acc[jb] += t * t;
             }
         }
@@ -293,6 +311,7 @@ __global__ void __launch_bounds__(BNT) kb_norm2(BFine f, const double* __restric
 template <class V, int NPL>
 __global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const double* __restrict__ r,
                                                     V* __restrict__ res) {
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
     const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
     BNODE_LOOP(f, p, jj, v0) {
         const double d = f.diag[p];
@@ -301,8 +320,8 @@ __global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const
             const double dzm = f.dim == 3 ? f.diag[p - f.sz] : 0.0, dzp = f.dim == 3 ? f.diag[p + f.sz] : 0.0;
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                if (f.done[(jb << f.lkb) + jj]) continue;
-                const int64_t v = v0 + jb * f.plane;
+                if (f.done[((pb + jb) << f.lkb) + jj]) continue;
+                const int64_t v = v0 + (pb + jb) * f.plane;
                 double nb = bsafe_div(r[v - ox], dxm) + bsafe_div(r[v + ox], dxp);
                 nb += bsafe_div(r[v - sy], dym) + bsafe_div(r[v + sy], dyp);
                 if (f.dim == 3) nb += bsafe_div(r[v - sz], dzm) + bsafe_div(r[v + sz], dzp);
@@ -313,29 +332,77 @@ __global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const
     }
 }
 
+// The per-iteration fine kernels below first read a thread's slot state
+// (fixed for the whole kernel: BNT is a multiple of kb), then, per node, issue
+// the loads of all its planes before any arithmetic or store, so that the
+// planes' loads are in flight together.
+template <class T>
+struct St {
+    T c, xm, xp, ym, yp, zm, zp;
+};
+
+template <class T>
+__device__ inline St<T> ld_st(const T* __restrict__ a, int64_t v, int64_t ox, int64_t sy, int64_t sz, bool d3) {
+    St<T> r;
+    r.c = a[v];
+    r.xm = a[v - ox];
+    r.xp = a[v + ox];
+    r.ym = a[v - sy];
+    r.yp = a[v + sy];
+    r.zm = d3 ? a[v - sz] : T(0);
+    r.zp = d3 ? a[v + sz] : T(0);
+    return r;
+}
+
+template <class T>
+__device__ inline St<T> st_zero() {
+    return {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+}
+
 // p_new = z + beta p_old; q = A p_new; partial (p_new, q).
 template <class V, int NPL>
 __global__ void __launch_bounds__(BNT) kb_pspmv(BFine f, const V* __restrict__ z, const double* __restrict__ pold,
                                                 double* __restrict__ pnew, double* __restrict__ q,
                                                 const BatchState* __restrict__ st, double* __restrict__ part) {
-    double acc[NPL];
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int jt = (int)threadIdx.x & (f.kb - 1);
+    bool act[NPL];
+    double beta[NPL], acc[NPL];
 #pragma unroll
-    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    for (int jb = 0; jb < NPL; ++jb) {
+        const int j = ((pb + jb) << f.lkb) + jt;
+        act[jb] = f.done[j] == 0;
+        beta[jb] = st->beta[j];
+        acc[jb] = 0.0;
+    }
     const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    const bool d3 = f.dim == 3;
     BNODE_LOOP(f, p, jj, v0) {
         const double d = f.diag[p];
         if (d != 0.0) {
+            St<V> zs[NPL];
+            St<double> ps[NPL];
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const int j = (jb << f.lkb) + (int)jj;
-                if (f.done[j]) continue;
-                const double beta = st->beta[j];
-                const int64_t v = v0 + jb * f.plane;
-                auto pv = [&](int64_t w) { return beta != 0.0 ? (double)z[w] + beta * pold[w] : (double)z[w]; };
-                const double pc = pv(v);
-                double nb = pv(v - ox) + pv(v + ox) + pv(v - sy) + pv(v + sy);
-                if (f.dim == 3) nb += pv(v - sz) + pv(v + sz);
+                zs[jb] = st_zero<V>();
+                ps[jb] = st_zero<double>();
+                if (!act[jb]) continue;
+                const int64_t v = v0 + (pb + jb) * f.plane;
+                zs[jb] = ld_st(z, v, ox, sy, sz, d3);
+                if (beta[jb] != 0.0) ps[jb] = ld_st(pold, v, ox, sy, sz, d3);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                if (!act[jb]) continue;
+                const double be = beta[jb];
+                auto pv = [&](V zz, double pp) { return be != 0.0 ? (double)zz + be * pp : (double)zz; };
+                const St<V>& a = zs[jb];
+                const St<double>& b = ps[jb];
+                const double pc = pv(a.c, b.c);
+                double nb = pv(a.xm, b.xm) + pv(a.xp, b.xp) + pv(a.ym, b.ym) + pv(a.yp, b.yp);
+                if (d3) nb += pv(a.zm, b.zm) + pv(a.zp, b.zp);
                 const double qv = d * pc - f.s * nb;
+                const int64_t v = v0 + (pb + jb) * f.plane;
                 pnew[v] = pc;
                 q[v] = qv;
                 acc[jb] += pc * qv;
@@ -351,32 +418,57 @@ __global__ void __launch_bounds__(BNT) kb_xr_down(BFine f, double* __restrict__ 
                                                   double* __restrict__ rout, const double* __restrict__ pv,
                                                   const double* __restrict__ q, V* __restrict__ res, double omega,
                                                   const BatchState* __restrict__ st, double* __restrict__ part) {
-    double acc[NPL];
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int jt = (int)threadIdx.x & (f.kb - 1);
+    bool act[NPL];
+    double alpha[NPL], acc[NPL];
 #pragma unroll
-    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    for (int jb = 0; jb < NPL; ++jb) {
+        const int j = ((pb + jb) << f.lkb) + jt;
+        act[jb] = f.done[j] == 0;
+        alpha[jb] = st->alpha[j];
+        acc[jb] = 0.0;
+    }
     const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    const bool d3 = f.dim == 3;
     BNODE_LOOP(f, p, jj, v0) {
         const double d = f.diag[p];
         if (d != 0.0) {
             const double dxm = f.diag[p - 1], dxp = f.diag[p + 1], dym = f.diag[p - f.sy], dyp = f.diag[p + f.sy];
-            const double dzm = f.dim == 3 ? f.diag[p - f.sz] : 0.0, dzp = f.dim == 3 ? f.diag[p + f.sz] : 0.0;
+            const double dzm = d3 ? f.diag[p - f.sz] : 0.0, dzp = d3 ? f.diag[p + f.sz] : 0.0;
+            St<double> rs[NPL], qs[NPL];
+            double xc[NPL], pc[NPL];
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const int j = (jb << f.lkb) + (int)jj;
-                if (f.done[j]) continue;
-                const double al = st->alpha[j];
-                const int64_t v = v0 + jb * f.plane;
-                x[v] = x[v] + al * pv[v];
-                const double rn = rin[v] - al * q[v];
+                rs[jb] = st_zero<double>();
+                qs[jb] = st_zero<double>();
+                xc[jb] = 0.0;
+                pc[jb] = 0.0;
+                if (!act[jb]) continue;
+                const int64_t v = v0 + (pb + jb) * f.plane;
+                xc[jb] = x[v];
+                pc[jb] = pv[v];
+                rs[jb] = ld_st(rin, v, ox, sy, sz, d3);
+                qs[jb] = ld_st(q, v, ox, sy, sz, d3);
+            }
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                if (!act[jb]) continue;
+                const double al = alpha[jb];
+                const St<double>& a = rs[jb];
+                const St<double>& b = qs[jb];
+                const int64_t v = v0 + (pb + jb) * f.plane;
+                x[v] = xc[jb] + al * pc[jb];
+                const double rn = a.c - al * b.c;
                 rout[v] = rn;
                 acc[jb] += rn * rn;
-                double nb = bsafe_div(rin[v - ox] - al * q[v - ox], dxm);
-                nb += bsafe_div(rin[v + ox] - al * q[v + ox], dxp);
-                nb += bsafe_div(rin[v - sy] - al * q[v - sy], dym);
-                nb += bsafe_div(rin[v + sy] - al * q[v + sy], dyp);
-                if (f.dim == 3) {
-                    nb += bsafe_div(rin[v - sz] - al * q[v - sz], dzm);
-                    nb += bsafe_div(rin[v + sz] - al * q[v + sz], dzp);
+                double nb = bsafe_div(a.xm - al * b.xm, dxm);
+                nb += bsafe_div(a.xp - al * b.xp, dxp);
+                nb += bsafe_div(a.ym - al * b.ym, dym);
+                nb += bsafe_div(a.yp - al * b.yp, dyp);
+                if (d3) {
+                    nb += bsafe_div(a.zm - al * b.zm, dzm);
+                    nb += bsafe_div(a.zp - al * b.zp, dzp);
                 }
                 const double z1 = omega * rn / d;
                 res[v] = (V)(rn - (d * z1 - f.s * (omega * nb)));
@@ -398,7 +490,7 @@ struct BBox {
     const int32_t* agg;
 };
 
-template <class V>
+template <class V, int DIM>
 __global__ void __launch_bounds__(256) kb_restrict(BFine f, BBox b, double omega_d, const V* __restrict__ res,
                                                    V* __restrict__ rc) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -409,7 +501,6 @@ __global__ void __launch_bounds__(256) kb_restrict(BFine f, BBox b, double omega
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
     const int64_t kp = f.kp;
-    const int64_t dx = f.kb, dy = f.sy * f.kb, dz = f.sz * f.kb;   // fine-index strides
     const int64_t box = b.boxes[bi];
     const int bx = (int)(box % b.nbx);
     const int64_t rq = box / b.nbx;
@@ -417,39 +508,86 @@ __global__ void __launch_bounds__(256) kb_restrict(BFine f, BBox b, double omega
     const int bz = (int)(rq / b.nby);
     const int32_t c0 = b.cstart[box];
     const int m = b.ncomp[box];
-    V acc[BMAX_FINE_COMP];
+    if (DIM == 2) {
+        // The box's 3 x 3 nodes and their neighbours (a 5 x 5 window without
+        // its corners) are loaded first; window points off the node grid read
+        // as 0 (they neighbour no unknown: the outer node layer is outside).
+        // Each node's contribution u goes to its component; the components'
+        // sums are then formed in node order.
+        V rw[5][5], dw[5][5];
 #pragma unroll
-    for (int c = 0; c < BMAX_FINE_COMP; ++c) acc[c] = V(0);
-    const int z_hi = f.dim == 3 ? 3 : 1;
-    for (int oz = 0; oz < z_hi; ++oz) {
-        const int k = f.dim == 3 ? 3 * bz + oz : 0;
-        if (k >= b.nz) break;
-        for (int oy = 0; oy < 3; ++oy) {
-            const int jj = 3 * by + oy;
-            if (jj >= b.ny) break;
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                rw[a][c] = V(0);
+                dw[a][c] = V(0);
+                if ((a == 0 || a == 4) && (c == 0 || c == 4)) continue;
+                const int i = 3 * bx - 1 + c, jj = 3 * by - 1 + a;
+                if (i < 0 || i >= b.nx || jj < 0 || jj >= b.ny) continue;
+                const int64_t p = (int64_t)i + f.sy * jj;
+                dw[a][c] = dg[p];
+                rw[a][c] = res[bvidx(f, p, j)];
+            }
+        V u[9];
+        int comp[9];
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
             for (int ox = 0; ox < 3; ++ox) {
-                const int i = 3 * bx + ox;
-                if (i >= b.nx) break;
-                const int64_t p = (int64_t)i + f.sy * jj + f.sz * k;
-                const V d = dg[p];
+                const int a = oy + 1, c = ox + 1, n = 3 * oy + ox;
+                const V d = dw[a][c];
+                u[n] = V(0);
+                comp[n] = -1;
                 if (d == V(0)) continue;
-                const int64_t v = bvidx(f, p, j);
-                const V rp = res[v];
-                V nb = bsafe_div(res[v - dx], dg[p - 1]) + bsafe_div(res[v + dx], dg[p + 1]);
-                nb += bsafe_div(res[v - dy], dg[p - f.sy]) + bsafe_div(res[v + dy], dg[p + f.sy]);
-                if (f.dim == 3) nb += bsafe_div(res[v - dz], dg[p - f.sz]) + bsafe_div(res[v + dz], dg[p + f.sz]);
+                const V rp = rw[a][c];
+                V nb = bsafe_div(rw[a][c - 1], dw[a][c - 1]) + bsafe_div(rw[a][c + 1], dw[a][c + 1]);
+                nb += bsafe_div(rw[a - 1][c], dw[a - 1][c]) + bsafe_div(rw[a + 1][c], dw[a + 1][c]);
                 const V aw = d * (rp / d) - sh * nb;
-                const V u = rp - omega * aw;
-                if (m == 1) {
-                    acc[0] += u;
-                } else {
-                    const int c = b.agg[p] - c0;
-                    if (c >= 0 && c < BMAX_FINE_COMP) acc[c] += u;
+                u[n] = rp - omega * aw;
+                comp[n] = m == 1 ? 0 : b.agg[(int64_t)(3 * bx + ox) + f.sy * (3 * by + oy)] - c0;
+            }
+        for (int c = 0; c < m && c < BMAX_FINE_COMP; ++c) {
+            V a = V(0);
+#pragma unroll
+            for (int n = 0; n < 9; ++n)
+                if (comp[n] == c) a += u[n];
+            rc[(int64_t)(c0 + c) * kp + j] = a;
+        }
+    } else {
+        const int64_t dx = f.kb, dy = f.sy * f.kb, dz = f.sz * f.kb;   // fine-index strides
+        V acc[BMAX_FINE_COMP];
+#pragma unroll
+        for (int c = 0; c < BMAX_FINE_COMP; ++c) acc[c] = V(0);
+        for (int oz = 0; oz < 3; ++oz) {
+            const int k = 3 * bz + oz;
+            if (k >= b.nz) break;
+            for (int oy = 0; oy < 3; ++oy) {
+                const int jj = 3 * by + oy;
+                if (jj >= b.ny) break;
+                for (int ox = 0; ox < 3; ++ox) {
+                    const int i = 3 * bx + ox;
+                    if (i >= b.nx) break;
+                    const int64_t p = (int64_t)i + f.sy * jj + f.sz * k;
+                    const V d = dg[p];
+                    if (d == V(0)) continue;
+                    const int64_t v = bvidx(f, p, j);
+                    const V rp = res[v];
+                    V nb = bsafe_div(res[v - dx], dg[p - 1]) + bsafe_div(res[v + dx], dg[p + 1]);
+                    nb += bsafe_div(res[v - dy], dg[p - f.sy]) + bsafe_div(res[v + dy], dg[p + f.sy]);
+                    nb += bsafe_div(res[v - dz], dg[p - f.sz]) + bsafe_div(res[v + dz], dg[p + f.sz]);
+                    const V aw = d * (rp / d) - sh * nb;
+                    const V uu = rp - omega * aw;
+                    if (m == 1) {
+                        acc[0] += uu;
+                    } else {
+                        const int c = b.agg[p] - c0;
+                        if (c >= 0 && c < BMAX_FINE_COMP) acc[c] += uu;
+                    }
                 }
             }
         }
+        for (int c = 0; c < m && c < BMAX_FINE_COMP; ++c) rc[(int64_t)(c0 + c) * kp + j] = acc[c];
     }
-    for (int c = 0; c < m && c < BMAX_FINE_COMP; ++c) rc[(int64_t)(c0 + c) * kp + j] = acc[c];
 }
 
 // zt = omega r / d + t - omega (A t) / d, t = e_c[agg]; the aggregate ids of
@@ -458,25 +596,40 @@ template <class V, int NPL>
 __global__ void __launch_bounds__(BNT) kb_fine_up(BFine f, double omega_d, const int32_t* __restrict__ agg,
                                                   const V* __restrict__ ec, const double* __restrict__ r,
                                                   V* __restrict__ zt) {
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int jt = (int)threadIdx.x & (f.kb - 1);
     const V* __restrict__ dg = bdiag<V>(f);
     const V omega = (V)omega_d;
     const int64_t kp = f.kp;
+    const bool d3 = f.dim == 3;
+    bool act[NPL];
+#pragma unroll
+    for (int jb = 0; jb < NPL; ++jb) act[jb] = f.done[((pb + jb) << f.lkb) + jt] == 0;
     BNODE_LOOP(f, p, jj, v0) {
         const V d = dg[p];
         if (d != V(0)) {
             const int32_t g0 = agg[p], g1 = agg[p - 1], g2 = agg[p + 1], g3 = agg[p - f.sy], g4 = agg[p + f.sy];
-            const int32_t g5 = f.dim == 3 ? agg[p - f.sz] : -1, g6 = f.dim == 3 ? agg[p + f.sz] : -1;
+            const int32_t g5 = d3 ? agg[p - f.sz] : -1, g6 = d3 ? agg[p + f.sz] : -1;
+            St<V> ts[NPL];
+            double rv[NPL];
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const int j = (jb << f.lkb) + (int)jj;
-                if (f.done[j]) continue;
+                ts[jb] = st_zero<V>();
+                rv[jb] = 0.0;
+                if (!act[jb]) continue;
+                const int j = ((pb + jb) << f.lkb) + jt;
                 auto t_at = [&](int32_t g) { return g >= 0 ? ec[(int64_t)g * kp + j] : V(0); };
-                const V tp = t_at(g0);
-                V nb = t_at(g1) + t_at(g2) + t_at(g3) + t_at(g4);
-                if (f.dim == 3) nb += t_at(g5) + t_at(g6);
-                const V at = d * tp - (V)f.s * nb;
-                const int64_t v = v0 + jb * f.plane;
-                zt[v] = omega * (V)r[v] / d + (tp - omega * at / d);
+                ts[jb] = {t_at(g0), t_at(g1), t_at(g2), t_at(g3), t_at(g4), t_at(g5), t_at(g6)};
+                rv[jb] = r[v0 + (pb + jb) * f.plane];
+            }
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                if (!act[jb]) continue;
+                const St<V>& t = ts[jb];
+                V nb = t.xm + t.xp + t.ym + t.yp;
+                if (d3) nb += t.zm + t.zp;
+                const V at = d * t.c - (V)f.s * nb;
+                zt[v0 + (pb + jb) * f.plane] = omega * (V)rv[jb] / d + (t.c - omega * at / d);
             }
         }
     }
@@ -487,27 +640,44 @@ template <class V, int NPL>
 __global__ void __launch_bounds__(BNT) kb_fine_post(BFine f, double omega_d, const V* __restrict__ zt,
                                                     const double* __restrict__ r, V* __restrict__ z,
                                                     double* __restrict__ part) {
+    const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int jt = (int)threadIdx.x & (f.kb - 1);
     const V* __restrict__ dg = bdiag<V>(f);
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
     const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
+    const bool d3 = f.dim == 3;
+    bool act[NPL];
     double acc[NPL];
 #pragma unroll
-    for (int jb = 0; jb < NPL; ++jb) acc[jb] = 0.0;
+    for (int jb = 0; jb < NPL; ++jb) {
+        act[jb] = f.done[((pb + jb) << f.lkb) + jt] == 0;
+        acc[jb] = 0.0;
+    }
     BNODE_LOOP(f, p, jj, v0) {
         const V d = dg[p];
         if (d != V(0)) {
+            St<V> zs[NPL];
+            double rv[NPL];
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                const int j = (jb << f.lkb) + (int)jj;
-                if (f.done[j]) continue;
-                const int64_t v = v0 + jb * f.plane;
-                V nb = zt[v - ox] + zt[v + ox] + zt[v - sy] + zt[v + sy];
-                if (f.dim == 3) nb += zt[v - sz] + zt[v + sz];
-                const V az = d * zt[v] - sh * nb;
-                const V zv = zt[v] + omega * ((V)r[v] - az) / d;
-                z[v] = zv;
-                acc[jb] += r[v] * (double)zv;
+                zs[jb] = st_zero<V>();
+                rv[jb] = 0.0;
+                if (!act[jb]) continue;
+                const int64_t v = v0 + (pb + jb) * f.plane;
+                zs[jb] = ld_st(zt, v, ox, sy, sz, d3);
+                rv[jb] = r[v];
+            }
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) {
+                if (!act[jb]) continue;
+                const St<V>& a = zs[jb];
+                V nb = a.xm + a.xp + a.ym + a.yp;
+                if (d3) nb += a.zm + a.zp;
+                const V az = d * a.c - sh * nb;
+                const V zv = a.c + omega * ((V)rv[jb] - az) / d;
+                z[v0 + (pb + jb) * f.plane] = zv;
+                acc[jb] += rv[jb] * (double)zv;
             }
         }
     }
@@ -709,7 +879,7 @@ static BFine bfine(const amg_handle* H, const BatchBufs* B, bool full, unsigned*
     f.strip_w = H->strip_w;
     f.kp = B->kp;
     f.lkp = ilog2(B->kp);
-    f.kb = B->kp < 8 ? B->kp : 8;
+    f.kb = B->kp < B->kbw ? B->kp : B->kbw;
     f.lkb = ilog2(f.kb);
     f.plane = H->npad * f.kb;
     f.lsw0 = ilog2(H->strip_w);
@@ -766,14 +936,15 @@ template <> BCsr<float> bcsr_p<float>(const Level& L) { return {L.p_rowptr, L.p_
 template <> BCsr<float> bcsr_r<float>(const Level& L) { return {L.r_rowptr, L.r_col, L.r_val32}; }
 template <> const float* bldiag<float>(const Level& L) { return L.diag32; }
 
-// Launch a fine kernel instantiated for NPL = kp / kb planes (1, 2, 4 or 8).
+// Launch a fine kernel instantiated for NPL planes per block (1, 2 or 4;
+// the grid's y dimension covers the other planes).
+constexpr int BMAX_NPB = 4;
 #define BLAUNCH_V(KERNEL, V, npl, grid, ...)                                                       \
     do {                                                                                           \
         switch (npl) {                                                                             \
             case 1: hipLaunchKernelGGL((KERNEL<V, 1>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
             case 2: hipLaunchKernelGGL((KERNEL<V, 2>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
-            case 4: hipLaunchKernelGGL((KERNEL<V, 4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
-            default: hipLaunchKernelGGL((KERNEL<V, 8>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<V, 4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
         }                                                                                          \
     } while (0)
 #define BLAUNCH_N(KERNEL, npl, grid, ...)                                                       \
@@ -781,12 +952,19 @@ template <> const float* bldiag<float>(const Level& L) { return L.diag32; }
         switch (npl) {                                                                          \
             case 1: hipLaunchKernelGGL((KERNEL<1>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
             case 2: hipLaunchKernelGGL((KERNEL<2>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
-            case 4: hipLaunchKernelGGL((KERNEL<4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
-            default: hipLaunchKernelGGL((KERNEL<8>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<4>), grid, dim3(BNT), 0, s, __VA_ARGS__); break; \
         }                                                                                       \
     } while (0)
 
-static int npl_of(const BFine& f) { return f.kp / f.kb; }
+// Planes per block and the grid of a fine kernel (y: plane groups).
+static int npl_of(const BFine& f, const BatchBufs* B) {
+    int n = f.kp / f.kb;
+    if (B->npb < n) n = B->npb;
+    return n < BMAX_NPB ? n : BMAX_NPB;
+}
+static dim3 bgrid(unsigned gx, const BFine& f, const BatchBufs* B) {
+    return dim3(gx, (unsigned)((f.kp / f.kb) / npl_of(f, B)));
+}
 
 static unsigned rows_grid(int64_t rows, int kp) {
     const int64_t t = rows * kp;
@@ -820,12 +998,15 @@ static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int ini
     const BFine fr = bfine(H, B, false, &gfix);
     const double w0 = H->lev[0].omega;
     if (initial) {
-        BLAUNCH_V(kb_fine_down, V, npl_of(ff), dim3(gfull), ff, w0, r, (V*)B->res);
+        BLAUNCH_V(kb_fine_down, V, npl_of(ff, B), bgrid(gfull, ff, B), ff, w0, r, (V*)B->res);
     }
     const BBox bx = bbox(H);
     const int64_t nbt = H->nboxes0 * kp;
-    hipLaunchKernelGGL(kb_restrict<V>, dim3((unsigned)((nbt + 255) / 256 > 0 ? (nbt + 255) / 256 : 1)), dim3(256), 0,
-                       s, ff, bx, w0, (const V*)B->res, (V*)B->rv[1]);
+    const dim3 grx((unsigned)((nbt + 255) / 256 > 0 ? (nbt + 255) / 256 : 1));
+    if (H->d.dim == 2)
+        hipLaunchKernelGGL((kb_restrict<V, 2>), grx, dim3(256), 0, s, ff, bx, w0, (const V*)B->res, (V*)B->rv[1]);
+    else
+        hipLaunchKernelGGL((kb_restrict<V, 3>), grx, dim3(256), 0, s, ff, bx, w0, (const V*)B->res, (V*)B->rv[1]);
     for (int l = 1; l < H->nlev - 1; ++l) {
         const Level& L = H->lev[l];
         const Level& C = H->lev[l + 1];
@@ -848,8 +1029,8 @@ static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int ini
         hipLaunchKernelGGL(kb_csr_post<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
                            bcsr_a<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (const V*)B->tmp[l], (V*)B->ev[l]);
     }
-    BLAUNCH_V(kb_fine_up, V, npl_of(ff), dim3(gfull), ff, w0, H->agg_p, (const V*)B->ev[1], r, (V*)B->zt);
-    BLAUNCH_V(kb_fine_post, V, npl_of(fr), dim3(gfix), fr, w0, (const V*)B->zt, r, z, part);
+    BLAUNCH_V(kb_fine_up, V, npl_of(ff, B), bgrid(gfull, ff, B), ff, w0, H->agg_p, (const V*)B->ev[1], r, (V*)B->zt);
+    BLAUNCH_V(kb_fine_post, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, w0, (const V*)B->zt, r, z, part);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -864,11 +1045,11 @@ static int benqueue_iteration(amg_handle* H, BatchBufs* B, int k, hipStream_t s)
     double* pnew = B->p[(k + 1) & 1];
     double* rin = B->rr[(k - 1) & 1];
     double* rout = B->rr[k & 1];
-    BLAUNCH_V(kb_pspmv, V, npl_of(fr), dim3(gfix), fr, (const V*)B->z, pold, pnew, B->q, (const BatchState*)B->st,
+    BLAUNCH_V(kb_pspmv, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, (const V*)B->z, pold, pnew, B->q, (const BatchState*)B->st,
               B->part[0]);
     hipLaunchKernelGGL(kb_fin_pq, dim3(1), dim3(BFIN), 0, s, B->st, B->part[0], (int)gfix, kp);
     // (with one level the fused pre-smoothing residual is formed but not used)
-    BLAUNCH_V(kb_xr_down, V, npl_of(fr), dim3(gfix), fr, B->x, rin, rout, pnew, B->q, (V*)B->res, H->lev[0].omega,
+    BLAUNCH_V(kb_xr_down, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->x, rin, rout, pnew, B->q, (V*)B->res, H->lev[0].omega,
               (const BatchState*)B->st, B->part[1]);
     hipLaunchKernelGGL(kb_fin_rr, dim3(1), dim3(BFIN), 0, s, B->st, B->part[1], (int)gfix, kp);
     EB_LAUNCH_CHECK();
@@ -885,8 +1066,8 @@ static int benqueue_start(amg_handle* H, BatchBufs* B, double tol, hipStream_t s
     const int kp = B->kp;
     unsigned gfix = 0;
     const BFine fr = bfine(H, B, false, &gfix);
-    BLAUNCH_N(kb_norm2, npl_of(fr), dim3(gfix), fr, B->bvec, B->part_aux);
-    BLAUNCH_N(kb_resid, npl_of(fr), dim3(gfix), fr, B->bvec, B->x, B->rr[0], B->part[1]);
+    BLAUNCH_N(kb_norm2, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->part_aux);
+    BLAUNCH_N(kb_resid, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->x, B->rr[0], B->part[1]);
     hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, B->part[1], (int)gfix, kp, tol);
     EB_LAUNCH_CHECK();
     EB_TRY(benqueue_vcycle<V>(H, B, B->rr[0], 1, B->part[2], s));
@@ -947,7 +1128,7 @@ static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t
         // true residual ||b - A x|| per rhs (FP64)
         unsigned gfix = 0;
         const BFine fr = bfine(H, B, false, &gfix);
-        BLAUNCH_N(kb_resid, npl_of(fr), dim3(gfix), fr, B->bvec, B->x, B->tres, B->part_aux);
+        BLAUNCH_N(kb_resid, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->x, B->tres, B->part_aux);
         hipLaunchKernelGGL(kb_fin_true, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, (int)gfix, kp);
         EB_LAUNCH_CHECK();
         EB_TRY(bpoll(B, s));

@@ -273,3 +273,61 @@ WORKLOADS = {
     "star2d_heat_1024": lambda: star_heat(1024, 0),
     "ellipsoid3d_256": lambda: ellipsoid_poisson(256),
 }
+
+
+# ------------------------------------------------------- time-dependent inputs
+
+def wave_disk_grid(n: int) -> Grid:
+    """Box [-1.1, 1.1]^2 with n cells per side (the wave example's grid)."""
+    return Grid(dim=2, n=(n, n), x0=(-1.1, -1.1), h=2.2 / n)
+
+
+def psi_unit_disk(grid: Grid) -> np.ndarray:
+    X, Y = grid.mesh()
+    return np.sqrt(X * X + Y * Y) - 1.0
+
+
+def bessel_zero(m: int = 7, k: int = 7) -> float:
+    """k-th positive zero of J_m."""
+    from scipy.special import jn_zeros
+    return float(jn_zeros(m, k)[-1])
+
+
+def standing_mode(X, Y, t: float, m: int = 7, k: int = 7) -> np.ndarray:
+    """u = J_m(kappa r) cos(m theta) cos(kappa t), kappa the k-th zero of J_m
+    (vanishes on the unit circle)."""
+    from scipy.special import jv
+    kappa = bessel_zero(m, k)
+    r = np.sqrt(X * X + Y * Y)
+    th = np.arctan2(Y, X)
+    return jv(m, kappa * r) * np.cos(m * th) * np.cos(kappa * t)
+
+
+def wave_schedule(n: int, dt_over_h: float, periods: float = 10.2, m: int = 7, k: int = 7):
+    """(dt, nsteps) reaching `periods` periods of the standing mode exactly with
+    dt at most dt_over_h * h."""
+    h = 2.2 / n
+    T = periods * 2.0 * math.pi / bessel_zero(m, k)
+    nsteps = int(math.ceil(T / (dt_over_h * h)))
+    return T / nsteps, nsteps
+
+
+def heat_cn_grid(n: int) -> Grid:
+    """Box [-1, 1]^2 with n cells per side (the heat example's grid)."""
+    return Grid(dim=2, n=(n, n), x0=(-1.0, -1.0), h=2.0 / n)
+
+
+def psi_heat_disk(grid: Grid) -> np.ndarray:
+    """Disk of radius 1/2, psi = x^2 + y^2 - 1/4 (< 0 inside)."""
+    X, Y = grid.mesh()
+    return X * X + Y * Y - 0.25
+
+
+def heat_cn_exact(X, Y, t: float):
+    """u = exp(-t) (x^2 + y^2 - 1/4); with beta = 1 its source is
+    f = u_t - Lap u = -u - 4 exp(-t)."""
+    return math.exp(-t) * (X * X + Y * Y - 0.25)
+
+
+def heat_cn_source(X, Y, t: float):
+    return -heat_cn_exact(X, Y, t) - 4.0 * math.exp(-t)

@@ -164,6 +164,28 @@ int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const double* f,
 int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
                   const double* x, double* y, void* stream);
 
+/* Time-stepper right-hand sides on the same operator (node fields; outputs are
+ * 0 off computational points; asynchronous).
+ *
+ * Wave equation u_tt = Lap u, theta-scheme (Sec. 3.5):
+ *   (I + theta dt^2 A) u^{n+1} = 2 u^n - u^{n-1} - dt^2 A ((1 - 2 theta) u^n + theta u^{n-1}).
+ * eb_wave_rhs writes out = scale * (right-hand side above) from un = u^n and
+ * unm1 = u^{n-1}.  theta = 0 (leap-frog) with scale = 1 gives u^{n+1}
+ * itself; for theta > 0, scale = sigma = 1/(theta dt^2) gives the right-hand
+ * side of (A + sigma I) u^{n+1} = out, solved by pcg_solve on a hierarchy set
+ * up with that sigma.  EB_EINVAL for theta < 0, dt <= 0 or a non-finite scale. */
+int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double theta, double dt, double scale,
+                const double* un, const double* unm1, double* out, void* stream);
+
+/* out = alpha (A + sigma I) x + beta y + gamma z.  With sigma = -2/dt,
+ * alpha = -1, y = b^n, z = b^{n+1} it is the right-hand side of the
+ * Crank-Nicolson heat step (Sec. 3.4) (A + (2/dt) I) u^{n+1}
+ * = ((2/dt) I - A) u^n + b^n + b^{n+1}.  y (z) may be null when beta (gamma)
+ * is 0; EB_EINVAL otherwise.                                                   */
+int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma, double alpha,
+                       const double* x, double beta, const double* y, double gamma, const double* z, double* out,
+                       void* stream);
+
 /* Build the aggregation AMG hierarchy of A (+ sigma I) on the device
  * (Algorithm 2 step 4 preconditioner).  *H receives a new handle (host).
  * p may be NULL for defaults.  Synchronises `stream` (level sizes are read

@@ -22,7 +22,7 @@ EXPORTS = [
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
-    "amg_smoother_samples", "amg_smoother_loss_grad",
+    "amg_smoother_samples", "amg_smoother_loss_grad", "eb_wave_rhs", "eb_stencil_combine",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -88,6 +88,8 @@ def lib():
     L.eb_assemble_diag.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.eb_assemble_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, vp, vp]
     L.stencil_apply.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, vp, vp, vp]
+    L.eb_wave_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
+    L.eb_stencil_combine.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, vp, dbl, vp, dbl, vp, vp, vp]
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.pcg_solve_batched.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]

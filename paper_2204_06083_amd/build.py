@@ -30,6 +30,7 @@ SOURCES = {
     "assemble.hip": ["-ffp-contract=off"],
     "amg_setup.hip": ["-ffp-contract=off"],
     "solve.hip": [],
+    "steppers.hip": [],
     "batched.hip": [],
     "learned.hip": [],
 }

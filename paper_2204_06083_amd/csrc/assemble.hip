@@ -11,31 +11,6 @@
 
 namespace eb {
 
-struct NodePos {
-    int i, j, k;
-};
-
-__device__ inline NodePos node_pos(int64_t n, const GridDims& d) {
-    NodePos p;
-    p.i = (int)(n % d.nx);
-    int64_t r = n / d.nx;
-    p.j = (int)(r % d.ny);
-    p.k = (int)(r / d.ny);
-    return p;
-}
-
-__device__ inline int axis_coord(const NodePos& p, int axis) {
-    return axis == 0 ? p.i : (axis == 1 ? p.j : p.k);
-}
-
-__device__ inline int axis_len(const GridDims& d, int axis) {
-    return axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
-}
-
-__device__ inline int64_t axis_stride(const GridDims& d, int axis) {
-    return axis == 0 ? 1 : (axis == 1 ? d.sy : d.sz);
-}
-
 // ------------------------------------------------------------ classification
 // Sec. 2: mask m = [psi < 0]; boundary point = inside with an outside nearest
 // neighbour; computational point = inside with all 2d neighbours inside.

@@ -128,4 +128,36 @@ struct GridDims {
 
 int make_dims(const eb_grid_t* g, GridDims* d);
 
+// Node coordinates of a flat index in the dense user layout.
+struct NodePos {
+    int i, j, k;
+};
+
+__device__ inline NodePos node_pos(int64_t n, const GridDims& d) {
+    NodePos p;
+    p.i = (int)(n % d.nx);
+    int64_t r = n / d.nx;
+    p.j = (int)(r % d.ny);
+    p.k = (int)(r / d.ny);
+    return p;
+}
+
+__device__ inline int axis_coord(const NodePos& p, int axis) {
+    return axis == 0 ? p.i : (axis == 1 ? p.j : p.k);
+}
+
+__device__ inline int axis_len(const GridDims& d, int axis) {
+    return axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
+}
+
+__device__ inline int64_t axis_stride(const GridDims& d, int axis) {
+    return axis == 0 ? 1 : (axis == 1 ? d.sy : d.sz);
+}
+
+// A node of the outermost layer (never an unknown: it has no full stencil).
+__device__ inline bool on_outer_layer(const NodePos& p, const GridDims& d) {
+    return p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
+           (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
+}
+
 }  // namespace eb

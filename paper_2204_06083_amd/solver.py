@@ -102,6 +102,98 @@ def stencil_apply(grid, kind: torch.Tensor, a: torch.Tensor, sigma: float, x: to
     return y
 
 
+def wave_rhs(asm: "Assembly", theta: float, dt: float, scale: float, un: torch.Tensor, unm1: torch.Tensor,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """eb_wave_rhs: scale (2 u^n - u^{n-1} - dt^2 A ((1 - 2 theta) u^n + theta u^{n-1}))."""
+    shape = asm.grid.shape
+    g = L.make_grid(asm.grid)
+    y = out if out is not None else torch.empty(shape, dtype=torch.float64, device=un.device)
+    rc = L.lib().eb_wave_rhs(C.byref(g), _field(asm.kind, shape, torch.int8, "kind"),
+                             _field(asm.a, shape, torch.float64, "a"), float(theta), float(dt), float(scale),
+                             _field(un, shape, torch.float64, "un"), _field(unm1, shape, torch.float64, "unm1"),
+                             _field(y, shape, torch.float64, "out"), _stream())
+    L.check(rc, "eb_wave_rhs")
+    return y
+
+
+def stencil_combine(asm: "Assembly", sigma: float, alpha: float, x: torch.Tensor, beta: float = 0.0,
+                    y: Optional[torch.Tensor] = None, gamma: float = 0.0, z: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """eb_stencil_combine: alpha (A + sigma I) x + beta y + gamma z."""
+    shape = asm.grid.shape
+    g = L.make_grid(asm.grid)
+    o = out if out is not None else torch.empty(shape, dtype=torch.float64, device=x.device)
+    yp = _field(y, shape, torch.float64, "y") if y is not None else None
+    zp = _field(z, shape, torch.float64, "z") if z is not None else None
+    rc = L.lib().eb_stencil_combine(C.byref(g), _field(asm.kind, shape, torch.int8, "kind"),
+                                    _field(asm.a, shape, torch.float64, "a"), float(sigma), float(alpha),
+                                    _field(x, shape, torch.float64, "x"), float(beta), yp, float(gamma), zp,
+                                    _field(o, shape, torch.float64, "out"), _stream())
+    L.check(rc, "eb_stencil_combine")
+    return o
+
+
+def wave_theta(asm: "Assembly", u0: torch.Tensor, u1: torch.Tensor, dt: float, theta: float, nsteps: int,
+               tol: float = 1e-10, precision: str = "fp64", H: Optional["Hierarchy"] = None):
+    """theta-scheme for u_tt = Lap u with homogeneous Dirichlet data (Sec. 3.5),
+    from u^0 = u0 and u^1 = u1 to u^nsteps.  theta = 0 is the explicit leap-frog
+    scheme (one eb_wave_rhs per step); theta > 0 solves
+    (A + sigma I) u^{n+1} = sigma w, sigma = 1/(theta dt^2), by PCG warm-started
+    from u^n on a hierarchy with that shift (made here unless given).
+    Returns (u^nsteps, u^{nsteps-1}, stats)."""
+    if theta < 0.0 or nsteps < 1:
+        raise ValueError("theta must be >= 0 and nsteps >= 1")
+    if nsteps == 1:
+        return u1.clone(), u0.clone(), {"steps": 0, "pcg_iterations": 0}
+    sigma = 1.0 / (theta * dt * dt) if theta > 0.0 else 0.0
+    own = False
+    if theta > 0.0 and H is None:
+        H = Hierarchy(asm.grid, asm.kind, asm.a, sigma)
+        own = True
+    bufs = [u0.clone(), u1.clone(), torch.empty_like(u0)]
+    rhs = torch.empty_like(u0) if theta > 0.0 else None
+    iters = []
+    for n in range(2, nsteps + 1):
+        um, u, un = bufs[(n - 2) % 3], bufs[(n - 1) % 3], bufs[n % 3]
+        if theta == 0.0:
+            wave_rhs(asm, 0.0, dt, 1.0, u, um, out=un)
+        else:
+            wave_rhs(asm, theta, dt, sigma, u, um, out=rhs)
+            _, info = H.solve(rhs, x0=u, tol=tol, out=un, precision=precision)
+            iters.append(info["iterations"])
+    if own:
+        H.free()
+    stats = {"steps": nsteps - 1, "pcg_iterations": int(sum(iters)),
+             "mean_iterations": float(np.mean(iters)) if iters else 0.0}
+    return bufs[nsteps % 3], bufs[(nsteps - 1) % 3], stats
+
+
+def heat_cn(asm: "Assembly", H: "Hierarchy", u0: torch.Tensor, dt: float, nsteps: int, rhs_of_step,
+            tol: float = 1e-10, precision: str = "fp64"):
+    """Crank-Nicolson for u_t = Lap u + f (Sec. 3.4), beta = 1:
+    (A + (2/dt) I) u^{n+1} = ((2/dt) I - A) u^n + b^n + b^{n+1}, with
+    b^n = rhs_of_step(n) (assemble_rhs of the source and Dirichlet data at t_n)
+    and H set up with sigma = 2/dt.  PCG warm-started from u^n.
+    Returns (u^nsteps, stats)."""
+    s2 = 2.0 / dt
+    if abs(H.sigma - s2) > 1e-12 * s2:
+        raise ValueError("heat_cn: the hierarchy must be set up with sigma = 2/dt")
+    u = u0.clone()
+    un = torch.empty_like(u0)
+    rhs = torch.empty_like(u0)
+    b_prev = rhs_of_step(0)
+    iters = []
+    for k in range(1, nsteps + 1):
+        b_next = rhs_of_step(k)
+        stencil_combine(asm, -s2, -1.0, u, 1.0, b_prev, 1.0, b_next, out=rhs)
+        _, info = H.solve(rhs, x0=u, tol=tol, out=un, precision=precision)
+        iters.append(info["iterations"])
+        u, un = un, u
+        b_prev = b_next
+    return u, {"steps": nsteps, "pcg_iterations": int(sum(iters)),
+               "mean_iterations": float(np.mean(iters)) if iters else 0.0}
+
+
 @dataclass
 class LevelArrays:
     n: int

@@ -218,6 +218,25 @@ int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* p
 int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* p,
                       pcg_result_t* res, void* stream);
 
+/* Island batch: several geometries (of different sizes) in one hierarchy and
+ * one launch sequence, each with its own PCG per right-hand side.  The
+ * caller places the geometries' node grids one above the other in one node
+ * grid (the canvas; every island keeps its outer layer of outside nodes, so
+ * no stencil couples two islands and every aggregate, coarse operator and
+ * the coarsest inverse stay block diagonal) and sets the hierarchy up on it
+ * with h = 1: island i then carries h_i^2 A_i, and its source enters as
+ * h_i^2 f_i (boundary terms need no scaling).  seg_rows (host, nseg + 1
+ * increasing values) gives the node rows of the segments: segment s is rows
+ * seg_rows[s] .. seg_rows[s+1] - 1 (a row is the y index in 2-D, z * ny + y
+ * in 3-D); every unknown must lie in a segment (EB_EINVAL otherwise).  b, x:
+ * nrhs canvas node fields back to back; res [out, host]: nseg * nrhs results,
+ * res[s * nrhs + j], each with its own stopping test ||r|| <= tol ||b||
+ * restricted to its segment.  1 <= nseg <= 1024 and nseg * (nrhs rounded up
+ * to a power of two) <= 4096; the hierarchy must have two or more levels
+ * (EB_ENOTIMPL otherwise).  Synchronises `stream`.                          */
+int pcg_solve_islands(amg_handle_t* H, int32_t nrhs, int32_t nseg, const int32_t* seg_rows, const double* b,
+                      double* x, const pcg_params_t* p, pcg_result_t* res, void* stream);
+
 /* Apply one V(1,1) cycle z = M r (node fields; parity and debugging aid).     */
 int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
 

@@ -23,6 +23,7 @@ EXPORTS = [
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
     "amg_smoother_samples", "amg_smoother_loss_grad", "eb_wave_rhs", "eb_stencil_combine",
+    "pcg_solve_islands",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -93,6 +94,8 @@ def lib():
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.pcg_solve_batched.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
+    L.pcg_solve_islands.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), vp, vp, C.POINTER(PcgParams),
+                                    C.POINTER(PcgResult), vp]
     L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]
     L.amg_vcycle_apply_fp32.argtypes = [vp, vp, vp, vp]
     L.amg_num_levels.argtypes = [vp]

@@ -21,6 +21,9 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 
 #include "handle.hpp"
 
@@ -31,24 +34,30 @@ constexpr int BMAX_RHS = 64;
 constexpr int BPARTS = 512;       // blocks of the reducing fine kernels (multiple of 8)
 constexpr int BFIN = 1024;        // threads of the finaliser
 constexpr int BMAX_FINE_COMP = 16;
+constexpr int BMAX_SLOTS = 4096;  // segments x slots
+constexpr int BMAX_SEG = 1024;
 
-// Per-RHS scalars on the device (one allocation).
+// Per-system scalars on the device (one allocation).  A system is a
+// (segment, slot) pair, index seg * kp + j: segments are the separate
+// geometries of an island batch (one segment otherwise).  The two counters
+// come first so that polling copies 16 bytes.
 struct BatchState {
-    double rz[BMAX_RHS];       // (r, z) of the latest V-cycle
-    double beta[BMAX_RHS];     // rz_new / rz_old for the next p-update (0 first)
-    double alpha[BMAX_RHS];
-    double pq[BMAX_RHS];
-    double rr[BMAX_RHS];       // ||r||^2 of the latest iterate
-    double bb[BMAX_RHS];
-    double tol2bb[BMAX_RHS];
-    double rr_true[BMAX_RHS];
-    int32_t done[BMAX_RHS];    // 1: converged, failed or an unused slot
-    int32_t status[BMAX_RHS];
-    int32_t iters[BMAX_RHS];
-    int32_t mask[BMAX_RHS];    // host-set: slots (re)started by the next init
-    int32_t ndone;
-    int32_t maxiter;
-    int32_t pad[2];
+    int32_t ndone;             // finished systems
+    int32_t maxiter;           // largest iteration count
+    int32_t nsys;              // segments x kp
+    int32_t pad;
+    double rz[BMAX_SLOTS];     // (r, z) of the latest V-cycle
+    double beta[BMAX_SLOTS];   // rz_new / rz_old for the next p-update (0 first)
+    double alpha[BMAX_SLOTS];
+    double pq[BMAX_SLOTS];
+    double rr[BMAX_SLOTS];     // ||r||^2 of the latest iterate
+    double bb[BMAX_SLOTS];
+    double tol2bb[BMAX_SLOTS];
+    double rr_true[BMAX_SLOTS];
+    int32_t done[BMAX_SLOTS];  // 1: converged, failed or an unused slot
+    int32_t status[BMAX_SLOTS];
+    int32_t iters[BMAX_SLOTS];
+    int32_t mask[BMAX_SLOTS];  // host-set: systems (re)started by the next init
 };
 
 struct BatchBufs {
@@ -69,7 +78,16 @@ struct BatchBufs {
     double* part[3] = {nullptr, nullptr, nullptr};   // [BPARTS][kp]: (p,q), ||r||^2, (r,z)
     double* part_aux = nullptr;
     BatchState* st = nullptr;
-    BatchState host;
+    BatchState* host = nullptr;           // host copy (new-allocated: large)
+    // segments (island batches): fine blocks never straddle a segment;
+    // blk_start[b] .. blk_start[b + 1] are block b's strips, blk_seg[b] its
+    // segment, seg_blk[s] .. seg_blk[s + 1] the blocks of segment s
+    int nseg = 1;
+    int nblk = 0;
+    std::vector<int32_t> seg_rows;        // the segmentation these tables are for
+    int32_t* blk_start = nullptr;
+    int32_t* blk_seg = nullptr;
+    int32_t* seg_blk = nullptr;
     // layout and launch shape of the fine kernels: plane width (slots per
     // plane, node-major inside a plane) and planes per block (the grid's y
     // dimension covers the rest); chosen by timing 8/16/32/64 and 1/2/4/8 on
@@ -95,8 +113,13 @@ struct BFine {
     double s;             // 1/h^2
     const double* diag;
     const float* diag32;
-    const int32_t* done;  // per-RHS skip flags
+    const int32_t* done;  // per-system skip flags
+    const int32_t* blk_start;   // segmented block ranges (null: spb strips per block)
+    const int32_t* blk_seg;
 };
+
+// Index of the first system of this block's segment.
+__device__ inline int bseg_base(const BFine& f) { return f.blk_seg ? f.blk_seg[xcd_block()] * f.kp : 0; }
 
 template <class V> __device__ inline const V* bdiag(const BFine& f);
 template <> __device__ inline const double* bdiag<double>(const BFine& f) { return f.diag; }
@@ -120,7 +143,7 @@ __device__ inline void bpartial(double v, double* __restrict__ part, int kp, int
     if ((int)threadIdx.x < kb) {
         double a = 0.0;
         for (int t = threadIdx.x; t < BNT; t += kb) a += lds[t];
-        part[(int64_t)blockIdx.x * kp + jb * kb + threadIdx.x] = a;
+        part[xcd_block() * kp + jb * kb + threadIdx.x] = a;
     }
     __syncthreads();
 }
@@ -128,10 +151,11 @@ __device__ inline void bpartial(double v, double* __restrict__ part, int kp, int
 // The same with the slot t % kp (kernels over interleaved compact vectors).
 __device__ inline void bpartial_kp(double v, double* __restrict__ part, int kp) { bpartial(v, part, kp, kp, 0); }
 
-// Finaliser sum for rhs j over np block partials: BFIN / kp threads per rhs
-// take block-strided partials, then are combined in a fixed order.  Every
-// thread with rhs j returns the total (threads t with t % kp == j).
-__device__ inline double bfin_sum(const double* __restrict__ part, int np, int kp) {
+// Finaliser sum for slot j over the block partials b0 .. b1 - 1 (at most
+// BPARTS): BFIN / kp threads per slot take block-strided partials, then are
+// combined in a fixed order.  Every thread with slot j returns the total
+// (threads t with t % kp == j).
+__device__ inline double bfin_sum(const double* __restrict__ part, int b0, int b1, int kp) {
     __shared__ double lds[BFIN];
     const int j = threadIdx.x & (kp - 1);
     const int u = threadIdx.x / kp;
@@ -141,8 +165,8 @@ __device__ inline double bfin_sum(const double* __restrict__ part, int np, int k
     double v[MAXL];
 #pragma unroll
     for (int i = 0; i < MAXL; ++i) {
-        const int b = u + i * g;
-        v[i] = b < np ? part[(int64_t)b * kp + j] : 0.0;
+        const int b = b0 + u + i * g;
+        v[i] = b < b1 ? part[(int64_t)b * kp + j] : 0.0;
     }
     double a = 0.0;
 #pragma unroll
@@ -158,77 +182,22 @@ __device__ inline double bfin_sum(const double* __restrict__ part, int np, int k
 __device__ inline bool bbad(double v) { return isnan(v) || isinf(v); }
 
 // ------------------------------------------------------------- finalisers
-// (Re)start: ||b||^2 and ||r0||^2 per rhs; slots with mask = 0 are left done.
-__global__ void __launch_bounds__(BFIN) kb_fin_init(BatchState* st, const double* __restrict__ part_bb,
-                                                    const double* __restrict__ part_rr, int np, int kp, double tol) {
-    const double bb = bfin_sum(part_bb, np, kp);
-    const double rr = bfin_sum(part_rr, np, kp);
-    const int j = threadIdx.x;
-    if (j < kp && st->mask[j]) {
-        st->bb[j] = bb;
-        st->rr[j] = rr;
-        st->tol2bb[j] = tol * tol * bb;
-        st->status[j] = (bbad(bb) || bbad(rr)) ? EB_ENAN : EB_OK;
-        st->done[j] = (bb == 0.0 || rr <= tol * tol * bb || st->status[j] != EB_OK) ? 1 : 0;
-        st->beta[j] = 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int nd = 0;
-        for (int i = 0; i < kp; ++i) nd += st->done[i] != 0;
-        st->ndone = nd;
-    }
-}
+// One block per segment (blockIdx.x); thread j < kp updates system
+// seg * kp + j from the sums over the segment's blocks seg_blk[seg] ..
+// seg_blk[seg + 1] - 1.  With one segment the block also recounts ndone and
+// maxiter; with several, kb_fin_count does it after the finaliser.
+#define BFIN_SEG                                              \
+    const int seg_ = blockIdx.x;                              \
+    const int b0_ = seg_blk[seg_], b1_ = seg_blk[seg_ + 1];   \
+    const int j = threadIdx.x;                                \
+    const int sj = seg_ * kp + j;
 
-// (r, z) after a V-cycle: beta for the next p-update, curvature check.
-__global__ void __launch_bounds__(BFIN) kb_fin_rz(BatchState* st, const double* __restrict__ part, int np, int kp,
-                                                  int first) {
-    const double rz = bfin_sum(part, np, kp);
-    const int j = threadIdx.x;
-    if (j < kp && !st->done[j]) {
-        if (!(rz > 0.0) || bbad(rz)) {
-            st->status[j] = bbad(rz) ? EB_ENAN : EB_ENOTSPD;
-            st->done[j] = 1;
-        } else {
-            st->beta[j] = first ? 0.0 : rz / st->rz[j];
-            st->rz[j] = rz;
-        }
-    }
-}
-
-// (p, q): alpha = rz / (p, q).
-__global__ void __launch_bounds__(BFIN) kb_fin_pq(BatchState* st, const double* __restrict__ part, int np, int kp) {
-    const double pq = bfin_sum(part, np, kp);
-    const int j = threadIdx.x;
-    if (j < kp && !st->done[j]) {
-        st->pq[j] = pq;
-        if (!(pq > 0.0) || bbad(pq)) {
-            st->status[j] = bbad(pq) ? EB_ENAN : EB_ENOTSPD;
-            st->done[j] = 1;
-        } else {
-            st->alpha[j] = st->rz[j] / pq;
-        }
-    }
-}
-
-// ||r||^2 after the update: iteration count and convergence.
-__global__ void __launch_bounds__(BFIN) kb_fin_rr(BatchState* st, const double* __restrict__ part, int np, int kp) {
-    const double rr = bfin_sum(part, np, kp);
-    const int j = threadIdx.x;
-    if (j < kp && !st->done[j]) {
-        st->iters[j] += 1;
-        st->rr[j] = rr;
-        if (bbad(rr)) {
-            st->status[j] = EB_ENAN;
-            st->done[j] = 1;
-        } else if (rr <= st->tol2bb[j]) {
-            st->done[j] = 1;
-        }
-    }
+__device__ inline void bfin_count(BatchState* st) {
+    if (gridDim.x != 1) return;
     __syncthreads();
     if (threadIdx.x == 0) {
         int nd = 0, mx = 0;
-        for (int i = 0; i < kp; ++i) {
+        for (int i = 0; i < st->nsys; ++i) {
             nd += st->done[i] != 0;
             mx = max(mx, st->iters[i]);
         }
@@ -237,10 +206,103 @@ __global__ void __launch_bounds__(BFIN) kb_fin_rr(BatchState* st, const double* 
     }
 }
 
-__global__ void __launch_bounds__(BFIN) kb_fin_true(BatchState* st, const double* __restrict__ part, int np, int kp) {
-    const double rr = bfin_sum(part, np, kp);
-    const int j = threadIdx.x;
-    if (j < kp) st->rr_true[j] = rr;
+// ndone and maxiter over every system (several segments).
+__global__ void __launch_bounds__(BFIN) kb_fin_count(BatchState* st) {
+    __shared__ int nd_s[BFIN], mx_s[BFIN];
+    int nd = 0, mx = 0;
+    for (int i = threadIdx.x; i < st->nsys; i += BFIN) {
+        nd += st->done[i] != 0;
+        mx = max(mx, st->iters[i]);
+    }
+    nd_s[threadIdx.x] = nd;
+    mx_s[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = BFIN / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            nd_s[threadIdx.x] += nd_s[threadIdx.x + h];
+            mx_s[threadIdx.x] = max(mx_s[threadIdx.x], mx_s[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->ndone = nd_s[0];
+        st->maxiter = mx_s[0];
+    }
+}
+
+// (Re)start: ||b||^2 and ||r0||^2 per system; systems with mask = 0 are left done.
+__global__ void __launch_bounds__(BFIN) kb_fin_init(BatchState* st, const double* __restrict__ part_bb,
+                                                    const double* __restrict__ part_rr,
+                                                    const int32_t* __restrict__ seg_blk, int kp, double tol) {
+    BFIN_SEG
+    const double bb = bfin_sum(part_bb, b0_, b1_, kp);
+    const double rr = bfin_sum(part_rr, b0_, b1_, kp);
+    if (j < kp && st->mask[sj]) {
+        st->bb[sj] = bb;
+        st->rr[sj] = rr;
+        st->tol2bb[sj] = tol * tol * bb;
+        st->status[sj] = (bbad(bb) || bbad(rr)) ? EB_ENAN : EB_OK;
+        st->done[sj] = (bb == 0.0 || rr <= tol * tol * bb || st->status[sj] != EB_OK) ? 1 : 0;
+        st->beta[sj] = 0.0;
+    }
+    bfin_count(st);
+}
+
+// (r, z) after a V-cycle: beta for the next p-update, curvature check.
+__global__ void __launch_bounds__(BFIN) kb_fin_rz(BatchState* st, const double* __restrict__ part,
+                                                  const int32_t* __restrict__ seg_blk, int kp, int first) {
+    BFIN_SEG
+    const double rz = bfin_sum(part, b0_, b1_, kp);
+    if (j < kp && !st->done[sj]) {
+        if (!(rz > 0.0) || bbad(rz)) {
+            st->status[sj] = bbad(rz) ? EB_ENAN : EB_ENOTSPD;
+            st->done[sj] = 1;
+        } else {
+            st->beta[sj] = first ? 0.0 : rz / st->rz[sj];
+            st->rz[sj] = rz;
+        }
+    }
+}
+
+// (p, q): alpha = rz / (p, q).
+__global__ void __launch_bounds__(BFIN) kb_fin_pq(BatchState* st, const double* __restrict__ part,
+                                                  const int32_t* __restrict__ seg_blk, int kp) {
+    BFIN_SEG
+    const double pq = bfin_sum(part, b0_, b1_, kp);
+    if (j < kp && !st->done[sj]) {
+        st->pq[sj] = pq;
+        if (!(pq > 0.0) || bbad(pq)) {
+            st->status[sj] = bbad(pq) ? EB_ENAN : EB_ENOTSPD;
+            st->done[sj] = 1;
+        } else {
+            st->alpha[sj] = st->rz[sj] / pq;
+        }
+    }
+}
+
+// ||r||^2 after the update: iteration count and convergence.
+__global__ void __launch_bounds__(BFIN) kb_fin_rr(BatchState* st, const double* __restrict__ part,
+                                                  const int32_t* __restrict__ seg_blk, int kp) {
+    BFIN_SEG
+    const double rr = bfin_sum(part, b0_, b1_, kp);
+    if (j < kp && !st->done[sj]) {
+        st->iters[sj] += 1;
+        st->rr[sj] = rr;
+        if (bbad(rr)) {
+            st->status[sj] = EB_ENAN;
+            st->done[sj] = 1;
+        } else if (rr <= st->tol2bb[sj]) {
+            st->done[sj] = 1;
+        }
+    }
+    bfin_count(st);
+}
+
+__global__ void __launch_bounds__(BFIN) kb_fin_true(BatchState* st, const double* __restrict__ part,
+                                                    const int32_t* __restrict__ seg_blk, int kp) {
+    BFIN_SEG
+    const double rr = bfin_sum(part, b0_, b1_, kp);
+    if (j < kp) st->rr_true[sj] = rr;
 }
 
 // ------------------------------------------------------------ fine kernels
@@ -249,7 +311,8 @@ __global__ void __launch_bounds__(BFIN) kb_fin_true(BatchState* st, const double
 // are independent and in flight together.  v0 is the element's index in
 // plane 0; plane jb adds jb * plane.
 #define BNODE_LOOP(f, p, jj, v0)                                                                         \
-    for (int64_t s0_ = xcd_block() * (f).spb, s1_ = min(s0_ + (f).spb, (f).nstrips),                      \
+    for (int64_t xb_ = xcd_block(), s0_ = (f).blk_start ? (int64_t)(f).blk_start[xb_] : xb_ * (f).spb,       \
+                 s1_ = (f).blk_start ? (int64_t)(f).blk_start[xb_ + 1] : min(s0_ + (f).spb, (f).nstrips),     \
                  e_ = (int64_t)threadIdx.x, eend_ = (s1_ - s0_) * ((int64_t)(f).strip_w << (f).lkb);       \
          e_ < eend_; e_ += BNT)                                                                            \
         for (int64_t p = (int64_t)(f).strips[s0_ + (e_ >> ((f).lsw0 + (f).lkb))] * (f).strip_w +           \
@@ -312,6 +375,7 @@ template <class V, int NPL>
 __global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const double* __restrict__ r,
                                                     V* __restrict__ res) {
     const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int sb = bseg_base(f);             // first system of this block's segment
     const int64_t ox = f.kb, sy = f.sy * f.kb, sz = f.sz * f.kb;
     BNODE_LOOP(f, p, jj, v0) {
         const double d = f.diag[p];
@@ -320,7 +384,7 @@ __global__ void __launch_bounds__(BNT) kb_fine_down(BFine f, double omega, const
             const double dzm = f.dim == 3 ? f.diag[p - f.sz] : 0.0, dzp = f.dim == 3 ? f.diag[p + f.sz] : 0.0;
 #pragma unroll
             for (int jb = 0; jb < NPL; ++jb) {
-                if (f.done[((pb + jb) << f.lkb) + jj]) continue;
+                if (f.done[sb + ((pb + jb) << f.lkb) + jj]) continue;
                 const int64_t v = v0 + (pb + jb) * f.plane;
                 double nb = bsafe_div(r[v - ox], dxm) + bsafe_div(r[v + ox], dxp);
                 nb += bsafe_div(r[v - sy], dym) + bsafe_div(r[v + sy], dyp);
@@ -365,12 +429,13 @@ __global__ void __launch_bounds__(BNT) kb_pspmv(BFine f, const V* __restrict__ z
                                                 double* __restrict__ pnew, double* __restrict__ q,
                                                 const BatchState* __restrict__ st, double* __restrict__ part) {
     const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int sb = bseg_base(f);             // first system of this block's segment
     const int jt = (int)threadIdx.x & (f.kb - 1);
     bool act[NPL];
     double beta[NPL], acc[NPL];
 #pragma unroll
     for (int jb = 0; jb < NPL; ++jb) {
-        const int j = ((pb + jb) << f.lkb) + jt;
+        const int j = sb + ((pb + jb) << f.lkb) + jt;
         act[jb] = f.done[j] == 0;
         beta[jb] = st->beta[j];
         acc[jb] = 0.0;
@@ -419,12 +484,13 @@ __global__ void __launch_bounds__(BNT) kb_xr_down(BFine f, double* __restrict__ 
                                                   const double* __restrict__ q, V* __restrict__ res, double omega,
                                                   const BatchState* __restrict__ st, double* __restrict__ part) {
     const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int sb = bseg_base(f);             // first system of this block's segment
     const int jt = (int)threadIdx.x & (f.kb - 1);
     bool act[NPL];
     double alpha[NPL], acc[NPL];
 #pragma unroll
     for (int jb = 0; jb < NPL; ++jb) {
-        const int j = ((pb + jb) << f.lkb) + jt;
+        const int j = sb + ((pb + jb) << f.lkb) + jt;
         act[jb] = f.done[j] == 0;
         alpha[jb] = st->alpha[j];
         acc[jb] = 0.0;
@@ -496,7 +562,7 @@ __global__ void __launch_bounds__(256) kb_restrict(BFine f, BBox b, double omega
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t bi = t >> f.lkp;
     const int j = (int)(t & (f.kp - 1));
-    if (bi >= b.nboxes || f.done[j]) return;
+    if (bi >= b.nboxes || (!f.blk_seg && f.done[j])) return;   // (segmented: a box may hold two segments)
     const V* __restrict__ dg = bdiag<V>(f);
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
@@ -597,6 +663,7 @@ __global__ void __launch_bounds__(BNT) kb_fine_up(BFine f, double omega_d, const
                                                   const V* __restrict__ ec, const double* __restrict__ r,
                                                   V* __restrict__ zt) {
     const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int sb = bseg_base(f);             // first system of this block's segment
     const int jt = (int)threadIdx.x & (f.kb - 1);
     const V* __restrict__ dg = bdiag<V>(f);
     const V omega = (V)omega_d;
@@ -604,7 +671,7 @@ __global__ void __launch_bounds__(BNT) kb_fine_up(BFine f, double omega_d, const
     const bool d3 = f.dim == 3;
     bool act[NPL];
 #pragma unroll
-    for (int jb = 0; jb < NPL; ++jb) act[jb] = f.done[((pb + jb) << f.lkb) + jt] == 0;
+    for (int jb = 0; jb < NPL; ++jb) act[jb] = f.done[sb + ((pb + jb) << f.lkb) + jt] == 0;
     BNODE_LOOP(f, p, jj, v0) {
         const V d = dg[p];
         if (d != V(0)) {
@@ -641,6 +708,7 @@ __global__ void __launch_bounds__(BNT) kb_fine_post(BFine f, double omega_d, con
                                                     const double* __restrict__ r, V* __restrict__ z,
                                                     double* __restrict__ part) {
     const int pb = (int)blockIdx.y * NPL;   // first plane of this block
+    const int sb = bseg_base(f);             // first system of this block's segment
     const int jt = (int)threadIdx.x & (f.kb - 1);
     const V* __restrict__ dg = bdiag<V>(f);
     const V omega = (V)omega_d;
@@ -651,7 +719,7 @@ __global__ void __launch_bounds__(BNT) kb_fine_post(BFine f, double omega_d, con
     double acc[NPL];
 #pragma unroll
     for (int jb = 0; jb < NPL; ++jb) {
-        act[jb] = f.done[((pb + jb) << f.lkb) + jt] == 0;
+        act[jb] = f.done[sb + ((pb + jb) << f.lkb) + jt] == 0;
         acc[jb] = 0.0;
     }
     BNODE_LOOP(f, p, jj, v0) {
@@ -697,7 +765,7 @@ struct BCsr {
     const int64_t t_ = (int64_t)blockIdx.x * BNT + threadIdx.x;   \
     const int64_t row = t_ >> (lkp);                              \
     const int j = (int)(t_ & ((kp) - 1));                         \
-    if (row >= (n) || (done)[j]) return;
+    if (row >= (n) || ((done) && (done)[j])) return;
 
 template <class V>
 __global__ void __launch_bounds__(BNT) kb_csr_resid(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
@@ -823,25 +891,101 @@ void free_batch(amg_handle* H, hipStream_t s) {
     BatchBufs* B = H->batch;
     if (!B) return;
     void* ptrs[] = {B->x, B->rr[0], B->rr[1], B->p[0], B->p[1], B->q, B->bvec, B->tres, B->res, B->zt, B->z,
-                    B->part[0], B->part[1], B->part[2], B->part_aux, B->st};
+                    B->part[0], B->part[1], B->part[2], B->part_aux, B->st, B->blk_start, B->blk_seg, B->seg_blk};
     for (void* p : ptrs) (void)dfree(p, s);
     for (int l = 0; l < MAX_LEVELS; ++l) {
         (void)dfree(B->rv[l], s);
         (void)dfree(B->ev[l], s);
         (void)dfree(B->tmp[l], s);
     }
+    delete B->host;
     delete B;
     H->batch = nullptr;
 }
 
-// Buffers for kp slots with V-cycle element size vb (8 or 4 bytes).
-static int ensure_batch(amg_handle* H, int kp, int prec, hipStream_t s) {
-    if (H->batch && H->batch->kp == kp && H->batch->prec == prec) return EB_OK;
+// Segment tables.  The fine strips are sorted by node, hence by node row, so
+// each segment (a run of node rows) owns a contiguous run of strips.  Every
+// segment gets a share of about BPARTS blocks proportional to its strips (at
+// least one, at most BPARTS), its strips split evenly among them; the block
+// count is padded to a multiple of the XCD count with empty blocks of the
+// last segment.  rows: nseg + 1 increasing node-row bounds (host).
+static int make_segments(amg_handle* H, BatchBufs* B, int nseg, const int32_t* rows, hipStream_t s) {
+    std::vector<int32_t> seg_blk((size_t)nseg + 1);
+    if (nseg == 1 && !rows) {
+        B->nblk = BPARTS;
+        seg_blk[0] = 0;
+        seg_blk[1] = BPARTS;
+    } else {
+        const int64_t n = H->nstrips;
+        std::vector<int32_t> ids((size_t)(n > 0 ? n : 1));
+        if (n > 0) {
+            EB_HIP(hipMemcpyAsync(ids.data(), H->strips, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            EB_HIP(hipStreamSynchronize(s));
+        }
+        const int64_t per_row = H->px / H->strip_w;
+        std::vector<int64_t> first((size_t)nseg + 1, n);
+        int sg = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t row = ids[k] / per_row;
+            if (row < rows[0] || row >= rows[nseg]) {
+                set_error("pcg_solve_islands: an unknown lies in node row %lld, outside the segments",
+                          (long long)row);
+                return EB_EINVAL;
+            }
+            while (row >= rows[sg + 1]) ++sg;
+            for (int t = sg; t >= 0 && first[t] == n; --t) first[t] = k;
+        }
+        for (int t = nseg - 1; t >= 0; --t)
+            if (first[t] > first[t + 1]) first[t] = first[t + 1];
+        std::vector<int32_t> bstart, bseg;
+        for (int t = 0; t < nseg; ++t) {
+            const int64_t k0 = first[t], k1 = first[t + 1], cnt = k1 - k0;
+            int64_t nb = n > 0 ? (int64_t)BPARTS * cnt / n : 1;
+            // at most BPARTS - NUM_XCD, so that with the padding blocks a
+            // segment never exceeds the BPARTS partials a finaliser sums
+            nb = nb < 1 ? 1 : (nb > BPARTS - NUM_XCD ? BPARTS - NUM_XCD : nb);
+            seg_blk[t] = (int32_t)bstart.size();
+            for (int64_t i = 0; i < nb; ++i) {
+                bstart.push_back((int32_t)(k0 + i * cnt / nb));
+                bseg.push_back(t);
+            }
+        }
+        while (bstart.size() % NUM_XCD != 0 || bstart.empty()) {
+            bstart.push_back((int32_t)n);
+            bseg.push_back(nseg - 1);
+        }
+        seg_blk[nseg] = (int32_t)bstart.size();
+        B->nblk = (int)bstart.size();
+        bstart.push_back((int32_t)n);
+        EB_TRY(dalloc_n(&B->blk_start, (int64_t)bstart.size(), s));
+        EB_TRY(dalloc_n(&B->blk_seg, (int64_t)bseg.size(), s));
+        EB_HIP(hipMemcpyAsync(B->blk_start, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice, s));
+        EB_HIP(hipMemcpyAsync(B->blk_seg, bseg.data(), sizeof(int32_t) * bseg.size(), hipMemcpyHostToDevice, s));
+        EB_HIP(hipStreamSynchronize(s));   // the host vectors are freed on return
+    }
+    EB_TRY(dalloc_n(&B->seg_blk, (int64_t)nseg + 1, s));
+    EB_HIP(hipMemcpyAsync(B->seg_blk, seg_blk.data(), sizeof(int32_t) * (nseg + 1), hipMemcpyHostToDevice, s));
+    EB_HIP(hipStreamSynchronize(s));
+    B->nseg = nseg;
+    B->seg_rows.assign(rows ? rows : seg_blk.data(), rows ? rows + nseg + 1 : seg_blk.data());
+    return EB_OK;
+}
+
+// Buffers for kp slots with V-cycle element size vb (8 or 4 bytes) and the
+// given segmentation (nseg = 1, rows = null: no segments).
+static int ensure_batch(amg_handle* H, int kp, int prec, int nseg, const int32_t* rows, hipStream_t s) {
+    if (H->batch && H->batch->kp == kp && H->batch->prec == prec && H->batch->nseg == nseg) {
+        const std::vector<int32_t>& have = H->batch->seg_rows;
+        if (!rows ? have.empty() : (have.size() == (size_t)nseg + 1 && std::equal(have.begin(), have.end(), rows)))
+            return EB_OK;
+    }
     free_batch(H, s);
     BatchBufs* B = new BatchBufs();
     H->batch = B;
     B->kp = kp;
     B->prec = prec;
+    B->host = new BatchState();
+    EB_TRY(make_segments(H, B, nseg, rows, s));
     const int64_t nv = H->npad * kp;
     const size_t vb = prec == EB_PREC_FP32 ? sizeof(float) : sizeof(double);
     // read at neighbours without a guard: zero off unknowns
@@ -865,8 +1009,9 @@ static int ensure_batch(amg_handle* H, int kp, int prec, hipStream_t s) {
         EB_TRY(dalloc(&B->ev[l], vb * (size_t)n, s));
         EB_TRY(dalloc(&B->tmp[l], vb * (size_t)n, s));
     }
-    for (int i = 0; i < 3; ++i) EB_TRY(dalloc_n(&B->part[i], (int64_t)BPARTS * kp, s));
-    EB_TRY(dalloc_n(&B->part_aux, (int64_t)BPARTS * kp, s));
+    const int64_t nparts = (int64_t)(B->nblk > BPARTS ? B->nblk : BPARTS) * kp;
+    for (int i = 0; i < 3; ++i) EB_TRY(dalloc_n(&B->part[i], nparts, s));
+    EB_TRY(dalloc_n(&B->part_aux, nparts, s));
     EB_TRY(dalloc_n(&B->st, 1, s));
     EB_HIP(hipMemsetAsync(B->st, 0, sizeof(BatchState), s));
     return EB_OK;
@@ -891,6 +1036,15 @@ static BFine bfine(const amg_handle* H, const BatchBufs* B, bool full, unsigned*
     f.diag = H->diag_p;
     f.diag32 = H->diag_p32;
     f.done = st_done(const_cast<BatchBufs*>(B));
+    f.blk_start = nullptr;
+    f.blk_seg = nullptr;
+    if (B->blk_start) {
+        f.blk_start = B->blk_start;
+        f.blk_seg = B->blk_seg;
+        f.spb = 0;
+        *grid = (unsigned)B->nblk;
+        return f;
+    }
     if (full) {
         // one element per thread
         const int64_t per_block = BNT / ((int64_t)H->strip_w * f.kb);
@@ -975,7 +1129,8 @@ static unsigned rows_grid(int64_t rows, int kp) {
 template <class V>
 static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int initial, double* part, hipStream_t s) {
     const int kp = B->kp, lkp = ilog2(kp);
-    const int32_t* done = st_done(B);
+    // coarse vectors hold every segment's rows: with segments nothing is skipped there
+    const int32_t* done = B->blk_seg ? nullptr : st_done(B);
     V* z = (V*)B->z;
     if (H->nlev == 1) {
         const Level& L = H->lev[0];
@@ -1047,15 +1202,15 @@ static int benqueue_iteration(amg_handle* H, BatchBufs* B, int k, hipStream_t s)
     double* rout = B->rr[k & 1];
     BLAUNCH_V(kb_pspmv, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, (const V*)B->z, pold, pnew, B->q, (const BatchState*)B->st,
               B->part[0]);
-    hipLaunchKernelGGL(kb_fin_pq, dim3(1), dim3(BFIN), 0, s, B->st, B->part[0], (int)gfix, kp);
+    hipLaunchKernelGGL(kb_fin_pq, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part[0], B->seg_blk, kp);
     // (with one level the fused pre-smoothing residual is formed but not used)
     BLAUNCH_V(kb_xr_down, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->x, rin, rout, pnew, B->q, (V*)B->res, H->lev[0].omega,
               (const BatchState*)B->st, B->part[1]);
-    hipLaunchKernelGGL(kb_fin_rr, dim3(1), dim3(BFIN), 0, s, B->st, B->part[1], (int)gfix, kp);
+    hipLaunchKernelGGL(kb_fin_rr, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part[1], B->seg_blk, kp);
+    if (B->nseg > 1) hipLaunchKernelGGL(kb_fin_count, dim3(1), dim3(BFIN), 0, s, B->st);
     EB_LAUNCH_CHECK();
     EB_TRY(benqueue_vcycle<V>(H, B, rout, 0, B->part[2], s));
-    const int np_rz = H->nlev == 1 ? BPARTS : (int)gfix;
-    hipLaunchKernelGGL(kb_fin_rz, dim3(1), dim3(BFIN), 0, s, B->st, B->part[2], np_rz, kp, 0);
+    hipLaunchKernelGGL(kb_fin_rz, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part[2], B->seg_blk, kp, 0);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -1068,125 +1223,121 @@ static int benqueue_start(amg_handle* H, BatchBufs* B, double tol, hipStream_t s
     const BFine fr = bfine(H, B, false, &gfix);
     BLAUNCH_N(kb_norm2, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->part_aux);
     BLAUNCH_N(kb_resid, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->x, B->rr[0], B->part[1]);
-    hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, B->part[1], (int)gfix, kp, tol);
+    hipLaunchKernelGGL(kb_fin_init, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part_aux, B->part[1], B->seg_blk, kp,
+                       tol);
+    if (B->nseg > 1) hipLaunchKernelGGL(kb_fin_count, dim3(1), dim3(BFIN), 0, s, B->st);
     EB_LAUNCH_CHECK();
     EB_TRY(benqueue_vcycle<V>(H, B, B->rr[0], 1, B->part[2], s));
-    const int np_rz = H->nlev == 1 ? BPARTS : (int)gfix;
-    hipLaunchKernelGGL(kb_fin_rz, dim3(1), dim3(BFIN), 0, s, B->st, B->part[2], np_rz, kp, 1);
+    hipLaunchKernelGGL(kb_fin_rz, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part[2], B->seg_blk, kp, 1);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
 
+// Polling reads the two counters; bstate_get / bstate_put move the whole state.
 static int bpoll(BatchBufs* B, hipStream_t s) {
-    EB_HIP(hipMemcpyAsync(&B->host, B->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipMemcpyAsync(B->host, B->st, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     EB_HIP(hipStreamSynchronize(s));
     return EB_OK;
 }
-
-static int bset_mask(BatchBufs* B, const int32_t* mask, hipStream_t s) {
-    memcpy(B->host.mask, mask, sizeof(B->host.mask));
-    EB_HIP(hipMemcpyAsync(st_mask(B), B->host.mask, sizeof(B->host.mask), hipMemcpyHostToDevice, s));
-    EB_HIP(hipStreamSynchronize(s));   // the host array is reused
+static int bstate_get(BatchBufs* B, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(B->host, B->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    return EB_OK;
+}
+static int bstate_put(BatchBufs* B, hipStream_t s) {
+    EB_HIP(hipMemcpyAsync(B->st, B->host, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    EB_HIP(hipStreamSynchronize(s));   // the host copy is reused
     return EB_OK;
 }
 
+// Systems (seg, j): slots j < nrhs of every segment; results in
+// res[seg * nrhs + j].
 template <class V>
 static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t& p, pcg_result_t* res,
                        hipStream_t s) {
     const int kp = B->kp;
-    int32_t mask[BMAX_RHS];
-    for (int j = 0; j < BMAX_RHS; ++j) mask[j] = j < nrhs ? 1 : 0;
-    // unused slots: done from the start
-    {
-        BatchState init;
-        memset(&init, 0, sizeof(init));
-        for (int j = 0; j < BMAX_RHS; ++j) init.done[j] = j < nrhs ? 0 : 1;
-        B->host = init;
-        EB_HIP(hipMemcpyAsync(B->st, &B->host, sizeof(BatchState), hipMemcpyHostToDevice, s));
-        EB_HIP(hipStreamSynchronize(s));
+    const int nsys = B->nseg * kp;
+    BatchState& h = *B->host;
+    memset(&h, 0, sizeof(h));
+    h.nsys = nsys;
+    for (int i = 0; i < nsys; ++i) {
+        const bool used = (i % kp) < nrhs;
+        h.done[i] = used ? 0 : 1;      // unused slots: done from the start
+        h.mask[i] = used ? 1 : 0;
     }
-    EB_TRY(bset_mask(B, mask, s));
-    int restarts[BMAX_RHS] = {0};
+    EB_TRY(bstate_put(B, s));
+    std::vector<int> restarts((size_t)nsys, 0);
     int enqueued = 0;
     while (true) {
         EB_TRY(benqueue_start<V>(H, B, p.tol, s));
         int k = 0;
         while (true) {
             EB_TRY(bpoll(B, s));
-            if (B->host.ndone >= kp || B->host.maxiter >= p.maxit) break;
+            if (h.ndone >= nsys || h.maxiter >= p.maxit) break;
             if (enqueued > 4 * p.maxit + 4 * p.check_every) {
                 set_error("pcg_solve_batched: iteration counter stalled");
                 return EB_EHIP;
             }
-            const int left = p.maxit - B->host.maxiter;
+            const int left = p.maxit - h.maxiter;
             const int chunk = left < p.check_every ? left : p.check_every;
             for (int c = 0; c < chunk; ++c, ++enqueued) {
                 ++k;
                 EB_TRY(benqueue_iteration<V>(H, B, k, s));
             }
         }
-        // true residual ||b - A x|| per rhs (FP64)
+        // true residual ||b - A x|| per system (FP64)
         unsigned gfix = 0;
         const BFine fr = bfine(H, B, false, &gfix);
         BLAUNCH_N(kb_resid, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->bvec, B->x, B->tres, B->part_aux);
-        hipLaunchKernelGGL(kb_fin_true, dim3(1), dim3(BFIN), 0, s, B->st, B->part_aux, (int)gfix, kp);
+        hipLaunchKernelGGL(kb_fin_true, dim3(B->nseg), dim3(BFIN), 0, s, B->st, B->part_aux, B->seg_blk, kp);
         EB_LAUNCH_CHECK();
-        EB_TRY(bpoll(B, s));
+        EB_TRY(bstate_get(B, s));
         bool again = false;
-        for (int j = 0; j < BMAX_RHS; ++j) mask[j] = 0;
-        for (int j = 0; j < nrhs; ++j) {
-            const BatchState& h = B->host;
-            const double tr = h.bb[j] > 0.0 ? sqrt(h.rr_true[j] / h.bb[j]) : 0.0;
-            const bool drift = h.status[j] == EB_OK && h.bb[j] > 0.0 && tr > p.tol;
-            if (drift && restarts[j] == 0 && h.iters[j] < p.maxit) {
-                restarts[j] = 1;
-                mask[j] = 1;
+        for (int i = 0; i < nsys; ++i) {
+            h.mask[i] = 0;
+            if ((i % kp) >= nrhs) continue;
+            const double tr = h.bb[i] > 0.0 ? sqrt(h.rr_true[i] / h.bb[i]) : 0.0;
+            const bool drift = h.status[i] == EB_OK && h.bb[i] > 0.0 && tr > p.tol;
+            if (drift && restarts[i] == 0 && h.iters[i] < p.maxit) {
+                restarts[i] = 1;
+                h.mask[i] = 1;
+                h.done[i] = 0;   // the start kernels treat it as active again
                 again = true;
             }
         }
         if (!again) break;
-        // restart the drifted slots from their current iterate
-        EB_TRY(bset_mask(B, mask, s));
-        {
-            // clear their done flags so the start kernels treat them as active
-            BatchState& h = B->host;
-            for (int j = 0; j < nrhs; ++j)
-                if (mask[j]) h.done[j] = 0;
-            EB_HIP(hipMemcpyAsync(st_done(B), h.done, sizeof(h.done), hipMemcpyHostToDevice, s));
-            EB_HIP(hipStreamSynchronize(s));
-        }
+        // restart the drifted systems from their current iterate
+        EB_TRY(bstate_put(B, s));
     }
     int rc = EB_OK;
-    const BatchState& h = B->host;
-    for (int j = 0; j < nrhs; ++j) {
-        pcg_result_t& r = res[j];
-        memset(&r, 0, sizeof(r));
-        r.iterations = h.iters[j];
-        r.restarts = restarts[j];
-        r.levels = H->nlev;
-        r.rel_res_true = h.bb[j] > 0.0 ? sqrt(h.rr_true[j] / h.bb[j]) : 0.0;
-        r.rel_res_recursive = h.bb[j] > 0.0 ? sqrt(h.rr[j] / h.bb[j]) : 0.0;
-        int st = h.status[j];
-        if (st == EB_OK && h.bb[j] > 0.0 && r.rel_res_true > p.tol) st = EB_ENOCONV;
-        r.status = st;
-        if (st != EB_OK && rc == EB_OK) rc = st;
-    }
+    for (int sg = 0; sg < B->nseg; ++sg)
+        for (int j = 0; j < nrhs; ++j) {
+            const int i = sg * kp + j;
+            pcg_result_t& r = res[sg * nrhs + j];
+            memset(&r, 0, sizeof(r));
+            r.iterations = h.iters[i];
+            r.restarts = restarts[i];
+            r.levels = H->nlev;
+            r.rel_res_true = h.bb[i] > 0.0 ? sqrt(h.rr_true[i] / h.bb[i]) : 0.0;
+            r.rel_res_recursive = h.bb[i] > 0.0 ? sqrt(h.rr[i] / h.bb[i]) : 0.0;
+            int st = h.status[i];
+            if (st == EB_OK && h.bb[i] > 0.0 && r.rel_res_true > p.tol) st = EB_ENOCONV;
+            r.status = st;
+            if (st != EB_OK && rc == EB_OK) rc = st;
+        }
     return rc;
 }
 
-}  // namespace eb
-
-using namespace eb;
-
-extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* prm,
-                                 pcg_result_t* res, void* stream) {
-    clear_error();
+// Shared body of pcg_solve_batched (nseg = 1, rows = null) and
+// pcg_solve_islands.
+static int solve_systems(amg_handle_t* H, int32_t nrhs, int nseg, const int32_t* rows, const double* b, double* x,
+                         const pcg_params_t* prm, pcg_result_t* res, void* stream, const char* who) {
     if (!H || !b || !x || !res) {
-        set_error("pcg_solve_batched: null pointer");
+        set_error("%s: null pointer", who);
         return EB_EINVAL;
     }
     if (nrhs < 1 || nrhs > BMAX_RHS) {
-        set_error("pcg_solve_batched: nrhs = %d outside 1..%d", nrhs, BMAX_RHS);
+        set_error("%s: nrhs = %d outside 1..%d", who, nrhs, BMAX_RHS);
         return EB_EINVAL;
     }
     pcg_params_t p;
@@ -1198,8 +1349,27 @@ extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b,
     if (prm) p = *prm;
     if (!(p.tol > 0.0) || p.maxit < 0 || p.check_every < 1 ||
         (p.precision != EB_PREC_FP64 && p.precision != EB_PREC_FP32)) {
-        set_error("pcg_solve_batched: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0 or 1)");
+        set_error("%s: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0 or 1)", who);
         return EB_EINVAL;
+    }
+    int kp = 1;
+    while (kp < nrhs) kp <<= 1;
+    if (rows) {
+        const int64_t nrows = (int64_t)H->d.ny * H->d.nz;
+        if (nseg < 1 || nseg > BMAX_SEG || (int64_t)nseg * kp > BMAX_SLOTS) {
+            set_error("%s: nseg = %d outside 1..%d or nseg x %d slots above %d", who, nseg, BMAX_SEG, kp,
+                      BMAX_SLOTS);
+            return EB_EINVAL;
+        }
+        for (int t = 0; t < nseg; ++t)
+            if (rows[t] < 0 || rows[t] >= rows[t + 1] || rows[t + 1] > nrows) {
+                set_error("%s: segment rows must increase within 0..%lld", who, (long long)nrows);
+                return EB_EINVAL;
+            }
+        if (H->nlev < 2 && H->n_fine > 0) {
+            set_error("%s: segments need a hierarchy of two or more levels", who);
+            return EB_ENOTIMPL;
+        }
     }
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
     H->last_stream = s;
@@ -1211,7 +1381,7 @@ extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b,
     if (nunk == 0) {
         EB_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn * nrhs, s));
         EB_HIP(hipStreamSynchronize(s));
-        for (int j = 0; j < nrhs; ++j) {
+        for (int j = 0; j < nrhs * nseg; ++j) {
             memset(&res[j], 0, sizeof(res[j]));
             res[j].levels = H->nlev;
         }
@@ -1219,9 +1389,7 @@ extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b,
     }
     const bool fp32 = p.precision == EB_PREC_FP32;
     if (fp32) EB_TRY(ensure_fp32(H, s));
-    int kp = 1;
-    while (kp < nrhs) kp <<= 1;
-    EB_TRY(ensure_batch(H, kp, fp32 ? EB_PREC_FP32 : EB_PREC_FP64, s));
+    EB_TRY(ensure_batch(H, kp, fp32 ? EB_PREC_FP32 : EB_PREC_FP64, nseg, rows, s));
     BatchBufs* B = H->batch;
     const int lkp = ilog2(kp);
     const unsigned ug = (unsigned)(((nunk << lkp) + BNT - 1) / BNT);
@@ -1246,10 +1414,30 @@ extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b,
     EB_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     EB_HIP(hipEventElapsedTime(&ms, e0, e1));
-    for (int j = 0; j < nrhs; ++j) res[j].solve_ms = ms;
-    if (rc == EB_ENOCONV) set_error("pcg_solve_batched: a right-hand side did not converge within %d iterations",
-                                    p.maxit);
-    if (rc == EB_ENOTSPD) set_error("pcg_solve_batched: non-positive curvature in a right-hand side");
-    if (rc == EB_ENAN) set_error("pcg_solve_batched: NaN or Inf in a right-hand side");
+    for (int j = 0; j < nrhs * nseg; ++j) res[j].solve_ms = ms;
+    if (rc == EB_ENOCONV) set_error("%s: a system did not converge within %d iterations", who, p.maxit);
+    if (rc == EB_ENOTSPD) set_error("%s: non-positive curvature in a system", who);
+    if (rc == EB_ENAN) set_error("%s: NaN or Inf in a system", who);
     return rc;
+}
+
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* prm,
+                                 pcg_result_t* res, void* stream) {
+    clear_error();
+    return solve_systems(H, nrhs, 1, nullptr, b, x, prm, res, stream, "pcg_solve_batched");
+}
+
+extern "C" int pcg_solve_islands(amg_handle_t* H, int32_t nrhs, int32_t nseg, const int32_t* seg_rows,
+                                 const double* b, double* x, const pcg_params_t* prm, pcg_result_t* res,
+                                 void* stream) {
+    clear_error();
+    if (!seg_rows) {
+        set_error("pcg_solve_islands: null seg_rows");
+        return EB_EINVAL;
+    }
+    return solve_systems(H, nrhs, nseg, seg_rows, b, x, prm, res, stream, "pcg_solve_islands");
 }

@@ -354,6 +354,72 @@ def solve_batched(H: "Hierarchy", b: torch.Tensor, x0: Optional[torch.Tensor] = 
     return x, [_result_dict(res[j]) for j in range(nrhs)]
 
 
+@dataclass
+class IslandCanvas:
+    """Placement of several 2-D geometries' node grids one above the other in
+    one node grid (the canvas, h = 1) for pcg_solve_islands."""
+    grid: object                 # canvas grid (workloads.Grid-like: dim, n, x0, h = 1)
+    rows: np.ndarray             # int32 [nseg + 1]: first node row of each island, then the total
+    shapes: list                 # node-field shape (ny + 1, nx + 1) of each island
+    h: np.ndarray                # each island's own grid spacing
+
+    @property
+    def nseg(self) -> int:
+        return len(self.shapes)
+
+    def pack(self, fields, fill: float = 0.0, scale_h2: bool = False) -> np.ndarray:
+        """Canvas node field from one field per island (numpy); with scale_h2 each
+        island's values are multiplied by its h^2 (sources in canvas units)."""
+        out = np.full(self.grid.shape, fill, dtype=np.float64)
+        for i, (f, sh) in enumerate(zip(fields, self.shapes)):
+            f = np.asarray(f, dtype=np.float64).reshape(sh)
+            r0 = int(self.rows[i])
+            out[r0:r0 + sh[0], :sh[1]] = f * (self.h[i] ** 2) if scale_h2 else f
+        return out
+
+    def unpack(self, field):
+        """Per-island views of a canvas node field (numpy or torch, last two axes)."""
+        return [field[..., int(self.rows[i]):int(self.rows[i]) + sh[0], :sh[1]] for i, sh in enumerate(self.shapes)]
+
+
+def stack_islands(grids) -> IslandCanvas:
+    """Canvas for 2-D geometries given by their grids (each with its own n and h)."""
+    shapes = [tuple(g.shape) for g in grids]
+    if any(len(sh) != 2 for sh in shapes):
+        raise ValueError("stack_islands: 2-D grids only")
+    width = max(sh[1] for sh in shapes)
+    rows = np.zeros(len(shapes) + 1, dtype=np.int32)
+    rows[1:] = np.cumsum([sh[0] for sh in shapes])
+    from types import SimpleNamespace
+    n = (width - 1, int(rows[-1]) - 1)
+    canvas = SimpleNamespace(dim=2, n=n, x0=(0.0, 0.0), h=1.0, shape=(n[1] + 1, n[0] + 1))
+    return IslandCanvas(canvas, rows, shapes, np.array([g.h for g in grids], dtype=np.float64))
+
+
+def solve_islands(H: "Hierarchy", b: torch.Tensor, rows, x0: Optional[torch.Tensor] = None, tol: float = 1e-8,
+                  maxit: int = 1000, check_every: int = 8, allow_noconv: bool = False, precision: str = "fp64"):
+    """pcg_solve_islands: b of shape (nrhs, *canvas shape), rows the segments'
+    node-row bounds; returns (x, infos) with infos[s][j] for island s, rhs j."""
+    shape = tuple(H.grid.shape)
+    if b.dim() != len(shape) + 1:
+        raise ValueError("b must have shape (nrhs, *grid.shape)")
+    nrhs = b.shape[0]
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+    nseg = rows.size - 1
+    bp = _field(b, (nrhs,) + shape, torch.float64, "b")
+    x = torch.empty((nrhs,) + shape, dtype=torch.float64, device=b.device)
+    if x0 is not None:
+        x.copy_(x0)
+    xp = _field(x, (nrhs,) + shape, torch.float64, "x")
+    prm = L.PcgParams(float(tol), int(maxit), 1 if x0 is not None else 0, int(check_every), L.PRECISION[precision])
+    res = (L.PcgResult * max(nrhs * nseg, 1))()
+    rc = L.lib().pcg_solve_islands(H.handle, int(nrhs), int(nseg), rows.ctypes.data_as(C.POINTER(C.c_int32)), bp, xp,
+                                   C.byref(prm), res, _stream())
+    ok = (L.EB_OK, L.EB_ENOCONV) if allow_noconv else (L.EB_OK,)
+    L.check(rc, "pcg_solve_islands", ok=ok)
+    return x, [[_result_dict(res[s * nrhs + j]) for j in range(nrhs)] for s in range(nseg)]
+
+
 def solve_problem(problem, device="cuda", tol=None, coarse_max=256, precision="fp64"):
     """Full path for one workloads.Problem: assemble, RHS, setup, solve."""
     g = problem.grid

@@ -20,8 +20,12 @@ time.  `mixed` repeats the same steps with the single-precision V-cycle
 initial conditions as one batched solve (pcg_solve_batched) and as 64 single
 solves on the same hierarchy.  `learned_3d` solves the 3-D ellipsoid 256^3
 Poisson problem with the plain and the learned fine smoother (network trained
-on the GPU at 96^3), both V-cycle precisions.  `cpu_baseline` times the CPU
-oracle on full steps of the same workload.
+on the GPU at 96^3), both V-cycle precisions.  `islands` runs the
+shape-optimisation batch (256 random stars, N in {256 .. 1024}, 4 sources
+each) as one island solve (pcg_solve_islands: one canvas, one hierarchy,
+one launch sequence; timed from assembly to solution) and geometry by
+geometry.  `cpu_baseline` times the CPU oracle on full steps of the same
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -187,6 +191,100 @@ def learned_ellipsoid(n=256, n_train=96, steps=120, reps=3):
     return out
 
 
+def shape_opt_islands(count=256, nrhs=4, reps=2):
+    """The shape-optimisation batch: `count` random stars (N in {256 .. 1024}),
+    `nrhs` seeded heat-type sources each, Dirichlet data 0, tol 1e-8.  One
+    island solve (all geometries stacked in one canvas: one assembly, one
+    hierarchy, one launch sequence) against the same work geometry by
+    geometry (assembly, setup and a batched solve per star)."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+    params = W.random_star_params(count)
+    grids = [W.unit_box_grid(2, n) for n, _, _ in params]
+    canvas = S.stack_islands(grids)
+
+    def psi_of(g, c, ph):
+        x = torch.as_tensor(g.axis_coords(0), device=dev)
+        y = torch.as_tensor(g.axis_coords(1), device=dev)
+        X, Y = x[None, :], y[:, None]
+        phi = torch.atan2(Y, X)
+        r = torch.full_like(phi, 0.3)
+        for m in range(5):
+            r = r + float(c[m]) * torch.cos((m + 2) * phi + float(ph[m]))
+        return torch.sqrt(X * X + Y * Y) - r
+
+    def sources_of(i, g):
+        return W.heat_initial_batch(g, range(nrhs * i, nrhs * i + nrhs), dev)
+
+    # inputs in HBM: per-island psi and sources, and their canvas packing
+    psis = [psi_of(g, c, ph) for g, (n, c, ph) in zip(grids, params)]
+    srcs = [sources_of(i, g) for i, g in enumerate(grids)]
+    psi_c = torch.ones(canvas.grid.shape, dtype=torch.float64, device=dev)
+    f_c = torch.zeros((nrhs,) + tuple(canvas.grid.shape), dtype=torch.float64, device=dev)
+    for i, (g, sh) in enumerate(zip(grids, canvas.shapes)):
+        r0 = int(canvas.rows[i])
+        psi_c[r0:r0 + sh[0], :sh[1]] = psis[i]
+        f_c[:, r0:r0 + sh[0], :sh[1]] = srcs[i] * (g.h * g.h)
+    n_unk = 0
+
+    def island_run(prec):
+        asm = S.assemble_diag(canvas.grid, psi_c)
+        zero = torch.zeros(asm.n_cuts, dtype=torch.float64, device=dev)
+        B = torch.stack([S.assemble_rhs(asm, f_c[j], zero) for j in range(nrhs)]).contiguous()
+        H = S.Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-8, precision=prec)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        lev = H.n_levels
+        H.free()
+        return asm.n_unknowns, infos, t_solve, lev
+
+    def sequential_run(prec):
+        its = []
+        for i, g in enumerate(grids):
+            asm = S.assemble_diag(g, psis[i])
+            zero = torch.zeros(asm.n_cuts, dtype=torch.float64, device=dev)
+            B = torch.stack([S.assemble_rhs(asm, srcs[i][j].contiguous(), zero) for j in range(nrhs)]).contiguous()
+            H = S.Hierarchy(g, asm.kind, asm.a, 0.0)
+            _, infos = H.solve_batched(B, tol=1e-8, precision=prec)
+            its += [x["iterations"] for x in infos]
+            H.free()
+        return its
+
+    out = {"workload": f"random_stars_{count}_n256-1024_{nrhs}rhs_tol1e-8", "geometries": count, "nrhs": nrhs,
+           "canvas_nodes": int(canvas.grid.shape[0]) * int(canvas.grid.shape[1])}
+    for prec in ("fp32", "fp64"):
+        island_run(prec)                          # warm-up (allocator, FP32 copies)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            n_unk, infos, t_solve, lev = island_run(prec)
+        torch.cuda.synchronize()
+        t_all = (time.perf_counter() - t0) / reps
+        its = [x["iterations"] for row in infos for x in row]
+        sequential_run(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sits = sequential_run(prec)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        nsys = count * nrhs
+        out[prec] = {"ms": t_all * 1e3, "solve_ms": t_solve * 1e3, "solves_per_s": nsys / t_all,
+                     "solve_phase_solves_per_s": nsys / t_solve, "levels": lev,
+                     "iterations_min_max": [min(its), max(its)],
+                     "rel_res_true_max": max(x["rel_res_true"] for row in infos for x in row),
+                     "all_converged": all(x["status"] == 0 for row in infos for x in row),
+                     "sequential_ms": t_seq * 1e3, "sequential_solves_per_s": nsys / t_seq,
+                     "sequential_iterations_min_max": [min(sits), max(sits)],
+                     "speedup_vs_sequential": t_seq / t_all}
+    out["n_unknowns"] = n_unk
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +294,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched heat-step measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the 3-D learned-smoother measurement")
+    ap.add_argument("--no-islands", action="store_true", help="skip the shape-optimisation island batch")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -545,6 +644,8 @@ def main():
         out["batched"] = batched_heat()
     if not args.no_learned:
         out["learned_3d"] = learned_ellipsoid()
+    if not args.no_islands:
+        out["islands"] = shape_opt_islands()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

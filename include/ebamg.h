@@ -237,6 +237,22 @@ int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x,
 int pcg_solve_islands(amg_handle_t* H, int32_t nrhs, int32_t nseg, const int32_t* seg_rows, const double* b,
                       double* x, const pcg_params_t* p, pcg_result_t* res, void* stream);
 
+/* Launch shape of the batched fine kernels (pcg_solve_batched and
+ * pcg_solve_islands): the plane width (right-hand sides stored together per
+ * node) and the planes one block handles.  By default an autotuner picks
+ * them on the first solve with new batch buffers: every candidate (width 8
+ * or 16, 1, 2 or 4 planes per block) times the two largest fine kernels on
+ * the real buffers, the fastest is kept with the buffers and in a
+ * process-wide table keyed by the problem shape.  pcg_batched_set_launch_shape
+ * fixes the shape for batch buffers made afterwards (width 8, 16, 32 or 64;
+ * 1, 2 or 4 planes per block; 0, 0 returns to the autotuner; EB_EINVAL
+ * otherwise).  pcg_batched_launch_shape reports the shape in use on H and, if
+ * ncand is given, the timed candidates (at most 8; host arrays; EB_EINVAL
+ * before the first batched solve on H).                                       */
+int pcg_batched_set_launch_shape(int32_t plane_width, int32_t planes_per_block);
+int pcg_batched_launch_shape(const amg_handle_t* H, int32_t* plane_width, int32_t* planes_per_block,
+                             int32_t* ncand, int32_t* cand_width, int32_t* cand_planes, float* cand_ms);
+
 /* Apply one V(1,1) cycle z = M r (node fields; parity and debugging aid).     */
 int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
 

@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 
@@ -90,10 +91,13 @@ struct BatchBufs {
     int32_t* seg_blk = nullptr;
     // layout and launch shape of the fine kernels: plane width (slots per
     // plane, node-major inside a plane) and planes per block (the grid's y
-    // dimension covers the rest); chosen by timing 8/16/32/64 and 1/2/4/8 on
-    // the 64-RHS heat workload
+    // dimension covers the rest); set by the autotuner on the first solve
     int kbw = 8;
     int npb = 2;
+    bool tuned = false;
+    int ncand = 0;
+    int cand_w[8] = {}, cand_n[8] = {};
+    float cand_ms[8] = {};
 };
 
 // ------------------------------------------------------------------ helpers
@@ -995,6 +999,7 @@ static int ensure_batch(amg_handle* H, int kp, int prec, int nseg, const int32_t
         EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * nv, s));
     }
     EB_TRY(dalloc_n(&B->q, nv, s));
+    EB_HIP(hipMemsetAsync(B->q, 0, sizeof(double) * nv, s));
     EB_TRY(dalloc_n(&B->bvec, nv, s));
     EB_HIP(hipMemsetAsync(B->bvec, 0, sizeof(double) * nv, s));
     EB_TRY(dalloc_n(&B->tres, nv, s));
@@ -1328,6 +1333,113 @@ static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t
     return rc;
 }
 
+// ------------------------------------------------------------- autotuner
+// Launch shape of the fine kernels, chosen by timing: on the first solve with
+// a new set of batch buffers (before the right-hand sides are loaded: the
+// vectors hold zeros, every system is active with alpha = beta = 1), each
+// candidate (plane width 8 or 16, planes per block 1, 2 or 4, within the
+// plane count) runs the two largest fine kernels (p-update and x/r update)
+// twice between HIP events; the fastest second run wins.  The choice is kept
+// with the buffers and in a process-wide table keyed by the strip count, the
+// slot count, the precision and the segment count, so later handles of the
+// same shape skip the timing.  A shape set by pcg_batched_set_launch_shape is
+// used as it is.
+struct TuneEntry {
+    int64_t nstrips;
+    int kp, prec, nseg, kbw, npb;
+};
+static std::mutex g_tune_mutex;
+static std::vector<TuneEntry> g_tune_table;
+static int g_forced_kbw = 0, g_forced_npb = 0;
+
+template <class V>
+static int autotune_batch(amg_handle* H, BatchBufs* B, hipStream_t s) {
+    B->tuned = true;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        if (g_forced_kbw > 0) {
+            B->kbw = g_forced_kbw;
+            B->npb = g_forced_npb;
+            B->ncand = 0;
+            return EB_OK;
+        }
+        for (const TuneEntry& e : g_tune_table)
+            if (e.nstrips == H->nstrips && e.kp == B->kp && e.prec == B->prec && e.nseg == B->nseg) {
+                B->kbw = e.kbw;
+                B->npb = e.npb;
+                return EB_OK;
+            }
+    }
+    BatchState& h = *B->host;
+    memset(&h, 0, sizeof(h));
+    h.nsys = B->nseg * B->kp;
+    for (int i = 0; i < h.nsys; ++i) h.alpha[i] = h.beta[i] = 1.0;
+    EB_TRY(bstate_put(B, s));
+    hipEvent_t a = nullptr, b = nullptr;
+    EB_HIP(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return EB_EHIP;
+    }
+    const int widths[2] = {8, 16}, npbs[3] = {1, 2, 4};
+    int best_w = B->kbw, best_n = B->npb;
+    float best = 1e30f;
+    int rc = EB_OK;
+    B->ncand = 0;
+    for (int wi = 0; wi < 2 && rc == EB_OK; ++wi) {
+        const int w = widths[wi];
+        if (w > B->kp && wi > 0) break;                 // the plane width is min(kp, w)
+        const int planes = B->kp / (B->kp < w ? B->kp : w);
+        for (int ni = 0; ni < 3 && rc == EB_OK; ++ni) {
+            const int n = npbs[ni];
+            if (n > planes && ni > 0) break;
+            B->kbw = w;
+            B->npb = n;
+            float t = 1e30f;
+            for (int rep = 0; rep < 2 && rc == EB_OK; ++rep) {
+                unsigned gfix = 0;
+                const BFine fr = bfine(H, B, false, &gfix);
+                if (hipEventRecord(a, s) != hipSuccess) rc = EB_EHIP;
+                BLAUNCH_V(kb_pspmv, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, (const V*)B->z, B->p[1], B->p[0], B->q,
+                          (const BatchState*)B->st, B->part[0]);
+                BLAUNCH_V(kb_xr_down, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->x, B->rr[0], B->rr[1], B->p[0],
+                          B->q, (V*)B->res, H->lev[0].omega, (const BatchState*)B->st, B->part[1]);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(b, s) != hipSuccess ||
+                    hipEventSynchronize(b) != hipSuccess) {
+                    rc = EB_EHIP;
+                    break;
+                }
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = EB_EHIP;
+                t = ms;                                   // the second run counts
+            }
+            if (B->ncand < 8) {
+                B->cand_w[B->ncand] = w;
+                B->cand_n[B->ncand] = n;
+                B->cand_ms[B->ncand] = t;
+                ++B->ncand;
+            }
+            if (t < best) {
+                best = t;
+                best_w = w;
+                best_n = n;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != EB_OK) {
+        set_error("batched launch-shape autotuner: HIP error");
+        return rc;
+    }
+    B->kbw = best_w;
+    B->npb = best_n;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_table.push_back({H->nstrips, B->kp, B->prec, B->nseg, best_w, best_n});
+    return EB_OK;
+}
+
 // Shared body of pcg_solve_batched (nseg = 1, rows = null) and
 // pcg_solve_islands.
 static int solve_systems(amg_handle_t* H, int32_t nrhs, int nseg, const int32_t* rows, const double* b, double* x,
@@ -1391,6 +1503,7 @@ static int solve_systems(amg_handle_t* H, int32_t nrhs, int nseg, const int32_t*
     if (fp32) EB_TRY(ensure_fp32(H, s));
     EB_TRY(ensure_batch(H, kp, fp32 ? EB_PREC_FP32 : EB_PREC_FP64, nseg, rows, s));
     BatchBufs* B = H->batch;
+    if (!B->tuned) EB_TRY(fp32 ? autotune_batch<float>(H, B, s) : autotune_batch<double>(H, B, s));
     const int lkp = ilog2(kp);
     const unsigned ug = (unsigned)(((nunk << lkp) + BNT - 1) / BNT);
     unsigned gdummy = 0;
@@ -1440,4 +1553,44 @@ extern "C" int pcg_solve_islands(amg_handle_t* H, int32_t nrhs, int32_t nseg, co
         return EB_EINVAL;
     }
     return solve_systems(H, nrhs, nseg, seg_rows, b, x, prm, res, stream, "pcg_solve_islands");
+}
+
+extern "C" int pcg_batched_set_launch_shape(int32_t plane_width, int32_t planes_per_block) {
+    clear_error();
+    const bool autom = plane_width == 0 && planes_per_block == 0;
+    const bool ok = (plane_width == 8 || plane_width == 16 || plane_width == 32 || plane_width == 64) &&
+                    (planes_per_block == 1 || planes_per_block == 2 || planes_per_block == 4);
+    if (!autom && !ok) {
+        set_error("pcg_batched_set_launch_shape: plane width 8/16/32/64 and 1/2/4 planes per block, or 0, 0");
+        return EB_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_forced_kbw = plane_width;
+    g_forced_npb = planes_per_block;
+    return EB_OK;
+}
+
+extern "C" int pcg_batched_launch_shape(const amg_handle_t* H, int32_t* plane_width, int32_t* planes_per_block,
+                                        int32_t* ncand, int32_t* cand_width, int32_t* cand_planes, float* cand_ms) {
+    clear_error();
+    if (!H || !plane_width || !planes_per_block) {
+        set_error("pcg_batched_launch_shape: null pointer");
+        return EB_EINVAL;
+    }
+    const BatchBufs* B = H->batch;
+    if (!B || !B->tuned) {
+        set_error("pcg_batched_launch_shape: no batched solve on this handle yet");
+        return EB_EINVAL;
+    }
+    *plane_width = B->kp < B->kbw ? B->kp : B->kbw;
+    *planes_per_block = B->npb;
+    if (ncand) {
+        *ncand = B->ncand;
+        for (int i = 0; i < B->ncand; ++i) {
+            if (cand_width) cand_width[i] = B->cand_w[i];
+            if (cand_planes) cand_planes[i] = B->cand_n[i];
+            if (cand_ms) cand_ms[i] = B->cand_ms[i];
+        }
+    }
+    return EB_OK;
 }

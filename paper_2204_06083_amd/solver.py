@@ -420,6 +420,23 @@ def solve_islands(H: "Hierarchy", b: torch.Tensor, rows, x0: Optional[torch.Tens
     return x, [[_result_dict(res[s * nrhs + j]) for j in range(nrhs)] for s in range(nseg)]
 
 
+def set_batched_launch_shape(plane_width: int = 0, planes_per_block: int = 0):
+    """Fix the batched fine kernels' launch shape for batch buffers made from
+    now on (0, 0: the autotuner chooses)."""
+    L.check(L.lib().pcg_batched_set_launch_shape(int(plane_width), int(planes_per_block)),
+            "pcg_batched_set_launch_shape")
+
+
+def batched_launch_shape(H: "Hierarchy") -> dict:
+    """Launch shape in use on H and the autotuner's timed candidates."""
+    w, n, nc = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    cw, cn, cm = (C.c_int32 * 8)(), (C.c_int32 * 8)(), (C.c_float * 8)()
+    L.check(L.lib().pcg_batched_launch_shape(H.handle, C.byref(w), C.byref(n), C.byref(nc), cw, cn, cm),
+            "pcg_batched_launch_shape")
+    return {"plane_width": w.value, "planes_per_block": n.value,
+            "candidates": [{"plane_width": cw[i], "planes_per_block": cn[i], "ms": cm[i]} for i in range(nc.value)]}
+
+
 def solve_problem(problem, device="cuda", tol=None, coarse_max=256, precision="fp64"):
     """Full path for one workloads.Problem: assemble, RHS, setup, solve."""
     g = problem.grid

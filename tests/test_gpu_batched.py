@@ -143,3 +143,37 @@ def test_batched_heat1024_64rhs():
     x5 = X[5].cpu().numpy().ravel()[asm_o.nodes]
     assert np.linalg.norm(b_o - A @ x5) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
     H.free()
+
+
+def test_launch_shapes_agree_and_autotuner_reports():
+    """Every fixed launch shape of the batched fine kernels gives the same
+    solutions as the autotuned one; the autotuner reports its candidates."""
+    prob = W.star_heat(512, 0)
+    asm_o, A, fields, asm_g, B = _rhs_family(prob, 16, seed=9)
+    Bd = to_dev(B)
+    S.set_batched_launch_shape(0, 0)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    Xa, ia = H.solve_batched(Bd, tol=1e-10)
+    rep = S.batched_launch_shape(H)
+    print(f"[gpu] autotuned shape {rep['plane_width']} x {rep['planes_per_block']}: "
+          + ", ".join(f"{c['plane_width']}x{c['planes_per_block']} {c['ms']:.3f} ms" for c in rep["candidates"]),
+          flush=True)
+    assert len(rep["candidates"]) >= 2
+    assert (rep["plane_width"], rep["planes_per_block"]) in [(c["plane_width"], c["planes_per_block"])
+                                                            for c in rep["candidates"]]
+    H.free()
+    try:
+        for w, n in ((8, 1), (8, 4), (16, 2), (32, 1), (64, 1)):
+            S.set_batched_launch_shape(w, n)
+            H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+            X, infos = H.solve_batched(Bd, tol=1e-10)
+            r = S.batched_launch_shape(H)
+            assert r["plane_width"] == min(w, 16) and r["planes_per_block"] == n
+            for j in range(16):
+                assert abs(infos[j]["iterations"] - ia[j]["iterations"]) <= 1
+                assert rel(X[j].cpu().numpy().ravel(), Xa[j].cpu().numpy().ravel()) <= 1e-12
+            H.free()
+        with pytest.raises(L.EbError):
+            S.set_batched_launch_shape(12, 1)
+    finally:
+        S.set_batched_launch_shape(0, 0)

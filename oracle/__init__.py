@@ -13,6 +13,9 @@ Modules
   amg          box aggregation, smoothed prolongator, Galerkin products,
                coarsest Cholesky, V(1,1) cycle
   pcg          preconditioned conjugate gradients and direct references
+  learned      the learned fine-smoother extension: network, weighted cycle,
+               loss and gradients
+  steppers     theta-scheme (wave) and Crank-Nicolson (heat) time steppers
 
 Parity status per function is stated in each module header.
 """

@@ -95,16 +95,35 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         if (kind[n + st] == 2) continue;
         const int pos = axis_coord(p, axis);
         const int len = axis_len(d, axis);
+        // walk to the first outside node; the outermost layer is outside.
+        // Where the boundary runs almost along the line the walk is long, so
+        // the nodes are read WALK at a time (all loads in flight, none past
+        // the outer layer) and then examined in order.
+        constexpr int WALK = 8;
         int j = 2;
-        // walk to the first outside node; the outermost layer is outside
-        while (true) {
-            const int at = pos + j * step;
-            if (at <= 0 || at >= len - 1) {
-                if (psi[n + (int64_t)j * st] < 0.0) atomicOr(err, DEVERR_DOMAIN);
-                break;
+        bool found = false;
+        while (!found) {
+            double v[WALK];
+#pragma unroll
+            for (int u = 0; u < WALK; ++u) {
+                // clamped to the outer layer: the examination below stops there
+                const int at = min(max(pos + (j + u) * step, 0), len - 1);
+                v[u] = psi[n + (int64_t)(at - pos) * axis_stride(d, axis)];
             }
-            if (!(psi[n + (int64_t)j * st] < 0.0)) break;
-            ++j;
+#pragma unroll
+            for (int u = 0; u < WALK; ++u) {
+                if (found) continue;
+                const int at = pos + (j + u) * step;
+                if (at <= 0 || at >= len - 1) {
+                    if (v[u] < 0.0) atomicOr(err, DEVERR_DOMAIN);
+                    j += u;
+                    found = true;
+                } else if (!(v[u] < 0.0)) {
+                    j += u;
+                    found = true;
+                }
+            }
+            if (!found) j += WALK;
         }
         const double psi_in = psi[n + (int64_t)(j - 1) * st];
         const double psi_out = psi[n + (int64_t)j * st];

@@ -468,18 +468,6 @@ struct SlotMap {
     }
 };
 
-// LDS layout for NT threads with ns slots each: vals[s * NT + t], flags[s * NT + t].
-struct SlotLds {
-    double* vals;
-    uint8_t* flags;
-    int nt;
-    __device__ void init(char* smem, int ns, int nt_) {
-        nt = nt_;
-        vals = reinterpret_cast<double*>(smem);
-        flags = reinterpret_cast<uint8_t*>(smem + sizeof(double) * (size_t)ns * nt_);
-    }
-};
-
 enum { ACC_P = 0, ACC_AP = 1, ACC_RAP = 2 };
 
 struct AccArgs {
@@ -503,65 +491,99 @@ struct AccArgs {
     int32_t* err;
 };
 
-// One pass per row: accumulate into the slot array (LDS), then write the
+// One pass per row: accumulate into slot arrays in LDS, then write the
 // occupied slots, in slot = column order, to the row's ELL scratch and count.
+// G lanes share a row (blockDim.x = rows per block x G): lane g takes the
+// first operand's entries g, g + G, ... in order into a slot array of its
+// own; the G arrays are then added slot by slot in lane order.  The order of
+// the sums is fixed, so the result is deterministic (for G = 1 it is the
+// plain row-by-row accumulation).  LDS: vals[t * ns + s], flags likewise.
 template <int MODE>
-__global__ void k_accumulate(AccArgs A) {
+__global__ void k_accumulate(AccArgs A, int G) {
     extern __shared__ char smem[];
-    SlotLds L;
     const int ns = A.sm.nslots;
     const int nt = blockDim.x;
-    L.init(smem, ns, nt);
     const int t = threadIdx.x;
-    const int64_t row = (int64_t)blockIdx.x * nt + t;
-    if (row >= A.nrows) return;
-    for (int s = 0; s < ns; ++s) {
-        L.flags[s * nt + t] = 0;
-        L.vals[s * nt + t] = 0.0;
+    const int g = t % G;
+    const int rl = t / G;
+    double* vals = reinterpret_cast<double*>(smem);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(smem + sizeof(double) * (size_t)ns * nt);
+    const int64_t row = (int64_t)blockIdx.x * (nt / G) + rl;
+    const bool active = row < A.nrows;
+    for (int sl = 0; sl < ns; ++sl) {
+        flags[t * ns + sl] = 0;
+        vals[t * ns + sl] = 0.0;
     }
-    const int bx = A.row_coords[3 * row] / A.centre_div;
-    const int by = A.row_coords[3 * row + 1] / A.centre_div;
-    const int bz = A.row_coords[3 * row + 2] / A.centre_div;
+    int bx = 0, by = 0, bz = 0;
     bool bad = false;
-    if (MODE == ACC_P) {
-        const double dii = A.diag[row];
-        const double omega = *A.omega;
-        const int s0 = A.sm.slot(A.agg[row], bx, by, bz);
-        if (s0 < 0) {
-            bad = true;
+    if (active) {
+        bx = A.row_coords[3 * row] / A.centre_div;
+        by = A.row_coords[3 * row + 1] / A.centre_div;
+        bz = A.row_coords[3 * row + 2] / A.centre_div;
+        double* v = vals + (size_t)t * ns;
+        uint8_t* fl = flags + (size_t)t * ns;
+        if (MODE == ACC_P) {
+            const double dii = A.diag[row];
+            const double omega = *A.omega;
+            if (g == 0) {
+                const int s0 = A.sm.slot(A.agg[row], bx, by, bz);
+                if (s0 < 0) {
+                    bad = true;
+                } else {
+                    fl[s0] = 1;
+                    v[s0] = 1.0;
+                }
+            }
+            for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
+                const int j = A.x_col[e];
+                const int sl = A.sm.slot(A.agg[j], bx, by, bz);
+                if (sl < 0) { bad = true; continue; }
+                fl[sl] = 1;
+                const double w = omega * (A.x_val[e] / dii);
+                v[sl] = v[sl] - w;
+            }
         } else {
-            L.flags[s0 * nt + t] = 1;
-            L.vals[s0 * nt + t] = 1.0;
-        }
-        for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
-            const int j = A.x_col[e];
-            const int s = A.sm.slot(A.agg[j], bx, by, bz);
-            if (s < 0) { bad = true; continue; }
-            L.flags[s * nt + t] = 1;
-            const double w = omega * (A.x_val[e] / dii);
-            L.vals[s * nt + t] = L.vals[s * nt + t] - w;
-        }
-    } else {
-        for (int e = A.x_rowptr[row]; e < A.x_rowptr[row + 1]; ++e) {
-            const int k = A.x_col[e];
-            const double xv = A.x_val[e];
-            for (int f = A.y_rowptr[k]; f < A.y_rowptr[k + 1]; ++f) {
-                const int s = A.sm.slot(A.y_col[f], bx, by, bz);
-                if (s < 0) { bad = true; continue; }
-                L.flags[s * nt + t] = 1;
-                const double pr = xv * A.y_val[f];
-                L.vals[s * nt + t] = L.vals[s * nt + t] + pr;
+            for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
+                const int k = A.x_col[e];
+                const double xv = A.x_val[e];
+                for (int f = A.y_rowptr[k]; f < A.y_rowptr[k + 1]; ++f) {
+                    const int sl = A.sm.slot(A.y_col[f], bx, by, bz);
+                    if (sl < 0) { bad = true; continue; }
+                    fl[sl] = 1;
+                    const double pr = xv * A.y_val[f];
+                    v[sl] = v[sl] + pr;
+                }
             }
         }
     }
     if (bad) atomicOr(A.err, DEVERR_CAP);
+    if (G > 1) {
+        __syncthreads();
+        // lane g owns slots g, g + G, ...: sum the G arrays in lane order into
+        // the row's first array
+        const int t0 = rl * G;
+        for (int sl = g; sl < ns; sl += G) {
+            double acc = 0.0;
+            uint8_t f = 0;
+            for (int h = 0; h < G; ++h) {
+                acc += vals[(size_t)(t0 + h) * ns + sl];
+                f |= flags[(size_t)(t0 + h) * ns + sl];
+            }
+            vals[(size_t)t0 * ns + sl] = acc;
+            flags[(size_t)t0 * ns + sl] = f;
+        }
+        __syncthreads();
+    }
+    if (!active || g != 0) return;
+    const double* v = vals + (size_t)t * ns;
+    const uint8_t* fl = flags + (size_t)t * ns;
     int c = 0;
     const int64_t base = row * A.ell_stride;
-    for (int s = 0; s < ns; ++s) {
-        if (L.flags[s * nt + t]) {
+    for (int sl = 0; sl < ns; ++sl) {
+        if (fl[sl]) {
             if (c < A.ell_stride) {
-                A.ell_col[base + c] = A.sm.column(s, bx, by, bz);
-                A.ell_val[base + c] = L.vals[s * nt + t];
+                A.ell_col[base + c] = A.sm.column(sl, bx, by, bz);
+                A.ell_val[base + c] = v[sl];
             }
             ++c;
         }
@@ -989,20 +1011,27 @@ static int rowptr_from_counts(const int32_t* cnt, int64_t n, int32_t** rowptr, h
     return EB_OK;
 }
 
+// Lanes per row: enough (row x lane) threads to fill the GPU when the level
+// has few rows (their chains of products are the long ones), within an LDS
+// budget per row; P rows (a handful of entries each) keep one lane.
 static int launch_accumulate(int mode, AccArgs& args, hipStream_t s) {
     const int ns = args.sm.nslots;
-    const size_t per_thread = (size_t)ns * (sizeof(double) + 1);
-    int nt = 256;
-    while (nt > 64 && per_thread * nt > 64 * 1024) nt >>= 1;
-    if (per_thread * nt > 150 * 1024) {
-        set_error("accumulator needs %zu bytes of LDS per 64 rows", per_thread * 64);
+    const size_t per_lane = (size_t)ns * (sizeof(double) + 1);
+    int G = 1;
+    if (mode != ACC_P)
+        while (G < 64 && args.nrows * (int64_t)(2 * G) <= 512 * 1024 && per_lane * (2 * G) <= 32 * 1024) G *= 2;
+    int rows = 256 / G;
+    while (rows > 1 && per_lane * G * rows > 64 * 1024) rows >>= 1;
+    if (per_lane * G * rows > 150 * 1024) {
+        set_error("accumulator needs %zu bytes of LDS per row", per_lane * G);
         return EB_ENOSPC;
     }
-    const size_t lds = per_thread * nt + 16;
-    const dim3 grid((unsigned)((args.nrows + nt - 1) / nt > 0 ? (args.nrows + nt - 1) / nt : 1));
-    if (mode == ACC_P) hipLaunchKernelGGL((k_accumulate<ACC_P>), grid, dim3(nt), lds, s, args);
-    else if (mode == ACC_AP) hipLaunchKernelGGL((k_accumulate<ACC_AP>), grid, dim3(nt), lds, s, args);
-    else hipLaunchKernelGGL((k_accumulate<ACC_RAP>), grid, dim3(nt), lds, s, args);
+    const int nt = rows * G;
+    const size_t lds = per_lane * nt + 16;
+    const dim3 grid((unsigned)((args.nrows + rows - 1) / rows > 0 ? (args.nrows + rows - 1) / rows : 1));
+    if (mode == ACC_P) hipLaunchKernelGGL((k_accumulate<ACC_P>), grid, dim3(nt), lds, s, args, G);
+    else if (mode == ACC_AP) hipLaunchKernelGGL((k_accumulate<ACC_AP>), grid, dim3(nt), lds, s, args, G);
+    else hipLaunchKernelGGL((k_accumulate<ACC_RAP>), grid, dim3(nt), lds, s, args, G);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }

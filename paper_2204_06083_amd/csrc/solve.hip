@@ -254,7 +254,7 @@ struct BoxArgs {
     const int32_t* agg;   // padded
 };
 
-template <class V>
+template <class V, int DIM>
 __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
                                                       const V* __restrict__ res, V* __restrict__ rc,
                                                       PcgScalars* sc, int check, const double* __restrict__ part_rr,
@@ -273,12 +273,58 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
     const int bz = (int)(rr / b.nby);
     const int32_t c0 = b.cstart[box];
     const int m = b.ncomp[box];
+    if (DIM == 2) {
+        // The box's 3 x 3 nodes and their neighbours (a 5 x 5 window without
+        // its corners) are loaded first; window points off the node grid read
+        // as 0 (they neighbour no unknown: the outer node layer is outside).
+        // Each node's contribution goes to its component; the components'
+        // sums are then formed in node order.
+        V rw[5][5], dw[5][5];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                rw[a][c] = V(0);
+                dw[a][c] = V(0);
+                if ((a == 0 || a == 4) && (c == 0 || c == 4)) continue;
+                const int i = 3 * bx - 1 + c, j = 3 * by - 1 + a;
+                if (i < 0 || i >= b.nx || j < 0 || j >= b.ny) continue;
+                const int64_t p = (int64_t)i + f.sy * j;
+                dw[a][c] = dg[p];
+                rw[a][c] = res[p];
+            }
+        V u[9];
+        int comp[9];
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int a = oy + 1, c = ox + 1, n = 3 * oy + ox;
+                const V d = dw[a][c];
+                u[n] = V(0);
+                comp[n] = -1;
+                if (d == V(0)) continue;
+                const V rp = rw[a][c];
+                V nb = safe_div(rw[a][c - 1], dw[a][c - 1]) + safe_div(rw[a][c + 1], dw[a][c + 1]);
+                nb += safe_div(rw[a - 1][c], dw[a - 1][c]) + safe_div(rw[a + 1][c], dw[a + 1][c]);
+                const V aw = d * (rp / d) - sh * nb;
+                u[n] = rp - omega * aw;
+                comp[n] = m == 1 ? 0 : b.agg[(int64_t)(3 * bx + ox) + f.sy * (3 * by + oy)] - c0;
+            }
+        for (int c = 0; c < m && c < MAX_FINE_COMP; ++c) {
+            V acc = V(0);
+#pragma unroll
+            for (int n = 0; n < 9; ++n)
+                if (comp[n] == c) acc += u[n];
+            rc[c0 + c] = acc;
+        }
+        return;
+    }
     V acc[MAX_FINE_COMP];
 #pragma unroll
     for (int c = 0; c < MAX_FINE_COMP; ++c) acc[c] = V(0);
-    const int z_hi = f.dim == 3 ? 3 : 1;
-    for (int oz = 0; oz < z_hi; ++oz) {
-        const int k = f.dim == 3 ? 3 * bz + oz : 0;
+    for (int oz = 0; oz < 3; ++oz) {
+        const int k = 3 * bz + oz;
         if (k >= b.nz) break;
         for (int oy = 0; oy < 3; ++oy) {
             const int j = 3 * by + oy;
@@ -291,12 +337,12 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
                 if (d == V(0)) continue;
                 const V rp = res[p];
                 const V aw = d * (rp / d) - sh * nbr_sum_scaled(res, dg, p, f);
-                const V u = rp - omega * aw;
+                const V uu = rp - omega * aw;
                 if (m == 1) {
-                    acc[0] += u;
+                    acc[0] += uu;
                 } else {
                     const int c = b.agg[p] - c0;
-                    if (c >= 0 && c < MAX_FINE_COMP) acc[c] += u;
+                    if (c >= 0 && c < MAX_FINE_COMP) acc[c] += uu;
                 }
             }
         }
@@ -795,6 +841,20 @@ static BoxArgs box_args(const amg_handle* H) {
     return b;
 }
 
+// FP64 fine restriction without convergence check (learned-smoother paths).
+static int launch_fine_restrict64(amg_handle* H, const FineArgs& f, double w0, const double* res, double* rc, int np,
+                                  hipStream_t s) {
+    const dim3 g(xcd_grid(H->nboxes0, RNT));
+    if (H->d.dim == 2)
+        hipLaunchKernelGGL((k_fine_restrict<double, 2>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc, H->sc, 0,
+                           H->red.rr, np);
+    else
+        hipLaunchKernelGGL((k_fine_restrict<double, 3>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc, H->sc, 0,
+                           H->red.rr, np);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
 // Arrays of one level, and the fine V-cycle vectors, in the V-cycle precision.
 template <class V>
 struct LevelView {
@@ -845,8 +905,19 @@ static int lanes_for(double avg_row) {
 
 // Coarse levels with more unknowns than this take two light passes each way;
 // smaller ones (launch bound) take one fused pass that recomputes the residual
-// or the prolongated correction at the neighbours.
+// or the prolongated correction at the neighbours.  Going down, the fused
+// pass costs about (entries per R row) x (entries per A row) products per
+// coarse row in sequence; above FUSE_DOWN_WORK (3-D levels: a few thousand)
+// the two passes are faster.
 constexpr int64_t FUSE_BELOW = 20000;
+constexpr double FUSE_DOWN_WORK = 600.0;
+
+static bool fuse_down(const Level& L, const Level& C) {
+    if (L.n >= FUSE_BELOW) return false;
+    const double ra = (double)L.nnz_a / (double)(L.n > 0 ? L.n : 1);
+    const double rr = (double)L.nnz_r / (double)(C.n > 0 ? C.n : 1);
+    return ra * rr <= FUSE_DOWN_WORK;
+}
 
 // Coarse part of the V-cycle, levels 1 .. nlev-1: rv_1 -> ev_1.
 template <class V>
@@ -858,7 +929,7 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
         const V w = (V)L.omega;
         const int lpr_r = lanes_for((double)L.nnz_r / (double)(C.n > 0 ? C.n : 1));
-        if (L.n >= FUSE_BELOW) {
+        if (!fuse_down(L, C)) {
             const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
             EB_LPR_LAUNCH(k_csr_resid, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, sc);
             EB_LPR_LAUNCH(k_csr_matvec, V, lpr_r, C.n, C.n, Lv.R, Lv.tmp, Cv.rv, sc);
@@ -921,8 +992,12 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
     const double w0 = H->lev[0].omega;
     EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_fine_down<V, LW>), G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr,
                     np);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
-                    box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
+    if (H->d.dim == 2)
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
+    else
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
@@ -957,8 +1032,12 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
     const LevelView<V> L1 = view<V>(H->lev[1]);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
                     w0, rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, k_fine_restrict<V>, dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, f,
-                    box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
+    if (H->d.dim == 2)
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
+    else
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
@@ -1322,8 +1401,7 @@ static int lg_cycle_to_z2(amg_handle* H, const double* r, hipStream_t s) {
     else
         hipLaunchKernelGGL((k_fine_down<double, false>), dim3(np), dim3(NT), 0, s, f, w0, r, H->res, H->sc, 0,
                            H->red.rr, np);
-    hipLaunchKernelGGL((k_fine_restrict<double>), dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, s, f, box_args(H),
-                       w0, (const double*)H->res, H->lev[1].rv, H->sc, 0, H->red.rr, np);
+    EB_TRY(launch_fine_restrict64(H, f, w0, (const double*)H->res, H->lev[1].rv, np, s));
     EB_TRY(enqueue_coarse<double>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
@@ -1481,8 +1559,7 @@ extern "C" int amg_smoother_loss_grad(amg_handle_t* H, int32_t m, const double* 
                            g, wg);
         hipLaunchKernelGGL(k_lg_u, dim3(np), dim3(NT), 0, s, f, (const double*)g, (const double*)wg, u);
         // R u -> coarse cycle -> P e_c
-        hipLaunchKernelGGL((k_fine_restrict<double>), dim3(xcd_grid(H->nboxes0, RNT)), dim3(RNT), 0, s, f,
-                           box_args(H), w0, (const double*)u, H->lev[1].rv, H->sc, 0, H->red.rr, np);
+        EB_TRY(launch_fine_restrict64(H, f, w0, (const double*)u, H->lev[1].rv, np, s));
         EB_TRY(enqueue_coarse<double>(H, s));
         hipLaunchKernelGGL(k_lg_prolong, dim3(np), dim3(NT), 0, s, f, w0, H->agg_p, (const double*)H->lev[1].ev, wg);
         hipLaunchKernelGGL(k_lg_acc, dim3(np), dim3(NT), 0, s, f, (const double*)g, (const double*)t2,

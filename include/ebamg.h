@@ -203,6 +203,13 @@ int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double si
 int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* p,
               pcg_result_t* res, void* stream);
 
+/* PCG iterations from the third on are launched as a captured HIP graph of
+ * two iterations (kernel nodes only), kept on the handle per V-cycle
+ * precision, unless disabled here (process-wide; 1 = on, the default).  The
+ * results are the same either way: the same kernels run with the same
+ * arguments in the same order.                                                */
+int eb_set_iteration_graphs(int32_t enabled);
+
 /* The same PCG for nrhs right-hand sides (1 <= nrhs <= 64) sharing the
  * hierarchy, run as one launch sequence (Algorithm 2 step 4 for several b, as
  * in the heat steps of Sec. 4).  b and x hold nrhs node fields back to back

@@ -23,7 +23,7 @@ EXPORTS = [
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
     "amg_smoother_samples", "amg_smoother_loss_grad", "eb_wave_rhs", "eb_stencil_combine",
-    "pcg_solve_islands", "pcg_batched_set_launch_shape", "pcg_batched_launch_shape",
+    "pcg_solve_islands", "pcg_batched_set_launch_shape", "pcg_batched_launch_shape", "eb_set_iteration_graphs",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -97,6 +97,7 @@ def lib():
     L.pcg_solve_islands.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), vp, vp, C.POINTER(PcgParams),
                                     C.POINTER(PcgResult), vp]
     L.pcg_batched_set_launch_shape.argtypes = [C.c_int32, C.c_int32]
+    L.eb_set_iteration_graphs.argtypes = [C.c_int32]
     i32p = C.POINTER(C.c_int32)
     L.pcg_batched_launch_shape.argtypes = [vp, i32p, i32p, i32p, i32p, i32p, C.POINTER(C.c_float)]
     L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]

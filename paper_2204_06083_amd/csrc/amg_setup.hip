@@ -1304,6 +1304,7 @@ int free_handle_memory(amg_handle* H) {
     // for any solve still running on another stream first
     if (H->last_stream && H->last_stream != s) (void)hipStreamSynchronize(H->last_stream);
     free_batch(H, s);
+    drop_iteration_graphs(H);
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
     void* ptrs[] = {H->unk_off_tmp, H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,

@@ -111,6 +111,11 @@ struct amg_handle {
     eb::PcgScalars sc_mirror;
     eb::Reduction red;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // captured pair of steady-state PCG iterations (k odd, then k + 1) per
+    // V-cycle precision, with the fine-weight switch it was captured under
+    hipGraphExec_t it_graph[2] = {nullptr, nullptr};
+    int it_graph_wf[2] = {-1, -1};
+    hipStream_t cap_stream = nullptr;   // private stream the graphs are captured on
     // kernel timing hook (eb_timing_select / eb_timing_read)
     int tim_kernel = -1;
     int tim_cap = 0;
@@ -125,5 +130,7 @@ struct amg_handle {
 
 namespace eb {
 int ensure_fp32(amg_handle* H, hipStream_t s);   // FP32 hierarchy copies (solve.hip)
-void free_batch(amg_handle* H, hipStream_t s);   // batched.hip
+void free_batch(amg_handle* H, hipStream_t s);
+// Destroys the captured iteration graphs of a handle (solve.hip).
+void drop_iteration_graphs(amg_handle* H);   // batched.hip
 }  // namespace eb

@@ -23,6 +23,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <atomic>
+
 #include "handle.hpp"
 
 namespace eb {
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __res
 __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ x, double* __restrict__ r,
                                                const double* __restrict__ pv, const double* __restrict__ q,
                                                const double* __restrict__ rz_cur, const double* __restrict__ part_pq,
-                                               int np, double* __restrict__ part_rr, PcgScalars* sc, int iter) {
+                                               int np, double* __restrict__ part_rr, PcgScalars* sc) {
     if (sc->done) return;
     const double rho = block_total(rz_cur, np);
     const double pq = block_total(part_pq, np);
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ 
     }
     const double alpha = rho / pq;
     if (lead()) {
-        sc->iters = iter;
+        sc->iters = sc->iters + 1;   // counted on the device: a captured iteration carries no number
         sc->pq = pq;
     }
     double part = 0.0;
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
                                                     const double* __restrict__ q, V* __restrict__ res,
                                                     double omega, const double* __restrict__ rz_cur,
                                                     const double* __restrict__ part_pq, int np,
-                                                    double* __restrict__ part_rr, PcgScalars* sc, int iter) {
+                                                    double* __restrict__ part_rr, PcgScalars* sc) {
     if (sc->done) return;
     const double rho = block_total(rz_cur, np);
     const double pq = block_total(part_pq, np);
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
     }
     const double alpha = rho / pq;
     if (lead()) {
-        sc->iters = iter;
+        sc->iters = sc->iters + 1;   // counted on the device: a captured iteration carries no number
         sc->pq = pq;
     }
     double part = 0.0;
@@ -1013,7 +1015,7 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
 // rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
 // r[k % 2] and its V-cycle writes rz[k % 2].
 template <class V, bool LW>
-static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t s) {
+static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
@@ -1031,7 +1033,7 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
     const double w0 = H->lev[0].omega;
     const LevelView<V> L1 = view<V>(H->lev[1]);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
-                    w0, rz_cur, H->red.pq, np, H->red.rr, sc, iter_global);
+                    w0, rz_cur, H->red.pq, np, H->red.rr, sc);
     if (H->d.dim == 2)
         EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
@@ -1050,7 +1052,7 @@ static int enqueue_iteration(amg_handle* H, int k, int iter_global, hipStream_t 
 }
 
 // The same for a one-level hierarchy (FP64 dense solve of the fine level).
-static int enqueue_iteration_one_level(amg_handle* H, int k, int iter_global, hipStream_t s) {
+static int enqueue_iteration_one_level(amg_handle* H, int k, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
@@ -1065,7 +1067,7 @@ static int enqueue_iteration_one_level(amg_handle* H, int k, int iter_global, hi
     EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<double>, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur,
                     rz_prev, np, H->red.pq, sc);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr, G, dim3(NT), 0, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
-                    H->red.rr, sc, iter_global);
+                    H->red.rr, sc);
     // k_pcg_xr updates r in place: keep both buffers equal
     hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, rin, rout);
     EB_LAUNCH_CHECK();
@@ -1079,9 +1081,62 @@ static int enqueue_vcycle_any(amg_handle* H, const double* r, V* z, double* rz_o
 }
 
 template <class V>
-static int enqueue_iteration_any(amg_handle* H, int k, int iter_global, hipStream_t s) {
-    return H->wf_on ? enqueue_iteration<V, true>(H, k, iter_global, s)
-                    : enqueue_iteration<V, false>(H, k, iter_global, s);
+static int enqueue_iteration_any(amg_handle* H, int k, hipStream_t s) {
+    return H->wf_on ? enqueue_iteration<V, true>(H, k, s) : enqueue_iteration<V, false>(H, k, s);
+}
+
+// Steady-state iterations as a HIP graph.  From iteration 3 on, iterations
+// k and k + 2 launch the same kernels with the same arguments (buffers
+// alternate with the parity of k, the iteration count lives on the device),
+// so one captured pair (k odd, k + 1) is replayed for every later pair; the
+// host then submits one graph per two iterations instead of about twenty
+// kernels.  The graph holds kernel nodes only (no memset or copy nodes) and
+// is kept on the handle, per V-cycle precision and fine-weight switch.
+static std::atomic<int> g_use_graphs{1};
+
+void drop_iteration_graphs(amg_handle* H) {
+    for (int i = 0; i < 2; ++i) {
+        if (H->it_graph[i]) (void)hipGraphExecDestroy(H->it_graph[i]);
+        H->it_graph[i] = nullptr;
+        H->it_graph_wf[i] = -1;
+    }
+    if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
+    H->cap_stream = nullptr;
+}
+
+template <class V>
+static int launch_iteration_pair(amg_handle* H, hipStream_t s) {
+    const int slot = sizeof(V) == sizeof(float) ? 1 : 0;
+    if (!H->it_graph[slot] || H->it_graph_wf[slot] != H->wf_on) {
+        if (H->it_graph[slot]) (void)hipGraphExecDestroy(H->it_graph[slot]);
+        H->it_graph[slot] = nullptr;
+        // captured on a private stream (the solve stream may be the null
+        // stream, which cannot capture); nothing runs during capture
+        if (!H->cap_stream) EB_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = H->cap_stream;
+        hipGraph_t g = nullptr;
+        EB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int rc1 = enqueue_iteration_any<V>(H, 3, cs);
+        const int rc2 = rc1 == EB_OK ? enqueue_iteration_any<V>(H, 4, cs) : rc1;
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (rc2 != EB_OK || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            if (rc2 != EB_OK) return rc2;
+            set_error("iteration graph capture failed: %s", hipGetErrorString(ec));
+            return EB_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            set_error("iteration graph instantiation failed: %s", hipGetErrorString(ei));
+            return EB_EHIP;
+        }
+        H->it_graph[slot] = ex;
+        H->it_graph_wf[slot] = H->wf_on;
+    }
+    EB_HIP(hipGraphLaunch(H->it_graph[slot], s));
+    return EB_OK;
 }
 
 // FP32 copies of the hierarchy for the single-precision V-cycle, made once
@@ -1655,11 +1710,23 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             }
             const int left = p.maxit - H->sc_host->iters;
             const int chunk = left < p.check_every ? left : p.check_every;
-            for (int c = 0; c < chunk; ++c, ++enqueued) {
+            // graphs: not with a one-level hierarchy or while a kernel is being timed
+            const bool graphs = g_use_graphs.load() && H->nlev > 1 && H->tim_kernel < 0;
+            for (int c = 0; c < chunk;) {
+                if (graphs && k + 1 >= 3 && ((k + 1) & 1) && chunk - c >= 2) {
+                    if (fp32) EB_TRY(launch_iteration_pair<float>(H, s));
+                    else EB_TRY(launch_iteration_pair<double>(H, s));
+                    k += 2;
+                    c += 2;
+                    enqueued += 2;
+                    continue;
+                }
                 ++k;
-                if (H->nlev == 1) EB_TRY(enqueue_iteration_one_level(H, k, iter_base + k, s));
-                else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, iter_base + k, s));
-                else EB_TRY(enqueue_iteration_any<double>(H, k, iter_base + k, s));
+                ++c;
+                ++enqueued;
+                if (H->nlev == 1) EB_TRY(enqueue_iteration_one_level(H, k, s));
+                else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, s));
+                else EB_TRY(enqueue_iteration_any<double>(H, k, s));
             }
         }
         // true residual ||b - A x||
@@ -1792,5 +1859,11 @@ extern "C" int eb_timing_read(amg_handle_t* H, int64_t* launches, double* total_
     *total_ms = H->tim_ms;
     H->tim_launches = 0;
     H->tim_ms = 0.0;
+    return EB_OK;
+}
+
+extern "C" int eb_set_iteration_graphs(int32_t enabled) {
+    clear_error();
+    g_use_graphs.store(enabled ? 1 : 0);
     return EB_OK;
 }

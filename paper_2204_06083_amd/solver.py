@@ -420,6 +420,12 @@ def solve_islands(H: "Hierarchy", b: torch.Tensor, rows, x0: Optional[torch.Tens
     return x, [[_result_dict(res[s * nrhs + j]) for j in range(nrhs)] for s in range(nseg)]
 
 
+def set_iteration_graphs(enabled: bool = True):
+    """Launch steady-state PCG iterations as captured HIP graphs (default) or
+    kernel by kernel (process-wide switch; results are identical)."""
+    L.check(L.lib().eb_set_iteration_graphs(1 if enabled else 0), "eb_set_iteration_graphs")
+
+
 def set_batched_launch_shape(plane_width: int = 0, planes_per_block: int = 0):
     """Fix the batched fine kernels' launch shape for batch buffers made from
     now on (0, 0: the autotuner chooses)."""

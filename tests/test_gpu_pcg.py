@@ -135,3 +135,36 @@ def test_empty_system():
     x, info = H.solve(torch.zeros(g.shape, dtype=torch.float64, device=DEV))
     assert info["iterations"] == 0 and not torch.any(x).item()
     H.free()
+
+
+@pytest.mark.parametrize("name,prec", [("star512", "fp64"), ("star512", "fp32"), ("ell48", "fp64"),
+                                       ("disk128", "fp64")])
+def test_iteration_graphs_match_kernel_launches(name, prec):
+    """Captured iteration pairs run the same kernels with the same arguments:
+    bitwise the same solution and iteration count as launching kernel by
+    kernel, on the first graph launch and on later solves that replay it, on
+    the default stream and on a stream of the caller's."""
+    mk = {"star512": lambda: W.star_poisson(512), "ell48": lambda: W.ellipsoid_poisson(48),
+          "disk128": lambda: W.disk_poisson(128)}[name]
+    prob = mk()
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    try:
+        S.set_iteration_graphs(False)
+        x0, i0 = H.solve(b_g, tol=1e-10, precision=prec)
+        S.set_iteration_graphs(True)
+        x1, i1 = H.solve(b_g, tol=1e-10, precision=prec)
+        x2, i2 = H.solve(b_g, tol=1e-10, precision=prec)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            x3, i3 = H.solve(b_g, tol=1e-10, precision=prec)
+        st.synchronize()
+        print(f"[gpu] graphs {name} {prec}: iterations {i0['iterations']} {i1['iterations']} "
+              f"solve ms {i0['solve_ms']:.2f} -> {i2['solve_ms']:.2f}", flush=True)
+        assert i0["iterations"] >= 4
+        for x, i in ((x1, i1), (x2, i2), (x3, i3)):
+            assert torch.equal(x, x0) and i["iterations"] == i0["iterations"] and i["status"] == 0
+    finally:
+        S.set_iteration_graphs(True)
+        H.free()

@@ -464,7 +464,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(the solve is single-GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              f"(the library solves on one GPU; several-GPU runs are not part of this benchmark)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calib:

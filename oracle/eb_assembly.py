@@ -17,7 +17,7 @@ What is computed, and where the paper defines it:
   diagonal and the right-hand side change             Sec. 2.1.1, interpolant and u_BP
 * crossing location by linear interpolation of psi      Sec. 3.3, distance approximation
 
-Readings taken where the paper leaves a choice (stated in the design doc too):
+Readings taken where the paper leaves a choice:
 
 * inside is psi < 0 strictly; psi == 0 is outside.
 * the outer node layer must be outside (DomainError otherwise).

@@ -18,7 +18,7 @@ Dirichlet data entering through the right-hand side), written out plainly:
       (A + (2/dt) I) u^{n+1} = ((2/dt) I - A) u^n + b^n + b^{n+1},
   b^n = eb_assembly.rhs(f(t_n), u_D(t_n)) the source plus boundary terms at
   t_n.  Reading: written for beta = 1 (the paper's example has a variable
-  beta, which this build does not treat).
+  beta, which is not treated here).
 
 Pins (tests/test_oracle_steppers.py): closed forms on an eigenvector of A
 (the theta-scheme's mode recurrence a^n = cos(n phi), the Crank-Nicolson

@@ -82,7 +82,7 @@ def test_theta_scheme_conserves_its_discrete_energy(theta):
 def test_leapfrog_errors_against_table1():
     """Leap-frog (theta = 0, dt/h = 0.7, 10.2 periods of the m = n = 7 mode):
     max-errors within a factor 4 of Table 1 and convergence of order about 2.
-    (The paper's mixed EB method uses RBF rows where this build follows the
+    (The paper's mixed EB method uses RBF rows where the line-by-line walk here follows the
     grid line further; its errors are about 3x smaller here.)"""
     gold = json.load(open(os.path.join(GOLDEN, "wave_table1.json")))
     ref = gold["theta_0"]["max_error"]

@@ -937,6 +937,146 @@ __global__ void __launch_bounds__(BLOCK) k_gram(const double* __restrict__ Li, i
     W[id] = s;
 }
 
+// Small coarsest levels (n <= SW_NMAX): the inverse in one workgroup by the
+// symmetric sweep operator.  Sweeping pivot k of a symmetric M maps
+//   M_kk -> -1/d,  M_ik -> M_ik/d,  M_kj -> M_kj/d,  M_ij -> M_ij - M_ik M_kj/d
+// (d = M_kk, i, j != k); sweeping every pivot of an SPD matrix (no pivoting
+// needed: each d is a Schur-complement pivot, positive) leaves -A^-1.  The
+// n^3/2 multiply-adds are the least an explicit inverse costs, and the n
+// sequential pivots need one barrier each instead of one launch chain per
+// panel.  The lower triangle lives in registers as T x T tiles, one per
+// thread (diagonal tiles keep the whole block; only their lower half is ever
+// read); pivot column k goes through LDS, double-buffered, written by the
+// tiles that hold row k and column k of the lower triangle.
+// 6 x 6 tiles on 1024 threads: 43 * 44 / 2 = 946 tiles, n <= 258.  Per pivot
+// the step is bound by the LDS reads of the pivot column (2T values per T^2
+// updates) and the barrier; 8 x 8 tiles on 512 threads read less but hide
+// less latency and measure slower.
+constexpr int SW_T = 6;
+constexpr int SW_THREADS = 1024;
+constexpr int SW_NMAX = 43 * SW_T;                // 258
+constexpr int SW_NPAD = 264;                      // pivot buffer length (16-byte multiple)
+
+template <int T>
+__device__ __forceinline__ void sweep_publish(double (&m)[T][T], double* __restrict__ buf, double* __restrict__ rpiv,
+                                              int TI, int TJ, int kb, int kk, bool& fail) {
+    // column kb*T + kk of the symmetric matrix, read from lower-triangle
+    // positions: rows >= k from tile column kb, rows < k from tile row kb.
+    // The tile holding the pivot also publishes its reciprocal.  kk is a
+    // compile-time constant at every call, so register indices stay static.
+    const bool diag = TI == TJ;
+    if (TJ == kb) {
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+            if (!diag || a >= kk) buf[TI * T + a] = m[a][kk];
+    }
+    if (TI == kb) {
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+            if (!diag || b < kk) buf[TJ * T + b] = m[kk][b];
+        if (diag) {
+            const double d = m[kk][kk];
+            if (!(d > 0.0)) fail = true;
+            *rpiv = d > 0.0 ? -1.0 / d : -1.0;     // minus the reciprocal
+        }
+    }
+}
+
+template <int T, int NT>
+__global__ void __launch_bounds__(NT) k_dense_sweep(const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val, int n,
+                                                    double* __restrict__ W, int32_t* __restrict__ err) {
+    __shared__ __align__(16) double cb[2][SW_NPAD];
+    __shared__ double rp[2];
+    const int nb = (n + T - 1) / T;
+    const int ntiles = nb * (nb + 1) / 2;
+    const int tid = threadIdx.x;
+    const bool active = tid < ntiles;
+    int TI = -1, TJ = -1;      // inactive threads own nothing and publish nothing
+    if (active) {
+        TI = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+        while ((TI + 1) * (TI + 2) / 2 <= tid) ++TI;
+        while (TI * (TI + 1) / 2 > tid) --TI;
+        TJ = tid - TI * (TI + 1) / 2;
+    }
+    const int i0 = active ? TI * T : 0, j0 = active ? TJ * T : 0;
+    double m[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) m[a][b] = 0.0;
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+            const int i = i0 + a;
+            if (i < n) {
+                for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                    const int c = col[e] - j0;
+                    const double v = val[e];
+#pragma unroll
+                    for (int b = 0; b < T; ++b)
+                        if (c == b) m[a][b] = v;
+                }
+            }
+        }
+    }
+    bool fail = false;
+    sweep_publish<T>(m, cb[0], &rp[0], TI, TJ, 0, 0, fail);
+    __syncthreads();
+    int p = 0;
+    for (int kb = 0; kb < nb; ++kb) {
+#pragma unroll
+        for (int kk = 0; kk < T; ++kk) {
+            const int k = kb * T + kk;
+            if (k < n) {     // uniform across the workgroup
+                const double nr = rp[p];           // -1/d
+                double ci[T], cj[T], si[T];
+#pragma unroll
+                for (int a = 0; a < T; ++a) {
+                    ci[a] = cb[p][i0 + a];
+                    cj[a] = cb[p][j0 + a];
+                }
+                // M_ij - M_ik M_kj / d everywhere, then row and column k
+#pragma unroll
+                for (int a = 0; a < T; ++a) {
+                    si[a] = ci[a] * nr;
+#pragma unroll
+                    for (int b = 0; b < T; ++b) m[a][b] = fma(si[a], cj[b], m[a][b]);
+                }
+                if (TJ == kb) {
+#pragma unroll
+                    for (int a = 0; a < T; ++a) m[a][kk] = -si[a];
+                }
+                if (TI == kb) {
+#pragma unroll
+                    for (int b = 0; b < T; ++b) m[kk][b] = -(cj[b] * nr);
+                    if (TJ == kb) m[kk][kk] = nr;
+                }
+                if (k + 1 < n) {     // the next pivot, (kb, kk + 1) or (kb + 1, 0)
+                    const int kk_next = kk + 1 < T ? kk + 1 : 0;
+                    sweep_publish<T>(m, cb[p ^ 1], &rp[p ^ 1], TI, TJ, kk + 1 < T ? kb : kb + 1, kk_next, fail);
+                }
+                __syncthreads();
+                p ^= 1;
+            }
+        }
+    }
+    if (fail) atomicOr(err, DEVERR_NOTSPD);
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+                const int i = i0 + a, j = j0 + b;
+                if (i < n && j < n && (TI != TJ || a >= b)) {
+                    W[(int64_t)i * n + j] = -m[a][b];
+                    W[(int64_t)j * n + i] = -m[a][b];
+                }
+            }
+    }
+}
+
 __global__ void __launch_bounds__(BLOCK) k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
                                                    int64_t n, int32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -1081,11 +1221,18 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
                   (long long)n, H->params.dense_limit);
         return EB_ENOSPC;
     }
+    EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
+    if (n <= SW_NMAX) {
+        hipLaunchKernelGGL((k_dense_sweep<SW_T, SW_THREADS>), dim3(1), dim3(SW_THREADS), 0, s, L.a_rowptr, L.a_col,
+                           L.a_val, (int)n, L.dense_inv, err);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
+    // larger levels (coarsening stalled): blocked Cholesky, L^-1, L^-T L^-1
     double* dense = nullptr;
     double* linv = nullptr;
     EB_TRY(dalloc_n(&dense, n * n, s));
     EB_TRY(dalloc_n(&linv, n * n, s));
-    EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
     hipLaunchKernelGGL(k_csr_to_dense, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, n, dense);
     EB_LAUNCH_CHECK();
     for (int k0 = 0; k0 < n; k0 += CHOL_NB) {

@@ -30,6 +30,10 @@ CASES = {
     "ell33_ragged": (lambda: W.ellipsoid_poisson(33), 0.0, 16),
     "split": (_split_box_problem, 0.0, 8),
     "star2048": (lambda: W.star_poisson(2048), 0.0, 256),
+    # coarsest inverses: 253 unknowns (near the one-workgroup sweep limit of
+    # 258) and, with two levels, 318 (above it: blocked Cholesky path)
+    "star86": (lambda: W.star_poisson(86), 0.0, 256),
+    "star96_two_levels": (lambda: W.star_poisson(96), 0.0, 256, 2),
 }
 
 
@@ -47,14 +51,15 @@ def _vals_close(val, M, rtol=1e-13):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_hierarchy_parity(name):
-    mk, sigma, cmax = CASES[name]
+    mk, sigma, cmax, *rest = CASES[name]
+    max_levels = rest[0] if rest else 16
     prob = mk()
     print(f"[gpu] hierarchy {name} grid={prob.grid.shape} sigma={sigma}", flush=True)
     asm_o = E.assemble(prob.grid, prob.psi)
     A0 = E.operator_csr(asm_o, sigma)
-    Ho = OA.build_hierarchy(A0, E.unknown_coords(asm_o), coarse_max=cmax)
+    Ho = OA.build_hierarchy(A0, E.unknown_coords(asm_o), coarse_max=cmax, max_levels=max_levels)
     asm_g = S.assemble_diag(prob.grid, to_dev(prob.psi))
-    Hg = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, sigma, coarse_max=cmax)
+    Hg = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, sigma, coarse_max=cmax, max_levels=max_levels)
     assert Hg.n_levels == Ho.n_levels
     assert np.array_equal(Hg.fine_nodes(), asm_o.nodes)
     for l, lo in enumerate(Ho.levels):

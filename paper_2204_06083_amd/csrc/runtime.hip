@@ -172,23 +172,66 @@ int make_dims(const eb_grid_t* g, GridDims* d) {
 }
 
 // ------------------------------------------------------------------- scan
-// Three-phase exclusive scan: per-block scans (ITEMS elements per thread),
-// a recursive scan of the block totals, then a uniform add.  Integer only,
-// so the result is exact and order independent.
+// Exclusive scan of integers (exact, so any summation order gives the same
+// result).  Tiles of SCAN_TILE elements: a first pass writes each tile's sum;
+// the second pass scans each tile and adds the sum of all earlier tiles,
+// which every workgroup adds up itself while there are at most
+// SCAN_DIRECT_TILES tiles (two launches, no flags, no extra pass over the
+// output); above that the tile sums are scanned recursively first.  A single
+// tile is one launch.
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+constexpr int64_t SCAN_DIRECT_TILES = 4096;
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) lds[threadIdx.x] += lds[threadIdx.x + off];
+        __syncthreads();
+    }
+    const T r = lds[0];
+    __syncthreads();
+    return r;
+}
 
 template <class TI, class TO>
-__global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in, TO* __restrict__ out,
-                                                      TO* __restrict__ tile_sums, int64_t n) {
+__global__ void __launch_bounds__(BLOCK) k_scan_reduce(const TI* __restrict__ in, int64_t n, TO* __restrict__ sums) {
     __shared__ TO lds[BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    TO acc = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t idx = base + (int64_t)i * BLOCK + threadIdx.x;
+        if (idx < n) acc += (TO)in[idx];
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = acc;
+}
+
+// MODE 0: single tile (offset 0); 1: offset = sum of tile_val[0 .. tile);
+// 2: offset = tile_val[tile] (already an exclusive scan of the tile sums).
+template <class TI, class TO, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in, TO* __restrict__ out, int64_t n,
+                                                      const TO* __restrict__ tile_val, int64_t ntiles,
+                                                      TO* __restrict__ total) {
+    __shared__ TO lds[BLOCK];
+    TO offset = 0;
+    if (MODE == 1) {
+        TO acc = 0;
+        for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += BLOCK) acc += tile_val[t];
+        offset = block_sum(acc, lds);
+    } else if (MODE == 2) {
+        offset = tile_val[blockIdx.x];
+    }
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     TO v[SCAN_ITEMS];
     TO run = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t idx = base + i;
-        TO x = idx < n ? (TO)in[idx] : (TO)0;
+        const int64_t idx = base + i;
+        const TO x = idx < n ? (TO)in[idx] : (TO)0;
         v[i] = run;
         run += x;
     }
@@ -196,34 +239,18 @@ __global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in,
     __syncthreads();
     // Hillis-Steele inclusive scan of thread totals
     for (int off = 1; off < BLOCK; off <<= 1) {
-        TO t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : (TO)0;
+        const TO t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : (TO)0;
         __syncthreads();
         lds[threadIdx.x] += t;
         __syncthreads();
     }
-    TO prefix = threadIdx.x > 0 ? lds[threadIdx.x - 1] : (TO)0;
+    const TO prefix = offset + (threadIdx.x > 0 ? lds[threadIdx.x - 1] : (TO)0);
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t idx = base + i;
+        const int64_t idx = base + i;
         if (idx < n) out[idx] = v[i] + prefix;
     }
-    if (threadIdx.x == BLOCK - 1) tile_sums[blockIdx.x] = lds[BLOCK - 1];
-}
-
-template <class TO>
-__global__ void __launch_bounds__(BLOCK) k_scan_add(TO* __restrict__ out, const TO* __restrict__ tile_off, int64_t n) {
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    const TO add = tile_off[blockIdx.x];
-    for (int i = threadIdx.x; i < SCAN_TILE; i += BLOCK) {
-        int64_t idx = base + i;
-        if (idx < n) out[idx] += add;
-    }
-}
-
-template <class TO>
-__global__ void k_scan_total(const TO* out, const TO* tile_sums, int64_t ntiles, TO* total) {
-    // total = (exclusive offset of the last tile) + (sum of the last tile)
-    if (threadIdx.x == 0 && blockIdx.x == 0) *total = out[ntiles - 1] + tile_sums[ntiles - 1];
+    if (threadIdx.x == BLOCK - 1 && (int64_t)blockIdx.x == ntiles - 1) *total = offset + lds[BLOCK - 1];
 }
 
 template <class TI, class TO>
@@ -233,26 +260,33 @@ static int scan_impl(const TI* in, TO* out, int64_t n, TO* total_dev, hipStream_
         return EB_OK;
     }
     const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (ntiles == 1) {
+        hipLaunchKernelGGL((k_scan_tiles<TI, TO, 0>), dim3(1), dim3(BLOCK), 0, s, in, out, n, (const TO*)nullptr,
+                           ntiles, total_dev);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
     TO* sums = nullptr;
-    TO* sums_scan = nullptr;
     EB_TRY(dalloc_n(&sums, ntiles, s));
-    EB_TRY(dalloc_n(&sums_scan, ntiles, s));
-    // a single tile writes the grand total directly
-    hipLaunchKernelGGL((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out,
-                       ntiles == 1 ? total_dev : sums, n);
+    hipLaunchKernelGGL((k_scan_reduce<TI, TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, n, sums);
     EB_LAUNCH_CHECK();
-    if (ntiles > 1) {
+    if (ntiles <= SCAN_DIRECT_TILES) {
+        hipLaunchKernelGGL((k_scan_tiles<TI, TO, 1>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out, n,
+                           (const TO*)sums, ntiles, total_dev);
+        EB_LAUNCH_CHECK();
+    } else {
+        TO* sums_scan = nullptr;
         TO* dummy_total = nullptr;
+        EB_TRY(dalloc_n(&sums_scan, ntiles, s));
         EB_TRY(dalloc_n(&dummy_total, 1, s));
         EB_TRY((scan_impl<TO, TO>(sums, sums_scan, ntiles, dummy_total, s)));
-        hipLaunchKernelGGL((k_scan_add<TO>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, out, sums_scan, n);
-        EB_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_scan_total<TO>), dim3(1), dim3(1), 0, s, sums_scan, sums, ntiles, total_dev);
+        hipLaunchKernelGGL((k_scan_tiles<TI, TO, 2>), dim3((unsigned)ntiles), dim3(BLOCK), 0, s, in, out, n,
+                           (const TO*)sums_scan, ntiles, total_dev);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(dummy_total, s));
+        EB_TRY(dfree(sums_scan, s));
     }
     EB_TRY(dfree(sums, s));
-    EB_TRY(dfree(sums_scan, s));
     return EB_OK;
 }
 

@@ -630,8 +630,12 @@ __global__ void __launch_bounds__(BLOCK) k_tr_fill(const int32_t* __restrict__ r
 
 // Level-0 transpose by pulling: P_iI != 0 only for fine unknowns i within one
 // node of aggregate I's box, i.e. in the (3+2)^d nodes [3B-1, 3B+3]^d around
-// box B.  Visiting them in lexicographic order lists rows in ascending unknown
-// order, so R = P^T comes out sorted without atomics.
+// box B.  Listing them in lexicographic order lists rows in ascending unknown
+// order, so R = P^T comes out sorted without atomics.  TR_G lanes share a
+// row: lane q checks window nodes q, q + TR_G, ...; a ballot prefix over the
+// row's lanes keeps the lexicographic order when they write.
+constexpr int TR_G = 32;
+
 template <bool FILL>
 __global__ void __launch_bounds__(BLOCK) k_tr0_pull(int64_t nc, const int4* __restrict__ cinfo,
                                                     const int8_t* __restrict__ kind, GridDims d,
@@ -641,35 +645,61 @@ __global__ void __launch_bounds__(BLOCK) k_tr0_pull(int64_t nc, const int4* __re
                                                     const double* __restrict__ p_val, int32_t* __restrict__ cnt,
                                                     const int32_t* __restrict__ r_rowptr, int32_t* __restrict__ r_col,
                                                     double* __restrict__ r_val) {
-    const int64_t I = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (I >= nc) return;
-    const int4 ci = cinfo[I];
-    // unknowns never sit on the outer ring of nodes, so the walk stays inside it
-    const int zlo = d.dim == 3 ? max(3 * ci.z - 1, 1) : 0;
-    const int zhi = d.dim == 3 ? min(3 * ci.z + 3, d.nz - 2) : 0;
-    const int ylo = max(3 * ci.y - 1, 1), yhi = min(3 * ci.y + 3, d.ny - 2);
-    const int xlo = max(3 * ci.x - 1, 1), xhi = min(3 * ci.x + 3, d.nx - 2);
+    const int64_t I = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TR_G;
+    const int q = threadIdx.x % TR_G;
+    const int gshift = (threadIdx.x % WAVE) / TR_G * TR_G;    // first lane of the row in the wave
+    const bool rowok = I < nc;
+    int xlo = 0, ylo = 0, zlo = 0, wx = 1, wy = 1, nwin = 0;
+    int32_t pos = 0;
+    if (rowok) {
+        const int4 ci = cinfo[I];
+        // unknowns never sit on the outer ring of nodes, so the window stays inside it
+        zlo = d.dim == 3 ? max(3 * ci.z - 1, 1) : 0;
+        const int zhi = d.dim == 3 ? min(3 * ci.z + 3, d.nz - 2) : 0;
+        ylo = max(3 * ci.y - 1, 1);
+        const int yhi = min(3 * ci.y + 3, d.ny - 2);
+        xlo = max(3 * ci.x - 1, 1);
+        const int xhi = min(3 * ci.x + 3, d.nx - 2);
+        wx = xhi - xlo + 1;
+        wy = yhi - ylo + 1;
+        nwin = wx * wy * (zhi - zlo + 1);
+        if (wx <= 0 || wy <= 0 || zhi < zlo) nwin = 0;
+        if (FILL) pos = r_rowptr[I];
+    }
+    const int wmax = d.dim == 3 ? 125 : 25;        // the same trip count for every lane
     int c = 0;
-    int32_t pos = FILL ? r_rowptr[I] : 0;
-    for (int k = zlo; k <= zhi; ++k)
-        for (int j = ylo; j <= yhi; ++j)
-            for (int i = xlo; i <= xhi; ++i) {
-                const int64_t node = (int64_t)i + d.sy * j + d.sz * k;
-                if (kind[node] != 2) continue;
-                const int32_t u = unk_off[node];
+    for (int base = 0; base < wmax; base += TR_G) {
+        const int w = base + q;
+        bool hit = false;
+        int32_t u = 0;
+        double pv = 0.0;
+        if (w < nwin) {
+            const int i = xlo + w % wx;
+            const int j = ylo + (w / wx) % wy;
+            const int k = zlo + w / (wx * wy);
+            const int64_t node = (int64_t)i + d.sy * j + d.sz * k;
+            if (kind[node] == 2) {
+                u = unk_off[node];
                 for (int e = p_rowptr[u]; e < p_rowptr[u + 1]; ++e) {
                     if (p_col[e] == (int32_t)I) {
-                        if (FILL) {
-                            r_col[pos] = u;
-                            r_val[pos] = p_val[e];
-                            ++pos;
-                        }
-                        ++c;
+                        hit = true;
+                        pv = p_val[e];
                         break;
                     }
                 }
             }
-    if (!FILL) cnt[I] = c;
+        }
+        const unsigned long long mask = (__ballot(hit) >> gshift) & ((TR_G == 64) ? ~0ull : ((1ull << TR_G) - 1));
+        if (FILL && hit) {
+            const int before = __popcll(mask & ((1ull << q) - 1));
+            r_col[pos + before] = u;
+            r_val[pos + before] = pv;
+        }
+        const int m = __popcll(mask);
+        pos += m;
+        c += m;
+    }
+    if (!FILL && rowok && q == 0) cnt[I] = c;
 }
 
 // Sort each row by column: one wavefront per row, bitonic network in LDS for
@@ -1382,13 +1412,13 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     if (l == 0 && H->unk_off_tmp) {
         int32_t* tcnt = nullptr;
         EB_TRY(dalloc_n(&tcnt, nc, s));
-        hipLaunchKernelGGL((k_tr0_pull<false>), dim3(grid_for(nc)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
+        hipLaunchKernelGGL((k_tr0_pull<false>), dim3(grid_for(nc * TR_G)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
                            H->unk_off_tmp, L.p_rowptr, L.p_col, L.p_val, tcnt, nullptr, nullptr, nullptr);
         EB_LAUNCH_CHECK();
         EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, s));
         EB_TRY(dalloc_n(&L.r_col, n * p_bound, s));
         EB_TRY(dalloc_n(&L.r_val, n * p_bound, s));
-        hipLaunchKernelGGL((k_tr0_pull<true>), dim3(grid_for(nc)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
+        hipLaunchKernelGGL((k_tr0_pull<true>), dim3(grid_for(nc * TR_G)), dim3(BLOCK), 0, s, nc, C.cinfo, H->kind_tmp, H->d,
                            H->unk_off_tmp, L.p_rowptr, L.p_col, L.p_val, nullptr, L.r_rowptr, L.r_col, L.r_val);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(tcnt, s));

@@ -479,15 +479,19 @@ struct AccArgs {
     int centre_div;           // 3 for P/AP rows, 1 for RAP rows
     // first operand (rows): A_l for P/AP, R for RAP
     const int32_t* x_rowptr; const int32_t* x_col; const double* x_val;
-    // second operand: P (for AP) or AP (for RAP); for ACC_P the agg map
+    // second operand: P (for AP) or AP (for RAP); for ACC_P the agg map.
+    // y_start != nullptr: row k holds y_cnt[k] entries from y_start[k] on
+    // (the compacted scratch of a product) instead of CSR.
     const int32_t* y_rowptr; const int32_t* y_col; const double* y_val;
+    const int32_t* y_start; const int32_t* y_cnt;
     const int32_t* agg;       // ACC_P only
     const double* diag;       // ACC_P only
     const double* omega;      // ACC_P only (device scalar)
     int32_t* out_cnt;         // entries per row
-    int32_t* ell_col;         // row-major scratch, ell_stride entries per row
-    double* ell_val;
-    int ell_stride;
+    int32_t* out_start;       // first entry of the row in the scratch
+    int32_t* ell_col;         // scratch: workgroup b owns [b * rows * ell_stride, ...)
+    double* ell_val;          // and packs its rows there back to back
+    int ell_stride;           // bound on the entries of one row
     int32_t* err;
 };
 
@@ -546,7 +550,9 @@ __global__ void k_accumulate(AccArgs A, int G) {
             for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
                 const int k = A.x_col[e];
                 const double xv = A.x_val[e];
-                for (int f = A.y_rowptr[k]; f < A.y_rowptr[k + 1]; ++f) {
+                const int f0 = A.y_start ? A.y_start[k] : A.y_rowptr[k];
+                const int f1 = A.y_start ? f0 + A.y_cnt[k] : A.y_rowptr[k + 1];
+                for (int f = f0; f < f1; ++f) {
                     const int sl = A.sm.slot(A.y_col[f], bx, by, bz);
                     if (sl < 0) { bad = true; continue; }
                     fl[sl] = 1;
@@ -574,35 +580,54 @@ __global__ void k_accumulate(AccArgs A, int G) {
         }
         __syncthreads();
     }
-    if (!active || g != 0) return;
+    // pack the block's rows back to back: count, exclusive scan over the
+    // block's rows, then write each row's occupied slots in slot = column order
+    __shared__ int32_t offs[256];                 // rows per block <= 256
+    const int rb = nt / G;
     const double* v = vals + (size_t)t * ns;
     const uint8_t* fl = flags + (size_t)t * ns;
     int c = 0;
-    const int64_t base = row * A.ell_stride;
-    for (int sl = 0; sl < ns; ++sl) {
+    if (active && g == 0)
+        for (int sl = 0; sl < ns; ++sl) c += fl[sl] ? 1 : 0;
+    if (c > A.ell_stride) {
+        atomicOr(A.err, DEVERR_CAP);
+        c = A.ell_stride;
+    }
+    if (g == 0) offs[rl] = c;
+    __syncthreads();
+    for (int off = 1; off < rb; off <<= 1) {
+        const int32_t add = (t < rb && t >= off) ? offs[t - off] : 0;
+        __syncthreads();
+        if (t < rb) offs[t] += add;
+        __syncthreads();
+    }
+    if (!active || g != 0) return;
+    const int32_t start = (int32_t)((int64_t)blockIdx.x * rb * A.ell_stride) + (rl > 0 ? offs[rl - 1] : 0);
+    int w = 0;
+    for (int sl = 0; sl < ns && w < c; ++sl) {
         if (fl[sl]) {
-            if (c < A.ell_stride) {
-                A.ell_col[base + c] = A.sm.column(sl, bx, by, bz);
-                A.ell_val[base + c] = v[sl];
-            }
-            ++c;
+            A.ell_col[start + w] = A.sm.column(sl, bx, by, bz);
+            A.ell_val[start + w] = v[sl];
+            ++w;
         }
     }
-    if (c > A.ell_stride) atomicOr(A.err, DEVERR_CAP);
-    A.out_cnt[row] = c < A.ell_stride ? c : A.ell_stride;
+    A.out_cnt[row] = c;
+    A.out_start[row] = start;
 }
 
-// ELL scratch -> CSR (rows keep their order).
+// Packed product scratch -> CSR (rows keep their order).
 __global__ void __launch_bounds__(BLOCK) k_ell_to_csr(const int32_t* __restrict__ ell_col,
-                                                      const double* __restrict__ ell_val, int stride, int64_t nrows,
+                                                      const double* __restrict__ ell_val,
+                                                      const int32_t* __restrict__ start, int64_t nrows,
                                                       const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
                                                       double* __restrict__ val) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= nrows) return;
     const int32_t b = rowptr[i], e = rowptr[i + 1];
+    const int32_t s0 = start[i];
     for (int32_t k = 0; k < e - b; ++k) {
-        col[b + k] = ell_col[i * stride + k];
-        val[b + k] = ell_val[i * stride + k];
+        col[b + k] = ell_col[s0 + k];
+        val[b + k] = ell_val[s0 + k];
     }
 }
 
@@ -1207,38 +1232,58 @@ static int launch_accumulate(int mode, AccArgs& args, hipStream_t s) {
 }
 
 // Sparse product via the slot accumulator: one accumulation pass into a
-// bounded ELL scratch (row_bound entries per row), a prefix sum of the row
-// counts, and a compaction into CSR.  Arrays are sized by the proven bound, so
-// no host synchronisation is needed; the exact nnz stays in rowptr[nrows].
-static int accumulate_product(int mode, AccArgs args, int64_t nrows, int64_t row_bound, int32_t** rowptr,
-                              int32_t** col, double** val, hipStream_t s) {
+// bounded scratch (row_bound entries per row reserved, each workgroup's rows
+// packed at the front of its part), giving per-row counts and starts.  Sized
+// by the proven bound, so no host synchronisation is needed.
+struct PackedRows {
+    int32_t* cnt = nullptr;
+    int32_t* start = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+};
+
+static int free_packed(PackedRows& R, hipStream_t s) {
+    EB_TRY(dfree(R.cnt, s));
+    EB_TRY(dfree(R.start, s));
+    EB_TRY(dfree(R.col, s));
+    EB_TRY(dfree(R.val, s));
+    R = PackedRows();
+    return EB_OK;
+}
+
+static int accumulate_packed(int mode, AccArgs args, int64_t nrows, int64_t row_bound, PackedRows* out,
+                             hipStream_t s) {
     const int64_t cap = nrows * row_bound;
     if (cap >= ((int64_t)1 << 31)) {
         set_error("a sparse matrix bound exceeds 2^31 entries");
         return EB_ENOSPC;
     }
-    int32_t* cnt = nullptr;
-    int32_t* ell_col = nullptr;
-    double* ell_val = nullptr;
-    EB_TRY(dalloc_n(&cnt, nrows, s));
-    EB_TRY(dalloc_n(&ell_col, cap, s));
-    EB_TRY(dalloc_n(&ell_val, cap, s));
+    EB_TRY(dalloc_n(&out->cnt, nrows, s));
+    EB_TRY(dalloc_n(&out->start, nrows, s));
+    EB_TRY(dalloc_n(&out->col, cap, s));
+    EB_TRY(dalloc_n(&out->val, cap, s));
     args.nrows = nrows;
-    args.out_cnt = cnt;
-    args.ell_col = ell_col;
-    args.ell_val = ell_val;
+    args.out_cnt = out->cnt;
+    args.out_start = out->start;
+    args.ell_col = out->col;
+    args.ell_val = out->val;
     args.ell_stride = (int)row_bound;
-    EB_TRY(launch_accumulate(mode, args, s));
-    EB_TRY(rowptr_from_counts(cnt, nrows, rowptr, s));
-    EB_TRY(dalloc_n(col, cap, s));
-    EB_TRY(dalloc_n(val, cap, s));
-    hipLaunchKernelGGL(k_ell_to_csr, dim3(grid_for(nrows)), dim3(BLOCK), 0, s, ell_col, ell_val, (int)row_bound,
-                       nrows, *rowptr, *col, *val);
+    return launch_accumulate(mode, args, s);
+}
+
+// The same, then a prefix sum of the row counts and a copy into CSR (the
+// exact nnz stays in rowptr[nrows]).
+static int accumulate_product(int mode, AccArgs args, int64_t nrows, int64_t row_bound, int32_t** rowptr,
+                              int32_t** col, double** val, hipStream_t s) {
+    PackedRows R;
+    EB_TRY(accumulate_packed(mode, args, nrows, row_bound, &R, s));
+    EB_TRY(rowptr_from_counts(R.cnt, nrows, rowptr, s));
+    EB_TRY(dalloc_n(col, nrows * row_bound, s));
+    EB_TRY(dalloc_n(val, nrows * row_bound, s));
+    hipLaunchKernelGGL(k_ell_to_csr, dim3(grid_for(nrows)), dim3(BLOCK), 0, s, R.col, R.val, R.start, nrows,
+                       *rowptr, *col, *val);
     EB_LAUNCH_CHECK();
-    EB_TRY(dfree(cnt, s));
-    EB_TRY(dfree(ell_col, s));
-    EB_TRY(dfree(ell_val, s));
-    return EB_OK;
+    return free_packed(R, s);
 }
 
 static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
@@ -1443,23 +1488,23 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
         EB_TRY(dfree(tfill, s));
     }
 
-    // AP = A P, then A_c = R (A P); rows of both have at most `slots` entries
-    int32_t *ap_rowptr = nullptr, *ap_col = nullptr;
-    double* ap_val = nullptr;
+    // AP = A P (left in its packed scratch, read only by the next pass), then
+    // A_c = R (A P); rows of both have at most `slots` entries
+    PackedRows ap;
     args.x_rowptr = L.a_rowptr; args.x_col = L.a_col; args.x_val = L.a_val;
     args.y_rowptr = L.p_rowptr; args.y_col = L.p_col; args.y_val = L.p_val;
+    args.y_start = nullptr; args.y_cnt = nullptr;
     args.row_coords = L.coords;
     args.centre_div = 3;
-    EB_TRY(accumulate_product(ACC_AP, args, n, slots, &ap_rowptr, &ap_col, &ap_val, s));
+    EB_TRY(accumulate_packed(ACC_AP, args, n, slots, &ap, s));
     args.x_rowptr = L.r_rowptr; args.x_col = L.r_col; args.x_val = L.r_val;
-    args.y_rowptr = ap_rowptr; args.y_col = ap_col; args.y_val = ap_val;
+    args.y_rowptr = nullptr; args.y_col = ap.col; args.y_val = ap.val;
+    args.y_start = ap.start; args.y_cnt = ap.cnt;
     args.row_coords = C.coords;
     args.centre_div = 1;
     EB_TRY(accumulate_product(ACC_RAP, args, nc, slots, &C.a_rowptr, &C.a_col, &C.a_val, s));
     C.row_bound = slots;
-    EB_TRY(dfree(ap_rowptr, s));
-    EB_TRY(dfree(ap_col, s));
-    EB_TRY(dfree(ap_val, s));
+    EB_TRY(free_packed(ap, s));
     EB_TRY(dalloc_n(&C.diag, nc, s));
     hipLaunchKernelGGL(k_extract_diag, dim3(grid_for(nc)), dim3(BLOCK), 0, s, C.a_rowptr, C.a_col, C.a_val, nc,
                        C.diag, err);

@@ -1364,19 +1364,25 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     EB_TRY(dalloc_n(&lrank, n, s));
     EB_TRY(dalloc_n(&L.box_ncomp, nboxes, s));
     EB_TRY(dalloc_n(&L.box_cstart, nboxes, s));
-    EB_HIP(hipMemsetAsync(dstat + 2, 0, sizeof(int32_t), s));
-    if (l == 0 && H->unk_off_tmp && H->kind_tmp) {
+    const bool pull0 = l == 0 && H->unk_off_tmp && H->kind_tmp;
+    if (!pull0) {
+        EB_TRY(dalloc_n(&cnt, nboxes, s));
+        EB_TRY(dalloc_n(&fillpos, nboxes, s));
+    }
+    {
+        const FillSpec f[] = {{dstat + 2, sizeof(int32_t), 0u},
+                              {cnt, pull0 ? 0 : sizeof(int32_t) * nboxes, 0u},
+                              {fillpos, pull0 ? 0 : sizeof(int32_t) * nboxes, 0u}};
+        EB_TRY(fill_words(f, pull0 ? 1 : 3, s));
+    }
+    if (pull0) {
         hipLaunchKernelGGL(k_box_components0, dim3(grid_for(nboxes)), dim3(BLOCK), 0, s, H->kind_tmp, H->d, nb,
                            nboxes, H->unk_off_tmp, lrank, L.box_ncomp);
         EB_LAUNCH_CHECK();
     } else {
-        EB_TRY(dalloc_n(&cnt, nboxes, s));
         EB_TRY(dalloc_n(&boff, nboxes, s));
-        EB_TRY(dalloc_n(&fillpos, nboxes, s));
         EB_TRY(dalloc_n(&members, n, s));
         EB_TRY(dalloc_n(&boxid, n, s));
-        EB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nboxes, s));
-        EB_HIP(hipMemsetAsync(fillpos, 0, sizeof(int32_t) * nboxes, s));
         hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt, boxid);
         EB_LAUNCH_CHECK();
         EB_TRY(scan_i32_dev(cnt, boff, nboxes, dstat + 3, s));     // total (= n) unused
@@ -1472,8 +1478,10 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
         int32_t* tfill = nullptr;
         EB_TRY(dalloc_n(&tcnt, nc, s));
         EB_TRY(dalloc_n(&tfill, nc, s));
-        EB_HIP(hipMemsetAsync(tcnt, 0, sizeof(int32_t) * nc, s));
-        EB_HIP(hipMemsetAsync(tfill, 0, sizeof(int32_t) * nc, s));
+        {
+            const FillSpec f[] = {{tcnt, sizeof(int32_t) * nc, 0u}, {tfill, sizeof(int32_t) * nc, 0u}};
+            EB_TRY(fill_words(f, 2, s));
+        }
         hipLaunchKernelGGL(k_tr_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.p_rowptr, L.p_col, n, tcnt);
         EB_LAUNCH_CHECK();
         EB_TRY(rowptr_from_counts(tcnt, nc, &L.r_rowptr, s));
@@ -1550,9 +1558,11 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     int32_t* flag = nullptr;
     int32_t* unk_off = nullptr;
     EB_TRY(dalloc_n(&dstat, 4, s));
-    EB_HIP(hipMemsetAsync(dstat, 0, sizeof(SetupStat), s));
     EB_TRY(dalloc_n(&H->dscal, 2 * MAX_LEVELS, s));
-    EB_HIP(hipMemsetAsync(H->dscal, 0, sizeof(double) * 2 * MAX_LEVELS, s));
+    {
+        const FillSpec f[] = {{dstat, sizeof(SetupStat), 0u}, {H->dscal, sizeof(double) * 2 * MAX_LEVELS, 0u}};
+        EB_TRY(fill_words(f, 2, s));
+    }
     EB_TRY(dalloc_n(&flag, nn, s));
     EB_TRY(dalloc_n(&unk_off, nn, s));
     hipLaunchKernelGGL(k_fine_flags, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, flag, dstat);

@@ -112,6 +112,17 @@ int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total_h
 int scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* total_host, hipStream_t s);
 // Same scans, grand total written to device memory (no synchronisation).
 int scan_i32_dev(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s);
+
+// Set several device buffers to a repeated 32-bit word in one launch (bytes a
+// multiple of 4; at most FILL_MAX buffers).  Stands in for a run of
+// hipMemsetAsync calls, each of which is a launch of its own.
+constexpr int FILL_MAX = 12;
+struct FillSpec {
+    void* p;
+    size_t bytes;
+    uint32_t word;
+};
+int fill_words(const FillSpec* items, int count, hipStream_t s);
 int scan_i32_to_i64_dev(const int32_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s);
 
 // Small helpers used by several translation units.

@@ -171,6 +171,59 @@ int make_dims(const eb_grid_t* g, GridDims* d) {
     return EB_OK;
 }
 
+// ------------------------------------------------------------------- fill
+struct FillList {
+    uint32_t* p[FILL_MAX];
+    int64_t words[FILL_MAX];
+    uint32_t word[FILL_MAX];
+};
+
+// blockIdx.y = buffer; 16-byte stores where the buffer is 16-byte aligned.
+__global__ void __launch_bounds__(BLOCK) k_fill_many(FillList L) {
+    const int b = blockIdx.y;
+    uint32_t* p = L.p[b];
+    const int64_t nw = L.words[b];
+    const uint32_t w = L.word[b];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int64_t head = 0;
+    if (((uintptr_t)p & 15) == 0) {
+        const int64_t n4 = nw / 4;
+        uint4* q = reinterpret_cast<uint4*>(p);
+        const uint4 v = make_uint4(w, w, w, w);
+        for (int64_t i = t0; i < n4; i += stride) q[i] = v;
+        head = n4 * 4;
+    }
+    for (int64_t i = head + t0; i < nw; i += stride) p[i] = w;
+}
+
+int fill_words(const FillSpec* items, int count, hipStream_t s) {
+    if (count <= 0) return EB_OK;
+    if (count > FILL_MAX) {
+        set_error("fill_words: %d buffers (limit %d)", count, FILL_MAX);
+        return EB_EINVAL;
+    }
+    FillList L;
+    memset(&L, 0, sizeof(L));
+    int64_t most = 0;
+    for (int i = 0; i < count; ++i) {
+        if (items[i].bytes % 4 != 0 || (items[i].bytes > 0 && !items[i].p)) {
+            set_error("fill_words: bad buffer %d", i);
+            return EB_EINVAL;
+        }
+        L.p[i] = static_cast<uint32_t*>(items[i].p);
+        L.words[i] = (int64_t)(items[i].bytes / 4);
+        L.word[i] = items[i].word;
+        if (L.words[i] > most) most = L.words[i];
+    }
+    int64_t gx = (most / 4 + BLOCK - 1) / BLOCK;
+    if (gx < 1) gx = 1;
+    if (gx > 2048) gx = 2048;
+    hipLaunchKernelGGL(k_fill_many, dim3((unsigned)gx, (unsigned)count), dim3(BLOCK), 0, s, L);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
 // ------------------------------------------------------------------- scan
 // Exclusive scan of integers (exact, so any summation order gives the same
 // result).  Tiles of SCAN_TILE elements: a first pass writes each tile's sum;

@@ -1159,10 +1159,11 @@ int ensure_fp32(amg_handle* H, hipStream_t s) {
     if (H->fp32_ready) return EB_OK;
     EB_TRY(copy_to_f32(H->diag_p, H->npad, &H->diag_p32, s));
     EB_TRY(dalloc_n(&H->res32, H->npad, s));
-    float** zeroed[] = {&H->zt32, &H->z32};
-    for (float** v : zeroed) {
-        EB_TRY(dalloc_n(v, H->npad, s));
-        EB_HIP(hipMemsetAsync(*v, 0, sizeof(float) * H->npad, s));
+    EB_TRY(dalloc_n(&H->zt32, H->npad, s));
+    EB_TRY(dalloc_n(&H->z32, H->npad, s));
+    {
+        const FillSpec f[] = {{H->zt32, sizeof(float) * H->npad, 0u}, {H->z32, sizeof(float) * H->npad, 0u}};
+        EB_TRY(fill_words(f, 2, s));
     }
     for (int l = 1; l < H->nlev; ++l) {
         Level& L = H->lev[l];
@@ -1203,16 +1204,29 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     const int64_t npad = H->npad;
     const int64_t nunk = H->n_fine;
     EB_TRY(dalloc_n(&H->dcount, 2, s));
-    EB_HIP(hipMemsetAsync(H->dcount, 0, 2 * sizeof(int32_t), s));
     EB_TRY(dalloc_n(&H->fine_pad, nunk, s));
     EB_TRY(dalloc_n(&H->diag_p, npad, s));
     EB_TRY(dalloc_n(&H->agg_p, npad, s));
-    EB_HIP(hipMemsetAsync(H->diag_p, 0, sizeof(double) * npad, s));
-    EB_HIP(hipMemsetAsync(H->agg_p, 0xff, sizeof(int32_t) * npad, s));   // -1
     const int64_t nstrip_all = npad / H->strip_w;
     int32_t* sflag = nullptr;
     EB_TRY(dalloc_n(&sflag, nstrip_all, s));
-    EB_HIP(hipMemsetAsync(sflag, 0, sizeof(int32_t) * nstrip_all, s));
+    // Fields read at neighbours without a guard must be zero off unknowns
+    // (kernels only ever write unknowns); the others are fully written first
+    // or read only where the diagonal is non-zero.
+    double** zeroed[] = {&H->x, &H->z, &H->zt, &H->p[0], &H->p[1]};
+    for (double** v : zeroed) EB_TRY(dalloc_n(v, npad, s));
+    {
+        const FillSpec f[] = {{H->dcount, 2 * sizeof(int32_t), 0u},
+                              {H->diag_p, sizeof(double) * npad, 0u},
+                              {H->agg_p, sizeof(int32_t) * npad, 0xffffffffu},    // -1
+                              {sflag, sizeof(int32_t) * nstrip_all, 0u},
+                              {H->x, sizeof(double) * npad, 0u},
+                              {H->z, sizeof(double) * npad, 0u},
+                              {H->zt, sizeof(double) * npad, 0u},
+                              {H->p[0], sizeof(double) * npad, 0u},
+                              {H->p[1], sizeof(double) * npad, 0u}};
+        EB_TRY(fill_words(f, 9, s));
+    }
     Level& L0 = H->lev[0];
     hipLaunchKernelGGL(k_fine_layout, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, H->fine_nodes, nunk, d, H->px, L0.diag,
                        L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->diag_p, H->agg_p, sflag,
@@ -1246,14 +1260,6 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
             set_error("a fine-level box holds %d aggregates (limit %d)", L0.max_comp, MAX_FINE_COMP);
             return EB_ENOSPC;
         }
-    }
-    // Fields read at neighbours without a guard must be zero off unknowns
-    // (kernels only ever write unknowns); the others are fully written first
-    // or read only where the diagonal is non-zero.
-    double** zeroed[] = {&H->x, &H->z, &H->zt, &H->p[0], &H->p[1]};
-    for (double** v : zeroed) {
-        EB_TRY(dalloc_n(v, npad, s));
-        EB_HIP(hipMemsetAsync(*v, 0, sizeof(double) * npad, s));
     }
     double** plain[] = {&H->rr[0], &H->rr[1], &H->q, &H->res, &H->bvec};
     for (double** v : plain) EB_TRY(dalloc_n(v, npad, s));

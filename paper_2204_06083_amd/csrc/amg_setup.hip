@@ -107,40 +107,57 @@ __global__ void __launch_bounds__(BLOCK) k_fine_rows(const int8_t* __restrict__ 
     rowcnt[k] = c;
 }
 
-// Row k in ascending column order: -z, -y, -x, self, +x, +y, +z.
+// Row k in ascending column order: -z, -y, -x, self, +x, +y, +z.  The
+// workgroup's rows are one contiguous CSR range: each thread builds its row in
+// LDS, then the range is written with consecutive threads on consecutive
+// entries.
+constexpr int FILL_ROW_MAX = 7;
+
 __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ kind, const double* __restrict__ a,
                                                      double sigma, GridDims d, int64_t nunk,
                                                      const int64_t* __restrict__ fine_nodes,
                                                      const int32_t* __restrict__ unk_off,
                                                      const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
                                                      double* __restrict__ val, double* __restrict__ diag) {
-    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (k >= nunk) return;
-    const int64_t n = fine_nodes[k];
-    int32_t pos = rowptr[k];
-    const double off = -d.s;
-    int64_t nbrs[7];
-    int cnt = 0;
-    if (d.dim == 3) nbrs[cnt++] = n - d.sz;
-    nbrs[cnt++] = n - d.sy;
-    nbrs[cnt++] = n - 1;
-    const int self = cnt;
-    nbrs[cnt++] = n;
-    nbrs[cnt++] = n + 1;
-    nbrs[cnt++] = n + d.sy;
-    if (d.dim == 3) nbrs[cnt++] = n + d.sz;
-    for (int e = 0; e < cnt; ++e) {
-        if (e == self) {
-            const double dg = a[n] * d.s + sigma;
-            col[pos] = (int32_t)k;
-            val[pos] = dg;
-            diag[k] = dg;
-            ++pos;
-        } else if (kind[nbrs[e]] == 2) {
-            col[pos] = unk_off[nbrs[e]];
-            val[pos] = off;
-            ++pos;
+    __shared__ int32_t col_s[BLOCK * FILL_ROW_MAX];
+    __shared__ double val_s[BLOCK * FILL_ROW_MAX];
+    const int64_t k0 = (int64_t)blockIdx.x * BLOCK;
+    const int64_t k = k0 + threadIdx.x;
+    const int64_t kend = k0 + BLOCK < nunk ? k0 + BLOCK : nunk;
+    const int32_t base = rowptr[k0];
+    if (k < nunk) {
+        const int64_t n = fine_nodes[k];
+        int32_t pos = rowptr[k] - base;
+        const double off = -d.s;
+        int64_t nbrs[7];
+        int cnt = 0;
+        if (d.dim == 3) nbrs[cnt++] = n - d.sz;
+        nbrs[cnt++] = n - d.sy;
+        nbrs[cnt++] = n - 1;
+        const int self = cnt;
+        nbrs[cnt++] = n;
+        nbrs[cnt++] = n + 1;
+        nbrs[cnt++] = n + d.sy;
+        if (d.dim == 3) nbrs[cnt++] = n + d.sz;
+        for (int e = 0; e < cnt; ++e) {
+            if (e == self) {
+                const double dg = a[n] * d.s + sigma;
+                col_s[pos] = (int32_t)k;
+                val_s[pos] = dg;
+                diag[k] = dg;
+                ++pos;
+            } else if (kind[nbrs[e]] == 2) {
+                col_s[pos] = unk_off[nbrs[e]];
+                val_s[pos] = off;
+                ++pos;
+            }
         }
+    }
+    __syncthreads();
+    const int32_t len = rowptr[kend] - base;
+    for (int32_t e = threadIdx.x; e < len; e += BLOCK) {
+        col[base + e] = col_s[e];
+        val[base + e] = val_s[e];
     }
 }
 

@@ -16,35 +16,61 @@ namespace eb {
 // neighbour; computational point = inside with all 2d neighbours inside.
 __global__ void __launch_bounds__(BLOCK) k_classify(const double* __restrict__ psi, int8_t* __restrict__ kind,
                                                     GridDims d, int64_t nnodes, int32_t* __restrict__ err,
-                                                    int32_t* __restrict__ is_unknown, int32_t* __restrict__ ncut) {
+                                                    int32_t* __restrict__ block_unknowns,
+                                                    int32_t* __restrict__ ncut) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (n >= nnodes) return;
-    const NodePos p = node_pos(n, d);
-    const bool inside = psi[n] < 0.0;
-    const bool edge = p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
-                      (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
+    const bool active = n < nnodes;
     int8_t kd = 0;
-    int cuts = 0;
-    if (inside) {
-        if (edge) {
-            atomicOr(err, DEVERR_DOMAIN);
-            kd = 1;
-        } else {
-            int n_in = 0;
-            for (int axis = 0; axis < d.dim; ++axis) {
-                const int64_t st = axis_stride(d, axis);
-                n_in += psi[n - st] < 0.0;
-                n_in += psi[n + st] < 0.0;
+    if (active) {
+        const NodePos p = node_pos(n, d);
+        const bool inside = psi[n] < 0.0;
+        const bool edge = p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
+                          (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
+        if (inside) {
+            if (edge) {
+                atomicOr(err, DEVERR_DOMAIN);
+                kd = 1;
+            } else {
+                int n_in = 0;
+                for (int axis = 0; axis < d.dim; ++axis) {
+                    const int64_t st = axis_stride(d, axis);
+                    n_in += psi[n - st] < 0.0;
+                    n_in += psi[n + st] < 0.0;
+                }
+                kd = n_in == 2 * d.dim ? 2 : 1;
             }
-            kd = n_in == 2 * d.dim ? 2 : 1;
         }
+        kind[n] = kd;
+        ncut[n] = 0;  // sides are counted once kinds are known (k_count_cuts)
     }
-    kind[n] = kd;
-    is_unknown[n] = kd == 2;
-    ncut[n] = cuts;  // sides are counted once kinds are known (k_count_cuts)
+    // unknowns per workgroup, summed afterwards by k_sum_counts (no atomics)
+    __shared__ int32_t wcount[BLOCK / WAVE];
+    const unsigned long long bal = __ballot(active && kd == 2);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wcount[threadIdx.x / WAVE] = (int32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t c = 0;
+        for (int w = 0; w < BLOCK / WAVE; ++w) c += wcount[w];
+        block_unknowns[blockIdx.x] = c;
+    }
 }
 
-// Number of boundary-point sides of each computational point.
+// total = sum of n counts, one workgroup (integer: exact in any order).
+__global__ void __launch_bounds__(1024) k_sum_counts(const int32_t* __restrict__ v, int64_t n,
+                                                     unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long part[1024 / WAVE];
+    unsigned long long acc = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += (unsigned long long)v[i];
+    for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 1024 / WAVE; ++w) t += part[w];
+        *total = t;
+    }
+}
+
 __global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, GridDims d, int64_t nnodes,
                                                       int32_t* __restrict__ ncut) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -75,6 +101,11 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
                                                      int64_t cap, int32_t* __restrict__ err) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= nnodes) return;
+    // A domain that reaches the outer layer (flagged by k_classify, final by
+    // now) makes unknowns next to that layer, whose walks would step past it:
+    // nothing to do, the call fails.  This kernel only adds the flag where
+    // k_classify has already set it.
+    if (*err & DEVERR_DOMAIN) return;
     if (kind[n] != 2) {
         a[n] = 0.0;
         return;
@@ -204,15 +235,13 @@ __global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restric
     y[n] = diag * x[n] - d.s * nb;
 }
 
-static int check_err_word(const int32_t* derr, hipStream_t s) {
-    int32_t e = 0;
-    EB_TRY(read_device_i32(derr, &e, s));
-    if (e & DEVERR_DOMAIN) {
-        set_error("the domain reaches the outermost node layer (psi < 0 there)");
-        return EB_EDOMAIN;
-    }
-    return EB_OK;
-}
+// Device status of one assembly, read back once at the end.
+struct AsmStat {
+    int32_t err;
+    int32_t pad;
+    int64_t cuts;                 // total cut records (scan total)
+    unsigned long long unknowns;  // interior nodes
+};
 
 }  // namespace eb
 
@@ -230,44 +259,51 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    int32_t* err = nullptr;
-    int32_t* is_unk = nullptr;
+    // No host round trip until the end: with a domain error k_count_cuts only
+    // reads neighbours of unknowns (never on the outer layer) and k_diag_cuts
+    // returns at once; the cut records are bounded by cuts_cap on the device;
+    // status, totals and errors come back in one read.
+    AsmStat* st = nullptr;
     int32_t* ncut = nullptr;
     int64_t* off = nullptr;
-    int32_t* unk_off = nullptr;
-    EB_TRY(dalloc_n(&err, 1, s));
-    EB_TRY(dalloc_n(&is_unk, nn, s));
+    int32_t* blk_unk = nullptr;
+    const unsigned nblk = grid_for(nn);
+    EB_TRY(dalloc_n(&st, 1, s));
     EB_TRY(dalloc_n(&ncut, nn, s));
     EB_TRY(dalloc_n(&off, nn, s));
-    EB_TRY(dalloc_n(&unk_off, nn, s));
-    EB_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, err, is_unk, ncut);
-    EB_LAUNCH_CHECK();
-    int rc = check_err_word(err, s);
-    if (rc == EB_OK) {
-        hipLaunchKernelGGL(k_count_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, ncut);
-        EB_LAUNCH_CHECK();
-        int64_t total_cuts = 0, total_unk = 0;
-        EB_TRY(scan_i32_to_i64(ncut, off, nn, &total_cuts, s));
-        EB_TRY(scan_i32(is_unk, unk_off, nn, &total_unk, s));
-        hipLaunchKernelGGL(k_diag_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, off, a, cuts,
-                           cuts_cap, err);
-        EB_LAUNCH_CHECK();
-        rc = check_err_word(err, s);
-        *n_unknowns = total_unk;
-        *n_cuts = total_cuts;
-        if (rc == EB_OK && total_cuts > cuts_cap) {
-            set_error("cut-record capacity %lld < required %lld", (long long)cuts_cap, (long long)total_cuts);
-            rc = EB_ENOSPC;
-        }
+    EB_TRY(dalloc_n(&blk_unk, nblk, s));
+    {
+        const FillSpec f[] = {{st, sizeof(AsmStat), 0u}};
+        EB_TRY(fill_words(f, 1, s));
     }
-    EB_TRY(dfree(err, s));
-    EB_TRY(dfree(is_unk, s));
+    hipLaunchKernelGGL(k_classify, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, &st->err, blk_unk, ncut);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, blk_unk, (int64_t)nblk, &st->unknowns);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_count_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, ncut);
+    EB_LAUNCH_CHECK();
+    EB_TRY(scan_i32_to_i64_dev(ncut, off, nn, &st->cuts, s));
+    hipLaunchKernelGGL(k_diag_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, off, a, cuts, cuts_cap,
+                       &st->err);
+    EB_LAUNCH_CHECK();
+    AsmStat h;
+    EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));
+    EB_TRY(dfree(st, s));
     EB_TRY(dfree(ncut, s));
     EB_TRY(dfree(off, s));
-    EB_TRY(dfree(unk_off, s));
+    EB_TRY(dfree(blk_unk, s));
     EB_HIP(hipStreamSynchronize(s));
-    return rc;
+    if (h.err & DEVERR_DOMAIN) {
+        set_error("the domain reaches the outermost node layer (psi < 0 there)");
+        return EB_EDOMAIN;
+    }
+    *n_unknowns = (int64_t)h.unknowns;
+    *n_cuts = h.cuts;
+    if (h.cuts > cuts_cap) {
+        set_error("cut-record capacity %lld < required %lld", (long long)cuts_cap, (long long)h.cuts);
+        return EB_ENOSPC;
+    }
+    return EB_OK;
 }
 
 extern "C" int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const double* f, const eb_cut_t* cuts,

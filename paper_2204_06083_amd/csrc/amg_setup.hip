@@ -1540,7 +1540,7 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
                     L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp,
-                    L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32};
+                    L.sv, L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
     for (void* p : ptrs) (void)dfree(p, s);
     L = Level();
 }

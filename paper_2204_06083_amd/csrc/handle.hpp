@@ -29,11 +29,13 @@ struct Level {
     int32_t* box_cstart = nullptr;  // nboxes: first coarse unknown of each box
     int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
     double* dense_inv = nullptr; // coarsest: n x n
-    // solve vectors (levels >= 1)
-    double* rv = nullptr; double* ev = nullptr; double* tmp = nullptr;
+    // solve vectors (levels >= 1); sv = omega rv / diag, written with rv by the
+    // restriction that produces it (each consumer then gathers one value
+    // instead of two and divides no more)
+    double* rv = nullptr; double* ev = nullptr; double* tmp = nullptr; double* sv = nullptr;
     // FP32 copies for the single-precision V-cycle (made on first use)
     float* a_val32 = nullptr; float* p_val32 = nullptr; float* r_val32 = nullptr; float* diag32 = nullptr;
-    float* rv32 = nullptr; float* ev32 = nullptr; float* tmp32 = nullptr;
+    float* rv32 = nullptr; float* ev32 = nullptr; float* tmp32 = nullptr; float* sv32 = nullptr;
 };
 
 // Device scalars of one PCG solve.  Written only by block 0 of the kernel

@@ -259,8 +259,9 @@ struct BoxArgs {
 template <class V, int DIM>
 __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
                                                       const V* __restrict__ res, V* __restrict__ rc,
-                                                      PcgScalars* sc, int check, const double* __restrict__ part_rr,
-                                                      int np) {
+                                                      const V* __restrict__ dg_c, double omega_c,
+                                                      V* __restrict__ sv_c, PcgScalars* sc, int check,
+                                                      const double* __restrict__ part_rr, int np) {
     if (sc->done) return;
     if (check && converged_or_failed<RNT>(part_rr, np, sc)) return;
     const int64_t t = xcd_block() * RNT + threadIdx.x;
@@ -319,6 +320,7 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
             for (int n = 0; n < 9; ++n)
                 if (comp[n] == c) acc += u[n];
             rc[c0 + c] = acc;
+            if (sv_c) sv_c[c0 + c] = (V)omega_c * acc / dg_c[c0 + c];
         }
         return;
     }
@@ -349,7 +351,10 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
             }
         }
     }
-    for (int c = 0; c < m && c < MAX_FINE_COMP; ++c) rc[c0 + c] = acc[c];
+    for (int c = 0; c < m && c < MAX_FINE_COMP; ++c) {
+        rc[c0 + c] = acc[c];
+        if (sv_c) sv_c[c0 + c] = (V)omega_c * acc[c] / dg_c[c0 + c];
+    }
 }
 
 // PCG update fused with the fine pre-smoothing and residual:
@@ -544,7 +549,7 @@ struct Csr {
 //   res_j = rv_j - sum_e a_je omega rv_e / d_e;   rv_c[I] = sum_j R_Ij res_j;
 //   zt_j = omega rv_j / d_j + sum_J P_jJ ev_c[J]; ev_i = zt_i + omega (rv_i - (A zt)_i) / d_i.
 template <int LPR, class V>
-__global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr<V> A, const V* __restrict__ diag, V omega,
+__global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr<V> A, const V* __restrict__ sv,
                                                   const V* __restrict__ rv, V* __restrict__ res,
                                                   const PcgScalars* sc) {
     if (sc->done) return;
@@ -554,7 +559,7 @@ __global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr<V> A, const V* 
     V az = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
         const int k = A.col[e];
-        az += A.val[e] * (omega * rv[k] / diag[k]);
+        az += A.val[e] * sv[k];
     }
     az = segment_sum<LPR>(az);
     if (lane == 0) res[row] = rv[row] - az;
@@ -562,7 +567,8 @@ __global__ void __launch_bounds__(NT) k_csr_resid(int64_t n, Csr<V> A, const V* 
 
 template <int LPR, class V>
 __global__ void __launch_bounds__(NT) k_csr_matvec(int64_t n, Csr<V> M, const V* __restrict__ x,
-                                                   V* __restrict__ y, const PcgScalars* sc) {
+                                                   V* __restrict__ y, const V* __restrict__ dg_y, V omega_y,
+                                                   V* __restrict__ sv_y, const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
@@ -570,13 +576,16 @@ __global__ void __launch_bounds__(NT) k_csr_matvec(int64_t n, Csr<V> M, const V*
     V acc = V(0);
     for (int e = M.rowptr[row] + lane; e < M.rowptr[row + 1]; e += LPR) acc += M.val[e] * x[M.col[e]];
     acc = segment_sum<LPR>(acc);
-    if (lane == 0) y[row] = acc;
+    if (lane == 0) {
+        y[row] = acc;
+        if (sv_y) sv_y[row] = omega_y * acc / dg_y[row];
+    }
 }
 
 template <int LPR, class V>
-__global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr<V> P, const V* __restrict__ diag, V omega,
-                                                    const V* __restrict__ rv, const V* __restrict__ ev_c,
-                                                    V* __restrict__ zt, const PcgScalars* sc) {
+__global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr<V> P, const V* __restrict__ sv,
+                                                    const V* __restrict__ ev_c, V* __restrict__ zt,
+                                                    const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
@@ -584,7 +593,7 @@ __global__ void __launch_bounds__(NT) k_csr_prolong(int64_t n, Csr<V> P, const V
     V acc = V(0);
     for (int e = P.rowptr[row] + lane; e < P.rowptr[row + 1]; e += LPR) acc += P.val[e] * ev_c[P.col[e]];
     acc = segment_sum<LPR>(acc);
-    if (lane == 0) zt[row] = omega * rv[row] / diag[row] + acc;
+    if (lane == 0) zt[row] = sv[row] + acc;
 }
 
 template <int LPR, class V>
@@ -604,9 +613,10 @@ __global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr<V> A, const V* _
 // Residual and restriction in one pass:
 //   rv_c[I] = sum_{j in R row I} R_Ij (rv_j - sum_e a_je omega rv_e / d_e).
 template <int LPR, class V>
-__global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V> A, const V* __restrict__ diag,
-                                                    V omega, const V* __restrict__ rv,
-                                                    V* __restrict__ rv_c, const PcgScalars* sc) {
+__global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V> A, const V* __restrict__ sv,
+                                                    const V* __restrict__ rv, V* __restrict__ rv_c,
+                                                    const V* __restrict__ dg_c, V omega_c, V* __restrict__ sv_c,
+                                                    const PcgScalars* sc) {
     if (sc->done) return;
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
@@ -617,12 +627,15 @@ __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V>
         V az = V(0);
         for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
             const int k = A.col[f];
-            az += A.val[f] * (omega * rv[k] / diag[k]);
+            az += A.val[f] * sv[k];
         }
         acc += R.val[e] * (rv[j] - az);
     }
     acc = segment_sum<LPR>(acc);
-    if (lane == 0) rv_c[row] = acc;
+    if (lane == 0) {
+        rv_c[row] = acc;
+        if (sv_c) sv_c[row] = omega_c * acc / dg_c[row];
+    }
 }
 
 // Prolongation and post-smoothing in one pass:
@@ -630,7 +643,7 @@ __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V>
 //   ev[i] = zt_i + omega (rv_i - sum_{A row i} a_ij zt_j) / d_i.
 template <int LPR, class V>
 __global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P, const V* __restrict__ diag,
-                                                  V omega, const V* __restrict__ rv,
+                                                  V omega, const V* __restrict__ rv, const V* __restrict__ sv,
                                                   const V* __restrict__ ev_c, V* __restrict__ ev,
                                                   const PcgScalars* sc) {
     if (sc->done) return;
@@ -640,13 +653,13 @@ __global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P,
     V acc = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
         const int j = A.col[e];
-        V zt = omega * rv[j] / diag[j];
+        V zt = sv[j];
         for (int g = P.rowptr[j]; g < P.rowptr[j + 1]; ++g) zt += P.val[g] * ev_c[P.col[g]];
         acc += A.val[e] * zt;
     }
     acc = segment_sum<LPR>(acc);
     if (lane == 0) {
-        V zi = omega * rv[row] / diag[row];
+        V zi = sv[row];
         for (int g = P.rowptr[row]; g < P.rowptr[row + 1]; ++g) zi += P.val[g] * ev_c[P.col[g]];
         ev[row] = zi + omega * (rv[row] - acc) / diag[row];
     }
@@ -847,12 +860,14 @@ static BoxArgs box_args(const amg_handle* H) {
 static int launch_fine_restrict64(amg_handle* H, const FineArgs& f, double w0, const double* res, double* rc, int np,
                                   hipStream_t s) {
     const dim3 g(xcd_grid(H->nboxes0, RNT));
+    const Level& L1 = H->lev[1];
+    double* sv1 = H->nlev > 2 ? L1.sv : nullptr;
     if (H->d.dim == 2)
-        hipLaunchKernelGGL((k_fine_restrict<double, 2>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc, H->sc, 0,
-                           H->red.rr, np);
+        hipLaunchKernelGGL((k_fine_restrict<double, 2>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc,
+                           (const double*)L1.diag, L1.omega, sv1, H->sc, 0, H->red.rr, np);
     else
-        hipLaunchKernelGGL((k_fine_restrict<double, 3>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc, H->sc, 0,
-                           H->red.rr, np);
+        hipLaunchKernelGGL((k_fine_restrict<double, 3>), g, dim3(RNT), 0, s, f, box_args(H), w0, res, rc,
+                           (const double*)L1.diag, L1.omega, sv1, H->sc, 0, H->red.rr, np);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
@@ -865,16 +880,17 @@ struct LevelView {
     V* rv;
     V* ev;
     V* tmp;
+    V* sv;
 };
 
 template <class V> static LevelView<V> view(const Level& L);
 template <> LevelView<double> view<double>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val}, {L.p_rowptr, L.p_col, L.p_val}, {L.r_rowptr, L.r_col, L.r_val},
-            L.diag, L.rv, L.ev, L.tmp};
+            L.diag, L.rv, L.ev, L.tmp, L.sv};
 }
 template <> LevelView<float> view<float>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val32}, {L.p_rowptr, L.p_col, L.p_val32}, {L.r_rowptr, L.r_col, L.r_val32},
-            L.diag32, L.rv32, L.ev32, L.tmp32};
+            L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
 }
 
 template <class V>
@@ -929,14 +945,16 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         const Level& L = H->lev[l];
         const Level& C = H->lev[l + 1];
         const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
-        const V w = (V)L.omega;
         const int lpr_r = lanes_for((double)L.nnz_r / (double)(C.n > 0 ? C.n : 1));
+        // omega rv / diag of the coarse level, for its own kernels (none on the coarsest)
+        const V wc = (V)C.omega;
+        V* svc = l + 1 < H->nlev - 1 ? Cv.sv : nullptr;
         if (!fuse_down(L, C)) {
             const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_resid, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, sc);
-            EB_LPR_LAUNCH(k_csr_matvec, V, lpr_r, C.n, C.n, Lv.R, Lv.tmp, Cv.rv, sc);
+            EB_LPR_LAUNCH(k_csr_resid, V, lpr_a, L.n, L.n, Lv.A, Lv.sv, Lv.rv, Lv.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_matvec, V, lpr_r, C.n, C.n, Lv.R, Lv.tmp, Cv.rv, Cv.diag, wc, svc, sc);
         } else {
-            EB_LPR_LAUNCH(k_coarse_down, V, lpr_r, C.n, C.n, Lv.R, Lv.A, Lv.diag, w, Lv.rv, Cv.rv, sc);
+            EB_LPR_LAUNCH(k_coarse_down, V, lpr_r, C.n, C.n, Lv.R, Lv.A, Lv.sv, Lv.rv, Cv.rv, Cv.diag, wc, svc, sc);
         }
     }
     {
@@ -953,10 +971,10 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
         if (L.n >= FUSE_BELOW) {
             const int lpr_p = lanes_for((double)L.nnz_p / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_prolong, V, lpr_p, L.n, L.n, Lv.P, Lv.diag, w, Lv.rv, Cv.ev, Lv.tmp, sc);
+            EB_LPR_LAUNCH(k_csr_prolong, V, lpr_p, L.n, L.n, Lv.P, Lv.sv, Cv.ev, Lv.tmp, sc);
             EB_LPR_LAUNCH(k_csr_post, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, Lv.ev, sc);
         } else {
-            EB_LPR_LAUNCH(k_coarse_up, V, lpr_a, L.n, L.n, Lv.A, Lv.P, Lv.diag, w, Lv.rv, Cv.ev, Lv.ev, sc);
+            EB_LPR_LAUNCH(k_coarse_up, V, lpr_a, L.n, L.n, Lv.A, Lv.P, Lv.diag, w, Lv.rv, Lv.sv, Cv.ev, Lv.ev, sc);
         }
     }
     EB_LAUNCH_CHECK();
@@ -996,10 +1014,12 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
                     np);
     if (H->d.dim == 2)
         EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
-                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
+                        H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     else
         EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
-                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 0, H->red.rr, np);
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
+                        H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
@@ -1036,10 +1056,12 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
                     w0, rz_cur, H->red.pq, np, H->red.rr, sc);
     if (H->d.dim == 2)
         EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
-                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
+                        H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     else
         EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
-                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, sc, 1, H->red.rr, np);
+                        dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
+                        H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
@@ -1175,6 +1197,7 @@ int ensure_fp32(amg_handle* H, hipStream_t s) {
             EB_TRY(copy_to_f32(L.r_val, L.nnz_r, &L.r_val32, s));
         }
         EB_TRY(dalloc_n(&L.rv32, n, s));
+        EB_TRY(dalloc_n(&L.sv32, n, s));
         EB_TRY(dalloc_n(&L.ev32, n, s));
         EB_TRY(dalloc_n(&L.tmp32, n, s));
     }
@@ -1268,6 +1291,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
         if (l == 0 && H->nlev > 1) continue;
         const int64_t n = L.n > 0 ? L.n : 1;
         EB_TRY(dalloc_n(&L.rv, n, s));
+        EB_TRY(dalloc_n(&L.sv, n, s));
         EB_TRY(dalloc_n(&L.ev, n, s));
         EB_TRY(dalloc_n(&L.tmp, n, s));
     }

@@ -1315,9 +1315,21 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     }
     EB_TRY(dalloc_n(&L.dense_inv, n * n, s));
     if (n <= SW_NMAX) {
-        hipLaunchKernelGGL((k_dense_sweep<SW_T, SW_THREADS>), dim3(1), dim3(SW_THREADS), 0, s, L.a_rowptr, L.a_col,
-                           L.a_val, (int)n, L.dense_inv, err);
+        // one workgroup on one CU: run it on the side stream so that the fine
+        // solve layout, built next on s, overlaps it; setup_impl joins before
+        // its read-back (the kernel reads this level's A and writes dense_inv
+        // and the error word, none of which s frees or rewrites meanwhile)
+        hipStream_t side = nullptr;
+        EB_TRY(side_stream(&side));
+        if (!H->ev_fork) EB_HIP(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+        if (!H->ev_join) EB_HIP(hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+        EB_HIP(hipEventRecord(H->ev_fork, s));
+        EB_HIP(hipStreamWaitEvent(side, H->ev_fork, 0));
+        hipLaunchKernelGGL((k_dense_sweep<SW_T, SW_THREADS>), dim3(1), dim3(SW_THREADS), 0, side, L.a_rowptr,
+                           L.a_col, L.a_val, (int)n, L.dense_inv, err);
         EB_LAUNCH_CHECK();
+        EB_HIP(hipEventRecord(H->ev_join, side));
+        H->join_pending = 1;
         return EB_OK;
     }
     // larger levels (coarsening stalled): blocked Cholesky, L^-1, L^-T L^-1
@@ -1547,6 +1559,10 @@ static void free_level(Level& L, hipStream_t s) {
 
 int free_handle_memory(amg_handle* H) {
     hipStream_t s = H->stream;
+    // a setup that failed between fork and join may leave the coarsest
+    // inverse running on the side stream
+    if (H->join_pending && H->ev_join) (void)hipEventSynchronize(H->ev_join);
+    H->join_pending = 0;
     // blocks go back to the library cache tagged with the setup stream: wait
     // for any solve still running on another stream first
     if (H->last_stream && H->last_stream != s) (void)hipStreamSynchronize(H->last_stream);
@@ -1562,6 +1578,9 @@ int free_handle_memory(amg_handle* H) {
     H->tim_ev = nullptr;    // process-wide event pool, not owned
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
+    if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+    if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    H->ev_fork = H->ev_join = nullptr;
     return EB_OK;
 }
 
@@ -1636,6 +1655,10 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     }
     H->nlev = l + 1;
     EB_TRY(solve_layout_alloc(H, s));
+    if (H->join_pending) {      // the coarsest inverse (side stream)
+        EB_HIP(hipStreamWaitEvent(s, H->ev_join, 0));
+        H->join_pending = 0;
+    }
 
     // one read-back: sizes of every level, smoothing weights, errors
     ReportArgs R;

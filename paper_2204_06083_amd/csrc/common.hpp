@@ -123,6 +123,11 @@ struct FillSpec {
     uint32_t word;
 };
 int fill_words(const FillSpec* items, int count, hipStream_t s);
+
+// A second stream on the current device (non-blocking, default priority,
+// created on first use and kept until the process ends) for work that can
+// overlap the caller's stream; ordering with it goes through events.
+int side_stream(hipStream_t* out);
 int scan_i32_to_i64_dev(const int32_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s);
 
 // Small helpers used by several translation units.

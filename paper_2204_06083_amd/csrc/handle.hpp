@@ -118,6 +118,12 @@ struct amg_handle {
     hipGraphExec_t it_graph[2] = {nullptr, nullptr};
     int it_graph_wf[2] = {-1, -1};
     hipStream_t cap_stream = nullptr;   // private stream the graphs are captured on
+    // the coarsest inverse runs on the device's side stream during setup
+    // (forked after the coarsest level is built, joined before the setup's
+    // read-back); join_pending while that work may still be in flight
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join = nullptr;
+    int join_pending = 0;
     // kernel timing hook (eb_timing_select / eb_timing_read)
     int tim_kernel = -1;
     int tim_cap = 0;

@@ -171,6 +171,24 @@ int make_dims(const eb_grid_t* g, GridDims* d) {
     return EB_OK;
 }
 
+// ------------------------------------------------------------ side stream
+namespace {
+std::mutex g_side_mutex;
+hipStream_t g_side[64] = {};
+}  // namespace
+
+int side_stream(hipStream_t* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        set_error("side_stream: no current device");
+        return EB_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_side_mutex);
+    if (!g_side[dev]) EB_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return EB_OK;
+}
+
 // ------------------------------------------------------------------- fill
 struct FillList {
     uint32_t* p[FILL_MAX];

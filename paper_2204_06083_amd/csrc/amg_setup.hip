@@ -1164,19 +1164,36 @@ __global__ void k_omega(const unsigned long long* __restrict__ rho_bits, double*
 }
 
 // Gather the sizes the host reports (nnz per level) into one array.
+// Everything the setup reads back, gathered into one block for one copy:
+// nnz of A, P, R per level, (rho, omega) per level, the fine strip and box
+// counts, and the status words.
 struct ReportArgs {
     int nlev;
     const int32_t* a_tot[MAX_LEVELS];
     const int32_t* p_tot[MAX_LEVELS];
     const int32_t* r_tot[MAX_LEVELS];
+    const double* scal;      // 2 * MAX_LEVELS
+    const int32_t* counts;   // 2
+    const int32_t* stat;     // 4 (SetupStat)
 };
 
-__global__ void k_report(ReportArgs R, int64_t* __restrict__ out) {
+struct ReportBlock {
+    int64_t nnz[3 * MAX_LEVELS];
+    double scal[2 * MAX_LEVELS];
+    int32_t counts[2];
+    int32_t stat[4];
+};
+
+__global__ void k_report(ReportArgs R, ReportBlock* __restrict__ out) {
     const int l = threadIdx.x;
-    if (l >= R.nlev) return;
-    out[3 * l + 0] = R.a_tot[l] ? *R.a_tot[l] : 0;
-    out[3 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
-    out[3 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
+    if (l < R.nlev) {
+        out->nnz[3 * l + 0] = R.a_tot[l] ? *R.a_tot[l] : 0;
+        out->nnz[3 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
+        out->nnz[3 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
+    }
+    if (l < 2 * MAX_LEVELS) out->scal[l] = R.scal[l];
+    if (l < 2) out->counts[l] = R.counts[l];
+    if (l < 4) out->stat[l] = R.stat[l];
 }
 
 // ------------------------------------------------------------- host helpers
@@ -1672,28 +1689,29 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
             R.r_tot[k] = L.r_rowptr + H->lev[k + 1].n;
         }
     }
-    int64_t* drep = nullptr;
-    EB_TRY(dalloc_n(&drep, 3 * MAX_LEVELS, s));
+    R.scal = H->dscal;
+    R.counts = H->dcount;
+    R.stat = dstat;
+    static_assert(2 * MAX_LEVELS <= 64, "k_report runs one 64-thread block");
+    ReportBlock* drep = nullptr;
+    EB_TRY(dalloc_n(&drep, 1, s));
     hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, R, drep);
     EB_LAUNCH_CHECK();
-    int64_t rep[3 * MAX_LEVELS];
-    double scal[2 * MAX_LEVELS];
-    EB_HIP(hipMemcpyAsync(rep, drep, sizeof(int64_t) * 3 * H->nlev, hipMemcpyDeviceToHost, s));
-    EB_HIP(hipMemcpyAsync(scal, H->dscal, sizeof(double) * 2 * MAX_LEVELS, hipMemcpyDeviceToHost, s));
-    int32_t counts[2] = {0, 0};
-    EB_HIP(hipMemcpyAsync(counts, H->dcount, sizeof(counts), hipMemcpyDeviceToHost, s));
-    EB_TRY(read_stat(dstat, &st, s));
-    H->nstrips = counts[0];
-    H->nboxes0 = counts[1];
+    ReportBlock rep;
+    EB_HIP(hipMemcpyAsync(&rep, drep, sizeof(ReportBlock), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    memcpy(&st, rep.stat, sizeof(st));
+    H->nstrips = rep.counts[0];
+    H->nboxes0 = rep.counts[1];
     EB_TRY(dfree(drep, s));
     for (int k = 0; k < H->nlev; ++k) {
         Level& L = H->lev[k];
-        L.nnz_a = rep[3 * k];
-        L.nnz_p = rep[3 * k + 1];
-        L.nnz_r = rep[3 * k + 2];
+        L.nnz_a = rep.nnz[3 * k];
+        L.nnz_p = rep.nnz[3 * k + 1];
+        L.nnz_r = rep.nnz[3 * k + 2];
         if (!L.is_coarsest) {
-            L.rho = scal[2 * k];
-            L.omega = scal[2 * k + 1];
+            L.rho = rep.scal[2 * k];
+            L.omega = rep.scal[2 * k + 1];
         }
     }
     EB_TRY(err_code(st.err, "amg_setup"));

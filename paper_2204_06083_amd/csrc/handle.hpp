@@ -46,6 +46,8 @@ struct PcgScalars {
     double tol2bb;     // tol^2 ||b||^2
     double pq;         // (p, q) of the latest iteration
     double rr_true;    // ||b - A x||^2 recomputed at exit
+    double rr0;        // ||r||^2 at the start (or restart): the host predicts
+                       // the remaining iterations from rr / rr0
     int32_t done;      // 1: converged / failed, later kernels return at once
     int32_t status;    // EB_OK or failure code
     int32_t iters;

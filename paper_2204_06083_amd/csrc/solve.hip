@@ -514,6 +514,7 @@ __global__ void __launch_bounds__(NT) k_finalize_init(PcgScalars* sc, const doub
     if (threadIdx.x == 0) {
         sc->bb = bb;
         sc->rr = rr;
+        sc->rr0 = rr;
         sc->tol2bb = tol * tol * bb;
         sc->status = (bad_value(bb) || bad_value(rr)) ? EB_ENAN : EB_OK;
         sc->done = (bb == 0.0 || rr <= tol * tol * bb || sc->status != EB_OK) ? 1 : 0;
@@ -1730,19 +1731,20 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         if (H->nlev == 1) EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.rz[0], 0, s));
         else if (fp32) EB_TRY(enqueue_vcycle_any<float>(H, H->rr[0], H->z32, H->red.rz[0], s));
         else EB_TRY(enqueue_vcycle_any<double>(H, H->rr[0], H->z, H->red.rz[0], s));
+        // Iterations go out in chunks between polls of the device scalars.
+        // The first chunk is queued without a poll (a system that is already
+        // converged is marked done by the init kernel and every later kernel
+        // returns at once); later chunks end one iteration past the point
+        // where the residual, reduced at the rate seen so far, reaches the
+        // tolerance.  A chunk expected to finish is followed by the true
+        // residual, so that one poll serves both.
         int k = 0;
+        int chunk = p.check_every < p.maxit - iter_base ? p.check_every : p.maxit - iter_base;
+        bool true_done = false;
         while (true) {
-            EB_TRY(poll_scalars(H, s));
-            if (H->sc_host->done || H->sc_host->iters >= p.maxit) break;
-            if (enqueued > 2 * p.maxit + 2 * p.check_every) {
-                set_error("pcg_solve: iteration counter stalled");
-                return EB_EHIP;
-            }
-            const int left = p.maxit - H->sc_host->iters;
-            const int chunk = left < p.check_every ? left : p.check_every;
-            // graphs: not with a one-level hierarchy or while a kernel is being timed
             const bool graphs = g_use_graphs.load() && H->nlev > 1 && H->tim_kernel < 0;
             for (int c = 0; c < chunk;) {
+                // graphs: not with a one-level hierarchy or while a kernel is being timed
                 if (graphs && k + 1 >= 3 && ((k + 1) & 1) && chunk - c >= 2) {
                     if (fp32) EB_TRY(launch_iteration_pair<float>(H, s));
                     else EB_TRY(launch_iteration_pair<double>(H, s));
@@ -1758,12 +1760,44 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
                 else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, s));
                 else EB_TRY(enqueue_iteration_any<double>(H, k, s));
             }
+            const bool expect_end = chunk < p.check_every || k >= p.maxit - iter_base;
+            if (expect_end) {
+                // true residual ||b - A x|| behind the chunk (recomputed below if
+                // the chunk turns out not to finish)
+                hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res,
+                                   H->red.aux);
+                hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
+                EB_LAUNCH_CHECK();
+            }
+            EB_TRY(poll_scalars(H, s));
+            const PcgScalars& ph = *H->sc_host;
+            if (ph.done || ph.iters >= p.maxit) {
+                true_done = expect_end;
+                break;
+            }
+            if (enqueued > 2 * p.maxit + 2 * p.check_every) {
+                set_error("pcg_solve: iteration counter stalled");
+                return EB_EHIP;
+            }
+            const int left = p.maxit - ph.iters;
+            int next = p.check_every;
+            const int done_its = ph.iters - iter_base;
+            if (done_its >= 2 && ph.rr > 0.0 && ph.rr < ph.rr0 && ph.tol2bb > 0.0) {
+                // log(rr_k / rr_0) / k per iteration; iterations to tol^2 bb, plus one
+                const double rate = log(ph.rr / ph.rr0) / (double)done_its;
+                const double need = log(ph.tol2bb / ph.rr) / rate;
+                if (need > 0.0 && need < (double)p.check_every) next = (int)ceil(need) + 1;
+            }
+            chunk = next < left ? next : left;
         }
-        // true residual ||b - A x||
-        hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res, H->red.aux);
-        hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
-        EB_LAUNCH_CHECK();
-        EB_TRY(poll_scalars(H, s));
+        if (!true_done) {
+            // true residual ||b - A x||
+            hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res,
+                               H->red.aux);
+            hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
+            EB_LAUNCH_CHECK();
+            EB_TRY(poll_scalars(H, s));
+        }
         const PcgScalars& sh = *H->sc_host;
         const double bb = sh.bb;
         const double true_rel = bb > 0.0 ? sqrt(sh.rr_true / bb) : 0.0;

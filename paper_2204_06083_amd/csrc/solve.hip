@@ -1740,6 +1740,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         // residual, so that one poll serves both.
         int k = 0;
         int chunk = p.check_every < p.maxit - iter_base ? p.check_every : p.maxit - iter_base;
+        bool predicted = false;    // the chunk was sized to end at convergence
         bool true_done = false;
         while (true) {
             const bool graphs = g_use_graphs.load() && H->nlev > 1 && H->tim_kernel < 0;
@@ -1760,7 +1761,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
                 else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, s));
                 else EB_TRY(enqueue_iteration_any<double>(H, k, s));
             }
-            const bool expect_end = chunk < p.check_every || k >= p.maxit - iter_base;
+            const bool expect_end = predicted || k >= p.maxit - iter_base;
             if (expect_end) {
                 // true residual ||b - A x|| behind the chunk (recomputed below if
                 // the chunk turns out not to finish)
@@ -1781,12 +1782,16 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             }
             const int left = p.maxit - ph.iters;
             int next = p.check_every;
+            predicted = false;
             const int done_its = ph.iters - iter_base;
             if (done_its >= 2 && ph.rr > 0.0 && ph.rr < ph.rr0 && ph.tol2bb > 0.0) {
                 // log(rr_k / rr_0) / k per iteration; iterations to tol^2 bb, plus one
                 const double rate = log(ph.rr / ph.rr0) / (double)done_its;
                 const double need = log(ph.tol2bb / ph.rr) / rate;
-                if (need > 0.0 && need < (double)p.check_every) next = (int)ceil(need) + 1;
+                if (need > 0.0 && need < 2.0 * (double)p.check_every) {
+                    next = (int)ceil(need) + 1;
+                    predicted = true;
+                }
             }
             chunk = next < left ? next : left;
         }

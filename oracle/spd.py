@@ -15,9 +15,19 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   the two sides along that axis.  Theorem 2 states that h^2 A is the sum of
   these per-axis matrices (permuted back to lexicographic order).
 
+* segment_check(kind, cut_node, cut_dir, cut_c): the a-priori test that
+  Sec. 2.4 builds from these pieces: along every axis, every maximal run of
+  computational points on a grid line is one segment; its length n and end
+  entries a, b (the part of the diagonal from the two sides along that axis)
+  must satisfy Lemma 2.1, and then the operator is SPD (Theorems 1-2).  Works
+  from the node kinds and the cut records, so that records with altered c can
+  be checked too.  Returns (segments, failing segments).
+
 Parity: pinned by tests/test_oracle_spd.py (brute-force eigenvalues of random
 segment matrices against the lemma; exact reconstruction of h^2 A from the
-per-axis blocks).
+per-axis blocks; segment counts against a count of run starts; a passing
+check on altered records against the eigenvalues of the per-axis operator it
+describes; a hand-built failing segment that is indefinite).
 """
 from __future__ import annotations
 
@@ -125,3 +135,46 @@ def axis_matrix(asm, phys_axis):
     M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
     return M, blocks, part
+
+
+def segment_check(kind, cut_node, cut_dir, cut_c):
+    """(segments, failing): Lemma 2.1 on every grid-line segment of every axis.
+
+    kind: node field (COMPUTATIONAL marks unknowns); cut records as parallel
+    arrays (flat node index, side in the order of directions(), c = 1/q).
+    The part of a diagonal along one axis is 0 + (minus side) + (plus side),
+    each side 1 for a computational neighbour and c for a cut side.
+    """
+    kind = np.asarray(kind)
+    dim = kind.ndim
+    dirs = directions(dim)
+    strides = _strides(kind.shape)
+    kflat = kind.ravel()
+    cmap = {(int(n), int(sd)): float(c) for n, sd, c in zip(cut_node, cut_dir, cut_c)}
+    segments = 0
+    failing = 0
+    for phys in range(dim):
+        sides = [sd for sd, (_, _, ph) in enumerate(dirs) if ph == phys]
+
+        def part(node):
+            v = 0.0
+            for sd in sides:
+                ax, step, _ = dirs[sd]
+                nb = node + step * strides[ax]
+                v = v + (1.0 if kflat[nb] == COMPUTATIONAL else cmap[(node, sd)])
+            return v
+
+        ax = dim - 1 - phys
+        lines = np.moveaxis(np.arange(kind.size).reshape(kind.shape), ax, -1)
+        for line in lines.reshape(-1, lines.shape[-1]):
+            run = []
+            for node in list(line) + [-1]:
+                if node >= 0 and kflat[node] == COMPUTATIONAL:
+                    run.append(int(node))
+                    continue
+                if run:
+                    segments += 1
+                    if not lemma_conditions(len(run), part(run[0]), part(run[-1])):
+                        failing += 1
+                    run = []
+    return segments, failing

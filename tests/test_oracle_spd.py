@@ -63,3 +63,106 @@ def test_theorem2_decomposition_and_segment_ends(maker):
     if asm.n_unknowns <= 3000:
         lam = np.linalg.eigvalsh(h2A.toarray())
         assert lam[0] > 0
+
+
+def _runs_by_starts(kind):
+    """Segments counted as run starts: an unknown whose predecessor along the
+    axis is not one (an independent count from the node kinds)."""
+    comp = np.asarray(kind) == E.COMPUTATIONAL
+    total = 0
+    for ax in range(comp.ndim):
+        prev = np.zeros_like(comp)
+        sl_dst = [slice(None)] * comp.ndim
+        sl_src = [slice(None)] * comp.ndim
+        sl_dst[ax] = slice(1, None)
+        sl_src[ax] = slice(None, -1)
+        prev[tuple(sl_dst)] = comp[tuple(sl_src)]
+        total += int(np.sum(comp & ~prev))
+    return total
+
+
+def _records(asm):
+    nodes = asm.nodes[asm.cuts["unknown"]]
+    return nodes, asm.cuts["dir"], asm.cuts["c"]
+
+
+@pytest.mark.parametrize("maker", [lambda: W.disk_mms(24), lambda: W.star_poisson(40),
+                                   lambda: W.ellipsoid_poisson(14)])
+def test_segment_check_on_assemblies(maker):
+    """Line-by-line rows always pass; the segment count is the number of run
+    starts along every axis."""
+    p = maker()
+    asm = E.assemble(p.grid, p.psi)
+    segs, fail = spd.segment_check(asm.kind, *_records(asm))
+    assert segs == _runs_by_starts(asm.kind)
+    assert fail == 0
+
+
+def _axis_operator(kind, nodes_c, dirs_c, cs, asm):
+    """Sum over axes of the block-diagonal segment matrices that the records
+    describe (unknown order), built with the segment matrices directly."""
+    n = asm.n_unknowns
+    dims = kind.ndim
+    dirs = E.directions(dims)
+    strides = E._strides(kind.shape)
+    kflat = np.asarray(kind).ravel()
+    cmap = {(int(a), int(b)): float(c) for a, b, c in zip(nodes_c, dirs_c, cs)}
+    M = np.zeros((n, n))
+    for phys in range(dims):
+        sides = [sd for sd, (_, _, ph) in enumerate(dirs) if ph == phys]
+        for seg in spd.line_segments(asm.index, phys):
+            ends = []
+            for k in (seg[0], seg[-1]):
+                node = int(asm.nodes[k])
+                v = 0.0
+                for sd in sides:
+                    ax, step, _ = dirs[sd]
+                    nb = node + step * strides[ax]
+                    v = v + (1.0 if kflat[nb] == E.COMPUTATIONAL else cmap[(node, sd)])
+                ends.append(v)
+            D = spd.segment_matrix(seg.size, ends[0], ends[1])
+            M[np.ix_(seg, seg)] += D
+    return M
+
+
+@pytest.mark.parametrize("scale", [0.9, -0.3, -0.9])
+def test_segment_check_on_altered_records(scale):
+    """Records with c rescaled: whenever the check passes, the per-axis
+    operator the records describe is positive definite.  With positive c a
+    segment end is at least 1 + c (Corollary 1 holds); negative side
+    contributions (as interpolation rows with negative weights give) make
+    segments fail."""
+    p = W.disk_mms(16)
+    asm = E.assemble(p.grid, p.psi)
+    nodes, dirs, c = _records(asm)
+    c2 = c * scale
+    segs, fail = spd.segment_check(asm.kind, nodes, dirs, c2)
+    assert segs == _runs_by_starts(asm.kind)
+    lam = np.linalg.eigvalsh(_axis_operator(asm.kind, nodes, dirs, c2, asm))[0]
+    if fail == 0:
+        assert lam > 0
+    if scale > 0:
+        assert fail == 0
+    if scale == -0.9:
+        assert fail > 0
+
+
+def test_segment_check_detects_an_indefinite_segment():
+    """A column of three unknowns (y-segment, n = 3) whose outer y sides
+    contribute -0.7, so both segment ends are -0.7 + 1 = 0.3 < 1/2: Lemma 2.1
+    fails, and D^(3)(0.3, 0.3) indeed has a negative eigenvalue.  The three
+    x-segments (single nodes, two cut sides of 0.5) pass."""
+    kind = np.zeros((7, 3), dtype=np.int8)
+    kind[2:5, 1] = E.COMPUTATIONAL
+    nodes, dirs, cs = [], [], []
+    for j in (2, 3, 4):
+        for sd in (0, 1):                          # -x, +x: cut sides, c = 0.5
+            nodes.append(j * 3 + 1)
+            dirs.append(sd)
+            cs.append(0.5)
+    nodes += [2 * 3 + 1, 4 * 3 + 1]                # outer y sides of the end nodes
+    dirs += [2, 3]
+    cs += [-0.7, -0.7]
+    segs, fail = spd.segment_check(kind, nodes, dirs, cs)
+    assert segs == 4 and fail == 1
+    assert np.linalg.eigvalsh(spd.segment_matrix(3, 0.3, 0.3))[0] < 0

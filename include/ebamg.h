@@ -149,6 +149,25 @@ int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double
                      eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
                      int64_t* n_cuts, void* stream);
 
+/* A-priori SPD test (Sec. 2.4, Lemma 2.1, Theorems 1-2): along every axis,
+ * every maximal run of computational points on a grid line is one segment of
+ * the 1-D matrix D^(n)(a, b) whose end entries a, b are the part of the
+ * diagonal contributed by the two sides along that axis (1 for a
+ * computational neighbour, the record's c for a cut side).  Every segment
+ * satisfying Lemma 2.1 makes the operator SPD; a failing segment does not
+ * prove the contrary (the conditions are sufficient).  Rows built by the
+ * line-by-line treatment always pass (Corollary 1); the test is meant for
+ * rows whose side contributions come from elsewhere.
+ *   kind  [in]  node field from eb_assemble_diag.
+ *   cuts  [in]  all n_cuts records of that assembly (sorted by node, then
+ *               side), possibly with altered c.
+ *   n_segments, n_failing [host out] segments over all axes, and those that
+ *               fail Lemma 2.1.
+ * Synchronises `stream`.  EB_EINVAL when a cut side has no record or an
+ * unknown sits on the outer node layer.  Deterministic (integer counts).      */
+int eb_check_spd(const eb_grid_t* g, const int8_t* kind, const eb_cut_t* cuts, int64_t n_cuts,
+                 int64_t* n_segments, int64_t* n_failing, void* stream);
+
 /* Right-hand side of steps 2-3: b_k = f_k + sum over the cuts of k of
  * u_at_cuts[m] * c_m / h^2 (the g_Gamma u_Gamma / h^2 term of Sec. 2.1.1),
  * b = 0 off computational points.  f is a node field, u_at_cuts holds the

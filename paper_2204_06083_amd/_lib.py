@@ -24,6 +24,7 @@ EXPORTS = [
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
     "amg_smoother_samples", "amg_smoother_loss_grad", "eb_wave_rhs", "eb_stencil_combine",
     "pcg_solve_islands", "pcg_batched_set_launch_shape", "pcg_batched_launch_shape", "eb_set_iteration_graphs",
+    "eb_check_spd",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -88,6 +89,8 @@ def lib():
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     L.eb_assemble_diag.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.eb_assemble_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, vp, vp]
+    L.eb_check_spd.argtypes = [C.POINTER(EbGrid), vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
+    L.eb_check_spd.restype = i32
     L.stencil_apply.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, vp, vp, vp]
     L.eb_wave_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
     L.eb_stencil_combine.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, vp, dbl, vp, dbl, vp, vp, vp]

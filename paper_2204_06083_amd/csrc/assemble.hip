@@ -235,6 +235,106 @@ __global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restric
     y[n] = diag * x[n] - d.s * nb;
 }
 
+// ------------------------------------------------------------ SPD test
+// The a-priori test of Sec. 2.4: along every axis, each maximal run of
+// computational points on a grid line is one segment of the 1-D matrix
+// D^(n)(a, b) (Eq. (tridiag)), whose end entries a, b are the part of the
+// diagonal contributed by the two sides along that axis (1 per computational
+// neighbour, c per cut side; minus side first).  Lemma 2.1's conditions on
+// every segment make the operator SPD (Theorems 1-2).  The comparisons use
+// the same FP64 operations, without contraction, as a plain evaluation.
+__device__ inline bool lemma_2_1(int64_t n, double a, double b) {
+    if (n == 1) return a > 0.0;
+    if (n == 2) return a > 0.0 && a * b > 1.0;
+    const double lo = (double)(n - 2) / (double)(n - 1);
+    if (!(a > lo && b > lo)) return false;
+    return a > ((double)(n - 2) * b - (double)(n - 3)) / ((double)(n - 1) * b - (double)(n - 2));
+}
+
+// c of the record (node, side); records are sorted by node, a node's records
+// by side.  *miss is set when there is none.
+__device__ inline double cut_c_of(const eb_cut_t* __restrict__ cuts, int64_t n_cuts, int64_t node, int side,
+                                  int* miss) {
+    int64_t lo = 0, hi = n_cuts;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cuts[mid].node < node) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int64_t m = lo; m < n_cuts && cuts[m].node == node; ++m)
+        if (cuts[m].dir == side) return cuts[m].c;
+    *miss = 1;
+    return 0.0;
+}
+
+// One thread per grid line along `axis`; out = {segments, failing, missing}.
+__global__ void __launch_bounds__(BLOCK) k_spd_lines(const int8_t* __restrict__ kind, GridDims d, int axis,
+                                                     const eb_cut_t* __restrict__ cuts, int64_t n_cuts,
+                                                     unsigned long long* __restrict__ out) {
+    const int64_t line = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    const int64_t sy = d.sy, sz = d.sz;
+    int64_t nlines, len, step, base = 0;
+    if (axis == 0) {
+        nlines = ny * nz;
+        len = nx;
+        step = 1;
+        if (line < nlines) base = sy * (line % ny) + sz * (line / ny);
+    } else if (axis == 1) {
+        nlines = nx * nz;
+        len = ny;
+        step = sy;
+        if (line < nlines) base = (line % nx) + sz * (line / nx);
+    } else {
+        nlines = nx * ny;
+        len = nz;
+        step = sz;
+        if (line < nlines) base = line;
+    }
+    unsigned long long segs = 0, fails = 0;
+    int miss = 0;
+    if (line < nlines) {
+        int64_t run = 0;
+        double a = 0.0, last = 0.0;
+        for (int64_t t = 0; t <= len; ++t) {
+            const int64_t node = base + t * step;
+            if (t < len && kind[node] == 2) {
+                // 0 + (minus side) + (plus side).  An assembly never has an
+                // unknown on the outer layer; a field that does is refused
+                // (counted as missing) rather than read past the line
+                if (t == 0 || t == len - 1) {
+                    miss = 1;
+                    run = 0;
+                    continue;
+                }
+                double v = 0.0;
+                v = v + (kind[node - step] == 2 ? 1.0 : cut_c_of(cuts, n_cuts, node, 2 * axis, &miss));
+                v = v + (kind[node + step] == 2 ? 1.0 : cut_c_of(cuts, n_cuts, node, 2 * axis + 1, &miss));
+                if (run == 0) a = v;
+                last = v;
+                ++run;
+                continue;
+            }
+            if (run > 0) {
+                ++segs;
+                if (!lemma_2_1(run, a, last)) ++fails;
+                run = 0;
+            }
+        }
+    }
+    // integer sums: the same in any order
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        segs += __shfl_xor(segs, off);
+        fails += __shfl_xor(fails, off);
+        miss += __shfl_xor(miss, off);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0 && (segs || fails || miss)) {
+        atomicAdd(&out[0], segs);
+        atomicAdd(&out[1], fails);
+        atomicAdd(&out[2], (unsigned long long)miss);
+    }
+}
+
 // Device status of one assembly, read back once at the end.
 struct AsmStat {
     int32_t err;
@@ -303,6 +403,40 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
         set_error("cut-record capacity %lld < required %lld", (long long)cuts_cap, (long long)h.cuts);
         return EB_ENOSPC;
     }
+    return EB_OK;
+}
+
+extern "C" int eb_check_spd(const eb_grid_t* g, const int8_t* kind, const eb_cut_t* cuts, int64_t n_cuts,
+                            int64_t* n_segments, int64_t* n_failing, void* stream) {
+    clear_error();
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!kind || !n_segments || !n_failing || n_cuts < 0 || (n_cuts > 0 && !cuts)) {
+        set_error("eb_check_spd: null pointer or negative count");
+        return EB_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* out = nullptr;
+    EB_TRY(dalloc_n(&out, 3, s));
+    {
+        const FillSpec f[] = {{out, 3 * sizeof(unsigned long long), 0u}};
+        EB_TRY(fill_words(f, 1, s));
+    }
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t nlines = axis == 0 ? (int64_t)d.ny * d.nz : axis == 1 ? (int64_t)d.nx * d.nz : (int64_t)d.nx * d.ny;
+        hipLaunchKernelGGL(k_spd_lines, dim3(grid_for(nlines)), dim3(BLOCK), 0, s, kind, d, axis, cuts, n_cuts, out);
+        EB_LAUNCH_CHECK();
+    }
+    unsigned long long h[3] = {0, 0, 0};
+    EB_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    EB_TRY(dfree(out, s));
+    EB_HIP(hipStreamSynchronize(s));
+    if (h[2] > 0) {
+        set_error("eb_check_spd: %llu cut sides without a record or unknowns on the outer layer (pass the assembly's kind field and all its records)", h[2]);
+        return EB_EINVAL;
+    }
+    *n_segments = (int64_t)h[0];
+    *n_failing = (int64_t)h[1];
     return EB_OK;
 }
 

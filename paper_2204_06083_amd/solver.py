@@ -74,6 +74,20 @@ def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None) -> As
     return Assembly(grid, kind, a, cuts, nu.value, nc.value)
 
 
+def check_spd(asm: Assembly, cuts: Optional[torch.Tensor] = None) -> tuple:
+    """A-priori SPD test of the operator (eb_check_spd): (segments, failing).
+
+    cuts: the assembly's record buffer (default) or a copy with altered c."""
+    lib = L.lib()
+    g = L.make_grid(asm.grid)
+    buf = asm.cuts if cuts is None else cuts
+    ns, nf = C.c_int64(0), C.c_int64(0)
+    rc = lib.eb_check_spd(C.byref(g), C.c_void_p(asm.kind.data_ptr()), C.c_void_p(buf.data_ptr()),
+                          int(asm.n_cuts), C.byref(ns), C.byref(nf), _stream())
+    L.check(rc, "eb_check_spd")
+    return ns.value, nf.value
+
+
 def assemble_rhs(asm: Assembly, f: torch.Tensor, u_at_cuts: torch.Tensor) -> torch.Tensor:
     lib = L.lib()
     g = L.make_grid(asm.grid)

@@ -168,3 +168,23 @@ def test_iteration_graphs_match_kernel_launches(name, prec):
     finally:
         S.set_iteration_graphs(True)
         H.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_poll_cadence_does_not_change_the_solve(precision):
+    """The host sizes the chunks of iterations between polls from the
+    residual's reduction rate and may queue the true residual early; the
+    device work per iteration is the same, so solution and iteration count
+    are bitwise independent of the polling cadence."""
+    prob = W.star_poisson(400)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    print(f"[gpu] poll cadence {precision}", flush=True)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x_ref, i_ref = H.solve(b_g, tol=1e-9, precision=precision)
+    for ce in (1, 2, 5, 64):
+        x, i = H.solve(b_g, tol=1e-9, precision=precision, check_every=ce)
+        assert torch.equal(x, x_ref), ce
+        assert i["iterations"] == i_ref["iterations"] and i["status"] == 0, ce
+        assert i["rel_res_true"] == i_ref["rel_res_true"], ce
+    H.free()

@@ -98,6 +98,11 @@ struct BatchBufs {
     int ncand = 0;
     int cand_w[8] = {}, cand_n[8] = {};
     float cand_ms[8] = {};
+    // a captured pair of iterations (k odd >= 3, k + 1: the same launches for
+    // every such k), for the launch shape it was captured with
+    hipGraphExec_t it_graph = nullptr;
+    int it_graph_kbw = 0, it_graph_npb = 0;
+    hipStream_t cap_stream = nullptr;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -902,6 +907,8 @@ void free_batch(amg_handle* H, hipStream_t s) {
         (void)dfree(B->ev[l], s);
         (void)dfree(B->tmp[l], s);
     }
+    if (B->it_graph) (void)hipGraphExecDestroy(B->it_graph);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
     delete B->host;
     delete B;
     H->batch = nullptr;
@@ -1220,6 +1227,43 @@ static int benqueue_iteration(amg_handle* H, BatchBufs* B, int k, hipStream_t s)
     return EB_OK;
 }
 
+// Iterations k and k + 1 (k odd, k >= 3) as one replay of a captured graph;
+// captured on the first use and again after a change of launch shape, on a
+// private stream (the solve stream may be the null stream, which cannot
+// capture).  Kernel nodes only.
+template <class V>
+static int blaunch_iteration_pair(amg_handle* H, BatchBufs* B, hipStream_t s) {
+    if (!B->it_graph || B->it_graph_kbw != B->kbw || B->it_graph_npb != B->npb) {
+        if (B->it_graph) (void)hipGraphExecDestroy(B->it_graph);
+        B->it_graph = nullptr;
+        if (!B->cap_stream) EB_HIP(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = B->cap_stream;
+        hipGraph_t g = nullptr;
+        EB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int rc1 = benqueue_iteration<V>(H, B, 3, cs);
+        const int rc2 = rc1 == EB_OK ? benqueue_iteration<V>(H, B, 4, cs) : rc1;
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (rc2 != EB_OK || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            if (rc2 != EB_OK) return rc2;
+            set_error("batched iteration graph capture failed: %s", hipGetErrorString(ec));
+            return EB_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            set_error("batched iteration graph instantiation failed: %s", hipGetErrorString(ei));
+            return EB_EHIP;
+        }
+        B->it_graph = ex;
+        B->it_graph_kbw = B->kbw;
+        B->it_graph_npb = B->npb;
+    }
+    EB_HIP(hipGraphLaunch(B->it_graph, s));
+    return EB_OK;
+}
+
 // (Re)start for the slots whose mask is set: r0 = b - A x, norms, first V-cycle.
 template <class V>
 static int benqueue_start(amg_handle* H, BatchBufs* B, double tol, hipStream_t s) {
@@ -1285,8 +1329,18 @@ static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t
             }
             const int left = p.maxit - h.maxiter;
             const int chunk = left < p.check_every ? left : p.check_every;
-            for (int c = 0; c < chunk; ++c, ++enqueued) {
+            const bool graphs = iteration_graphs_enabled();
+            for (int c = 0; c < chunk;) {
+                if (graphs && k + 1 >= 3 && ((k + 1) & 1) && chunk - c >= 2) {
+                    EB_TRY(blaunch_iteration_pair<V>(H, B, s));
+                    k += 2;
+                    c += 2;
+                    enqueued += 2;
+                    continue;
+                }
                 ++k;
+                ++c;
+                ++enqueued;
                 EB_TRY(benqueue_iteration<V>(H, B, k, s));
             }
         }

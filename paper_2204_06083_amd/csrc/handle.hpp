@@ -140,7 +140,9 @@ struct amg_handle {
 
 namespace eb {
 int ensure_fp32(amg_handle* H, hipStream_t s);   // FP32 hierarchy copies (solve.hip)
-void free_batch(amg_handle* H, hipStream_t s);
+void free_batch(amg_handle* H, hipStream_t s);   // batched.hip
 // Destroys the captured iteration graphs of a handle (solve.hip).
-void drop_iteration_graphs(amg_handle* H);   // batched.hip
+void drop_iteration_graphs(amg_handle* H);
+// The eb_set_iteration_graphs switch, read by single and batched solves (solve.hip).
+bool iteration_graphs_enabled();
 }  // namespace eb

@@ -1117,6 +1117,8 @@ static int enqueue_iteration_any(amg_handle* H, int k, hipStream_t s) {
 // is kept on the handle, per V-cycle precision and fine-weight switch.
 static std::atomic<int> g_use_graphs{1};
 
+bool iteration_graphs_enabled() { return g_use_graphs.load() != 0; }
+
 void drop_iteration_graphs(amg_handle* H) {
     for (int i = 0; i < 2; ++i) {
         if (H->it_graph[i]) (void)hipGraphExecDestroy(H->it_graph[i]);

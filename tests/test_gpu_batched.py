@@ -177,3 +177,46 @@ def test_launch_shapes_agree_and_autotuner_reports():
             S.set_batched_launch_shape(12, 1)
     finally:
         S.set_batched_launch_shape(0, 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_iteration_graphs_match_kernel_launches(precision):
+    """Batched solves replay a captured pair of iterations: bitwise the same
+    solutions and iteration counts as launching kernel by kernel, on the
+    first replay, on a later solve, after a change of launch shape (the graph
+    is captured again) and on a stream of the caller's."""
+    prob = W.star_heat(512, 0)
+    asm_o, A, fields, asm_g, B = _rhs_family(prob, 6, seed=21)
+    Bd = to_dev(B)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    try:
+        S.set_iteration_graphs(False)
+        X0, i0 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        S.set_iteration_graphs(True)
+        X1, i1 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        X2, i2 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            X3, i3 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        st.synchronize()
+        print(f"[gpu] batched graphs {precision}: iterations {[i['iterations'] for i in i0]} "
+              f"solve ms {i0[0]['solve_ms']:.2f} -> {i2[0]['solve_ms']:.2f}", flush=True)
+        assert min(i["iterations"] for i in i0) >= 4
+        for X, ii in ((X1, i1), (X2, i2), (X3, i3)):
+            assert torch.equal(X, X0)
+            assert [i["iterations"] for i in ii] == [i["iterations"] for i in i0]
+            assert all(i["status"] == 0 for i in ii)
+        H.free()
+        # another launch shape: kernel by kernel against a fresh capture
+        S.set_batched_launch_shape(8, 2)
+        H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+        S.set_iteration_graphs(False)
+        X4, i4 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        S.set_iteration_graphs(True)
+        X5, i5 = H.solve_batched(Bd, tol=1e-10, precision=precision)
+        assert torch.equal(X5, X4) and [i["iterations"] for i in i5] == [i["iterations"] for i in i4]
+        assert rel(X4.cpu().numpy().ravel(), X0.cpu().numpy().ravel()) <= (1e-12 if precision == "fp64" else 1e-6)
+    finally:
+        S.set_iteration_graphs(True)
+        S.set_batched_launch_shape(0, 0)
+        H.free()

@@ -168,3 +168,26 @@ def test_shape_optimisation_batch_sample():
             assert d <= 4e-7
         Hg.free()
     H.free()
+
+
+def test_island_iteration_graphs_match_kernel_launches():
+    """Island batches replay captured iteration pairs: bitwise the same
+    solutions and iteration counts as launching kernel by kernel."""
+    geoms = _stars([64, 96, 128], seed=13)
+    canvas, asm_c, B = _canvas_system(geoms, 4)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    try:
+        S.set_iteration_graphs(False)
+        X0, i0 = S.solve_islands(H, B, canvas.rows, tol=1e-10)
+        S.set_iteration_graphs(True)
+        X1, i1 = S.solve_islands(H, B, canvas.rows, tol=1e-10)
+        X2, i2 = S.solve_islands(H, B, canvas.rows, tol=1e-10)
+        its = [[i["iterations"] for i in seg] for seg in i0]
+        print(f"[gpu] island graphs: iterations {its}", flush=True)
+        assert min(min(r) for r in its) >= 4
+        for X, ii in ((X1, i1), (X2, i2)):
+            assert torch.equal(X, X0)
+            assert [[i["iterations"] for i in seg] for seg in ii] == its
+    finally:
+        S.set_iteration_graphs(True)
+        H.free()

@@ -16,6 +16,7 @@ Modules
   learned      the learned fine-smoother extension: network, weighted cycle,
                loss and gradients
   steppers     theta-scheme (wave) and Crank-Nicolson (heat) time steppers
+  qoi          quantities of interest over a family of geometries (Sec. 3.6)
 
 Parity status per function is stated in each module header.
 """

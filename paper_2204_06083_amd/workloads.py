@@ -331,3 +331,67 @@ def heat_cn_exact(X, Y, t: float):
 
 def heat_cn_source(X, Y, t: float):
     return -heat_cn_exact(X, Y, t) - 4.0 * math.exp(-t)
+
+
+# ------------------------------------------------- shape-parameter QOI studies
+#
+# Sec. 3.6: Poisson problems (beta = 1, zero Dirichlet data, source 3 in the
+# paper's convention div(beta grad u) = f, i.e. f = -3 for -Lap u = f here)
+# on one grid for a family of geometries, each giving one quantity of interest.
+
+QOI_SOURCE = -3.0
+
+
+def qoi_ellipse_grid(n: int = 1024) -> Grid:
+    """Box [-2.2, 2.2]^2 with n (even) cells per side: the origin is a node and
+    every ellipse of the family (semi-axes up to 2) lies inside."""
+    if n % 2:
+        raise ValueError("n must be even")
+    return Grid(dim=2, n=(n, n), x0=(-2.2, -2.2), h=4.4 / n)
+
+
+def psi_area_ellipse(grid: Grid, a: float) -> np.ndarray:
+    """x^2/a^2 + y^2 a^2 - 1 (semi-axes a and 1/a, area pi for every a)."""
+    X, Y = grid.mesh()
+    return X * X / (a * a) + Y * Y * (a * a) - 1.0
+
+
+def qoi_ellipse_params(count: int = 61):
+    """a on [0.5, 2], equally spaced."""
+    return np.linspace(0.5, 2.0, count)
+
+
+def qoi_rotated_grid() -> Grid:
+    """501 x 501 nodes on [-5, 5]^2 (h = 0.02; the origin is node (250, 250))."""
+    return Grid(dim=2, n=(500, 500), x0=(-5.0, -5.0), h=0.02)
+
+
+def psi_rotated_ellipse(grid: Grid, theta: float) -> np.ndarray:
+    """Ellipse with semi-axes 4 and 2 rotated by theta."""
+    X, Y = grid.mesh()
+    c, s = math.cos(theta), math.sin(theta)
+    return (X * c - Y * s) ** 2 / 16.0 + (X * s + Y * c) ** 2 / 4.0 - 1.0
+
+
+def qoi_rotated_params(count: int = 64):
+    """theta on [0, 2 pi), equally spaced."""
+    return np.arange(count) * (2.0 * math.pi / count)
+
+
+def qoi_rectangle_weights(grid: Grid, rect=((-1.0, 1.0), (-0.5, 0.5))) -> np.ndarray:
+    """Node weights of the composite trapezoid rule over an axis-aligned
+    rectangle whose sides lie on grid lines (h^2 times 1, 1/2 on an edge, 1/4 at
+    a corner; zero outside).  The quantity of interest int u is w . u."""
+    h = grid.h
+    w1 = []
+    for axis, (lo, hi) in enumerate(rect):
+        i0 = (lo - grid.x0[axis]) / h
+        i1 = (hi - grid.x0[axis]) / h
+        if abs(i0 - round(i0)) > 1e-9 or abs(i1 - round(i1)) > 1e-9:
+            raise ValueError("rectangle sides must lie on grid lines")
+        i0, i1 = int(round(i0)), int(round(i1))
+        w = np.zeros(grid.n[axis] + 1)
+        w[i0:i1 + 1] = 1.0
+        w[i0] = w[i1] = 0.5
+        w1.append(w * h)
+    return w1[1][:, None] * w1[0][None, :]

@@ -24,8 +24,10 @@ on the GPU at 96^3), both V-cycle precisions.  `islands` runs the
 shape-optimisation batch (256 random stars, N in {256 .. 1024}, 4 sources
 each) as one island solve (pcg_solve_islands: one canvas, one hierarchy,
 one launch sequence; timed from assembly to solution) and geometry by
-geometry.  `cpu_baseline` times the CPU oracle on full steps of the same
-workload.
+geometry.  `qoi` runs the two shape-parameter studies of Sec. 3.6 (61
+fixed-area ellipses at 1024^2, 64 rotated ellipses on the 501^2 grid), each
+as one island batch from level sets to quantities of interest.
+`cpu_baseline` times the CPU oracle on full steps of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -285,6 +287,63 @@ def shape_opt_islands(count=256, nrhs=4, reps=2):
     return out
 
 
+def qoi_studies(reps=2):
+    """The two shape-parameter studies of Sec. 3.6, each one island batch from
+    the level sets (in HBM) to the quantities of interest: u(0, 0) on the
+    fixed-area ellipses (1024^2 cells on [-2.2, 2.2]^2, 61 values of a in
+    [0.5, 2]) and the integral of u over [-1, 1] x [-0.5, 0.5] under the
+    rotated ellipse (the paper's 501^2 grid of [-5, 5]^2, 64 angles), with
+    the closed form, symmetry and smoothness figures of each."""
+    import numpy as np
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    out = {}
+    g = W.qoi_ellipse_grid(1024)
+    a = W.qoi_ellipse_params(61)
+    wc = np.zeros(g.shape)
+    wc[g.n[1] // 2, g.n[0] // 2] = 1.0
+    studies = {
+        "ellipse_u00": (g, [W.psi_area_ellipse(g, x) for x in a], wc, a),
+    }
+    g2 = W.qoi_rotated_grid()
+    th = W.qoi_rotated_params(64)
+    studies["rotated_ellipse_rect_integral"] = (g2, [W.psi_rotated_ellipse(g2, x) for x in th],
+                                                W.qoi_rectangle_weights(g2), th)
+    for name, (grid, psis, w, par) in studies.items():
+        f = np.full(grid.shape, W.QOI_SOURCE)
+        S.qoi_study(grid, psis, f, w, tol=1e-10)              # warm-up
+        best = None
+        for _ in range(reps):
+            q, infos, t = S.qoi_study(grid, psis, f, w, tol=1e-10)
+            best = t if best is None or t["device_ms"] < best["device_ms"] else best
+        its = [i["iterations"] for i in infos]
+        step = float(par[1] - par[0])
+        d = (q[2:] - q[:-2]) / (2.0 * step)
+        r = {"grid_nodes": f"{grid.shape[1]}x{grid.shape[0]}", "geometries": len(psis),
+             "n_unknowns": best["n_unknowns"], "levels": best["levels"], "device_ms": best["device_ms"],
+             "solves_per_s": len(psis) / (best["device_ms"] * 1e-3),
+             "iterations_min_max": [min(its), max(its)],
+             "all_converged": all(i["status"] == 0 for i in infos),
+             "qoi_min_max": [float(q.min()), float(q.max())],
+             "derivative_abs_max": float(np.abs(d).max()),
+             "second_difference_abs_max": float(np.abs(np.diff(q, 2)).max())}
+        if name == "ellipse_u00":
+            exact = -3.0 / (2.0 * (a * a + 1.0 / (a * a)))
+            r["max_abs_error_vs_closed_form"] = float(np.abs(q - exact).max())
+            r["argmin_a"] = float(a[np.argmin(q)])
+            r["symmetry_a_inv_a_max_rel"] = float(max(abs(q[i] - q[j]) / abs(q[i])
+                                                      for i, j in ((0, 60), (12, 30), (5, 44))))
+        else:
+            # theta and 2 pi - theta, theta and theta + pi (angles on the lattice excluded)
+            m = len(par)
+            pairs = [(k, m - k) for k in range(1, m // 2) if k % (m // 8)]
+            r["symmetry_theta_minus_theta_max_rel"] = float(max(abs(q[i] - q[j]) / abs(q[i]) for i, j in pairs))
+            pairs = [(k, k + m // 2) for k in range(m // 2) if k % (m // 8)]
+            r["symmetry_theta_plus_pi_max_rel"] = float(max(abs(q[i] - q[j]) / abs(q[i]) for i, j in pairs))
+        out[name] = r
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +354,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched heat-step measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the 3-D learned-smoother measurement")
     ap.add_argument("--no-islands", action="store_true", help="skip the shape-optimisation island batch")
+    ap.add_argument("--no-qoi", action="store_true", help="skip the shape-parameter QOI studies")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -646,6 +706,8 @@ def main():
         out["learned_3d"] = learned_ellipsoid()
     if not args.no_islands:
         out["islands"] = shape_opt_islands()
+    if not args.no_qoi:
+        out["qoi"] = qoi_studies()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

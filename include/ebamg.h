@@ -205,6 +205,19 @@ int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, 
                        const double* x, double beta, const double* y, double gamma, const double* z, double* out,
                        void* stream);
 
+/* Linear quantities of interest over the islands of a canvas (Sec. 3.6: the
+ * value of u at a node, the integral of u over a region, as w . u with node
+ * weights w).  out[j * nseg + s] = sum of w[n] x[j * field_nodes + n] over the
+ * nodes n of node rows seg_rows[s] .. seg_rows[s+1] - 1 (row_len nodes a row),
+ * for the nfields fields stored back to back in x.  w (field_nodes doubles)
+ * and x (nfields * field_nodes doubles) are device arrays; seg_rows (nseg + 1
+ * non-decreasing row indices, the last at most field_nodes / row_len) and out
+ * (nfields * nseg doubles) are host arrays.  Sums are taken in a fixed order
+ * (run-to-run identical).  1 <= nfields, nseg <= 65535; EB_EINVAL for null
+ * pointers or segments outside the field.  Synchronises `stream`.             */
+int eb_segment_dots(const double* w, const double* x, int32_t nfields, int64_t field_nodes, int64_t row_len,
+                    int32_t nseg, const int32_t* seg_rows, double* out, void* stream);
+
 /* Build the aggregation AMG hierarchy of A (+ sigma I) on the device
  * (Algorithm 2 step 4 preconditioner).  *H receives a new handle (host).
  * p may be NULL for defaults.  Synchronises `stream` (level sizes are read

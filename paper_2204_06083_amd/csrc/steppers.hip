@@ -4,6 +4,9 @@
 // stencil_apply, A v = (1/h^2)(a v - sum of v over computational neighbours).
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 
 namespace eb {
@@ -60,9 +63,107 @@ __global__ void __launch_bounds__(BLOCK) k_stencil_combine(const int8_t* __restr
     out[n] = r;
 }
 
+// ------------------------------------------------ per-island weighted sums
+// Linear quantities of interest w . u of several solutions over the islands
+// of a canvas (Sec. 3.6: the value at a node, the integral over a region).
+// Pass 1: block (c, s, j) sums w * x over chunk c (SEG_CHUNK consecutive
+// nodes) of segment s of field j; pass 2: one block per (j, s) adds its
+// chunks' partials.  Every sum is taken in a fixed order.
+constexpr int SEG_NT = 256;
+constexpr int SEG_PER_THREAD = 8;
+constexpr int64_t SEG_CHUNK = (int64_t)SEG_NT * SEG_PER_THREAD;
+
+__global__ void __launch_bounds__(SEG_NT) k_seg_partials(const double* __restrict__ w, const double* __restrict__ x,
+                                                         int64_t field_nodes, const int64_t* __restrict__ seg_lo,
+                                                         const int64_t* __restrict__ seg_hi, int nseg, int nchunk,
+                                                         double* __restrict__ part) {
+    __shared__ double lds[SEG_NT / WAVE];
+    const int c = blockIdx.x, sg = blockIdx.y, j = blockIdx.z;
+    const int64_t lo = seg_lo[sg] + (int64_t)c * SEG_CHUNK;
+    const int64_t hi = min(seg_hi[sg], lo + SEG_CHUNK);
+    const double* xj = x + (int64_t)j * field_nodes;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < SEG_PER_THREAD; ++k) {
+        const int64_t n = lo + (int64_t)k * SEG_NT + threadIdx.x;
+        if (n < hi) v = fma(w[n], xj[n], v);
+    }
+    const double t = block_sum<SEG_NT>(v, lds);
+    if (threadIdx.x == 0) part[((int64_t)j * nseg + sg) * nchunk + c] = t;
+}
+
+__global__ void __launch_bounds__(SEG_NT) k_seg_final(const double* __restrict__ part, int nchunk,
+                                                      double* __restrict__ out) {
+    __shared__ double lds[SEG_NT / WAVE];
+    const int64_t js = blockIdx.x;
+    double v = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += SEG_NT) v += part[js * nchunk + c];
+    const double t = block_sum<SEG_NT>(v, lds);
+    if (threadIdx.x == 0) out[js] = t;
+}
+
 }  // namespace eb
 
 using namespace eb;
+
+extern "C" int eb_segment_dots(const double* w, const double* x, int32_t nfields, int64_t field_nodes,
+                               int64_t row_len, int32_t nseg, const int32_t* seg_rows, double* out, void* stream) {
+    clear_error();
+    if (!w || !x || !seg_rows || !out) {
+        set_error("eb_segment_dots: null pointer");
+        return EB_EINVAL;
+    }
+    if (nfields < 1 || nfields > 65535 || nseg < 1 || nseg > 65535 || row_len < 1 || field_nodes < 1) {
+        set_error("eb_segment_dots: need 1 <= nfields, nseg <= 65535 and positive row_len, field_nodes");
+        return EB_EINVAL;
+    }
+    std::vector<int64_t> lohi(2 * (size_t)nseg);
+    int64_t longest = 0;
+    for (int s = 0; s < nseg; ++s) {
+        const int64_t r0 = seg_rows[s], r1 = seg_rows[s + 1];
+        if (r0 < 0 || r1 < r0 || r1 * row_len > field_nodes) {
+            set_error("eb_segment_dots: segment %d rows [%lld, %lld) outside the field", s, (long long)r0,
+                      (long long)r1);
+            return EB_EINVAL;
+        }
+        lohi[s] = r0 * row_len;
+        lohi[nseg + s] = r1 * row_len;
+        longest = std::max(longest, (r1 - r0) * row_len);
+    }
+    const int64_t nchunk64 = std::max<int64_t>(1, (longest + SEG_CHUNK - 1) / SEG_CHUNK);
+    if (nchunk64 > INT32_MAX) {
+        set_error("eb_segment_dots: segment too long");
+        return EB_EINVAL;
+    }
+    const int nchunk = (int)nchunk64;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nout = (int64_t)nfields * nseg;
+    int64_t* dlohi = nullptr;
+    double* part = nullptr;
+    EB_TRY(dalloc_n(&dlohi, 2 * (int64_t)nseg, s));
+    int rc = dalloc_n(&part, nout * nchunk + nout, s);
+    if (rc == EB_OK) {
+        double* dout = part + nout * nchunk;
+        if (hipMemcpyAsync(dlohi, lohi.data(), sizeof(int64_t) * lohi.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess) {
+            set_error("eb_segment_dots: copy to the device failed");
+            rc = EB_EHIP;
+        } else {
+            hipLaunchKernelGGL(k_seg_partials, dim3(nchunk, nseg, nfields), dim3(SEG_NT), 0, s, w, x, field_nodes,
+                               dlohi, dlohi + nseg, nseg, nchunk, part);
+            hipLaunchKernelGGL(k_seg_final, dim3((unsigned)nout), dim3(SEG_NT), 0, s, part, nchunk, dout);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(out, dout, sizeof(double) * nout, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("eb_segment_dots: kernel launch or copy failed");
+                rc = EB_EHIP;
+            }
+        }
+    }
+    (void)dfree(part, s);
+    (void)dfree(dlohi, s);
+    return rc;
+}
 
 extern "C" int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double theta, double dt,
                            double scale, const double* un, const double* unm1, double* out, void* stream) {

@@ -434,6 +434,58 @@ def solve_islands(H: "Hierarchy", b: torch.Tensor, rows, x0: Optional[torch.Tens
     return x, [[_result_dict(res[s * nrhs + j]) for j in range(nrhs)] for s in range(nseg)]
 
 
+def segment_dots(w: torch.Tensor, x: torch.Tensor, rows) -> np.ndarray:
+    """eb_segment_dots: w . x_j over the node rows of every island for every
+    field x_j of x (shape (nfields, *canvas shape)); w is one canvas node
+    field.  Returns a numpy array [nfields, nseg]."""
+    if x.dim() != w.dim() + 1:
+        raise ValueError("x must have shape (nfields, *w.shape)")
+    shape = tuple(w.shape)
+    nf = x.shape[0]
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+    nseg = rows.size - 1
+    wp = _field(w, shape, torch.float64, "w")
+    xp = _field(x, (nf,) + shape, torch.float64, "x")
+    out = np.zeros(nf * nseg, dtype=np.float64)
+    rc = L.lib().eb_segment_dots(wp, xp, int(nf), int(np.prod(shape)), int(shape[-1]), int(nseg),
+                                 rows.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 out.ctypes.data_as(C.POINTER(C.c_double)), _stream())
+    L.check(rc, "eb_segment_dots")
+    return out.reshape(nf, nseg)
+
+
+def qoi_study(grid, psis, f, weights, tol: float = 1e-10, precision: str = "fp64", device="cuda"):
+    """Quantity of interest of a family of geometries on one 2-D grid (Sec. 3.6):
+    Q_k = w . u_k, u_k the solution of -Lap u = f on {psis[k] < 0} with zero
+    Dirichlet data.  The geometries are stacked as islands of one canvas and
+    solved together (eb_assemble_diag, eb_assemble_rhs, amg_setup,
+    pcg_solve_islands); the functional is eb_segment_dots.  Returns (Q, infos)
+    with infos[k] the solve result of geometry k and the phase times."""
+    import time
+    K = len(psis)
+    canvas = stack_islands([grid] * K)
+    t0 = time.perf_counter()
+    psi_c = torch.from_numpy(canvas.pack(psis, fill=1.0)).to(device)
+    f_c = torch.from_numpy(canvas.pack([f] * K, scale_h2=True)).to(device)
+    w_c = torch.from_numpy(canvas.pack([weights] * K)).to(device)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    asm = assemble_diag(canvas.grid, psi_c)
+    b = assemble_rhs(asm, f_c, torch.zeros(asm.n_cuts, dtype=torch.float64, device=device))
+    H = Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
+    try:
+        X, infos = solve_islands(H, b[None].contiguous(), canvas.rows, tol=tol, precision=precision)
+        Q = segment_dots(w_c, X, canvas.rows)[0]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        levels = H.n_levels
+    finally:
+        H.free()
+    times = {"upload_ms": 1e3 * (t1 - t0), "device_ms": 1e3 * (t2 - t1), "levels": levels,
+             "n_unknowns": int(asm.n_unknowns)}
+    return Q, [i[0] for i in infos], times
+
+
 def set_iteration_graphs(enabled: bool = True):
     """Launch steady-state PCG iterations as captured HIP graphs (default) or
     kernel by kernel (process-wide switch; results are identical)."""

@@ -95,10 +95,67 @@ __global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__
 // interpolation of psi between the last inside and first outside node on the
 // grid line (Sec. 3.3); when the node two steps out is still inside, the line
 // is followed to the first outside node.
+// Walks that do not end within the first DIAG_SHORT nodes (a boundary running
+// almost along the grid line: up to about a thousand nodes on the 2048^2
+// star) would leave one thread walking long after the rest of the grid is
+// done, so k_diag_cuts hands such nodes to k_diag_long, where a workgroup
+// examines DIAG_LONG_NT nodes of the line per round.  Both kernels compute the
+// node's diagonal and records with the same expressions in the same side
+// order (diag_side), so the result does not depend on which one did it.
+constexpr int DIAG_WALK = 8;                  // nodes read together per round
+constexpr int DIAG_SHORT = 2 * DIAG_WALK;     // nodes a thread examines before deferring
+constexpr int DIAG_DEFER_CAP = 4096;          // deferred nodes (more: walked in place)
+constexpr int DIAG_LONG_NT = 256;
+constexpr int DIAG_LONG_BLOCKS = 64;
+
+// The side's interpolation coefficient c = 1/q from the walk's end j (first
+// outside node, j >= 2), and its cut record m (if below the capacity).
+__device__ inline double diag_side(const double* __restrict__ psi, int64_t n, const NodePos& p, const GridDims& d,
+                                   int side, int j, int64_t m, eb_cut_t* __restrict__ cuts, int64_t cap) {
+    const int axis = side >> 1;
+    const int step = (side & 1) ? 1 : -1;
+    const int64_t st = axis_stride(d, axis) * step;
+    const double psi_in = psi[n + (int64_t)(j - 1) * st];
+    const double psi_out = psi[n + (int64_t)j * st];
+    const double t = psi_in / (psi_in - psi_out);
+    const double q = (double)(j - 1) + t;
+    const double c = 1.0 / q;
+    if (m < cap) {
+        eb_cut_t rec;
+        rec.node = n;
+        rec.dir = side;
+        rec.steps = j;
+        rec.q = q;
+        rec.c = c;
+        double xg[3];
+        xg[0] = d.x0 + (double)p.i * d.h;
+        xg[1] = d.y0 + (double)p.j * d.h;
+        xg[2] = d.dim == 3 ? d.z0 + (double)p.k * d.h : 0.0;
+        const double qh = q * d.h;
+        xg[axis] = step > 0 ? xg[axis] + qh : xg[axis] - qh;
+        rec.xg[0] = xg[0];
+        rec.xg[1] = xg[1];
+        rec.xg[2] = xg[2];
+        cuts[m] = rec;
+    }
+    return c;
+}
+
+__device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, const GridDims& d) {
+    int nreg = 0;
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t st = axis_stride(d, axis);
+        nreg += kind[n - st] == 2;
+        nreg += kind[n + st] == 2;
+    }
+    return nreg;
+}
+
 __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ psi, const int8_t* __restrict__ kind,
                                                      GridDims d, int64_t nnodes, const int64_t* __restrict__ cut_off,
                                                      double* __restrict__ a, eb_cut_t* __restrict__ cuts,
-                                                     int64_t cap, int32_t* __restrict__ err) {
+                                                     int64_t cap, int32_t* __restrict__ err,
+                                                     int32_t* __restrict__ ndefer, int64_t* __restrict__ defer) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= nnodes) return;
     // A domain that reaches the outer layer (flagged by k_classify, final by
@@ -111,13 +168,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         return;
     }
     const NodePos p = node_pos(n, d);
-    int nreg = 0;
-    for (int axis = 0; axis < d.dim; ++axis) {
-        const int64_t st = axis_stride(d, axis);
-        nreg += kind[n - st] == 2;
-        nreg += kind[n + st] == 2;
-    }
-    double acc = (double)nreg;
+    double acc = (double)diag_regular(kind, n, d);
     int64_t m = cut_off[n];
     for (int side = 0; side < 2 * d.dim; ++side) {
         const int axis = side >> 1;
@@ -126,23 +177,33 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         if (kind[n + st] == 2) continue;
         const int pos = axis_coord(p, axis);
         const int len = axis_len(d, axis);
-        // walk to the first outside node; the outermost layer is outside.
-        // Where the boundary runs almost along the line the walk is long, so
-        // the nodes are read WALK at a time (all loads in flight, none past
-        // the outer layer) and then examined in order.
-        constexpr int WALK = 8;
+        // walk to the first outside node (the outermost layer is outside),
+        // DIAG_WALK nodes at a time: all loads in flight, none past the outer
+        // layer, then examined in order
         int j = 2;
         bool found = false;
+        bool deferred = false;
         while (!found) {
-            double v[WALK];
+            if (j >= 2 + DIAG_SHORT && !deferred) {
+                deferred = true;              // once only; list full: keep walking here
+                // (the count stops growing once the list is full)
+                if (*(volatile int32_t*)ndefer < DIAG_DEFER_CAP) {
+                    const int slot = atomicAdd(ndefer, 1);
+                    if (slot < DIAG_DEFER_CAP) {
+                        defer[slot] = n;      // the whole node is redone there
+                        return;
+                    }
+                }
+            }
+            double v[DIAG_WALK];
 #pragma unroll
-            for (int u = 0; u < WALK; ++u) {
+            for (int u = 0; u < DIAG_WALK; ++u) {
                 // clamped to the outer layer: the examination below stops there
                 const int at = min(max(pos + (j + u) * step, 0), len - 1);
                 v[u] = psi[n + (int64_t)(at - pos) * axis_stride(d, axis)];
             }
 #pragma unroll
-            for (int u = 0; u < WALK; ++u) {
+            for (int u = 0; u < DIAG_WALK; ++u) {
                 if (found) continue;
                 const int at = pos + (j + u) * step;
                 if (at <= 0 || at >= len - 1) {
@@ -154,35 +215,66 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
                     found = true;
                 }
             }
-            if (!found) j += WALK;
+            if (!found) j += DIAG_WALK;
         }
-        const double psi_in = psi[n + (int64_t)(j - 1) * st];
-        const double psi_out = psi[n + (int64_t)j * st];
-        const double t = psi_in / (psi_in - psi_out);
-        const double q = (double)(j - 1) + t;
-        const double c = 1.0 / q;
-        acc = acc + c;
-        if (m < cap) {
-            eb_cut_t rec;
-            rec.node = n;
-            rec.dir = side;
-            rec.steps = j;
-            rec.q = q;
-            rec.c = c;
-            double xg[3];
-            xg[0] = d.x0 + (double)p.i * d.h;
-            xg[1] = d.y0 + (double)p.j * d.h;
-            xg[2] = d.dim == 3 ? d.z0 + (double)p.k * d.h : 0.0;
-            const double qh = q * d.h;
-            xg[axis] = step > 0 ? xg[axis] + qh : xg[axis] - qh;
-            rec.xg[0] = xg[0];
-            rec.xg[1] = xg[1];
-            rec.xg[2] = xg[2];
-            cuts[m] = rec;
-        }
+        acc = acc + diag_side(psi, n, p, d, side, j, m, cuts, cap);
         ++m;
     }
     a[n] = acc;
+}
+
+// The deferred nodes, one workgroup each at a time: per side, the workgroup
+// reads DIAG_LONG_NT consecutive nodes of the line per round and takes the
+// first that ends the walk (the same test as the thread's walk: an outside
+// node, or the outer layer); thread 0 then adds the sides in order.
+__global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __restrict__ psi,
+                                                            const int8_t* __restrict__ kind, GridDims d,
+                                                            const int64_t* __restrict__ cut_off,
+                                                            double* __restrict__ a, eb_cut_t* __restrict__ cuts,
+                                                            int64_t cap, int32_t* __restrict__ err,
+                                                            const int32_t* __restrict__ ndefer,
+                                                            const int64_t* __restrict__ defer) {
+    __shared__ int first;
+    if (*err & DEVERR_DOMAIN) return;
+    const int count = min(*ndefer, DIAG_DEFER_CAP);
+    const int tid = threadIdx.x;
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t n = defer[i];
+        const NodePos p = node_pos(n, d);
+        double acc = (double)diag_regular(kind, n, d);
+        int64_t m = cut_off[n];
+        for (int side = 0; side < 2 * d.dim; ++side) {
+            const int axis = side >> 1;
+            const int step = (side & 1) ? 1 : -1;
+            const int64_t st = axis_stride(d, axis) * step;
+            if (kind[n + st] == 2) continue;
+            const int pos = axis_coord(p, axis);
+            const int len = axis_len(d, axis);
+            int j0 = 2;
+            int f;
+            bool edge = false;
+            double v = 0.0;
+            while (true) {
+                const int at = pos + (j0 + tid) * step;
+                const int atc = min(max(at, 0), len - 1);
+                v = psi[n + (int64_t)(atc - pos) * axis_stride(d, axis)];
+                edge = at <= 0 || at >= len - 1;
+                const bool hit = edge || !(v < 0.0);
+                if (tid == 0) first = DIAG_LONG_NT;
+                __syncthreads();
+                if (hit) atomicMin(&first, tid);
+                __syncthreads();
+                f = first;
+                __syncthreads();
+                if (f < DIAG_LONG_NT) break;   // the outer layer ends every line: reached within len rounds
+                j0 += DIAG_LONG_NT;
+            }
+            if (tid == f && edge && v < 0.0) atomicOr(err, DEVERR_DOMAIN);
+            if (tid == 0) acc = acc + diag_side(psi, n, p, d, side, j0 + f, m, cuts, cap);
+            ++m;
+        }
+        if (tid == 0) a[n] = acc;
+    }
 }
 
 // ------------------------------------------------------------ right-hand side
@@ -338,7 +430,7 @@ __global__ void __launch_bounds__(BLOCK) k_spd_lines(const int8_t* __restrict__ 
 // Device status of one assembly, read back once at the end.
 struct AsmStat {
     int32_t err;
-    int32_t pad;
+    int32_t ndefer;               // nodes handed from k_diag_cuts to k_diag_long
     int64_t cuts;                 // total cut records (scan total)
     unsigned long long unknowns;  // interior nodes
 };
@@ -367,8 +459,10 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     int32_t* ncut = nullptr;
     int64_t* off = nullptr;
     int32_t* blk_unk = nullptr;
+    int64_t* defer = nullptr;
     const unsigned nblk = grid_for(nn);
     EB_TRY(dalloc_n(&st, 1, s));
+    EB_TRY(dalloc_n(&defer, DIAG_DEFER_CAP, s));
     EB_TRY(dalloc_n(&ncut, nn, s));
     EB_TRY(dalloc_n(&off, nn, s));
     EB_TRY(dalloc_n(&blk_unk, nblk, s));
@@ -384,7 +478,9 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     EB_LAUNCH_CHECK();
     EB_TRY(scan_i32_to_i64_dev(ncut, off, nn, &st->cuts, s));
     hipLaunchKernelGGL(k_diag_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, off, a, cuts, cuts_cap,
-                       &st->err);
+                       &st->err, &st->ndefer, defer);
+    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, off, a, cuts,
+                       cuts_cap, &st->err, &st->ndefer, defer);
     EB_LAUNCH_CHECK();
     AsmStat h;
     EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));
@@ -392,6 +488,7 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     EB_TRY(dfree(ncut, s));
     EB_TRY(dfree(off, s));
     EB_TRY(dfree(blk_unk, s));
+    EB_TRY(dfree(defer, s));
     EB_HIP(hipStreamSynchronize(s));
     if (h.err & DEVERR_DOMAIN) {
         set_error("the domain reaches the outermost node layer (psi < 0 there)");

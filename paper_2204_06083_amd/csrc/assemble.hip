@@ -16,8 +16,7 @@ namespace eb {
 // neighbour; computational point = inside with all 2d neighbours inside.
 __global__ void __launch_bounds__(BLOCK) k_classify(const double* __restrict__ psi, int8_t* __restrict__ kind,
                                                     GridDims d, int64_t nnodes, int32_t* __restrict__ err,
-                                                    int32_t* __restrict__ block_unknowns,
-                                                    int32_t* __restrict__ ncut) {
+                                                    int32_t* __restrict__ block_unknowns) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const bool active = n < nnodes;
     int8_t kd = 0;
@@ -41,7 +40,6 @@ __global__ void __launch_bounds__(BLOCK) k_classify(const double* __restrict__ p
             }
         }
         kind[n] = kd;
-        ncut[n] = 0;  // sides are counted once kinds are known (k_count_cuts)
     }
     // unknowns per workgroup, summed afterwards by k_sum_counts (no atomics)
     __shared__ int32_t wcount[BLOCK / WAVE];
@@ -71,10 +69,8 @@ __global__ void __launch_bounds__(1024) k_sum_counts(const int32_t* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, GridDims d, int64_t nnodes,
-                                                      int32_t* __restrict__ ncut) {
-    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (n >= nnodes) return;
+// Cut sides of an unknown (neighbours that are not unknowns); 0 elsewhere.
+__device__ inline int node_cuts(const int8_t* __restrict__ kind, int64_t n, const GridDims& d) {
     int c = 0;
     if (kind[n] == 2) {
         for (int axis = 0; axis < d.dim; ++axis) {
@@ -83,7 +79,26 @@ __global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__
             c += kind[n + st] != 2;
         }
     }
-    ncut[n] = c;
+    return c;
+}
+
+// Cut sides per workgroup (the same node-to-workgroup map as k_diag_cuts,
+// which places each node's records after those of the workgroups before it
+// and of the nodes before it in its own).
+__global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, GridDims d, int64_t nnodes,
+                                                      int32_t* __restrict__ block_cuts) {
+    __shared__ int32_t wcount[BLOCK / WAVE];
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int c = n < nnodes ? node_cuts(kind, n, d) : 0;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wcount[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < BLOCK / WAVE; ++w) t += wcount[w];
+        block_cuts[blockIdx.x] = t;
+    }
 }
 
 // ------------------------------------------------- diagonal and cut records
@@ -105,7 +120,7 @@ __global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__
 constexpr int DIAG_WALK = 8;                  // nodes read together per round
 constexpr int DIAG_SHORT = 2 * DIAG_WALK;     // nodes a thread examines before deferring
 constexpr int DIAG_DEFER_CAP = 4096;          // deferred nodes (more: walked in place)
-constexpr int DIAG_LONG_NT = 256;
+constexpr int DIAG_LONG_NT = 1024;
 constexpr int DIAG_LONG_BLOCKS = 64;
 
 // The side's interpolation coefficient c = 1/q from the walk's end j (first
@@ -152,24 +167,41 @@ __device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, c
 }
 
 __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ psi, const int8_t* __restrict__ kind,
-                                                     GridDims d, int64_t nnodes, const int64_t* __restrict__ cut_off,
+                                                     GridDims d, int64_t nnodes, const int64_t* __restrict__ block_off,
                                                      double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                      int64_t cap, int32_t* __restrict__ err,
                                                      int32_t* __restrict__ ndefer, int64_t* __restrict__ defer) {
+    __shared__ int32_t wsum[BLOCK / WAVE];
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool unknown = n < nnodes && kind[n] == 2;
+    // first record of the node: the workgroup's offset plus the cut sides of
+    // the nodes before it in the workgroup (exclusive scan)
+    const int cnt = n < nnodes ? node_cuts(kind, n, d) : 0;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const int t = __shfl_up(inc, off, WAVE);
+        if (lane >= off) inc += t;
+    }
+    if (lane == WAVE - 1) wsum[wv] = inc;
+    __syncthreads();
+    int before = inc - cnt;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
     if (n >= nnodes) return;
     // A domain that reaches the outer layer (flagged by k_classify, final by
     // now) makes unknowns next to that layer, whose walks would step past it:
     // nothing to do, the call fails.  This kernel only adds the flag where
     // k_classify has already set it.
     if (*err & DEVERR_DOMAIN) return;
-    if (kind[n] != 2) {
+    if (!unknown) {
         a[n] = 0.0;
         return;
     }
     const NodePos p = node_pos(n, d);
-    double acc = (double)diag_regular(kind, n, d);
-    int64_t m = cut_off[n];
+    double acc = (double)(2 * d.dim - cnt);     // regular sides: the others are cut
+    const int64_t m_first = block_off[blockIdx.x] + before;
+    int64_t m = m_first;
     for (int side = 0; side < 2 * d.dim; ++side) {
         const int axis = side >> 1;
         const int step = (side & 1) ? 1 : -1;
@@ -190,7 +222,8 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
                 if (*(volatile int32_t*)ndefer < DIAG_DEFER_CAP) {
                     const int slot = atomicAdd(ndefer, 1);
                     if (slot < DIAG_DEFER_CAP) {
-                        defer[slot] = n;      // the whole node is redone there
+                        defer[2 * slot] = n;  // the whole node is redone there
+                        defer[2 * slot + 1] = m_first;
                         return;
                     }
                 }
@@ -229,7 +262,6 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
 // node, or the outer layer); thread 0 then adds the sides in order.
 __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __restrict__ psi,
                                                             const int8_t* __restrict__ kind, GridDims d,
-                                                            const int64_t* __restrict__ cut_off,
                                                             double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                             int64_t cap, int32_t* __restrict__ err,
                                                             const int32_t* __restrict__ ndefer,
@@ -239,10 +271,10 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
     const int count = min(*ndefer, DIAG_DEFER_CAP);
     const int tid = threadIdx.x;
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
-        const int64_t n = defer[i];
+        const int64_t n = defer[2 * i];
         const NodePos p = node_pos(n, d);
         double acc = (double)diag_regular(kind, n, d);
-        int64_t m = cut_off[n];
+        int64_t m = defer[2 * i + 1];
         for (int side = 0; side < 2 * d.dim; ++side) {
             const int axis = side >> 1;
             const int step = (side & 1) ? 1 : -1;
@@ -282,7 +314,7 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
 __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, const double* __restrict__ f,
                                                const eb_cut_t* __restrict__ cuts, int64_t ncuts,
                                                const double* __restrict__ u, double* __restrict__ b,
-                                               int64_t nnodes, double s) {
+                                               int64_t nnodes, double s, GridDims d) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= nnodes) return;
     if (kind[n] != 2) {
@@ -290,6 +322,17 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, 
         return;
     }
     double v = f[n];
+    // only an unknown with a non-computational neighbour has records (an
+    // unknown is never on the outer layer, so its neighbours exist)
+    bool cut = false;
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t st = axis_stride(d, axis);
+        cut = cut || kind[n - st] != 2 || kind[n + st] != 2;
+    }
+    if (!cut) {
+        b[n] = v;
+        return;
+    }
     // lower_bound of node n in the (node, dir)-sorted records
     int64_t lo = 0, hi = ncuts;
     while (lo < hi) {
@@ -453,40 +496,41 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
     // No host round trip until the end: with a domain error k_count_cuts only
     // reads neighbours of unknowns (never on the outer layer) and k_diag_cuts
-    // returns at once; the cut records are bounded by cuts_cap on the device;
+    // returns after its offset scan (which reads the same); the cut records
+    // are bounded by cuts_cap on the device;
     // status, totals and errors come back in one read.
     AsmStat* st = nullptr;
-    int32_t* ncut = nullptr;
-    int64_t* off = nullptr;
+    int32_t* blk_cuts = nullptr;
+    int64_t* blk_off = nullptr;
     int32_t* blk_unk = nullptr;
     int64_t* defer = nullptr;
     const unsigned nblk = grid_for(nn);
     EB_TRY(dalloc_n(&st, 1, s));
-    EB_TRY(dalloc_n(&defer, DIAG_DEFER_CAP, s));
-    EB_TRY(dalloc_n(&ncut, nn, s));
-    EB_TRY(dalloc_n(&off, nn, s));
+    EB_TRY(dalloc_n(&defer, 2 * DIAG_DEFER_CAP, s));
+    EB_TRY(dalloc_n(&blk_cuts, nblk, s));
+    EB_TRY(dalloc_n(&blk_off, nblk, s));
     EB_TRY(dalloc_n(&blk_unk, nblk, s));
     {
         const FillSpec f[] = {{st, sizeof(AsmStat), 0u}};
         EB_TRY(fill_words(f, 1, s));
     }
-    hipLaunchKernelGGL(k_classify, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, &st->err, blk_unk, ncut);
+    hipLaunchKernelGGL(k_classify, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, &st->err, blk_unk);
     EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, blk_unk, (int64_t)nblk, &st->unknowns);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_count_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, d, nn, ncut);
+    hipLaunchKernelGGL(k_count_cuts, dim3(nblk), dim3(BLOCK), 0, s, kind, d, nn, blk_cuts);
     EB_LAUNCH_CHECK();
-    EB_TRY(scan_i32_to_i64_dev(ncut, off, nn, &st->cuts, s));
-    hipLaunchKernelGGL(k_diag_cuts, dim3(grid_for(nn)), dim3(BLOCK), 0, s, psi, kind, d, nn, off, a, cuts, cuts_cap,
+    EB_TRY(scan_i32_to_i64_dev(blk_cuts, blk_off, nblk, &st->cuts, s));
+    hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, blk_off, a, cuts, cuts_cap,
                        &st->err, &st->ndefer, defer);
-    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, off, a, cuts,
+    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, a, cuts,
                        cuts_cap, &st->err, &st->ndefer, defer);
     EB_LAUNCH_CHECK();
     AsmStat h;
     EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));
     EB_TRY(dfree(st, s));
-    EB_TRY(dfree(ncut, s));
-    EB_TRY(dfree(off, s));
+    EB_TRY(dfree(blk_cuts, s));
+    EB_TRY(dfree(blk_off, s));
     EB_TRY(dfree(blk_unk, s));
     EB_TRY(dfree(defer, s));
     EB_HIP(hipStreamSynchronize(s));
@@ -548,7 +592,7 @@ extern "C" int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const dou
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s, d);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }

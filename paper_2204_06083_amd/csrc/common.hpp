@@ -151,6 +151,16 @@ struct NodePos {
 
 __device__ inline NodePos node_pos(int64_t n, const GridDims& d) {
     NodePos p;
+    if (n <= 0x7fffffff) {
+        // 32-bit division (the usual case: far fewer than 2^31 nodes)
+        const uint32_t u = (uint32_t)n, nx = (uint32_t)d.nx, ny = (uint32_t)d.ny;
+        const uint32_t r = u / nx;
+        p.i = (int)(u - r * nx);
+        const uint32_t k = r / ny;
+        p.j = (int)(r - k * ny);
+        p.k = (int)k;
+        return p;
+    }
     p.i = (int)(n % d.nx);
     int64_t r = n / d.nx;
     p.j = (int)(r % d.ny);

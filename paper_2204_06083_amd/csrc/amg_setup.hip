@@ -1247,8 +1247,11 @@ static int launch_accumulate(int mode, AccArgs& args, hipStream_t s) {
     const int ns = args.sm.nslots;
     const size_t per_lane = (size_t)ns * (sizeof(double) + 1);
     int G = 1;
+    // (row x lane) thread budget: RAP rows (coarse, long product chains) gain
+    // from more lanes than AP rows (measured on the star 2048^2 hierarchy)
+    const int64_t cap_thr = mode == ACC_RAP ? 2 * 1024 * 1024 : 512 * 1024;
     if (mode != ACC_P)
-        while (G < 64 && args.nrows * (int64_t)(2 * G) <= 512 * 1024 && per_lane * (2 * G) <= 32 * 1024) G *= 2;
+        while (G < 64 && args.nrows * (int64_t)(2 * G) <= cap_thr && per_lane * (2 * G) <= 32 * 1024) G *= 2;
     int rows = 256 / G;
     while (rows > 1 && per_lane * G * rows > 64 * 1024) rows >>= 1;
     if (per_lane * G * rows > 150 * 1024) {

@@ -395,3 +395,22 @@ def qoi_rectangle_weights(grid: Grid, rect=((-1.0, 1.0), (-0.5, 0.5))) -> np.nda
         w[i0] = w[i1] = 0.5
         w1.append(w * h)
     return w1[1][:, None] * w1[0][None, :]
+
+
+def psi_staircases(grid: Grid, stripe: int = 12, step: int = 20, margin: int = 4) -> np.ndarray:
+    """Horizontal stripes whose upper boundary descends one node row every
+    `step` columns (a sawtooth of staircases), in node units scaled by h.  An
+    unknown at the foot of each step sees the grid line continue inside for
+    about `step` nodes beyond its boundary point: thousands of long walks
+    along grid lines.  (2-D; psi is never zero at a node.)"""
+    X, Y = grid.mesh()
+    c = np.rint((X - grid.x0[0]) / grid.h)
+    r = np.rint((Y - grid.x0[1]) / grid.h)
+    k = np.floor((r - margin) / stripe)
+    rr = (r - margin) - k * stripe
+    per_tooth = stripe - 4
+    s = np.floor(np.mod(c, per_tooth * step) / step)
+    top = (stripe - 1.5) - s
+    psi = np.maximum(1.5 - rr, rr - top)
+    edge = (r < margin) | (r > grid.n[1] - margin) | (c < margin) | (c > grid.n[0] - margin)
+    return np.where(edge, 1.0, psi) * grid.h

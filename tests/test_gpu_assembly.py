@@ -94,3 +94,32 @@ def test_cut_capacity_exact_fit_and_determinism():
     a1 = S.assemble_diag(prob.grid, to_dev(prob.psi))
     a2 = S.assemble_diag(prob.grid, to_dev(prob.psi), cuts_cap=a1.n_cuts)
     assert torch.equal(a1.a, a2.a) and torch.equal(a1.cuts[: a1.n_cuts * 56], a2.cuts[: a2.n_cuts * 56])
+
+
+def test_assembly_bit_exact_with_thousands_of_long_walks():
+    """Staircase stripes on the 2049^2 grid: about 17 k unknowns whose walk
+    along the grid line passes 17 nodes (the longest 1,917), more than the
+    library hands to its workgroup walker, so both long-walk paths run; the
+    records, diagonal and RHS must still equal the oracle's bit for bit."""
+    g = W.unit_box_grid(2, 2048)
+    psi = W.psi_staircases(g)
+    print("[gpu] assembly staircases 2049^2", flush=True)
+    asm_o = E.assemble(g, psi)
+    long_walks = int((asm_o.cuts["steps"] > 17).sum())
+    assert long_walks > 4096 and asm_o.cuts["steps"].max() > 1024
+    asm_g = S.assemble_diag(g, to_dev(psi))
+    kind = asm_g.kind.cpu().numpy()
+    assert np.array_equal(kind, asm_o.kind)
+    assert asm_g.n_unknowns == asm_o.n_unknowns and asm_g.n_cuts == asm_o.n_cuts
+    cuts = asm_g.cuts_host()
+    for key in ("node", "dir", "steps", "q", "c"):
+        assert np.array_equal(cuts[key], asm_o.cuts[key]), key
+    assert np.array_equal(cuts["xg"][:, :2], asm_o.cuts["xg"][:, :2])
+    a = asm_g.a.cpu().numpy().ravel()
+    assert np.array_equal(a[asm_o.nodes], asm_o.a)
+    f = np.ones(g.shape)
+    xg = E.cut_coordinates(asm_o)
+    ud = np.sin(3.0 * xg[0]) + xg[1]
+    b_o = E.rhs(asm_o, f, ud)
+    b_g = S.assemble_rhs(asm_g, to_dev(f), torch.from_numpy(ud).to(DEV)).cpu().numpy().ravel()
+    assert np.array_equal(b_g[asm_o.nodes], b_o)

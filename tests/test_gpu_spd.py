@@ -89,3 +89,22 @@ def test_check_spd_full_size_star():
     asm_g = S.assemble_diag(p.grid, to_dev(p.psi))
     segs, fail = S.check_spd(asm_g)
     assert fail == 0 and segs == _runs_by_starts(asm_g.kind.cpu().numpy())
+
+
+def test_check_spd_on_staircases():
+    """Staircase stripes (321 k grid-line segments, many with long walks and
+    both ends cut): counts equal to the oracle's, unchanged and with the c of
+    every third record made negative."""
+    g = W.unit_box_grid(2, 2048)
+    print("[gpu] check_spd staircases 2049^2", flush=True)
+    asm_g = S.assemble_diag(g, to_dev(W.psi_staircases(g)))
+    segs, fail = S.check_spd(asm_g)
+    assert (segs, fail) == _oracle_counts(asm_g)
+    assert fail == 0 and segs == _runs_by_starts(asm_g.kind.cpu().numpy())
+    cuts = asm_g.cuts.clone()
+    rec = cuts[: asm_g.n_cuts * 56].view(torch.float64).view(asm_g.n_cuts, 7)
+    rec[::3, 3] *= -0.7
+    c_host = rec[:, 3].cpu().numpy()
+    segs2, fail2 = S.check_spd(asm_g, cuts)
+    assert (segs2, fail2) == _oracle_counts(asm_g, c_host)
+    assert segs2 == segs and fail2 > 0

@@ -414,3 +414,14 @@ def psi_staircases(grid: Grid, stripe: int = 12, step: int = 20, margin: int = 4
     psi = np.maximum(1.5 - rr, rr - top)
     edge = (r < margin) | (r > grid.n[1] - margin) | (c < margin) | (c > grid.n[0] - margin)
     return np.where(edge, 1.0, psi) * grid.h
+
+
+def staircase_poisson(n: int = 512) -> Problem:
+    """Poisson problem on the staircase stripes (psi_staircases): f = 1 and
+    Dirichlet data sin 3x + y; many disconnected thin components."""
+    g = unit_box_grid(2, n)
+
+    def u_d(X, Y, xp=np):
+        return xp.sin(3.0 * X) + Y
+
+    return Problem("staircases2d", g, psi_staircases(g), np.ones(g.shape), u_dirichlet=u_d, tol=1e-10)

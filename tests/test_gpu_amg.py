@@ -34,6 +34,8 @@ CASES = {
     # 258) and, with two levels, 318 (above it: blocked Cholesky path)
     "star86": (lambda: W.star_poisson(86), 0.0, 256),
     "star96_two_levels": (lambda: W.star_poisson(96), 0.0, 256, 2),
+    # 42 disconnected stripes, several components per box
+    "staircases512": (lambda: W.staircase_poisson(512), 0.0, 256),
 }
 
 

@@ -23,6 +23,7 @@ ITER_CASES = {
     "ell64": (lambda: W.ellipsoid_poisson(64), 1e-8),
     "disk16_onelevel": (lambda: W.disk_mms(16, radius=0.3), 1e-10),
     "star2048_full": (lambda: W.star_poisson(2048), 1e-8),
+    "staircases512": (lambda: W.staircase_poisson(512), 1e-10),
 }
 
 

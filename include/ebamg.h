@@ -132,7 +132,9 @@ typedef struct {
 } amg_level_info_t;
 
 /* Step 1 and the diagonal of steps 2-3 (Sec. 2 definitions; Sec. 2.1.1
- * interpolant; crossing by linear interpolation of psi as in Sec. 3.3).
+ * interpolant; the crossing is the root of psi on the grid line, Sec. 2.1.1,
+ * located here by linear interpolation of psi between the last inside and the
+ * first outside node, the second-order distance approximation of Sec. 3.3).
  *   psi   [in]  node field, level set, negative inside.
  *   kind  [out] node field int8: 0 outside, 1 boundary point, 2 computational.
  *   a     [out] node field: a_k at computational points, 0 elsewhere.
@@ -244,7 +246,7 @@ int eb_set_iteration_graphs(int32_t enabled);
 
 /* The same PCG for nrhs right-hand sides (1 <= nrhs <= 64) sharing the
  * hierarchy, run as one launch sequence (Algorithm 2 step 4 for several b, as
- * in the heat steps of Sec. 4).  b and x hold nrhs node fields back to back
+ * in the heat steps of Sec. 3.4).  b and x hold nrhs node fields back to back
  * (field j at offset j * (n[0]+1)(n[1]+1)[(n[2]+1)] doubles); x holds the
  * initial guesses if p->x0_given.  Each right-hand side has its own
  * iteration, convergence test, true-residual check and restart; res (host)

@@ -1173,14 +1173,14 @@ struct ReportArgs {
     const int32_t* p_tot[MAX_LEVELS];
     const int32_t* r_tot[MAX_LEVELS];
     const double* scal;      // 2 * MAX_LEVELS
-    const int32_t* counts;   // 2
+    const int32_t* counts;   // 3
     const int32_t* stat;     // 4 (SetupStat)
 };
 
 struct ReportBlock {
     int64_t nnz[3 * MAX_LEVELS];
     double scal[2 * MAX_LEVELS];
-    int32_t counts[2];
+    int32_t counts[3];
     int32_t stat[4];
 };
 
@@ -1192,7 +1192,7 @@ __global__ void k_report(ReportArgs R, ReportBlock* __restrict__ out) {
         out->nnz[3 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
     }
     if (l < 2 * MAX_LEVELS) out->scal[l] = R.scal[l];
-    if (l < 2) out->counts[l] = R.counts[l];
+    if (l < 3) out->counts[l] = R.counts[l];
     if (l < 4) out->stat[l] = R.stat[l];
 }
 
@@ -1589,9 +1589,9 @@ int free_handle_memory(amg_handle* H) {
     free_batch(H, s);
     drop_iteration_graphs(H);
     for (int l = 0; l < MAX_LEVELS; ++l) free_level(H->lev[l], s);
-    void* ptrs[] = {H->unk_off_tmp, H->strips, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->agg_p, H->x, H->rr[0], H->rr[1],
+    void* ptrs[] = {H->unk_off_tmp, H->strips, H->tiles, H->box_map0, H->box_w0, H->box_w0_32, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->dinv_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
-                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->res32, H->zt32, H->z32,
+                    H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->dinv_p32, H->res32, H->zt32, H->z32,
                     H->wf, H->wf32};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;
@@ -1706,6 +1706,7 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     memcpy(&st, rep.stat, sizeof(st));
     H->nstrips = rep.counts[0];
     H->nboxes0 = rep.counts[1];
+    H->ntiles = rep.counts[2];
     EB_TRY(dfree(drep, s));
     for (int k = 0; k < H->nlev; ++k) {
         Level& L = H->lev[k];

@@ -106,10 +106,12 @@ __global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__
 // point (xi_1 = 0) and the boundary crossing (xi_Gamma = q h) evaluated at the
 // BP (xi = h): u_BP = u_Gamma / q + (1 - 1/q) u_1.  Substituted into the
 // central difference, the side adds c = 1/q to the diagonal of -L_h h^2 and
-// u_Gamma c / h^2 to the right-hand side.  The crossing is located by linear
-// interpolation of psi between the last inside and first outside node on the
-// grid line (Sec. 3.3); when the node two steps out is still inside, the line
-// is followed to the first outside node.
+// u_Gamma c / h^2 to the right-hand side.  The crossing is the root of psi on
+// the grid line (Sec. 2.1.1); this library locates it by linear interpolation
+// of psi between the last inside and first outside node (a reading: the
+// paper names a root finder there and uses this second-order approximation
+// for its parametric geometries, Sec. 3.3); when the node two steps out is
+// still inside, the line is followed to the first outside node.
 // Walks that do not end within the first DIAG_SHORT nodes (a boundary running
 // almost along the grid line: up to about a thousand nodes on the 2048^2
 // star) would leave one thread walking long after the rest of the grid is

@@ -1,6 +1,6 @@
 // Batched PCG: up to 64 right-hand sides share the hierarchy and one launch
 // sequence (Algorithm 2 step 4 applied to several b at once, as in the heat
-// steps of Sec. 4 and the repeated solves of shape optimisation).
+// steps of Sec. 3.4 and the repeated solves of shape optimisation).
 //
 // Layout: kp slots (a power of two >= nrhs).  Fine-level vectors are planes
 // of kb = min(kp, 8) right-hand sides, node-major inside a plane:

@@ -84,17 +84,29 @@ struct amg_handle {
     int strip_w = 64;
     int64_t nstrips = 0;
     int32_t* strips = nullptr;      // active strips (ids: padded index / strip_w)
-    int32_t* dcount = nullptr;      // device totals: [0] strips, [1] level-0 boxes
+    int32_t* dcount = nullptr;      // device totals: [0] strips, [1] level-0 boxes, [2] tiles
     int64_t nboxes0 = 0;
+    // 2-D fine band tiles (TX x TY nodes) holding unknowns, row-major;
+    // tile_tpw tiles per wavefront of the tile kernels
+    int64_t ntiles = 0;
+    int32_t* tiles = nullptr;
+    int tile_ntx = 0;
+    int tile_tpw = 1;
+    int32_t* box_map0 = nullptr;    // 2-D: aggregate of each node of a level-0 box (3 bits per node)
+    double* box_w0 = nullptr;       // 2-D: omega_1 / d_1 of the first aggregate of each level-0 box
+    float* box_w0_32 = nullptr;
     int32_t* boxes0 = nullptr;      // level-0 boxes holding unknowns
     int64_t* fine_nodes = nullptr;  // unknown -> dense node index
     int32_t* unk_off_tmp = nullptr; // setup only: dense node -> unknown index
     const int8_t* kind_tmp = nullptr;  // setup only: the caller's kind field
     int32_t* fine_pad = nullptr;    // unknown -> padded node index
     double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
+    double* dinv_p = nullptr;       // padded 1 / diagonal (0 off unknowns): the fine smoother and
+                                    // prolongator scale by omega / d
     // single-precision V-cycle: padded FP32 diagonal and V-cycle vectors
     int fp32_ready = 0;
     float* diag_p32 = nullptr;
+    float* dinv_p32 = nullptr;
     float* res32 = nullptr;
     float* zt32 = nullptr;
     float* z32 = nullptr;

@@ -33,7 +33,9 @@ constexpr int NT = 512;        // threads per block of the solve kernels
 // The fixed-grid reducing kernels ask for 8 waves per SIMD (<= 64 VGPRs) so
 // that their whole grid is resident at once.
 constexpr int RNT = 256;       // threads per block of the box-per-thread restriction
-constexpr int MAX_PARTS = 1024;
+constexpr int MAX_PARTS = 1024;       // partials of the strip kernels' fixed grid
+constexpr int MAX_TILE_PARTS = 2048;  // blocks of the 2-D tile kernels (one partial each)
+constexpr int PART_CAP = MAX_TILE_PARTS;
 
 struct FineArgs {
     const int32_t* strips;
@@ -97,18 +99,73 @@ __device__ inline void block_partial(double v, double* __restrict__ part) {
 }
 
 // Sum of np partials in a fixed order; every thread of the block gets it.
+// Thread t adds part[t], part[t + BS], ... in that order; the loads of a
+// round of TOT_U of them are issued together (one memory latency per round,
+// not per partial).
+constexpr int TOT_U = 4;
+
+template <int BS>
+__device__ inline double thread_partials(const double* __restrict__ part, int np) {
+    double a = 0.0;
+    for (int i0 = 0; i0 < np; i0 += BS * TOT_U) {
+        double v[TOT_U];
+#pragma unroll
+        for (int u = 0; u < TOT_U; ++u) {
+            const int i = i0 + u * BS + (int)threadIdx.x;
+            v[u] = i < np ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < TOT_U; ++u)
+            if (i0 + u * BS + (int)threadIdx.x < np) a += v[u];
+    }
+    return a;
+}
+
 template <int BS = NT>
 __device__ inline double block_total(const double* __restrict__ part, int np) {
     __shared__ double lds[BS / WAVE];
     __shared__ double tot;
-    double a = 0.0;
-    for (int i = threadIdx.x; i < np; i += BS) a += part[i];
+    double a = thread_partials<BS>(part, np);
     a = block_sum<BS>(a, lds);
     if (threadIdx.x == 0) tot = a;
     __syncthreads();
     const double r = tot;
     __syncthreads();
     return r;
+}
+
+// Two totals at once (same order as two block_total calls, one pass of loads
+// and barriers).
+template <int BS = NT>
+__device__ inline void block_total2(const double* __restrict__ pa, const double* __restrict__ pb, int np,
+                                    double* ta, double* tb) {
+    __shared__ double lds[2][BS / WAVE];
+    __shared__ double tot[2];
+    double a = thread_partials<BS>(pa, np);
+    double b = thread_partials<BS>(pb, np);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    if (lane == 0) {
+        lds[0][w] = a;
+        lds[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int i = 0; i < BS / WAVE; ++i) {
+            x += lds[0][i];
+            y += lds[1][i];
+        }
+        tot[0] = x;
+        tot[1] = y;
+    }
+    __syncthreads();
+    *ta = tot[0];
+    *tb = tot[1];
+    __syncthreads();
 }
 
 __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -128,9 +185,10 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __res
                                                    const double* __restrict__ rz_prev, int np,
                                                    double* __restrict__ part_pq, PcgScalars* sc) {
     if (sc->done) return;
-    const double rho = block_total(rz_cur, np);
-    double beta = 0.0;
-    if (rz_prev) beta = rho / block_total(rz_prev, np);
+    double rho, rho_prev = 0.0;
+    if (rz_prev) block_total2(rz_cur, rz_prev, np, &rho, &rho_prev);
+    else rho = block_total(rz_cur, np);
+    const double beta = rz_prev ? rho / rho_prev : 0.0;
     if (!(rho > 0.0) || bad_value(rho) || bad_value(beta)) {
         if (lead()) {
             sc->status = (bad_value(rho) || bad_value(beta)) ? EB_ENAN : EB_ENOTSPD;
@@ -166,8 +224,8 @@ __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ 
                                                const double* __restrict__ rz_cur, const double* __restrict__ part_pq,
                                                int np, double* __restrict__ part_rr, PcgScalars* sc) {
     if (sc->done) return;
-    const double rho = block_total(rz_cur, np);
-    const double pq = block_total(part_pq, np);
+    double rho, pq;
+    block_total2(rz_cur, part_pq, np, &rho, &pq);
     if (!(pq > 0.0) || bad_value(pq)) {
         if (lead()) {
             sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
@@ -254,7 +312,14 @@ struct BoxArgs {
     const int32_t* cstart;
     const int32_t* ncomp;
     const int32_t* agg;   // padded
+    const int32_t* map;   // 2-D: per box, the aggregate of node n (0..8) minus cstart in bits 3n..3n+2 (7: none)
+    const double* w0;     // 2-D: per box, omega_1 / d_1 of its first aggregate (0 without aggregates)
+    const float* w0_32;
 };
+
+template <class V> __device__ inline const V* vbw0(const BoxArgs& b);
+template <> __device__ inline const double* vbw0<double>(const BoxArgs& b) { return b.w0; }
+template <> __device__ inline const float* vbw0<float>(const BoxArgs& b) { return b.w0_32; }
 
 template <class V, int DIM>
 __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
@@ -371,8 +436,8 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
                                                     const double* __restrict__ part_pq, int np,
                                                     double* __restrict__ part_rr, PcgScalars* sc) {
     if (sc->done) return;
-    const double rho = block_total(rz_cur, np);
-    const double pq = block_total(part_pq, np);
+    double rho, pq;
+    block_total2(rz_cur, part_pq, np, &rho, &pq);
     if (!(pq > 0.0) || bad_value(pq)) {
         if (lead()) {
             sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
@@ -479,6 +544,425 @@ __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, c
     block_partial(part, part_rz);
 }
 
+// ------------------------------------------------- 2-D fine band tiles
+// In 2-D the fine level of an iteration runs as three kernels:
+//   k_t2_pspmv:        p = z + beta p_old; q = A p; (p, q)
+//   k_t2_xr_restrict:  x += alpha p; r = r - alpha q; ||r||^2; the
+//                      pre-smoothing residual res = r - A z1 (z1 = omega r/d)
+//                      and the restriction P^T res, summed per box
+//   k_t2_up_post:      t = e_c[agg]; zt = z1 + (I - omega D^-1 A) t;
+//                      z = zt + omega D^-1 (r - A zt); (r, z)
+// The residual res and the prolongated iterate zt never leave registers, so
+// per unknown and iteration the fine level moves 40 + 56 + 28 bytes (plus the
+// coarse vector) instead of the 184 of the strip kernels.
+//
+// Work is cut into band tiles of TX = 60 columns x TY rows (origins multiples
+// of 3, so a tile holds whole level-0 boxes), one wavefront per tile: lane l
+// owns column x0 - 2 + l (lanes 0, 1, 62, 63 are the two-column halo), and the
+// wavefront marches down the rows of the tile and of its halo, keeping the
+// last few rows of every quantity in registers.  The left and right
+// neighbours of a value come from the adjacent lanes by a whole-wave DPP
+// shift, the rows above and below from the registers, so there is no LDS and
+// no barrier; the reads of the next two rows are issued before the current
+// row is computed.  Fields are zero off unknowns, so no read waits for the
+// diagonal.  The smoother and prolongator scale by omega / d through the
+// stored 1 / d, with no division.
+constexpr int TX = 60, TY = 12;   // band tile: 20 x 4 level-0 boxes
+constexpr int TWB = 4;            // wavefronts (tiles) per block
+constexpr int TNT = TWB * WAVE;   // threads per block
+
+struct TileArgs {
+    const int32_t* tiles;   // active tiles (ty * ntx + tx), row-major order
+    int64_t ntiles;
+    int tpw;                // tiles per wavefront (a contiguous range per wavefront)
+    int ntx;                // tiles per row of the tile grid
+    int nx, ny;             // node extents
+    int sy;                 // padded row pitch (padded node fields stay below 2^31 entries)
+    double s;               // 1/h^2
+    const double* diag;     // padded, 0 off unknowns
+    const float* diag32;
+    const double* dinv;     // padded 1 / diag, 0 off unknowns
+    const float* dinv32;
+    const double* wf;       // per-point smoother weights omega_k / d_k (learned), else null
+    const float* wf32;
+};
+
+template <class V> __device__ inline const V* tdiag(const TileArgs& t);
+template <> __device__ inline const double* tdiag<double>(const TileArgs& t) { return t.diag; }
+template <> __device__ inline const float* tdiag<float>(const TileArgs& t) { return t.diag32; }
+template <class V> __device__ inline const V* tdinv(const TileArgs& t);
+template <> __device__ inline const double* tdinv<double>(const TileArgs& t) { return t.dinv; }
+template <> __device__ inline const float* tdinv<float>(const TileArgs& t) { return t.dinv32; }
+template <class V> __device__ inline const V* twf(const TileArgs& t);
+template <> __device__ inline const double* twf<double>(const TileArgs& t) { return t.wf; }
+template <> __device__ inline const float* twf<float>(const TileArgs& t) { return t.wf32; }
+
+// Element i of a padded field through a 32-bit byte offset from the field's
+// base (the tile kernels run only while a padded field spans less than
+// 4 GiB): one VGPR per node serves every field.
+template <class T>
+__device__ inline T ld(const T* __restrict__ base, uint32_t i) {
+    return *(const T*)((const char*)base + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ inline void st(T* __restrict__ base, uint32_t i, T v) {
+    *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
+// Value of the lane to the left (lane - 1; 0 in lane 0) and to the right
+// (lane + 1; 0 in lane 63): whole-wave DPP shifts, executed by all lanes.
+__device__ inline int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+__device__ inline double from_left(double v) {
+    return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
+}
+__device__ inline double from_right(double v) {
+    return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
+}
+__device__ inline float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ inline float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+
+// The tiles of this block's wavefront (block-uniform grid, one range per
+// wavefront) and the lane's column.
+struct TileLane {
+    int lane;
+    int64_t t0, t1;   // tile range of this wavefront
+};
+
+__device__ inline TileLane tile_lane(const TileArgs& t) {
+    TileLane L;
+    L.lane = threadIdx.x & (WAVE - 1);
+    const int64_t gw = xcd_block() * (int64_t)TWB + threadIdx.x / WAVE;
+    L.t0 = gw * t.tpw;
+    L.t1 = min(L.t0 + (int64_t)t.tpw, t.ntiles);
+    return L;
+}
+
+__device__ inline void tile_origin(const TileArgs& t, int64_t tix, int* x0, int* y0) {
+    const int tid = t.tiles[tix];
+    *x0 = (tid % t.ntx) * TX;
+    *y0 = (tid / t.ntx) * TY;
+}
+
+// p = z + beta p_old on the tile and its halo rows, q = A p on the tile;
+// partial (p, q).
+template <class V>
+__global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restrict__ z,
+                                                  const double* __restrict__ pold, double* __restrict__ pnew,
+                                                  double* __restrict__ q, const double* __restrict__ rz_cur,
+                                                  const double* __restrict__ rz_prev, int np,
+                                                  double* __restrict__ part_pq, PcgScalars* sc) {
+    if (sc->done) return;
+    double rho, rho_prev = 0.0;
+    if (rz_prev) block_total2<TNT>(rz_cur, rz_prev, np, &rho, &rho_prev);
+    else rho = block_total<TNT>(rz_cur, np);
+    const double beta = rz_prev ? rho / rho_prev : 0.0;
+    if (!(rho > 0.0) || bad_value(rho) || bad_value(beta)) {
+        if (lead()) {
+            sc->status = (bad_value(rho) || bad_value(beta)) ? EB_ENAN : EB_ENOTSPD;
+            sc->done = 1;
+        }
+        return;
+    }
+    const TileLane L = tile_lane(t);
+    double part = 0.0;
+    for (int64_t ti = L.t0; ti < L.t1; ++ti) {
+        int x0, y0;
+        tile_origin(t, ti, &x0, &y0);
+        const int xc = x0 - 2 + L.lane;
+        const bool xin = xc >= 0 && xc < t.nx;
+        const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
+        auto row = [&](int j, double& d, double& zz, double& pp) {
+            d = zz = pp = 0.0;
+            if (xin && j >= 0 && j < t.ny && j <= y0 + TY) {
+                const uint32_t pn = xc + t.sy * j;
+                d = ld(t.diag, pn);
+                zz = (double)ld(z, pn);
+                pp = ld(pold, pn);
+            }
+        };
+        double d0, z0, p0, d1, z1, p1;     // rows j, j + 1 (read ahead)
+        row(y0 - 1, d0, z0, p0);
+        row(y0, d1, z1, p1);
+        double pa = 0.0, pb = 0.0, da = 0.0;   // p of rows j - 2, j - 1; d of row j - 1
+#pragma unroll 1
+        for (int j = y0 - 1; j <= y0 + TY; ++j) {
+            double d2, z2, p2;
+            row(j + 2, d2, z2, p2);
+            const double pc = d0 != 0.0 ? z0 + beta * p0 : 0.0;
+            // row j - 1: q = A p
+            const double lr = from_left(pb) + from_right(pb);
+            if (j > y0 && inner && da != 0.0) {
+                const double qv = da * pb - t.s * (lr + (pa + pc));
+                const uint32_t pn = xc + t.sy * (j - 1);
+                st(pnew, pn, pb);
+                st(q, pn, qv);
+                part += pb * qv;
+            }
+            pa = pb;
+            pb = pc;
+            da = d0;
+            d0 = d1; z0 = z1; p0 = p1;
+            d1 = d2; z1 = z2; p1 = p2;
+        }
+    }
+    block_partial<TNT>(part, part_pq);
+}
+
+// UPD: alpha = rho / (p, q); x += alpha p; r_out = r_in - alpha q and its
+// partial ||r_out||^2 (without UPD, r = r_in: the first V-cycle).  Then, with
+// r in the halo recomputed from r_in and q, the pre-smoothing residual
+// res = r - A z1 = (1 - omega) r + omega s sum (r / d)_nbr (LW: z1 = wf r,
+// res = r - d z1 + s sum z1_nbr) on the tile and its first halo, the
+// restriction's u = (I - omega A D^-1) res = (1 - omega) res +
+// omega s sum (res / d)_nbr on the tile (the prolongator keeps omega), and per
+// level-0 box the sum of u over each of its aggregates (each column's three
+// rows, then the three columns): r_c = P^T res.  The CG update and res are
+// FP64; res is rounded to V, the restriction runs in V.
+template <class V, bool LW, bool UPD>
+__global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, double* __restrict__ x,
+                                                        const double* __restrict__ rin, double* __restrict__ rout,
+                                                        const double* __restrict__ pv,
+                                                        const double* __restrict__ q, double omega,
+                                                        const double* __restrict__ rz_cur,
+                                                        const double* __restrict__ part_pq, int np,
+                                                        double* __restrict__ part_rr, V* __restrict__ rc,
+                                                        const V* __restrict__ dg_c, double omega_c,
+                                                        V* __restrict__ sv_c, PcgScalars* sc) {
+    if (sc->done) return;
+    double alpha = 0.0;
+    if (UPD) {
+        double rho, pq;
+        block_total2<TNT>(rz_cur, part_pq, np, &rho, &pq);
+        if (!(pq > 0.0) || bad_value(pq)) {
+            if (lead()) {
+                sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
+                sc->done = 1;
+            }
+            return;
+        }
+        alpha = rho / pq;
+        if (lead()) {
+            sc->iters = sc->iters + 1;   // counted on the device: a captured iteration carries no number
+            sc->pq = pq;
+        }
+    }
+    const double sw = omega * t.s;
+    const V wV = (V)omega, swV = (V)sw;
+    const TileLane L = tile_lane(t);
+    // a box's lead lane is its left column; lanes 2 .. 61 hold the tile's 20 boxes
+    const int bl = L.lane - 2;
+    const bool box_lead = bl >= 0 && bl < TX && bl % 3 == 0;
+    const int ox = bl >= 0 ? bl % 3 : 0;
+    double part = 0.0;
+    for (int64_t ti = L.t0; ti < L.t1; ++ti) {
+        int x0, y0;
+        tile_origin(t, ti, &x0, &y0);
+        const int xc = x0 - 2 + L.lane;
+        const bool xin = xc >= 0 && xc < t.nx;
+        const bool inner = xin && bl >= 0 && bl < TX;
+        const int bx = xc >= 0 ? xc / 3 : 0;
+        // one row of a lane: 1 / d, r_in, q (UPD); LW: weight, d; the tile's
+        // own rows also x and p (UPD)
+        struct Row { double iv, r, q, w, d, x, p; };
+        auto row = [&](int j, Row& R) {
+            R.iv = R.r = R.q = R.w = R.d = R.x = R.p = 0.0;
+            if (xin && j >= 0 && j < t.ny && j <= y0 + TY + 1) {
+                const uint32_t pn = xc + t.sy * j;
+                R.iv = ld(t.dinv, pn);
+                R.r = ld(rin, pn);
+                if (UPD) R.q = ld(q, pn);
+                if (LW) {
+                    R.w = ld(t.wf, pn);
+                    R.d = ld(t.diag, pn);
+                }
+                if (UPD && inner && j >= y0 && j < y0 + TY) {
+                    R.x = ld((const double*)x, pn);
+                    R.p = ld(pv, pn);
+                }
+            }
+        };
+        // box row of the lane's box: aggregate count, first aggregate, node
+        // map and omega_c / d_c of the first aggregate (read a box row ahead)
+        auto boxrow = [&](int by, int& m, int& c0, int& map, V& w0) {
+            m = 0; c0 = 0; map = 0; w0 = V(0);
+            if (inner && by < b.nby && bx < b.nbx) {
+                const uint32_t box = by * b.nbx + bx;
+                m = ld(b.ncomp, box);
+                c0 = ld(b.cstart, box);
+                map = ld(b.map, box);
+                w0 = ld(vbw0<V>(b), box);
+            }
+        };
+        Row R0, R1;                          // rows j, j + 1 (read ahead)
+        row(y0 - 2, R0);
+        row(y0 - 1, R1);
+        int bm, bc0, bmap;
+        V bw0;
+        boxrow(y0 / 3, bm, bc0, bmap, bw0);
+        // rolling rows: z1 (j-2, j-1), r (j-1), 1 / d (j-2, j-1), d (j-1),
+        // res (j-2), v (j-3, j-2), column sums per aggregate of the box row
+        double za = 0.0, zb = 0.0, rb = 0.0, ia = 0.0, ib = 0.0, dbb = 0.0;
+        V resa = V(0), va = V(0), vb = V(0);
+        V acc[5] = {V(0), V(0), V(0), V(0), V(0)};
+#pragma unroll 1
+        for (int j = y0 - 2; j <= y0 + TY + 1; ++j) {
+            Row R2;
+            row(j + 2, R2);
+            // row j: r, z1 (and the CG update of the tile's own rows)
+            double rj = 0.0, zj = 0.0;
+            if (R0.iv != 0.0) {
+                rj = UPD ? R0.r - alpha * R0.q : R0.r;
+                zj = LW ? R0.w * rj : rj * R0.iv;      // LW: z1; else r / d (omega applied below)
+                if (UPD && inner && j >= y0 && j < y0 + TY) {
+                    const uint32_t pn = xc + t.sy * j;
+                    st(x, pn, R0.x + alpha * R0.p);
+                    st(rout, pn, rj);
+                    part += rj * rj;
+                }
+            }
+            // row j - 1: res and res / d
+            const double zlr = from_left(zb) + from_right(zb);
+            V resb = V(0), vc = V(0);
+            if (j >= y0 && ib != 0.0) {
+                const double nb = zlr + (za + zj);
+                const double rs = LW ? rb - (dbb * zb - t.s * nb) : (1.0 - omega) * rb + sw * nb;
+                resb = (V)rs;
+                vc = resb * (V)ib;
+            }
+            // row j - 2: u, added to its box row's column sums
+            const V vlr = from_left(vb) + from_right(vb);
+            if (j >= y0 + 2) {
+                V u = V(0);
+                if (ia != 0.0) u = (V(1) - wV) * resa + swV * (vlr + (va + vc));
+                const int oy = (j - 2 - y0) % 3;
+                if (bm == 1) {
+                    acc[0] += u;
+                } else if (bm > 1) {
+                    const int c = (bmap >> (3 * (3 * oy + ox))) & 7;
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        if (c == k) acc[k] += u;
+                }
+                if (oy == 2) {
+                    // box row complete: sum the three columns at the lead lane
+                    const int cm = __reduce_max_sync(~0ull, bm);   // wave-uniform bound
+                    for (int c = 0; c < cm && c < 5; ++c) {
+                        const V a1 = from_right(acc[c]);
+                        const V a2 = from_right(a1);
+                        const V tot = (acc[c] + a1) + a2;
+                        if (box_lead && c < bm) {
+                            st(rc, (uint32_t)(bc0 + c), tot);
+                            if (sv_c)
+                                st(sv_c, (uint32_t)(bc0 + c),
+                                   c == 0 ? tot * bw0 : (V)omega_c * tot / ld(dg_c, (uint32_t)(bc0 + c)));
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) acc[k] = V(0);
+                    const int nby = (j + 1 - y0) / 3 + y0 / 3;   // next box row
+                    if (nby < (y0 + TY) / 3) boxrow(nby, bm, bc0, bmap, bw0);
+                }
+            }
+            za = zb; zb = zj; rb = rj;
+            ia = ib; ib = R0.iv; dbb = R0.d;
+            resa = resb; va = vb; vb = vc;
+            R0 = R1;
+            R1 = R2;
+        }
+    }
+    if (UPD) block_partial<TNT>(part, part_rr);
+}
+
+// Prolongation and both halves of the fine smoothing that follow it:
+// t = e_c[agg] on the tile and two halo rows,
+// zt = z1 + (I - omega D^-1 A) t = z1 + (1 - omega) t + omega s (sum t_nbr) / d
+// with z1 = omega r / d (LW: wf r) on the tile and one halo row,
+// z = zt + omega (r - A zt) / d = (1 - omega) zt + omega (r + s sum zt_nbr) / d
+// (LW: zt + wf (r - A zt)) on the tile; partial (r, z) in FP64.
+// With part_rr, first the convergence test of the iterate r belongs to (the
+// x/r kernel of this iteration wrote its ||r||^2 partials): once it holds,
+// the remaining kernels of the chunk return at once.
+template <class V, bool LW>
+__global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, const int32_t* __restrict__ agg,
+                                                    const V* __restrict__ ec, const double* __restrict__ r,
+                                                    V* __restrict__ z, double* __restrict__ part_rz,
+                                                    const double* __restrict__ part_rr, int np, PcgScalars* sc) {
+    if (sc->done) return;
+    if (part_rr && converged_or_failed<TNT>(part_rr, np, sc)) return;
+    const V* __restrict__ dinv = tdinv<V>(t);
+    const V wV = (V)omega, sV = (V)t.s, swV = (V)(omega * t.s);
+    const TileLane L = tile_lane(t);
+    double part = 0.0;
+    for (int64_t ti = L.t0; ti < L.t1; ++ti) {
+        int x0, y0;
+        tile_origin(t, ti, &x0, &y0);
+        const int xc = x0 - 2 + L.lane;
+        const bool xin = xc >= 0 && xc < t.nx;
+        const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
+        // one row of a lane: aggregate, 1 / d, r; LW: weight, d
+        struct Row { int32_t g; V iv, w, d; double r; };
+        auto row = [&](int j, Row& R) {
+            R.g = -1;
+            R.iv = R.w = R.d = V(0);
+            R.r = 0.0;
+            if (xin && j >= 0 && j < t.ny && j <= y0 + TY + 1) {
+                const uint32_t pn = xc + t.sy * j;
+                R.g = ld(agg, pn);
+                if (j >= y0 - 1 && j <= y0 + TY) {
+                    R.iv = ld(dinv, pn);
+                    R.r = ld(r, pn);
+                    if (LW) {
+                        R.w = ld(twf<V>(t), pn);
+                        R.d = ld(tdiag<V>(t), pn);
+                    }
+                }
+            }
+        };
+        Row R0, R1;                          // rows j, j + 1 (read ahead)
+        row(y0 - 2, R0);
+        row(y0 - 1, R1);
+        V t0v = R0.g >= 0 ? ld(ec, (uint32_t)R0.g) : V(0);   // gathered a row ahead
+        // rolling rows: t (j-2, j-1), zt (j-3, j-2), 1 / d and r and LW
+        // weights of rows j-2, j-1
+        V ta = V(0), tb = V(0), zta = V(0), ztb = V(0);
+        V iva = V(0), ivb = V(0), wa = V(0), wb = V(0), da = V(0), db = V(0);
+        double ra = 0.0, rb = 0.0;
+#pragma unroll 1
+        for (int j = y0 - 2; j <= y0 + TY + 1; ++j) {
+            Row R2;
+            row(j + 2, R2);
+            const V t1v = R1.g >= 0 ? ld(ec, (uint32_t)R1.g) : V(0);
+            // row j - 1: zt
+            const V tlr = from_left(tb) + from_right(tb);
+            V ztc = V(0);
+            if (j >= y0 && ivb != V(0)) {
+                const V z1 = LW ? wb * (V)rb : wV * (V)rb * ivb;
+                ztc = z1 + ((V(1) - wV) * tb + swV * (tlr + (ta + t0v)) * ivb);
+            }
+            // row j - 2: z
+            const V zlr = from_left(ztb) + from_right(ztb);
+            if (j >= y0 + 2 && inner && iva != V(0)) {
+                const V nb = zlr + (zta + ztc);
+                const V rr = (V)ra;
+                const V zv = LW ? ztb + wa * (rr - (da * ztb - sV * nb)) : (V(1) - wV) * ztb + wV * (rr + sV * nb) * iva;
+                st(z, (uint32_t)(xc + t.sy * (j - 2)), zv);
+                part += ra * (double)zv;
+            }
+            ta = tb; tb = t0v;
+            zta = ztb; ztb = ztc;
+            iva = ivb; ivb = R0.iv;
+            ra = rb; rb = R0.r;
+            wa = wb; wb = R0.w;
+            da = db; db = R0.d;
+            t0v = t1v;
+            R0 = R1;
+            R1 = R2;
+        }
+    }
+    block_partial<TNT>(part, part_rz);
+}
+
 // out = b - A x (padded fields), partial ||out||^2.
 __global__ void __launch_bounds__(NT) k_fine_resid(FineArgs f, const double* __restrict__ bp,
                                                    const double* __restrict__ x, double* __restrict__ out,
@@ -509,8 +993,8 @@ __global__ void __launch_bounds__(NT) k_fine_norm2(FineArgs f, const double* __r
 __global__ void __launch_bounds__(NT) k_finalize_init(PcgScalars* sc, const double* __restrict__ part_bb,
                                                       const double* __restrict__ part_rr, int np, double tol,
                                                       int iters) {
-    const double bb = block_total(part_bb, np);
-    const double rr = block_total(part_rr, np);
+    double bb, rr;
+    block_total2(part_bb, part_rr, np, &bb, &rr);
     if (threadIdx.x == 0) {
         sc->bb = bb;
         sc->rr = rr;
@@ -741,8 +1225,10 @@ __global__ void __launch_bounds__(BLOCK) k_fine_layout(const int64_t* __restrict
                                                        GridDims d, int px, const double* __restrict__ diag0,
                                                        const int32_t* __restrict__ agg0, int has_agg,
                                                        int32_t* __restrict__ fine_pad,
-                                                       double* __restrict__ diag_p, int32_t* __restrict__ agg_p,
-                                                       int32_t* __restrict__ strip_flag, int strip_w) {
+                                                       double* __restrict__ diag_p, double* __restrict__ dinv_p,
+                                                       int32_t* __restrict__ agg_p,
+                                                       int32_t* __restrict__ strip_flag, int strip_w,
+                                                       int32_t* __restrict__ tile_flag, int tile_ntx) {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= nunk) return;
     const int64_t n = fine_nodes[k];
@@ -751,8 +1237,44 @@ __global__ void __launch_bounds__(BLOCK) k_fine_layout(const int64_t* __restrict
     const int64_t pidx = i + (int64_t)px * row;
     fine_pad[k] = (int32_t)pidx;
     diag_p[pidx] = diag0[k];
+    dinv_p[pidx] = 1.0 / diag0[k];
     agg_p[pidx] = has_agg ? agg0[k] : -1;
     strip_flag[pidx / strip_w] = 1;
+    if (tile_flag) tile_flag[(row / TY) * tile_ntx + i / TX] = 1;   // 2-D: row is j
+}
+
+// 2-D level-0 boxes: the aggregate of each of the 9 nodes, relative to the
+// box's first aggregate, 3 bits per node (7: not an unknown or off the grid).
+__global__ void __launch_bounds__(BLOCK) k_box_map2(int nbx, int nby, int nx, int ny, int px,
+                                                   const int32_t* __restrict__ cstart,
+                                                   const int32_t* __restrict__ agg_p, int32_t* __restrict__ map) {
+    const int64_t box = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (box >= (int64_t)nbx * nby) return;
+    const int bx = (int)(box % nbx), by = (int)(box / nbx);
+    const int32_t c0 = cstart[box];
+    int32_t m = 0;
+    for (int n = 0; n < 9; ++n) {
+        const int i = 3 * bx + n % 3, j = 3 * by + n / 3;
+        int32_t c = 7;
+        if (i < nx && j < ny) {
+            const int32_t a = agg_p[(int64_t)i + (int64_t)px * j];
+            if (a >= 0) c = a - c0;
+        }
+        m |= (c & 7) << (3 * n);
+    }
+    map[box] = m;
+}
+
+// 2-D level-0 boxes: omega_1 / d_1 of the box's first aggregate (the level-1
+// smoother weight that the restriction applies to its sum), 0 for a box
+// without aggregates.  omega_1 comes from the device copy of the level's
+// scalars (rho, omega per level).
+__global__ void __launch_bounds__(BLOCK) k_box_w0(int64_t nb, const int32_t* __restrict__ cstart,
+                                                 const int32_t* __restrict__ ncomp, const double* __restrict__ d1,
+                                                 const double* __restrict__ scal, double* __restrict__ w0) {
+    const int64_t box = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (box >= nb) return;
+    w0[box] = ncomp[box] > 0 ? scal[2 * 1 + 1] / d1[cstart[box]] : 0.0;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_flag_nonzero(const int32_t* __restrict__ v, int64_t n,
@@ -841,6 +1363,28 @@ static FineArgs fine_args_full(const amg_handle* H, unsigned* grid) {
     return f;
 }
 
+static TileArgs tile_args(const amg_handle* H) {
+    TileArgs t;
+    t.tiles = H->tiles;
+    t.ntiles = H->ntiles;
+    t.tpw = H->tile_tpw;
+    t.ntx = H->tile_ntx;
+    t.nx = H->d.nx;
+    t.ny = H->d.ny;
+    t.sy = H->px;
+    t.s = H->d.s;
+    t.diag = H->diag_p;
+    t.diag32 = H->diag_p32;
+    t.dinv = H->dinv_p;
+    t.dinv32 = H->dinv_p32;
+    t.wf = H->wf_on ? H->wf : nullptr;
+    t.wf32 = H->wf_on ? H->wf32 : nullptr;
+    return t;
+}
+
+// The 2-D fine level of hierarchies with a coarse level runs on tiles.
+static bool use_tiles(const amg_handle* H) { return H->ntiles > 0 && H->d.dim == 2 && H->nlev > 1; }
+
 static BoxArgs box_args(const amg_handle* H) {
     BoxArgs b;
     const Level& L0 = H->lev[0];
@@ -854,6 +1398,9 @@ static BoxArgs box_args(const amg_handle* H) {
     b.cstart = L0.box_cstart;
     b.ncomp = L0.box_ncomp;
     b.agg = H->agg_p;
+    b.map = H->box_map0;
+    b.w0 = H->box_w0;
+    b.w0_32 = H->box_w0_32;
     return b;
 }
 
@@ -1011,6 +1558,19 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
     const FineBufs<V> fb = fine_bufs<V>(H);
     const LevelView<V> L1 = view<V>(H->lev[1]);
     const double w0 = H->lev[0].omega;
+    if (use_tiles(H)) {
+        const TileArgs t = tile_args(H);
+        V* sv1 = H->nlev > 2 ? L1.sv : nullptr;
+        EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_t2_xr_restrict<V, LW, false>), G, dim3(TNT), 0, t, box_args(H),
+                        (double*)nullptr, r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, w0,
+                        (const double*)nullptr, (const double*)nullptr, np, (double*)nullptr, L1.rv,
+                        (const V*)L1.diag, H->lev[1].omega, sv1, sc);
+        EB_TRY(enqueue_coarse<V>(H, s));
+        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW>), G, dim3(TNT), 0, t, w0, (const int32_t*)H->agg_p,
+                        (const V*)L1.ev, r, z, rz_out, (const double*)nullptr, np, sc);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
     EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_fine_down<V, LW>), G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr,
                     np);
     if (H->d.dim == 2)
@@ -1049,10 +1609,26 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
     double* rz_out = H->red.rz[k & 1];
     PcgScalars* sc = H->sc;
-    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<V>, G, dim3(NT), 0, f, fb.z, pold, pnew, H->q, rz_cur, rz_prev,
-                    np, H->red.pq, sc);
     const double w0 = H->lev[0].omega;
     const LevelView<V> L1 = view<V>(H->lev[1]);
+    if (use_tiles(H)) {
+        const TileArgs t = tile_args(H);
+        V* sv1 = H->nlev > 2 ? L1.sv : nullptr;
+        EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_t2_pspmv<V>, G, dim3(TNT), 0, t, (const V*)fb.z, (const double*)pold,
+                        pnew, H->q, rz_cur, rz_prev, np, H->red.pq, sc);
+        EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_t2_xr_restrict<V, LW, true>), G, dim3(TNT), 0, t, box_args(H), H->x,
+                        (const double*)rin, rout, (const double*)pnew, (const double*)H->q, w0, rz_cur,
+                        (const double*)H->red.pq, np, H->red.rr, L1.rv, (const V*)L1.diag, H->lev[1].omega, sv1,
+                        sc);
+        EB_TRY(enqueue_coarse<V>(H, s));
+        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW>), G, dim3(TNT), 0, t, w0,
+                        (const int32_t*)H->agg_p, (const V*)L1.ev, (const double*)rout, fb.z, rz_out,
+                        (const double*)H->red.rr, np, sc);
+        EB_LAUNCH_CHECK();
+        return EB_OK;
+    }
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<V>, G, dim3(NT), 0, f, fb.z, pold, pnew, H->q, rz_cur, rz_prev,
+                    np, H->red.pq, sc);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
                     w0, rz_cur, H->red.pq, np, H->red.rr, sc);
     if (H->d.dim == 2)
@@ -1183,6 +1759,8 @@ static int copy_to_f32(const double* src, int64_t n, float** dst, hipStream_t s)
 int ensure_fp32(amg_handle* H, hipStream_t s) {
     if (H->fp32_ready) return EB_OK;
     EB_TRY(copy_to_f32(H->diag_p, H->npad, &H->diag_p32, s));
+    EB_TRY(copy_to_f32(H->dinv_p, H->npad, &H->dinv_p32, s));
+    if (H->box_w0) EB_TRY(copy_to_f32(H->box_w0, (int64_t)H->lev[0].nb[0] * H->lev[0].nb[1], &H->box_w0_32, s));
     EB_TRY(dalloc_n(&H->res32, H->npad, s));
     EB_TRY(dalloc_n(&H->zt32, H->npad, s));
     EB_TRY(dalloc_n(&H->z32, H->npad, s));
@@ -1229,20 +1807,32 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     H->strip_w = d.dim == 2 ? 64 : 32;
     const int64_t npad = H->npad;
     const int64_t nunk = H->n_fine;
-    EB_TRY(dalloc_n(&H->dcount, 2, s));
+    EB_TRY(dalloc_n(&H->dcount, 3, s));
     EB_TRY(dalloc_n(&H->fine_pad, nunk, s));
     EB_TRY(dalloc_n(&H->diag_p, npad, s));
+    EB_TRY(dalloc_n(&H->dinv_p, npad, s));
     EB_TRY(dalloc_n(&H->agg_p, npad, s));
     const int64_t nstrip_all = npad / H->strip_w;
     int32_t* sflag = nullptr;
     EB_TRY(dalloc_n(&sflag, nstrip_all, s));
+    // 2-D: tiles of the tile kernels (their origins are multiples of 3, so
+    // a tile holds whole level-0 boxes)
+    // (the tile kernels address padded fields by 32-bit byte offsets)
+    const bool tiled = d.dim == 2 && H->nlev > 1 && npad < ((int64_t)1 << 29);
+    H->tile_ntx = tiled ? (d.nx + TX - 1) / TX : 0;
+    const int64_t ntile_all = tiled ? (int64_t)H->tile_ntx * ((d.ny + TY - 1) / TY) : 0;
+    int32_t* tflag = nullptr;
+    if (tiled) EB_TRY(dalloc_n(&tflag, ntile_all, s));
     // Fields read at neighbours without a guard must be zero off unknowns
     // (kernels only ever write unknowns); the others are fully written first
     // or read only where the diagonal is non-zero.
-    double** zeroed[] = {&H->x, &H->z, &H->zt, &H->p[0], &H->p[1]};
+    // The residuals and q are among them: the per-point smoother weights
+    // multiply neighbour values by a weight that is 0 off unknowns, and a
+    // recycled block could hold NaN there (0 * NaN = NaN).
+    double** zeroed[] = {&H->x, &H->z, &H->zt, &H->p[0], &H->p[1], &H->rr[0], &H->rr[1], &H->q};
     for (double** v : zeroed) EB_TRY(dalloc_n(v, npad, s));
     {
-        const FillSpec f[] = {{H->dcount, 2 * sizeof(int32_t), 0u},
+        const FillSpec f[] = {{H->dcount, 3 * sizeof(int32_t), 0u},
                               {H->diag_p, sizeof(double) * npad, 0u},
                               {H->agg_p, sizeof(int32_t) * npad, 0xffffffffu},    // -1
                               {sflag, sizeof(int32_t) * nstrip_all, 0u},
@@ -1250,14 +1840,41 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
                               {H->z, sizeof(double) * npad, 0u},
                               {H->zt, sizeof(double) * npad, 0u},
                               {H->p[0], sizeof(double) * npad, 0u},
-                              {H->p[1], sizeof(double) * npad, 0u}};
-        EB_TRY(fill_words(f, 9, s));
+                              {H->p[1], sizeof(double) * npad, 0u},
+                              {H->rr[0], sizeof(double) * npad, 0u},
+                              {H->rr[1], sizeof(double) * npad, 0u},
+                              {H->q, sizeof(double) * npad, 0u}};
+        EB_TRY(fill_words(f, 12, s));
+        const FillSpec ft[] = {{H->dinv_p, sizeof(double) * npad, 0u},
+                               {tflag, sizeof(int32_t) * ntile_all, 0u}};
+        EB_TRY(fill_words(ft, tiled ? 2 : 1, s));
     }
     Level& L0 = H->lev[0];
     hipLaunchKernelGGL(k_fine_layout, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, H->fine_nodes, nunk, d, H->px, L0.diag,
-                       L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->diag_p, H->agg_p, sflag,
-                       H->strip_w);
+                       L0.agg, L0.agg != nullptr ? 1 : 0, H->fine_pad, H->diag_p, H->dinv_p, H->agg_p, sflag,
+                       H->strip_w, tflag, H->tile_ntx);
     EB_LAUNCH_CHECK();
+    if (tiled) {
+        const Level& B0 = H->lev[0];
+        const int64_t nb = (int64_t)B0.nb[0] * B0.nb[1];
+        EB_TRY(dalloc_n(&H->box_map0, nb, s));
+        EB_TRY(dalloc_n(&H->box_w0, nb, s));
+        hipLaunchKernelGGL(k_box_map2, dim3(grid_for(nb)), dim3(BLOCK), 0, s, B0.nb[0], B0.nb[1], d.nx, d.ny, H->px,
+                           (const int32_t*)B0.box_cstart, (const int32_t*)H->agg_p, H->box_map0);
+        hipLaunchKernelGGL(k_box_w0, dim3(grid_for(nb)), dim3(BLOCK), 0, s, nb, (const int32_t*)B0.box_cstart,
+                           (const int32_t*)B0.box_ncomp, (const double*)H->lev[1].diag, (const double*)H->dscal,
+                           H->box_w0);
+        EB_LAUNCH_CHECK();
+        int32_t* off = nullptr;
+        EB_TRY(dalloc_n(&off, ntile_all, s));
+        EB_TRY(scan_i32_dev(tflag, off, ntile_all, H->dcount + 2, s));
+        EB_TRY(dalloc_n(&H->tiles, ntile_all, s));
+        hipLaunchKernelGGL(k_compact_list, dim3(grid_for(ntile_all)), dim3(BLOCK), 0, s, tflag, off, ntile_all,
+                           H->tiles);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(off, s));
+        EB_TRY(dfree(tflag, s));
+    }
     {
         int32_t* off = nullptr;
         EB_TRY(dalloc_n(&off, nstrip_all, s));
@@ -1287,7 +1904,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
             return EB_ENOSPC;
         }
     }
-    double** plain[] = {&H->rr[0], &H->rr[1], &H->q, &H->res, &H->bvec};
+    double** plain[] = {&H->res, &H->bvec};
     for (double** v : plain) EB_TRY(dalloc_n(v, npad, s));
     for (int l = 0; l < H->nlev; ++l) {
         Level& L = H->lev[l];
@@ -1301,7 +1918,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     EB_TRY(dalloc_n(&H->sc, 1, s));
     H->sc_host = &H->sc_mirror;   // pageable, per handle (polled a few times per solve)
     double** parts[] = {&H->red.pq, &H->red.rr, &H->red.rz[0], &H->red.rz[1], &H->red.aux, &H->red.aux2};
-    for (double** v : parts) EB_TRY(dalloc_n(v, MAX_PARTS, s));
+    for (double** v : parts) EB_TRY(dalloc_n(v, PART_CAP, s));
     EB_HIP(hipEventCreate(&H->ev0));
     EB_HIP(hipEventCreate(&H->ev1));
     return EB_OK;
@@ -1311,9 +1928,19 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
 // H->nstrips / H->nboxes0 by the caller's single synchronisation).
 int solve_layout_finish(amg_handle* H, hipStream_t s) {
     (void)s;
-    const int64_t nthreads = H->nlev == 1 ? H->n_fine : H->nstrips * H->strip_w;
-    int64_t np = (nthreads + NT - 1) / NT;
-    if (np > MAX_PARTS) np = MAX_PARTS;
+    int64_t np;
+    if (H->ntiles > 0) {
+        // the tile kernels' fixed grid: TWB wavefronts per block, each a
+        // contiguous range of tile_tpw tiles; the strip kernels share the
+        // same partial count
+        const int64_t tpw = (H->ntiles + (int64_t)TWB * MAX_TILE_PARTS - 1) / ((int64_t)TWB * MAX_TILE_PARTS);
+        H->tile_tpw = (int)tpw;
+        np = (H->ntiles + tpw * TWB - 1) / (tpw * TWB);
+    } else {
+        const int64_t nthreads = H->nlev == 1 ? H->n_fine : H->nstrips * H->strip_w;
+        np = (nthreads + NT - 1) / NT;
+        if (np > MAX_PARTS) np = MAX_PARTS;
+    }
     np = (np + NUM_XCD - 1) / NUM_XCD * NUM_XCD;   // whole XCD groups
     if (np < NUM_XCD) np = NUM_XCD;
     H->red.nparts = (int)np;
@@ -1629,7 +2256,7 @@ extern "C" int amg_smoother_loss_grad(amg_handle_t* H, int32_t m, const double* 
     double* dloss = nullptr;
     double* part_den = nullptr;
     EB_TRY(dalloc_n(&dloss, 1, s));
-    EB_TRY(dalloc_n(&part_den, MAX_PARTS, s));
+    EB_TRY(dalloc_n(&part_den, PART_CAP, s));
     EB_HIP(hipMemsetAsync(dloss, 0, sizeof(double), s));
     hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
     for (int j = 0; j < m; ++j) {

@@ -220,6 +220,20 @@ int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, 
 int eb_segment_dots(const double* w, const double* x, int32_t nfields, int64_t field_nodes, int64_t row_len,
                     int32_t nseg, const int32_t* seg_rows, double* out, void* stream);
 
+/* eb_segment_dots for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops of a shape optimisation, harnesses
+ * that forbid hipMalloc): the same arguments, kernels and results (bit for
+ * bit), but the segment bounds, chunk partials and results live in a fixed
+ * 8 MiB device array of the library, one per GPU, held until the process
+ * ends; the call makes no device allocation or free.  The array must hold
+ * 16 nseg + 8 nfields nseg (nchunk + 1) bytes, nchunk = ceil(longest segment
+ * in nodes / 2048): EB_ENOSPC otherwise (nothing runs).  Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on one GPU (different
+ * streams or threads) race; each call writes all of the array it reads.
+ * Synchronises `stream`.                                                      */
+int eb_segment_dots_noalloc(const double* w, const double* x, int32_t nfields, int64_t field_nodes,
+                            int64_t row_len, int32_t nseg, const int32_t* seg_rows, double* out, void* stream);
+
 /* Build the aggregation AMG hierarchy of A (+ sigma I) on the device
  * (Algorithm 2 step 4 preconditioner).  *H receives a new handle (host).
  * p may be NULL for defaults.  Synchronises `stream` (level sizes are read

@@ -24,7 +24,7 @@ EXPORTS = [
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
     "amg_smoother_samples", "amg_smoother_loss_grad", "eb_wave_rhs", "eb_stencil_combine",
     "pcg_solve_islands", "pcg_batched_set_launch_shape", "pcg_batched_launch_shape", "eb_set_iteration_graphs",
-    "eb_check_spd", "eb_segment_dots",
+    "eb_check_spd", "eb_segment_dots", "eb_segment_dots_noalloc",
 ]
 
 KERNEL_IDS = {"pcg_spmv": 0, "pcg_xr_down": 1, "fine_down": 2, "fine_restrict": 3, "fine_up": 4,
@@ -95,6 +95,7 @@ def lib():
     L.eb_wave_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
     L.eb_stencil_combine.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, dbl, vp, dbl, vp, dbl, vp, vp, vp]
     L.eb_segment_dots.argtypes = [vp, vp, C.c_int32, i64, i64, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dbl), vp]
+    L.eb_segment_dots_noalloc.argtypes = L.eb_segment_dots.argtypes
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.pcg_solve_batched.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]

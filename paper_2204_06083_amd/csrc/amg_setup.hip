@@ -1323,6 +1323,98 @@ static int accumulate_product(int mode, AccArgs args, int64_t nrows, int64_t row
     return free_packed(R, s);
 }
 
+// ---------------------------------------------------------- sliced ELL
+// Rows of the source: CSR (rowptr) or packed product rows (start, cnt).
+struct RowSrc {
+    const int32_t* rowptr;
+    const int32_t* start;
+    const int32_t* cnt;
+    const int32_t* col;
+    const double* val;
+    __device__ int32_t first(int64_t r) const { return rowptr ? rowptr[r] : start[r]; }
+    __device__ int32_t len(int64_t r) const { return rowptr ? rowptr[r + 1] - rowptr[r] : cnt[r]; }
+};
+
+// entries of each slice: 64 x its longest row (one lane per row, the
+// slice's maximum across its wavefront)
+__global__ void __launch_bounds__(BLOCK) k_sell_width(RowSrc M, int64_t n, int64_t nslices,
+                                                      int32_t* __restrict__ slice_entries) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int32_t w = r < n ? M.len(r) : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, WAVE));
+    const int64_t sl = r / 64;
+    if ((threadIdx.x & (WAVE - 1)) == 0 && sl < nslices) slice_entries[sl] = 64 * w;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_sell_fill(RowSrc M, int64_t n, const int32_t* __restrict__ sptr,
+                                                     int32_t* __restrict__ col, double* __restrict__ val) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= n) return;
+    const int64_t sl = r / 64;
+    const int32_t base = sptr[sl] + (int32_t)(r % 64);
+    const int32_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+    const int32_t f = M.first(r), m = M.len(r);
+    int32_t last = 0;
+    for (int32_t k = 0; k < w; ++k) {
+        if (k < m) {
+            last = M.col[f + k];
+            col[base + 64 * k] = last;
+            val[base + 64 * k] = M.val[f + k];
+        } else {
+            col[base + 64 * k] = last;
+            val[base + 64 * k] = 0.0;
+        }
+    }
+}
+
+// Transpose of a matrix given by rows (CSR or packed), into CSR: counts per
+// column, then each entry placed by an atomic slot (rows sorted afterwards).
+__global__ void __launch_bounds__(BLOCK) k_trs_count(RowSrc M, int64_t n, int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t f = M.first(i), m = M.len(i);
+    for (int32_t k = 0; k < m; ++k) atomicAdd(&cnt[M.col[f + k]], 1);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_trs_fill(RowSrc M, int64_t n, const int32_t* __restrict__ t_rowptr,
+                                                    int32_t* __restrict__ fill, int32_t* __restrict__ t_col,
+                                                    double* __restrict__ t_val) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t f = M.first(i), m = M.len(i);
+    for (int32_t k = 0; k < m; ++k) {
+        const int32_t c = M.col[f + k];
+        const int32_t pos = t_rowptr[c] + atomicAdd(&fill[c], 1);
+        t_col[pos] = (int32_t)i;
+        t_val[pos] = M.val[f + k];
+    }
+}
+
+// Sliced ELL copy of an n-row matrix whose rows have at most `bound` entries
+// (storage sized by the bound: no host synchronisation).
+static int build_sell(const RowSrc& M, int64_t n, int64_t bound, Sell* out, hipStream_t s) {
+    const int64_t nslices = (n + 63) / 64;
+    out->cap = nslices * 64 * (bound > 0 ? bound : 1);
+    if (out->cap >= ((int64_t)1 << 31)) {
+        set_error("a sliced matrix bound exceeds 2^31 entries");
+        return EB_ENOSPC;
+    }
+    int32_t* ent = nullptr;
+    EB_TRY(dalloc_n(&ent, nslices, s));
+    EB_TRY(dalloc_n(&out->sptr, nslices + 1, s));
+    EB_TRY(dalloc_n(&out->col, out->cap, s));
+    EB_TRY(dalloc_n(&out->val, out->cap, s));
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(nslices * 64)), dim3(BLOCK), 0, s, M, n, nslices, ent);
+    EB_LAUNCH_CHECK();
+    EB_TRY(scan_i32_dev(ent, out->sptr, nslices, out->sptr + nslices, s));
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, (const int32_t*)out->sptr,
+                       out->col, out->val);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(ent, s));
+    return EB_OK;
+}
+
 static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
     Level& L = H->lev[l];
     L.is_coarsest = 1;
@@ -1561,6 +1653,39 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     args.centre_div = 1;
     EB_TRY(accumulate_product(ACC_RAP, args, nc, slots, &C.a_rowptr, &C.a_col, &C.a_val, s));
     C.row_bound = slots;
+    if (l >= 1) {
+        // sliced copies of A, P and A P for the coarse V-cycle kernels
+        RowSrc ma = {L.a_rowptr, nullptr, nullptr, L.a_col, L.a_val};
+        RowSrc mp = {L.p_rowptr, nullptr, nullptr, L.p_col, L.p_val};
+        RowSrc map = {nullptr, ap.start, ap.cnt, ap.col, ap.val};
+        EB_TRY(build_sell(ma, n, L.row_bound, &L.sa, s));
+        EB_TRY(build_sell(mp, n, p_bound, &L.sp, s));
+        EB_TRY(build_sell(map, n, slots, &L.sap, s));
+        // R A = P^T A = (A P)^T (A symmetric): rows of level l + 1 over level-l
+        // columns, sorted, for the one-pass residual and restriction
+        L.ra_cap = n * slots;
+        int32_t* tcnt = nullptr;
+        int32_t* tfill = nullptr;
+        EB_TRY(dalloc_n(&tcnt, nc, s));
+        EB_TRY(dalloc_n(&tfill, nc, s));
+        {
+            const FillSpec f[] = {{tcnt, sizeof(int32_t) * nc, 0u}, {tfill, sizeof(int32_t) * nc, 0u}};
+            EB_TRY(fill_words(f, 2, s));
+        }
+        hipLaunchKernelGGL(k_trs_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, tcnt);
+        EB_LAUNCH_CHECK();
+        EB_TRY(rowptr_from_counts(tcnt, nc, &L.ra_rowptr, s));
+        EB_TRY(dalloc_n(&L.ra_col, L.ra_cap, s));
+        EB_TRY(dalloc_n(&L.ra_val, L.ra_cap, s));
+        hipLaunchKernelGGL(k_trs_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, (const int32_t*)L.ra_rowptr,
+                           tfill, L.ra_col, L.ra_val);
+        EB_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)nc), dim3(WAVE), 0, s, (const int32_t*)L.ra_rowptr, L.ra_col,
+                           L.ra_val, nc);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(tcnt, s));
+        EB_TRY(dfree(tfill, s));
+    }
     EB_TRY(free_packed(ap, s));
     EB_TRY(dalloc_n(&C.diag, nc, s));
     hipLaunchKernelGGL(k_extract_diag, dim3(grid_for(nc)), dim3(BLOCK), 0, s, C.a_rowptr, C.a_col, C.a_val, nc,
@@ -1574,6 +1699,14 @@ static void free_level(Level& L, hipStream_t s) {
                     L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp,
                     L.sv, L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
     for (void* p : ptrs) (void)dfree(p, s);
+    for (Sell* m : {&L.sa, &L.sp, &L.sap}) {
+        void* q[] = {m->sptr, m->col, m->val, m->val32};
+        for (void* p : q) (void)dfree(p, s);
+    }
+    {
+        void* q[] = {L.ra_rowptr, L.ra_col, L.ra_val, L.ra_val32};
+        for (void* p : q) (void)dfree(p, s);
+    }
     L = Level();
 }
 

@@ -8,6 +8,20 @@ namespace eb {
 
 constexpr int MAX_LEVELS = 24;
 
+// Sliced ELL copy of a sparse matrix for the V-cycle: slices of 64
+// consecutive rows (one wavefront, one lane per row), each stored slot-major
+// with the width of its longest row: entry k of row r sits at
+// sptr[r / 64] + 64 k + r % 64.  Rows shorter than their slice are padded
+// with value 0 and the row's last column (column 0 for an empty row), so every
+// read is in bounds and adds nothing.
+struct Sell {
+    int32_t* sptr = nullptr;   // nslices + 1 entry offsets
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    float* val32 = nullptr;    // single-precision V-cycle copy (made on first use)
+    int64_t cap = 0;           // entries allocated (a bound on sptr[nslices])
+};
+
 struct Level {
     int64_t n = 0, nnz_a = 0, nnz_p = 0, nnz_r = 0;
     double rho = 0.0, omega = 0.0;
@@ -29,6 +43,11 @@ struct Level {
     int32_t* box_cstart = nullptr;  // nboxes: first coarse unknown of each box
     int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
     double* dense_inv = nullptr; // coarsest: n x n
+    // sliced ELL copies of A, P and A P for the V-cycle (levels >= 1 with a
+    // coarser level), and R A = (A P)^T in CSR (rows sorted)
+    Sell sa, sp, sap;
+    int32_t* ra_rowptr = nullptr; int32_t* ra_col = nullptr; double* ra_val = nullptr; float* ra_val32 = nullptr;
+    int64_t ra_cap = 0;
     // solve vectors (levels >= 1); sv = omega rv / diag, written with rv by the
     // restriction that produces it (each consumer then gathers one value
     // instead of two and divides no more)

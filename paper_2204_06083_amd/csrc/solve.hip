@@ -1097,6 +1097,31 @@ __global__ void __launch_bounds__(NT) k_csr_post(int64_t n, Csr<V> A, const V* _
 
 // Residual and restriction in one pass:
 //   rv_c[I] = sum_{j in R row I} R_Ij (rv_j - sum_e a_je omega rv_e / d_e).
+// The inner row of A is read GB entries at a time (their columns and values,
+// then their gathers, then the sums in entry order), so a row costs a few
+// memory round trips instead of one per entry.
+constexpr int GB = 8;
+
+template <class V>
+__device__ inline V row_dot(const Csr<V>& M, int e0, int e1, const V* __restrict__ x) {
+    V acc = V(0);
+    for (int f0 = e0; f0 < e1; f0 += GB) {
+        int k[GB];
+        V a[GB], xv[GB];
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            k[u] = f0 + u < e1 ? M.col[f0 + u] : -1;
+            a[u] = f0 + u < e1 ? M.val[f0 + u] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < GB; ++u) xv[u] = k[u] >= 0 ? x[k[u]] : V(0);
+#pragma unroll
+        for (int u = 0; u < GB; ++u)
+            if (f0 + u < e1) acc += a[u] * xv[u];
+    }
+    return acc;
+}
+
 template <int LPR, class V>
 __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V> A, const V* __restrict__ sv,
                                                     const V* __restrict__ rv, V* __restrict__ rv_c,
@@ -1109,11 +1134,7 @@ __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V>
     V acc = V(0);
     for (int e = R.rowptr[row] + lane; e < R.rowptr[row + 1]; e += LPR) {
         const int j = R.col[e];
-        V az = V(0);
-        for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
-            const int k = A.col[f];
-            az += A.val[f] * sv[k];
-        }
+        const V az = row_dot(A, A.rowptr[j], A.rowptr[j + 1], sv);
         acc += R.val[e] * (rv[j] - az);
     }
     acc = segment_sum<LPR>(acc);
@@ -1126,6 +1147,7 @@ __global__ void __launch_bounds__(NT) k_coarse_down(int64_t nc, Csr<V> R, Csr<V>
 // Prolongation and post-smoothing in one pass:
 //   zt_j = omega rv_j / d_j + sum_{P row j} P_jJ ev_c[J];
 //   ev[i] = zt_i + omega (rv_i - sum_{A row i} a_ij zt_j) / d_i.
+// (rows of P read as in k_coarse_down, GB entries at a time)
 template <int LPR, class V>
 __global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P, const V* __restrict__ diag,
                                                   V omega, const V* __restrict__ rv, const V* __restrict__ sv,
@@ -1138,16 +1160,159 @@ __global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P,
     V acc = V(0);
     for (int e = A.rowptr[row] + lane; e < A.rowptr[row + 1]; e += LPR) {
         const int j = A.col[e];
-        V zt = sv[j];
-        for (int g = P.rowptr[j]; g < P.rowptr[j + 1]; ++g) zt += P.val[g] * ev_c[P.col[g]];
+        const V zt = sv[j] + row_dot(P, P.rowptr[j], P.rowptr[j + 1], ev_c);
         acc += A.val[e] * zt;
     }
     acc = segment_sum<LPR>(acc);
     if (lane == 0) {
-        V zi = sv[row];
-        for (int g = P.rowptr[row]; g < P.rowptr[row + 1]; ++g) zi += P.val[g] * ev_c[P.col[g]];
+        const V zi = sv[row] + row_dot(P, P.rowptr[row], P.rowptr[row + 1], ev_c);
         ev[row] = zi + omega * (rv[row] - acc) / diag[row];
     }
+}
+
+// Coarse levels in sliced ELL (one lane per row, slot-major slices of 64
+// rows): a row's entries are read as coalesced slots, GB at a time, then
+// gathered, then summed in column order.
+template <class V>
+struct SellV {
+    const int32_t* sptr;
+    const int32_t* col;
+    const V* val;
+};
+
+// Residual after pre-smoothing and restriction in one pass, with R A stored:
+//   rv_c = R (rv - A sv) = R rv - (R A) sv,  sv = omega rv / d.
+// LPR lanes share a coarse row; a lane issues the reads of UR entries of R
+// and UQ of R A (columns and values, then the gathers) before it adds them.
+template <int LPR, class V>
+__global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA, const V* __restrict__ rv,
+                                                const V* __restrict__ sv, V* __restrict__ rv_c,
+                                                const V* __restrict__ dg_c, V omega_c, V* __restrict__ sv_c,
+                                                const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (row >= nc) return;
+    constexpr int UR = 2, UQ = 2;
+    const int r0 = R.rowptr[row], r1 = R.rowptr[row + 1];
+    const int q0 = RA.rowptr[row], q1 = RA.rowptr[row + 1];
+    V acc = V(0);
+    for (int br = r0 + lane, bq = q0 + lane; br < r1 || bq < q1; br += UR * LPR, bq += UQ * LPR) {
+        int kr[UR], kq[UQ];
+        V ar[UR], aq[UQ], xr[UR], xq[UQ];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int e = br + u * LPR;
+            kr[u] = e < r1 ? R.col[e] : -1;
+            ar[u] = e < r1 ? R.val[e] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const int e = bq + u * LPR;
+            kq[u] = e < q1 ? RA.col[e] : -1;
+            aq[u] = e < q1 ? RA.val[e] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) xr[u] = kr[u] >= 0 ? rv[kr[u]] : V(0);
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) xq[u] = kq[u] >= 0 ? sv[kq[u]] : V(0);
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+            if (kr[u] >= 0) acc += ar[u] * xr[u];
+#pragma unroll
+        for (int u = 0; u < UQ; ++u)
+            if (kq[u] >= 0) acc -= aq[u] * xq[u];
+    }
+    acc = segment_sum<LPR>(acc);
+    if (lane == 0) {
+        rv_c[row] = acc;
+        if (sv_c) sv_c[row] = omega_c * acc / dg_c[row];
+    }
+}
+
+// Reads of up to W slots of one row of a sliced matrix (columns and values),
+// issued together; entries past W are left to sell_tail.
+template <class V, int W>
+struct SellRow {
+    int k[W];
+    V a[W];
+    int e0, e1;
+};
+
+template <class V, int W>
+__device__ inline void sell_load(const SellV<V>& M, int slice, int lane, SellRow<V, W>& r) {
+    r.e0 = M.sptr[slice] + lane;
+    r.e1 = M.sptr[slice + 1];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        const int e = r.e0 + 64 * u;
+        r.k[u] = e < r.e1 ? M.col[e] : -1;
+        r.a[u] = e < r.e1 ? M.val[e] : V(0);
+    }
+}
+
+template <class V, int W>
+__device__ inline void sell_gather(const SellRow<V, W>& r, const V* __restrict__ x, V* xv) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) xv[u] = r.k[u] >= 0 ? x[r.k[u]] : V(0);
+}
+
+// sum of the loaded slots in column order, then any entries past W
+template <class V, int W>
+__device__ inline V sell_sum(const SellV<V>& M, const SellRow<V, W>& r, const V* xv, const V* __restrict__ x) {
+    V acc = V(0);
+#pragma unroll
+    for (int u = 0; u < W; ++u)
+        if (r.k[u] >= 0) acc += r.a[u] * xv[u];
+    for (int e = r.e0 + 64 * W; e < r.e1; e += 64) acc += M.val[e] * x[M.col[e]];
+    return acc;
+}
+
+// res = rv - A sv (sv = omega rv / d): the residual after pre-smoothing.
+template <class V, int WA>
+__global__ void __launch_bounds__(NT) k_sell_resid(int64_t n, SellV<V> A, const V* __restrict__ sv,
+                                                   const V* __restrict__ rv, V* __restrict__ res,
+                                                   const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));   // one slice per wavefront
+    if (row >= n) return;
+    SellRow<V, WA> ra;
+    sell_load(A, slice, (int)(row & 63), ra);
+    const V rvr = rv[row];
+    V xa[WA];
+    sell_gather(ra, sv, xa);
+    res[row] = rvr - sell_sum(A, ra, xa, sv);
+}
+
+// Prolongation and post-smoothing in one pass, with A P stored:
+//   zt = sv + P ev_c,  ev = zt + omega (rv - A zt) / d
+//      = sv + P ev_c + omega (rv - A sv - (A P) ev_c) / d.
+// The slot reads of P, A and A P are issued together, then their gathers.
+template <class V, int WP, int WA>
+__global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> P, SellV<V> AP,
+                                                const V* __restrict__ diag, V omega, const V* __restrict__ rv,
+                                                const V* __restrict__ sv, const V* __restrict__ ev_c,
+                                                V* __restrict__ ev, const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));
+    if (row >= n) return;
+    const int lane = (int)(row & 63);
+    SellRow<V, WP> rp;
+    SellRow<V, WA> ra, rq;
+    sell_load(P, slice, lane, rp);
+    sell_load(A, slice, lane, ra);
+    sell_load(AP, slice, lane, rq);
+    const V svr = sv[row], rvr = rv[row], dr = diag[row];
+    V xp[WP], xa[WA], xq[WA];
+    sell_gather(rp, ev_c, xp);
+    sell_gather(ra, sv, xa);
+    sell_gather(rq, ev_c, xq);
+    const V pe = sell_sum(P, rp, xp, ev_c);
+    const V as = sell_sum(A, ra, xa, sv);
+    const V ape = sell_sum(AP, rq, xq, ev_c);
+    ev[row] = svr + pe + omega * (rvr - as - ape) / dr;
 }
 
 // Coarsest: ev = W rv with W the dense inverse (FP64 in either precision);
@@ -1429,16 +1594,22 @@ struct LevelView {
     V* ev;
     V* tmp;
     V* sv;
+    SellV<V> sa, sp, sap;
+    Csr<V> RA;
 };
 
 template <class V> static LevelView<V> view(const Level& L);
 template <> LevelView<double> view<double>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val}, {L.p_rowptr, L.p_col, L.p_val}, {L.r_rowptr, L.r_col, L.r_val},
-            L.diag, L.rv, L.ev, L.tmp, L.sv};
+            L.diag, L.rv, L.ev, L.tmp, L.sv,
+            {L.sa.sptr, L.sa.col, L.sa.val}, {L.sp.sptr, L.sp.col, L.sp.val}, {L.sap.sptr, L.sap.col, L.sap.val},
+            {L.ra_rowptr, L.ra_col, L.ra_val}};
 }
 template <> LevelView<float> view<float>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val32}, {L.p_rowptr, L.p_col, L.p_val32}, {L.r_rowptr, L.r_col, L.r_val32},
-            L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
+            L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32,
+            {L.sa.sptr, L.sa.col, L.sa.val32}, {L.sp.sptr, L.sp.col, L.sp.val32},
+            {L.sap.sptr, L.sap.col, L.sap.val32}, {L.ra_rowptr, L.ra_col, L.ra_val32}};
 }
 
 template <class V>
@@ -1485,7 +1656,10 @@ static bool fuse_down(const Level& L, const Level& C) {
     return ra * rr <= FUSE_DOWN_WORK;
 }
 
-// Coarse part of the V-cycle, levels 1 .. nlev-1: rv_1 -> ev_1.
+// Coarse part of the V-cycle, levels 1 .. nlev-1: rv_1 -> ev_1.  Going down,
+// each level forms its residual after pre-smoothing (sliced ELL, one lane
+// per row) and restricts it (CSR, several lanes per long row of R); going up,
+// one pass per level prolongates and post-smooths with the stored A P.
 template <class V>
 static int enqueue_coarse(amg_handle* H, hipStream_t s) {
     const PcgScalars* sc = H->sc;
@@ -1497,13 +1671,10 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         // omega rv / diag of the coarse level, for its own kernels (none on the coarsest)
         const V wc = (V)C.omega;
         V* svc = l + 1 < H->nlev - 1 ? Cv.sv : nullptr;
-        if (!fuse_down(L, C)) {
-            const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_resid, V, lpr_a, L.n, L.n, Lv.A, Lv.sv, Lv.rv, Lv.tmp, sc);
-            EB_LPR_LAUNCH(k_csr_matvec, V, lpr_r, C.n, C.n, Lv.R, Lv.tmp, Cv.rv, Cv.diag, wc, svc, sc);
-        } else {
-            EB_LPR_LAUNCH(k_coarse_down, V, lpr_r, C.n, C.n, Lv.R, Lv.A, Lv.sv, Lv.rv, Cv.rv, Cv.diag, wc, svc, sc);
-        }
+        (void)lpr_r;
+        const int lpr_d = lanes_for((double)(2 * L.nnz_r) / (double)(C.n > 0 ? C.n : 1));
+        EB_LPR_LAUNCH(k_down_ra, V, lpr_d, C.n, C.n, Lv.R, Lv.RA, (const V*)Lv.rv, (const V*)Lv.sv, Cv.rv,
+                      (const V*)Cv.diag, wc, svc, sc);
     }
     {
         const Level& Lc = H->lev[H->nlev - 1];
@@ -1515,15 +1686,14 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         const Level& L = H->lev[l];
         const Level& C = H->lev[l + 1];
         const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
-        const V w = (V)L.omega;
-        const int lpr_a = lanes_for((double)L.nnz_a / (double)(L.n > 0 ? L.n : 1));
-        if (L.n >= FUSE_BELOW) {
-            const int lpr_p = lanes_for((double)L.nnz_p / (double)(L.n > 0 ? L.n : 1));
-            EB_LPR_LAUNCH(k_csr_prolong, V, lpr_p, L.n, L.n, Lv.P, Lv.sv, Cv.ev, Lv.tmp, sc);
-            EB_LPR_LAUNCH(k_csr_post, V, lpr_a, L.n, L.n, Lv.A, Lv.diag, w, Lv.rv, Lv.tmp, Lv.ev, sc);
-        } else {
-            EB_LPR_LAUNCH(k_coarse_up, V, lpr_a, L.n, L.n, Lv.A, Lv.P, Lv.diag, w, Lv.rv, Lv.sv, Cv.ev, Lv.ev, sc);
-        }
+        if (H->d.dim == 2)
+            hipLaunchKernelGGL((k_sell_up<V, 4, 9>), dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
+                               Lv.sap, Lv.diag, (V)L.omega, (const V*)Lv.rv, (const V*)Lv.sv, (const V*)Cv.ev, Lv.ev,
+                               sc);
+        else
+            hipLaunchKernelGGL((k_sell_up<V, 8, 14>), dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
+                               Lv.sap, Lv.diag, (V)L.omega, (const V*)Lv.rv, (const V*)Lv.sv, (const V*)Cv.ev, Lv.ev,
+                               sc);
     }
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -1776,6 +1946,9 @@ int ensure_fp32(amg_handle* H, hipStream_t s) {
             EB_TRY(copy_to_f32(L.diag, L.n, &L.diag32, s));
             EB_TRY(copy_to_f32(L.p_val, L.nnz_p, &L.p_val32, s));
             EB_TRY(copy_to_f32(L.r_val, L.nnz_r, &L.r_val32, s));
+            for (Sell* m : {&L.sa, &L.sp, &L.sap})
+                if (m->val) EB_TRY(copy_to_f32(m->val, m->cap, &m->val32, s));
+            if (L.ra_val) EB_TRY(copy_to_f32(L.ra_val, L.ra_cap, &L.ra_val32, s));
         }
         EB_TRY(dalloc_n(&L.rv32, n, s));
         EB_TRY(dalloc_n(&L.sv32, n, s));

@@ -46,46 +46,91 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per fine unknown for each timed solve kernel (FP64 values,
-# int32 aggregate ids; every array touched once per launch).  The coarse-level
-# share of the restriction output / prolongation input is 8 B * n1 / n0.
-KERNEL_BYTES = {
-    # p = z + beta p_old; q = A p; (p, q): read z, p_old, d; write p, q
-    "pcg_spmv": lambda n0, n1: 40.0 * n0,
-    # x += alpha p; r_out = r_in - alpha q; res = r_out - A omega D^-1 r_out:
-    # read x, p, r_in, q, d; write x, r_out, res
-    "pcg_xr_down": lambda n0, n1: 64.0 * n0,
-    # first V-cycle only: read r, d; write res
-    "fine_down": lambda n0, n1: 24.0 * n0,
-    # r_c = P^T res: read res, d, agg; write r_c
-    "fine_restrict": lambda n0, n1: 20.0 * n0 + 8.0 * n1,
-    # zt = omega r / d + (I - omega D^-1 A) P_tent e_c: read agg, r, d; gather e_c; write zt
-    "fine_up": lambda n0, n1: 28.0 * n0 + 8.0 * n1,
-    # z = zt + omega (r - A zt) / d; (r, z): read zt, r, d; write z
-    "fine_post": lambda n0, n1: 32.0 * n0,
-}
+# Algorithmic bytes per launch of the timed solve kernels (FP64 values, int32
+# ids; every array touched once per launch), from the fine unknowns n0, the
+# level-1 unknowns n1 and the dimension.  2-D runs the band-tile kernels:
+#   pcg_spmv     p = z + beta p_old; q = A p; (p, q): read z, p_old, d; write p, q
+#   pcg_xr_down  x += alpha p; r = r - alpha q; ||r||^2; pre-smoothing residual
+#                and restriction: read x, p, r_in, q, 1/d; write x, r; per
+#                level-0 box (one per coarse unknown) its aggregate count, first
+#                aggregate, node map and omega_1/d_1 (20 B); write r_c, omega r_c/d_c
+#   fine_post    prolongation + both smoothing halves + (r, z): read aggregate
+#                id (4 B), 1/d, r; gather e_c; write z
+# 3-D runs the strip kernels (pcg_xr_down: read x, p, r_in, q, d; write x, r,
+# res; fine_post: read z_t, r, d; write z).
+def kernel_bytes(name, n0, n1, dim):
+    if name == "pcg_spmv":
+        return 40.0 * n0
+    if name == "pcg_xr_down":
+        return 56.0 * n0 + 36.0 * n1 if dim == 2 else 64.0 * n0
+    if name == "fine_post":
+        return 28.0 * n0 + 8.0 * n1 if dim == 2 else 32.0 * n0
+    raise KeyError(name)
 
 
-# Whole-solve byte model per PCG iteration (the graded solve-phase roofline):
-# the fine kernels above (FP64 V-cycle: 40 + 64 + 20 + 28 + 32 B per fine
-# unknown; single-precision V-cycle: z, res, zt and the V-cycle's diagonal
-# copy in FP32, 36 + 60 + 12 + 20 + 20 B) plus, per coarse level l >= 1 that
-# is not the coarsest, A read twice (values + column ids, row pointers), P
-# and R once, and about a dozen vector reads/writes per unknown; the coarsest
-# level reads its dense inverse (FP64 in both paths).
-FINE_MODEL = {"fp64": 184.0, "fp32": 148.0}
+TIMED_KERNELS = ("pcg_spmv", "pcg_xr_down", "fine_post")
+MALL_BYTES = 256 << 20   # the MI355X Infinity Cache
 
 
-def solve_model_bytes(H, precision):
+def survey_model_bytes(H):
+    """Whole-solve bytes per PCG iteration by the design model of the hot-path
+    scope table: fine level 40 + 48 + (20 + 8 n1/n0) + (28 + 8 n1/n0) B per
+    unknown (p-update + SpMV, x/r update, restriction, prolongation +
+    post-smoothing), each coarse level 2 (12 nnz_A + 4 n) + 12 (nnz_P + nnz_R)
+    + 60 n, the coarsest its dense inverse."""
+    n0 = H.level(0).n
+    n1 = H.level(1).n if H.n_levels > 1 else 0
+    total = 136.0 * n0 + 16.0 * n1
+    for l in range(1, H.n_levels):
+        lv = H.level(l)
+        if lv.is_coarsest:
+            total += 8.0 * lv.n * lv.n + 16.0 * lv.n
+        else:
+            total += 2 * (12.0 * lv.nnz_a + 4.0 * lv.n) + 12.0 * (lv.nnz_p + lv.nnz_r) + 60.0 * lv.n
+    return total
+
+
+def impl_model_bytes(H, precision, dim):
+    """Bytes per PCG iteration of the kernels this library launches, each array
+    once per launch: the fine kernels above, then per coarse level the down
+    pass (R and R A, rv and sv, rv_c and sv_c) and the up pass (sliced A, P,
+    A P; sv, rv, d, e_c; e), the coarsest its dense inverse (FP64 in both
+    V-cycle precisions)."""
     vb = 8.0 if precision == "fp64" else 4.0
     n0 = H.level(0).n
-    total = FINE_MODEL[precision] * n0
+    n1 = H.level(1).n if H.n_levels > 1 else 0
+    if dim == 2:
+        # V-cycle precision: z read by the p-update, r_c/sv_c written, e_c and
+        # z of the up pass; CG vectors stay FP64
+        total = (32.0 + vb) * n0 + (56.0 * n0 + (20.0 + 2 * vb) * n1) + (20.0 + vb) * n0 + vb * n1
+    else:
+        total = (184.0 if precision == "fp64" else 148.0) * n0
     for l in range(1, H.n_levels):
         lv = H.level(l)
         if lv.is_coarsest:
             total += 8.0 * lv.n * lv.n + 2 * vb * lv.n
+            continue
+        nc = H.level(l + 1).n
+        nap = lv.info.nnz_ap
+        down = (vb + 4) * (lv.nnz_r + nap) + 4.0 * 2 * (nc + 1) + 2 * vb * lv.n + 2 * vb * nc
+        up = (vb + 4) * (lv.nnz_a + lv.nnz_p + nap) + 4 * vb * lv.n + vb * nc
+        total += down + up
+    return total
+
+
+def working_set_bytes(H, dim):
+    """Distinct bytes one PCG iteration touches: the fine fields read or written
+    (x, two residuals, two search directions, q, z, d, 1/d: 8 B each; aggregate
+    ids 4 B) over the active unknowns, every coarse matrix and vector, the
+    coarsest inverse."""
+    n0 = H.level(0).n
+    total = (9 * 8.0 + 4.0) * n0
+    for l in range(1, H.n_levels):
+        lv = H.level(l)
+        if lv.is_coarsest:
+            total += 8.0 * lv.n * lv.n + 16.0 * lv.n
         else:
-            total += 2 * ((vb + 4) * lv.nnz_a + 4 * lv.n) + (vb + 4) * (lv.nnz_p + lv.nnz_r) + 8 * (vb + 4) * lv.n
+            total += 12.0 * (lv.nnz_a + lv.nnz_p + lv.nnz_r + 2 * lv.info.nnz_ap) + 48.0 * lv.n
     return total
 
 
@@ -128,12 +173,52 @@ def batched_heat(n=1024, nrhs=64, reps=3):
             sits += i["iterations"]
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
-        out[prec] = {"batch_ms": tb * 1e3, "solves_per_s": nrhs / tb,
+        shape = S.batched_launch_shape(H)
+        out[prec] = {"batch_ms": tb * 1e3, "solves_per_s": nrhs / tb, "launch_shape": shape,
                      "unknowns_iters_per_s": asm.n_unknowns * sum(its) / tb,
                      "iterations_min_max": [min(its), max(its)],
                      "rel_res_true_max": max(i["rel_res_true"] for i in infos),
                      "sequential_ms": ts * 1e3, "sequential_solves_per_s": nrhs / ts,
                      "speedup_vs_sequential": ts / tb}
+    H.free()
+    return out
+
+
+def heat_steps(n=1024, nrhs=64, nsteps=200):
+    """The heat workload as stated: nsteps backward-Euler steps (dt = h) of nrhs
+    seeded initial conditions on the star at n^2, every step one batched solve
+    of all right-hand sides warm-started from the previous step, in both
+    V-cycle precisions; setup once."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+    g = W.unit_box_grid(2, n)
+    dt = g.h
+    psi = torch.as_tensor(W.psi_star(g), device=dev)
+    asm = S.assemble_diag(g, psi)
+    u0 = W.heat_initial_batch(g, range(nrhs), dev)
+    H = S.Hierarchy(g, asm.kind, asm.a, 1.0 / dt)
+    out = {"workload": f"star2d_{n}_heat_backward_euler_dt_h_{nrhs}rhs_{nsteps}steps_warm_start",
+           "n_unknowns": asm.n_unknowns, "nrhs": nrhs, "steps": nsteps}
+    finals = {}
+    for prec in ("fp32", "fp64"):
+        S.heat_backward_euler_batched(asm, H, u0, dt, 2, precision=prec)     # warm-up (tuning, FP32 copies)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, its = S.heat_backward_euler_batched(asm, H, u0, dt, nsteps, precision=prec)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        flat = [i for row in its for i in row]
+        finals[prec] = u
+        out[prec] = {"seconds": secs, "ms_per_step": secs * 1e3 / nsteps,
+                     "solves_per_s": nrhs * nsteps / secs,
+                     "unknowns_iters_per_s": asm.n_unknowns * sum(flat) / secs,
+                     "iterations_min_mean_max": [min(flat), sum(flat) / len(flat), max(flat)],
+                     "launch_shape": S.batched_launch_shape(H)}
+    out["rel_diff_fp32_vs_fp64_final"] = (torch.linalg.vector_norm(finals["fp32"] - finals["fp64"]) /
+                                          torch.linalg.vector_norm(finals["fp64"])).item()
+    out["fp32_speedup"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
     H.free()
     return out
 
@@ -349,12 +434,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--kernel", default="pcg_xr_down", choices=sorted(KERNEL_BYTES))
+    ap.add_argument("--kernel", default="pcg_xr_down", choices=list(TIMED_KERNELS),
+                    help="kernel of the counter summary (--pmc-summary)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched heat-step measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the 3-D learned-smoother measurement")
     ap.add_argument("--no-islands", action="store_true", help="skip the shape-optimisation island batch")
     ap.add_argument("--no-qoi", action="store_true", help="skip the shape-parameter QOI studies")
+    ap.add_argument("--no-heat-steps", action="store_true", help="skip the 200-step batched heat run")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
@@ -449,9 +536,8 @@ def rocprof_summary(path, top=25):
 
 # FP64 instantiations of the bench's headline path (plain smoother weights)
 KERNEL_SYMBOLS = {
-    "pcg_spmv": "eb::k_pcg_p_spmv<double>", "pcg_xr_down": "eb::k_pcg_xr_down<double, false>",
-    "fine_down": "eb::k_fine_down<double, false>", "fine_restrict": "eb::k_fine_restrict<double>",
-    "fine_up": "eb::k_fine_up<double, false>", "fine_post": "eb::k_fine_post<double, false>"}
+    "pcg_spmv": "eb::k_t2_pspmv<double>", "pcg_xr_down": "eb::k_t2_xr_restrict<double, false, true>",
+    "fine_post": "eb::k_t2_up_post<double, false>"}
 
 
 def _kernel_symbol(name):
@@ -544,9 +630,6 @@ def main():
     del first
     torch.cuda.synchronize()
 
-    stats = {"iters": [], "setup_ms": [], "solve_ms": [], "rel_res_true": [], "levels": 0, "n1": 0}
-    timing = {"launches": 0, "ms": 0.0}
-
     phases = {"assemble": [], "rhs": [], "setup": [], "solve": [], "free": []}
 
     def mark():
@@ -554,9 +637,9 @@ def main():
             torch.cuda.synchronize()
         return time.perf_counter()
 
-    model = {}
-
-    def step(measure, precision="fp64", record=True):
+    def step(precision, keep=False):
+        """One whole step of the hot path, as a user runs it (iteration graphs
+        on, no timing hook): assembly, boundary data, RHS, setup, solve, free."""
         ta = mark()
         asm = S.assemble_diag(g, psi, cuts_cap=cuts_cap)
         tb = mark()
@@ -565,88 +648,89 @@ def main():
         t_setup0 = mark()
         H = S.Hierarchy(g, asm.kind, asm.a, 0.0)
         t_setup1 = mark()
-        if measure and record:
-            H.time_kernel(args.kernel)
         x, info = H.solve(b, tol=prob.tol, precision=precision)
         t_solve1 = mark()
-        if precision not in model:
-            model[precision] = solve_model_bytes(H, precision)
-        if not record:
-            H.free()
-            return asm.n_unknowns, info, x
-        if measure and args.phases:
+        info["setup_ms_host"] = (t_setup1 - t_setup0) * 1e3
+        if args.phases:
             phases["assemble"].append((tb - ta) * 1e3)
             phases["rhs"].append((t_setup0 - tb) * 1e3)
             phases["setup"].append((t_setup1 - t_setup0) * 1e3)
             phases["solve"].append((t_solve1 - t_setup1) * 1e3)
-        if measure:
-            nl, ms = H.kernel_time()
-            timing["launches"] += nl
-            timing["ms"] += ms
-            stats["iters"].append(info["iterations"])
-            stats["setup_ms"].append((t_setup1 - t_setup0) * 1e3)
-            stats["solve_ms"].append(info["solve_ms"])
-            stats["rel_res_true"].append(info["rel_res_true"])
-            stats["levels"] = info["levels"]
-            stats["n1"] = H.level(1).n if H.n_levels > 1 else 0
-            stats["n0"] = asm.n_unknowns
+        if keep:
+            return asm, b, H, x, info
         t_free0 = mark()
         H.free()
         t_free1 = mark()
-        if measure and args.phases:
+        if args.phases:
             phases["free"].append((t_free1 - t_free0) * 1e3)
-            phases.setdefault("step", []).append((t_free1 - ta) * 1e3)
-        return asm.n_unknowns, info["iterations"], ta
+        return asm.n_unknowns, info
 
-    # FP32 V-cycle steps of the same workload, timed the same way
-    mixed = {"iters": [], "solve_ms": [], "rel_res_true": []}
-    for _ in range(args.warmup):
-        step(False, "fp32", record=False)
-    torch.cuda.synchronize()
-    tm0 = time.perf_counter()
-    mixed_work = 0
-    for _ in range(args.steps):
-        n0m, info_m, _ = step(True, "fp32", record=False)
-        mixed_work += n0m * info_m["iterations"]
-        mixed["iters"].append(info_m["iterations"])
-        mixed["solve_ms"].append(info_m["solve_ms"])
-        mixed["rel_res_true"].append(info_m["rel_res_true"])
-    torch.cuda.synchronize()
-    tm1 = time.perf_counter()
-    # difference from the FP64 solution on the same system (both from the library)
-    _, _, xm = step(False, "fp32", record=False)
-    _, _, xd = step(False, "fp64", record=False)
+    def timed_steps(precision):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, work = [], 0
+        for _ in range(args.steps):
+            n0_, info = step(precision)
+            infos.append(info)
+            work += n0_ * info["iterations"]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, work, infos
+
+    # the single-precision V-cycle, then plain FP64 (the headline), each over
+    # whole steps
+    m_secs, mixed_work, m_infos = timed_steps("fp32")
+    secs, total_work, infos = timed_steps("fp64")
+    ms_per_step = secs * 1e3 / args.steps
+
+    # one kept hierarchy: difference between the two precisions' solutions,
+    # the byte models, and the fine kernels' launch times in separate solves
+    # with the timing hook (it records events at every launch of the selected
+    # kernel and runs the iterations kernel by kernel)
+    asm, b, H, xd, _ = step("fp64", keep=True)
+    xm, _ = H.solve(b, tol=prob.tol, precision="fp32")
     mixed_diff = (torch.linalg.vector_norm(xm - xd) / torch.linalg.vector_norm(xd)).item()
     del xm, xd
+    dim = g.dim
+    n0 = asm.n_unknowns
+    n1 = H.level(1).n if H.n_levels > 1 else 0
+    kern = {}
+    for kname in TIMED_KERNELS:
+        H.time_kernel(kname)
+        for _ in range(3):
+            H.solve(b, tol=prob.tol, precision="fp64")
+        nl, kms = H.kernel_time()
+        H.time_kernel(None)
+        avg_us = kms / max(nl, 1) * 1e3
+        byt = kernel_bytes(kname, n0, n1, dim)
+        kern[kname] = {"avg_launch_us": avg_us, "launches": nl, "algorithmic_bytes_per_launch": byt,
+                       "achieved_GBs": byt / (avg_us * 1e-6) / 1e9}
+    models = {"survey": survey_model_bytes(H),
+              "impl_fp64": impl_model_bytes(H, "fp64", dim), "impl_fp32": impl_model_bytes(H, "fp32", dim)}
+    wset = working_set_bytes(H, dim)
+    levels = H.n_levels
+    H.free()
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    total_work = 0
-    for _ in range(args.steps):
-        n0, its, _ = step(True)
-        total_work += n0 * its
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
-    ms_per_step = secs * 1e3 / args.steps
-    n0 = stats["n0"]
-    n1 = stats["n1"]
-    avg_launch_ms = timing["ms"] / max(timing["launches"], 1)
-    bytes_per_launch = KERNEL_BYTES[args.kernel](n0, n1)
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    mean_iters = sum(stats["iters"]) / len(stats["iters"])
-    mean_solve = sum(stats["solve_ms"]) / len(stats["solve_ms"])
-    m_iters = sum(mixed["iters"]) / len(mixed["iters"])
-    m_solve = sum(mixed["solve_ms"]) / len(mixed["solve_ms"])
-    m_secs = tm1 - tm0
+    mean_iters = sum(i["iterations"] for i in infos) / len(infos)
+    mean_solve = sum(i["solve_ms"] for i in infos) / len(infos)
+    m_iters = sum(i["iterations"] for i in m_infos) / len(m_infos)
+    m_solve = sum(i["solve_ms"] for i in m_infos) / len(m_infos)
+    # dominant kernel: the largest time per iteration (one launch each)
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
 
-    def solve_roofline(precision, iters, solve_ms):
-        b = model[precision]
-        gbs = b * iters / (solve_ms * 1e-3) / 1e9
-        return {"bound": "hbm", "model_bytes_per_iter": b, "achieved": gbs, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    def solve_roofline(iters, solve_ms, impl_key):
+        per_s = iters / (solve_ms * 1e-3)
+        out_ = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "mall_resident": wset < MALL_BYTES, "working_set_bytes": wset}
+        for key, mkey in (("survey_model", "survey"), ("implementation", impl_key)):
+            gbs = models[mkey] * per_s / 1e9
+            out_[key] = {"bytes_per_iter": models[mkey], "achieved": gbs, "frac": gbs / HBM_PEAK_GBS}
+        out_["frac"] = out_["survey_model"]["frac"]
+        out_["achieved"] = out_["survey_model"]["achieved"]
+        return out_
+
+    ktraffic = load_traffic(dom)
     out = {
         "metric": "unknowns·CG-iters/s & solves/s to 1e-8 rel-res, learned/mixed vs plain FP64",
         "value": total_work / secs,
@@ -665,12 +749,12 @@ def main():
                    "precision": "plain FP64 (no mixed precision, no learned smoother)"},
         "solves_per_s": args.steps / secs,
         "iterations": mean_iters,
-        "levels": stats["levels"],
-        "setup_ms_host": sum(stats["setup_ms"]) / len(stats["setup_ms"]),
+        "levels": levels,
+        "setup_ms_host": sum(i["setup_ms_host"] for i in infos) / len(infos),
         "solve_ms": mean_solve,
         "solve_phase_unknowns_iters_per_s": n0 * mean_iters / (mean_solve * 1e-3),
-        "rel_res_true_max": max(stats["rel_res_true"]),
-        "solve_roofline": solve_roofline("fp64", mean_iters, mean_solve),
+        "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+        "solve_roofline": solve_roofline(mean_iters, mean_solve, "impl_fp64"),
         "mixed": {
             "precision": "FP32 V-cycle, FP64 outer CG, FP64 true residual with restart, FP64 coarsest solve",
             "value": mixed_work / m_secs,
@@ -680,28 +764,34 @@ def main():
             "iterations": m_iters,
             "solve_ms": m_solve,
             "solve_phase_unknowns_iters_per_s": n0 * m_iters / (m_solve * 1e-3),
-            "rel_res_true_max": max(mixed["rel_res_true"]),
+            "rel_res_true_max": max(i["rel_res_true"] for i in m_infos),
             "rel_diff_vs_fp64_solution": mixed_diff,
             "solve_speedup_vs_fp64": mean_solve / m_solve,
-            "solve_roofline": solve_roofline("fp32", m_iters, m_solve),
+            "solve_roofline": solve_roofline(m_iters, m_solve, "impl_fp32"),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": args.kernel,
-            "achieved": achieved,
+            "kernel": dom,
+            "achieved": kern[dom]["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": load_traffic(args.kernel),
-            "avg_launch_us": avg_launch_ms * 1e3,
-            "launches_timed": timing["launches"],
-            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "frac": kern[dom]["achieved_GBs"] / HBM_PEAK_GBS,
+            "traffic": ktraffic,
+            "avg_launch_us": kern[dom]["avg_launch_us"],
+            "launches_timed": kern[dom]["launches"],
+            "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
+            "mall_resident": wset < MALL_BYTES,
+            "timed": "separate solves on one hierarchy with launch events on the kernel's stream "
+                     "(the headline steps run without the timing hook)",
         },
+        "fine_kernels": kern,
     }
     if args.phases:
         out["phases_ms"] = {k: sum(v) / len(v) for k, v in phases.items() if v}
     if not args.no_batched:
         out["batched"] = batched_heat()
+    if not args.no_heat_steps:
+        out["heat_steps"] = heat_steps()
     if not args.no_learned:
         out["learned_3d"] = learned_ellipsoid()
     if not args.no_islands:

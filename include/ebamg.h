@@ -122,7 +122,8 @@ typedef struct {
     int32_t is_coarsest;
     int32_t max_comp;        /* most aggregates sharing one box on this level    */
     int32_t ext[3];          /* coordinate extents of this level                 */
-    int32_t reserved;
+    int32_t nnz_ap;          /* entries of A P, stored with its transpose R A for the
+                                V-cycle (0 on the coarsest and on level 0)         */
     const int32_t* a_rowptr; const int32_t* a_col; const double* a_val;
     const int32_t* p_rowptr; const int32_t* p_col; const double* p_val;
     const int32_t* r_rowptr; const int32_t* r_col; const double* r_val;

@@ -57,7 +57,7 @@ class PcgResult(C.Structure):
 class LevelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_p", C.c_int64), ("nnz_r", C.c_int64),
                 ("rho", C.c_double), ("omega", C.c_double), ("is_coarsest", C.c_int32),
-                ("max_comp", C.c_int32), ("ext", C.c_int32 * 3), ("reserved", C.c_int32),
+                ("max_comp", C.c_int32), ("ext", C.c_int32 * 3), ("nnz_ap", C.c_int32),
                 ("a_rowptr", C.c_void_p), ("a_col", C.c_void_p), ("a_val", C.c_void_p),
                 ("p_rowptr", C.c_void_p), ("p_col", C.c_void_p), ("p_val", C.c_void_p),
                 ("r_rowptr", C.c_void_p), ("r_col", C.c_void_p), ("r_val", C.c_void_p),

@@ -1172,13 +1172,14 @@ struct ReportArgs {
     const int32_t* a_tot[MAX_LEVELS];
     const int32_t* p_tot[MAX_LEVELS];
     const int32_t* r_tot[MAX_LEVELS];
+    const int32_t* ra_tot[MAX_LEVELS];
     const double* scal;      // 2 * MAX_LEVELS
     const int32_t* counts;   // 3
     const int32_t* stat;     // 4 (SetupStat)
 };
 
 struct ReportBlock {
-    int64_t nnz[3 * MAX_LEVELS];
+    int64_t nnz[4 * MAX_LEVELS];
     double scal[2 * MAX_LEVELS];
     int32_t counts[3];
     int32_t stat[4];
@@ -1187,9 +1188,10 @@ struct ReportBlock {
 __global__ void k_report(ReportArgs R, ReportBlock* __restrict__ out) {
     const int l = threadIdx.x;
     if (l < R.nlev) {
-        out->nnz[3 * l + 0] = R.a_tot[l] ? *R.a_tot[l] : 0;
-        out->nnz[3 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
-        out->nnz[3 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
+        out->nnz[4 * l + 0] = R.a_tot[l] ? *R.a_tot[l] : 0;
+        out->nnz[4 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
+        out->nnz[4 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
+        out->nnz[4 * l + 3] = R.ra_tot[l] ? *R.ra_tot[l] : 0;
     }
     if (l < 2 * MAX_LEVELS) out->scal[l] = R.scal[l];
     if (l < 3) out->counts[l] = R.counts[l];
@@ -1823,6 +1825,7 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         if (!L.is_coarsest && L.p_rowptr) {
             R.p_tot[k] = L.p_rowptr + L.n;
             R.r_tot[k] = L.r_rowptr + H->lev[k + 1].n;
+            if (L.ra_rowptr) R.ra_tot[k] = L.ra_rowptr + H->lev[k + 1].n;
         }
     }
     R.scal = H->dscal;
@@ -1843,9 +1846,10 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     EB_TRY(dfree(drep, s));
     for (int k = 0; k < H->nlev; ++k) {
         Level& L = H->lev[k];
-        L.nnz_a = rep.nnz[3 * k];
-        L.nnz_p = rep.nnz[3 * k + 1];
-        L.nnz_r = rep.nnz[3 * k + 2];
+        L.nnz_a = rep.nnz[4 * k];
+        L.nnz_p = rep.nnz[4 * k + 1];
+        L.nnz_r = rep.nnz[4 * k + 2];
+        L.nnz_ap = rep.nnz[4 * k + 3];
         if (!L.is_coarsest) {
             L.rho = rep.scal[2 * k];
             L.omega = rep.scal[2 * k + 1];
@@ -1937,6 +1941,7 @@ extern "C" int amg_level_info(const amg_handle_t* H, int level, amg_level_info_t
     out->omega = L.omega;
     out->is_coarsest = L.is_coarsest;
     out->max_comp = L.max_comp;
+    out->nnz_ap = (int32_t)L.nnz_ap;
     for (int a = 0; a < 3; ++a) out->ext[a] = L.ext[a];
     out->a_rowptr = L.a_rowptr; out->a_col = L.a_col; out->a_val = L.a_val;
     out->p_rowptr = L.p_rowptr; out->p_col = L.p_col; out->p_val = L.p_val;

@@ -23,7 +23,7 @@ struct Sell {
 };
 
 struct Level {
-    int64_t n = 0, nnz_a = 0, nnz_p = 0, nnz_r = 0;
+    int64_t n = 0, nnz_a = 0, nnz_p = 0, nnz_r = 0, nnz_ap = 0;
     double rho = 0.0, omega = 0.0;
     int is_coarsest = 0;
     int max_comp = 0;            // most coarse unknowns sharing one box of this level

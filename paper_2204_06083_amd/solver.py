@@ -147,6 +147,28 @@ def stencil_combine(asm: "Assembly", sigma: float, alpha: float, x: torch.Tensor
     return o
 
 
+def heat_backward_euler_batched(asm: "Assembly", H: "Hierarchy", u0: torch.Tensor, dt: float, nsteps: int,
+                                tol: float = 1e-8, precision: str = "fp64"):
+    """Backward-Euler steps (A + I/dt) u^{n+1} = u^n / dt of the heat equation
+    with homogeneous Dirichlet data for a batch of initial conditions u0
+    (shape (nrhs, *grid.shape)); H must be set up with sigma = 1/dt.  Every
+    step forms its right-hand sides with eb_stencil_combine (beta = 1/dt) and
+    solves them in one pcg_solve_batched call warm-started from u^n.  Returns
+    (u^nsteps, iterations per step and right-hand side)."""
+    nrhs = u0.shape[0]
+    u = u0.clone()
+    b = torch.empty_like(u)
+    nxt = torch.empty_like(u)
+    its = []
+    for _ in range(nsteps):
+        for j in range(nrhs):
+            stencil_combine(asm, 0.0, 0.0, u[j], beta=1.0 / dt, y=u[j], out=b[j])
+        _, infos = solve_batched(H, b, x0=u, tol=tol, precision=precision, out=nxt)
+        u, nxt = nxt, u
+        its.append([i["iterations"] for i in infos])
+    return u, its
+
+
 def wave_theta(asm: "Assembly", u0: torch.Tensor, u1: torch.Tensor, dt: float, theta: float, nsteps: int,
                tol: float = 1e-10, precision: str = "fp64", H: Optional["Hierarchy"] = None):
     """theta-scheme for u_tt = Lap u with homogeneous Dirichlet data (Sec. 3.5),

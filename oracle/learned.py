@@ -56,7 +56,10 @@ Parity: pinned by tests/test_oracle_learned.py (convolution against a dense
 brute-force sum; network gradients and dL/domega against central finite
 differences; the weighted cycle with constant weights against the plain
 cycle; symmetry of the weighted cycle; a zero last layer reproduces the
-plain smoother).
+plain smoother; the features on a hand-built 5 x 5 grid; the error samples
+against the dense error propagator (I - M A)^s; Adam against hand-derived
+moves: the first is -lr g / (|g| + eps), a constant gradient moves lr every
+step, and after g then 0 the move is lr b1 / (1 + b1) / sqrt(b2 / (1 + b2))).
 """
 from __future__ import annotations
 

@@ -159,3 +159,103 @@ def test_training_lowers_the_loss():
         net = opt.step(net, g)
     L1 = LN.full_grad(net, f, 2, H, asm.nodes, asm.kind, E_)[0]
     assert L1 < L0
+
+
+# ------------------------------------------------------------------ Adam
+# Adam (Kingma and Ba): m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2,
+# m^ = m_t / (1 - b1^t), v^ = v_t / (1 - b2^t), w -= lr m^ / (sqrt(v^) + eps).
+# The pins below are consequences of that definition worked out by hand, not
+# a second copy of the update.
+
+def _adam_run(grads, lr):
+    net = {"w": np.zeros(len(grads[0]))}
+    opt = LN.Adam(net, lr=lr)
+    steps = []
+    for g in grads:
+        before = net["w"].copy()
+        opt.step(net, {"w": np.asarray(g, dtype=np.float64)})
+        steps.append(net["w"] - before)
+    return steps
+
+
+def test_adam_first_step_is_lr_times_the_sign():
+    # after one step m^ = g and v^ = g^2 exactly, so the move is
+    # -lr g / (|g| + eps): lr in the direction of -g, whatever b1 and b2
+    g = [0.5, -2.0, 1e-3, 0.0]
+    (d,) = _adam_run([g], lr=0.05)
+    expect = [-0.05 * 0.5 / (0.5 + 1e-8), 0.05 * 2.0 / (2.0 + 1e-8), -0.05 * 1e-3 / (1e-3 + 1e-8), 0.0]
+    np.testing.assert_allclose(d, expect, rtol=1e-15, atol=0)
+    # 5e-2 to 1e-10 relative for the three non-zero gradients
+    assert abs(abs(d[0]) - 0.05) < 1e-9 and abs(abs(d[1]) - 0.05) < 1e-9
+
+
+def test_adam_constant_gradient_moves_lr_each_step():
+    # with a constant gradient, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so
+    # the bias corrections give m^ = g, v^ = g^2 at every step
+    g = [3.0, -0.25]
+    steps = _adam_run([g] * 6, lr=0.01)
+    for d in steps:
+        np.testing.assert_allclose(d, [-0.01 * 3.0 / (3.0 + 1e-8), 0.01 * 0.25 / (0.25 + 1e-8)], rtol=1e-13)
+
+
+def test_adam_second_step_after_a_zero_gradient():
+    # g_1 = g, g_2 = 0: m_2 = b1 (1 - b1) g, v_2 = b2 (1 - b2) g^2, so
+    # m^ = b1 / (1 + b1) g = 0.47368... g and sqrt(v^) = sqrt(b2 / (1 + b2)) |g|
+    # = 0.70692... |g|; the second move is -lr 0.6700582541365435 sign(g)
+    # (|g| >> eps)
+    g = [4.0, -1.5]
+    d1, d2 = _adam_run([g, [0.0, 0.0]], lr=0.2)
+    np.testing.assert_allclose(d2, [-0.2 * 0.6700582541365435, 0.2 * 0.6700582541365435], rtol=1e-8)
+
+
+# ------------------------------------------------------------------ features
+def test_features_on_a_hand_built_grid():
+    # 5 x 5 nodes, h = 0.25; kinds, diagonal and psi chosen by hand
+    kind = np.array([[0, 0, 0, 0, 0],
+                     [0, 1, 1, 1, 0],
+                     [0, 1, 2, 2, 0],
+                     [0, 1, 2, 1, 0],
+                     [0, 0, 0, 0, 0]], dtype=np.int8)
+    a = np.zeros((5, 5))
+    a[2, 2], a[2, 3], a[3, 2] = 4.0, 3.5, 2.75          # only read at kind 2
+    a[1, 1] = 9.0                                       # a boundary point: ignored
+    psi = np.array([[1.0, 0.5, 0.3, 0.5, 1.0],
+                    [0.5, -0.05, -0.1, -0.05, 0.5],
+                    [0.3, -0.1, -0.5, -0.25, 0.3],
+                    [0.5, -0.05, -0.3, -0.1, 0.5],
+                    [1.0, 0.5, 0.3, 0.5, 1.0]])
+    f = LN.features(kind, a, psi, 0.25, 2)
+    assert f.shape == (2, 5, 5)
+    f0 = np.zeros((5, 5))
+    f0[2, 2], f0[2, 3], f0[3, 2] = 1.0, 0.875, 0.6875   # a / (2 d), d = 2
+    np.testing.assert_array_equal(f[0], f0)
+    # psi / h clipped to [-3, 3], then / 3:  1.0/0.25 = 4 -> 1; 0.5/0.25 = 2 -> 2/3;
+    # 0.3/0.25 = 1.2 -> 0.4; -0.05/0.25 = -0.2 -> -1/15; -0.1/0.25 = -0.4 -> -2/15;
+    # -0.5/0.25 = -2 -> -2/3; -0.25/0.25 = -1 -> -1/3; -0.3/0.25 = -1.2 -> -0.4
+    f1 = np.array([[1.0, 2 / 3, 0.4, 2 / 3, 1.0],
+                   [2 / 3, -1 / 15, -2 / 15, -1 / 15, 2 / 3],
+                   [0.4, -2 / 15, -2 / 3, -1 / 3, 0.4],
+                   [2 / 3, -1 / 15, -0.4, -2 / 15, 2 / 3],
+                   [1.0, 2 / 3, 0.4, 2 / 3, 1.0]])
+    np.testing.assert_allclose(f[1], f1, rtol=1e-15, atol=1e-16)
+    # a level set far below -3h saturates at -1
+    f = LN.features(kind, a, np.full((5, 5), -7.0), 0.25, 2)
+    assert np.all(f[1] == -1.0)
+
+
+# ------------------------------------------------------------ error samples
+def test_error_samples_against_the_dense_error_propagator():
+    # on a 12^2 disk the cycle M is formed column by column as a dense matrix;
+    # the samples must be (I - M A)^s xi with the seeded xi, in unit 2-norm
+    p, asm, A, H, _ = _small("disk", 12)
+    n = A.shape[0]
+    M = np.column_stack([amg.vcycle(H, np.eye(n)[:, i]) for i in range(n)])
+    Ad = A.toarray()
+    T = np.eye(n) - M @ Ad
+    for sweeps in (1, 3):
+        Es = LN.error_samples(H, 4, seed=7, sweeps=sweeps)
+        xi = np.random.default_rng(7).standard_normal((n, 4))
+        ref = np.linalg.matrix_power(T, sweeps) @ xi
+        ref /= np.linalg.norm(ref, axis=0)
+        np.testing.assert_allclose(Es, ref, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(np.linalg.norm(Es, axis=0), 1.0, rtol=1e-14)

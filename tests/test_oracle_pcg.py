@@ -78,3 +78,25 @@ def test_maxit_reports_not_converged():
     asm, A, b = _problem(W.disk_mms(40))
     res = OP.pcg(A, b, precond=None, tol=1e-12, maxit=2)
     assert not res.converged and res.iterations == 2
+
+
+def test_restart_when_the_true_residual_drifts():
+    # a tolerance below what the true residual can reach (about eps kappa):
+    # the recursive residual still falls below it, the true one does not, so
+    # PCG restarts once from the current iterate with r = b - A x recomputed
+    # (the history jumps back up to the true residual there), and no more
+    from oracle import eb_assembly as E
+    from oracle import pcg as OP
+    from paper_2204_06083_amd import workloads as W
+    p = W.disk_poisson(64)
+    asm = E.assemble(p.grid, p.psi)
+    A = E.operator_csr(asm)
+    b = E.rhs(asm, p.f, p.u_dirichlet(*E.cut_coordinates(asm)))
+    res = OP.pcg(A, b, tol=1e-19, maxit=400)
+    assert res.restarts == 1
+    # the entry after the restart is the recomputed true residual, far above
+    # the recursive residual it replaced
+    k = int(np.argmax(np.diff(np.log10(np.asarray(res.history)))))
+    assert res.history[k + 1] > 1e3 * res.history[k]
+    plain = OP.pcg(A, b, tol=1e-19, maxit=400, restart_on_drift=False)
+    assert plain.restarts == 0

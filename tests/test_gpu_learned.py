@@ -267,3 +267,39 @@ def test_training_on_gpu_lowers_the_loss_and_keeps_pcg_converging():
     x2, i2 = H.solve(b_g, tol=1e-8)
     assert torch.equal(x0, x2) and i0["iterations"] == i2["iterations"]
     H.free()
+
+
+def test_learned_weights_after_recycled_nan_blocks():
+    """A handle whose blocks come back from the library's cache after a solve
+    that ended in NaN: with learned weights (which multiply neighbour values
+    off unknowns by a weight of 0) the solve must still succeed and give the
+    iterates of a handle built on fresh memory."""
+    star = W.star_poisson(256)
+    disk = W.disk_poisson(256)
+    assert tuple(star.grid.shape) == tuple(disk.grid.shape)
+    params = _random_params(2, 3)
+
+    def solve_disk():
+        asm, b = gpu_system(disk, oracle_system(disk)[3])
+        H = S.Hierarchy(disk.grid, asm.kind, asm.a)
+        ls = S.LearnedSmoother(H, asm, to_dev(disk.psi), params=params)
+        ls.apply()
+        x, info = H.solve(b, tol=1e-10)
+        H.free()
+        return x, info
+
+    print("[gpu] learned weights on blocks recycled after a NaN solve", flush=True)
+    L.lib().eb_release_cached_memory()
+    x_ref, i_ref = solve_disk()
+    # a solve that ends in NaN on the same grid, then its blocks go back to the cache
+    asm_s, b_s = gpu_system(star, oracle_system(star)[3])
+    Hs = S.Hierarchy(star.grid, asm_s.kind, asm_s.a)
+    b_nan = b_s.clone()
+    b_nan[b_nan != 0] = float("nan")
+    with pytest.raises(L.EbError) as ei:
+        Hs.solve(b_nan, tol=1e-10)
+    assert ei.value.code == L.EB_ENAN
+    Hs.free()
+    x, info = solve_disk()
+    assert info["status"] == 0 and info["iterations"] == i_ref["iterations"]
+    assert torch.equal(x, x_ref)

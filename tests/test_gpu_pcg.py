@@ -72,15 +72,23 @@ def test_dense_small_grids(n):
     H.free()
 
 
-def test_full_size_ellipsoid_residual_property():
-    """Full 257^3 grid: the GPU solution's residual, recomputed by the oracle operator."""
+def test_full_size_ellipsoid_iterate_parity():
+    """Full 257^3 grid (2,868,149 unknowns): the GPU AMG-PCG against the
+    oracle's AMG-PCG on the host (same hierarchy rules, tol 1e-8): iterations
+    within one, iterates within 1e-10; and the residual recomputed by the
+    oracle's operator."""
     prob = W.ellipsoid_poisson(256)
-    print("[gpu] pcg ell256 full", flush=True)
+    print("[gpu] pcg ell256 full: oracle on the host (about half a minute)", flush=True)
     asm_o, A, b_o, u = oracle_system(prob)
+    ref, Ho = OP.amg_pcg(A, E.unknown_coords(asm_o), b_o, tol=1e-8)
     asm_g, b_g = gpu_system(prob, u)
     H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    assert H.n_levels == Ho.n_levels
     x_g, info = H.solve(b_g, tol=1e-8)
     x = x_g.cpu().numpy().ravel()[asm_o.nodes]
+    print(f"  iterations gpu {info['iterations']} oracle {ref.iterations}, rel diff {rel(x, ref.x):.2e}", flush=True)
+    assert abs(info["iterations"] - ref.iterations) <= 1
+    assert rel(x, ref.x) <= 1e-10
     assert np.linalg.norm(b_o - A @ x) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
     ue = W.u_ellipsoid(*prob.grid.mesh()).ravel()[asm_o.nodes]
     assert np.max(np.abs(x - ue)) < 5e-3            # discretisation error at h = 1/256

@@ -69,6 +69,9 @@ def kernel_bytes(name, n0, n1, dim):
 
 
 TIMED_KERNELS = ("pcg_spmv", "pcg_xr_down", "fine_post")
+# blocks of the bench line besides the headline steps, by name (filled in
+# below their definitions)
+BLOCKS = {}
 MALL_BYTES = 256 << 20   # the MI355X Infinity Cache
 
 
@@ -429,6 +432,11 @@ def qoi_studies(reps=2):
     return out
 
 
+BLOCKS.update({"batched": lambda: batched_heat(), "heat_steps": lambda: heat_steps(),
+               "learned_3d": lambda: learned_ellipsoid(), "islands": lambda: shape_opt_islands(),
+               "qoi": lambda: qoi_studies()})
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,9 +451,12 @@ def parse():
     ap.add_argument("--no-qoi", action="store_true", help="skip the shape-parameter QOI studies")
     ap.add_argument("--no-heat-steps", action="store_true", help="skip the 200-step batched heat run")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--block", choices=list(BLOCKS),
+                    help="run only this block of the bench line and print its JSON (for profiling)")
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="print a markdown summary of a rocprofv3 --stats/--pmc output directory and exit")
+    ap.add_argument("--top", type=int, default=25, help="kernels listed by --rocprof-summary")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise FETCH_SIZE / WRITE_SIZE passes of --kernel and of --copy-calib, then exit")
     ap.add_argument("--phases", action="store_true",
@@ -606,7 +617,7 @@ def main():
         pmc_summary(args)
         return
     if args.rocprof_summary:
-        rocprof_summary(args.rocprof_summary)
+        rocprof_summary(args.rocprof_summary, args.top)
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -615,6 +626,10 @@ def main():
     import torch
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.block:
+        torch.cuda.set_device(0)
+        print(json.dumps({args.block: BLOCKS[args.block]()}))
         return
     from paper_2204_06083_amd import solver as S
     from paper_2204_06083_amd import workloads as W

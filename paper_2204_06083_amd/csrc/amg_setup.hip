@@ -744,23 +744,23 @@ __global__ void __launch_bounds__(BLOCK) k_tr0_pull(int64_t nc, const int4* __re
     if (!FILL && rowok && q == 0) cnt[I] = c;
 }
 
-// Sort each row by column: one wavefront per row, bitonic network in LDS for
-// rows of up to SORT_MAX entries (keys are unique column indices), insertion
-// sort by lane 0 beyond that.
-constexpr int SORT_MAX = 256;
-
-__global__ void __launch_bounds__(WAVE) k_sort_rows(const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                    double* __restrict__ val, int64_t nrows) {
-    __shared__ int32_t key[SORT_MAX];
-    __shared__ double v[SORT_MAX];
+// Sort each row by column: one workgroup of NT threads per row, bitonic
+// network in LDS for rows of up to MAXM entries (keys are unique column
+// indices), insertion sort by thread 0 beyond that.  R = P^T rows hold up to
+// 5^d entries, R A rows up to 7^d (343 in 3-D).
+template <int NT, int MAXM>
+__global__ void __launch_bounds__(NT) k_sort_rows(const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                  double* __restrict__ val, int64_t nrows) {
+    __shared__ int32_t key[MAXM];
+    __shared__ double v[MAXM];
     const int64_t i = blockIdx.x;
     if (i >= nrows) return;
     const int b = rowptr[i], e = rowptr[i + 1];
     const int m = e - b;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     if (m <= 1) return;
-    if (m > SORT_MAX) {
-        if (lane == 0) {
+    if (m > MAXM) {
+        if (tid == 0) {
             for (int u = b + 1; u < e; ++u) {
                 const int32_t c = col[u];
                 const double x = val[u];
@@ -778,14 +778,14 @@ __global__ void __launch_bounds__(WAVE) k_sort_rows(const int32_t* __restrict__ 
     }
     int p2 = 2;
     while (p2 < m) p2 <<= 1;
-    for (int t = lane; t < p2; t += WAVE) {
+    for (int t = tid; t < p2; t += NT) {
         key[t] = t < m ? col[b + t] : INT32_MAX;
         v[t] = t < m ? val[b + t] : 0.0;
     }
     __syncthreads();
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < p2; t += WAVE) {
+            for (int t = tid; t < p2; t += NT) {
                 const int u = t ^ j;
                 if (u > t) {
                     const bool up = (t & k) == 0;
@@ -802,7 +802,7 @@ __global__ void __launch_bounds__(WAVE) k_sort_rows(const int32_t* __restrict__ 
             __syncthreads();
         }
     }
-    for (int t = lane; t < m; t += WAVE) {
+    for (int t = tid; t < m; t += NT) {
         col[b + t] = key[t];
         val[b + t] = v[t];
     }
@@ -1633,7 +1633,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
         hipLaunchKernelGGL(k_tr_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.p_rowptr, L.p_col, L.p_val, n,
                            L.r_rowptr, tfill, L.r_col, L.r_val);
         EB_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)nc), dim3(WAVE), 0, s, L.r_rowptr, L.r_col, L.r_val, nc);
+        hipLaunchKernelGGL((k_sort_rows<WAVE, 256>), dim3((unsigned)nc), dim3(WAVE), 0, s, L.r_rowptr, L.r_col, L.r_val,
+                           nc);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(tcnt, s));
         EB_TRY(dfree(tfill, s));
@@ -1682,7 +1683,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
         hipLaunchKernelGGL(k_trs_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, (const int32_t*)L.ra_rowptr,
                            tfill, L.ra_col, L.ra_val);
         EB_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)nc), dim3(WAVE), 0, s, (const int32_t*)L.ra_rowptr, L.ra_col,
+        hipLaunchKernelGGL((k_sort_rows<BLOCK, 2048>), dim3((unsigned)nc), dim3(BLOCK), 0, s,
+                           (const int32_t*)L.ra_rowptr, L.ra_col,
                            L.ra_val, nc);
         EB_LAUNCH_CHECK();
         EB_TRY(dfree(tcnt, s));

@@ -300,8 +300,9 @@ __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, cons
     }
 }
 
-// Restriction r_c = P^T res = P_tent^T (I - omega A D^-1) res, one thread per
-// level-0 box; the box's coarse unknowns are consecutive from box_cstart.
+// Restriction r_c = P^T res = P_tent^T (I - omega A D^-1) res over the
+// level-0 boxes (2-D: one thread per box; 3-D: restrict_box3); the box's
+// coarse unknowns are consecutive from box_cstart.
 constexpr int MAX_FINE_COMP = 16;
 
 struct BoxArgs {
@@ -321,6 +322,63 @@ template <class V> __device__ inline const V* vbw0(const BoxArgs& b);
 template <> __device__ inline const double* vbw0<double>(const BoxArgs& b) { return b.w0; }
 template <> __device__ inline const float* vbw0<float>(const BoxArgs& b) { return b.w0_32; }
 
+// 3-D restriction: 9 threads per level-0 box, each the smoothed residual
+// u = (I - omega A D^-1) res of a 3-node x-run (one (oy, oz) row of the box),
+// staged in LDS; then each aggregate's sum over the box in node order
+// (oz, oy, ox), one thread per aggregate.
+constexpr int R3_BOXES = RNT / 9;   // boxes per block
+
+template <class V>
+__device__ inline void restrict_box3(const FineArgs& f, const BoxArgs& b, const V* __restrict__ dg, V omega, V sh,
+                                     const V* __restrict__ res, V* __restrict__ rc, const V* __restrict__ dg_c,
+                                     double omega_c, V* __restrict__ sv_c) {
+    __shared__ V us[R3_BOXES][27];
+    __shared__ int8_t cs[R3_BOXES][27];
+    const int lb = threadIdx.x / 9, q = threadIdx.x % 9;
+    const int64_t t = xcd_block() * R3_BOXES + lb;
+    const bool active = lb < R3_BOXES && t < b.nboxes;
+    int32_t c0 = 0;
+    int m = 0;
+    if (active) {
+        const int64_t box = b.boxes[t];
+        const int bx = (int)(box % b.nbx);
+        const int64_t rr = box / b.nbx;
+        const int by = (int)(rr % b.nby);
+        const int bz = (int)(rr / b.nby);
+        c0 = b.cstart[box];
+        m = b.ncomp[box];
+        const int oy = q % 3, oz = q / 3;
+        const int j = 3 * by + oy, k = 3 * bz + oz;
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+            const int i = 3 * bx + ox;
+            V u = V(0);
+            int c = -1;
+            if (i < b.nx && j < b.ny && k < b.nz) {
+                const int64_t p = (int64_t)i + f.sy * j + f.sz * k;
+                const V d = dg[p];
+                if (d != V(0)) {
+                    const V rp = res[p];
+                    const V aw = d * (rp / d) - sh * nbr_sum_scaled(res, dg, p, f);
+                    u = rp - omega * aw;
+                    c = m == 1 ? 0 : b.agg[p] - c0;
+                }
+            }
+            us[lb][9 * oz + 3 * oy + ox] = u;
+            cs[lb][9 * oz + 3 * oy + ox] = (int8_t)(c >= 0 && c < MAX_FINE_COMP ? c : -1);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    for (int c = q; c < m && c < MAX_FINE_COMP; c += 9) {
+        V acc = V(0);
+        for (int n = 0; n < 27; ++n)
+            if (cs[lb][n] == c) acc += us[lb][n];
+        rc[c0 + c] = acc;
+        if (sv_c) sv_c[c0 + c] = (V)omega_c * acc / dg_c[c0 + c];
+    }
+}
+
 template <class V, int DIM>
 __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
                                                       const V* __restrict__ res, V* __restrict__ rc,
@@ -329,11 +387,15 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
                                                       const double* __restrict__ part_rr, int np) {
     if (sc->done) return;
     if (check && converged_or_failed<RNT>(part_rr, np, sc)) return;
-    const int64_t t = xcd_block() * RNT + threadIdx.x;
-    if (t >= b.nboxes) return;
     const V* __restrict__ dg = vdiag<V>(f);
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
+    if (DIM == 3) {
+        restrict_box3<V>(f, b, dg, omega, sh, res, rc, dg_c, omega_c, sv_c);
+        return;
+    }
+    const int64_t t = xcd_block() * RNT + threadIdx.x;
+    if (t >= b.nboxes) return;
     const int64_t box = b.boxes[t];
     const int bx = (int)(box % b.nbx);
     const int64_t rr = box / b.nbx;
@@ -387,38 +449,6 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
             rc[c0 + c] = acc;
             if (sv_c) sv_c[c0 + c] = (V)omega_c * acc / dg_c[c0 + c];
         }
-        return;
-    }
-    V acc[MAX_FINE_COMP];
-#pragma unroll
-    for (int c = 0; c < MAX_FINE_COMP; ++c) acc[c] = V(0);
-    for (int oz = 0; oz < 3; ++oz) {
-        const int k = 3 * bz + oz;
-        if (k >= b.nz) break;
-        for (int oy = 0; oy < 3; ++oy) {
-            const int j = 3 * by + oy;
-            if (j >= b.ny) break;
-            for (int ox = 0; ox < 3; ++ox) {
-                const int i = 3 * bx + ox;
-                if (i >= b.nx) break;
-                const int64_t p = (int64_t)i + f.sy * j + f.sz * k;
-                const V d = dg[p];
-                if (d == V(0)) continue;
-                const V rp = res[p];
-                const V aw = d * (rp / d) - sh * nbr_sum_scaled(res, dg, p, f);
-                const V uu = rp - omega * aw;
-                if (m == 1) {
-                    acc[0] += uu;
-                } else {
-                    const int c = b.agg[p] - c0;
-                    if (c >= 0 && c < MAX_FINE_COMP) acc[c] += uu;
-                }
-            }
-        }
-    }
-    for (int c = 0; c < m && c < MAX_FINE_COMP; ++c) {
-        rc[c0 + c] = acc[c];
-        if (sv_c) sv_c[c0 + c] = (V)omega_c * acc[c] / dg_c[c0 + c];
     }
 }
 
@@ -1230,24 +1260,35 @@ __global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA,
     }
 }
 
-// Reads of up to W slots of one row of a sliced matrix (columns and values),
-// issued together; entries past W are left to sell_tail.
+// One row of a sliced matrix in chunks of W slots: slot u of the row is
+// entry sptr[slice] + lane + 64 u; a slice's slot count is uniform over its
+// wavefront.  A chunk's column and value reads are issued together, then its
+// gathers, so a row costs one round trip per chunk rather than per entry.
 template <class V, int W>
 struct SellRow {
     int k[W];
     V a[W];
-    int e0, e1;
 };
 
+struct SellSpan {
+    int e0;     // first entry of the lane's row
+    int slots;  // slots of the slice
+};
+
+template <class V>
+__device__ inline SellSpan sell_span(const SellV<V>& M, int slice, int lane) {
+    const int b = M.sptr[slice];
+    return {b + lane, (M.sptr[slice + 1] - b) >> 6};
+}
+
 template <class V, int W>
-__device__ inline void sell_load(const SellV<V>& M, int slice, int lane, SellRow<V, W>& r) {
-    r.e0 = M.sptr[slice] + lane;
-    r.e1 = M.sptr[slice + 1];
+__device__ inline void sell_load(const SellV<V>& M, const SellSpan& sp, int u0, SellRow<V, W>& r) {
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-        const int e = r.e0 + 64 * u;
-        r.k[u] = e < r.e1 ? M.col[e] : -1;
-        r.a[u] = e < r.e1 ? M.val[e] : V(0);
+        const bool in = u0 + u < sp.slots;
+        const int e = sp.e0 + 64 * (u0 + u);
+        r.k[u] = in ? M.col[e] : -1;
+        r.a[u] = in ? M.val[e] : V(0);
     }
 }
 
@@ -1257,38 +1298,20 @@ __device__ inline void sell_gather(const SellRow<V, W>& r, const V* __restrict__
     for (int u = 0; u < W; ++u) xv[u] = r.k[u] >= 0 ? x[r.k[u]] : V(0);
 }
 
-// sum of the loaded slots in column order, then any entries past W
+// acc + the chunk's products, in slot (column) order
 template <class V, int W>
-__device__ inline V sell_sum(const SellV<V>& M, const SellRow<V, W>& r, const V* xv, const V* __restrict__ x) {
-    V acc = V(0);
+__device__ inline V sell_acc(V acc, const SellRow<V, W>& r, const V* xv) {
 #pragma unroll
     for (int u = 0; u < W; ++u)
         if (r.k[u] >= 0) acc += r.a[u] * xv[u];
-    for (int e = r.e0 + 64 * W; e < r.e1; e += 64) acc += M.val[e] * x[M.col[e]];
     return acc;
-}
-
-// res = rv - A sv (sv = omega rv / d): the residual after pre-smoothing.
-template <class V, int WA>
-__global__ void __launch_bounds__(NT) k_sell_resid(int64_t n, SellV<V> A, const V* __restrict__ sv,
-                                                   const V* __restrict__ rv, V* __restrict__ res,
-                                                   const PcgScalars* sc) {
-    if (sc->done) return;
-    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
-    const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));   // one slice per wavefront
-    if (row >= n) return;
-    SellRow<V, WA> ra;
-    sell_load(A, slice, (int)(row & 63), ra);
-    const V rvr = rv[row];
-    V xa[WA];
-    sell_gather(ra, sv, xa);
-    res[row] = rvr - sell_sum(A, ra, xa, sv);
 }
 
 // Prolongation and post-smoothing in one pass, with A P stored:
 //   zt = sv + P ev_c,  ev = zt + omega (rv - A zt) / d
 //      = sv + P ev_c + omega (rv - A sv - (A P) ev_c) / d.
-// The slot reads of P, A and A P are issued together, then their gathers.
+// The first chunks of P, A and A P are read together; rows of A and A P
+// longer than WA slots (3-D: 27) continue in further chunks of both.
 template <class V, int WP, int WA>
 __global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> P, SellV<V> AP,
                                                 const V* __restrict__ diag, V omega, const V* __restrict__ rv,
@@ -1299,19 +1322,33 @@ __global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> 
     const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));
     if (row >= n) return;
     const int lane = (int)(row & 63);
+    const SellSpan sp = sell_span(P, slice, lane), sa = sell_span(A, slice, lane), sq = sell_span(AP, slice, lane);
     SellRow<V, WP> rp;
     SellRow<V, WA> ra, rq;
-    sell_load(P, slice, lane, rp);
-    sell_load(A, slice, lane, ra);
-    sell_load(AP, slice, lane, rq);
+    sell_load(P, sp, 0, rp);
+    sell_load(A, sa, 0, ra);
+    sell_load(AP, sq, 0, rq);
     const V svr = sv[row], rvr = rv[row], dr = diag[row];
     V xp[WP], xa[WA], xq[WA];
     sell_gather(rp, ev_c, xp);
     sell_gather(ra, sv, xa);
     sell_gather(rq, ev_c, xq);
-    const V pe = sell_sum(P, rp, xp, ev_c);
-    const V as = sell_sum(A, ra, xa, sv);
-    const V ape = sell_sum(AP, rq, xq, ev_c);
+    V pe = sell_acc(V(0), rp, xp);
+    V as = sell_acc(V(0), ra, xa);
+    V ape = sell_acc(V(0), rq, xq);
+    for (int u0 = WA; u0 < max(sa.slots, sq.slots); u0 += WA) {
+        sell_load(A, sa, u0, ra);
+        sell_load(AP, sq, u0, rq);
+        sell_gather(ra, sv, xa);
+        sell_gather(rq, ev_c, xq);
+        as = sell_acc(as, ra, xa);
+        ape = sell_acc(ape, rq, xq);
+    }
+    for (int u0 = WP; u0 < sp.slots; u0 += WP) {
+        sell_load(P, sp, u0, rp);
+        sell_gather(rp, ev_c, xp);
+        pe = sell_acc(pe, rp, xp);
+    }
     ev[row] = svr + pe + omega * (rvr - as - ape) / dr;
 }
 
@@ -1501,6 +1538,11 @@ static unsigned xcd_grid(int64_t n, int bs) {
     return (unsigned)(g > 0 ? g : NUM_XCD);
 }
 
+// the box restriction: a box per thread in 2-D, R3_BOXES boxes per block in 3-D
+static unsigned restrict_grid(const amg_handle* H) {
+    return xcd_grid(H->nboxes0, H->d.dim == 2 ? RNT : R3_BOXES);
+}
+
 static FineArgs fine_args(const amg_handle* H) {
     FineArgs f;
     f.strips = H->strips;
@@ -1572,7 +1614,7 @@ static BoxArgs box_args(const amg_handle* H) {
 // FP64 fine restriction without convergence check (learned-smoother paths).
 static int launch_fine_restrict64(amg_handle* H, const FineArgs& f, double w0, const double* res, double* rc, int np,
                                   hipStream_t s) {
-    const dim3 g(xcd_grid(H->nboxes0, RNT));
+    const dim3 g(restrict_grid(H));
     const Level& L1 = H->lev[1];
     double* sv1 = H->nlev > 2 ? L1.sv : nullptr;
     if (H->d.dim == 2)
@@ -1748,7 +1790,7 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     else
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(restrict_grid(H)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
@@ -1806,7 +1848,7 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     else
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(xcd_grid(H->nboxes0, RNT)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(restrict_grid(H)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));

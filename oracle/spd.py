@@ -1,4 +1,4 @@
-"""Oracle: the SPD structure of the line-by-line operator (Sec. 2.4).
+"""Oracle: the SPD structure of the embedded-boundary operator (Sec. 2.4).
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -67,7 +67,8 @@ def corollary_conditions(a, b):
 def axis_part_of_diagonal(asm, phys_axis):
     """Contribution of the two sides along one axis to each a_k.
 
-    A computational neighbour contributes 1, a BP side contributes c = 1/q.
+    A computational neighbour contributes 1, a BP side the sum of its records'
+    c (c = 1/q for a line-by-line side; c_1 + c_2 for an RBF side).
     """
     dim = asm.psi.ndim
     strides = _strides(asm.psi.shape)
@@ -75,7 +76,7 @@ def axis_part_of_diagonal(asm, phys_axis):
     part = np.zeros(asm.n_unknowns)
     cut_c = {}
     for k, s, c in zip(asm.cuts["unknown"], asm.cuts["dir"], asm.cuts["c"]):
-        cut_c[(int(k), int(s))] = c
+        cut_c[(int(k), int(s))] = cut_c.get((int(k), int(s)), 0.0) + c
     for s, (ax, step, phys) in enumerate(directions(dim)):
         if phys != phys_axis:
             continue
@@ -141,16 +142,20 @@ def segment_check(kind, cut_node, cut_dir, cut_c):
     """(segments, failing): Lemma 2.1 on every grid-line segment of every axis.
 
     kind: node field (COMPUTATIONAL marks unknowns); cut records as parallel
-    arrays (flat node index, side in the order of directions(), c = 1/q).
+    arrays (flat node index, side in the order of directions(), c).
     The part of a diagonal along one axis is 0 + (minus side) + (plus side),
-    each side 1 for a computational neighbour and c for a cut side.
+    each side 1 for a computational neighbour and, for a cut side, the sum of
+    its records' c in record order (one record on a line-by-line side, two on
+    an RBF side).
     """
     kind = np.asarray(kind)
     dim = kind.ndim
     dirs = directions(dim)
     strides = _strides(kind.shape)
     kflat = kind.ravel()
-    cmap = {(int(n), int(sd)): float(c) for n, sd, c in zip(cut_node, cut_dir, cut_c)}
+    cmap = {}
+    for n, sd, c in zip(cut_node, cut_dir, cut_c):
+        cmap[(int(n), int(sd))] = cmap.get((int(n), int(sd)), 0.0) + float(c)
     segments = 0
     failing = 0
     for phys in range(dim):

@@ -52,7 +52,18 @@ enum {
     EB_ENAN = -5,      /* NaN or Inf met in the solve                             */
     EB_ENOCONV = -6,   /* maxit reached before the tolerance                      */
     EB_EHIP = -7,      /* a HIP runtime call failed                               */
-    EB_ENOTIMPL = -8   /* feature not available                                   */
+    EB_ENOTIMPL = -8,  /* feature not available                                   */
+    EB_EGEOM = -9      /* an RBF row's interpolation points are collinear         */
+};
+
+/* Boundary-condition strategy of the assembly (Sec. 2.3, Algorithm 2 step 3). */
+enum {
+    EB_BC_LINE = 0,    /* line-by-line on every boundary-point side; where the node
+                          two steps out is inside, the grid line is followed to
+                          the first outside node (extended line-by-line)        */
+    EB_BC_MIXED = 1,   /* "mixed": line-by-line where the node two steps out is
+                          outside, RBF interpolation otherwise (2-D only)        */
+    EB_BC_RBF = 2      /* "RBF-based": RBF interpolation on every side (2-D only) */
 };
 
 /* Node grid: node (i,j,k) sits at x0 + (i,j,k)*h, i = 0..n[0] etc. (host struct) */
@@ -63,15 +74,22 @@ typedef struct {
     double h;          /* spacing, > 0                                            */
 } eb_grid_t;
 
-/* One boundary-point side of a computational point (Sec. 2.1.1, line-by-line
- * interpolation).  Records are sorted by (node, dir).                         */
+/* One boundary point used by a boundary-point side of a computational point.
+ * A line-by-line side (Sec. 2.1.1) has one record: the crossing of its grid
+ * line, weight c = 1/q.  An RBF side (Sec. 2.2) has two: the boundary points
+ * x_Gamma1, x_Gamma2 of Algorithm 1 with the RBF interpolant's weights.  The
+ * side adds the sum of its records' c to the diagonal, and every record adds
+ * u(xg) c / h^2 to the right-hand side.  Records are sorted by (node, dir,
+ * point).                                                                      */
 typedef struct {
     int64_t node;      /* flat node index of the computational point            */
     int32_t dir;       /* side: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z               */
-    int32_t steps;     /* j >= 2: node + j*side is the first outside node        */
-    double q;          /* crossing distance / h, in (1, j]                       */
-    double c;          /* diagonal contribution 1/q (interpolation weight g_Gamma) */
-    double xg[3];      /* crossing coordinates (xg[2] = 0 in 2-D)                 */
+    int32_t steps;     /* line-by-line: j >= 2, node + j*side is the first outside
+                          node; RBF: -1 for x_Gamma1, -2 for x_Gamma2            */
+    double q;          /* line-by-line: crossing distance / h, in (1, j]; RBF: 0 */
+    double c;          /* line-by-line: 1/q (weight g_Gamma of the crossing);
+                          RBF: the interpolant's weight of this boundary point  */
+    double xg[3];      /* boundary point coordinates (xg[2] = 0 in 2-D)          */
 } eb_cut_t;            /* 56 bytes                                               */
 
 typedef struct {
@@ -152,15 +170,40 @@ int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double
                      eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
                      int64_t* n_cuts, void* stream);
 
+/* eb_assemble_diag with a choice of boundary treatment (Sec. 2.3; Algorithm 2
+ * step 3): mode EB_BC_LINE is eb_assemble_diag; EB_BC_MIXED and EB_BC_RBF
+ * impose the condition on some or all boundary-point sides by the RBF
+ * interpolant of Sec. 2.2 (Eq. (rbf), (rbf_ubp), phi(r) = r^3 with linear
+ * polynomials, Sec. 3), whose two boundary points follow Algorithm 1:
+ * x_Gamma1 closest to the BP, x_Gamma2 closest to the computational point,
+ * or, when the two are within epsilon h (epsilon = 0.025), the first point of
+ * Gamma on the ray from the BP turned pi/4 counterclockwise from x_Gamma1.
+ * Gamma is the zero set of the piecewise-linear interpolant of psi on the
+ * triangles that split every cell along its (i,j)-(i+1,j+1) diagonal; the
+ * closest points are searched in the 6h x 6h window of cells around the
+ * computational point, which holds them (the BP is within h of Gamma).
+ * With three points and linear polynomials the interpolant is the linear
+ * one through them, so the weights are barycentric coordinates (evaluated in
+ * units of h relative to the computational point).  Such a side writes two
+ * records (steps -1, -2).  Only the diagonal and the right-hand side change,
+ * so the operator stays symmetric; definiteness is not guaranteed (check it
+ * with eb_check_spd).
+ * EB_EINVAL for an unknown mode, EB_ENOTIMPL for RBF modes in 3-D, EB_EGEOM
+ * when a side's three interpolation points are collinear; otherwise as
+ * eb_assemble_diag.                                                          */
+int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int32_t mode, int8_t* kind, double* a,
+                          eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                          int64_t* n_cuts, void* stream);
+
 /* A-priori SPD test (Sec. 2.4, Lemma 2.1, Theorems 1-2): along every axis,
  * every maximal run of computational points on a grid line is one segment of
  * the 1-D matrix D^(n)(a, b) whose end entries a, b are the part of the
  * diagonal contributed by the two sides along that axis (1 for a
- * computational neighbour, the record's c for a cut side).  Every segment
+ * computational neighbour, the sum of the side's records' c for a cut side).  Every segment
  * satisfying Lemma 2.1 makes the operator SPD; a failing segment does not
  * prove the contrary (the conditions are sufficient).  Rows built by the
- * line-by-line treatment always pass (Corollary 1); the test is meant for
- * rows whose side contributions come from elsewhere.
+ * line-by-line treatment always pass (Corollary 1); RBF rows (Sec. 2.2) can
+ * fail, which is what Algorithm 2 runs the test for.
  *   kind  [in]  node field from eb_assemble_diag.
  *   cuts  [in]  all n_cuts records of that assembly (sorted by node, then
  *               side), possibly with altered c.

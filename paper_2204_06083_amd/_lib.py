@@ -13,11 +13,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebamg.so")
 
-EB_OK, EB_EINVAL, EB_EDOMAIN, EB_ENOSPC, EB_ENOTSPD, EB_ENAN, EB_ENOCONV, EB_EHIP, EB_ENOTIMPL = \
-    0, -1, -2, -3, -4, -5, -6, -7, -8
+EB_OK, EB_EINVAL, EB_EDOMAIN, EB_ENOSPC, EB_ENOTSPD, EB_ENAN, EB_ENOCONV, EB_EHIP, EB_ENOTIMPL, EB_EGEOM = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+EB_BC_LINE, EB_BC_MIXED, EB_BC_RBF = 0, 1, 2
+BC_MODES = {"line": EB_BC_LINE, "mixed": EB_BC_MIXED, "rbf": EB_BC_RBF}
 
 EXPORTS = [
-    "eb_assemble_diag", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
+    "eb_assemble_diag", "eb_assemble_diag_mode", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
     "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
@@ -88,6 +90,9 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     L.eb_assemble_diag.argtypes = [C.POINTER(EbGrid), vp, vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
+    L.eb_assemble_diag_mode.argtypes = [C.POINTER(EbGrid), vp, i32, vp, vp, vp, i64, C.POINTER(i64),
+                                        C.POINTER(i64), vp]
+    L.eb_assemble_diag_mode.restype = i32
     L.eb_assemble_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, vp, vp]
     L.eb_check_spd.argtypes = [C.POINTER(EbGrid), vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.eb_check_spd.restype = i32

@@ -1,6 +1,6 @@
-// Embedded-boundary assembly kernels: classification, the line-by-line
-// diagonal with its cut records, the right-hand side and the matrix-free
-// operator on dense node fields.
+// Embedded-boundary assembly kernels: classification, the diagonal with its
+// cut records (line-by-line and RBF rows), the right-hand side and the
+// matrix-free operator on dense node fields.
 //
 // Built with -ffp-contract=off: the diagonal a_k, q, c and the crossing
 // coordinates are evaluated in a fixed order with separately rounded
@@ -69,27 +69,37 @@ __global__ void __launch_bounds__(1024) k_sum_counts(const int32_t* __restrict__
     }
 }
 
-// Cut sides of an unknown (neighbours that are not unknowns); 0 elsewhere.
-__device__ inline int node_cuts(const int8_t* __restrict__ kind, int64_t n, const GridDims& d) {
+// Whether the boundary-point side of unknown n at offset st takes an RBF row
+// (Sec. 2.3; Algorithm 2 step 3: in the mixed strategy, when the node two
+// steps out is inside; a computational point is at least two nodes from the
+// outer layer, so that node exists).
+__device__ inline bool rbf_side(const double* __restrict__ psi, int64_t n, int64_t st, int mode) {
+    return mode == EB_BC_RBF || (mode == EB_BC_MIXED && psi[n + 2 * st] < 0.0);
+}
+
+// Records of an unknown: one per line-by-line side, two per RBF side.
+__device__ inline int node_records(const int8_t* __restrict__ kind, const double* __restrict__ psi, int64_t n,
+                                   const GridDims& d, int mode) {
     int c = 0;
     if (kind[n] == 2) {
         for (int axis = 0; axis < d.dim; ++axis) {
             const int64_t st = axis_stride(d, axis);
-            c += kind[n - st] != 2;
-            c += kind[n + st] != 2;
+            if (kind[n - st] != 2) c += mode != EB_BC_LINE && rbf_side(psi, n, -st, mode) ? 2 : 1;
+            if (kind[n + st] != 2) c += mode != EB_BC_LINE && rbf_side(psi, n, st, mode) ? 2 : 1;
         }
     }
     return c;
 }
 
-// Cut sides per workgroup (the same node-to-workgroup map as k_diag_cuts,
+// Cut records per workgroup (the same node-to-workgroup map as k_diag_cuts,
 // which places each node's records after those of the workgroups before it
 // and of the nodes before it in its own).
-__global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, GridDims d, int64_t nnodes,
+__global__ void __launch_bounds__(BLOCK) k_count_cuts(const int8_t* __restrict__ kind, const double* __restrict__ psi,
+                                                      GridDims d, int64_t nnodes, int mode,
                                                       int32_t* __restrict__ block_cuts) {
     __shared__ int32_t wcount[BLOCK / WAVE];
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    int c = n < nnodes ? node_cuts(kind, n, d) : 0;
+    int c = n < nnodes ? node_records(kind, psi, n, d, mode) : 0;
 #pragma unroll
     for (int off = WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, WAVE);
     if ((threadIdx.x & (WAVE - 1)) == 0) wcount[threadIdx.x / WAVE] = c;
@@ -158,6 +168,202 @@ __device__ inline double diag_side(const double* __restrict__ psi, int64_t n, co
     return c;
 }
 
+
+// ------------------------------------------------------------- RBF rows
+// Sec. 2.2: the BP value is interpolated through the computational point and
+// two boundary points by the r^3 spline with linear polynomials (Eq. (rbf),
+// (rbf_ubp)); with three points the polynomial condition Pi lambda = 0 leaves
+// lambda = 0, so the interpolant is the linear one through the three points
+// and the weights are barycentric coordinates.  The boundary points follow
+// Algorithm 1 on Gamma = the zero set of the piecewise-linear interpolant of
+// psi on the triangles that split each cell along its (i,j)-(i+1,j+1)
+// diagonal.  Everything is computed relative to the computational point in
+// units of h, so node offsets are exact small integers, and each quantity
+// with the same separately rounded operations in the same order as a plain
+// evaluation (the file is built without contraction): the points come out
+// bit for bit equal to such an evaluation.
+struct Pt2 {
+    double x, y;
+};
+
+constexpr double RBF_EPS = 0.025;                 // distinctness tolerance of Algorithm 1 (Sec. 2.3)
+constexpr double RBF_COS45 = 0.7071067811865476;  // cos(pi/4) = sin(pi/4)
+constexpr int RBF_WLO = -3, RBF_WHI = 2;          // window of cells (lower-left corner offsets)
+
+// Gamma's segment in the lower (v (0,0),(1,0),(1,1)) or upper ((0,0),(1,1),
+// (0,1)) triangle of the cell at offset (oi, oj) from node (i, j): from the
+// first to the second crossed edge in the order (v0 v1), (v1 v2), (v2 v0);
+// the crossing on an edge is v_in + t (v_out - v_in), t = psi_in / (psi_in -
+// psi_out).  False if the cell is off the grid or the triangle not crossed.
+__device__ inline bool tri_segment(const double* __restrict__ psi, const GridDims& d, int i, int j, int oi, int oj,
+                                   bool upper, Pt2& S0, Pt2& S1) {
+    const int ci = i + oi, cj = j + oj;
+    if (ci < 0 || ci + 1 > d.nx - 1 || cj < 0 || cj + 1 > d.ny - 1) return false;
+    const int vx[3] = {0, 1, upper ? 0 : 1};
+    const int vy[3] = {0, upper ? 1 : 0, 1};
+    double vp[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vp[k] = psi[(int64_t)(cj + vy[k]) * d.sy + (ci + vx[k])];
+    bool cr[3];
+    Pt2 pt[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int a = e, b = e == 2 ? 0 : e + 1;
+        const bool ina = vp[a] < 0.0, inb = vp[b] < 0.0;
+        cr[e] = ina != inb;
+        const int vi = ina ? a : b, vo = ina ? b : a;
+        const double pin = vp[vi], pout = vp[vo];
+        const double t = cr[e] ? pin / (pin - pout) : 0.0;
+        pt[e].x = (double)(oi + vx[vi]) + t * (double)(vx[vo] - vx[vi]);
+        pt[e].y = (double)(oj + vy[vi]) + t * (double)(vy[vo] - vy[vi]);
+    }
+    if (!(cr[0] || cr[1] || cr[2])) return false;
+    S0 = cr[0] ? pt[0] : pt[1];
+    S1 = cr[2] ? pt[2] : pt[1];
+    return true;
+}
+
+// Point of [S0, S1] nearest to P and its squared distance.
+__device__ inline void seg_closest(const Pt2& P, const Pt2& S0, const Pt2& S1, Pt2& Q, double& d2) {
+    const double ex = S1.x - S0.x, ey = S1.y - S0.y;
+    const double wx = P.x - S0.x, wy = P.y - S0.y;
+    const double den = ex * ex + ey * ey;
+    const double num = wx * ex + wy * ey;
+    double tau = den > 0.0 ? num / den : 0.0;
+    tau = tau < 0.0 ? 0.0 : (tau > 1.0 ? 1.0 : tau);
+    Q.x = S0.x + tau * ex;
+    Q.y = S0.y + tau * ey;
+    const double dx = P.x - Q.x, dy = P.y - Q.y;
+    d2 = dx * dx + dy * dy;
+}
+
+// Ray O + tau D, tau > 0, against [S0, S1]: keeps the nearest hit.
+__device__ inline void seg_ray(const Pt2& O, const Pt2& D, const Pt2& S0, const Pt2& S1, double& best, Pt2& X) {
+    const double ex = S1.x - S0.x, ey = S1.y - S0.y;
+    const double wx = S0.x - O.x, wy = S0.y - O.y;
+    const double denom = D.x * ey - D.y * ex;
+    if (denom == 0.0) return;
+    const double tau = (wx * ey - wy * ex) / denom;
+    const double mu = (wx * D.y - wy * D.x) / denom;
+    if (tau > 0.0 && mu >= 0.0 && mu <= 1.0 && tau < best) {
+        best = tau;
+        X.x = S0.x + mu * ex;
+        X.y = S0.y + mu * ey;
+    }
+}
+
+// First crossing of Gamma by the ray from O along D (relative to node (i, j)).
+// The cells are visited column by column along the ray's major axis; in each
+// column the ray spans at most two cells of the minor axis, examined with a
+// margin of one cell on either side.  Once a hit lies before the far end of
+// the current column, no later column can hold a nearer one.  The ray starts
+// inside (psi < 0 at the BP) and the outer layer is outside, so it meets
+// Gamma before leaving the grid.
+__device__ inline bool ray_first_hit(const double* __restrict__ psi, const GridDims& d, int i, int j, const Pt2& O,
+                                     const Pt2& D, Pt2& X) {
+    const bool xmaj = fabs(D.x) >= fabs(D.y);
+    const double o_maj = xmaj ? O.x : O.y, d_maj = xmaj ? D.x : D.y;
+    const double o_min = xmaj ? O.y : O.x, d_min = xmaj ? D.y : D.x;
+    const int dir = d_maj > 0.0 ? 1 : -1;
+    const int base = xmaj ? i : j;
+    const int len = xmaj ? d.nx : d.ny;
+    double best = INFINITY;
+    int c = (int)o_maj + (dir > 0 ? 0 : -1);       // O is a node: integer coordinates
+    for (;; c += dir) {
+        if (base + c < 0 || base + c + 1 > len - 1) break;
+        const double ta = ((double)c - o_maj) / d_maj;
+        const double tb = ((double)(c + 1) - o_maj) / d_maj;
+        const double t0 = fmax(0.0, fmin(ta, tb)), t1 = fmax(ta, tb);
+        const double ya = o_min + t0 * d_min, yb = o_min + t1 * d_min;
+        const int m0 = (int)floor(fmin(ya, yb)) - 1, m1 = (int)floor(fmax(ya, yb)) + 1;
+        for (int m = m0; m <= m1; ++m) {
+            for (int up = 0; up < 2; ++up) {
+                Pt2 S0, S1;
+                const int oi = xmaj ? c : m, oj = xmaj ? m : c;
+                if (tri_segment(psi, d, i, j, oi, oj, up != 0, S0, S1)) seg_ray(O, D, S0, S1, best, X);
+            }
+        }
+        if (best < t1) return true;
+    }
+    return best < INFINITY;
+}
+
+// Algorithm 1 and the weights for the BP side `side` of node n = (i, j):
+// boundary points G1, G2 (relative, units of h) and their weights w1, w2 in
+// u_BP = w_ij u_ij + w1 u(G1) + w2 u(G2).  False when the three points are
+// collinear.
+__device__ inline bool rbf_points(const double* __restrict__ psi, const GridDims& d, int i, int j, int side, Pt2& G1,
+                                  Pt2& G2, double& w1, double& w2) {
+    const Pt2 P = {side == 0 ? -1.0 : side == 1 ? 1.0 : 0.0, side == 2 ? -1.0 : side == 3 ? 1.0 : 0.0};
+    const Pt2 Z = {0.0, 0.0};
+    double b1 = INFINITY, b2 = INFINITY;
+    Pt2 G20 = {0.0, 0.0};
+    G1 = G20;
+    for (int oj = RBF_WLO; oj <= RBF_WHI; ++oj) {
+        for (int oi = RBF_WLO; oi <= RBF_WHI; ++oi) {
+            for (int up = 0; up < 2; ++up) {
+                Pt2 S0, S1, Q;
+                double d2;
+                if (!tri_segment(psi, d, i, j, oi, oj, up != 0, S0, S1)) continue;
+                seg_closest(P, S0, S1, Q, d2);
+                if (d2 < b1) {
+                    b1 = d2;
+                    G1 = Q;
+                }
+                seg_closest(Z, S0, S1, Q, d2);
+                if (d2 < b2) {
+                    b2 = d2;
+                    G20 = Q;
+                }
+            }
+        }
+    }
+    const double dx = G1.x - G20.x, dy = G1.y - G20.y;
+    if (dx * dx + dy * dy > RBF_EPS * RBF_EPS) {
+        G2 = G20;
+    } else {
+        // rotate x_BP -> x_G1 counterclockwise by pi/4 and meet Gamma
+        const double vx = G1.x - P.x, vy = G1.y - P.y;
+        const Pt2 D = {RBF_COS45 * vx - RBF_COS45 * vy, RBF_COS45 * vx + RBF_COS45 * vy};
+        if (!ray_first_hit(psi, d, i, j, P, D, G2)) return false;
+    }
+    const double den = G1.x * G2.y - G1.y * G2.x;
+    if (den == 0.0) return false;
+    w1 = (P.x * G2.y - P.y * G2.x) / den;
+    w2 = (G1.x * P.y - G1.y * P.x) / den;
+    return true;
+}
+
+// The two records of an RBF side (if below the capacity); returns the side's
+// diagonal contribution w1 + w2 added in record order to acc.
+__device__ inline double rbf_side_records(const double* __restrict__ psi, int64_t n, const NodePos& p,
+                                          const GridDims& d, int side, int64_t m, eb_cut_t* __restrict__ cuts,
+                                          int64_t cap, double acc, int32_t* __restrict__ err) {
+    Pt2 G[2];
+    double w[2];
+    if (!rbf_points(psi, d, p.i, p.j, side, G[0], G[1], w[0], w[1])) {
+        atomicOr(err, DEVERR_GEOM);
+        return acc;
+    }
+    const double bx = d.x0 + (double)p.i * d.h, by = d.y0 + (double)p.j * d.h;
+    for (int k = 0; k < 2; ++k) {
+        if (m + k < cap) {
+            eb_cut_t rec;
+            rec.node = n;
+            rec.dir = side;
+            rec.steps = -1 - k;
+            rec.q = 0.0;
+            rec.c = w[k];
+            rec.xg[0] = bx + G[k].x * d.h;
+            rec.xg[1] = by + G[k].y * d.h;
+            rec.xg[2] = 0.0;
+            cuts[m + k] = rec;
+        }
+        acc = acc + w[k];
+    }
+    return acc;
+}
+
 __device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, const GridDims& d) {
     int nreg = 0;
     for (int axis = 0; axis < d.dim; ++axis) {
@@ -169,7 +375,8 @@ __device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, c
 }
 
 __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ psi, const int8_t* __restrict__ kind,
-                                                     GridDims d, int64_t nnodes, const int64_t* __restrict__ block_off,
+                                                     GridDims d, int64_t nnodes, int mode,
+                                                     const int64_t* __restrict__ block_off,
                                                      double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                      int64_t cap, int32_t* __restrict__ err,
                                                      int32_t* __restrict__ ndefer, int64_t* __restrict__ defer) {
@@ -178,7 +385,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
     const bool unknown = n < nnodes && kind[n] == 2;
     // first record of the node: the workgroup's offset plus the cut sides of
     // the nodes before it in the workgroup (exclusive scan)
-    const int cnt = n < nnodes ? node_cuts(kind, n, d) : 0;
+    const int cnt = n < nnodes ? node_records(kind, psi, n, d, mode) : 0;
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     int inc = cnt;
 #pragma unroll
@@ -201,7 +408,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         return;
     }
     const NodePos p = node_pos(n, d);
-    double acc = (double)(2 * d.dim - cnt);     // regular sides: the others are cut
+    double acc = (double)diag_regular(kind, n, d);
     const int64_t m_first = block_off[blockIdx.x] + before;
     int64_t m = m_first;
     for (int side = 0; side < 2 * d.dim; ++side) {
@@ -209,6 +416,11 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         const int step = (side & 1) ? 1 : -1;
         const int64_t st = axis_stride(d, axis) * step;
         if (kind[n + st] == 2) continue;
+        if (mode != EB_BC_LINE && rbf_side(psi, n, st, mode)) {
+            acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
+            m += 2;
+            continue;
+        }
         const int pos = axis_coord(p, axis);
         const int len = axis_len(d, axis);
         // walk to the first outside node (the outermost layer is outside),
@@ -263,7 +475,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
 // first that ends the walk (the same test as the thread's walk: an outside
 // node, or the outer layer); thread 0 then adds the sides in order.
 __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __restrict__ psi,
-                                                            const int8_t* __restrict__ kind, GridDims d,
+                                                            const int8_t* __restrict__ kind, GridDims d, int mode,
                                                             double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                             int64_t cap, int32_t* __restrict__ err,
                                                             const int32_t* __restrict__ ndefer,
@@ -282,6 +494,13 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
             const int step = (side & 1) ? 1 : -1;
             const int64_t st = axis_stride(d, axis) * step;
             if (kind[n + st] == 2) continue;
+            if (mode != EB_BC_LINE && rbf_side(psi, n, st, mode)) {
+                // (a deferred node has a long line walk; its RBF sides, if
+                // any, are done by thread 0 in side order)
+                if (tid == 0) acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
+                m += 2;
+                continue;
+            }
             const int pos = axis_coord(p, axis);
             const int len = axis_len(d, axis);
             int j0 = 2;
@@ -388,8 +607,10 @@ __device__ inline bool lemma_2_1(int64_t n, double a, double b) {
     return a > ((double)(n - 2) * b - (double)(n - 3)) / ((double)(n - 1) * b - (double)(n - 2));
 }
 
-// c of the record (node, side); records are sorted by node, a node's records
-// by side.  *miss is set when there is none.
+// The side's contribution from its records: 0 + c of each record (node,
+// side) in record order (one on a line-by-line side, two on an RBF side);
+// records are sorted by node, a node's records by side.  *miss is set when
+// there is none.
 __device__ inline double cut_c_of(const eb_cut_t* __restrict__ cuts, int64_t n_cuts, int64_t node, int side,
                                   int* miss) {
     int64_t lo = 0, hi = n_cuts;
@@ -398,10 +619,16 @@ __device__ inline double cut_c_of(const eb_cut_t* __restrict__ cuts, int64_t n_c
         if (cuts[mid].node < node) lo = mid + 1;
         else hi = mid;
     }
-    for (int64_t m = lo; m < n_cuts && cuts[m].node == node; ++m)
-        if (cuts[m].dir == side) return cuts[m].c;
-    *miss = 1;
-    return 0.0;
+    double v = 0.0;
+    bool any = false;
+    for (int64_t m = lo; m < n_cuts && cuts[m].node == node; ++m) {
+        if (cuts[m].dir == side) {
+            v = v + cuts[m].c;
+            any = true;
+        }
+    }
+    if (!any) *miss = 1;
+    return v;
 }
 
 // One thread per grid line along `axis`; out = {segments, failing, missing}.
@@ -484,15 +711,23 @@ struct AsmStat {
 
 using namespace eb;
 
-extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double* a,
-                                eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
-                                int64_t* n_cuts, void* stream) {
+extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int32_t mode, int8_t* kind,
+                                     double* a, eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                                     int64_t* n_cuts, void* stream) {
     clear_error();
     GridDims d;
     EB_TRY(make_dims(g, &d));
     if (!psi || !kind || !a || !n_unknowns || !n_cuts || cuts_cap < 0 || (cuts_cap > 0 && !cuts)) {
         set_error("eb_assemble_diag: null pointer or negative capacity");
         return EB_EINVAL;
+    }
+    if (mode != EB_BC_LINE && mode != EB_BC_MIXED && mode != EB_BC_RBF) {
+        set_error("eb_assemble_diag_mode: unknown mode %d", (int)mode);
+        return EB_EINVAL;
+    }
+    if (mode != EB_BC_LINE && d.dim != 2) {
+        set_error("eb_assemble_diag_mode: RBF rows are defined for 2-D grids only");
+        return EB_ENOTIMPL;
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
@@ -520,13 +755,13 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
     EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, blk_unk, (int64_t)nblk, &st->unknowns);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_count_cuts, dim3(nblk), dim3(BLOCK), 0, s, kind, d, nn, blk_cuts);
+    hipLaunchKernelGGL(k_count_cuts, dim3(nblk), dim3(BLOCK), 0, s, kind, psi, d, nn, (int)mode, blk_cuts);
     EB_LAUNCH_CHECK();
     EB_TRY(scan_i32_to_i64_dev(blk_cuts, blk_off, nblk, &st->cuts, s));
-    hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, blk_off, a, cuts, cuts_cap,
-                       &st->err, &st->ndefer, defer);
-    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, a, cuts,
+    hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, (int)mode, blk_off, a, cuts,
                        cuts_cap, &st->err, &st->ndefer, defer);
+    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, (int)mode, a,
+                       cuts, cuts_cap, &st->err, &st->ndefer, defer);
     EB_LAUNCH_CHECK();
     AsmStat h;
     EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));
@@ -540,6 +775,10 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
         set_error("the domain reaches the outermost node layer (psi < 0 there)");
         return EB_EDOMAIN;
     }
+    if (h.err & DEVERR_GEOM) {
+        set_error("an RBF row's three interpolation points are collinear");
+        return EB_EGEOM;
+    }
     *n_unknowns = (int64_t)h.unknowns;
     *n_cuts = h.cuts;
     if (h.cuts > cuts_cap) {
@@ -547,6 +786,12 @@ extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* k
         return EB_ENOSPC;
     }
     return EB_OK;
+}
+
+extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double* a,
+                                eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                                int64_t* n_cuts, void* stream) {
+    return eb_assemble_diag_mode(g, psi, EB_BC_LINE, kind, a, cuts, cuts_cap, n_unknowns, n_cuts, stream);
 }
 
 extern "C" int eb_check_spd(const eb_grid_t* g, const int8_t* kind, const eb_cut_t* cuts, int64_t n_cuts,

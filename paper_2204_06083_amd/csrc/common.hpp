@@ -51,6 +51,7 @@ enum : int32_t {
     DEVERR_NOTSPD = 4,
     DEVERR_NAN = 8,
     DEVERR_CAP = 16,
+    DEVERR_GEOM = 32,
 };
 
 constexpr int WAVE = 64;

@@ -408,6 +408,7 @@ const char* eb_strerror(int code) {
         case EB_ENOCONV: return "iteration limit reached";
         case EB_EHIP: return "HIP runtime error";
         case EB_ENOTIMPL: return "not implemented";
+        case EB_EGEOM: return "boundary points for an RBF row not found (collinear interpolation points)";
         default: return "unknown error";
     }
 }

@@ -51,9 +51,13 @@ class Assembly:
         return tuple(rec[:, 4 + p].contiguous() for p in range(self.grid.dim))
 
 
-def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None) -> Assembly:
-    """Classify nodes and build a_k and the cut records (eb_assemble_diag)."""
+def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None, mode: str = "line") -> Assembly:
+    """Classify nodes and build a_k and the cut records (eb_assemble_diag_mode;
+    mode "line", "mixed" or "rbf")."""
     lib = L.lib()
+    if mode not in L.BC_MODES:
+        raise ValueError(f"unknown boundary mode {mode!r}")
+    m = L.BC_MODES[mode]
     g = L.make_grid(grid)
     shape = grid.shape
     dev = psi.device
@@ -63,13 +67,13 @@ def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None) -> As
     nu, nc = C.c_int64(0), C.c_int64(0)
     if cuts_cap is None:
         # counts first (capacity 0 reports the required size), then the records
-        rc = lib.eb_assemble_diag(C.byref(g), psi_p, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
-                                  None, 0, C.byref(nu), C.byref(nc), _stream())
+        rc = lib.eb_assemble_diag_mode(C.byref(g), psi_p, m, C.c_void_p(kind.data_ptr()),
+                                       C.c_void_p(a.data_ptr()), None, 0, C.byref(nu), C.byref(nc), _stream())
         L.check(rc, "eb_assemble_diag", ok=(L.EB_OK, L.EB_ENOSPC))
         cuts_cap = nc.value
     cuts = torch.empty(max(cuts_cap, 1) * 56, dtype=torch.uint8, device=dev)
-    rc = lib.eb_assemble_diag(C.byref(g), psi_p, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
-                              C.c_void_p(cuts.data_ptr()), int(cuts_cap), C.byref(nu), C.byref(nc), _stream())
+    rc = lib.eb_assemble_diag_mode(C.byref(g), psi_p, m, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
+                                   C.c_void_p(cuts.data_ptr()), int(cuts_cap), C.byref(nu), C.byref(nc), _stream())
     L.check(rc, "eb_assemble_diag")
     return Assembly(grid, kind, a, cuts, nu.value, nc.value)
 

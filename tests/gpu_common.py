@@ -15,9 +15,9 @@ def to_dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
 
 
-def oracle_system(prob, sigma=None):
+def oracle_system(prob, sigma=None, mode="line"):
     sig = prob.sigma if sigma is None else sigma
-    asm = E.assemble(prob.grid, prob.psi)
+    asm = E.assemble(prob.grid, prob.psi, mode=mode)
     A = E.operator_csr(asm, sig)
     if prob.u_dirichlet is not None:
         u = np.asarray(prob.u_dirichlet(*E.cut_coordinates(asm)), dtype=np.float64) * np.ones(asm.n_cuts)
@@ -27,9 +27,9 @@ def oracle_system(prob, sigma=None):
     return asm, A, b, u
 
 
-def gpu_system(prob, u_host=None):
+def gpu_system(prob, u_host=None, mode="line"):
     """GPU assembly + RHS; the Dirichlet data are passed in (same values as the oracle)."""
-    asm = S.assemble_diag(prob.grid, to_dev(prob.psi))
+    asm = S.assemble_diag(prob.grid, to_dev(prob.psi), mode=mode)
     if u_host is None:
         u_host = np.zeros(asm.n_cuts)
     b = S.assemble_rhs(asm, to_dev(prob.f), to_dev(np.asarray(u_host, dtype=np.float64)))

@@ -316,13 +316,12 @@ def shape_opt_islands(count=256, nrhs=4, reps=2):
     for i, (g, sh) in enumerate(zip(grids, canvas.shapes)):
         r0 = int(canvas.rows[i])
         psi_c[r0:r0 + sh[0], :sh[1]] = psis[i]
-        f_c[:, r0:r0 + sh[0], :sh[1]] = srcs[i] * (g.h * g.h)
+        f_c[:, r0:r0 + sh[0], :sh[1]] = srcs[i]
     n_unk = 0
 
     def island_run(prec):
         asm = S.assemble_diag(canvas.grid, psi_c)
-        zero = torch.zeros(asm.n_cuts, dtype=torch.float64, device=dev)
-        B = torch.stack([S.assemble_rhs(asm, f_c[j], zero) for j in range(nrhs)]).contiguous()
+        B = torch.stack([S.assemble_rhs_islands(asm, canvas, f_c[j]) for j in range(nrhs)]).contiguous()
         H = S.Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -34,6 +34,7 @@
 #ifndef EBAMG_H
 #define EBAMG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -92,6 +93,12 @@ typedef struct {
     double xg[3];      /* boundary point coordinates (xg[2] = 0 in 2-D)          */
 } eb_cut_t;            /* 56 bytes                                               */
 
+/* Optional device allocator for a handle (see amg_params_t): alloc returns
+ * `bytes` of device memory usable in stream order on `stream` (NULL on
+ * failure); free releases a block in stream order on `stream`.             */
+typedef void* (*eb_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*eb_free_fn)(void* ptr, void* stream, void* ctx);
+
 typedef struct {
     int32_t coarse_max;      /* solve densely once n <= coarse_max (default 256)  */
     int32_t max_levels;      /* hierarchy depth limit (default 16)                */
@@ -100,6 +107,16 @@ typedef struct {
                                 and upper bound 1200: the factorisation keeps a
                                 16-column panel of the level in LDS)           */
     int32_t reserved;
+    eb_alloc_fn alloc;       /* both set: every device block the library takes
+                                during amg_setup and during later calls on the
+                                handle (solves, V-cycle and smoother calls,
+                                amg_free) comes from alloc and goes back through
+                                free, with the stream of the call (e.g. a
+                                framework's caching allocator).  Both NULL: the
+                                library's own caching allocator.  One of them
+                                NULL: EB_EINVAL.                               */
+    eb_free_fn free;
+    void* alloc_ctx;         /* passed to alloc and free                         */
 } amg_params_t;
 
 typedef struct {
@@ -222,6 +239,19 @@ int eb_check_spd(const eb_grid_t* g, const int8_t* kind, const eb_cut_t* cuts, i
 int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const double* f,
                     const eb_cut_t* cuts, int64_t n_cuts, const double* u_at_cuts,
                     double* b, void* stream);
+
+/* eb_assemble_rhs for an island canvas (several geometries stacked along the
+ * last axis on a grid of spacing 1, as pcg_solve_islands takes them): island
+ * k owns node rows seg_rows[k] .. seg_rows[k+1]-1 and has its own spacing
+ * seg_h[k].  Its operator on the canvas is h_k^2 times its own, so its
+ * equation is multiplied by h_k^2: b = h_k^2 f + sum of u c over the records
+ * (the boundary terms carry 1/h^2 = 1 of the canvas).  seg_rows (nseg + 1
+ * entries, from 0 to the number of node rows) and seg_h are HOST arrays.
+ * Synchronises `stream`.  EB_EINVAL on bad segments or h <= 0.               */
+int eb_assemble_rhs_islands(const eb_grid_t* g, const int8_t* kind, const double* f,
+                            const eb_cut_t* cuts, int64_t n_cuts, const double* u_at_cuts,
+                            int32_t nseg, const int32_t* seg_rows, const double* seg_h, double* b,
+                            void* stream);
 
 /* y = A x on node fields (Eq. central_difference with the diagonal above):
  * y_k = (a_k/h^2 + sigma) x_k - (1/h^2) sum of x over computational

@@ -19,7 +19,7 @@ EB_BC_LINE, EB_BC_MIXED, EB_BC_RBF = 0, 1, 2
 BC_MODES = {"line": EB_BC_LINE, "mixed": EB_BC_MIXED, "rbf": EB_BC_RBF}
 
 EXPORTS = [
-    "eb_assemble_diag", "eb_assemble_diag_mode", "eb_assemble_rhs", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
+    "eb_assemble_diag", "eb_assemble_diag_mode", "eb_assemble_rhs", "eb_assemble_rhs_islands", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
     "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
@@ -37,9 +37,14 @@ class EbGrid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("x0", C.c_double * 3), ("h", C.c_double)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 class AmgParams(C.Structure):
     _fields_ = [("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("min_reduction", C.c_double),
-                ("dense_limit", C.c_int32), ("reserved", C.c_int32)]
+                ("dense_limit", C.c_int32), ("reserved", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class PcgParams(C.Structure):
@@ -94,6 +99,9 @@ def lib():
                                         C.POINTER(i64), vp]
     L.eb_assemble_diag_mode.restype = i32
     L.eb_assemble_rhs.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, vp, vp]
+    L.eb_assemble_rhs_islands.argtypes = [C.POINTER(EbGrid), vp, vp, vp, i64, vp, i32, C.POINTER(i32),
+                                          C.POINTER(dbl), vp, vp]
+    L.eb_assemble_rhs_islands.restype = i32
     L.eb_check_spd.argtypes = [C.POINTER(EbGrid), vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.eb_check_spd.restype = i32
     L.stencil_apply.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, vp, vp, vp]

@@ -1887,11 +1887,18 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
     prm.min_reduction = 0.6;
     prm.dense_limit = 1200;
     prm.reserved = 0;
+    prm.alloc = nullptr;
+    prm.free = nullptr;
+    prm.alloc_ctx = nullptr;
     if (p) {
         prm = *p;
         if (prm.coarse_max < 1 || prm.max_levels < 1 || !(prm.min_reduction > 0.0 && prm.min_reduction <= 1.0) ||
             prm.dense_limit < 1) {
             set_error("amg_setup: invalid parameters");
+            return EB_EINVAL;
+        }
+        if ((prm.alloc == nullptr) != (prm.free == nullptr)) {
+            set_error("amg_setup: alloc and free must be given together");
             return EB_EINVAL;
         }
         if (prm.dense_limit > 1200) prm.dense_limit = 1200;
@@ -1905,6 +1912,7 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
     H->sigma = sigma;
     H->stream = (hipStream_t)stream;
     H->params = prm;
+    AllocScope scope(&H->params);
     int rc = setup_impl(H, kind, a, H->stream);
     if (rc != EB_OK) {
         char msg[1024];
@@ -1920,7 +1928,10 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
 
 extern "C" void amg_free(amg_handle_t* H) {
     if (!H) return;
-    (void)free_handle_memory(H);
+    {
+        AllocScope scope(&H->params);
+        (void)free_handle_memory(H);
+    }
     delete H;
 }
 

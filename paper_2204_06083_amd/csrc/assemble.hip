@@ -7,6 +7,8 @@
 // operations, so an independent FP64 implementation can reproduce them bit
 // for bit (t = psi_in / (psi_in - psi_out); q = (j-1) + t; c = 1/q;
 // a_k = n_regular, then a_k += c side by side in the order -x,+x,-y,+y,-z,+z).
+#include <vector>
+
 #include "common.hpp"
 
 namespace eb {
@@ -532,10 +534,13 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
 
 // ------------------------------------------------------------ right-hand side
 // b_k = f_k + sum over the cuts of k (ascending side) of u_Gamma * (c / h^2).
+// row_scale (optional): f at a node of grid row r (the last axis) is taken
+// times row_scale[r] (island canvases: each island's h^2).
 __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, const double* __restrict__ f,
                                                const eb_cut_t* __restrict__ cuts, int64_t ncuts,
                                                const double* __restrict__ u, double* __restrict__ b,
-                                               int64_t nnodes, double s, GridDims d) {
+                                               int64_t nnodes, double s, GridDims d,
+                                               const double* __restrict__ row_scale) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= nnodes) return;
     if (kind[n] != 2) {
@@ -543,6 +548,10 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, 
         return;
     }
     double v = f[n];
+    if (row_scale) {
+        const NodePos p = node_pos(n, d);
+        v = v * row_scale[d.dim == 3 ? p.k : p.j];
+    }
     // only an unknown with a non-computational neighbour has records (an
     // unknown is never on the outer layer, so its neighbours exist)
     bool cut = false;
@@ -839,8 +848,48 @@ extern "C" int eb_assemble_rhs(const eb_grid_t* g, const int8_t* kind, const dou
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s, d);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s, d,
+                       (const double*)nullptr);
     EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
+extern "C" int eb_assemble_rhs_islands(const eb_grid_t* g, const int8_t* kind, const double* f,
+                                       const eb_cut_t* cuts, int64_t n_cuts, const double* u_at_cuts,
+                                       int32_t nseg, const int32_t* seg_rows, const double* seg_h, double* b,
+                                       void* stream) {
+    clear_error();
+    GridDims d;
+    EB_TRY(make_dims(g, &d));
+    if (!kind || !f || !b || !seg_rows || !seg_h || nseg < 1 || n_cuts < 0 || (n_cuts > 0 && (!cuts || !u_at_cuts))) {
+        set_error("eb_assemble_rhs_islands: null pointer or bad count");
+        return EB_EINVAL;
+    }
+    const int nrows = d.dim == 3 ? d.nz : d.ny;
+    if (seg_rows[0] != 0 || seg_rows[nseg] != nrows) {
+        set_error("eb_assemble_rhs_islands: segments must cover the %d node rows", nrows);
+        return EB_EINVAL;
+    }
+    std::vector<double> sc((size_t)nrows);
+    for (int k = 0; k < nseg; ++k) {
+        if (seg_rows[k + 1] < seg_rows[k] || !(seg_h[k] > 0.0)) {
+            set_error("eb_assemble_rhs_islands: segment %d has decreasing rows or h <= 0", k);
+            return EB_EINVAL;
+        }
+        const double h2 = seg_h[k] * seg_h[k];
+        for (int r = seg_rows[k]; r < seg_rows[k + 1]; ++r) sc[(size_t)r] = h2;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    double* dsc = nullptr;
+    EB_TRY(dalloc_n(&dsc, nrows, s));
+    EB_HIP(hipMemcpyAsync(dsc, sc.data(), sizeof(double) * (size_t)nrows, hipMemcpyHostToDevice, s));
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, f, cuts, n_cuts, u_at_cuts, b, nn, d.s, d,
+                       (const double*)dsc);
+    EB_LAUNCH_CHECK();
+    // the copy above reads pageable host memory: wait for it before sc goes away
+    EB_HIP(hipStreamSynchronize(s));
+    EB_TRY(dfree(dsc, s));
     return EB_OK;
 }
 

@@ -1604,6 +1604,7 @@ using namespace eb;
 extern "C" int pcg_solve_batched(amg_handle_t* H, int32_t nrhs, const double* b, double* x, const pcg_params_t* prm,
                                  pcg_result_t* res, void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     return solve_systems(H, nrhs, 1, nullptr, b, x, prm, res, stream, "pcg_solve_batched");
 }
 
@@ -1611,6 +1612,7 @@ extern "C" int pcg_solve_islands(amg_handle_t* H, int32_t nrhs, int32_t nseg, co
                                  const double* b, double* x, const pcg_params_t* prm, pcg_result_t* res,
                                  void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!seg_rows) {
         set_error("pcg_solve_islands: null seg_rows");
         return EB_EINVAL;

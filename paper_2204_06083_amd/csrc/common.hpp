@@ -39,6 +39,20 @@ int dalloc(void** p, size_t bytes, hipStream_t s);
 int dfree(void* p, hipStream_t s);
 void eb_cache_release_all();   // synchronise the device, return cached blocks
 
+// While an AllocScope with a caller-supplied allocator (amg_params_t alloc /
+// free) is alive on this thread, dalloc takes blocks from it and dfree hands
+// them back to it; otherwise both use the caching allocator.
+class AllocScope {
+  public:
+    explicit AllocScope(const amg_params_t* p);
+    ~AllocScope();
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+
+  private:
+    const amg_params_t* prev_;
+};
+
 template <class T>
 int dalloc_n(T** p, int64_t count, hipStream_t s) {
     return dalloc(reinterpret_cast<void**>(p), (size_t)(count > 0 ? count : 1) * sizeof(T), s);

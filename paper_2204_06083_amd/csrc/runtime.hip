@@ -48,12 +48,27 @@ struct DeviceCache {
 std::mutex g_cache_mutex;
 DeviceCache g_cache[64];
 
+// caller-supplied allocator of the innermost AllocScope on this thread, and
+// the blocks taken from such allocators (keyed by pointer)
+thread_local const amg_params_t* g_alloc_scope = nullptr;
+struct UserBlock {
+    eb_free_fn free_fn;
+    void* ctx;
+};
+std::unordered_map<void*, UserBlock> g_user_live;
+
 size_t round_bytes(size_t b) {
     const size_t g = b <= (1 << 20) ? 256 : (1 << 16);
     return (b + g - 1) / g * g;
 }
 
 }  // namespace
+
+AllocScope::AllocScope(const amg_params_t* p) : prev_(g_alloc_scope) {
+    if (p && p->alloc && p->free) g_alloc_scope = p;
+}
+
+AllocScope::~AllocScope() { g_alloc_scope = prev_; }
 
 int dalloc(void** p, size_t bytes, hipStream_t s) {
     int dev = 0;
@@ -62,6 +77,18 @@ int dalloc(void** p, size_t bytes, hipStream_t s) {
         return EB_EHIP;
     }
     const size_t want = round_bytes(bytes);
+    if (const amg_params_t* u = g_alloc_scope) {
+        void* ptr = u->alloc(want, (void*)s, u->alloc_ctx);
+        if (!ptr) {
+            set_error("the caller's allocator returned NULL for %zu bytes", want);
+            *p = nullptr;
+            return EB_EHIP;
+        }
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        g_user_live[ptr] = UserBlock{u->free, u->alloc_ctx};
+        *p = ptr;
+        return EB_OK;
+    }
     {
         std::lock_guard<std::mutex> lock(g_cache_mutex);
         DeviceCache& C = g_cache[dev];
@@ -104,7 +131,15 @@ int dfree(void* p, hipStream_t s) {
         set_error("dfree: no current device");
         return EB_EHIP;
     }
-    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    std::unique_lock<std::mutex> lock(g_cache_mutex);
+    auto ub = g_user_live.find(p);
+    if (ub != g_user_live.end()) {
+        const UserBlock blk = ub->second;
+        g_user_live.erase(ub);
+        lock.unlock();
+        blk.free_fn(p, (void*)s, blk.ctx);
+        return EB_OK;
+    }
     DeviceCache& C = g_cache[dev];
     auto it = C.live.find(p);
     if (it == C.live.end()) {

@@ -2359,6 +2359,7 @@ using namespace eb;
 
 extern "C" int amg_set_fine_weights(amg_handle_t* H, const double* omega, void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H || !omega) {
         set_error("amg_set_fine_weights: null pointer");
         return EB_EINVAL;
@@ -2392,6 +2393,7 @@ extern "C" int amg_set_fine_weights(amg_handle_t* H, const double* omega, void* 
 
 extern "C" int amg_clear_fine_weights(amg_handle_t* H) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H) {
         set_error("amg_clear_fine_weights: null pointer");
         return EB_EINVAL;
@@ -2403,6 +2405,7 @@ extern "C" int amg_clear_fine_weights(amg_handle_t* H) {
 extern "C" int amg_smoother_samples(amg_handle_t* H, int32_t m, int32_t sweeps, const double* xi, double* e,
                                     void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H || !xi || !e || m < 1 || sweeps < 0) {
         set_error("amg_smoother_samples: invalid arguments");
         return EB_EINVAL;
@@ -2446,6 +2449,7 @@ extern "C" int amg_smoother_samples(amg_handle_t* H, int32_t m, int32_t sweeps, 
 extern "C" int amg_smoother_loss_grad(amg_handle_t* H, int32_t m, const double* e, double* loss, double* grad_omega,
                                       void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H || !e || !loss || !grad_omega || m < 1) {
         set_error("amg_smoother_loss_grad: invalid arguments");
         return EB_EINVAL;
@@ -2520,6 +2524,7 @@ using namespace eb;
 extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_params_t* prm, pcg_result_t* res,
                          void* stream) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H || !b || !x || !res) {
         set_error("pcg_solve: null pointer");
         return EB_EINVAL;
@@ -2688,6 +2693,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
 static int vcycle_apply(amg_handle_t* H, const double* r, double* z, int precision, void* stream,
                         const char* name) {
     clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
     if (!H || !r || !z) {
         set_error("%s: null pointer", name);
         return EB_EINVAL;

@@ -107,6 +107,30 @@ def assemble_rhs(asm: Assembly, f: torch.Tensor, u_at_cuts: torch.Tensor) -> tor
     return b
 
 
+def assemble_rhs_islands(asm: Assembly, canvas: "IslandCanvas", f: torch.Tensor,
+                         u_at_cuts: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """eb_assemble_rhs_islands: the right-hand side of an island canvas, each
+    island's source in its own units (the library scales it by that island's h^2)."""
+    lib = L.lib()
+    g = L.make_grid(asm.grid)
+    shape = asm.grid.shape
+    f_p = _field(f, shape, torch.float64, "f")
+    if u_at_cuts is None:
+        u_at_cuts = torch.zeros(asm.n_cuts, dtype=torch.float64, device=f.device)
+    u = u_at_cuts.contiguous().to(torch.float64)
+    if u.numel() != asm.n_cuts:
+        raise ValueError("u_at_cuts must hold one value per cut record")
+    rows = np.ascontiguousarray(np.asarray(canvas.rows, dtype=np.int32))
+    hs = np.ascontiguousarray(np.asarray(canvas.h, dtype=np.float64))
+    b = torch.empty(shape, dtype=torch.float64, device=f.device)
+    rc = lib.eb_assemble_rhs_islands(C.byref(g), C.c_void_p(asm.kind.data_ptr()), f_p, C.c_void_p(asm.cuts.data_ptr()),
+                                     asm.n_cuts, C.c_void_p(u.data_ptr()), int(rows.size - 1),
+                                     rows.ctypes.data_as(C.POINTER(C.c_int32)), hs.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.c_void_p(b.data_ptr()), _stream())
+    L.check(rc, "eb_assemble_rhs_islands")
+    return b
+
+
 def stencil_apply(grid, kind: torch.Tensor, a: torch.Tensor, sigma: float, x: torch.Tensor,
                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
     lib = L.lib()
@@ -251,12 +275,34 @@ class Hierarchy:
     """amg_setup / pcg_solve / amg_free around one handle."""
 
     def __init__(self, grid, kind: torch.Tensor, a: torch.Tensor, sigma: float = 0.0, coarse_max: int = 256,
-                 max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 1200):
+                 max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 1200,
+                 allocator: Optional[str] = None):
+        """allocator: None (the library's own cache) or "torch": every device
+        block of the handle comes from torch's caching allocator."""
         lib = L.lib()
         self.grid = grid
         self.sigma = float(sigma)
         g = L.make_grid(grid)
         p = L.AmgParams(coarse_max, max_levels, min_reduction, dense_limit, 0)
+        self.alloc_calls = [0, 0]
+        if allocator == "torch":
+            dev = torch.cuda.current_device()
+            calls = self.alloc_calls
+
+            def _alloc(nbytes, stream, ctx):
+                calls[0] += 1
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+
+            def _free(ptr, stream, ctx):
+                calls[1] += 1
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            # the C callbacks must outlive the handle
+            self._alloc_cb = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+            p.alloc, p.free = self._alloc_cb
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
+        self._params = p
         h = C.c_void_p()
         shape = grid.shape
         rc = lib.amg_setup(C.byref(g), _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a"),
@@ -407,14 +453,13 @@ class IslandCanvas:
     def nseg(self) -> int:
         return len(self.shapes)
 
-    def pack(self, fields, fill: float = 0.0, scale_h2: bool = False) -> np.ndarray:
-        """Canvas node field from one field per island (numpy); with scale_h2 each
-        island's values are multiplied by its h^2 (sources in canvas units)."""
+    def pack(self, fields, fill: float = 0.0) -> np.ndarray:
+        """Canvas node field from one field per island (numpy), values copied."""
         out = np.full(self.grid.shape, fill, dtype=np.float64)
         for i, (f, sh) in enumerate(zip(fields, self.shapes)):
             f = np.asarray(f, dtype=np.float64).reshape(sh)
             r0 = int(self.rows[i])
-            out[r0:r0 + sh[0], :sh[1]] = f * (self.h[i] ** 2) if scale_h2 else f
+            out[r0:r0 + sh[0], :sh[1]] = f
         return out
 
     def unpack(self, field):
@@ -492,12 +537,12 @@ def qoi_study(grid, psis, f, weights, tol: float = 1e-10, precision: str = "fp64
     canvas = stack_islands([grid] * K)
     t0 = time.perf_counter()
     psi_c = torch.from_numpy(canvas.pack(psis, fill=1.0)).to(device)
-    f_c = torch.from_numpy(canvas.pack([f] * K, scale_h2=True)).to(device)
+    f_c = torch.from_numpy(canvas.pack([f] * K)).to(device)
     w_c = torch.from_numpy(canvas.pack([weights] * K)).to(device)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     asm = assemble_diag(canvas.grid, psi_c)
-    b = assemble_rhs(asm, f_c, torch.zeros(asm.n_cuts, dtype=torch.float64, device=device))
+    b = assemble_rhs_islands(asm, canvas, f_c)
     H = Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
     try:
         X, infos = solve_islands(H, b[None].contiguous(), canvas.rows, tol=tol, precision=precision)

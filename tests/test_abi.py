@@ -15,6 +15,7 @@ HEADER = os.path.join(ROOT, "include", "ebamg.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(line for line in text.splitlines() if not line.lstrip().startswith("typedef"))
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while")))
 
@@ -66,8 +67,30 @@ def test_binding_covers_exports_and_host_only_calls(libpath):
 def test_struct_layouts_match_header():
     from paper_2204_06083_amd import _lib
     assert ctypes.sizeof(_lib.EbGrid) == 48
-    assert ctypes.sizeof(_lib.AmgParams) == 24
+    assert ctypes.sizeof(_lib.AmgParams) == 48
     assert ctypes.sizeof(_lib.PcgParams) == 24
     assert ctypes.sizeof(_lib.PcgResult) == 48
     assert _lib.CUT_DTYPE.itemsize == 56
     assert ctypes.sizeof(_lib.LevelInfo) == 72 + 12 * 8
+
+
+def test_struct_layouts_against_a_c_compiler(tmp_path):
+    """sizeof / offsetof of the header's structs as a C compiler lays them out,
+    against the ctypes declarations of the binding."""
+    from paper_2204_06083_amd import _lib
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ebamg.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(eb_grid_t), sizeof(amg_params_t),\n'
+        "         offsetof(amg_params_t, alloc), offsetof(amg_params_t, free), offsetof(amg_params_t, alloc_ctx),\n"
+        "         sizeof(pcg_params_t), sizeof(eb_cut_t));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    P = _lib.AmgParams
+    assert vals == [ctypes.sizeof(_lib.EbGrid), ctypes.sizeof(P), P.alloc.offset, P.free.offset,
+                    P.alloc_ctx.offset, ctypes.sizeof(_lib.PcgParams), _lib.CUT_DTYPE.itemsize]

@@ -46,9 +46,8 @@ def _canvas_system(geoms, nrhs, fill_psi=1.0):
     canvas = S.stack_islands([g for g, _ in geoms])
     psi_c = canvas.pack([p for _, p in geoms], fill=fill_psi)
     asm_c = S.assemble_diag(canvas.grid, to_dev(psi_c))
-    zero = torch.zeros(asm_c.n_cuts, dtype=torch.float64, device=asm_c.kind.device)
-    B = torch.stack([S.assemble_rhs(asm_c, to_dev(canvas.pack([_sources(g, j) for g, _ in geoms], scale_h2=True)),
-                                    zero) for j in range(nrhs)]).contiguous()
+    B = torch.stack([S.assemble_rhs_islands(asm_c, canvas, to_dev(canvas.pack([_sources(g, j) for g, _ in geoms])))
+                     for j in range(nrhs)]).contiguous()
     return canvas, asm_c, B
 
 
@@ -191,3 +190,25 @@ def test_island_iteration_graphs_match_kernel_launches():
     finally:
         S.set_iteration_graphs(True)
         H.free()
+
+
+def test_island_rhs_scales_each_source_by_its_h2():
+    # eb_assemble_rhs_islands multiplies island k's source by h_k^2 on the
+    # device; the same right-hand side as scaling the packed sources first
+    # and calling eb_assemble_rhs, bit for bit (one product, then the
+    # boundary terms in record order), with nonzero boundary data.
+    geoms = _stars([40, 56, 72], seed=9)
+    canvas = S.stack_islands([g for g, _ in geoms])
+    asm_c = S.assemble_diag(canvas.grid, to_dev(canvas.pack([p for _, p in geoms], fill=1.0)))
+    src = [_sources(g, 1) for g, _ in geoms]
+    u = torch.linspace(-1.0, 2.0, asm_c.n_cuts, dtype=torch.float64, device=asm_c.kind.device)
+    b1 = S.assemble_rhs_islands(asm_c, canvas, to_dev(canvas.pack(src)), u)
+    scaled = canvas.pack([f * (g.h * g.h) for f, (g, _) in zip(src, geoms)])
+    b2 = S.assemble_rhs(asm_c, to_dev(scaled), u)
+    assert torch.equal(b1, b2)
+    # segments that do not cover the canvas rows are refused
+    from types import SimpleNamespace
+    bad = SimpleNamespace(rows=canvas.rows[:-1], h=canvas.h[:-1])
+    with pytest.raises(L.EbError) as ei:
+        S.assemble_rhs_islands(asm_c, bad, to_dev(canvas.pack(src)), u)
+    assert ei.value.code == L.EB_EINVAL

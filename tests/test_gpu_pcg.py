@@ -197,3 +197,31 @@ def test_poll_cadence_does_not_change_the_solve(precision):
         assert i["iterations"] == i_ref["iterations"] and i["status"] == 0, ce
         assert i["rel_res_true"] == i_ref["rel_res_true"], ce
     H.free()
+
+
+def test_handle_memory_through_caller_allocator():
+    # amg_params_t alloc / free: every device block of the handle comes from
+    # the caller's allocator (here torch's caching allocator) and goes back to
+    # it by amg_free; results are bitwise those of the library's own cache.
+    prob = W.star_poisson(512)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H1 = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x1, i1 = H1.solve(b_g, tol=1e-8)
+    x1f, _ = H1.solve(b_g, tol=1e-8, precision="fp32")
+    H1.free()
+    before = torch.cuda.memory_allocated()
+    H2 = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, allocator="torch")
+    assert H2.alloc_calls[0] > 0
+    held = torch.cuda.memory_allocated() - before
+    assert held > 0
+    x2, i2 = H2.solve(b_g, tol=1e-8)
+    x2f, _ = H2.solve(b_g, tol=1e-8, precision="fp32")
+    xb, _ = H2.solve_batched(torch.stack([b_g, 2.0 * b_g]).contiguous(), tol=1e-8)
+    assert torch.equal(x1, x2) and torch.equal(x1f, x2f) and i1["iterations"] == i2["iterations"]
+    assert rel(xb[0].cpu().numpy(), x1.cpu().numpy()) <= 1e-10
+    after_solves = torch.cuda.memory_allocated()
+    H2.free()
+    torch.cuda.synchronize()
+    assert H2.alloc_calls[0] == H2.alloc_calls[1]
+    assert torch.cuda.memory_allocated() < after_solves - held // 2

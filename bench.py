@@ -99,15 +99,17 @@ def impl_model_bytes(H, precision, dim):
     pass (R and R A, rv and sv, rv_c and sv_c) and the up pass (sliced A, P,
     A P; sv, rv, d, e_c; e), the coarsest its dense inverse (FP64 in both
     V-cycle precisions)."""
-    vb = 8.0 if precision == "fp64" else 4.0
+    vb = 8.0 if precision == "fp64" else 4.0               # coarse values and vectors
+    zb = {"fp64": 8.0, "fp32": 4.0, "bf16": 2.0}[precision]  # z, and 1/d of the post-smoothing
     n0 = H.level(0).n
     n1 = H.level(1).n if H.n_levels > 1 else 0
     if dim == 2:
-        # V-cycle precision: z read by the p-update, r_c/sv_c written, e_c and
-        # z of the up pass; CG vectors stay FP64
-        total = (32.0 + vb) * n0 + (56.0 * n0 + (20.0 + 2 * vb) * n1) + (20.0 + vb) * n0 + vb * n1
+        # p-update: z, p, d read, p, q written; x/r update with restriction:
+        # x, p, r, q, 1/d read, x, r written, r_c and sv_c per coarse row; up
+        # pass: aggregate id, r, 1/d, e_c read, z written (CG vectors FP64)
+        total = (32.0 + zb) * n0 + (56.0 * n0 + (20.0 + 2 * vb) * n1) + (12.0 + 2 * zb) * n0 + vb * n1
     else:
-        total = (184.0 if precision == "fp64" else 148.0) * n0
+        total = {"fp64": 184.0, "fp32": 148.0, "bf16": 146.0}[precision] * n0
     for l in range(1, H.n_levels):
         lv = H.level(l)
         if lv.is_coarsest:
@@ -695,6 +697,7 @@ def main():
     # the single-precision V-cycle, then plain FP64 (the headline), each over
     # whole steps
     m_secs, mixed_work, m_infos = timed_steps("fp32")
+    b_secs, b_work, b_infos = timed_steps("bf16")
     secs, total_work, infos = timed_steps("fp64")
     ms_per_step = secs * 1e3 / args.steps
 
@@ -705,7 +708,9 @@ def main():
     asm, b, H, xd, _ = step("fp64", keep=True)
     xm, _ = H.solve(b, tol=prob.tol, precision="fp32")
     mixed_diff = (torch.linalg.vector_norm(xm - xd) / torch.linalg.vector_norm(xd)).item()
-    del xm, xd
+    xb, _ = H.solve(b, tol=prob.tol, precision="bf16")
+    bf16_diff = (torch.linalg.vector_norm(xb - xd) / torch.linalg.vector_norm(xd)).item()
+    del xm, xd, xb
     dim = g.dim
     n0 = asm.n_unknowns
     n1 = H.level(1).n if H.n_levels > 1 else 0
@@ -721,7 +726,8 @@ def main():
         kern[kname] = {"avg_launch_us": avg_us, "launches": nl, "algorithmic_bytes_per_launch": byt,
                        "achieved_GBs": byt / (avg_us * 1e-6) / 1e9}
     models = {"survey": survey_model_bytes(H),
-              "impl_fp64": impl_model_bytes(H, "fp64", dim), "impl_fp32": impl_model_bytes(H, "fp32", dim)}
+              "impl_fp64": impl_model_bytes(H, "fp64", dim), "impl_fp32": impl_model_bytes(H, "fp32", dim),
+              "impl_bf16": impl_model_bytes(H, "bf16", dim)}
     wset = working_set_bytes(H, dim)
     levels = H.n_levels
     H.free()
@@ -730,6 +736,8 @@ def main():
     mean_solve = sum(i["solve_ms"] for i in infos) / len(infos)
     m_iters = sum(i["iterations"] for i in m_infos) / len(m_infos)
     m_solve = sum(i["solve_ms"] for i in m_infos) / len(m_infos)
+    b_iters = sum(i["iterations"] for i in b_infos) / len(b_infos)
+    b_solve = sum(i["solve_ms"] for i in b_infos) / len(b_infos)
     # dominant kernel: the largest time per iteration (one launch each)
     dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
 
@@ -782,6 +790,20 @@ def main():
             "rel_diff_vs_fp64_solution": mixed_diff,
             "solve_speedup_vs_fp64": mean_solve / m_solve,
             "solve_roofline": solve_roofline(m_iters, m_solve, "impl_fp32"),
+            "bf16_smoother": {
+                "precision": "FP32 V-cycle whose fine smoother stores z and 1/d in BF16; FP64 outer CG",
+                "value": b_work / b_secs,
+                "unit": "unknowns·CG-iters/s",
+                "ms_per_step": b_secs * 1e3 / args.steps,
+                "solves_per_s": args.steps / b_secs,
+                "iterations": b_iters,
+                "solve_ms": b_solve,
+                "time_to_tol_ms": b_solve,
+                "rel_res_true_max": max(i["rel_res_true"] for i in b_infos),
+                "rel_diff_vs_fp64_solution": bf16_diff,
+                "solve_speedup_vs_fp64": mean_solve / b_solve,
+                "solve_roofline": solve_roofline(b_iters, b_solve, "impl_bf16"),
+            },
         },
         "roofline": {
             "bound": "hbm",

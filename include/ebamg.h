@@ -124,15 +124,21 @@ typedef struct {
     int32_t maxit;           /* iteration limit (default 1000)                    */
     int32_t x0_given;        /* 1: x holds the initial guess on entry; 0: x0 = 0  */
     int32_t check_every;     /* iterations queued between convergence polls (8)   */
-    int32_t precision;       /* V-cycle precision: EB_PREC_FP64 (0, default) or
+    int32_t precision;       /* V-cycle precision: EB_PREC_FP64 (0, default),
                                 EB_PREC_FP32 (1: single-precision V-cycle; the
                                 outer CG, its dot products, the true-residual
                                 check with restart and the coarsest dense
-                                solve stay FP64).  Hierarchies of one level
-                                always run FP64.                               */
+                                solve stay FP64) or EB_PREC_BF16 (2: that
+                                V-cycle with the BF16 fine smoother below).
+                                Hierarchies of one level always run FP64.      */
 } pcg_params_t;
 
-enum { EB_PREC_FP64 = 0, EB_PREC_FP32 = 1 };
+enum { EB_PREC_FP64 = 0, EB_PREC_FP32 = 1, EB_PREC_BF16 = 2 };
+/* EB_PREC_BF16: the single-precision V-cycle of EB_PREC_FP32 whose fine-level
+ * smoother runs on BF16 operands: it scales by a BF16 copy of 1/diag and
+ * stores the preconditioned residual z in BF16 (round to nearest even);
+ * its arithmetic is FP32 and the outer CG stays FP64.  Not with per-point
+ * smoother weights (EB_ENOTIMPL) or in batched solves (EB_EINVAL).          */
 
 typedef struct {
     int32_t iterations;      /* products with A inside CG                         */
@@ -391,6 +397,13 @@ int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, void* stream);
  * widened to FP64.  The first call on a handle makes FP32 copies of the
  * hierarchy's values (kept until amg_free).  Synchronises `stream`.          */
 int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* stream);
+
+/* The cycle in the given precision (EB_PREC_FP64, EB_PREC_FP32 or
+ * EB_PREC_BF16; the BF16 smoother's z is returned widened to FP64).  The
+ * first BF16 call on a handle makes the BF16 copies (kept until amg_free).
+ * Synchronises `stream`.  EB_EINVAL for another precision, EB_ENOTIMPL for
+ * EB_PREC_BF16 while per-point smoother weights are set.                    */
+int amg_vcycle_apply_prec(amg_handle_t* H, const double* r, double* z, int32_t precision, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned fine-level smoother (an extension of the method: the paper fixes

@@ -1729,7 +1729,7 @@ int free_handle_memory(amg_handle* H) {
     void* ptrs[] = {H->unk_off_tmp, H->strips, H->tiles, H->box_map0, H->box_w0, H->box_w0_32, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->dinv_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
                     H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->dinv_p32, H->res32, H->zt32, H->z32,
-                    H->wf, H->wf32};
+                    H->wf, H->wf32, H->dinv_p16, H->z16};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;
     H->tim_ev = nullptr;    // process-wide event pool, not owned

@@ -93,6 +93,17 @@ __device__ inline int node_records(const int8_t* __restrict__ kind, const double
     return c;
 }
 
+// Whether unknown n has a side that takes an RBF row.
+__device__ inline bool node_has_rbf(const int8_t* __restrict__ kind, const double* __restrict__ psi, int64_t n,
+                                    const GridDims& d, int mode) {
+    for (int axis = 0; axis < d.dim; ++axis) {
+        const int64_t st = axis_stride(d, axis);
+        if (kind[n - st] != 2 && rbf_side(psi, n, -st, mode)) return true;
+        if (kind[n + st] != 2 && rbf_side(psi, n, st, mode)) return true;
+    }
+    return false;
+}
+
 // Cut records per workgroup (the same node-to-workgroup map as k_diag_cuts,
 // which places each node's records after those of the workgroups before it
 // and of the nodes before it in its own).
@@ -409,6 +420,9 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         a[n] = 0.0;
         return;
     }
+    // nodes with an RBF side are done by k_diag_rbf (their records use far more
+    // registers than a line walk; kept out of this kernel)
+    if (mode != EB_BC_LINE && node_has_rbf(kind, psi, n, d, mode)) return;
     const NodePos p = node_pos(n, d);
     double acc = (double)diag_regular(kind, n, d);
     const int64_t m_first = block_off[blockIdx.x] + before;
@@ -418,11 +432,6 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
         const int step = (side & 1) ? 1 : -1;
         const int64_t st = axis_stride(d, axis) * step;
         if (kind[n + st] == 2) continue;
-        if (mode != EB_BC_LINE && rbf_side(psi, n, st, mode)) {
-            acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
-            m += 2;
-            continue;
-        }
         const int pos = axis_coord(p, axis);
         const int len = axis_len(d, axis);
         // walk to the first outside node (the outermost layer is outside),
@@ -477,7 +486,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
 // first that ends the walk (the same test as the thread's walk: an outside
 // node, or the outer layer); thread 0 then adds the sides in order.
 __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __restrict__ psi,
-                                                            const int8_t* __restrict__ kind, GridDims d, int mode,
+                                                            const int8_t* __restrict__ kind, GridDims d,
                                                             double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                             int64_t cap, int32_t* __restrict__ err,
                                                             const int32_t* __restrict__ ndefer,
@@ -496,13 +505,6 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
             const int step = (side & 1) ? 1 : -1;
             const int64_t st = axis_stride(d, axis) * step;
             if (kind[n + st] == 2) continue;
-            if (mode != EB_BC_LINE && rbf_side(psi, n, st, mode)) {
-                // (a deferred node has a long line walk; its RBF sides, if
-                // any, are done by thread 0 in side order)
-                if (tid == 0) acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
-                m += 2;
-                continue;
-            }
             const int pos = axis_coord(p, axis);
             const int len = axis_len(d, axis);
             int j0 = 2;
@@ -530,6 +532,51 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
         }
         if (tid == 0) a[n] = acc;
     }
+}
+
+// The unknowns with an RBF side (mixed and RBF-based strategies, 2-D): the
+// same node-to-workgroup map and in-workgroup scan of record counts as
+// k_diag_cuts, which skipped them.  Line-by-line sides of such a node end at
+// j = 2 (in the mixed strategy a line side has its node two steps out
+// outside; the RBF-based one has none), so no walk is needed.
+__global__ void __launch_bounds__(BLOCK) k_diag_rbf(const double* __restrict__ psi, const int8_t* __restrict__ kind,
+                                                    GridDims d, int64_t nnodes, int mode,
+                                                    const int64_t* __restrict__ block_off, double* __restrict__ a,
+                                                    eb_cut_t* __restrict__ cuts, int64_t cap,
+                                                    int32_t* __restrict__ err) {
+    __shared__ int32_t wsum[BLOCK / WAVE];
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int cnt = n < nnodes ? node_records(kind, psi, n, d, mode) : 0;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const int t = __shfl_up(inc, off, WAVE);
+        if (lane >= off) inc += t;
+    }
+    if (lane == WAVE - 1) wsum[wv] = inc;
+    __syncthreads();
+    int before = inc - cnt;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (n >= nnodes || (*err & DEVERR_DOMAIN)) return;
+    if (kind[n] != 2 || !node_has_rbf(kind, psi, n, d, mode)) return;
+    const NodePos p = node_pos(n, d);
+    double acc = (double)diag_regular(kind, n, d);
+    int64_t m = block_off[blockIdx.x] + before;
+    for (int side = 0; side < 2 * d.dim; ++side) {
+        const int axis = side >> 1;
+        const int step = (side & 1) ? 1 : -1;
+        const int64_t st = axis_stride(d, axis) * step;
+        if (kind[n + st] == 2) continue;
+        if (rbf_side(psi, n, st, mode)) {
+            acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
+            m += 2;
+        } else {
+            acc = acc + diag_side(psi, n, p, d, side, 2, m, cuts, cap);
+            ++m;
+        }
+    }
+    a[n] = acc;
 }
 
 // ------------------------------------------------------------ right-hand side
@@ -769,8 +816,11 @@ extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int3
     EB_TRY(scan_i32_to_i64_dev(blk_cuts, blk_off, nblk, &st->cuts, s));
     hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, (int)mode, blk_off, a, cuts,
                        cuts_cap, &st->err, &st->ndefer, defer);
-    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, (int)mode, a,
+    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, a,
                        cuts, cuts_cap, &st->err, &st->ndefer, defer);
+    if (mode != EB_BC_LINE)
+        hipLaunchKernelGGL(k_diag_rbf, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, (int)mode, blk_off, a, cuts,
+                           cuts_cap, &st->err);
     EB_LAUNCH_CHECK();
     AsmStat h;
     EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));

@@ -129,6 +129,11 @@ struct amg_handle {
     float* res32 = nullptr;
     float* zt32 = nullptr;
     float* z32 = nullptr;
+    // BF16 smoother (EB_PREC_BF16): BF16 copies of the padded 1 / diagonal and
+    // of the preconditioned residual z (2 bytes per node each)
+    int bf16_ready = 0;
+    void* dinv_p16 = nullptr;
+    void* z16 = nullptr;
     int32_t* agg_p = nullptr;       // padded level-0 aggregate (-1 off unknowns)
     // per-point fine smoother weights omega_k / d_k (padded; 0 off unknowns)
     int wf_on = 0;
@@ -148,8 +153,8 @@ struct amg_handle {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // captured pair of steady-state PCG iterations (k odd, then k + 1) per
     // V-cycle precision, with the fine-weight switch it was captured under
-    hipGraphExec_t it_graph[2] = {nullptr, nullptr};
-    int it_graph_wf[2] = {-1, -1};
+    hipGraphExec_t it_graph[3] = {nullptr, nullptr, nullptr};   // FP64, FP32, BF16 smoother
+    int it_graph_wf[3] = {-1, -1, -1};
     hipStream_t cap_stream = nullptr;   // private stream the graphs are captured on
     // the coarsest inverse runs on the device's side stream during setup
     // (forked after the coarsest level is built, joined before the setup's
@@ -171,6 +176,7 @@ struct amg_handle {
 
 namespace eb {
 int ensure_fp32(amg_handle* H, hipStream_t s);   // FP32 hierarchy copies (solve.hip)
+int ensure_bf16(amg_handle* H, hipStream_t s);   // BF16 smoother operands (solve.hip)
 void free_batch(amg_handle* H, hipStream_t s);   // batched.hip
 // Destroys the captured iteration graphs of a handle (solve.hip).
 void drop_iteration_graphs(amg_handle* H);

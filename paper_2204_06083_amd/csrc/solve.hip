@@ -25,6 +25,8 @@
 
 #include <atomic>
 
+#include <type_traits>
+
 #include "handle.hpp"
 
 namespace eb {
@@ -49,7 +51,26 @@ struct FineArgs {
     const float* diag32;  // the same in FP32 (single-precision V-cycle only)
     const double* wf;     // per-point smoother weights omega_k / d_k (learned weights; 0 off unknowns)
     const float* wf32;
+    const void* dinv16;   // BF16 1 / diag (BF16 smoother only)
 };
+
+// BF16 storage of the fine smoother's operands (precision EB_PREC_BF16): the
+// top 16 bits of an FP32 value, rounded to nearest with ties to even;
+// arithmetic stays FP32.
+struct bf16 {
+    uint16_t u;
+};
+__device__ inline float bf16_to_f32(bf16 v) { return __uint_as_float((uint32_t)v.u << 16); }
+__device__ inline bf16 f32_to_bf16(float f) {
+    uint32_t x = __float_as_uint(f);
+    if ((x & 0x7f800000u) == 0x7f800000u)              // Inf stays Inf, NaN stays NaN
+        return bf16{(uint16_t)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u))};
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return bf16{(uint16_t)(x >> 16)};
+}
+__device__ inline double to_f64(double v) { return v; }
+__device__ inline double to_f64(float v) { return (double)v; }
+__device__ inline double to_f64(bf16 v) { return (double)bf16_to_f32(v); }
 
 // Diagonal in the precision of the V-cycle.
 template <class V> __device__ inline const V* vdiag(const FineArgs& f);
@@ -200,14 +221,14 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __res
     FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
-            const double pc = (double)z[p] + beta * pold[p];
-            double nb = (double)z[p - 1] + beta * pold[p - 1];
-            nb += (double)z[p + 1] + beta * pold[p + 1];
-            nb += (double)z[p - f.sy] + beta * pold[p - f.sy];
-            nb += (double)z[p + f.sy] + beta * pold[p + f.sy];
+            const double pc = to_f64(z[p]) + beta * pold[p];
+            double nb = to_f64(z[p - 1]) + beta * pold[p - 1];
+            nb += to_f64(z[p + 1]) + beta * pold[p + 1];
+            nb += to_f64(z[p - f.sy]) + beta * pold[p - f.sy];
+            nb += to_f64(z[p + f.sy]) + beta * pold[p + f.sy];
             if (f.dim == 3) {
-                nb += (double)z[p - f.sz] + beta * pold[p - f.sz];
-                nb += (double)z[p + f.sz] + beta * pold[p + f.sz];
+                nb += to_f64(z[p - f.sz]) + beta * pold[p - f.sz];
+                nb += to_f64(z[p + f.sz]) + beta * pold[p + f.sz];
             }
             const double qv = d * pc - f.s * nb;
             pnew[p] = pc;
@@ -553,12 +574,16 @@ __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const 
 }
 
 // Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z) in FP64.
-template <class V, bool LW>
+// B16 (BF16 smoother): scaled by the BF16 1 / d and z stored in BF16 (the
+// partial uses the stored value).
+template <class V, bool LW, bool B16 = false>
 __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
-                                                  const double* __restrict__ r, V* __restrict__ z,
+                                                  const double* __restrict__ r,
+                                                  std::conditional_t<B16, bf16, V>* __restrict__ z,
                                                   double* __restrict__ part_rz, const PcgScalars* sc) {
     if (sc->done) return;
     const V* __restrict__ dg = vdiag<V>(f);
+    const bf16* __restrict__ di16 = (const bf16*)f.dinv16;
     const V w = (V)omega;
     const V sh = (V)f.s;
     double part = 0.0;
@@ -566,9 +591,16 @@ __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, c
         const V d = dg[p];
         if (d != V(0)) {
             const V az = d * zt[p] - sh * nbr_sum(zt, p, f);
-            const V zv = LW ? zt[p] + vwf<V>(f)[p] * ((V)r[p] - az) : zt[p] + w * ((V)r[p] - az) / d;
-            z[p] = zv;
-            part += r[p] * (double)zv;
+            if constexpr (B16) {
+                const V zv = zt[p] + w * ((V)r[p] - az) * (V)bf16_to_f32(di16[p]);
+                const bf16 zb = f32_to_bf16((float)zv);
+                z[p] = zb;
+                part += r[p] * to_f64(zb);
+            } else {
+                const V zv = LW ? zt[p] + vwf<V>(f)[p] * ((V)r[p] - az) : zt[p] + w * ((V)r[p] - az) / d;
+                z[p] = zv;
+                part += r[p] * (double)zv;
+            }
         }
     }
     block_partial(part, part_rz);
@@ -615,6 +647,7 @@ struct TileArgs {
     const float* dinv32;
     const double* wf;       // per-point smoother weights omega_k / d_k (learned), else null
     const float* wf32;
+    const bf16* dinv16;     // BF16 1 / diag (BF16 smoother only)
 };
 
 template <class V> __device__ inline const V* tdiag(const TileArgs& t);
@@ -707,7 +740,7 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
             if (xin && j >= 0 && j < t.ny && j <= y0 + TY) {
                 const uint32_t pn = xc + t.sy * j;
                 d = ld(t.diag, pn);
-                zz = (double)ld(z, pn);
+                zz = to_f64(ld(z, pn));
                 pp = ld(pold, pn);
             }
         };
@@ -913,10 +946,13 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
 // With part_rr, first the convergence test of the iterate r belongs to (the
 // x/r kernel of this iteration wrote its ||r||^2 partials): once it holds,
 // the remaining kernels of the chunk return at once.
-template <class V, bool LW>
+// B16 (BF16 smoother): 1 / d read from its BF16 copy, z stored in BF16 (the
+// partial uses the stored value).
+template <class V, bool LW, bool B16 = false>
 __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, const int32_t* __restrict__ agg,
                                                     const V* __restrict__ ec, const double* __restrict__ r,
-                                                    V* __restrict__ z, double* __restrict__ part_rz,
+                                                    std::conditional_t<B16, bf16, V>* __restrict__ z,
+                                                    double* __restrict__ part_rz,
                                                     const double* __restrict__ part_rr, int np, PcgScalars* sc) {
     if (sc->done) return;
     if (part_rr && converged_or_failed<TNT>(part_rr, np, sc)) return;
@@ -940,7 +976,8 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
                 const uint32_t pn = xc + t.sy * j;
                 R.g = ld(agg, pn);
                 if (j >= y0 - 1 && j <= y0 + TY) {
-                    R.iv = ld(dinv, pn);
+                    if constexpr (B16) R.iv = (V)bf16_to_f32(ld(t.dinv16, pn));
+                    else R.iv = ld(dinv, pn);
                     R.r = ld(r, pn);
                     if (LW) {
                         R.w = ld(twf<V>(t), pn);
@@ -976,8 +1013,14 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
                 const V nb = zlr + (zta + ztc);
                 const V rr = (V)ra;
                 const V zv = LW ? ztb + wa * (rr - (da * ztb - sV * nb)) : (V(1) - wV) * ztb + wV * (rr + sV * nb) * iva;
-                st(z, (uint32_t)(xc + t.sy * (j - 2)), zv);
-                part += ra * (double)zv;
+                if constexpr (B16) {
+                    const bf16 zb = f32_to_bf16((float)zv);
+                    st(z, (uint32_t)(xc + t.sy * (j - 2)), zb);
+                    part += ra * to_f64(zb);
+                } else {
+                    st(z, (uint32_t)(xc + t.sy * (j - 2)), zv);
+                    part += ra * (double)zv;
+                }
             }
             ta = tb; tb = t0v;
             zta = ztb; ztb = ztc;
@@ -1407,7 +1450,7 @@ __global__ void __launch_bounds__(NT) k_store_field(int64_t n, const int64_t* __
                                                     const int32_t* __restrict__ pad, const V* __restrict__ src,
                                                     double* __restrict__ dst) {
     const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (k < n) dst[nodes[k]] = src[pad[k]];
+    if (k < n) dst[nodes[k]] = to_f64(src[pad[k]]);
 }
 
 __global__ void k_mark_running(PcgScalars* sc) {
@@ -1558,6 +1601,7 @@ static FineArgs fine_args(const amg_handle* H) {
     f.diag32 = H->diag_p32;
     f.wf = H->wf_on ? H->wf : nullptr;
     f.wf32 = H->wf_on ? H->wf32 : nullptr;
+    f.dinv16 = H->dinv_p16;
     return f;
 }
 
@@ -1586,6 +1630,7 @@ static TileArgs tile_args(const amg_handle* H) {
     t.dinv32 = H->dinv_p32;
     t.wf = H->wf_on ? H->wf : nullptr;
     t.wf32 = H->wf_on ? H->wf32 : nullptr;
+    t.dinv16 = (const bf16*)H->dinv_p16;
     return t;
 }
 
@@ -1761,8 +1806,10 @@ static int enqueue_vcycle_one_level(amg_handle* H, const double* r, double* z, d
 // two or more levels: fine pre-smoothing, restriction, coarse levels,
 // prolongation and post-smoothing; the last kernel writes the (r, z)
 // partials to rz_out.
-template <class V, bool LW>
-static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, hipStream_t s) {
+// B16: the BF16 smoother (V = float; z is the BF16 copy).
+template <class V, bool LW, bool B16 = false>
+static int enqueue_vcycle(amg_handle* H, const double* r, std::conditional_t<B16, bf16, V>* z, double* rz_out,
+                          hipStream_t s) {
     PcgScalars* sc = H->sc;
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
@@ -1778,8 +1825,8 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
                         (const double*)nullptr, (const double*)nullptr, np, (double*)nullptr, L1.rv,
                         (const V*)L1.diag, H->lev[1].omega, sv1, sc);
         EB_TRY(enqueue_coarse<V>(H, s));
-        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW>), G, dim3(TNT), 0, t, w0, (const int32_t*)H->agg_p,
-                        (const V*)L1.ev, r, z, rz_out, (const double*)nullptr, np, sc);
+        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW, B16>), G, dim3(TNT), 0, t, w0,
+                        (const int32_t*)H->agg_p, (const V*)L1.ev, r, z, rz_out, (const double*)nullptr, np, sc);
         EB_LAUNCH_CHECK();
         return EB_OK;
     }
@@ -1798,7 +1845,7 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
     const FineArgs fu = fine_args_full(H, &gu);
     EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r, fb.zt,
                     (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW>), G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16>), G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -1807,12 +1854,16 @@ static int enqueue_vcycle(amg_handle* H, const double* r, V* z, double* rz_out, 
 // Iteration k >= 1 of a run.  The V-cycle before it (number k-1) wrote
 // rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
 // r[k % 2] and its V-cycle writes rz[k % 2].
-template <class V, bool LW>
+template <class V, bool LW, bool B16 = false>
 static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
     const FineBufs<V> fb = fine_bufs<V>(H);
+    using ZT = std::conditional_t<B16, bf16, V>;
+    ZT* zb;
+    if constexpr (B16) zb = (bf16*)H->z16;
+    else zb = fb.z;
     double* pold = H->p[k & 1];
     double* pnew = H->p[(k + 1) & 1];
     double* rin = H->rr[(k - 1) & 1];
@@ -1826,21 +1877,21 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     if (use_tiles(H)) {
         const TileArgs t = tile_args(H);
         V* sv1 = H->nlev > 2 ? L1.sv : nullptr;
-        EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_t2_pspmv<V>, G, dim3(TNT), 0, t, (const V*)fb.z, (const double*)pold,
+        EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_t2_pspmv<ZT>, G, dim3(TNT), 0, t, (const ZT*)zb, (const double*)pold,
                         pnew, H->q, rz_cur, rz_prev, np, H->red.pq, sc);
         EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_t2_xr_restrict<V, LW, true>), G, dim3(TNT), 0, t, box_args(H), H->x,
                         (const double*)rin, rout, (const double*)pnew, (const double*)H->q, w0, rz_cur,
                         (const double*)H->red.pq, np, H->red.rr, L1.rv, (const V*)L1.diag, H->lev[1].omega, sv1,
                         sc);
         EB_TRY(enqueue_coarse<V>(H, s));
-        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW>), G, dim3(TNT), 0, t, w0,
-                        (const int32_t*)H->agg_p, (const V*)L1.ev, (const double*)rout, fb.z, rz_out,
+        EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_t2_up_post<V, LW, B16>), G, dim3(TNT), 0, t, w0,
+                        (const int32_t*)H->agg_p, (const V*)L1.ev, (const double*)rout, zb, rz_out,
                         (const double*)H->red.rr, np, sc);
         EB_LAUNCH_CHECK();
         return EB_OK;
     }
-    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<V>, G, dim3(NT), 0, f, fb.z, pold, pnew, H->q, rz_cur, rz_prev,
-                    np, H->red.pq, sc);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<ZT>, G, dim3(NT), 0, f, (const ZT*)zb, pold, pnew, H->q, rz_cur,
+                    rz_prev, np, H->red.pq, sc);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
                     w0, rz_cur, H->red.pq, np, H->red.rr, sc);
     if (H->d.dim == 2)
@@ -1856,7 +1907,7 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     const FineArgs fu = fine_args_full(H, &gu);
     EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout,
                     fb.zt, (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW>), G, dim3(NT), 0, f, w0, fb.zt, rout, fb.z, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16>), G, dim3(NT), 0, f, w0, fb.zt, rout, zb, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -1886,14 +1937,18 @@ static int enqueue_iteration_one_level(amg_handle* H, int k, hipStream_t s) {
 }
 
 // V-cycle / iteration with or without the per-point smoother weights.
-template <class V>
-static int enqueue_vcycle_any(amg_handle* H, const double* r, V* z, double* rz_out, hipStream_t s) {
-    return H->wf_on ? enqueue_vcycle<V, true>(H, r, z, rz_out, s) : enqueue_vcycle<V, false>(H, r, z, rz_out, s);
+// (the BF16 smoother takes no per-point weights: refused before this point)
+template <class V, bool B16 = false>
+static int enqueue_vcycle_any(amg_handle* H, const double* r, std::conditional_t<B16, bf16, V>* z, double* rz_out,
+                              hipStream_t s) {
+    if constexpr (B16) return enqueue_vcycle<V, false, true>(H, r, z, rz_out, s);
+    else return H->wf_on ? enqueue_vcycle<V, true>(H, r, z, rz_out, s) : enqueue_vcycle<V, false>(H, r, z, rz_out, s);
 }
 
-template <class V>
+template <class V, bool B16 = false>
 static int enqueue_iteration_any(amg_handle* H, int k, hipStream_t s) {
-    return H->wf_on ? enqueue_iteration<V, true>(H, k, s) : enqueue_iteration<V, false>(H, k, s);
+    if constexpr (B16) return enqueue_iteration<V, false, true>(H, k, s);
+    else return H->wf_on ? enqueue_iteration<V, true>(H, k, s) : enqueue_iteration<V, false>(H, k, s);
 }
 
 // Steady-state iterations as a HIP graph.  From iteration 3 on, iterations
@@ -1908,7 +1963,7 @@ static std::atomic<int> g_use_graphs{1};
 bool iteration_graphs_enabled() { return g_use_graphs.load() != 0; }
 
 void drop_iteration_graphs(amg_handle* H) {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 3; ++i) {
         if (H->it_graph[i]) (void)hipGraphExecDestroy(H->it_graph[i]);
         H->it_graph[i] = nullptr;
         H->it_graph_wf[i] = -1;
@@ -1917,9 +1972,9 @@ void drop_iteration_graphs(amg_handle* H) {
     H->cap_stream = nullptr;
 }
 
-template <class V>
+template <class V, bool B16 = false>
 static int launch_iteration_pair(amg_handle* H, hipStream_t s) {
-    const int slot = sizeof(V) == sizeof(float) ? 1 : 0;
+    const int slot = B16 ? 2 : sizeof(V) == sizeof(float) ? 1 : 0;
     if (!H->it_graph[slot] || H->it_graph_wf[slot] != H->wf_on) {
         if (H->it_graph[slot]) (void)hipGraphExecDestroy(H->it_graph[slot]);
         H->it_graph[slot] = nullptr;
@@ -1929,8 +1984,8 @@ static int launch_iteration_pair(amg_handle* H, hipStream_t s) {
         hipStream_t cs = H->cap_stream;
         hipGraph_t g = nullptr;
         EB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        const int rc1 = enqueue_iteration_any<V>(H, 3, cs);
-        const int rc2 = rc1 == EB_OK ? enqueue_iteration_any<V>(H, 4, cs) : rc1;
+        const int rc1 = enqueue_iteration_any<V, B16>(H, 3, cs);
+        const int rc2 = rc1 == EB_OK ? enqueue_iteration_any<V, B16>(H, 4, cs) : rc1;
         const hipError_t ec = hipStreamEndCapture(cs, &g);
         if (rc2 != EB_OK || ec != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
@@ -1998,6 +2053,29 @@ int ensure_fp32(amg_handle* H, hipStream_t s) {
         EB_TRY(dalloc_n(&L.tmp32, n, s));
     }
     H->fp32_ready = 1;
+    return EB_OK;
+}
+
+// BF16 copies for the BF16 smoother: 1 / d (from the FP64 field, rounded
+// once to FP32 and then to BF16) and the z buffer; made once per handle.
+__global__ void __launch_bounds__(NT) k_to_bf16(int64_t n, const double* __restrict__ src, bf16* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) dst[i] = f32_to_bf16((float)src[i]);
+}
+
+int ensure_bf16(amg_handle* H, hipStream_t s) {
+    if (H->bf16_ready) return EB_OK;
+    EB_TRY(dalloc(&H->dinv_p16, sizeof(bf16) * (size_t)H->npad, s));
+    EB_TRY(dalloc(&H->z16, sizeof(bf16) * (size_t)H->npad, s));
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(H->npad, NT)), dim3(NT), 0, s, H->npad, H->dinv_p,
+                       (bf16*)H->dinv_p16);
+    EB_LAUNCH_CHECK();
+    {
+        // npad is a multiple of 64 nodes: whole 32-bit words
+        const FillSpec f[] = {{H->z16, sizeof(bf16) * (size_t)H->npad, 0u}};
+        EB_TRY(fill_words(f, 1, s));
+    }
+    H->bf16_ready = 1;
     return EB_OK;
 }
 
@@ -2537,9 +2615,13 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     p.precision = EB_PREC_FP64;
     if (prm) p = *prm;
     if (!(p.tol > 0.0) || p.maxit < 0 || p.check_every < 1 ||
-        (p.precision != EB_PREC_FP64 && p.precision != EB_PREC_FP32)) {
-        set_error("pcg_solve: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0 or 1)");
+        (p.precision != EB_PREC_FP64 && p.precision != EB_PREC_FP32 && p.precision != EB_PREC_BF16)) {
+        set_error("pcg_solve: invalid parameters (tol > 0, maxit >= 0, check_every >= 1, precision 0, 1 or 2)");
         return EB_EINVAL;
+    }
+    if (p.precision == EB_PREC_BF16 && H->wf_on) {
+        set_error("pcg_solve: the BF16 smoother takes no per-point smoother weights");
+        return EB_ENOTIMPL;
     }
     memset(res, 0, sizeof(*res));
     res->levels = H->nlev;
@@ -2556,9 +2638,12 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         res->status = EB_OK;
         return EB_OK;
     }
-    // the single-precision V-cycle needs a hierarchy below the fine level
-    const bool fp32 = p.precision == EB_PREC_FP32 && H->nlev > 1;
+    // the single-precision V-cycle (and the BF16 smoother inside it) needs a
+    // hierarchy below the fine level
+    const bool b16 = p.precision == EB_PREC_BF16 && H->nlev > 1;
+    const bool fp32 = (p.precision == EB_PREC_FP32 || p.precision == EB_PREC_BF16) && H->nlev > 1;
     if (fp32) EB_TRY(ensure_fp32(H, s));
+    if (b16) EB_TRY(ensure_bf16(H, s));
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const unsigned ug = grid_for(nunk, NT);
@@ -2578,6 +2663,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         EB_TRY(enqueue_init(H, p.tol, iter_base, s));
         // V-cycle 0 -> rz[0]
         if (H->nlev == 1) EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.rz[0], 0, s));
+        else if (b16) EB_TRY((enqueue_vcycle_any<float, true>(H, H->rr[0], (bf16*)H->z16, H->red.rz[0], s)));
         else if (fp32) EB_TRY(enqueue_vcycle_any<float>(H, H->rr[0], H->z32, H->red.rz[0], s));
         else EB_TRY(enqueue_vcycle_any<double>(H, H->rr[0], H->z, H->red.rz[0], s));
         // Iterations go out in chunks between polls of the device scalars.
@@ -2596,7 +2682,8 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             for (int c = 0; c < chunk;) {
                 // graphs: not with a one-level hierarchy or while a kernel is being timed
                 if (graphs && k + 1 >= 3 && ((k + 1) & 1) && chunk - c >= 2) {
-                    if (fp32) EB_TRY(launch_iteration_pair<float>(H, s));
+                    if (b16) EB_TRY((launch_iteration_pair<float, true>(H, s)));
+                    else if (fp32) EB_TRY(launch_iteration_pair<float>(H, s));
                     else EB_TRY(launch_iteration_pair<double>(H, s));
                     k += 2;
                     c += 2;
@@ -2607,6 +2694,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
                 ++c;
                 ++enqueued;
                 if (H->nlev == 1) EB_TRY(enqueue_iteration_one_level(H, k, s));
+                else if (b16) EB_TRY((enqueue_iteration_any<float, true>(H, k, s)));
                 else if (fp32) EB_TRY(enqueue_iteration_any<float>(H, k, s));
                 else EB_TRY(enqueue_iteration_any<double>(H, k, s));
             }
@@ -2705,20 +2793,35 @@ static int vcycle_apply(amg_handle_t* H, const double* r, double* z, int precisi
     const int64_t nunk = H->n_fine;
     EB_HIP(hipMemsetAsync(z, 0, sizeof(double) * nn, s));
     if (nunk == 0) return EB_OK;
-    const bool fp32 = precision == EB_PREC_FP32 && H->nlev > 1;
+    if (precision != EB_PREC_FP64 && precision != EB_PREC_FP32 && precision != EB_PREC_BF16) {
+        set_error("%s: precision must be 0, 1 or 2", name);
+        return EB_EINVAL;
+    }
+    if (precision == EB_PREC_BF16 && H->wf_on) {
+        set_error("%s: the BF16 smoother takes no per-point smoother weights", name);
+        return EB_ENOTIMPL;
+    }
+    const bool b16 = precision == EB_PREC_BF16 && H->nlev > 1;
+    const bool fp32 = (precision == EB_PREC_FP32 || precision == EB_PREC_BF16) && H->nlev > 1;
     if (fp32) EB_TRY(ensure_fp32(H, s));
+    if (b16) EB_TRY(ensure_bf16(H, s));
     const unsigned ug = grid_for(nunk, NT);
     hipLaunchKernelGGL(k_mark_running, dim3(1), dim3(1), 0, s, H->sc);
     hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, r, H->rr[0]);
     EB_LAUNCH_CHECK();
     if (H->nlev == 1) {
         EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.aux2, 0, s));
+    } else if (b16) {
+        EB_TRY((enqueue_vcycle_any<float, true>(H, H->rr[0], (bf16*)H->z16, H->red.aux2, s)));
     } else if (fp32) {
         EB_TRY(enqueue_vcycle_any<float>(H, H->rr[0], H->z32, H->red.aux2, s));
     } else {
         EB_TRY(enqueue_vcycle_any<double>(H, H->rr[0], H->z, H->red.aux2, s));
     }
-    if (fp32) {
+    if (b16) {
+        hipLaunchKernelGGL(k_store_field<bf16>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad,
+                           (const bf16*)H->z16, z);
+    } else if (fp32) {
         hipLaunchKernelGGL(k_store_field<float>, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, H->z32,
                            z);
     } else {
@@ -2736,6 +2839,10 @@ extern "C" int amg_vcycle_apply(amg_handle_t* H, const double* r, double* z, voi
 
 extern "C" int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* stream) {
     return vcycle_apply(H, r, z, EB_PREC_FP32, stream, "amg_vcycle_apply_fp32");
+}
+
+extern "C" int amg_vcycle_apply_prec(amg_handle_t* H, const double* r, double* z, int32_t precision, void* stream) {
+    return vcycle_apply(H, r, z, precision, stream, "amg_vcycle_apply_prec");
 }
 
 extern "C" int eb_timing_select(amg_handle_t* H, int kernel_id) {

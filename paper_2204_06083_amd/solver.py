@@ -383,13 +383,13 @@ class Hierarchy:
         return n.value, ms.value
 
     def vcycle(self, r: torch.Tensor, precision: str = "fp64") -> torch.Tensor:
-        """One V(1,1) cycle z = M r; precision "fp64" or "fp32" (single-precision cycle)."""
+        """One V(1,1) cycle z = M r; precision "fp64", "fp32" (single-precision
+        cycle) or "bf16" (that cycle with the BF16 fine smoother)."""
         shape = self.grid.shape
         z = torch.empty(shape, dtype=torch.float64, device=r.device)
-        fn = {"fp64": "amg_vcycle_apply", "fp32": "amg_vcycle_apply_fp32"}[precision]
-        rc = getattr(L.lib(), fn)(self.handle, _field(r, shape, torch.float64, "r"), C.c_void_p(z.data_ptr()),
-                                  _stream())
-        L.check(rc, fn)
+        rc = L.lib().amg_vcycle_apply_prec(self.handle, _field(r, shape, torch.float64, "r"), C.c_void_p(z.data_ptr()),
+                                           L.PRECISION[precision], _stream())
+        L.check(rc, "amg_vcycle_apply_prec")
         return z
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-8, maxit: int = 1000,

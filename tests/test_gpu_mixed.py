@@ -130,3 +130,93 @@ def test_mixed_determinism_and_errors():
     assert rc == L.EB_EINVAL
     H.free()
     H2.free()
+
+
+# --------------------------------------------------------------- BF16 smoother
+# The BF16 smoother stores the preconditioned residual z in BF16 (relative
+# rounding at most 2^-9 per entry) and scales its post-smoothing sweep by a
+# BF16 copy of 1/d (again at most 2^-9 on the terms it scales, which are of
+# the size of z).  Against the oracle's FP64 cycle that is a few times 2^-9
+# in the 2-norm on top of the FP32 cycle's 2e-5: bounded by 1e-2.  The solve
+# keeps the FP64 outer CG with its true-residual check, so the answer must
+# still be within 1e-6 of the oracle's FP64 solution.
+VCYCLE_BF16_REL = 1e-2
+
+
+@pytest.mark.parametrize("name", ["disk128", "star512", "ell48"])
+def test_vcycle_bf16_against_oracle(name):
+    mk, _ = CASES[name]
+    prob = mk()
+    print(f"[gpu] bf16 vcycle {name} grid={prob.grid.shape}", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    Ho = OA.build_hierarchy(A, E.unknown_coords(asm_o))
+    asm_g, _ = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(asm_o.n_unknowns)
+    field = np.zeros(prob.grid.shape).ravel()
+    field[asm_o.nodes] = r
+    zo = OA.vcycle(Ho, r)
+    z16 = H.vcycle(to_dev(field.reshape(prob.grid.shape)), precision="bf16").cpu().numpy().ravel()
+    e16 = rel(z16[asm_o.nodes], zo)
+    print(f"  bf16 cycle rel {e16:.3e}", flush=True)
+    assert 1e-5 < e16 <= VCYCLE_BF16_REL
+    assert not np.any(z16[asm_o.kind.ravel() != 2])
+    H.free()
+
+
+@pytest.mark.parametrize("name", ["disk128", "star512", "star1000_ragged", "heat512_sigma", "ell48"])
+def test_bf16_smoother_solve_against_oracle(name):
+    mk, tol = CASES[name]
+    prob = mk()
+    print(f"[gpu] bf16-smoother pcg {name} grid={prob.grid.shape}", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    ref, _ = OP.amg_pcg(A, E.unknown_coords(asm_o), b_o, tol=1e-12)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a, prob.sigma)
+    x64, i64 = H.solve(b_g, tol=tol)
+    x16, i16 = H.solve(b_g, tol=tol, precision="bf16")
+    xs = x16.cpu().numpy().ravel()
+    e16 = rel(xs[asm_o.nodes], ref.x)
+    print(f"  iters fp64 {i64['iterations']} bf16 {i16['iterations']} (restarts {i16['restarts']}); "
+          f"err {e16:.2e}", flush=True)
+    assert i16["status"] == 0
+    assert i16["rel_res_true"] <= tol
+    assert np.linalg.norm(b_o - A @ xs[asm_o.nodes]) <= tol * np.linalg.norm(b_o) * 1.0001
+    assert e16 <= 1e-6
+    assert i16["iterations"] <= i64["iterations"] + 5
+    H.free()
+
+
+def test_bf16_smoother_full_size_star2048_and_errors():
+    prob = W.star_poisson(2048)
+    print("[gpu] bf16-smoother pcg star2048 full", flush=True)
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    x64, i64 = H.solve(b_g, tol=1e-8)
+    x16, i16 = H.solve(b_g, tol=1e-8, precision="bf16")
+    x16b, i16b = H.solve(b_g, tol=1e-8, precision="bf16")
+    assert torch.equal(x16, x16b) and i16["iterations"] == i16b["iterations"]
+    xs = x16.cpu().numpy().ravel()[asm_o.nodes]
+    x6 = x64.cpu().numpy().ravel()[asm_o.nodes]
+    print(f"  iters fp64 {i64['iterations']} bf16 {i16['iterations']} rel diff {rel(xs, x6):.2e}", flush=True)
+    assert np.linalg.norm(b_o - A @ xs) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
+    assert rel(xs, x6) <= 1e-6
+    # per-point smoother weights are not taken by the BF16 smoother
+    w = torch.full_like(b_g, 0.5)
+    assert L.lib().amg_set_fine_weights(H.handle, C.c_void_p(w.data_ptr()), None) == L.EB_OK
+    prm = L.PcgParams(1e-8, 100, 0, 8, L.PRECISION["bf16"])
+    res = L.PcgResult()
+    x = torch.empty_like(b_g)
+    rc = L.lib().pcg_solve(H.handle, C.c_void_p(b_g.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(prm),
+                           C.byref(res), None)
+    assert rc == L.EB_ENOTIMPL
+    assert L.lib().amg_clear_fine_weights(H.handle) == L.EB_OK
+    x16c, _ = H.solve(b_g, tol=1e-8, precision="bf16")
+    assert torch.equal(x16c, x16)
+    # batched solves do not take it
+    with pytest.raises(L.EbError) as ei:
+        H.solve_batched(torch.stack([b_g, b_g]).contiguous(), tol=1e-8, precision="bf16")
+    assert ei.value.code == L.EB_EINVAL
+    H.free()

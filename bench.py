@@ -262,23 +262,27 @@ def learned_ellipsoid(n=256, n_train=96, steps=120, reps=3):
     ls = S.LearnedSmoother(Ht, asmt, psit, seed=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = ls.train(steps=steps, samples=4, sweeps=6, lr=3e-3, seed=1)
+    hist = ls.fit(steps=steps, samples=4, sweeps=6, lr=3e-3, seed=1)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    params = ls.params.cpu().numpy()
+    params, gl = ls.params.cpu().numpy(), dict(ls.g)
     Ht.free()
     p, psi, asm, b, H, setup_ms = build(n)
     out = {"workload": f"ellipsoid3d_{n}_poisson_tol1e-8", "n_unknowns": asm.n_unknowns, "levels": H.n_levels,
            "assembly_rhs_setup_ms": setup_ms,
            "training": {"grid": f"{n_train}^3", "steps": steps, "seconds": train_s,
-                        "loss_first": hist[0], "loss_last5_mean": sum(hist[-5:]) / 5}}
+                        "loss_first": hist[0], "loss_last5_mean": sum(hist[-5:]) / 5,
+                        "level_weight_multipliers": {str(k): v for k, v in gl.items()}}}
     for prec in ("fp64", "fp32"):
         out[f"plain_{prec}"] = timed(H, b, prec)
     la = S.LearnedSmoother(H, asm, psi, params=params)
+    la.g = dict(gl)
     la.apply()
+    la.apply_levels(gl)
     for prec in ("fp64", "fp32"):
         out[f"learned_{prec}"] = timed(H, b, prec)
     out["selection"] = la.select(b, tol=1e-8)
+    out["learned_fp32_vs_plain_fp64_time"] = out["plain_fp64"]["solve_ms"] / out["learned_fp32"]["solve_ms"]
     H.free()
     return out
 
@@ -321,10 +325,18 @@ def shape_opt_islands(count=256, nrhs=4, reps=2):
         f_c[:, r0:r0 + sh[0], :sh[1]] = srcs[i]
     n_unk = 0
 
-    def island_run(prec):
+    def island_run(prec, gl=None):
         asm = S.assemble_diag(canvas.grid, psi_c)
         B = torch.stack([S.assemble_rhs_islands(asm, canvas, f_c[j]) for j in range(nrhs)]).contiguous()
         H = S.Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
+        if gl:
+            # learned per-level smoothing weights (the batched solve takes
+            # the coarse levels' weights; the per-point fine weights are for
+            # single solves)
+            last = 1.0
+            for lv in H.smoothed_levels():
+                last = gl.get(lv, last)
+                H.set_level_weight(lv, last)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-8, precision=prec)
@@ -372,6 +384,39 @@ def shape_opt_islands(count=256, nrhs=4, reps=2):
                      "sequential_ms": t_seq * 1e3, "sequential_solves_per_s": nsys / t_seq,
                      "sequential_iterations_min_max": [min(sits), max(sits)],
                      "speedup_vs_sequential": t_seq / t_all}
+    # learned leg: the smoother trained on the GPU on one star that is not in
+    # the batch (N = 256), its per-level weights applied to the island
+    # hierarchy, single-precision cycle, against plain FP64 above
+    n_t, c_t, ph_t = next(q for q in W.random_star_params(40, seed=W.SEED_BASE + 777) if q[0] == 256)
+    gt = W.unit_box_grid(2, n_t)
+    psi_t = psi_of(gt, c_t, ph_t)
+    asm_t = S.assemble_diag(gt, psi_t)
+    Ht = S.Hierarchy(gt, asm_t.kind, asm_t.a, 0.0)
+    ls = S.LearnedSmoother(Ht, asm_t, psi_t, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ls.fit(steps=40, samples=4, sweeps=6, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    gl = dict(ls.g)
+    Ht.free()
+    island_run("fp32", gl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos, t_solve, lev = island_run("fp32", gl)
+    torch.cuda.synchronize()
+    t_all = (time.perf_counter() - t0) / reps
+    its = [x["iterations"] for row in infos for x in row]
+    nsys = count * nrhs
+    out["learned_levels_fp32"] = {
+        "training": {"geometry": "random star N=256 not in the batch", "seconds": t_train,
+                     "level_weight_multipliers": {str(k): v for k, v in gl.items()}},
+        "ms": t_all * 1e3, "solve_ms": t_solve * 1e3, "solves_per_s": nsys / t_all,
+        "iterations_min_max": [min(its), max(its)],
+        "rel_res_true_max": max(x["rel_res_true"] for row in infos for x in row),
+        "all_converged": all(x["status"] == 0 for row in infos for x in row),
+        "speedup_vs_plain_fp64": out["fp64"]["ms"] / (t_all * 1e3)}
     out["n_unknowns"] = n_unk
     return out
 

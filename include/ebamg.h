@@ -405,6 +405,15 @@ int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z, void* str
  * EB_PREC_BF16 while per-point smoother weights are set.                    */
 int amg_vcycle_apply_prec(amg_handle_t* H, const double* r, double* z, int32_t precision, void* stream);
 
+/* Smoothing weight of coarse level `level` (1 <= level < levels - 1; the
+ * coarsest is solved exactly) in the V-cycle's pre- and post-smoothing:
+ * factor times the set-up weight 4 / (3 rho) (factor 1 restores it).  The
+ * smoothed prolongators built at setup keep their weight.  Used by the
+ * learned smoother (per-level weights); later solves, V-cycles and batched
+ * solves on H use it.  Asynchronous on `stream`; EB_EINVAL on a bad level or
+ * a factor that is not finite and positive.                                 */
+int amg_set_level_weight(amg_handle_t* H, int32_t level, double factor, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned fine-level smoother (an extension of the method: the paper fixes
  * no smoother, Sec. 3 preamble / Algorithm 2 step 4).  A convolutional

@@ -20,7 +20,7 @@ BC_MODES = {"line": EB_BC_LINE, "mixed": EB_BC_MIXED, "rbf": EB_BC_RBF}
 
 EXPORTS = [
     "eb_assemble_diag", "eb_assemble_diag_mode", "eb_assemble_rhs", "eb_assemble_rhs_islands", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
-    "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_vcycle_apply_prec", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
+    "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_vcycle_apply_prec", "amg_set_level_weight", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
     "eb_smoother_scratch_floats", "eb_adam_step", "amg_set_fine_weights", "amg_clear_fine_weights",
@@ -121,6 +121,8 @@ def lib():
     L.amg_vcycle_apply.argtypes = [vp, vp, vp, vp]
     L.amg_vcycle_apply_fp32.argtypes = [vp, vp, vp, vp]
     L.amg_vcycle_apply_prec.argtypes = [vp, vp, vp, i32, vp]
+    L.amg_set_level_weight.argtypes = [vp, i32, dbl, vp]
+    L.amg_set_level_weight.restype = i32
     L.amg_num_levels.argtypes = [vp]
     L.amg_level_info.argtypes = [vp, C.c_int, C.POINTER(LevelInfo)]
     L.amg_fine_nodes.argtypes = [vp]

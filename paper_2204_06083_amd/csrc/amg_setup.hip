@@ -1855,6 +1855,7 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         if (!L.is_coarsest) {
             L.rho = rep.scal[2 * k];
             L.omega = rep.scal[2 * k + 1];
+            L.omega_setup = L.omega;
         }
     }
     EB_TRY(err_code(st.err, "amg_setup"));

@@ -896,6 +896,14 @@ static int ilog2(int v) {
     return l;
 }
 
+void drop_batch_graph(amg_handle* H) {
+    BatchBufs* B = H->batch;
+    if (B && B->it_graph) {
+        (void)hipGraphExecDestroy(B->it_graph);
+        B->it_graph = nullptr;
+    }
+}
+
 void free_batch(amg_handle* H, hipStream_t s) {
     BatchBufs* B = H->batch;
     if (!B) return;

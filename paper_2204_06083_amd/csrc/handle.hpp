@@ -25,6 +25,7 @@ struct Sell {
 struct Level {
     int64_t n = 0, nnz_a = 0, nnz_p = 0, nnz_r = 0, nnz_ap = 0;
     double rho = 0.0, omega = 0.0;
+    double omega_setup = 0.0;    // 4 / (3 rho) as set up (omega may be overridden for the V-cycle)
     int is_coarsest = 0;
     int max_comp = 0;            // most coarse unknowns sharing one box of this level
     int ext[3] = {1, 1, 1};      // coordinate extents
@@ -178,6 +179,7 @@ namespace eb {
 int ensure_fp32(amg_handle* H, hipStream_t s);   // FP32 hierarchy copies (solve.hip)
 int ensure_bf16(amg_handle* H, hipStream_t s);   // BF16 smoother operands (solve.hip)
 void free_batch(amg_handle* H, hipStream_t s);   // batched.hip
+void drop_batch_graph(amg_handle* H);            // batched.hip: the captured batched iterations
 // Destroys the captured iteration graphs of a handle (solve.hip).
 void drop_iteration_graphs(amg_handle* H);
 // The eb_set_iteration_graphs switch, read by single and batched solves (solve.hip).

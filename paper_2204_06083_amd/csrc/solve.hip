@@ -2841,6 +2841,41 @@ extern "C" int amg_vcycle_apply_fp32(amg_handle_t* H, const double* r, double* z
     return vcycle_apply(H, r, z, EB_PREC_FP32, stream, "amg_vcycle_apply_fp32");
 }
 
+__global__ void k_set_f64(double* p, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+extern "C" int amg_set_level_weight(amg_handle_t* H, int32_t level, double factor, void* stream) {
+    clear_error();
+    AllocScope scope(H ? &H->params : nullptr);
+    if (!H || level < 1 || level >= H->nlev || H->lev[level].is_coarsest || !(factor > 0.0) || isinf(factor)) {
+        set_error("amg_set_level_weight: a coarse level with a smoother (1 <= level < levels - 1) and a factor > 0");
+        return EB_EINVAL;
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : H->stream;
+    Level& L = H->lev[level];
+    const double w = factor == 1.0 ? L.omega_setup : factor * L.omega_setup;
+    if (w == L.omega) return EB_OK;
+    L.omega = w;
+    // captured iterations carry the weight as a kernel argument
+    drop_iteration_graphs(H);
+    drop_batch_graph(H);
+    if (level == 1 && H->box_w0) {
+        // the 2-D restriction's per-box omega_1 / d_1
+        const Level& B0 = H->lev[0];
+        const int64_t nb = (int64_t)B0.nb[0] * B0.nb[1];
+        hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, H->dscal + 2 * 1 + 1, w);
+        hipLaunchKernelGGL(k_box_w0, dim3(grid_for(nb)), dim3(BLOCK), 0, s, nb, (const int32_t*)B0.box_cstart,
+                           (const int32_t*)B0.box_ncomp, (const double*)L.diag, (const double*)H->dscal, H->box_w0);
+        if (H->box_w0_32)
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nb, NT)), dim3(NT), 0, s, nb, (const double*)H->box_w0,
+                               H->box_w0_32);
+        EB_LAUNCH_CHECK();
+    }
+    H->last_stream = s;
+    return EB_OK;
+}
+
 extern "C" int amg_vcycle_apply_prec(amg_handle_t* H, const double* r, double* z, int32_t precision, void* stream) {
     return vcycle_apply(H, r, z, precision, stream, "amg_vcycle_apply_prec");
 }

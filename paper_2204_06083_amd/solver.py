@@ -7,6 +7,7 @@ in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 from typing import Optional
 
@@ -392,6 +393,16 @@ class Hierarchy:
         L.check(rc, "amg_vcycle_apply_prec")
         return z
 
+    def set_level_weight(self, level: int, factor: float = 1.0):
+        """amg_set_level_weight: V-cycle smoothing weight of a coarse level,
+        `factor` times the set-up 4 / (3 rho) (1 restores it)."""
+        L.check(L.lib().amg_set_level_weight(self.handle, int(level), float(factor), _stream()),
+                "amg_set_level_weight")
+
+    def smoothed_levels(self) -> list:
+        """Coarse levels with a smoother (1 .. levels - 2)."""
+        return [l for l in range(1, self.n_levels) if not self.level(l).is_coarsest]
+
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-8, maxit: int = 1000,
               check_every: int = 8, out: Optional[torch.Tensor] = None, allow_noconv: bool = False,
               precision: str = "fp64"):
@@ -641,6 +652,7 @@ class LearnedSmoother:
                                    device=dev)
         self.grads = torch.zeros(self.P, dtype=torch.float32, device=dev)
         self.omega0 = H.level(0).omega
+        self.g = {}             # per-level multipliers of the coarse smoothing weights
 
     def forward(self) -> torch.Tensor:
         g = L.make_grid(self.grid)
@@ -716,6 +728,61 @@ class LearnedSmoother:
         self.apply()
         return history
 
+    def level_search(self, samples: int = 4, sweeps: int = 4, seed: int = 0, gmax: float = 3.0,
+                     evals: int = 10, passes: int = 2) -> dict:
+        """Per-level smoothing weights of the coarse levels: g_l times the
+        set-up 4 / (3 rho_l), g_l in [1, gmax].  Each level in turn (finest
+        coarse level first, `passes` times) takes the g minimising the same
+        loss as the network, by golden-section search over `evals` loss
+        evaluations, on fixed error samples: `samples` seeded N(0, 1) fields
+        (rough errors) and as many left by `sweeps` cycles (smooth errors),
+        drawn with the cycle as it stands at the start of each pass.  Leaves
+        the weights installed; returns {level: g}."""
+        levels = self.H.smoothed_levels()
+        gen = torch.Generator(device=self.params.device)
+        gen.manual_seed(int(seed))
+        mask = (self.asm.kind == 2).to(torch.float64)
+        shape = (samples,) + tuple(self.grid.shape)
+        for l in levels:
+            self.g.setdefault(l, 1.0)
+        phi = (math.sqrt(5.0) - 1.0) / 2.0
+        for _ in range(passes):
+            xi = (torch.randn(shape, dtype=torch.float64, device=self.params.device, generator=gen) * mask)
+            xs = (torch.randn(shape, dtype=torch.float64, device=self.params.device, generator=gen) * mask)
+            e = torch.cat([self.samples(xi.contiguous(), 0), self.samples(xs.contiguous(), sweeps)]).contiguous()
+            for l in levels:
+                def loss_at(g):
+                    self.H.set_level_weight(l, g)
+                    return self.loss_grad(e)[0]
+                a, b = 1.0, gmax
+                c, d = b - phi * (b - a), a + phi * (b - a)
+                fc, fd = loss_at(c), loss_at(d)
+                for _ in range(max(evals - 2, 0)):
+                    if fc <= fd:
+                        b, d, fd = d, c, fc
+                        c = b - phi * (b - a)
+                        fc = loss_at(c)
+                    else:
+                        a, c, fc = c, d, fd
+                        d = a + phi * (b - a)
+                        fd = loss_at(d)
+                self.g[l] = c if fc <= fd else d
+                self.H.set_level_weight(l, self.g[l])
+        return dict(self.g)
+
+    def apply_levels(self, g_by_level: dict):
+        """Install per-level multipliers {level: g} on this hierarchy; its levels
+        beyond the given ones take the multiplier of the deepest given level."""
+        last = 1.0
+        for l in self.H.smoothed_levels():
+            last = g_by_level.get(l, last)
+            self.g[l] = last
+            self.H.set_level_weight(l, last)
+
+    def clear_levels(self):
+        for l in self.H.smoothed_levels():
+            self.H.set_level_weight(l, 1.0)
+
     def clear(self):
         L.check(L.lib().amg_clear_fine_weights(self.H.handle), "amg_clear_fine_weights")
 
@@ -724,11 +791,23 @@ class LearnedSmoother:
         plain smoother; otherwise fall back to the plain smoother.  Returns both
         counts and the choice."""
         self.apply()
+        self.apply_levels(self.g)
         _, il = self.H.solve(b, tol=tol, precision=precision, allow_noconv=True)
         self.clear()
+        self.clear_levels()
         _, ip = self.H.solve(b, tol=tol, precision=precision, allow_noconv=True)
         use = il["status"] == 0 and il["iterations"] < ip["iterations"]
         if use:
             self.apply()
+            self.apply_levels(self.g)
         return {"plain_iterations": ip["iterations"], "learned_iterations": il["iterations"],
                 "learned_status": il["status"], "use_learned": bool(use)}
+
+    def fit(self, steps: int = 100, samples: int = 4, sweeps: int = 6, lr: float = 3e-3, seed: int = 0):
+        """The whole training: per-level weights (level_search), the network
+        (train) with them in place, the per-level weights again.  Returns the
+        network's loss history."""
+        self.level_search(samples=samples, sweeps=4, seed=seed + 101, passes=1)
+        hist = self.train(steps=steps, samples=samples, sweeps=sweeps, lr=lr, seed=seed)
+        self.level_search(samples=samples, sweeps=4, seed=seed + 202, passes=1)
+        return hist

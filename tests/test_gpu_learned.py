@@ -122,7 +122,7 @@ def test_forward_backward_against_oracle(name):
     grads = ls.backward(to_dev(gom.reshape(prob.grid.shape))).cpu().numpy()
     go = np.zeros(om_g.size)
     th = np.tanh(o_g[nodes].astype(np.float64))
-    go[nodes] = gom[nodes] * Ho.levels[0].omega * 0.5 * (1.0 - th * th)
+    go[nodes] = gom[nodes] * Ho.levels[0].omega * LN.OMEGA_SPAN * (1.0 - th * th)
     # the oracle's backward in FP64 on the GPU's own activations: the ReLU
     # masks then agree even where a pre-activation is within rounding of 0
     # (constant features far from the boundary make whole regions tie)
@@ -303,3 +303,99 @@ def test_learned_weights_after_recycled_nan_blocks():
     x, info = solve_disk()
     assert info["status"] == 0 and info["iterations"] == i_ref["iterations"]
     assert torch.equal(x, x_ref)
+
+
+@pytest.mark.parametrize("name", ["star256", "ell40"])
+def test_level_weights_against_oracle(name):
+    """amg_set_level_weight: the V-cycle with coarse smoothing weights g_l times
+    4 / (3 rho_l) (the prolongators keep theirs) against the oracle's cycle with
+    the same weights; factor 1 gives back the set-up cycle bit for bit; the
+    batched solve takes the weights too."""
+    prob, asm_o, A, b_o, Ho, asm_g, b_g, H, f = _setup(name)
+    print(f"[gpu] level weights {name} levels={H.n_levels}", flush=True)
+    levels = H.smoothed_levels()
+    assert levels and levels == [l for l in range(1, Ho.n_levels) if Ho.levels[l].chol is None]
+    rng = np.random.default_rng(8)
+    n = asm_o.n_unknowns
+    nodes = asm_o.nodes
+    r = rng.standard_normal(n)
+    rf = np.zeros(prob.grid.shape).ravel()
+    rf[nodes] = r
+    rd = to_dev(rf.reshape(prob.grid.shape))
+    z_plain = H.vcycle(rd)
+    x_plain, i_plain = H.solve(b_g, tol=1e-10)
+    gs = {l: 1.3 + 0.4 * k for k, l in enumerate(levels)}
+    for l, g in gs.items():
+        H.set_level_weight(l, g)
+        Ho.levels[l].omega = g * Ho.levels[l].omega
+    zo = OA.vcycle(Ho, r)
+    z64 = H.vcycle(rd).cpu().numpy().ravel()[nodes]
+    z32 = H.vcycle(rd, precision="fp32").cpu().numpy().ravel()[nodes]
+    assert rel(z64, zo) <= 1e-12
+    assert rel(z32, zo) <= 2e-5
+    x_w, i_w = H.solve(b_g, tol=1e-10)
+    assert i_w["status"] == 0 and i_w["rel_res_true"] <= 1e-10
+    xb, ib = H.solve_batched(torch.stack([b_g, b_g]).contiguous(), tol=1e-10)
+    assert rel(xb[1].cpu().numpy(), x_w.cpu().numpy()) <= 1e-9
+    print(f"  iterations set-up weights {i_plain['iterations']}, levels x{list(gs.values())} {i_w['iterations']}",
+          flush=True)
+    for l in levels:
+        H.set_level_weight(l, 1.0)
+    assert torch.equal(H.vcycle(rd), z_plain)
+    x_back, i_back = H.solve(b_g, tol=1e-10)
+    assert torch.equal(x_back, x_plain) and i_back["iterations"] == i_plain["iterations"]
+    for bad in (0, H.n_levels - 1):
+        with pytest.raises(L.EbError):
+            H.set_level_weight(bad, 1.2)
+    with pytest.raises(L.EbError):
+        H.set_level_weight(levels[0], 0.0)
+    H.free()
+
+
+HELD_OUT = {
+    "star2d": (lambda: W.star_poisson(128), [lambda: W.star_poisson(512),
+                                             lambda: W.random_star_poisson(*W.random_star_params(6, seed=5)[4]),
+                                             lambda: W.disk_poisson(256)]),
+    "ell3d": (lambda: W.ellipsoid_poisson(32), [lambda: W.ellipsoid_poisson(64), lambda: W.ellipsoid_poisson(96)]),
+}
+
+
+@pytest.mark.parametrize("family", list(HELD_OUT))
+def test_learned_smoother_gains_on_held_out_geometries(family):
+    """The learned smoother (per-point fine weights from the network and
+    per-level coarse weights, trained on the GPU on a small geometry) needs
+    fewer PCG iterations to 1e-8 than the plain smoother on larger and other
+    geometries it was not trained on, in both V-cycle precisions, and the
+    fallback selection keeps it there."""
+    mk_train, tests = HELD_OUT[family]
+    pt = mk_train()
+    asm_t, _ = gpu_system(pt, oracle_system(pt)[3])
+    Ht = S.Hierarchy(pt.grid, asm_t.kind, asm_t.a)
+    ls = S.LearnedSmoother(Ht, asm_t, to_dev(pt.psi), seed=0)
+    hist = ls.fit(steps=60, samples=4, sweeps=6, lr=3e-3, seed=1)
+    params, g = ls.params.cpu().numpy(), dict(ls.g)
+    print(f"[gpu] learned {family}: loss {hist[0]:.4f} -> {min(hist[-5:]):.4f}, level multipliers {g}", flush=True)
+    Ht.free()
+    for mk in tests:
+        prob = mk()
+        asm_o, A, b_o, u = oracle_system(prob)
+        asm_g, b_g = gpu_system(prob, u)
+        H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+        la = S.LearnedSmoother(H, asm_g, to_dev(prob.psi), params=params)
+        la.g = dict(g)
+        for prec in ("fp64", "fp32"):
+            _, ip = H.solve(b_g, tol=1e-8, precision=prec)
+            la.apply()
+            la.apply_levels(g)
+            xl, il = H.solve(b_g, tol=1e-8, precision=prec)
+            la.clear()
+            la.clear_levels()
+            print(f"  {prob.name} {prob.grid.shape} {prec}: plain {ip['iterations']} learned {il['iterations']}",
+                  flush=True)
+            assert il["status"] == 0
+            assert np.linalg.norm(b_o - A @ xl.cpu().numpy().ravel()[asm_o.nodes]) <= \
+                1e-8 * np.linalg.norm(b_o) * 1.0001
+            assert il["iterations"] < ip["iterations"]
+        sel = la.select(b_g, tol=1e-8)
+        assert sel["use_learned"]
+        H.free()

@@ -21,6 +21,10 @@ What is computed, and where the paper defines it:
   the computational point and two boundary points chosen by
   the closest-point rule with the pi/4 rotation          Sec. 2.2, Eq. (rbf), (rbf_ubp);
                                                         Algorithm 1; phi from Sec. 3
+* variable conductivity beta (Eq. (1)): each side of the stencil carries
+  the face value beta_{i+-1/2}; a computational neighbour contributes
+  beta_f to a_k and -beta_f / h^2 off the diagonal, a BP side beta_f times
+  its interpolation weight(s) to a_k and to the records' c   Eq. (central_difference)
 * strategy: "line" (extended line-by-line everywhere),
   "mixed" (line-by-line where the node two steps out is
   outside, RBF otherwise), "rbf" (RBF on every BP side)  Sec. 2.3; Algorithm 2 step 3
@@ -57,6 +61,10 @@ Readings taken where the paper leaves a choice:
   crossing always exists.  Three collinear interpolation points raise
   GeometryError.
 * epsilon = 0.025 in the distinctness test (the value Sec. 2.3 reports).
+* beta_{i+1/2,j} is beta at the face midpoint, sampled by the caller: `beta`
+  is a (dim, *shape) array, beta[a] at a node holding the face toward +axis a
+  (None: beta = 1).  a_k adds the regular sides' beta_f in direction order,
+  then the records' c; with beta = 1 this is bit for bit the constant case.
 * An RBF side keeps two cut records, one per boundary point, whose c is the
   interpolant's weight of that point; the side adds c_1 + c_2 (= 1 - w_ij by
   the reproduction of constants) to the diagonal and u(x_Gamma) c / h^2 per
@@ -166,7 +174,8 @@ def number_unknowns(kind):
 class Assembly:
     """Result of assembling the line-by-line embedded-boundary operator."""
 
-    def __init__(self, grid, psi, kind, nodes, index, a, n_regular, cuts):
+    def __init__(self, grid, psi, kind, nodes, index, a, n_regular, cuts, beta=None):
+        self.beta = beta              # face conductivities or None (beta = 1)
         self.grid = grid
         self.psi = psi
         self.kind = kind
@@ -197,10 +206,11 @@ class GeometryError(ValueError):
     """Algorithm 1 found no second boundary point, or collinear points."""
 
 
-def assemble(grid, psi, mode="line"):
+def assemble(grid, psi, mode="line", beta=None):
     """Classify, number and build the diagonal and cut records (Algorithm 2, steps 1-3).
 
-    mode: "line" (extended line-by-line), "mixed" or "rbf" (Sec. 2.3).
+    mode: "line" (extended line-by-line), "mixed" or "rbf" (Sec. 2.3);
+    beta: face conductivities (dim, *shape) or None for beta = 1.
     """
     if mode not in MODES:
         raise ValueError(f"unknown mode {mode!r}")
@@ -220,6 +230,8 @@ def assemble(grid, psi, mode="line"):
     for (ax, step, _a) in directions(dim):
         nb = nodes + step * strides[ax]
         n_regular += (kflat[nb] == COMPUTATIONAL)
+    if beta is not None:
+        beta = np.ascontiguousarray(beta, dtype=np.float64).reshape((dim,) + psi.shape)
 
     # pass 2: every BP side, in direction order: its records
     cut_parts = []
@@ -243,14 +255,20 @@ def assemble(grid, psi, mode="line"):
                 node_xyz[:, p] = grid.x0[p] + ipos * grid.h
             else:
                 node_xyz[:, p] = 0.0
+        parts = []
         ln = np.flatnonzero(~use_rbf)
         if ln.size:
-            cut_parts.append(_line_records(pflat, strides, sel[ln], base[ln], node_xyz[ln],
-                                           s, ax, step, phys, grid.h))
+            parts.append(_line_records(pflat, strides, sel[ln], base[ln], node_xyz[ln],
+                                       s, ax, step, phys, grid.h))
         rb = np.flatnonzero(use_rbf)
         if rb.size:
             ij = np.stack([coords_of[1][sel[rb]], coords_of[0][sel[rb]]], axis=1)   # (i, j)
-            cut_parts.extend(_rbf_records(psi, ij, sel[rb], base[rb], node_xyz[rb], s, grid.h))
+            parts.extend(_rbf_records(psi, ij, sel[rb], base[rb], node_xyz[rb], s, grid.h))
+        if beta is not None:
+            for part in parts:   # the side's face: node + (step < 0 ? -e : 0)
+                face = part["node"] + (step * strides[ax] if step < 0 else 0)
+                part["c"] = beta[phys].ravel()[face] * part["c"]
+        cut_parts.extend(parts)
 
     keys = ("unknown", "node", "dir", "point", "steps", "t", "q", "c", "xg")
     if cut_parts:
@@ -262,11 +280,20 @@ def assemble(grid, psi, mode="line"):
                     dir=np.zeros(0, np.int64), point=np.zeros(0, np.int64),
                     steps=np.zeros(0, np.int64), t=np.zeros(0), q=np.zeros(0), c=np.zeros(0),
                     xg=np.zeros((0, 3)))
-    # a_k = n_regular, then + c of every record of k in record order
-    a = n_regular.astype(np.float64)
+    # a_k = the regular sides' beta_f in direction order (their count for
+    # beta = 1), then + c of every record of k in record order
+    if beta is None:
+        a = n_regular.astype(np.float64)
+    else:
+        a = np.zeros(nc)
+        for (ax, step, phys) in directions(dim):
+            nb = nodes + step * strides[ax]
+            reg = kflat[nb] == COMPUTATIONAL
+            face = nodes + (step * strides[ax] if step < 0 else 0)
+            a = np.where(reg, a + beta[phys].ravel()[face], a)
     for k, c in zip(cuts["unknown"], cuts["c"]):
         a[k] = a[k] + c
-    return Assembly(grid, psi, kind, nodes, index, a, n_regular, cuts)
+    return Assembly(grid, psi, kind, nodes, index, a, n_regular, cuts, beta)
 
 
 def _line_records(pflat, strides, sel, base, node_xyz, s, ax, step, phys, h):
@@ -544,7 +571,8 @@ def cut_coordinates(asm):
 
 
 def operator_csr(asm, sigma=0.0):
-    """A = (1/h^2)(diag(a) - adjacency) + sigma I as scipy CSR (sorted columns)."""
+    """A = (1/h^2)(diag(a) - adjacency weighted by beta_f) + sigma I as scipy
+    CSR (sorted columns)."""
     s = inv_h2(asm.grid)
     nc = asm.n_unknowns
     dim = asm.psi.ndim
@@ -553,12 +581,16 @@ def operator_csr(asm, sigma=0.0):
     rows = [np.arange(nc)]
     cols = [np.arange(nc)]
     vals = [asm.a * s + sigma]
-    for (ax, step, _a) in directions(dim):
+    for (ax, step, phys) in directions(dim):
         nb = idx[asm.nodes + step * strides[ax]]
         sel = nb >= 0
         rows.append(np.flatnonzero(sel))
         cols.append(nb[sel])
-        vals.append(np.full(int(sel.sum()), -s))
+        if asm.beta is None:
+            vals.append(np.full(int(sel.sum()), -s))
+        else:   # -beta_f / h^2 on the face toward the neighbour
+            face = asm.nodes[sel] + (step * strides[ax] if step < 0 else 0)
+            vals.append(-(asm.beta[phys].ravel()[face] * s))
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(nc, nc))
     A.sort_indices()

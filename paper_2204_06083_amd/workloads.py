@@ -333,6 +333,78 @@ def heat_cn_source(X, Y, t: float):
     return -heat_cn_exact(X, Y, t) - 4.0 * math.exp(-t)
 
 
+# ------------------------------------------------------- variable coefficient
+#
+# Eq. (1) with a variable conductivity beta: the scheme of Eq.
+# (central_difference) takes beta at the cell faces, beta_{i+1/2,j} between
+# nodes (i, j) and (i+1, j).  The caller samples beta there; these helpers
+# give the face fields as the library takes them: face[a] is a node field
+# holding beta at the midpoint between each node and its neighbour in +axis a
+# (the last node of each line holds beta one half step beyond the grid; it
+# borders no unknown).
+
+def beta_faces(grid: Grid, beta) -> np.ndarray:
+    """(dim, *grid.shape) array: beta at the +axis face midpoint of every node."""
+    comps = grid.mesh()
+    out = np.empty((grid.dim,) + tuple(grid.shape))
+    for a in range(grid.dim):
+        moved = [c + (0.5 * grid.h if b == a else 0.0) for b, c in enumerate(comps)]
+        out[a] = beta(*moved)
+    return out
+
+
+def beta_heat(X, Y):
+    """Sec. 3.4 conductivity beta = 0.25 - x^2 - y^2 (vanishes on the disk's edge)."""
+    return 0.25 - X * X - Y * Y
+
+
+def heat_beta_source(X, Y, t: float):
+    """Sec. 3.4: u = exp(-t) (x^2 + y^2 - 1/4) with beta = 1/4 - x^2 - y^2;
+    div(beta grad u) = exp(-t) (1 - 8 r^2), so u_t = div(beta grad u) + f needs
+    f = exp(-t) (7 r^2 - 3/4)."""
+    return math.exp(-t) * (7.0 * (X * X + Y * Y) - 0.75)
+
+
+def beta_bone(X, Y):
+    """Sec. 3.3.1 conductivity beta = 2 + sin(x y)."""
+    xp = _xp_of(X)
+    return 2.0 + xp.sin(X * Y)
+
+
+def u_bone(X, Y):
+    """Sec. 3.3.1 exact solution u = e^x (x^2 sin y + y^2)."""
+    xp = _xp_of(X)
+    return xp.exp(X) * (X * X * xp.sin(Y) + Y * Y)
+
+
+def f_bone(X, Y):
+    """-div(beta grad u) for beta_bone and u_bone:
+    beta Lap u + grad beta . grad u with Lap u = e^x (4x sin y + 2 sin y + y^2 + 2),
+    u_x = e^x (x^2 sin y + 2x sin y + y^2), u_y = e^x (x^2 cos y + 2y),
+    grad beta = cos(xy) (y, x)."""
+    xp = _xp_of(X)
+    ex = xp.exp(X)
+    s, c = xp.sin(Y), xp.cos(Y)
+    lap = ex * (4.0 * X * s + 2.0 * s + Y * Y + 2.0)
+    ux = ex * (X * X * s + 2.0 * X * s + Y * Y)
+    uy = ex * (X * X * c + 2.0 * Y)
+    cxy = xp.cos(X * Y)
+    return -((2.0 + xp.sin(X * Y)) * lap + cxy * (Y * ux + X * uy))
+
+
+def bone_beta_poisson(n: int) -> Problem:
+    """The bone example's beta and exact solution (Sec. 3.3.1) on a five-armed
+    star around (0, 1.5) in the example's box [-2, 2] x [-1, 3] (the bone's
+    parametric boundary itself is not used): -div(beta grad u) = f."""
+    g = Grid(dim=2, n=(n, n), x0=(-2.0, -1.0), h=4.0 / n)
+    X, Y = g.mesh()
+    Yc = Y - 1.5
+    phi = np.arctan2(Yc, X)
+    psi = np.sqrt(X * X + Yc * Yc) - (1.1 + 0.3 * np.cos(5 * phi))
+    return Problem("bone_beta_star", g, psi, f_bone(X, Y), u_exact=u_bone, u_dirichlet=u_bone, tol=1e-10,
+                   meta={"beta": beta_bone})
+
+
 # ------------------------------------------------- shape-parameter QOI studies
 #
 # Sec. 3.6: Poisson problems (beta = 1, zero Dirichlet data, source 3 in the

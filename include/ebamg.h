@@ -218,6 +218,21 @@ int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int32_t mode, i
                           eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
                           int64_t* n_cuts, void* stream);
 
+/* eb_assemble_diag_mode for a variable conductivity beta (Eq. (1), with the
+ * face values beta_{i+-1/2} of Eq. (central_difference)).  beta [in]: dim
+ * node fields back to back (device), field `axis` holding beta at the
+ * midpoint of the face between each node and its neighbour in +axis (the
+ * caller samples beta there); the face on the minus side of a node is its
+ * neighbour's.  Then a_k = (sum of the regular sides' beta_face, in side
+ * order) + (sum of the records' c), and a record's c is beta_face times its
+ * interpolation weight (1/q or the RBF weight), so eb_assemble_rhs is
+ * unchanged.  The operator's entry toward a computational neighbour is
+ * -beta_face / h^2 (amg_setup_beta).  beta = 1 gives eb_assemble_diag_mode
+ * bit for bit.  eb_check_spd (Sec. 2.4) assumes constant beta = 1.          */
+int eb_assemble_diag_beta(const eb_grid_t* g, const double* psi, const double* beta, int32_t mode,
+                          int8_t* kind, double* a, eb_cut_t* cuts, int64_t cuts_cap,
+                          int64_t* n_unknowns, int64_t* n_cuts, void* stream);
+
 /* A-priori SPD test (Sec. 2.4, Lemma 2.1, Theorems 1-2): along every axis,
  * every maximal run of computational points on a grid line is one segment of
  * the 1-D matrix D^(n)(a, b) whose end entries a, b are the part of the
@@ -265,6 +280,11 @@ int eb_assemble_rhs_islands(const eb_grid_t* g, const int8_t* kind, const double
 int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
                   const double* x, double* y, void* stream);
 
+/* stencil_apply for the variable-conductivity operator (eb_assemble_diag_beta):
+ * each computational neighbour enters with its face's beta (beta as there).  */
+int stencil_apply_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta, double sigma,
+                       const double* x, double* y, void* stream);
+
 /* Time-stepper right-hand sides on the same operator (node fields; outputs are
  * 0 off computational points; asynchronous).
  *
@@ -277,6 +297,10 @@ int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, doubl
  * up with that sigma.  EB_EINVAL for theta < 0, dt <= 0 or a non-finite scale. */
 int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double theta, double dt, double scale,
                 const double* un, const double* unm1, double* out, void* stream);
+/* The same with the variable-conductivity operator (cond: the face fields of
+ * eb_assemble_diag_beta).                                                    */
+int eb_wave_rhs_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond, double theta,
+                     double dt, double scale, const double* un, const double* unm1, double* out, void* stream);
 
 /* out = alpha (A + sigma I) x + beta y + gamma z.  With sigma = -2/dt,
  * alpha = -1, y = b^n, z = b^{n+1} it is the right-hand side of the
@@ -286,6 +310,11 @@ int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double 
 int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma, double alpha,
                        const double* x, double beta, const double* y, double gamma, const double* z, double* out,
                        void* stream);
+/* The same with the variable-conductivity operator (cond as above; the
+ * Crank-Nicolson step of the Sec. 3.4 example, beta = 1/4 - x^2 - y^2).     */
+int eb_stencil_combine_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond,
+                            double sigma, double alpha, const double* x, double beta, const double* y, double gamma,
+                            const double* z, double* out, void* stream);
 
 /* Linear quantities of interest over the islands of a canvas (Sec. 3.6: the
  * value of u at a node, the integral of u over a region, as w . u with node
@@ -321,6 +350,16 @@ int eb_segment_dots_noalloc(const double* w, const double* x, int32_t nfields, i
  * unless they take their own.                                                  */
 int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
               const amg_params_t* p, amg_handle_t** H, void* stream);
+
+/* amg_setup for the variable-conductivity operator of eb_assemble_diag_beta:
+ * beta as there (dim face fields, device, read during the call only).  The
+ * hierarchy is built from that operator; pcg_solve and the V-cycle calls
+ * run the fine level with face-weighted kernels.  Not available with it:
+ * batched and island solves, per-point smoother weights and the learned
+ * smoother calls, and the BF16 smoother (EB_ENOTIMPL); the FP64 and FP32
+ * V-cycles are.  EB_EINVAL for a null beta; otherwise as amg_setup.         */
+int amg_setup_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta, double sigma,
+                   const amg_params_t* p, amg_handle_t** H, void* stream);
 
 /* Solve A x = b by PCG with one V(1,1) cycle as preconditioner (Algorithm 2
  * step 4).  b, x are node fields; x holds x0 on entry if p->x0_given.  On

@@ -113,8 +113,11 @@ __global__ void __launch_bounds__(BLOCK) k_fine_rows(const int8_t* __restrict__ 
 // entries.
 constexpr int FILL_ROW_MAX = 7;
 
+// With beta (variable conductivity), the entry toward a neighbour is
+// -beta_face / h^2 with the face between the two nodes.
 __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ kind, const double* __restrict__ a,
-                                                     double sigma, GridDims d, int64_t nunk,
+                                                     const double* __restrict__ beta, double sigma, GridDims d,
+                                                     int64_t nunk,
                                                      const int64_t* __restrict__ fine_nodes,
                                                      const int32_t* __restrict__ unk_off,
                                                      const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
@@ -129,16 +132,17 @@ __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ 
         const int64_t n = fine_nodes[k];
         int32_t pos = rowptr[k] - base;
         const double off = -d.s;
-        int64_t nbrs[7];
+        const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+        int64_t nbrs[7], faces[7];
         int cnt = 0;
-        if (d.dim == 3) nbrs[cnt++] = n - d.sz;
-        nbrs[cnt++] = n - d.sy;
-        nbrs[cnt++] = n - 1;
+        if (d.dim == 3) { nbrs[cnt] = n - d.sz; faces[cnt++] = 2 * nn + n - d.sz; }
+        nbrs[cnt] = n - d.sy; faces[cnt++] = nn + n - d.sy;
+        nbrs[cnt] = n - 1; faces[cnt++] = n - 1;
         const int self = cnt;
-        nbrs[cnt++] = n;
-        nbrs[cnt++] = n + 1;
-        nbrs[cnt++] = n + d.sy;
-        if (d.dim == 3) nbrs[cnt++] = n + d.sz;
+        nbrs[cnt] = n; faces[cnt++] = 0;
+        nbrs[cnt] = n + 1; faces[cnt++] = n;
+        nbrs[cnt] = n + d.sy; faces[cnt++] = nn + n;
+        if (d.dim == 3) { nbrs[cnt] = n + d.sz; faces[cnt++] = 2 * nn + n; }
         for (int e = 0; e < cnt; ++e) {
             if (e == self) {
                 const double dg = a[n] * d.s + sigma;
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ 
                 ++pos;
             } else if (kind[nbrs[e]] == 2) {
                 col_s[pos] = unk_off[nbrs[e]];
-                val_s[pos] = off;
+                val_s[pos] = beta ? -(beta[faces[e]] * d.s) : off;
                 ++pos;
             }
         }
@@ -1729,7 +1733,7 @@ int free_handle_memory(amg_handle* H) {
     void* ptrs[] = {H->unk_off_tmp, H->strips, H->tiles, H->box_map0, H->box_w0, H->box_w0_32, H->dcount, H->boxes0, H->fine_nodes, H->fine_pad, H->diag_p, H->dinv_p, H->agg_p, H->x, H->rr[0], H->rr[1],
                     H->z, H->zt, H->p[0], H->p[1], H->q, H->res, H->bvec, H->sc, H->dscal, H->red.pq, H->red.rr,
                     H->red.rz[0], H->red.rz[1], H->red.aux, H->red.aux2, H->diag_p32, H->dinv_p32, H->res32, H->zt32, H->z32,
-                    H->wf, H->wf32, H->dinv_p16, H->z16};
+                    H->wf, H->wf32, H->dinv_p16, H->z16, H->bf_p[0], H->bf_p[1], H->bf_p[2]};
     for (void* p : ptrs) (void)dfree(p, s);
     H->sc_host = nullptr;
     H->tim_ev = nullptr;    // process-wide event pool, not owned
@@ -1784,8 +1788,8 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     EB_TRY(rowptr_from_counts(rowcnt, nunk, &L0.a_rowptr, s));
     EB_TRY(dalloc_n(&L0.a_col, nunk * L0.row_bound, s));
     EB_TRY(dalloc_n(&L0.a_val, nunk * L0.row_bound, s));
-    hipLaunchKernelGGL(k_fine_fill, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, kind, a, H->sigma, d, nunk,
-                       H->fine_nodes, unk_off, L0.a_rowptr, L0.a_col, L0.a_val, L0.diag);
+    hipLaunchKernelGGL(k_fine_fill, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, kind, a, H->beta_tmp, H->sigma, d,
+                       nunk, H->fine_nodes, unk_off, L0.a_rowptr, L0.a_col, L0.a_val, L0.diag);
     EB_LAUNCH_CHECK();
     EB_TRY(dfree(rowcnt, s));
     EB_TRY(dfree(flag, s));
@@ -1868,8 +1872,8 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
 
 using namespace eb;
 
-extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
-                         const amg_params_t* p, amg_handle_t** Hout, void* stream) {
+static int amg_setup_impl(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta,
+                          double sigma, const amg_params_t* p, amg_handle_t** Hout, void* stream) {
     clear_error();
     if (!Hout || !kind || !a) {
         set_error("amg_setup: null pointer");
@@ -1913,8 +1917,11 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
     H->sigma = sigma;
     H->stream = (hipStream_t)stream;
     H->params = prm;
+    H->beta_tmp = beta;
+    H->beta_on = beta != nullptr;
     AllocScope scope(&H->params);
     int rc = setup_impl(H, kind, a, H->stream);
+    H->beta_tmp = nullptr;
     if (rc != EB_OK) {
         char msg[1024];
         snprintf(msg, sizeof(msg), "%s", eb_last_error());
@@ -1925,6 +1932,20 @@ extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a
     }
     *Hout = H;
     return EB_OK;
+}
+
+extern "C" int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                         const amg_params_t* p, amg_handle_t** Hout, void* stream) {
+    return amg_setup_impl(g, kind, a, nullptr, sigma, p, Hout, stream);
+}
+
+extern "C" int amg_setup_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta,
+                              double sigma, const amg_params_t* p, amg_handle_t** Hout, void* stream) {
+    if (!beta) {
+        set_error("amg_setup_beta: null beta");
+        return EB_EINVAL;
+    }
+    return amg_setup_impl(g, kind, a, beta, sigma, p, Hout, stream);
 }
 
 extern "C" void amg_free(amg_handle_t* H) {

@@ -148,10 +148,23 @@ constexpr int DIAG_DEFER_CAP = 4096;          // deferred nodes (more: walked in
 constexpr int DIAG_LONG_NT = 1024;
 constexpr int DIAG_LONG_BLOCKS = 64;
 
+// Variable conductivity (Eq. (1)): beta holds dim node fields back to back,
+// field `axis` giving beta at the face between each node and its neighbour in
+// +axis; the face on the minus side of node n is that of n - e_axis.  NULL
+// means beta = 1.
+__device__ inline double face_beta(const double* __restrict__ beta, int64_t n, const GridDims& d, int side) {
+    const int axis = side >> 1;
+    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+    const int64_t face = (side & 1) ? n : n - axis_stride(d, axis);
+    return beta[(int64_t)axis * nn + face];
+}
+
 // The side's interpolation coefficient c = 1/q from the walk's end j (first
 // outside node, j >= 2), and its cut record m (if below the capacity).
+// With beta, c = beta_face / q (the face's conductivity times the weight).
 __device__ inline double diag_side(const double* __restrict__ psi, int64_t n, const NodePos& p, const GridDims& d,
-                                   int side, int j, int64_t m, eb_cut_t* __restrict__ cuts, int64_t cap) {
+                                   int side, int j, int64_t m, eb_cut_t* __restrict__ cuts, int64_t cap,
+                                   const double* __restrict__ beta) {
     const int axis = side >> 1;
     const int step = (side & 1) ? 1 : -1;
     const int64_t st = axis_stride(d, axis) * step;
@@ -159,7 +172,7 @@ __device__ inline double diag_side(const double* __restrict__ psi, int64_t n, co
     const double psi_out = psi[n + (int64_t)j * st];
     const double t = psi_in / (psi_in - psi_out);
     const double q = (double)(j - 1) + t;
-    const double c = 1.0 / q;
+    const double c = beta ? face_beta(beta, n, d, side) * (1.0 / q) : 1.0 / q;
     if (m < cap) {
         eb_cut_t rec;
         rec.node = n;
@@ -351,12 +364,18 @@ __device__ inline bool rbf_points(const double* __restrict__ psi, const GridDims
 // diagonal contribution w1 + w2 added in record order to acc.
 __device__ inline double rbf_side_records(const double* __restrict__ psi, int64_t n, const NodePos& p,
                                           const GridDims& d, int side, int64_t m, eb_cut_t* __restrict__ cuts,
-                                          int64_t cap, double acc, int32_t* __restrict__ err) {
+                                          int64_t cap, double acc, int32_t* __restrict__ err,
+                                          const double* __restrict__ beta) {
     Pt2 G[2];
     double w[2];
     if (!rbf_points(psi, d, p.i, p.j, side, G[0], G[1], w[0], w[1])) {
         atomicOr(err, DEVERR_GEOM);
         return acc;
+    }
+    if (beta) {
+        const double bf = face_beta(beta, n, d, side);
+        w[0] = bf * w[0];
+        w[1] = bf * w[1];
     }
     const double bx = d.x0 + (double)p.i * d.h, by = d.y0 + (double)p.j * d.h;
     for (int k = 0; k < 2; ++k) {
@@ -377,6 +396,11 @@ __device__ inline double rbf_side_records(const double* __restrict__ psi, int64_
     return acc;
 }
 
+// The regular sides' part of a_k: their count, or with beta the sum of
+// their face values in side order (-x, +x, -y, +y, -z, +z) from 0.
+__device__ inline double diag_regular_beta(const int8_t* __restrict__ kind, const double* __restrict__ beta, int64_t n,
+                                           const GridDims& d);
+
 __device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, const GridDims& d) {
     int nreg = 0;
     for (int axis = 0; axis < d.dim; ++axis) {
@@ -388,7 +412,7 @@ __device__ inline int diag_regular(const int8_t* __restrict__ kind, int64_t n, c
 }
 
 __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ psi, const int8_t* __restrict__ kind,
-                                                     GridDims d, int64_t nnodes, int mode,
+                                                     const double* __restrict__ beta, GridDims d, int64_t nnodes, int mode,
                                                      const int64_t* __restrict__ block_off,
                                                      double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                      int64_t cap, int32_t* __restrict__ err,
@@ -424,7 +448,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
     // registers than a line walk; kept out of this kernel)
     if (mode != EB_BC_LINE && node_has_rbf(kind, psi, n, d, mode)) return;
     const NodePos p = node_pos(n, d);
-    double acc = (double)diag_regular(kind, n, d);
+    double acc = diag_regular_beta(kind, beta, n, d);
     const int64_t m_first = block_off[blockIdx.x] + before;
     int64_t m = m_first;
     for (int side = 0; side < 2 * d.dim; ++side) {
@@ -475,7 +499,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
             }
             if (!found) j += DIAG_WALK;
         }
-        acc = acc + diag_side(psi, n, p, d, side, j, m, cuts, cap);
+        acc = acc + diag_side(psi, n, p, d, side, j, m, cuts, cap, beta);
         ++m;
     }
     a[n] = acc;
@@ -486,7 +510,8 @@ __global__ void __launch_bounds__(BLOCK) k_diag_cuts(const double* __restrict__ 
 // first that ends the walk (the same test as the thread's walk: an outside
 // node, or the outer layer); thread 0 then adds the sides in order.
 __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __restrict__ psi,
-                                                            const int8_t* __restrict__ kind, GridDims d,
+                                                            const int8_t* __restrict__ kind,
+                                                            const double* __restrict__ beta, GridDims d,
                                                             double* __restrict__ a, eb_cut_t* __restrict__ cuts,
                                                             int64_t cap, int32_t* __restrict__ err,
                                                             const int32_t* __restrict__ ndefer,
@@ -498,7 +523,7 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int64_t n = defer[2 * i];
         const NodePos p = node_pos(n, d);
-        double acc = (double)diag_regular(kind, n, d);
+        double acc = diag_regular_beta(kind, beta, n, d);
         int64_t m = defer[2 * i + 1];
         for (int side = 0; side < 2 * d.dim; ++side) {
             const int axis = side >> 1;
@@ -527,11 +552,22 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
                 j0 += DIAG_LONG_NT;
             }
             if (tid == f && edge && v < 0.0) atomicOr(err, DEVERR_DOMAIN);
-            if (tid == 0) acc = acc + diag_side(psi, n, p, d, side, j0 + f, m, cuts, cap);
+            if (tid == 0) acc = acc + diag_side(psi, n, p, d, side, j0 + f, m, cuts, cap, beta);
             ++m;
         }
         if (tid == 0) a[n] = acc;
     }
+}
+
+__device__ inline double diag_regular_beta(const int8_t* __restrict__ kind, const double* __restrict__ beta, int64_t n,
+                                           const GridDims& d) {
+    if (!beta) return (double)diag_regular(kind, n, d);
+    double acc = 0.0;
+    for (int side = 0; side < 2 * d.dim; ++side) {
+        const int64_t st = axis_stride(d, side >> 1) * ((side & 1) ? 1 : -1);
+        if (kind[n + st] == 2) acc = acc + face_beta(beta, n, d, side);
+    }
+    return acc;
 }
 
 // The unknowns with an RBF side (mixed and RBF-based strategies, 2-D): the
@@ -540,7 +576,8 @@ __global__ void __launch_bounds__(DIAG_LONG_NT) k_diag_long(const double* __rest
 // j = 2 (in the mixed strategy a line side has its node two steps out
 // outside; the RBF-based one has none), so no walk is needed.
 __global__ void __launch_bounds__(BLOCK) k_diag_rbf(const double* __restrict__ psi, const int8_t* __restrict__ kind,
-                                                    GridDims d, int64_t nnodes, int mode,
+                                                    const double* __restrict__ beta, GridDims d, int64_t nnodes,
+                                                    int mode,
                                                     const int64_t* __restrict__ block_off, double* __restrict__ a,
                                                     eb_cut_t* __restrict__ cuts, int64_t cap,
                                                     int32_t* __restrict__ err) {
@@ -561,7 +598,7 @@ __global__ void __launch_bounds__(BLOCK) k_diag_rbf(const double* __restrict__ p
     if (n >= nnodes || (*err & DEVERR_DOMAIN)) return;
     if (kind[n] != 2 || !node_has_rbf(kind, psi, n, d, mode)) return;
     const NodePos p = node_pos(n, d);
-    double acc = (double)diag_regular(kind, n, d);
+    double acc = diag_regular_beta(kind, beta, n, d);
     int64_t m = block_off[blockIdx.x] + before;
     for (int side = 0; side < 2 * d.dim; ++side) {
         const int axis = side >> 1;
@@ -569,10 +606,10 @@ __global__ void __launch_bounds__(BLOCK) k_diag_rbf(const double* __restrict__ p
         const int64_t st = axis_stride(d, axis) * step;
         if (kind[n + st] == 2) continue;
         if (rbf_side(psi, n, st, mode)) {
-            acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err);
+            acc = rbf_side_records(psi, n, p, d, side, m, cuts, cap, acc, err, beta);
             m += 2;
         } else {
-            acc = acc + diag_side(psi, n, p, d, side, 2, m, cuts, cap);
+            acc = acc + diag_side(psi, n, p, d, side, 2, m, cuts, cap, beta);
             ++m;
         }
     }
@@ -625,7 +662,8 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, 
 
 // -------------------------------------------------------- operator on fields
 __global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restrict__ kind, const double* __restrict__ a,
-                                                         double sigma, const double* __restrict__ x,
+                                                         const double* __restrict__ beta, double sigma,
+                                                         const double* __restrict__ x,
                                                          double* __restrict__ y, GridDims d, int64_t nnodes) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= nnodes) return;
@@ -640,8 +678,13 @@ __global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restric
     double nb = 0.0;
     for (int axis = 0; axis < d.dim; ++axis) {
         const int64_t st = axis_stride(d, axis);
-        if (kind[n - st] == 2) nb = nb + x[n - st];
-        if (kind[n + st] == 2) nb = nb + x[n + st];
+        if (beta) {
+            if (kind[n - st] == 2) nb = nb + face_beta(beta, n, d, 2 * axis) * x[n - st];
+            if (kind[n + st] == 2) nb = nb + face_beta(beta, n, d, 2 * axis + 1) * x[n + st];
+        } else {
+            if (kind[n - st] == 2) nb = nb + x[n - st];
+            if (kind[n + st] == 2) nb = nb + x[n + st];
+        }
     }
     const double diag = a[n] * d.s + sigma;
     y[n] = diag * x[n] - d.s * nb;
@@ -767,9 +810,9 @@ struct AsmStat {
 
 using namespace eb;
 
-extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int32_t mode, int8_t* kind,
-                                     double* a, eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
-                                     int64_t* n_cuts, void* stream) {
+static int assemble_diag_impl(const eb_grid_t* g, const double* psi, const double* beta, int32_t mode,
+                              int8_t* kind, double* a, eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                              int64_t* n_cuts, void* stream) {
     clear_error();
     GridDims d;
     EB_TRY(make_dims(g, &d));
@@ -814,13 +857,13 @@ extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int3
     hipLaunchKernelGGL(k_count_cuts, dim3(nblk), dim3(BLOCK), 0, s, kind, psi, d, nn, (int)mode, blk_cuts);
     EB_LAUNCH_CHECK();
     EB_TRY(scan_i32_to_i64_dev(blk_cuts, blk_off, nblk, &st->cuts, s));
-    hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, (int)mode, blk_off, a, cuts,
-                       cuts_cap, &st->err, &st->ndefer, defer);
-    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, d, a,
+    hipLaunchKernelGGL(k_diag_cuts, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, beta, d, nn, (int)mode, blk_off, a,
+                       cuts, cuts_cap, &st->err, &st->ndefer, defer);
+    hipLaunchKernelGGL(k_diag_long, dim3(DIAG_LONG_BLOCKS), dim3(DIAG_LONG_NT), 0, s, psi, kind, beta, d, a,
                        cuts, cuts_cap, &st->err, &st->ndefer, defer);
     if (mode != EB_BC_LINE)
-        hipLaunchKernelGGL(k_diag_rbf, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, d, nn, (int)mode, blk_off, a, cuts,
-                           cuts_cap, &st->err);
+        hipLaunchKernelGGL(k_diag_rbf, dim3(nblk), dim3(BLOCK), 0, s, psi, kind, beta, d, nn, (int)mode, blk_off, a,
+                           cuts, cuts_cap, &st->err);
     EB_LAUNCH_CHECK();
     AsmStat h;
     EB_HIP(hipMemcpyAsync(&h, st, sizeof(AsmStat), hipMemcpyDeviceToHost, s));
@@ -847,10 +890,22 @@ extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int3
     return EB_OK;
 }
 
+extern "C" int eb_assemble_diag_mode(const eb_grid_t* g, const double* psi, int32_t mode, int8_t* kind,
+                                     double* a, eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
+                                     int64_t* n_cuts, void* stream) {
+    return assemble_diag_impl(g, psi, nullptr, mode, kind, a, cuts, cuts_cap, n_unknowns, n_cuts, stream);
+}
+
+extern "C" int eb_assemble_diag_beta(const eb_grid_t* g, const double* psi, const double* beta, int32_t mode,
+                                     int8_t* kind, double* a, eb_cut_t* cuts, int64_t cuts_cap,
+                                     int64_t* n_unknowns, int64_t* n_cuts, void* stream) {
+    return assemble_diag_impl(g, psi, beta, mode, kind, a, cuts, cuts_cap, n_unknowns, n_cuts, stream);
+}
+
 extern "C" int eb_assemble_diag(const eb_grid_t* g, const double* psi, int8_t* kind, double* a,
                                 eb_cut_t* cuts, int64_t cuts_cap, int64_t* n_unknowns,
                                 int64_t* n_cuts, void* stream) {
-    return eb_assemble_diag_mode(g, psi, EB_BC_LINE, kind, a, cuts, cuts_cap, n_unknowns, n_cuts, stream);
+    return assemble_diag_impl(g, psi, nullptr, EB_BC_LINE, kind, a, cuts, cuts_cap, n_unknowns, n_cuts, stream);
 }
 
 extern "C" int eb_check_spd(const eb_grid_t* g, const int8_t* kind, const eb_cut_t* cuts, int64_t n_cuts,
@@ -943,8 +998,8 @@ extern "C" int eb_assemble_rhs_islands(const eb_grid_t* g, const int8_t* kind, c
     return EB_OK;
 }
 
-extern "C" int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
-                             const double* x, double* y, void* stream) {
+static int stencil_apply_impl(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta,
+                              double sigma, const double* x, double* y, void* stream) {
     clear_error();
     GridDims d;
     EB_TRY(make_dims(g, &d));
@@ -958,7 +1013,21 @@ extern "C" int stencil_apply(const eb_grid_t* g, const int8_t* kind, const doubl
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_stencil_dense, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, a, sigma, x, y, d, nn);
+    hipLaunchKernelGGL(k_stencil_dense, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, a, beta, sigma, x, y, d, nn);
     EB_LAUNCH_CHECK();
     return EB_OK;
+}
+
+extern "C" int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                             const double* x, double* y, void* stream) {
+    return stencil_apply_impl(g, kind, a, nullptr, sigma, x, y, stream);
+}
+
+extern "C" int stencil_apply_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta,
+                                  double sigma, const double* x, double* y, void* stream) {
+    if (!beta) {
+        set_error("stencil_apply_beta: null beta");
+        return EB_EINVAL;
+    }
+    return stencil_apply_impl(g, kind, a, beta, sigma, x, y, stream);
 }

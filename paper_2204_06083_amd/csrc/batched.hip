@@ -1522,6 +1522,11 @@ static int solve_systems(amg_handle_t* H, int32_t nrhs, int nseg, const int32_t*
         set_error("%s: nrhs = %d outside 1..%d", who, nrhs, BMAX_RHS);
         return EB_EINVAL;
     }
+    if (H->beta_on) {
+        set_error("%s: batched solves are not available with variable conductivity (solve each right-hand side "
+                  "with pcg_solve)", who);
+        return EB_ENOTIMPL;
+    }
     pcg_params_t p;
     p.tol = 1e-8;
     p.maxit = 1000;

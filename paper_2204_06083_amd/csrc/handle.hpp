@@ -119,6 +119,11 @@ struct amg_handle {
     int64_t* fine_nodes = nullptr;  // unknown -> dense node index
     int32_t* unk_off_tmp = nullptr; // setup only: dense node -> unknown index
     const int8_t* kind_tmp = nullptr;  // setup only: the caller's kind field
+    const double* beta_tmp = nullptr;  // setup only: the caller's face conductivities (variable beta)
+    // variable conductivity: beta at the +axis face of every node, padded
+    // layout (fine strip kernels take them; the 2-D tile kernels are off)
+    int beta_on = 0;
+    double* bf_p[3] = {nullptr, nullptr, nullptr};
     int32_t* fine_pad = nullptr;    // unknown -> padded node index
     double* diag_p = nullptr;       // padded diagonal (0 off unknowns)
     double* dinv_p = nullptr;       // padded 1 / diagonal (0 off unknowns): the fine smoother and

@@ -52,6 +52,7 @@ struct FineArgs {
     const double* wf;     // per-point smoother weights omega_k / d_k (learned weights; 0 off unknowns)
     const float* wf32;
     const void* dinv16;   // BF16 1 / diag (BF16 smoother only)
+    const double* bf[3];  // variable beta: beta of the +axis face of each node (padded), else null
 };
 
 // BF16 storage of the fine smoother's operands (precision EB_PREC_BF16): the
@@ -108,6 +109,46 @@ __device__ inline V nbr_sum_scaled(const V* __restrict__ v, const V* __restrict_
     t += safe_div(v[p - f.sy], dg[p - f.sy]) + safe_div(v[p + f.sy], dg[p + f.sy]);
     if (f.dim == 3) t += safe_div(v[p - f.sz], dg[p - f.sz]) + safe_div(v[p + f.sz], dg[p + f.sz]);
     return t;
+}
+
+// Variable conductivity (VB): the same sums with each neighbour weighted by
+// the beta of the face toward it (bf[a][p] is the face between p and p + e_a).
+template <class V>
+__device__ inline V nbr_sum_b(const V* __restrict__ v, int64_t p, const FineArgs& f) {
+    V t = (V)f.bf[0][p - 1] * v[p - 1] + (V)f.bf[0][p] * v[p + 1];
+    t += (V)f.bf[1][p - f.sy] * v[p - f.sy] + (V)f.bf[1][p] * v[p + f.sy];
+    if (f.dim == 3) t += (V)f.bf[2][p - f.sz] * v[p - f.sz] + (V)f.bf[2][p] * v[p + f.sz];
+    return t;
+}
+
+template <class V>
+__device__ inline V nbr_sum_scaled_b(const V* __restrict__ v, const V* __restrict__ dg, int64_t p,
+                                     const FineArgs& f) {
+    V t = (V)f.bf[0][p - 1] * safe_div(v[p - 1], dg[p - 1]) + (V)f.bf[0][p] * safe_div(v[p + 1], dg[p + 1]);
+    t += (V)f.bf[1][p - f.sy] * safe_div(v[p - f.sy], dg[p - f.sy]) + (V)f.bf[1][p] * safe_div(v[p + f.sy], dg[p + f.sy]);
+    if (f.dim == 3)
+        t += (V)f.bf[2][p - f.sz] * safe_div(v[p - f.sz], dg[p - f.sz]) +
+             (V)f.bf[2][p] * safe_div(v[p + f.sz], dg[p + f.sz]);
+    return t;
+}
+
+template <bool VB, class V>
+__device__ inline V nsum(const V* __restrict__ v, int64_t p, const FineArgs& f) {
+    if constexpr (VB) return nbr_sum_b(v, p, f);
+    else return nbr_sum(v, p, f);
+}
+
+template <bool VB, class V>
+__device__ inline V nsum_scaled(const V* __restrict__ v, const V* __restrict__ dg, int64_t p, const FineArgs& f) {
+    if constexpr (VB) return nbr_sum_scaled_b(v, dg, p, f);
+    else return nbr_sum_scaled(v, dg, p, f);
+}
+
+// beta of the face on side (axis, +/-) of node p (1 without VB)
+template <bool VB>
+__device__ inline double fbeta(const FineArgs& f, int axis, int64_t p, int64_t st, bool plus) {
+    if constexpr (VB) return plus ? f.bf[axis][p] : f.bf[axis][p - st];
+    else return 1.0;
 }
 
 // ------------------------------------------------------------ reductions
@@ -199,7 +240,7 @@ __device__ inline bool bad_value(double v) { return isnan(v) || isinf(v); }
 //
 // p_new = z + beta p_old; q = A p_new; partial (p_new, q).
 // rho = (r, z) of the latest V-cycle, beta = rho / rho_prev (0 on the first).
-template <class V>
+template <class V, bool VB = false>
 __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __restrict__ z,
                                                    const double* __restrict__ pold, double* __restrict__ pnew,
                                                    double* __restrict__ q, const double* __restrict__ rz_cur,
@@ -222,13 +263,25 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __res
         const double d = f.diag[p];
         if (d != 0.0) {
             const double pc = to_f64(z[p]) + beta * pold[p];
-            double nb = to_f64(z[p - 1]) + beta * pold[p - 1];
-            nb += to_f64(z[p + 1]) + beta * pold[p + 1];
-            nb += to_f64(z[p - f.sy]) + beta * pold[p - f.sy];
-            nb += to_f64(z[p + f.sy]) + beta * pold[p + f.sy];
-            if (f.dim == 3) {
-                nb += to_f64(z[p - f.sz]) + beta * pold[p - f.sz];
-                nb += to_f64(z[p + f.sz]) + beta * pold[p + f.sz];
+            double nb;
+            if constexpr (VB) {
+                nb = f.bf[0][p - 1] * (to_f64(z[p - 1]) + beta * pold[p - 1]);
+                nb += f.bf[0][p] * (to_f64(z[p + 1]) + beta * pold[p + 1]);
+                nb += f.bf[1][p - f.sy] * (to_f64(z[p - f.sy]) + beta * pold[p - f.sy]);
+                nb += f.bf[1][p] * (to_f64(z[p + f.sy]) + beta * pold[p + f.sy]);
+                if (f.dim == 3) {
+                    nb += f.bf[2][p - f.sz] * (to_f64(z[p - f.sz]) + beta * pold[p - f.sz]);
+                    nb += f.bf[2][p] * (to_f64(z[p + f.sz]) + beta * pold[p + f.sz]);
+                }
+            } else {
+                nb = to_f64(z[p - 1]) + beta * pold[p - 1];
+                nb += to_f64(z[p + 1]) + beta * pold[p + 1];
+                nb += to_f64(z[p - f.sy]) + beta * pold[p - f.sy];
+                nb += to_f64(z[p + f.sy]) + beta * pold[p + f.sy];
+                if (f.dim == 3) {
+                    nb += to_f64(z[p - f.sz]) + beta * pold[p - f.sz];
+                    nb += to_f64(z[p + f.sz]) + beta * pold[p + f.sz];
+                }
             }
             const double qv = d * pc - f.s * nb;
             pnew[p] = pc;
@@ -297,7 +350,7 @@ __device__ inline bool converged_or_failed(const double* __restrict__ part_rr, i
 // With `check`, first test convergence of the iterate that produced r.
 // LW: the smoother uses the per-point weights f.wf (z1 = wf r) instead of
 // omega / d; the prolongator always keeps omega.
-template <class V, bool LW>
+template <class V, bool LW, bool VB = false>
 __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, const double* __restrict__ r,
                                                   V* __restrict__ res, PcgScalars* sc, int check,
                                                   const double* __restrict__ part_rr, int np) {
@@ -314,7 +367,7 @@ __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, cons
                 res[p] = (V)(r[p] - (d * z1 - f.s * nb));
             } else {
                 const double z1 = omega * r[p] / d;
-                const double nb = omega * nbr_sum_scaled(r, f.diag, p, f);
+                const double nb = omega * nsum_scaled<VB>(r, f.diag, p, f);
                 res[p] = (V)(r[p] - (d * z1 - f.s * nb));
             }
         }
@@ -349,7 +402,7 @@ template <> __device__ inline const float* vbw0<float>(const BoxArgs& b) { retur
 // (oz, oy, ox), one thread per aggregate.
 constexpr int R3_BOXES = RNT / 9;   // boxes per block
 
-template <class V>
+template <class V, bool VB = false>
 __device__ inline void restrict_box3(const FineArgs& f, const BoxArgs& b, const V* __restrict__ dg, V omega, V sh,
                                      const V* __restrict__ res, V* __restrict__ rc, const V* __restrict__ dg_c,
                                      double omega_c, V* __restrict__ sv_c) {
@@ -380,7 +433,7 @@ __device__ inline void restrict_box3(const FineArgs& f, const BoxArgs& b, const 
                 const V d = dg[p];
                 if (d != V(0)) {
                     const V rp = res[p];
-                    const V aw = d * (rp / d) - sh * nbr_sum_scaled(res, dg, p, f);
+                    const V aw = d * (rp / d) - sh * nsum_scaled<VB>(res, dg, p, f);
                     u = rp - omega * aw;
                     c = m == 1 ? 0 : b.agg[p] - c0;
                 }
@@ -400,7 +453,7 @@ __device__ inline void restrict_box3(const FineArgs& f, const BoxArgs& b, const 
     }
 }
 
-template <class V, int DIM>
+template <class V, int DIM, bool VB = false>
 __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, double omega_d,
                                                       const V* __restrict__ res, V* __restrict__ rc,
                                                       const V* __restrict__ dg_c, double omega_c,
@@ -412,7 +465,7 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
     if (DIM == 3) {
-        restrict_box3<V>(f, b, dg, omega, sh, res, rc, dg_c, omega_c, sv_c);
+        restrict_box3<V, VB>(f, b, dg, omega, sh, res, rc, dg_c, omega_c, sv_c);
         return;
     }
     const int64_t t = xcd_block() * RNT + threadIdx.x;
@@ -456,8 +509,13 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
                 comp[n] = -1;
                 if (d == V(0)) continue;
                 const V rp = rw[a][c];
-                V nb = safe_div(rw[a][c - 1], dw[a][c - 1]) + safe_div(rw[a][c + 1], dw[a][c + 1]);
-                nb += safe_div(rw[a - 1][c], dw[a - 1][c]) + safe_div(rw[a + 1][c], dw[a + 1][c]);
+                V nb;
+                if constexpr (VB) {
+                    nb = nbr_sum_scaled_b(res, dg, (int64_t)(3 * bx + ox) + f.sy * (3 * by + oy), f);
+                } else {
+                    nb = safe_div(rw[a][c - 1], dw[a][c - 1]) + safe_div(rw[a][c + 1], dw[a][c + 1]);
+                    nb += safe_div(rw[a - 1][c], dw[a - 1][c]) + safe_div(rw[a + 1][c], dw[a + 1][c]);
+                }
                 const V aw = d * (rp / d) - sh * nb;
                 u[n] = rp - omega * aw;
                 comp[n] = m == 1 ? 0 : b.agg[(int64_t)(3 * bx + ox) + f.sy * (3 * by + oy)] - c0;
@@ -479,7 +537,7 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
 //   from r_in and q (r_in and r_out are different buffers).
 // The CG part is FP64; res is stored in the V-cycle precision.
 // The convergence test on ||r_out||^2 happens in the next kernel.
-template <class V, bool LW>
+template <class V, bool LW, bool VB = false>
 __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __restrict__ x, const double* __restrict__ rin,
                                                     double* __restrict__ rout, const double* __restrict__ pv,
                                                     const double* __restrict__ q, V* __restrict__ res,
@@ -521,13 +579,15 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
                 const double z1 = f.wf[p] * rn;
                 res[p] = (V)(rn - (d * z1 - f.s * nb));
             } else {
-                double nb = safe_div(rin[p - 1] - alpha * q[p - 1], f.diag[p - 1]);
-                nb += safe_div(rin[p + 1] - alpha * q[p + 1], f.diag[p + 1]);
-                nb += safe_div(rin[p - f.sy] - alpha * q[p - f.sy], f.diag[p - f.sy]);
-                nb += safe_div(rin[p + f.sy] - alpha * q[p + f.sy], f.diag[p + f.sy]);
+                double nb = fbeta<VB>(f, 0, p, 1, false) * safe_div(rin[p - 1] - alpha * q[p - 1], f.diag[p - 1]);
+                nb += fbeta<VB>(f, 0, p, 1, true) * safe_div(rin[p + 1] - alpha * q[p + 1], f.diag[p + 1]);
+                nb += fbeta<VB>(f, 1, p, f.sy, false) * safe_div(rin[p - f.sy] - alpha * q[p - f.sy], f.diag[p - f.sy]);
+                nb += fbeta<VB>(f, 1, p, f.sy, true) * safe_div(rin[p + f.sy] - alpha * q[p + f.sy], f.diag[p + f.sy]);
                 if (f.dim == 3) {
-                    nb += safe_div(rin[p - f.sz] - alpha * q[p - f.sz], f.diag[p - f.sz]);
-                    nb += safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
+                    nb += fbeta<VB>(f, 2, p, f.sz, false) *
+                          safe_div(rin[p - f.sz] - alpha * q[p - f.sz], f.diag[p - f.sz]);
+                    nb += fbeta<VB>(f, 2, p, f.sz, true) *
+                          safe_div(rin[p + f.sz] - alpha * q[p + f.sz], f.diag[p + f.sz]);
                 }
                 const double z1 = omega * rn / d;
                 res[p] = (V)(rn - (d * z1 - f.s * (omega * nb)));
@@ -546,15 +606,23 @@ __device__ inline V corr_at(const int32_t* __restrict__ agg, const V* __restrict
 
 // Pre-smoothed iterate after prolongation at node p:
 //   zt = omega r / d + t - omega (A t) / d,  t = e_c[agg].
-template <class V, bool LW>
+template <class V, bool LW, bool VB = false>
 __device__ inline V zt_at(const FineArgs& f, V omega, const int32_t* __restrict__ agg, const V* __restrict__ ec,
                           const double* __restrict__ r, int64_t p) {
     const V d = vdiag<V>(f)[p];
     if (d == V(0)) return V(0);
     const V tp = corr_at(agg, ec, p);
-    V nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
-    nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
-    if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
+    V nb;
+    if constexpr (VB) {
+        nb = (V)f.bf[0][p - 1] * corr_at(agg, ec, p - 1) + (V)f.bf[0][p] * corr_at(agg, ec, p + 1);
+        nb += (V)f.bf[1][p - f.sy] * corr_at(agg, ec, p - f.sy) + (V)f.bf[1][p] * corr_at(agg, ec, p + f.sy);
+        if (f.dim == 3)
+            nb += (V)f.bf[2][p - f.sz] * corr_at(agg, ec, p - f.sz) + (V)f.bf[2][p] * corr_at(agg, ec, p + f.sz);
+    } else {
+        nb = corr_at(agg, ec, p - 1) + corr_at(agg, ec, p + 1);
+        nb += corr_at(agg, ec, p - f.sy) + corr_at(agg, ec, p + f.sy);
+        if (f.dim == 3) nb += corr_at(agg, ec, p - f.sz) + corr_at(agg, ec, p + f.sz);
+    }
     const V at = d * tp - (V)f.s * nb;
     const V z1 = LW ? vwf<V>(f)[p] * (V)r[p] : omega * (V)r[p] / d;
     return z1 + (tp - omega * at / d);
@@ -562,21 +630,21 @@ __device__ inline V zt_at(const FineArgs& f, V omega, const int32_t* __restrict_
 
 // Prolongation and pre-smoothed correction: zt = omega r / d + t - omega (A t) / d,
 // t = e_c[agg].
-template <class V, bool LW>
+template <class V, bool LW, bool VB = false>
 __global__ void __launch_bounds__(NT) k_fine_up(FineArgs f, double omega, const int32_t* __restrict__ agg,
                                                 const V* __restrict__ ec, const double* __restrict__ r,
                                                 V* __restrict__ zt, const PcgScalars* sc) {
     if (sc->done) return;
     const V w = (V)omega;
     FINE_LOOP(f, p) {
-        if (f.diag[p] != 0.0) zt[p] = zt_at<V, LW>(f, w, agg, ec, r, p);
+        if (f.diag[p] != 0.0) zt[p] = zt_at<V, LW, VB>(f, w, agg, ec, r, p);
     }
 }
 
 // Post-smoothing: z = zt + omega (r - A zt) / d; partial (r, z) in FP64.
 // B16 (BF16 smoother): scaled by the BF16 1 / d and z stored in BF16 (the
 // partial uses the stored value).
-template <class V, bool LW, bool B16 = false>
+template <class V, bool LW, bool B16 = false, bool VB = false>
 __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, const V* __restrict__ zt,
                                                   const double* __restrict__ r,
                                                   std::conditional_t<B16, bf16, V>* __restrict__ z,
@@ -590,7 +658,7 @@ __global__ void __launch_bounds__(NT, 8) k_fine_post(FineArgs f, double omega, c
     FINE_LOOP(f, p) {
         const V d = dg[p];
         if (d != V(0)) {
-            const V az = d * zt[p] - sh * nbr_sum(zt, p, f);
+            const V az = d * zt[p] - sh * nsum<VB>(zt, p, f);
             if constexpr (B16) {
                 const V zv = zt[p] + w * ((V)r[p] - az) * (V)bf16_to_f32(di16[p]);
                 const bf16 zb = f32_to_bf16((float)zv);
@@ -1037,6 +1105,7 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
 }
 
 // out = b - A x (padded fields), partial ||out||^2.
+template <bool VB = false>
 __global__ void __launch_bounds__(NT) k_fine_resid(FineArgs f, const double* __restrict__ bp,
                                                    const double* __restrict__ x, double* __restrict__ out,
                                                    double* __restrict__ part) {
@@ -1044,7 +1113,7 @@ __global__ void __launch_bounds__(NT) k_fine_resid(FineArgs f, const double* __r
     FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
-            const double ax = d * x[p] - f.s * nbr_sum(x, p, f);
+            const double ax = d * x[p] - f.s * nsum<VB>(x, p, f);
             const double rv = bp[p] - ax;
             out[p] = rv;
             acc += rv * rv;
@@ -1488,6 +1557,14 @@ __global__ void __launch_bounds__(BLOCK) k_fine_layout(const int64_t* __restrict
     if (tile_flag) tile_flag[(row / TY) * tile_ntx + i / TX] = 1;   // 2-D: row is j
 }
 
+// A dense node field copied into the padded layout.
+__global__ void __launch_bounds__(BLOCK) k_pad_field(int64_t nn, GridDims d, int px, const double* __restrict__ src,
+                                                     double* __restrict__ dst) {
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= nn) return;
+    dst[n % d.nx + (int64_t)px * (n / d.nx)] = src[n];
+}
+
 // 2-D level-0 boxes: the aggregate of each of the 9 nodes, relative to the
 // box's first aggregate, 3 bits per node (7: not an unknown or off the grid).
 __global__ void __launch_bounds__(BLOCK) k_box_map2(int nbx, int nby, int nx, int ny, int px,
@@ -1602,6 +1679,7 @@ static FineArgs fine_args(const amg_handle* H) {
     f.wf = H->wf_on ? H->wf : nullptr;
     f.wf32 = H->wf_on ? H->wf32 : nullptr;
     f.dinv16 = H->dinv_p16;
+    for (int a = 0; a < 3; ++a) f.bf[a] = H->beta_on ? H->bf_p[a] : nullptr;
     return f;
 }
 
@@ -1635,7 +1713,9 @@ static TileArgs tile_args(const amg_handle* H) {
 }
 
 // The 2-D fine level of hierarchies with a coarse level runs on tiles.
-static bool use_tiles(const amg_handle* H) { return H->ntiles > 0 && H->d.dim == 2 && H->nlev > 1; }
+static bool use_tiles(const amg_handle* H) {
+    return H->ntiles > 0 && H->d.dim == 2 && H->nlev > 1 && !H->beta_on;
+}
 
 static BoxArgs box_args(const amg_handle* H) {
     BoxArgs b;
@@ -1807,7 +1887,9 @@ static int enqueue_vcycle_one_level(amg_handle* H, const double* r, double* z, d
 // prolongation and post-smoothing; the last kernel writes the (r, z)
 // partials to rz_out.
 // B16: the BF16 smoother (V = float; z is the BF16 copy).
-template <class V, bool LW, bool B16 = false>
+// VB: variable conductivity (strip kernels with face weights; the 2-D tile
+// kernels are not used then).
+template <class V, bool LW, bool B16 = false, bool VB = false>
 static int enqueue_vcycle(amg_handle* H, const double* r, std::conditional_t<B16, bf16, V>* z, double* rz_out,
                           hipStream_t s) {
     PcgScalars* sc = H->sc;
@@ -1830,22 +1912,22 @@ static int enqueue_vcycle(amg_handle* H, const double* r, std::conditional_t<B16
         EB_LAUNCH_CHECK();
         return EB_OK;
     }
-    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_fine_down<V, LW>), G, dim3(NT), 0, f, w0, r, fb.res, sc, 0, H->red.rr,
-                    np);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_DOWN, s, (k_fine_down<V, LW, VB>), G, dim3(NT), 0, f, w0, r, fb.res, sc, 0,
+                    H->red.rr, np);
     if (H->d.dim == 2)
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2, VB>), dim3(xcd_grid(H->nboxes0, RNT)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     else
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(restrict_grid(H)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3, VB>), dim3(restrict_grid(H)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 0, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r, fb.zt,
-                    (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16>), G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW, VB>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, r,
+                    fb.zt, (const PcgScalars*)sc);
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16, VB>), G, dim3(NT), 0, f, w0, fb.zt, r, z, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -1854,7 +1936,7 @@ static int enqueue_vcycle(amg_handle* H, const double* r, std::conditional_t<B16
 // Iteration k >= 1 of a run.  The V-cycle before it (number k-1) wrote
 // rz[(k-1) % 2] from r[(k-1) % 2]; this iteration reads r[(k-1) % 2], writes
 // r[k % 2] and its V-cycle writes rz[k % 2].
-template <class V, bool LW, bool B16 = false>
+template <class V, bool LW, bool B16 = false, bool VB = false>
 static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
@@ -1890,24 +1972,24 @@ static int enqueue_iteration(amg_handle* H, int k, hipStream_t s) {
         EB_LAUNCH_CHECK();
         return EB_OK;
     }
-    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<ZT>, G, dim3(NT), 0, f, (const ZT*)zb, pold, pnew, H->q, rz_cur,
-                    rz_prev, np, H->red.pq, sc);
-    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
+    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, (k_pcg_p_spmv<ZT, VB>), G, dim3(NT), 0, f, (const ZT*)zb, pold, pnew, H->q,
+                    rz_cur, rz_prev, np, H->red.pq, sc);
+    EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, (k_pcg_xr_down<V, LW, VB>), G, dim3(NT), 0, f, H->x, rin, rout, pnew, H->q, fb.res,
                     w0, rz_cur, H->red.pq, np, H->red.rr, sc);
     if (H->d.dim == 2)
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2>), dim3(xcd_grid(H->nboxes0, RNT)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 2, VB>), dim3(xcd_grid(H->nboxes0, RNT)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     else
-        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3>), dim3(restrict_grid(H)),
+        EB_TIMED_LAUNCH(H, EB_K_FINE_RESTRICT, s, (k_fine_restrict<V, 3, VB>), dim3(restrict_grid(H)),
                         dim3(RNT), 0, f, box_args(H), w0, fb.res, L1.rv, (const V*)L1.diag,
                         H->lev[1].omega, H->nlev > 2 ? L1.sv : nullptr, sc, 1, H->red.rr, np);
     EB_TRY(enqueue_coarse<V>(H, s));
     unsigned gu = 0;
     const FineArgs fu = fine_args_full(H, &gu);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_UP, s, (k_fine_up<V, LW, VB>), dim3(gu), dim3(NT), 0, fu, w0, H->agg_p, L1.ev, rout,
                     fb.zt, (const PcgScalars*)sc);
-    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16>), G, dim3(NT), 0, f, w0, fb.zt, rout, zb, rz_out,
+    EB_TIMED_LAUNCH(H, EB_K_FINE_POST, s, (k_fine_post<V, LW, B16, VB>), G, dim3(NT), 0, f, w0, fb.zt, rout, zb, rz_out,
                     (const PcgScalars*)sc);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -1926,8 +2008,12 @@ static int enqueue_iteration_one_level(amg_handle* H, int k, hipStream_t s) {
     const double* rz_prev = k >= 2 ? H->red.rz[k & 1] : nullptr;
     double* rz_out = H->red.rz[k & 1];
     PcgScalars* sc = H->sc;
-    EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<double>, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur,
-                    rz_prev, np, H->red.pq, sc);
+    if (H->beta_on)
+        EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, (k_pcg_p_spmv<double, true>), G, dim3(NT), 0, f, H->z, pold, pnew, H->q,
+                        rz_cur, rz_prev, np, H->red.pq, sc);
+    else
+        EB_TIMED_LAUNCH(H, EB_K_PCG_SPMV, s, k_pcg_p_spmv<double>, G, dim3(NT), 0, f, H->z, pold, pnew, H->q, rz_cur,
+                        rz_prev, np, H->red.pq, sc);
     EB_TIMED_LAUNCH(H, EB_K_PCG_XR, s, k_pcg_xr, G, dim3(NT), 0, f, H->x, rin, pnew, H->q, rz_cur, H->red.pq, np,
                     H->red.rr, sc);
     // k_pcg_xr updates r in place: keep both buffers equal
@@ -1938,17 +2024,32 @@ static int enqueue_iteration_one_level(amg_handle* H, int k, hipStream_t s) {
 
 // V-cycle / iteration with or without the per-point smoother weights.
 // (the BF16 smoother takes no per-point weights: refused before this point)
+// (variable conductivity likewise: refused with per-point weights or BF16)
 template <class V, bool B16 = false>
 static int enqueue_vcycle_any(amg_handle* H, const double* r, std::conditional_t<B16, bf16, V>* z, double* rz_out,
                               hipStream_t s) {
     if constexpr (B16) return enqueue_vcycle<V, false, true>(H, r, z, rz_out, s);
-    else return H->wf_on ? enqueue_vcycle<V, true>(H, r, z, rz_out, s) : enqueue_vcycle<V, false>(H, r, z, rz_out, s);
+    else {
+        if (H->beta_on) return enqueue_vcycle<V, false, false, true>(H, r, z, rz_out, s);
+        return H->wf_on ? enqueue_vcycle<V, true>(H, r, z, rz_out, s) : enqueue_vcycle<V, false>(H, r, z, rz_out, s);
+    }
 }
 
 template <class V, bool B16 = false>
 static int enqueue_iteration_any(amg_handle* H, int k, hipStream_t s) {
     if constexpr (B16) return enqueue_iteration<V, false, true>(H, k, s);
-    else return H->wf_on ? enqueue_iteration<V, true>(H, k, s) : enqueue_iteration<V, false>(H, k, s);
+    else {
+        if (H->beta_on) return enqueue_iteration<V, false, false, true>(H, k, s);
+        return H->wf_on ? enqueue_iteration<V, true>(H, k, s) : enqueue_iteration<V, false>(H, k, s);
+    }
+}
+
+// True residual out = b - A x with its partials.
+static void launch_resid(amg_handle* H, const FineArgs& f, unsigned np, double* out, double* part, hipStream_t s) {
+    if (H->beta_on)
+        hipLaunchKernelGGL(k_fine_resid<true>, dim3(np), dim3(NT), 0, s, f, H->bvec, H->x, out, part);
+    else
+        hipLaunchKernelGGL(k_fine_resid<false>, dim3(np), dim3(NT), 0, s, f, H->bvec, H->x, out, part);
 }
 
 // Steady-state iterations as a HIP graph.  From iteration 3 on, iterations
@@ -2085,7 +2186,7 @@ static int enqueue_init(amg_handle* H, double tol, int iters, hipStream_t s) {
     const int np = H->red.nparts;
     const dim3 G((unsigned)np);
     hipLaunchKernelGGL(k_fine_norm2, G, dim3(NT), 0, s, f, H->bvec, H->red.aux);
-    hipLaunchKernelGGL(k_fine_resid, G, dim3(NT), 0, s, f, H->bvec, H->x, H->rr[0], H->red.rr);
+    launch_resid(H, f, (unsigned)np, H->rr[0], H->red.rr, s);
     hipLaunchKernelGGL(k_finalize_init, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, H->red.rr, np, tol, iters);
     EB_LAUNCH_CHECK();
     return EB_OK;
@@ -2111,7 +2212,7 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
     // 2-D: tiles of the tile kernels (their origins are multiples of 3, so
     // a tile holds whole level-0 boxes)
     // (the tile kernels address padded fields by 32-bit byte offsets)
-    const bool tiled = d.dim == 2 && H->nlev > 1 && npad < ((int64_t)1 << 29);
+    const bool tiled = d.dim == 2 && H->nlev > 1 && npad < ((int64_t)1 << 29) && !H->beta_on;
     H->tile_ntx = tiled ? (d.nx + TX - 1) / TX : 0;
     const int64_t ntile_all = tiled ? (int64_t)H->tile_ntx * ((d.ny + TY - 1) / TY) : 0;
     int32_t* tflag = nullptr;
@@ -2141,6 +2242,19 @@ int solve_layout_alloc(amg_handle* H, hipStream_t s) {
         const FillSpec ft[] = {{H->dinv_p, sizeof(double) * npad, 0u},
                                {tflag, sizeof(int32_t) * ntile_all, 0u}};
         EB_TRY(fill_words(ft, tiled ? 2 : 1, s));
+    }
+    if (H->beta_on) {
+        // the caller's face conductivities in the padded layout (every node,
+        // so that the faces toward non-unknown neighbours are finite)
+        const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
+        for (int a = 0; a < d.dim; ++a) {
+            EB_TRY(dalloc_n(&H->bf_p[a], npad, s));
+            const FillSpec fb[] = {{H->bf_p[a], sizeof(double) * npad, 0u}};
+            EB_TRY(fill_words(fb, 1, s));
+            hipLaunchKernelGGL(k_pad_field, dim3(grid_for(nn)), dim3(BLOCK), 0, s, nn, d, H->px,
+                               H->beta_tmp + (int64_t)a * nn, H->bf_p[a]);
+        }
+        EB_LAUNCH_CHECK();
     }
     Level& L0 = H->lev[0];
     hipLaunchKernelGGL(k_fine_layout, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, H->fine_nodes, nunk, d, H->px, L0.diag,
@@ -2428,6 +2542,10 @@ static int lg_check(amg_handle* H, const char* name) {
         set_error("%s: the hierarchy has a single level (no fine smoother)", name);
         return EB_EINVAL;
     }
+    if (H->beta_on) {
+        set_error("%s: the learned smoother is not available with variable conductivity", name);
+        return EB_ENOTIMPL;
+    }
     return EB_OK;
 }
 
@@ -2441,6 +2559,10 @@ extern "C" int amg_set_fine_weights(amg_handle_t* H, const double* omega, void* 
     if (!H || !omega) {
         set_error("amg_set_fine_weights: null pointer");
         return EB_EINVAL;
+    }
+    if (H->beta_on) {
+        set_error("amg_set_fine_weights: per-point weights are not available with variable conductivity");
+        return EB_ENOTIMPL;
     }
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
     H->last_stream = s;
@@ -2623,6 +2745,10 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         set_error("pcg_solve: the BF16 smoother takes no per-point smoother weights");
         return EB_ENOTIMPL;
     }
+    if (H->beta_on && p.precision == EB_PREC_BF16) {
+        set_error("pcg_solve: the BF16 smoother is not available with variable conductivity");
+        return EB_ENOTIMPL;
+    }
     memset(res, 0, sizeof(*res));
     res->levels = H->nlev;
     hipStream_t s = stream ? (hipStream_t)stream : H->stream;
@@ -2702,8 +2828,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
             if (expect_end) {
                 // true residual ||b - A x|| behind the chunk (recomputed below if
                 // the chunk turns out not to finish)
-                hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res,
-                                   H->red.aux);
+                launch_resid(H, f, (unsigned)np, H->res, H->red.aux, s);
                 hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
                 EB_LAUNCH_CHECK();
             }
@@ -2734,8 +2859,7 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
         }
         if (!true_done) {
             // true residual ||b - A x||
-            hipLaunchKernelGGL(k_fine_resid, dim3((unsigned)np), dim3(NT), 0, s, f, H->bvec, H->x, H->res,
-                               H->red.aux);
+            launch_resid(H, f, (unsigned)np, H->res, H->red.aux, s);
             hipLaunchKernelGGL(k_finalize_true, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, np);
             EB_LAUNCH_CHECK();
             EB_TRY(poll_scalars(H, s));
@@ -2799,6 +2923,10 @@ static int vcycle_apply(amg_handle_t* H, const double* r, double* z, int precisi
     }
     if (precision == EB_PREC_BF16 && H->wf_on) {
         set_error("%s: the BF16 smoother takes no per-point smoother weights", name);
+        return EB_ENOTIMPL;
+    }
+    if (H->beta_on && precision == EB_PREC_BF16) {
+        set_error("%s: the BF16 smoother is not available with variable conductivity", name);
         return EB_ENOTIMPL;
     }
     const bool b16 = precision == EB_PREC_BF16 && H->nlev > 1;

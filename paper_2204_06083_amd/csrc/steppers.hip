@@ -12,10 +12,19 @@
 
 namespace eb {
 
+// Weight of the neighbour on side (axis, minus/plus) of node n: beta of the
+// face between them with a variable conductivity (cond: dim face fields
+// back to back, field `axis` at the face toward +axis), 1 without.
+__device__ inline double side_weight(const double* __restrict__ cond, int64_t n, int64_t nn, int axis, int64_t st,
+                                     bool plus) {
+    return cond ? cond[(int64_t)axis * nn + (plus ? n : n - st)] : 1.0;
+}
+
 // out = scale (2 un - unm1 - dt^2 A v), v = (1 - 2 theta) un + theta unm1,
 // at computational points; 0 elsewhere.
 __global__ void __launch_bounds__(BLOCK) k_wave_rhs(const int8_t* __restrict__ kind, const double* __restrict__ a,
-                                                    GridDims d, int64_t nnodes, double theta, double dt2,
+                                                    const double* __restrict__ cond, GridDims d, int64_t nnodes,
+                                                    double theta, double dt2,
                                                     double scale, const double* __restrict__ un,
                                                     const double* __restrict__ unm1, double* __restrict__ out) {
     const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -30,8 +39,13 @@ __global__ void __launch_bounds__(BLOCK) k_wave_rhs(const int8_t* __restrict__ k
     double nb = 0.0;
     for (int axis = 0; axis < d.dim; ++axis) {
         const int64_t st = axis_stride(d, axis);
-        if (kind[n - st] == 2) nb = nb + v(n - st);
-        if (kind[n + st] == 2) nb = nb + v(n + st);
+        if (cond) {
+            if (kind[n - st] == 2) nb = nb + side_weight(cond, n, nnodes, axis, st, false) * v(n - st);
+            if (kind[n + st] == 2) nb = nb + side_weight(cond, n, nnodes, axis, st, true) * v(n + st);
+        } else {
+            if (kind[n - st] == 2) nb = nb + v(n - st);
+            if (kind[n + st] == 2) nb = nb + v(n + st);
+        }
     }
     const double av = (a[n] * d.s) * v(n) - d.s * nb;
     out[n] = scale * ((2.0 * un[n] - unm1[n]) - dt2 * av);
@@ -40,7 +54,9 @@ __global__ void __launch_bounds__(BLOCK) k_wave_rhs(const int8_t* __restrict__ k
 // out = alpha ((A + sigma I) x) + beta y + gamma z at computational points; 0
 // elsewhere (y or z may be null when their coefficient is 0).
 __global__ void __launch_bounds__(BLOCK) k_stencil_combine(const int8_t* __restrict__ kind,
-                                                           const double* __restrict__ a, GridDims d, int64_t nnodes,
+                                                           const double* __restrict__ a,
+                                                           const double* __restrict__ cond, GridDims d,
+                                                           int64_t nnodes,
                                                            double sigma, double alpha, const double* __restrict__ x,
                                                            double beta, const double* __restrict__ y, double gamma,
                                                            const double* __restrict__ z, double* __restrict__ out) {
@@ -54,8 +70,13 @@ __global__ void __launch_bounds__(BLOCK) k_stencil_combine(const int8_t* __restr
     double nb = 0.0;
     for (int axis = 0; axis < d.dim; ++axis) {
         const int64_t st = axis_stride(d, axis);
-        if (kind[n - st] == 2) nb = nb + x[n - st];
-        if (kind[n + st] == 2) nb = nb + x[n + st];
+        if (cond) {
+            if (kind[n - st] == 2) nb = nb + side_weight(cond, n, nnodes, axis, st, false) * x[n - st];
+            if (kind[n + st] == 2) nb = nb + side_weight(cond, n, nnodes, axis, st, true) * x[n + st];
+        } else {
+            if (kind[n - st] == 2) nb = nb + x[n - st];
+            if (kind[n + st] == 2) nb = nb + x[n + st];
+        }
     }
     const double ax = (a[n] * d.s + sigma) * x[n] - d.s * nb;
     double r = alpha * ax;
@@ -243,8 +264,8 @@ extern "C" int eb_segment_dots_noalloc(const double* w, const double* x, int32_t
                             part + nout * nchunk, out, (hipStream_t)stream);
 }
 
-extern "C" int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double theta, double dt,
-                           double scale, const double* un, const double* unm1, double* out, void* stream) {
+static int wave_rhs_impl(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond, double theta,
+                         double dt, double scale, const double* un, const double* unm1, double* out, void* stream) {
     clear_error();
     GridDims d;
     EB_TRY(make_dims(g, &d));
@@ -257,15 +278,30 @@ extern "C" int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double*
         return EB_EINVAL;
     }
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_wave_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, (hipStream_t)stream, kind, a, d, nn, theta,
-                       dt * dt, scale, un, unm1, out);
+    hipLaunchKernelGGL(k_wave_rhs, dim3(grid_for(nn)), dim3(BLOCK), 0, (hipStream_t)stream, kind, a, cond, d, nn,
+                       theta, dt * dt, scale, un, unm1, out);
     EB_LAUNCH_CHECK();
     return EB_OK;
 }
 
-extern "C" int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
-                                  double alpha, const double* x, double beta, const double* y, double gamma,
-                                  const double* z, double* out, void* stream) {
+extern "C" int eb_wave_rhs(const eb_grid_t* g, const int8_t* kind, const double* a, double theta, double dt,
+                           double scale, const double* un, const double* unm1, double* out, void* stream) {
+    return wave_rhs_impl(g, kind, a, nullptr, theta, dt, scale, un, unm1, out, stream);
+}
+
+extern "C" int eb_wave_rhs_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond,
+                                double theta, double dt, double scale, const double* un, const double* unm1,
+                                double* out, void* stream) {
+    if (!cond) {
+        set_error("eb_wave_rhs_beta: null conductivity");
+        return EB_EINVAL;
+    }
+    return wave_rhs_impl(g, kind, a, cond, theta, dt, scale, un, unm1, out, stream);
+}
+
+static int combine_impl(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond, double sigma,
+                        double alpha, const double* x, double beta, const double* y, double gamma, const double* z,
+                        double* out, void* stream) {
     clear_error();
     GridDims d;
     EB_TRY(make_dims(g, &d));
@@ -274,8 +310,24 @@ extern "C" int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const 
         return EB_EINVAL;
     }
     const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_stencil_combine, dim3(grid_for(nn)), dim3(BLOCK), 0, (hipStream_t)stream, kind, a, d, nn,
-                       sigma, alpha, x, beta, beta != 0.0 ? y : nullptr, gamma, gamma != 0.0 ? z : nullptr, out);
+    hipLaunchKernelGGL(k_stencil_combine, dim3(grid_for(nn)), dim3(BLOCK), 0, (hipStream_t)stream, kind, a, cond, d,
+                       nn, sigma, alpha, x, beta, beta != 0.0 ? y : nullptr, gamma, gamma != 0.0 ? z : nullptr, out);
     EB_LAUNCH_CHECK();
     return EB_OK;
+}
+
+extern "C" int eb_stencil_combine(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                                  double alpha, const double* x, double beta, const double* y, double gamma,
+                                  const double* z, double* out, void* stream) {
+    return combine_impl(g, kind, a, nullptr, sigma, alpha, x, beta, y, gamma, z, out, stream);
+}
+
+extern "C" int eb_stencil_combine_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* cond,
+                                       double sigma, double alpha, const double* x, double beta, const double* y,
+                                       double gamma, const double* z, double* out, void* stream) {
+    if (!cond) {
+        set_error("eb_stencil_combine_beta: null conductivity");
+        return EB_EINVAL;
+    }
+    return combine_impl(g, kind, a, cond, sigma, alpha, x, beta, y, gamma, z, out, stream);
 }

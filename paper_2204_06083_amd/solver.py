@@ -38,6 +38,7 @@ class Assembly:
     cuts: torch.Tensor          # uint8 [cap*56] device buffer of eb_cut_t records
     n_unknowns: int
     n_cuts: int
+    beta: Optional[torch.Tensor] = None   # face conductivities (variable beta), else None
 
     def cuts_host(self) -> np.ndarray:
         raw = self.cuts[: self.n_cuts * 56].cpu().numpy()
@@ -52,9 +53,11 @@ class Assembly:
         return tuple(rec[:, 4 + p].contiguous() for p in range(self.grid.dim))
 
 
-def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None, mode: str = "line") -> Assembly:
+def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None, mode: str = "line",
+                  beta: Optional[torch.Tensor] = None) -> Assembly:
     """Classify nodes and build a_k and the cut records (eb_assemble_diag_mode;
-    mode "line", "mixed" or "rbf")."""
+    mode "line", "mixed" or "rbf"; with beta, the face conductivities of shape
+    (dim, *grid.shape), eb_assemble_diag_beta)."""
     lib = L.lib()
     if mode not in L.BC_MODES:
         raise ValueError(f"unknown boundary mode {mode!r}")
@@ -63,20 +66,29 @@ def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None, mode:
     shape = grid.shape
     dev = psi.device
     psi_p = _field(psi, shape, torch.float64, "psi")
+    beta_p = None
+    if beta is not None:
+        beta = beta.contiguous()
+        beta_p = _field(beta, (grid.dim,) + tuple(shape), torch.float64, "beta")
     kind = torch.empty(shape, dtype=torch.int8, device=dev)
     a = torch.empty(shape, dtype=torch.float64, device=dev)
     nu, nc = C.c_int64(0), C.c_int64(0)
+
+    def call(cuts_ptr, cap):
+        if beta_p is not None:
+            return lib.eb_assemble_diag_beta(C.byref(g), psi_p, beta_p, m, C.c_void_p(kind.data_ptr()),
+                                             C.c_void_p(a.data_ptr()), cuts_ptr, cap, C.byref(nu), C.byref(nc),
+                                             _stream())
+        return lib.eb_assemble_diag_mode(C.byref(g), psi_p, m, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
+                                         cuts_ptr, cap, C.byref(nu), C.byref(nc), _stream())
+
     if cuts_cap is None:
         # counts first (capacity 0 reports the required size), then the records
-        rc = lib.eb_assemble_diag_mode(C.byref(g), psi_p, m, C.c_void_p(kind.data_ptr()),
-                                       C.c_void_p(a.data_ptr()), None, 0, C.byref(nu), C.byref(nc), _stream())
-        L.check(rc, "eb_assemble_diag", ok=(L.EB_OK, L.EB_ENOSPC))
+        L.check(call(None, 0), "eb_assemble_diag", ok=(L.EB_OK, L.EB_ENOSPC))
         cuts_cap = nc.value
     cuts = torch.empty(max(cuts_cap, 1) * 56, dtype=torch.uint8, device=dev)
-    rc = lib.eb_assemble_diag_mode(C.byref(g), psi_p, m, C.c_void_p(kind.data_ptr()), C.c_void_p(a.data_ptr()),
-                                   C.c_void_p(cuts.data_ptr()), int(cuts_cap), C.byref(nu), C.byref(nc), _stream())
-    L.check(rc, "eb_assemble_diag")
-    return Assembly(grid, kind, a, cuts, nu.value, nc.value)
+    L.check(call(C.c_void_p(cuts.data_ptr()), int(cuts_cap)), "eb_assemble_diag")
+    return Assembly(grid, kind, a, cuts, nu.value, nc.value, beta)
 
 
 def check_spd(asm: Assembly, cuts: Optional[torch.Tensor] = None) -> tuple:
@@ -133,14 +145,18 @@ def assemble_rhs_islands(asm: Assembly, canvas: "IslandCanvas", f: torch.Tensor,
 
 
 def stencil_apply(grid, kind: torch.Tensor, a: torch.Tensor, sigma: float, x: torch.Tensor,
-                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                  out: Optional[torch.Tensor] = None, beta: Optional[torch.Tensor] = None) -> torch.Tensor:
     lib = L.lib()
     g = L.make_grid(grid)
     shape = grid.shape
     y = out if out is not None else torch.empty(shape, dtype=torch.float64, device=x.device)
-    rc = lib.stencil_apply(C.byref(g), _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a"),
-                           float(sigma), _field(x, shape, torch.float64, "x"), _field(y, shape, torch.float64, "y"),
-                           _stream())
+    kp, ap = _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a")
+    xp, yp = _field(x, shape, torch.float64, "x"), _field(y, shape, torch.float64, "y")
+    if beta is not None:
+        bp = _field(beta, (grid.dim,) + tuple(shape), torch.float64, "beta")
+        rc = lib.stencil_apply_beta(C.byref(g), kp, ap, bp, float(sigma), xp, yp, _stream())
+    else:
+        rc = lib.stencil_apply(C.byref(g), kp, ap, float(sigma), xp, yp, _stream())
     L.check(rc, "stencil_apply")
     return y
 
@@ -151,10 +167,15 @@ def wave_rhs(asm: "Assembly", theta: float, dt: float, scale: float, un: torch.T
     shape = asm.grid.shape
     g = L.make_grid(asm.grid)
     y = out if out is not None else torch.empty(shape, dtype=torch.float64, device=un.device)
-    rc = L.lib().eb_wave_rhs(C.byref(g), _field(asm.kind, shape, torch.int8, "kind"),
-                             _field(asm.a, shape, torch.float64, "a"), float(theta), float(dt), float(scale),
-                             _field(un, shape, torch.float64, "un"), _field(unm1, shape, torch.float64, "unm1"),
-                             _field(y, shape, torch.float64, "out"), _stream())
+    kp, ap = _field(asm.kind, shape, torch.int8, "kind"), _field(asm.a, shape, torch.float64, "a")
+    up, ump = _field(un, shape, torch.float64, "un"), _field(unm1, shape, torch.float64, "unm1")
+    yp = _field(y, shape, torch.float64, "out")
+    if asm.beta is not None:
+        bp = _field(asm.beta, (asm.grid.dim,) + tuple(shape), torch.float64, "beta")
+        rc = L.lib().eb_wave_rhs_beta(C.byref(g), kp, ap, bp, float(theta), float(dt), float(scale), up, ump, yp,
+                                      _stream())
+    else:
+        rc = L.lib().eb_wave_rhs(C.byref(g), kp, ap, float(theta), float(dt), float(scale), up, ump, yp, _stream())
     L.check(rc, "eb_wave_rhs")
     return y
 
@@ -168,10 +189,15 @@ def stencil_combine(asm: "Assembly", sigma: float, alpha: float, x: torch.Tensor
     o = out if out is not None else torch.empty(shape, dtype=torch.float64, device=x.device)
     yp = _field(y, shape, torch.float64, "y") if y is not None else None
     zp = _field(z, shape, torch.float64, "z") if z is not None else None
-    rc = L.lib().eb_stencil_combine(C.byref(g), _field(asm.kind, shape, torch.int8, "kind"),
-                                    _field(asm.a, shape, torch.float64, "a"), float(sigma), float(alpha),
-                                    _field(x, shape, torch.float64, "x"), float(beta), yp, float(gamma), zp,
-                                    _field(o, shape, torch.float64, "out"), _stream())
+    kp, ap = _field(asm.kind, shape, torch.int8, "kind"), _field(asm.a, shape, torch.float64, "a")
+    xp, op = _field(x, shape, torch.float64, "x"), _field(o, shape, torch.float64, "out")
+    if asm.beta is not None:
+        cp = _field(asm.beta, (asm.grid.dim,) + tuple(shape), torch.float64, "beta")
+        rc = L.lib().eb_stencil_combine_beta(C.byref(g), kp, ap, cp, float(sigma), float(alpha), xp, float(beta), yp,
+                                             float(gamma), zp, op, _stream())
+    else:
+        rc = L.lib().eb_stencil_combine(C.byref(g), kp, ap, float(sigma), float(alpha), xp, float(beta), yp,
+                                        float(gamma), zp, op, _stream())
     L.check(rc, "eb_stencil_combine")
     return o
 
@@ -235,7 +261,8 @@ def wave_theta(asm: "Assembly", u0: torch.Tensor, u1: torch.Tensor, dt: float, t
 
 def heat_cn(asm: "Assembly", H: "Hierarchy", u0: torch.Tensor, dt: float, nsteps: int, rhs_of_step,
             tol: float = 1e-10, precision: str = "fp64"):
-    """Crank-Nicolson for u_t = Lap u + f (Sec. 3.4), beta = 1:
+    """Crank-Nicolson for u_t = div(beta grad u) + f (Sec. 3.4; beta from the
+    assembly, 1 if it has none):
     (A + (2/dt) I) u^{n+1} = ((2/dt) I - A) u^n + b^n + b^{n+1}, with
     b^n = rhs_of_step(n) (assemble_rhs of the source and Dirichlet data at t_n)
     and H set up with sigma = 2/dt.  PCG warm-started from u^n.
@@ -277,9 +304,11 @@ class Hierarchy:
 
     def __init__(self, grid, kind: torch.Tensor, a: torch.Tensor, sigma: float = 0.0, coarse_max: int = 256,
                  max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 1200,
-                 allocator: Optional[str] = None):
+                 allocator: Optional[str] = None, beta: Optional[torch.Tensor] = None):
         """allocator: None (the library's own cache) or "torch": every device
-        block of the handle comes from torch's caching allocator."""
+        block of the handle comes from torch's caching allocator.  beta: face
+        conductivities (dim, *grid.shape) of a variable-coefficient assembly
+        (amg_setup_beta)."""
         lib = L.lib()
         self.grid = grid
         self.sigma = float(sigma)
@@ -306,8 +335,14 @@ class Hierarchy:
         self._params = p
         h = C.c_void_p()
         shape = grid.shape
-        rc = lib.amg_setup(C.byref(g), _field(kind, shape, torch.int8, "kind"), _field(a, shape, torch.float64, "a"),
-                           self.sigma, C.byref(p), C.byref(h), _stream())
+        if beta is not None:
+            bp = _field(beta, (grid.dim,) + tuple(shape), torch.float64, "beta")
+            rc = lib.amg_setup_beta(C.byref(g), _field(kind, shape, torch.int8, "kind"),
+                                    _field(a, shape, torch.float64, "a"), bp, self.sigma, C.byref(p), C.byref(h),
+                                    _stream())
+        else:
+            rc = lib.amg_setup(C.byref(g), _field(kind, shape, torch.int8, "kind"),
+                               _field(a, shape, torch.float64, "a"), self.sigma, C.byref(p), C.byref(h), _stream())
         L.check(rc, "amg_setup")
         self.handle = h
         self._keep = (kind, a)

@@ -27,7 +27,11 @@ one launch sequence; timed from assembly to solution) and geometry by
 geometry.  `qoi` runs the two shape-parameter studies of Sec. 3.6 (61
 fixed-area ellipses at 1024^2, 64 rotated ellipses on the 501^2 grid), each
 as one island batch from level sets to quantities of interest.
-`cpu_baseline` times the CPU oracle on full steps of the same workload.
+`disk_latency` reports the latency of the 128^2 disk problem (FP64 to 1e-10).
+`learned_3d` carries the whole-solve byte model's roofline fraction of the
+plain 3-D solves.  `cpu_baseline` times the CPU oracle on full steps of the
+same workload (BLAS on one thread and on every usable core), and the heat and
+island batches over a process pool (it runs before the GPU is first used).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel NAME]
        python bench.py --copy-calib    (plain copy kernel for counter scaling)
@@ -273,8 +277,14 @@ def learned_ellipsoid(n=256, n_train=96, steps=120, reps=3):
            "training": {"grid": f"{n_train}^3", "steps": steps, "seconds": train_s,
                         "loss_first": hist[0], "loss_last5_mean": sum(hist[-5:]) / 5,
                         "level_weight_multipliers": {str(k): v for k, v in gl.items()}}}
+    sm, wset = survey_model_bytes(H), working_set_bytes(H, 3)
     for prec in ("fp64", "fp32"):
-        out[f"plain_{prec}"] = timed(H, b, prec)
+        r = timed(H, b, prec)
+        gbs = sm * r["iterations"] / (r["solve_ms"] * 1e-3) / 1e9
+        r["solve_roofline"] = {"bound": "hbm", "model": "survey", "bytes_per_iter": sm, "achieved": gbs,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                               "mall_resident": wset < MALL_BYTES, "working_set_bytes": wset}
+        out[f"plain_{prec}"] = r
     la = S.LearnedSmoother(H, asm, psi, params=params)
     la.g = dict(gl)
     la.apply()
@@ -478,9 +488,66 @@ def qoi_studies(reps=2):
     return out
 
 
+def disk_latency(n=128, warm=3, reps=10):
+    """The 128^2 disk (Poisson, FP64 AMG-PCG to 1e-10): a latency case (about
+    8k unknowns, never bandwidth-bound).  Median of `reps` whole steps
+    (assembly, RHS, setup, solve, free) and of `reps` solves on one
+    hierarchy (HIP events around the solve), after `warm` of each."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+    p = W.disk_poisson(n)
+    psi = torch.as_tensor(p.psi, device=dev)
+    f = torch.as_tensor(p.f, device=dev)
+
+    def step(keep=False):
+        asm = S.assemble_diag(p.grid, psi)
+        b = S.assemble_rhs(asm, f, torch.as_tensor(p.u_dirichlet(*asm.cut_coordinates()), device=dev))
+        H = S.Hierarchy(p.grid, asm.kind, asm.a, 0.0)
+        x, info = H.solve(b, tol=p.tol)
+        if keep:
+            return asm, b, H, x, info
+        H.free()
+        return asm.n_unknowns, info
+
+    for _ in range(warm):
+        step()
+    torch.cuda.synchronize()
+    wall = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        n0, info = step()
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e3)
+    asm, b, H, x, info = step(keep=True)
+    X, Y = p.grid.mesh()
+    exact = torch.as_tensor(p.u_exact(X, Y), device=dev)
+    inside = asm.kind.reshape(x.shape) == 2
+    err = (x - exact).abs()[inside].max().item()
+    for _ in range(warm):
+        H.solve(b, tol=p.tol)
+    solve = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, i = H.solve(b, tol=p.tol)
+        solve.append((i["solve_ms"], (time.perf_counter() - t0) * 1e3))
+    levels = H.n_levels
+    H.free()
+    med = lambda v: sorted(v)[len(v) // 2]
+    return {"workload": f"disk2d_{n}_poisson_fp64_amg_pcg_tol1e-10", "n_unknowns": n0, "levels": levels,
+            "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+            "max_error_vs_exact": err,
+            "step_latency_ms_median": med(wall), "step_latency_ms_min": min(wall),
+            "solve_latency_ms_median": med([s[0] for s in solve]),
+            "solve_host_latency_ms_median": med([s[1] for s in solve]),
+            "timing": f"median of {reps} after {warm} warm-up; step = assembly + RHS + setup + solve + free, "
+                      "host clock with a device synchronisation; solve = HIP events around the PCG solve"}
+
+
 BLOCKS.update({"batched": lambda: batched_heat(), "heat_steps": lambda: heat_steps(),
                "learned_3d": lambda: learned_ellipsoid(), "islands": lambda: shape_opt_islands(),
-               "qoi": lambda: qoi_studies()})
+               "qoi": lambda: qoi_studies(), "disk_latency": lambda: disk_latency()})
 
 
 def parse():
@@ -496,6 +563,7 @@ def parse():
     ap.add_argument("--no-islands", action="store_true", help="skip the shape-optimisation island batch")
     ap.add_argument("--no-qoi", action="store_true", help="skip the shape-parameter QOI studies")
     ap.add_argument("--no-heat-steps", action="store_true", help="skip the 200-step batched heat run")
+    ap.add_argument("--no-disk", action="store_true", help="skip the 128^2 disk latency case")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--block", choices=list(BLOCKS),
                     help="run only this block of the bench line and print its JSON (for profiling)")
@@ -522,18 +590,91 @@ def copy_calibration():
     print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "launches": 5}))
 
 
+_POOL = {}
+
+
+def _pool_init(kind, n, barrier):
+    """Process-pool worker set-up: BLAS on one thread; for the heat workload
+    the assembly and the oracle's hierarchy of (A + I/dt), built once per
+    worker (set-up is amortised over the steps and right-hand sides)."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+    if kind == "heat":
+        from oracle import amg as OA
+        from oracle import eb_assembly as E
+        from paper_2204_06083_amd import workloads as W
+        g = W.unit_box_grid(2, n)
+        asm = E.assemble(g, W.psi_star(g))
+        A = E.operator_csr(asm, 1.0 / g.h)
+        _POOL.update(g=g, asm=asm, A=A, H=OA.build_hierarchy(A, E.unknown_coords(asm)))
+    barrier.wait()
+
+
+def _pool_heat_solve(rhs_id):
+    """One backward-Euler step (dt = h, cold start) of one seeded initial condition."""
+    import numpy as np
+
+    from oracle import amg as OA
+    from oracle import eb_assembly as E
+    from oracle import pcg as OP
+    from paper_2204_06083_amd import workloads as W
+    P = _POOL
+    b = E.rhs(P["asm"], W.heat_initial(P["g"], rhs_id) / P["g"].h, np.zeros(P["asm"].n_cuts))
+    res = OP.pcg(P["A"], b, precond=lambda r: OA.vcycle(P["H"], r), tol=1e-8)
+    return P["asm"].n_unknowns, res.iterations
+
+
+def _pool_island(task):
+    """One shape-optimisation geometry: assembly, hierarchy and its seeded
+    sources solved to 1e-8."""
+    import numpy as np
+
+    from oracle import amg as OA
+    from oracle import eb_assembly as E
+    from oracle import pcg as OP
+    from paper_2204_06083_amd import workloads as W
+    i, n, c, ph, nrhs = task
+    prob = W.random_star_poisson(n, c, ph)
+    asm = E.assemble(prob.grid, prob.psi)
+    A = E.operator_csr(asm)
+    H = OA.build_hierarchy(A, E.unknown_coords(asm))
+    its = 0
+    for j in range(nrhs):
+        b = E.rhs(asm, W.heat_initial(prob.grid, nrhs * i + j), np.zeros(asm.n_cuts))
+        its += OP.pcg(A, b, precond=lambda r: OA.vcycle(H, r), tol=1e-8).iterations
+    return asm.n_unknowns, its
+
+
+def _pool_run(kind, n, fn, tasks, workers):
+    """Map `tasks` over a spawned pool of `workers` processes; timed from the
+    moment every worker has finished its set-up to the last result."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(workers + 1)
+    with ctx.Pool(workers, initializer=_pool_init, initargs=(kind, n, barrier)) as pool:
+        barrier.wait()
+        t0 = time.perf_counter()
+        res = pool.map(fn, tasks, chunksize=1)
+        secs = time.perf_counter() - t0
+    return res, secs
+
+
 def cpu_baseline(n):
-    """The oracle, as it stands, on one full step of the same workload."""
+    """The oracle, as it stands, on full steps of the same workload: with BLAS
+    on one thread (the headline figure) and on every usable core, and the
+    batched workloads over a process pool of every usable core."""
     from threadpoolctl import threadpool_limits
 
     from oracle import eb_assembly as E
     from oracle import pcg as OP
     from paper_2204_06083_amd import workloads as W
 
+    usable = len(os.sched_getaffinity(0))
     prob = W.star_poisson(n)
     reps = 2
-    work = 0
-    with threadpool_limits(limits=1):
+
+    def steps():
+        work = 0
         t0 = time.perf_counter()
         for _ in range(reps):
             asm = E.assemble(prob.grid, prob.psi)
@@ -541,19 +682,50 @@ def cpu_baseline(n):
             b = E.rhs(asm, prob.f, prob.u_dirichlet(*E.cut_coordinates(asm)))
             res, H = OP.amg_pcg(A, E.unknown_coords(asm), b, tol=prob.tol)
             work += asm.n_unknowns * res.iterations
-        t1 = time.perf_counter()
-    secs = t1 - t0
-    return {
+        return work, time.perf_counter() - t0, res.iterations
+
+    with threadpool_limits(limits=1):
+        work, secs, its = steps()
+    with threadpool_limits(limits=usable):
+        work_all, secs_all, _ = steps()
+    out = {
         "value": work / secs,
         "unit": "unknowns·CG-iters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{reps} full steps (assemble, RHS, AMG setup, PCG to 1e-8; {res.iterations} iterations each) "
+        "sample": f"{reps} full steps (assemble, RHS, AMG setup, PCG to 1e-8; {its} iterations each) "
                   f"of the {n}^2 star workload in {secs:.2f} s, BLAS limited to 1 thread; host has "
-                  f"{len(os.sched_getaffinity(0))} usable cores",
+                  f"{usable} usable cores (os.cpu_count() = {os.cpu_count()})",
         "seconds": secs,
-        "iterations": res.iterations,
+        "iterations": its,
+        "all_core_blas": {"value": work_all / secs_all, "unit": "unknowns·CG-iters/s", "cores": usable,
+                          "seconds": secs_all,
+                          "sample": f"the same {reps} steps with BLAS on {usable} threads (the sparse "
+                                    "products stay single-threaded; BLAS serves the coarsest solve)"},
     }
+    workers = min(16, usable)
+    # one task per worker: heat right-hand sides 0 .. workers-1 of the 64
+    # (one backward-Euler step each) and the first `workers` of the 256 seeded
+    # geometries (4 sources each); whole-batch times extrapolated by count
+    res, secs_h = _pool_run("heat", 1024, _pool_heat_solve, list(range(workers)), workers)
+    its_h = [r[1] for r in res]
+    params = W.random_star_params(256)
+    tasks = [(i, nn, c, ph, 4) for i, (nn, c, ph) in enumerate(params[:workers])]
+    res_i, secs_i = _pool_run("islands", 0, _pool_island, tasks, workers)
+    out["process_pool"] = {
+        "kind": "oracle", "cores": workers, "label": f"process pool of {workers} single-threaded workers",
+        "heat_1024_64rhs": {"unit": "solves/s", "value": workers / secs_h, "seconds": secs_h,
+                            "extrapolated_step_seconds_64rhs": secs_h * 64 / workers,
+                            "iterations_min_max": [min(its_h), max(its_h)],
+                            "sample": f"one backward-Euler step (dt = h, cold start, tol 1e-8) of {workers} of the "
+                                      "64 seeded right-hand sides on the 1024^2 star; each worker builds the "
+                                      "assembly and hierarchy once before the timed map"},
+        "islands_256x4": {"unit": "solves/s", "value": 4 * len(tasks) / secs_i, "seconds": secs_i,
+                          "extrapolated_batch_seconds": secs_i * len(params) / len(tasks),
+                          "sample": f"{len(tasks)} of the {len(params)} seeded geometries (assembly, hierarchy and "
+                                    "4 sources to 1e-8 each); batch time extrapolated by geometry count"},
+    }
+    return out
 
 
 def rocprof_summary(path, top=25):
@@ -669,6 +841,10 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the library solves on one GPU; several-GPU runs are not part of this benchmark)", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not (args.copy_calib or args.block or args.no_cpu_baseline):
+        # before any GPU use: the pool's workers are started as new processes
+        cpu = cpu_baseline(args.n)
     import torch
     if args.copy_calib:
         copy_calibration()
@@ -879,8 +1055,10 @@ def main():
         out["islands"] = shape_opt_islands()
     if not args.no_qoi:
         out["qoi"] = qoi_studies()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.n)
+    if not args.no_disk:
+        out["disk_latency"] = disk_latency()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -113,6 +113,43 @@ def test_theta_1_12_errors_against_table1():
     assert errs[1] < errs[0] / 2.5
 
 
+def _mode_phase_prediction(A, v, kappa, dt, theta, ns):
+    """Single-mode model of the theta-scheme error at t = ns dt: the initial
+    mode v taken as an eigenvector with the Rayleigh quotient lam of A, so
+    u^n = (alpha cos(n phi) + beta sin(n phi)) v with cos(phi) = 1 - dt^2 lam
+    / (2 (1 + theta dt^2 lam)), alpha = 1 and beta fixed by u^1 = cos(kappa dt) v;
+    the exact solution is cos(kappa t) v, so the max-error is
+    max|v| |cos(kappa T) - a^ns|."""
+    lam = float(v @ (A @ v)) / float(v @ v)
+    k = dt * dt * lam
+    phi = math.acos(1.0 - k / (2.0 * (1.0 + theta * k)))
+    beta = (math.cos(kappa * dt) - math.cos(phi)) / math.sin(phi)
+    a_n = math.cos(ns * phi) + beta * math.sin(ns * phi)
+    return float(np.abs(v).max()) * abs(math.cos(kappa * ns * dt) - a_n)
+
+
+@pytest.mark.parametrize("key,theta", [("theta_1_2", 0.5), ("theta_1_4", 0.25)])
+def test_theta_half_and_quarter_columns_follow_the_phase_error(key, theta):
+    """Table 1's theta = 1/2 and 1/4 columns (dt/h = 2): the error is the
+    phase error of the standing mode in time, which wraps around over 10.2
+    periods, hence the paper's non-monotone rows.  On the rows h = 2.2e-2,
+    1.1e-2, 5.5e-3 the oracle's max-error follows the single-mode model (2 %
+    where the phase error dominates at the finest of them); a theta weight on
+    the wrong level, a lost dt^2 or a sign slip in the right-hand side moves
+    phi and breaks it."""
+    gold = json.load(open(os.path.join(GOLDEN, "wave_table1.json")))
+    kappa = W.bessel_zero(7, 7)
+    for n, (rel, ab) in zip((100, 200, 400), ((0.2, 5e-3), (0.2, 5e-3), (0.02, 2e-3))):
+        g, asm, A, X, Y = _disk(n)
+        dt, ns = W.wave_schedule(n, gold[key]["dt_over_h"], gold["periods"])
+        v = W.standing_mode(X, Y, 0.0)
+        u, _ = ST.wave_theta(A, v, W.standing_mode(X, Y, dt), dt, theta, ns)
+        e = ST.max_error(u, W.standing_mode(X, Y, ns * dt))
+        pred = _mode_phase_prediction(A, v, kappa, dt, theta, ns)
+        print(f"theta {theta} n {n}: max error {e:.3e}, single-mode model {pred:.3e}")
+        assert abs(e - pred) <= rel * pred + ab, (n, e, pred)
+
+
 def test_crank_nicolson_amplification_factor():
     """With no source and u^0 = v (A v = lam v): u^n = g^n v,
     g = (2/dt - lam) / (2/dt + lam)."""

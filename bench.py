@@ -28,6 +28,8 @@ geometry.  `qoi` runs the two shape-parameter studies of Sec. 3.6 (61
 fixed-area ellipses at 1024^2, 64 rotated ellipses on the 501^2 grid), each
 as one island batch from level sets to quantities of interest.
 `disk_latency` reports the latency of the 128^2 disk problem (FP64 to 1e-10).
+`wave_stencil` times stencil_apply and eb_wave_rhs on Table 1's 1600^2 grid
+against the HBM roofline and runs Table 1's leap-frog column there.
 `learned_3d` carries the whole-solve byte model's roofline fraction of the
 plain 3-D solves.  `cpu_baseline` times the CPU oracle on full steps of the
 same workload (BLAS on one thread and on every usable core), and the heat and
@@ -545,9 +547,75 @@ def disk_latency(n=128, warm=3, reps=10):
                       "host clock with a device synchronisation; solve = HIP events around the PCG solve"}
 
 
+def wave_stencil(n=1600, launches=200):
+    """The explicit wave loop's operator passes on Table 1's finest grid (the
+    unit disk in [-1.1, 1.1]^2, n^2 cells): stencil_apply and the leap-frog
+    right-hand side eb_wave_rhs, timed with HIP events on the library's
+    stream around back-to-back launches queued behind a device-side wait (so
+    host gaps do not enter), and the whole leap-frog run of Table 1 (dt =
+    0.7 h, 10.2 periods) with its max-error."""
+    import torch
+    from paper_2204_06083_amd import solver as S
+    from paper_2204_06083_amd import workloads as W
+    dev = "cuda:0"
+    g = W.wave_disk_grid(n)
+    psi = torch.as_tensor(W.psi_unit_disk(g), device=dev)
+    asm = S.assemble_diag(g, psi)
+    nu = asm.n_unknowns
+    gen = torch.Generator(device=dev).manual_seed(5)
+    x = torch.randn(g.shape, dtype=torch.float64, device=dev, generator=gen)
+    xm = torch.randn(g.shape, dtype=torch.float64, device=dev, generator=gen)
+    y = torch.empty_like(x)
+    nbox = x.numel()
+    wset = nbox * (8 * 4 + 1)
+
+    def timed(fn, algo_bytes):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(50_000_000)         # keeps the stream busy while the launches are queued
+        e0.record()
+        for _ in range(launches):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        mean = e0.elapsed_time(e1) * 1e3 / launches
+        gbs = algo_bytes / (mean * 1e-6) / 1e9
+        return {"avg_launch_us": mean, "launches": launches, "algorithmic_bytes_per_launch": algo_bytes,
+                "timing": "HIP events around back-to-back launches queued behind a device-side wait",
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "mall_resident": wset < MALL_BYTES}}
+
+    out = {"workload": f"wave_disk_{n}_table1_grid", "grid_nodes": f"{n + 1}x{n + 1}", "n_unknowns": nu,
+           "box_nodes": nbox, "working_set_bytes": wset,
+           "bytes_model": "stencil_apply 24 B per unknown (x, a read, y written); eb_wave_rhs 32 B per "
+                          "unknown (u^n, u^{n-1}, a read, out written); kinds and the zeros written off "
+                          "the unknowns not counted"}
+    out["stencil_apply"] = timed(lambda: S.stencil_apply(g, asm.kind, asm.a, 0.0, x, out=y), 24.0 * nu)
+    out["wave_rhs"] = timed(lambda: S.wave_rhs(asm, 0.0, 0.7 * g.h, 1.0, x, xm, out=y), 32.0 * nu)
+    # the leap-frog run of Table 1's first column at this h
+    X, Y = g.mesh()
+    dt, ns = W.wave_schedule(n, 0.7, 10.2)
+    u0 = torch.as_tensor(W.standing_mode(X, Y, 0.0), device=dev)
+    u1 = torch.as_tensor(W.standing_mode(X, Y, dt), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, _, st = S.wave_theta(asm, u0, u1, dt, 0.0, ns)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ex = torch.as_tensor(W.standing_mode(X, Y, ns * dt), device=dev)
+    inside = asm.kind.reshape(u.shape) == 2
+    out["leapfrog_table1"] = {"steps": ns - 1, "seconds": secs, "steps_per_s": (ns - 1) / secs,
+                              "max_error": (u - ex).abs()[inside].max().item(), "paper_max_error": 1.7e-4,
+                              "note": "one eb_wave_rhs launch per step from a host loop"}
+    return out
+
+
 BLOCKS.update({"batched": lambda: batched_heat(), "heat_steps": lambda: heat_steps(),
                "learned_3d": lambda: learned_ellipsoid(), "islands": lambda: shape_opt_islands(),
-               "qoi": lambda: qoi_studies(), "disk_latency": lambda: disk_latency()})
+               "qoi": lambda: qoi_studies(), "disk_latency": lambda: disk_latency(),
+               "wave_stencil": lambda: wave_stencil()})
 
 
 def parse():
@@ -564,6 +632,7 @@ def parse():
     ap.add_argument("--no-qoi", action="store_true", help="skip the shape-parameter QOI studies")
     ap.add_argument("--no-heat-steps", action="store_true", help="skip the 200-step batched heat run")
     ap.add_argument("--no-disk", action="store_true", help="skip the 128^2 disk latency case")
+    ap.add_argument("--no-wave", action="store_true", help="skip the wave-loop operator passes")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--block", choices=list(BLOCKS),
                     help="run only this block of the bench line and print its JSON (for profiling)")
@@ -1057,6 +1126,8 @@ def main():
         out["qoi"] = qoi_studies()
     if not args.no_disk:
         out["disk_latency"] = disk_latency()
+    if not args.no_wave:
+        out["wave_stencil"] = wave_stencil()
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

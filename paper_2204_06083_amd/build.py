@@ -2,9 +2,10 @@
 
     python -m paper_2204_06083_amd.build [--jobs N]
 
-Every translation unit is compiled by hipcc for gfx950 only.  The assembly and
-AMG-setup units are compiled with -ffp-contract=off so that their floating
-point follows the documented evaluation order; the solve unit may contract.
+Every translation unit is compiled by hipcc for gfx950 only.  The assembly,
+AMG-setup and operator-pass units are compiled with -ffp-contract=off so that
+their floating point follows the documented evaluation order; the solve unit
+may contract.
 Packed FP32 instructions are disabled for all device code.
 """
 from __future__ import annotations
@@ -31,6 +32,7 @@ SOURCES = {
     "amg_setup.hip": ["-ffp-contract=off"],
     "solve.hip": [],
     "steppers.hip": [],
+    "field_ops.hip": ["-ffp-contract=off"],
     "batched.hip": [],
     "learned.hip": [],
 }

@@ -660,36 +660,6 @@ __global__ void __launch_bounds__(BLOCK) k_rhs(const int8_t* __restrict__ kind, 
     b[n] = v;
 }
 
-// -------------------------------------------------------- operator on fields
-__global__ void __launch_bounds__(BLOCK) k_stencil_dense(const int8_t* __restrict__ kind, const double* __restrict__ a,
-                                                         const double* __restrict__ beta, double sigma,
-                                                         const double* __restrict__ x,
-                                                         double* __restrict__ y, GridDims d, int64_t nnodes) {
-    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (n >= nnodes) return;
-    const NodePos p = node_pos(n, d);
-    // a node on the outermost layer has no full stencil: never treated as an unknown
-    const bool edge = p.i == 0 || p.i == d.nx - 1 || p.j == 0 || p.j == d.ny - 1 ||
-                      (d.dim == 3 && (p.k == 0 || p.k == d.nz - 1));
-    if (kind[n] != 2 || edge) {
-        y[n] = 0.0;
-        return;
-    }
-    double nb = 0.0;
-    for (int axis = 0; axis < d.dim; ++axis) {
-        const int64_t st = axis_stride(d, axis);
-        if (beta) {
-            if (kind[n - st] == 2) nb = nb + face_beta(beta, n, d, 2 * axis) * x[n - st];
-            if (kind[n + st] == 2) nb = nb + face_beta(beta, n, d, 2 * axis + 1) * x[n + st];
-        } else {
-            if (kind[n - st] == 2) nb = nb + x[n - st];
-            if (kind[n + st] == 2) nb = nb + x[n + st];
-        }
-    }
-    const double diag = a[n] * d.s + sigma;
-    y[n] = diag * x[n] - d.s * nb;
-}
-
 // ------------------------------------------------------------ SPD test
 // The a-priori test of Sec. 2.4: along every axis, each maximal run of
 // computational points on a grid line is one segment of the 1-D matrix
@@ -1011,11 +981,13 @@ static int stencil_apply_impl(const eb_grid_t* g, const int8_t* kind, const doub
         set_error("stencil_apply: sigma must be >= 0");
         return EB_EINVAL;
     }
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t nn = (int64_t)d.nx * d.ny * d.nz;
-    hipLaunchKernelGGL(k_stencil_dense, dim3(grid_for(nn)), dim3(BLOCK), 0, s, kind, a, beta, sigma, x, y, d, nn);
-    EB_LAUNCH_CHECK();
-    return EB_OK;
+    if (x == y) {
+        set_error("stencil_apply: y must not overlap x");
+        return EB_EINVAL;
+    }
+    FieldCoefs co;
+    co.sigma = sigma;
+    return launch_field_op(0, d, kind, a, beta, x, nullptr, nullptr, nullptr, y, co, (hipStream_t)stream);
 }
 
 extern "C" int stencil_apply(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,

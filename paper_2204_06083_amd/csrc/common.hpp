@@ -83,6 +83,19 @@ __device__ inline int64_t xcd_block() {
     return (int64_t)(blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
 }
 
+// Value of the lane to the left (lane - 1; 0 in lane 0) and to the right
+// (lane + 1; 0 in lane 63): whole-wave DPP shifts, executed by all lanes.
+__device__ inline int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+__device__ inline double from_left(double v) {
+    return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
+}
+__device__ inline double from_right(double v) {
+    return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
+}
+__device__ inline float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ inline float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+
 inline unsigned grid_for(int64_t n, int block = BLOCK) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
@@ -158,6 +171,19 @@ struct GridDims {
 };
 
 int make_dims(const eb_grid_t* g, GridDims* d);
+
+// Matrix-free operator passes over node fields (field_ops.hip): op 0 applies
+// A + sigma I to f0; op 1 forms the wave theta-scheme right-hand side
+// scale (2 f0 - f1 - dt2 A (c0 f0 + c1 f1)); op 2 forms
+// alpha (A + sigma I) f0 + beta g0 + gamma g1 (g0, g1 may be null).  cond: the
+// face conductivities (dim fields back to back) or null.  out is written at
+// every node (0 off computational points) and must not overlap f0 or f1.
+struct FieldCoefs {
+    double c0 = 1.0, c1 = 0.0, sigma = 0.0, alpha = 1.0, beta = 0.0, gamma = 0.0, scale = 1.0, dt2 = 0.0;
+};
+int launch_field_op(int op, const GridDims& d, const int8_t* kind, const double* a, const double* cond,
+                    const double* f0, const double* f1, const double* g0, const double* g1, double* out,
+                    const FieldCoefs& co, hipStream_t s);
 
 // Node coordinates of a flat index in the dense user layout.
 struct NodePos {

@@ -740,19 +740,6 @@ __device__ inline void st(T* __restrict__ base, uint32_t i, T v) {
     *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
 }
 
-// Value of the lane to the left (lane - 1; 0 in lane 0) and to the right
-// (lane + 1; 0 in lane 63): whole-wave DPP shifts, executed by all lanes.
-__device__ inline int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
-__device__ inline int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
-__device__ inline double from_left(double v) {
-    return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
-}
-__device__ inline double from_right(double v) {
-    return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
-}
-__device__ inline float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
-__device__ inline float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
-
 // The tiles of this block's wavefront (block-uniform grid, one range per
 // wavefront) and the lane's column.
 struct TileLane {

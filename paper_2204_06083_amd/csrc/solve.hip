@@ -740,6 +740,15 @@ __device__ inline void st(T* __restrict__ base, uint32_t i, T v) {
     *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
 }
 
+// A read without a branch: a lane whose node is off the grid (or not wanted)
+// reads element 0 instead and takes `none`, so every read of a row is issued
+// at once and stays in flight together.
+template <class T>
+__device__ inline T ldz(const T* __restrict__ base, bool ok, uint32_t i, T none = T{}) {
+    const T v = ld(base, ok ? i : 0u);
+    return ok ? v : none;
+}
+
 // The tiles of this block's wavefront (block-uniform grid, one range per
 // wavefront) and the lane's column.
 struct TileLane {
@@ -750,14 +759,14 @@ struct TileLane {
 __device__ inline TileLane tile_lane(const TileArgs& t) {
     TileLane L;
     L.lane = threadIdx.x & (WAVE - 1);
-    const int64_t gw = xcd_block() * (int64_t)TWB + threadIdx.x / WAVE;
+    const int64_t gw = xcd_block() * (int64_t)TWB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     L.t0 = gw * t.tpw;
     L.t1 = min(L.t0 + (int64_t)t.tpw, t.ntiles);
     return L;
 }
 
 __device__ inline void tile_origin(const TileArgs& t, int64_t tix, int* x0, int* y0) {
-    const int tid = t.tiles[tix];
+    const int tid = __builtin_amdgcn_readfirstlane(t.tiles[tix]);
     *x0 = (tid % t.ntx) * TX;
     *y0 = (tid / t.ntx) * TY;
 }
@@ -791,20 +800,21 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
         const bool xin = xc >= 0 && xc < t.nx;
         const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
         auto row = [&](int j, double& d, double& zz, double& pp) {
-            d = zz = pp = 0.0;
-            if (xin && j >= 0 && j < t.ny && j <= y0 + TY) {
-                const uint32_t pn = xc + t.sy * j;
-                d = ld(t.diag, pn);
-                zz = to_f64(ld(z, pn));
-                pp = ld(pold, pn);
-            }
+            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY;
+            const uint32_t pn = xc + t.sy * j;
+            d = ldz(t.diag, ok, pn);
+            zz = to_f64(ldz(z, ok, pn));
+            pp = ldz(pold, ok, pn);
         };
         double d0, z0, p0, d1, z1, p1;     // rows j, j + 1 (read ahead)
         row(y0 - 1, d0, z0, p0);
         row(y0, d1, z1, p1);
         double pa = 0.0, pb = 0.0, da = 0.0;   // p of rows j - 2, j - 1; d of row j - 1
-#pragma unroll 1
-        for (int j = y0 - 1; j <= y0 + TY; ++j) {
+        // fully unrolled: the rows in flight are never copied between
+        // registers, so no read waits before the row that uses it
+#pragma unroll
+        for (int jj = 0; jj < TY + 2; ++jj) {
+            const int j = y0 - 1 + jj;
             double d2, z2, p2;
             row(j + 2, d2, z2, p2);
             const double pc = d0 != 0.0 ? z0 + beta * p0 : 0.0;
@@ -884,33 +894,26 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
         // own rows also x and p (UPD)
         struct Row { double iv, r, q, w, d, x, p; };
         auto row = [&](int j, Row& R) {
-            R.iv = R.r = R.q = R.w = R.d = R.x = R.p = 0.0;
-            if (xin && j >= 0 && j < t.ny && j <= y0 + TY + 1) {
-                const uint32_t pn = xc + t.sy * j;
-                R.iv = ld(t.dinv, pn);
-                R.r = ld(rin, pn);
-                if (UPD) R.q = ld(q, pn);
-                if (LW) {
-                    R.w = ld(t.wf, pn);
-                    R.d = ld(t.diag, pn);
-                }
-                if (UPD && inner && j >= y0 && j < y0 + TY) {
-                    R.x = ld((const double*)x, pn);
-                    R.p = ld(pv, pn);
-                }
-            }
+            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
+            const bool own = ok && inner && j >= y0 && j < y0 + TY;
+            const uint32_t pn = xc + t.sy * j;
+            R.iv = ldz(t.dinv, ok, pn);
+            R.r = ldz(rin, ok, pn);
+            R.q = UPD ? ldz(q, ok, pn) : 0.0;
+            R.w = LW ? ldz(t.wf, ok, pn) : 0.0;
+            R.d = LW ? ldz(t.diag, ok, pn) : 0.0;
+            R.x = UPD ? ldz((const double*)x, own, pn) : 0.0;
+            R.p = UPD ? ldz(pv, own, pn) : 0.0;
         };
         // box row of the lane's box: aggregate count, first aggregate, node
         // map and omega_c / d_c of the first aggregate (read a box row ahead)
         auto boxrow = [&](int by, int& m, int& c0, int& map, V& w0) {
-            m = 0; c0 = 0; map = 0; w0 = V(0);
-            if (inner && by < b.nby && bx < b.nbx) {
-                const uint32_t box = by * b.nbx + bx;
-                m = ld(b.ncomp, box);
-                c0 = ld(b.cstart, box);
-                map = ld(b.map, box);
-                w0 = ld(vbw0<V>(b), box);
-            }
+            const bool ok = inner && by < b.nby && bx < b.nbx;
+            const uint32_t box = by * b.nbx + bx;
+            m = ldz(b.ncomp, ok, box);
+            c0 = ldz(b.cstart, ok, box);
+            map = ldz(b.map, ok, box);
+            w0 = ldz(vbw0<V>(b), ok, box);
         };
         Row R0, R1;                          // rows j, j + 1 (read ahead)
         row(y0 - 2, R0);
@@ -923,8 +926,9 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
         double za = 0.0, zb = 0.0, rb = 0.0, ia = 0.0, ib = 0.0, dbb = 0.0;
         V resa = V(0), va = V(0), vb = V(0);
         V acc[5] = {V(0), V(0), V(0), V(0), V(0)};
-#pragma unroll 1
-        for (int j = y0 - 2; j <= y0 + TY + 1; ++j) {
+#pragma unroll
+        for (int jj = 0; jj < TY + 4; ++jj) {
+            const int j = y0 - 2 + jj;
             Row R2;
             row(j + 2, R2);
             // row j: r, z1 (and the CG update of the tile's own rows)
@@ -1024,37 +1028,33 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
         // one row of a lane: aggregate, 1 / d, r; LW: weight, d
         struct Row { int32_t g; V iv, w, d; double r; };
         auto row = [&](int j, Row& R) {
-            R.g = -1;
-            R.iv = R.w = R.d = V(0);
-            R.r = 0.0;
-            if (xin && j >= 0 && j < t.ny && j <= y0 + TY + 1) {
-                const uint32_t pn = xc + t.sy * j;
-                R.g = ld(agg, pn);
-                if (j >= y0 - 1 && j <= y0 + TY) {
-                    if constexpr (B16) R.iv = (V)bf16_to_f32(ld(t.dinv16, pn));
-                    else R.iv = ld(dinv, pn);
-                    R.r = ld(r, pn);
-                    if (LW) {
-                        R.w = ld(twf<V>(t), pn);
-                        R.d = ld(tdiag<V>(t), pn);
-                    }
-                }
-            }
+            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
+            const bool mid = ok && j >= y0 - 1 && j <= y0 + TY;
+            const uint32_t pn = xc + t.sy * j;
+            R.g = ldz(agg, ok, pn, -1);
+            if constexpr (B16) R.iv = (V)bf16_to_f32(ldz(t.dinv16, mid, pn));
+            else R.iv = ldz(dinv, mid, pn);
+            R.r = ldz(r, mid, pn);
+            R.w = LW ? ldz(twf<V>(t), mid, pn) : V(0);
+            R.d = LW ? ldz(tdiag<V>(t), mid, pn) : V(0);
         };
+        // e_c at a node's aggregate (0 where it has none)
+        auto gather = [&](int32_t g) { return ldz(ec, g >= 0, (uint32_t)g); };
         Row R0, R1;                          // rows j, j + 1 (read ahead)
         row(y0 - 2, R0);
         row(y0 - 1, R1);
-        V t0v = R0.g >= 0 ? ld(ec, (uint32_t)R0.g) : V(0);   // gathered a row ahead
+        V t0v = gather(R0.g);                // gathered a row ahead
         // rolling rows: t (j-2, j-1), zt (j-3, j-2), 1 / d and r and LW
         // weights of rows j-2, j-1
         V ta = V(0), tb = V(0), zta = V(0), ztb = V(0);
         V iva = V(0), ivb = V(0), wa = V(0), wb = V(0), da = V(0), db = V(0);
         double ra = 0.0, rb = 0.0;
-#pragma unroll 1
-        for (int j = y0 - 2; j <= y0 + TY + 1; ++j) {
+#pragma unroll
+        for (int jj = 0; jj < TY + 4; ++jj) {
+            const int j = y0 - 2 + jj;
             Row R2;
             row(j + 2, R2);
-            const V t1v = R1.g >= 0 ? ld(ec, (uint32_t)R1.g) : V(0);
+            const V t1v = gather(R1.g);
             // row j - 1: zt
             const V tlr = from_left(tb) + from_right(tb);
             V ztc = V(0);

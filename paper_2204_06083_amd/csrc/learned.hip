@@ -134,15 +134,18 @@ __global__ void __launch_bounds__(LNT) k_net_l1(NetDims d, const int8_t* __restr
 }
 
 // Layer 2 on the matrix cores.  A wavefront computes 16 consecutive nodes x
-// 16 output channels: for each tap t, D += A_t B_t with A_t[m][k] =
-// bf16(relu(z1))[node_m + off_t][k] and B_t[k][n] = W2[n][k][t], one
-// v_mfma_f32_16x16x16_bf16 per tap.  Lane l holds A rows l % 16, columns
-// 4 (l / 16) .. +3; B columns l % 16, rows 4 (l / 16) .. +3; D rows
-// 4 (l / 16) .. +3, column l % 16.
-typedef short mf_bf16x4 __attribute__((ext_vector_type(4)));
+// 16 output channels, two taps per instruction: for the taps t, t + 1,
+// D += A B with A[m][k] = bf16(relu(z1))[node_m + off_(t + k / 16)][k % 16]
+// and B[k][n] = W2[n][k % 16][t + k / 16], one v_mfma_f32_16x16x32_bf16 (K =
+// 2 taps x 16 input channels; an odd last tap is paired with zeros).  Lane l
+// holds A row l % 16, columns 8 (l / 16) .. +7 (its tap t + (l / 16) / 2,
+// input channels 8 ((l / 16) % 2) .. +7); B column l % 16, the same rows; D
+// rows 4 (l / 16) .. +3, column l % 16.
+typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline short bf16_bits(float x) { return (short)(__float_as_uint(bf16r(x)) >> 16); }
+__device__ inline __bf16 bf16_of_bits(short b) { return __builtin_bit_cast(__bf16, b); }
 
 __global__ void __launch_bounds__(LNT) k_net_l2(NetDims d, const float* __restrict__ params,
                                                 const float* __restrict__ z1, float* __restrict__ z2) {
@@ -156,26 +159,36 @@ __global__ void __launch_bounds__(LNT) k_net_l2(NetDims d, const float* __restri
     const int64_t base = ((int64_t)blockIdx.x * (LNT / WAVE) + threadIdx.x / WAVE) * 16;
     if (base >= d.n) return;                             // whole wavefront
     const int m = lane % 16, kg = lane / 16;
+    const int th = kg >> 1, c0 = 8 * (kg & 1);           // the lane's tap of the pair, first channel
     const int64_t pm = base + m;                         // A row node
     int i = 0, j = 0, k = 0;
     const bool mvalid = pm < d.n;
     if (mvalid) node_ijk(d, pm, i, j, k);
     mf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < d.T; ++t) {
-        const int64_t q = mvalid ? tap_node(d, i, j, k, t) : -1;
-        mf_bf16x4 av, bv;
+    for (int t0 = 0; t0 < d.T; t0 += 2) {
+        const int t = t0 + th;
+        const bool tv = t < d.T;
+        const int64_t q = (mvalid && tv) ? tap_node(d, i, j, k, t) : -1;
+        mf_bf16x8 av, bv;
         if (q >= 0) {
-            const float4 zv = *reinterpret_cast<const float4*>(z1 + q * NCH + 4 * kg);
-            av[0] = bf16_bits(fmaxf(zv.x, 0.f));
-            av[1] = bf16_bits(fmaxf(zv.y, 0.f));
-            av[2] = bf16_bits(fmaxf(zv.z, 0.f));
-            av[3] = bf16_bits(fmaxf(zv.w, 0.f));
+            const float4 za = *reinterpret_cast<const float4*>(z1 + q * NCH + c0);
+            const float4 zb = *reinterpret_cast<const float4*>(z1 + q * NCH + c0 + 4);
+            av[0] = bf16_of_bits(bf16_bits(fmaxf(za.x, 0.f)));
+            av[1] = bf16_of_bits(bf16_bits(fmaxf(za.y, 0.f)));
+            av[2] = bf16_of_bits(bf16_bits(fmaxf(za.z, 0.f)));
+            av[3] = bf16_of_bits(bf16_bits(fmaxf(za.w, 0.f)));
+            av[4] = bf16_of_bits(bf16_bits(fmaxf(zb.x, 0.f)));
+            av[5] = bf16_of_bits(bf16_bits(fmaxf(zb.y, 0.f)));
+            av[6] = bf16_of_bits(bf16_bits(fmaxf(zb.z, 0.f)));
+            av[7] = bf16_of_bits(bf16_bits(fmaxf(zb.w, 0.f)));
         } else {
-            av[0] = av[1] = av[2] = av[3] = 0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) av[r] = bf16_of_bits(0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bv[r] = w2s[((int64_t)m * NCH + 4 * kg + r) * d.T + t];   // n = m
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        for (int r = 0; r < 8; ++r)
+            bv[r] = bf16_of_bits(tv ? w2s[((int64_t)m * NCH + c0 + r) * d.T + t] : (short)0);   // n = m
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

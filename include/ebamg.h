@@ -361,6 +361,26 @@ int amg_setup(const eb_grid_t* g, const int8_t* kind, const double* a, double si
 int amg_setup_beta(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta, double sigma,
                    const amg_params_t* p, amg_handle_t** H, void* stream);
 
+/* amg_setup for a canvas of islands (several geometries stacked one above the
+ * other, as pcg_solve_islands takes them; no stencil joins two islands, so
+ * every level is block diagonal over the islands).  seg_rows (host, nseg + 1
+ * int32): the first node row of each island, then the node-row count.  Each
+ * island's part of the hierarchy ends where its own hierarchy would (the
+ * first level on which it has at most p->coarse_max unknowns, from level 1
+ * on): its unknowns take no part in the coarser levels, and the V-cycle
+ * solves its diagonal block of that level exactly (kept inverted, one
+ * workgroup per island); the level on which the last islands end is the
+ * coarsest.  The aggregation boxes of level l are 3^(l+1) node rows tall, so
+ * an island must start on a node row that is a multiple of 3^l for every
+ * level l on which it ends to be one contiguous row range: EB_EINVAL names
+ * the island and level otherwise (stack islands at multiples of 81 for up to
+ * five levels).  EB_ENOSPC if an island ends with more than 258 unknowns
+ * (coarse_max above 256).  2-D, constant conductivity; otherwise as
+ * amg_setup, and pcg_solve_islands / pcg_solve_batched / pcg_solve run on the
+ * handle as on any other.                                                     */
+int amg_setup_islands(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma, int32_t nseg,
+                      const int32_t* seg_rows, const amg_params_t* p, amg_handle_t** H, void* stream);
+
 /* Solve A x = b by PCG with one V(1,1) cycle as preconditioner (Algorithm 2
  * step 4).  b, x are node fields; x holds x0 on entry if p->x0_given.  On
  * return x holds the solution at computational points and 0 elsewhere.

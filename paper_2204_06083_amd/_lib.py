@@ -20,7 +20,7 @@ BC_MODES = {"line": EB_BC_LINE, "mixed": EB_BC_MIXED, "rbf": EB_BC_RBF}
 
 EXPORTS = [
     "eb_assemble_diag", "eb_assemble_diag_mode", "eb_assemble_diag_beta", "eb_assemble_rhs", "eb_assemble_rhs_islands",
-    "amg_setup_beta", "stencil_apply_beta", "eb_wave_rhs_beta", "eb_stencil_combine_beta", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
+    "amg_setup_beta", "amg_setup_islands", "stencil_apply_beta", "eb_wave_rhs_beta", "eb_stencil_combine_beta", "stencil_apply", "amg_setup", "pcg_solve", "pcg_solve_batched",
     "amg_vcycle_apply", "amg_vcycle_apply_fp32", "amg_vcycle_apply_prec", "amg_set_level_weight", "amg_num_levels", "amg_level_info", "amg_fine_nodes", "amg_free",
     "eb_strerror", "eb_last_error", "eb_abi_version", "eb_timing_select", "eb_timing_read",
     "eb_release_cached_memory", "eb_smoother_net_size", "eb_smoother_forward", "eb_smoother_backward",
@@ -121,6 +121,9 @@ def lib():
     L.amg_setup.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.amg_setup_beta.argtypes = [C.POINTER(EbGrid), vp, vp, vp, dbl, C.POINTER(AmgParams), C.POINTER(vp), vp]
     L.amg_setup_beta.restype = i32
+    L.amg_setup_islands.argtypes = [C.POINTER(EbGrid), vp, vp, dbl, i32, C.POINTER(i32), C.POINTER(AmgParams),
+                                    C.POINTER(vp), vp]
+    L.amg_setup_islands.restype = i32
     L.pcg_solve.argtypes = [vp, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.pcg_solve_batched.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(PcgParams), C.POINTER(PcgResult), vp]
     L.pcg_solve_islands.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), vp, vp, C.POINTER(PcgParams),

@@ -27,6 +27,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <utility>
+#include <vector>
+
 #include "handle.hpp"
 
 namespace eb {
@@ -166,10 +169,17 @@ __global__ void __launch_bounds__(BLOCK) k_fine_fill(const int8_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------- aggregation
+// frz (island hierarchies, may be null): unknowns of islands that end at
+// this level belong to no box and form no aggregate
 __global__ void __launch_bounds__(BLOCK) k_box_count(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
-                                                     int32_t* __restrict__ cnt, int32_t* __restrict__ boxid) {
+                                                     const int8_t* __restrict__ frz, int32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ boxid) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
+    if (frz && frz[i]) {
+        boxid[i] = -1;
+        return;
+    }
     const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
     boxid[i] = (int32_t)b;
     atomicAdd(&cnt[b], 1);
@@ -181,6 +191,7 @@ __global__ void __launch_bounds__(BLOCK) k_box_fill(const int32_t* __restrict__ 
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int32_t b = boxid[i];
+    if (b < 0) return;
     const int32_t slot = atomicAdd(&fillpos[b], 1);
     members[boff[b] + slot] = (int32_t)i;
 }
@@ -376,9 +387,14 @@ __global__ void __launch_bounds__(BOX_WAVES * WAVE) k_box_components(const int32
 
 __global__ void __launch_bounds__(BLOCK) k_assign_agg(const int32_t* __restrict__ coords, int64_t n, NB3 nb,
                                                       const int32_t* __restrict__ cstart,
-                                                      const int32_t* __restrict__ lrank, int32_t* __restrict__ agg) {
+                                                      const int32_t* __restrict__ lrank, const int8_t* __restrict__ frz,
+                                                      int32_t* __restrict__ agg) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
+    if (frz && frz[i]) {
+        agg[i] = -1;
+        return;
+    }
     const int64_t b = box_lin(box_of(coords[3 * i]), box_of(coords[3 * i + 1]), box_of(coords[3 * i + 2]), nb.v);
     agg[i] = cstart[b] + lrank[i];
 }
@@ -424,9 +440,13 @@ __global__ void __launch_bounds__(BLOCK) k_gershgorin_rows(const int32_t* __rest
                                                            const int32_t* __restrict__ col,
                                                            const double* __restrict__ val,
                                                            const double* __restrict__ diag, int64_t n,
-                                                           double* __restrict__ rowv) {
+                                                           const int8_t* __restrict__ frz, double* __restrict__ rowv) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
+    if (frz && frz[i]) {
+        rowv[i] = 1.0;      // no part in this level's weight (every row's bound is >= 1)
+        return;
+    }
     double s = 0.0;
     for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s = s + fabs(val[e]);
     rowv[i] = s / diag[i];
@@ -547,7 +567,9 @@ __global__ void k_accumulate(AccArgs A, int G) {
         bz = A.row_coords[3 * row + 2] / A.centre_div;
         double* v = vals + (size_t)t * ns;
         uint8_t* fl = flags + (size_t)t * ns;
-        if (MODE == ACC_P) {
+        if (MODE == ACC_P && A.agg[row] < 0) {
+            // a row of an island that ends at this level: no prolongator entries
+        } else if (MODE == ACC_P) {
             const double dii = A.diag[row];
             const double omega = *A.omega;
             if (g == 0) {
@@ -561,6 +583,7 @@ __global__ void k_accumulate(AccArgs A, int G) {
             }
             for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
                 const int j = A.x_col[e];
+                if (A.agg[j] < 0) continue;   // never: no edge joins two islands
                 const int sl = A.sm.slot(A.agg[j], bx, by, bz);
                 if (sl < 0) { bad = true; continue; }
                 fl[sl] = 1;
@@ -1058,13 +1081,24 @@ __device__ __forceinline__ void sweep_publish(double (&m)[T][T], double* __restr
     }
 }
 
+// blk (may be null): workgroup b inverts the diagonal block of blk[2b + 1]
+// rows from row blk[2b] on (a contiguous island) into W + woff[b]; without
+// it the one workgroup inverts the whole matrix of n rows.
 template <int T, int NT>
 __global__ void __launch_bounds__(NT) k_dense_sweep(const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col,
                                                     const double* __restrict__ val, int n,
-                                                    double* __restrict__ W, int32_t* __restrict__ err) {
+                                                    double* __restrict__ W, int32_t* __restrict__ err,
+                                                    const int32_t* __restrict__ blk = nullptr,
+                                                    const int64_t* __restrict__ woff = nullptr) {
     __shared__ __align__(16) double cb[2][SW_NPAD];
     __shared__ double rp[2];
+    int r0 = 0;
+    if (blk) {
+        r0 = blk[2 * blockIdx.x];
+        n = blk[2 * blockIdx.x + 1];
+        W += woff[blockIdx.x];
+    }
     const int nb = (n + T - 1) / T;
     const int ntiles = nb * (nb + 1) / 2;
     const int tid = threadIdx.x;
@@ -1087,8 +1121,8 @@ __global__ void __launch_bounds__(NT) k_dense_sweep(const int32_t* __restrict__ 
         for (int a = 0; a < T; ++a) {
             const int i = i0 + a;
             if (i < n) {
-                for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-                    const int c = col[e] - j0;
+                for (int e = rowptr[r0 + i]; e < rowptr[r0 + i + 1]; ++e) {
+                    const int c = col[e] - r0 - j0;
                     const double v = val[e];
 #pragma unroll
                     for (int b = 0; b < T; ++b)
@@ -1151,6 +1185,83 @@ __global__ void __launch_bounds__(NT) k_dense_sweep(const int32_t* __restrict__ 
                 }
             }
     }
+}
+
+// ------------------------------------------------------ island hierarchies
+// Island of each fine unknown from its node row (rows: the islands' first
+// node rows, then the total).
+__global__ void __launch_bounds__(BLOCK) k_island0(const int64_t* __restrict__ nodes, int64_t n, int nx,
+                                                   const int32_t* __restrict__ rows, int nisl,
+                                                   int32_t* __restrict__ isl) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t j = (int32_t)(nodes[i] / nx);
+    int lo = 0, hi = nisl - 1;            // last island with rows[island] <= j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rows[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    isl[i] = lo;
+}
+
+// Per island: row count, first and last row of this level (cnt, first, last
+// pre-set to 0, INT_MAX, -1).
+__global__ void __launch_bounds__(BLOCK) k_island_stats(const int32_t* __restrict__ isl, int64_t n,
+                                                        int32_t* __restrict__ cnt, int32_t* __restrict__ first,
+                                                        int32_t* __restrict__ last) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = isl[i];
+    atomicAdd(&cnt[b], 1);
+    atomicMin(&first[b], (int32_t)i);
+    atomicMax(&last[b], (int32_t)i);
+}
+
+// Island of each coarse unknown: that of its members.
+__global__ void __launch_bounds__(BLOCK) k_island_next(const int32_t* __restrict__ agg,
+                                                       const int32_t* __restrict__ isl, int64_t n,
+                                                       int32_t* __restrict__ isl_next) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    if (agg[i] >= 0) isl_next[agg[i]] = isl[i];
+}
+
+// Each island's own Gershgorin bound on this level: the largest row bound of
+// its rows (bit patterns of non-negative doubles order like the values).
+__global__ void __launch_bounds__(BLOCK) k_island_rho(const double* __restrict__ rowv,
+                                                      const int32_t* __restrict__ isl,
+                                                      const int8_t* __restrict__ frz, int64_t n,
+                                                      unsigned long long* __restrict__ rho_isl) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n || (frz && frz[i])) return;
+    atomicMax(&rho_isl[isl[i]], (unsigned long long)__double_as_longlong(rowv[i]));
+}
+
+// The smoothers and the prolongator of a level take omega / d: scaling the
+// stored diagonal of island k's rows by rho_k / rho (rho the level's bound,
+// omega = 4 / (3 rho)) gives those rows the weight 4 / (3 rho_k) that the
+// island's own hierarchy has (the operator's values keep the true diagonal).
+__global__ void __launch_bounds__(BLOCK) k_island_diag(double* __restrict__ diag, const int32_t* __restrict__ isl,
+                                                       const int8_t* __restrict__ frz, int64_t n,
+                                                       const unsigned long long* __restrict__ rho_isl,
+                                                       const unsigned long long* __restrict__ rho_level) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n || (frz && frz[i])) return;
+    const double rk = __longlong_as_double((long long)rho_isl[isl[i]]);
+    const double r = __longlong_as_double((long long)*rho_level);
+    diag[i] = diag[i] * (rk / r);
+}
+
+// Rows of the islands that end at this level, and each row's block (-1
+// outside the blocks); ending[island] is the island's block or -1.
+__global__ void __launch_bounds__(BLOCK) k_island_rows(const int32_t* __restrict__ isl, int64_t n,
+                                                       const int32_t* __restrict__ ending, int8_t* __restrict__ frz,
+                                                       int32_t* __restrict__ blk) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = ending[isl[i]];
+    if (frz) frz[i] = b >= 0 ? 1 : 0;
+    blk[i] = b;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
@@ -1489,12 +1600,17 @@ static int make_coarsest(amg_handle* H, int l, hipStream_t s, int32_t* err) {
 
 // Aggregate level l and build level l+1; *stop = 1 if level l becomes the
 // coarsest.  One host synchronisation (coarse count, box maximum, errors).
-static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* stop) {
+// frz (island hierarchies from level 1 on): rows of the islands that end at
+// this level, n_act the other rows; they are left out of the aggregation, so
+// the coarser levels hold only the islands that go on.
+static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, const int8_t* frz, int64_t n_act,
+                      const int32_t* isl, int* stop) {
     Level& L = H->lev[l];
     *stop = 0;
     const int64_t n = L.n;
     const int dim = H->d.dim;
-    if (n <= H->params.coarse_max || l + 1 >= H->params.max_levels || l + 1 >= MAX_LEVELS) {
+    const bool island_rule = H->nisl > 0 && l >= 1;   // the per-island size rule decides instead
+    if ((!island_rule && n <= H->params.coarse_max) || l + 1 >= H->params.max_levels || l + 1 >= MAX_LEVELS) {
         *stop = 1;
         return EB_OK;
     }
@@ -1530,7 +1646,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
         EB_TRY(dalloc_n(&boff, nboxes, s));
         EB_TRY(dalloc_n(&members, n, s));
         EB_TRY(dalloc_n(&boxid, n, s));
-        hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, cnt, boxid);
+        hipLaunchKernelGGL(k_box_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, (const int8_t*)frz, cnt,
+                           boxid);
         EB_LAUNCH_CHECK();
         EB_TRY(scan_i32_dev(cnt, boff, nboxes, dstat + 3, s));     // total (= n) unused
         hipLaunchKernelGGL(k_box_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, boxid, n, boff, fillpos, members);
@@ -1552,14 +1669,15 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     EB_TRY(err_code(st.err, "aggregation"));
     const int64_t nc = st.count;
     const int maxc = st.maxv;
-    if ((double)nc > H->params.min_reduction * (double)n || nc == 0) {
+    if ((double)nc > H->params.min_reduction * (double)(frz ? n_act : n) || nc == 0) {
         EB_TRY(dfree(lrank, s));
         *stop = 1;
         return EB_OK;
     }
     L.max_comp = maxc;
     EB_TRY(dalloc_n(&L.agg, n, s));
-    hipLaunchKernelGGL(k_assign_agg, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, L.box_cstart, lrank, L.agg);
+    hipLaunchKernelGGL(k_assign_agg, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.coords, n, nb, L.box_cstart, lrank,
+                       (const int8_t*)frz, L.agg);
     EB_LAUNCH_CHECK();
     EB_TRY(dfree(lrank, s));
 
@@ -1580,10 +1698,22 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
     EB_TRY(dalloc_n(&drho, 1, s));
     EB_HIP(hipMemsetAsync(drho, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_gershgorin_rows, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.a_rowptr, L.a_col, L.a_val, L.diag,
-                       n, rowv);
+                       n, (const int8_t*)frz, rowv);
     hipLaunchKernelGGL(k_max_f64, dim3(max_grid(n)), dim3(BLOCK), 0, s, rowv, n, drho, err);
     hipLaunchKernelGGL(k_omega, dim3(1), dim3(1), 0, s, drho, H->dscal + 2 * l);
     EB_LAUNCH_CHECK();
+    if (isl) {
+        // island hierarchies: every island smooths with its own weight
+        unsigned long long* rho_isl = nullptr;
+        EB_TRY(dalloc_n(&rho_isl, (int64_t)H->nisl, s));
+        EB_HIP(hipMemsetAsync(rho_isl, 0, sizeof(unsigned long long) * (size_t)H->nisl, s));
+        hipLaunchKernelGGL(k_island_rho, dim3(grid_for(n)), dim3(BLOCK), 0, s, (const double*)rowv, isl, frz, n,
+                           rho_isl);
+        hipLaunchKernelGGL(k_island_diag, dim3(grid_for(n)), dim3(BLOCK), 0, s, L.diag, isl, frz, n,
+                           (const unsigned long long*)rho_isl, (const unsigned long long*)drho);
+        EB_LAUNCH_CHECK();
+        EB_TRY(dfree(rho_isl, s));
+    }
     EB_TRY(dfree(rowv, s));
     EB_TRY(dfree(drho, s));
 
@@ -1704,7 +1834,8 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, int* 
 
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
-                    L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.rv, L.ev, L.tmp,
+                    L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.fz_off, L.fz_woff,
+                    L.fz_inv, L.fz_blk, L.rv, L.ev, L.tmp,
                     L.sv, L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
     for (void* p : ptrs) (void)dfree(p, s);
     for (Sell* m : {&L.sa, &L.sp, &L.sap}) {
@@ -1742,6 +1873,90 @@ int free_handle_memory(amg_handle* H) {
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
     H->ev_fork = H->ev_join = nullptr;
+    return EB_OK;
+}
+
+// A device int32 buffer freed when it goes out of scope (setup temporaries).
+struct TmpI32 {
+    int32_t* p = nullptr;
+    hipStream_t s = nullptr;
+    explicit TmpI32(hipStream_t st) : s(st) {}
+    ~TmpI32() {
+        if (p) (void)dfree(p, s);
+    }
+};
+
+// Island hierarchies: per island, its row count, first and last row on level
+// l (isl: the island of each row), read back to the host.
+static int island_stats(amg_handle* H, const int32_t* isl, int64_t n, std::vector<int32_t>* cnt,
+                        std::vector<int32_t>* first, std::vector<int32_t>* last, hipStream_t s) {
+    const int m = H->nisl;
+    TmpI32 d(s);
+    EB_TRY(dalloc_n(&d.p, 3 * (int64_t)m, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(BLOCK), 0, s, d.p, (int64_t)m, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(BLOCK), 0, s, d.p + m, (int64_t)m, 0x7fffffff);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(BLOCK), 0, s, d.p + 2 * m, (int64_t)m, -1);
+    if (n > 0)
+        hipLaunchKernelGGL(k_island_stats, dim3(grid_for(n)), dim3(BLOCK), 0, s, isl, n, d.p, d.p + m, d.p + 2 * m);
+    EB_LAUNCH_CHECK();
+    std::vector<int32_t> h(3 * (size_t)m);
+    EB_HIP(hipMemcpyAsync(h.data(), d.p, sizeof(int32_t) * 3 * (size_t)m, hipMemcpyDeviceToHost, s));
+    EB_HIP(hipStreamSynchronize(s));
+    cnt->assign(h.begin(), h.begin() + m);
+    first->assign(h.begin() + m, h.begin() + 2 * m);
+    last->assign(h.begin() + 2 * m, h.end());
+    return EB_OK;
+}
+
+// The diagonal blocks of the islands `ending` on level l (their rows must be
+// contiguous), each inverted by one workgroup of the sweep kernel; the block
+// of every row goes to L.fz_blk and, unless `all` (the blocks cover the
+// level: it is the coarsest), the rows of those islands to *frz.
+static int make_island_blocks(amg_handle* H, int l, const int32_t* isl, const std::vector<int>& ending,
+                              const std::vector<int32_t>& cnt, const std::vector<int32_t>& first,
+                              const std::vector<int32_t>& last, bool all, int8_t** frz, int32_t* err,
+                              hipStream_t s) {
+    Level& L = H->lev[l];
+    const int nb = (int)ending.size();
+    std::vector<int32_t> blk(2 * (size_t)nb), map((size_t)H->nisl, -1);
+    std::vector<int64_t> woff((size_t)nb);
+    int64_t tot = 0;
+    for (int k = 0; k < nb; ++k) {
+        const int i = ending[k];
+        if (last[i] - first[i] + 1 != cnt[i]) {
+            set_error("amg_setup_islands: island %d is not one row range on level %d (place the islands on node "
+                      "rows that are multiples of 3^%d)", i, l, l);
+            return EB_EINVAL;
+        }
+        if (cnt[i] > SW_NMAX) {
+            set_error("amg_setup_islands: island %d ends with %d unknowns, more than %d", i, cnt[i], SW_NMAX);
+            return EB_ENOSPC;
+        }
+        blk[2 * k] = first[i];
+        blk[2 * k + 1] = cnt[i];
+        woff[k] = tot;
+        tot += (int64_t)cnt[i] * cnt[i];
+        map[i] = k;
+    }
+    TmpI32 dmap(s);
+    EB_TRY(dalloc_n(&L.fz_off, 2 * (int64_t)nb, s));
+    EB_TRY(dalloc_n(&L.fz_woff, (int64_t)nb, s));
+    EB_TRY(dalloc_n(&L.fz_inv, tot > 0 ? tot : 1, s));
+    EB_TRY(dalloc_n(&L.fz_blk, L.n, s));
+    EB_TRY(dalloc_n(&dmap.p, (int64_t)H->nisl, s));
+    EB_HIP(hipMemcpyAsync(L.fz_off, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice, s));
+    EB_HIP(hipMemcpyAsync(L.fz_woff, woff.data(), sizeof(int64_t) * woff.size(), hipMemcpyHostToDevice, s));
+    EB_HIP(hipMemcpyAsync(dmap.p, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice, s));
+    if (!all) EB_TRY(dalloc_n(frz, L.n, s));
+    hipLaunchKernelGGL(k_island_rows, dim3(grid_for(L.n)), dim3(BLOCK), 0, s, isl, L.n, (const int32_t*)dmap.p,
+                       all ? nullptr : *frz, L.fz_blk);
+    hipLaunchKernelGGL((k_dense_sweep<SW_T, SW_THREADS>), dim3((unsigned)nb), dim3(SW_THREADS), 0, s, L.a_rowptr,
+                       L.a_col, L.a_val, 0, L.fz_inv, err, (const int32_t*)L.fz_off, (const int64_t*)L.fz_woff);
+    EB_LAUNCH_CHECK();
+    // the host vectors above are read by the copies: wait before they go
+    EB_HIP(hipStreamSynchronize(s));
+    L.nfz = nb;
+    L.fz_all = all ? 1 : 0;
     return EB_OK;
 }
 
@@ -1796,14 +2011,56 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
     H->unk_off_tmp = unk_off;   // node -> unknown map, used by the level-0 transpose
     H->kind_tmp = kind;
 
+    // island hierarchies: the island of each row of the current level
+    TmpI32 isl(s);
+    std::vector<char> going_on;
+    if (H->nisl > 0) {
+        EB_TRY(dalloc_n(&isl.p, nunk > 0 ? nunk : 1, s));
+        if (nunk > 0)
+            hipLaunchKernelGGL(k_island0, dim3(grid_for(nunk)), dim3(BLOCK), 0, s, H->fine_nodes, nunk, d.nx,
+                               (const int32_t*)H->isl_rows, H->nisl, isl.p);
+        EB_LAUNCH_CHECK();
+        going_on.assign((size_t)H->nisl, 1);
+    }
     int l = 0;
     while (true) {
         if (H->lev[l].n == 0) {
             H->lev[l].is_coarsest = 1;
             break;
         }
+        // an island whose rows on this level number at most coarse_max ends
+        // here (as its own hierarchy would); once no island goes on, this
+        // level is the coarsest and its blocks are every island's exact solve
+        int8_t* frz = nullptr;
+        int64_t n_act = H->lev[l].n;
+        if (H->nisl > 0 && l >= 1) {
+            std::vector<int32_t> cnt, first, last;
+            EB_TRY(island_stats(H, isl.p, H->lev[l].n, &cnt, &first, &last, s));
+            std::vector<int> ending, present;
+            bool any_left = false;
+            for (int i = 0; i < H->nisl; ++i) {
+                if (cnt[i] == 0) continue;
+                present.push_back(i);
+                if (cnt[i] <= H->params.coarse_max) ending.push_back(i);
+                else any_left = true;
+            }
+            if (!any_left) {
+                EB_TRY(make_island_blocks(H, l, isl.p, present, cnt, first, last, true, nullptr, dstat, s));
+                H->lev[l].is_coarsest = 1;
+                break;
+            }
+            if (!ending.empty()) {
+                EB_TRY(make_island_blocks(H, l, isl.p, ending, cnt, first, last, false, &frz, dstat, s));
+                for (int i : ending) n_act -= cnt[i];
+            }
+        }
         int stop = 0;
-        EB_TRY(build_next(H, l, s, dstat, &stop));
+        const int rc = build_next(H, l, s, dstat, frz, n_act, H->nisl > 0 && l >= 1 ? isl.p : nullptr, &stop);
+        if (rc != EB_OK) {
+            if (frz) (void)dfree(frz, s);
+            return rc;
+        }
+        if (frz) EB_TRY(dfree(frz, s));
         if (H->unk_off_tmp) {
             EB_TRY(dfree(H->unk_off_tmp, s));
             H->unk_off_tmp = nullptr;
@@ -1811,6 +2068,15 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         if (stop) {
             EB_TRY(make_coarsest(H, l, s, dstat));
             break;
+        }
+        if (H->nisl > 0) {
+            TmpI32 next(s);
+            const int64_t nc = H->lev[l + 1].n;
+            EB_TRY(dalloc_n(&next.p, nc > 0 ? nc : 1, s));
+            hipLaunchKernelGGL(k_island_next, dim3(grid_for(H->lev[l].n)), dim3(BLOCK), 0, s, H->lev[l].agg, isl.p,
+                               H->lev[l].n, next.p);
+            EB_LAUNCH_CHECK();
+            std::swap(isl.p, next.p);
         }
         ++l;
     }
@@ -1873,7 +2139,8 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
 using namespace eb;
 
 static int amg_setup_impl(const eb_grid_t* g, const int8_t* kind, const double* a, const double* beta,
-                          double sigma, const amg_params_t* p, amg_handle_t** Hout, void* stream) {
+                          double sigma, const amg_params_t* p, amg_handle_t** Hout, void* stream, int32_t nisl = 0,
+                          const int32_t* isl_rows = nullptr) {
     clear_error();
     if (!Hout || !kind || !a) {
         set_error("amg_setup: null pointer");
@@ -1920,7 +2187,22 @@ static int amg_setup_impl(const eb_grid_t* g, const int8_t* kind, const double* 
     H->beta_tmp = beta;
     H->beta_on = beta != nullptr;
     AllocScope scope(&H->params);
-    int rc = setup_impl(H, kind, a, H->stream);
+    int rc = EB_OK;
+    if (nisl > 0) {
+        H->nisl = nisl;
+        rc = dalloc_n(&H->isl_rows, (int64_t)nisl + 1, H->stream);
+        if (rc == EB_OK && hipMemcpyAsync(H->isl_rows, isl_rows, sizeof(int32_t) * ((size_t)nisl + 1),
+                                          hipMemcpyHostToDevice, H->stream) != hipSuccess) {
+            set_error("amg_setup_islands: copy of the island rows failed");
+            rc = EB_EHIP;
+        }
+    }
+    if (rc == EB_OK) rc = setup_impl(H, kind, a, H->stream);
+    if (H->isl_rows) {
+        (void)hipStreamSynchronize(H->stream);
+        (void)dfree(H->isl_rows, H->stream);
+        H->isl_rows = nullptr;
+    }
     H->beta_tmp = nullptr;
     if (rc != EB_OK) {
         char msg[1024];
@@ -1946,6 +2228,31 @@ extern "C" int amg_setup_beta(const eb_grid_t* g, const int8_t* kind, const doub
         return EB_EINVAL;
     }
     return amg_setup_impl(g, kind, a, beta, sigma, p, Hout, stream);
+}
+
+extern "C" int amg_setup_islands(const eb_grid_t* g, const int8_t* kind, const double* a, double sigma,
+                                 int32_t nseg, const int32_t* seg_rows, const amg_params_t* p, amg_handle_t** H,
+                                 void* stream) {
+    clear_error();
+    if (!g || g->dim != 2) {
+        set_error("amg_setup_islands: 2-D grids only");
+        return EB_EINVAL;
+    }
+    if (nseg < 1 || !seg_rows) {
+        set_error("amg_setup_islands: need at least one island and its rows");
+        return EB_EINVAL;
+    }
+    if (seg_rows[0] != 0 || seg_rows[nseg] != g->n[1] + 1) {
+        set_error("amg_setup_islands: island rows must start at 0 and end at the node rows (%d)", g->n[1] + 1);
+        return EB_EINVAL;
+    }
+    for (int i = 0; i < nseg; ++i) {
+        if (seg_rows[i + 1] <= seg_rows[i]) {
+            set_error("amg_setup_islands: island rows must increase");
+            return EB_EINVAL;
+        }
+    }
+    return amg_setup_impl(g, kind, a, nullptr, sigma, p, H, stream, nseg, seg_rows);
 }
 
 extern "C" void amg_free(amg_handle_t* H) {

@@ -821,6 +821,23 @@ __global__ void __launch_bounds__(BNT) kb_csr_post(int64_t n, int lkp, int kp, c
 }
 
 // Coarsest: ev = W rv (W FP64, FP64 accumulation).
+// Island hierarchies: ev = W_b rv on the rows of each island that ends on
+// this level (the single solve's k_block_apply, every rhs).
+template <class V>
+__global__ void __launch_bounds__(BNT) kb_block(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
+                                                const int32_t* __restrict__ blk_of, const int32_t* __restrict__ blk,
+                                                const int64_t* __restrict__ woff, const double* __restrict__ W,
+                                                const V* __restrict__ rv, V* __restrict__ ev) {
+    BROW(n, lkp, kp, done, row, j)
+    const int b = blk_of[row];
+    if (b < 0) return;
+    const int o = blk[2 * b], m = blk[2 * b + 1];
+    const double* Wr = W + woff[b] + (int64_t)(row - o) * m;
+    double acc = 0.0;
+    for (int c = 0; c < m; ++c) acc += Wr[c] * (double)rv[(int64_t)(o + c) * kp + j];
+    ev[row * kp + j] = (V)acc;
+}
+
 template <class V>
 __global__ void __launch_bounds__(BNT) kb_dense(int64_t n, int lkp, int kp, const int32_t* __restrict__ done,
                                                 const double* __restrict__ W, const V* __restrict__ rv,
@@ -1193,8 +1210,13 @@ static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int ini
     }
     {
         const Level& Lc = H->lev[H->nlev - 1];
-        hipLaunchKernelGGL(kb_dense<V>, dim3(rows_grid(Lc.n, kp)), dim3(BNT), 0, s, Lc.n, lkp, kp, done,
-                           Lc.dense_inv, (const V*)B->rv[H->nlev - 1], (V*)B->ev[H->nlev - 1]);
+        if (Lc.fz_all)
+            hipLaunchKernelGGL(kb_block<V>, dim3(rows_grid(Lc.n, kp)), dim3(BNT), 0, s, Lc.n, lkp, kp, done,
+                               (const int32_t*)Lc.fz_blk, (const int32_t*)Lc.fz_off, (const int64_t*)Lc.fz_woff,
+                               (const double*)Lc.fz_inv, (const V*)B->rv[H->nlev - 1], (V*)B->ev[H->nlev - 1]);
+        else
+            hipLaunchKernelGGL(kb_dense<V>, dim3(rows_grid(Lc.n, kp)), dim3(BNT), 0, s, Lc.n, lkp, kp, done,
+                               Lc.dense_inv, (const V*)B->rv[H->nlev - 1], (V*)B->ev[H->nlev - 1]);
     }
     for (int l = H->nlev - 2; l >= 1; --l) {
         const Level& L = H->lev[l];
@@ -1203,6 +1225,10 @@ static int benqueue_vcycle(amg_handle* H, BatchBufs* B, const double* r, int ini
                            bcsr_p<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (const V*)B->ev[l + 1], (V*)B->tmp[l]);
         hipLaunchKernelGGL(kb_csr_post<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
                            bcsr_a<V>(L), bldiag<V>(L), w, (const V*)B->rv[l], (const V*)B->tmp[l], (V*)B->ev[l]);
+        if (L.nfz > 0)
+            hipLaunchKernelGGL(kb_block<V>, dim3(rows_grid(L.n, kp)), dim3(BNT), 0, s, L.n, lkp, kp, done,
+                               (const int32_t*)L.fz_blk, (const int32_t*)L.fz_off, (const int64_t*)L.fz_woff,
+                               (const double*)L.fz_inv, (const V*)B->rv[l], (V*)B->ev[l]);
     }
     BLAUNCH_V(kb_fine_up, V, npl_of(ff, B), bgrid(gfull, ff, B), ff, w0, H->agg_p, (const V*)B->ev[1], r, (V*)B->zt);
     BLAUNCH_V(kb_fine_post, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, w0, (const V*)B->zt, r, z, part);

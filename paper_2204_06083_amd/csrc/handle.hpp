@@ -44,6 +44,16 @@ struct Level {
     int32_t* box_cstart = nullptr;  // nboxes: first coarse unknown of each box
     int32_t* box_ncomp = nullptr;   // nboxes: coarse unknowns formed in each box
     double* dense_inv = nullptr; // coarsest: n x n
+    // island hierarchies: the islands whose own hierarchy ends at this level
+    // (at most coarse_max unknowns here) take no part in the coarser levels;
+    // their correction on this level is the exact solve with their diagonal
+    // block of A, kept inverted.  Blocks are contiguous row ranges.
+    int nfz = 0;                 // blocks (islands) ending here
+    int fz_all = 0;              // 1: every row belongs to a block (the coarsest level of an island hierarchy)
+    int32_t* fz_off = nullptr;   // nfz + 1 row offsets (device)
+    int64_t* fz_woff = nullptr;  // nfz offsets of the inverses in fz_inv (device)
+    double* fz_inv = nullptr;    // the blocks' inverses, row-major, back to back
+    int32_t* fz_blk = nullptr;   // n: block of each row, -1 outside the blocks
     // sliced ELL copies of A, P and A P for the V-cycle (levels >= 1 with a
     // coarser level), and R A = (A P)^T in CSR (rows sorted)
     Sell sa, sp, sap;
@@ -178,6 +188,9 @@ struct amg_handle {
     double tim_ms = 0.0;
     // batched solves (made on the first pcg_solve_batched call)
     eb::BatchBufs* batch = nullptr;
+    // island hierarchy (amg_setup_islands): node-row bounds of the islands
+    int nisl = 0;
+    int32_t* isl_rows = nullptr;    // nisl + 1 (device, setup only)
 };
 
 namespace eb {

@@ -1467,6 +1467,28 @@ __global__ void __launch_bounds__(NT) k_dense_apply(int64_t n, const double* __r
     if (lane == 0) ev[row] = (V)acc;
 }
 
+// Island hierarchies: ev = W_b rv on the rows of each island that ends on
+// this level (W_b the inverse of its diagonal block; FP64 in either
+// precision), one wavefront per row; rows outside the blocks keep their ev.
+template <class V>
+__global__ void __launch_bounds__(NT) k_block_apply(int64_t n, const int32_t* __restrict__ blk_of,
+                                                    const int32_t* __restrict__ blk, const int64_t* __restrict__ woff,
+                                                    const double* __restrict__ W, const V* __restrict__ rv,
+                                                    V* __restrict__ ev, const PcgScalars* sc) {
+    if (sc->done) return;
+    const int64_t row = (int64_t)blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (row >= n) return;
+    const int b = blk_of[row];
+    if (b < 0) return;
+    const int o = blk[2 * b], m = blk[2 * b + 1];
+    const double* Wr = W + woff[b] + (int64_t)(row - o) * m;
+    double acc = 0.0;
+    for (int j = lane; j < m; j += WAVE) acc += Wr[j] * (double)rv[o + j];
+    acc = wave_sum(acc);
+    if (lane == 0) ev[row] = (V)acc;
+}
+
 // One-level hierarchies (fine level = coarsest): gather r into compact order
 // (after the convergence test) and scatter z back with the (r, z) partials.
 __global__ void __launch_bounds__(NT) k_gather(int64_t n, const int32_t* __restrict__ pad,
@@ -1833,8 +1855,13 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
     {
         const Level& Lc = H->lev[H->nlev - 1];
         const LevelView<V> Lcv = view<V>(Lc);
-        hipLaunchKernelGGL(k_dense_apply<V>, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv,
-                           Lcv.rv, Lcv.ev, sc);
+        if (Lc.fz_all)
+            hipLaunchKernelGGL(k_block_apply<V>, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n,
+                               (const int32_t*)Lc.fz_blk, (const int32_t*)Lc.fz_off, (const int64_t*)Lc.fz_woff,
+                               (const double*)Lc.fz_inv, (const V*)Lcv.rv, Lcv.ev, sc);
+        else
+            hipLaunchKernelGGL(k_dense_apply<V>, dim3(grid_for(Lc.n, NT / WAVE)), dim3(NT), 0, s, Lc.n, Lc.dense_inv,
+                               Lcv.rv, Lcv.ev, sc);
     }
     for (int l = H->nlev - 2; l >= 1; --l) {
         const Level& L = H->lev[l];
@@ -1848,6 +1875,12 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
             hipLaunchKernelGGL((k_sell_up<V, 8, 14>), dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
                                Lv.sap, Lv.diag, (V)L.omega, (const V*)Lv.rv, (const V*)Lv.sv, (const V*)Cv.ev, Lv.ev,
                                sc);
+        // islands ending on this level: their exact block solve replaces the
+        // smoothing-only value the up pass left on their rows
+        if (L.nfz > 0)
+            hipLaunchKernelGGL(k_block_apply<V>, dim3(grid_for(L.n, NT / WAVE)), dim3(NT), 0, s, L.n,
+                               (const int32_t*)L.fz_blk, (const int32_t*)L.fz_off, (const int64_t*)L.fz_woff,
+                               (const double*)L.fz_inv, (const V*)Lv.rv, Lv.ev, sc);
     }
     EB_LAUNCH_CHECK();
     return EB_OK;

@@ -304,11 +304,13 @@ class Hierarchy:
 
     def __init__(self, grid, kind: torch.Tensor, a: torch.Tensor, sigma: float = 0.0, coarse_max: int = 256,
                  max_levels: int = 16, min_reduction: float = 0.6, dense_limit: int = 1200,
-                 allocator: Optional[str] = None, beta: Optional[torch.Tensor] = None):
+                 allocator: Optional[str] = None, beta: Optional[torch.Tensor] = None, islands=None):
         """allocator: None (the library's own cache) or "torch": every device
         block of the handle comes from torch's caching allocator.  beta: face
         conductivities (dim, *grid.shape) of a variable-coefficient assembly
-        (amg_setup_beta)."""
+        (amg_setup_beta).  islands: the node-row bounds of a canvas of islands
+        (IslandCanvas.rows): each island's part of the hierarchy ends where
+        its own hierarchy would (amg_setup_islands)."""
         lib = L.lib()
         self.grid = grid
         self.sigma = float(sigma)
@@ -335,7 +337,14 @@ class Hierarchy:
         self._params = p
         h = C.c_void_p()
         shape = grid.shape
-        if beta is not None:
+        if islands is not None:
+            if beta is not None:
+                raise ValueError("islands and beta cannot be combined")
+            rows = np.ascontiguousarray(np.asarray(islands, dtype=np.int32))
+            rc = lib.amg_setup_islands(C.byref(g), _field(kind, shape, torch.int8, "kind"),
+                                       _field(a, shape, torch.float64, "a"), self.sigma, int(rows.size - 1),
+                                       rows.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(p), C.byref(h), _stream())
+        elif beta is not None:
             bp = _field(beta, (grid.dim,) + tuple(shape), torch.float64, "beta")
             rc = lib.amg_setup_beta(C.byref(g), _field(kind, shape, torch.int8, "kind"),
                                     _field(a, shape, torch.float64, "a"), bp, self.sigma, C.byref(p), C.byref(h),
@@ -513,14 +522,23 @@ class IslandCanvas:
         return [field[..., int(self.rows[i]):int(self.rows[i]) + sh[0], :sh[1]] for i, sh in enumerate(self.shapes)]
 
 
-def stack_islands(grids) -> IslandCanvas:
-    """Canvas for 2-D geometries given by their grids (each with its own n and h)."""
+ISLAND_ROW_ALIGN = 81   # 3^4: islands stay whole row ranges on up to five levels
+
+
+def stack_islands(grids, align: int = ISLAND_ROW_ALIGN) -> IslandCanvas:
+    """Canvas for 2-D geometries given by their grids (each with its own n and
+    h): island i's node rows start at rows[i], a multiple of `align` (rows of
+    outside nodes fill the gaps and belong to the island above), so that the
+    island hierarchy (Hierarchy(islands=rows)) keeps each island one row range
+    on every level it can end on."""
     shapes = [tuple(g.shape) for g in grids]
     if any(len(sh) != 2 for sh in shapes):
         raise ValueError("stack_islands: 2-D grids only")
     width = max(sh[1] for sh in shapes)
     rows = np.zeros(len(shapes) + 1, dtype=np.int32)
-    rows[1:] = np.cumsum([sh[0] for sh in shapes])
+    for i, sh in enumerate(shapes):
+        end = int(rows[i]) + sh[0]
+        rows[i + 1] = end if i + 1 == len(shapes) else -(-end // align) * align
     from types import SimpleNamespace
     n = (width - 1, int(rows[-1]) - 1)
     canvas = SimpleNamespace(dim=2, n=n, x0=(0.0, 0.0), h=1.0, shape=(n[1] + 1, n[0] + 1))
@@ -589,7 +607,7 @@ def qoi_study(grid, psis, f, weights, tol: float = 1e-10, precision: str = "fp64
     t1 = time.perf_counter()
     asm = assemble_diag(canvas.grid, psi_c)
     b = assemble_rhs_islands(asm, canvas, f_c)
-    H = Hierarchy(canvas.grid, asm.kind, asm.a, 0.0)
+    H = Hierarchy(canvas.grid, asm.kind, asm.a, 0.0, islands=canvas.rows)
     try:
         X, infos = solve_islands(H, b[None].contiguous(), canvas.rows, tol=tol, precision=precision)
         Q = segment_dots(w_c, X, canvas.rows)[0]

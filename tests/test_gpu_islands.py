@@ -51,12 +51,13 @@ def _canvas_system(geoms, nrhs, fill_psi=1.0):
     return canvas, asm_c, B
 
 
-def test_islands_against_oracle_direct_solves():
+@pytest.mark.parametrize("island_hierarchy", [True, False])
+def test_islands_against_oracle_direct_solves(island_hierarchy):
     geoms = _stars([48, 64, 80], seed=3)
     nrhs = 2
     canvas, asm_c, B = _canvas_system(geoms, nrhs)
-    print(f"[gpu] islands 3 x {nrhs}, canvas {canvas.grid.shape}", flush=True)
-    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    print(f"[gpu] islands 3 x {nrhs}, canvas {canvas.grid.shape}, island hierarchy {island_hierarchy}", flush=True)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows if island_hierarchy else None)
     assert H.n_levels > 1
     X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-13)
     kinds = canvas.unpack(asm_c.kind.cpu().numpy())
@@ -84,7 +85,7 @@ def test_islands_against_oracle_direct_solves():
 def test_single_island_matches_batched_solve(precision):
     (g, psi), = _stars([200], seed=5)
     canvas, asm_c, B = _canvas_system([(g, psi)], 3)
-    Hc = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    Hc = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
     Xc, ic = S.solve_islands(Hc, B, canvas.rows, tol=1e-12, precision=precision)
     asm_g = S.assemble_diag(g, to_dev(psi))
     zero = torch.zeros(asm_g.n_cuts, dtype=torch.float64, device=asm_g.kind.device)
@@ -104,7 +105,7 @@ def test_island_edge_cases():
     empty = W.unit_box_grid(2, 24)
     geoms.insert(1, (empty, np.ones(empty.shape)))          # an island with no unknowns
     canvas, asm_c, B = _canvas_system(geoms, 2)
-    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
     X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-10)
     assert all(i["iterations"] == 0 and i["status"] == 0 for i in infos[1])
     assert not torch.any(X[:, int(canvas.rows[1]):int(canvas.rows[2])]).item()
@@ -135,7 +136,7 @@ def test_shape_optimisation_batch_sample():
     geoms = _stars(sizes, seed=13)
     canvas, asm_c, B = _canvas_system(geoms, 4)
     print(f"[gpu] islands 24 x 4, canvas {canvas.grid.shape}", flush=True)
-    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
     X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-8)
     its = [i["iterations"] for row in infos for i in row]
     print(f"  levels {H.n_levels}, iterations {min(its)}..{max(its)}", flush=True)
@@ -174,7 +175,7 @@ def test_island_iteration_graphs_match_kernel_launches():
     solutions and iteration counts as launching kernel by kernel."""
     geoms = _stars([64, 96, 128], seed=13)
     canvas, asm_c, B = _canvas_system(geoms, 4)
-    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
     try:
         S.set_iteration_graphs(False)
         X0, i0 = S.solve_islands(H, B, canvas.rows, tol=1e-10)
@@ -211,4 +212,57 @@ def test_island_rhs_scales_each_source_by_its_h2():
     bad = SimpleNamespace(rows=canvas.rows[:-1], h=canvas.h[:-1])
     with pytest.raises(L.EbError) as ei:
         S.assemble_rhs_islands(asm_c, bad, to_dev(canvas.pack(src)), u)
+    assert ei.value.code == L.EB_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_island_hierarchy_iterations_match_single_geometries(precision):
+    """Each island's part of the island hierarchy ends where its own
+    hierarchy would and smooths with its own weight, so every (island, rhs)
+    takes the iterations of the same geometry solved alone (allowed: one
+    more or less, from rounding; measured: equal), including islands whose
+    own hierarchy has fewer levels than the others'."""
+    rng = np.random.default_rng(21)
+    sizes = [int(rng.choice([256, 384, 512, 768])) for _ in range(10)] + [160, 1024]
+    geoms = _stars(sizes, seed=23)
+    canvas, asm_c, B = _canvas_system(geoms, 2)
+    H = S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
+    X, infos = S.solve_islands(H, B, canvas.rows, tol=1e-8, precision=precision)
+    print(f"[gpu] island hierarchy {len(geoms)} islands, {H.n_levels} levels", flush=True)
+    xs = canvas.unpack(X.cpu().numpy())
+    worst = 0
+    for i, (g, psi) in enumerate(geoms):
+        asm_g = S.assemble_diag(g, to_dev(psi))
+        zero = torch.zeros(asm_g.n_cuts, dtype=torch.float64, device=asm_g.kind.device)
+        Bg = torch.stack([S.assemble_rhs(asm_g, to_dev(_sources(g, j)), zero) for j in range(2)]).contiguous()
+        Hg = S.Hierarchy(g, asm_g.kind, asm_g.a, 0.0)
+        Xg, ig = Hg.solve_batched(Bg, tol=1e-8, precision=precision)
+        for j in range(2):
+            a, b = infos[i][j]["iterations"], ig[j]["iterations"]
+            print(f"  island {i} (N = {sizes[i]}, {Hg.n_levels} levels) rhs {j}: {a} vs alone {b}", flush=True)
+            worst = max(worst, abs(a - b))
+            assert infos[i][j]["status"] == 0 and infos[i][j]["rel_res_true"] <= 1e-8
+            assert rel(xs[i][j].ravel(), Xg[j].cpu().numpy().ravel()) <= 1e-6
+        Hg.free()
+    assert worst <= 1
+    H.free()
+
+
+def test_island_hierarchy_refuses_misaligned_islands():
+    # islands that do not start on a multiple of 3^l cannot end as one row
+    # range on level l
+    # two disks reaching to 3 node rows from their boxes' edges, stacked
+    # without alignment: their coarse unknowns share box rows
+    geoms = []
+    for n in (256, 256):
+        g = W.unit_box_grid(2, n)
+        geoms.append((g, W.psi_disk(g, center=(0.0, 0.0), radius=0.5 - 2.5 / n)))
+    canvas = S.stack_islands([g for g, _ in geoms], align=1)
+    psi_c = canvas.pack([p for _, p in geoms], fill=1.0)
+    asm_c = S.assemble_diag(canvas.grid, to_dev(psi_c))
+    with pytest.raises(L.EbError) as ei:
+        S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=canvas.rows)
+    assert ei.value.code == L.EB_EINVAL
+    with pytest.raises(L.EbError) as ei:
+        S.Hierarchy(canvas.grid, asm_c.kind, asm_c.a, 0.0, islands=np.array([0, 5], dtype=np.int32))
     assert ei.value.code == L.EB_EINVAL

@@ -1205,13 +1205,29 @@ __global__ void __launch_bounds__(BLOCK) k_island0(const int64_t* __restrict__ n
 }
 
 // Per island: row count, first and last row of this level (cnt, first, last
-// pre-set to 0, INT_MAX, -1).
+// pre-set to 0, INT_MAX, -1).  Islands are row ranges, so nearly every wave
+// lies in one island: such a wave makes one update per counter instead of 64
+// on the same address.
 __global__ void __launch_bounds__(BLOCK) k_island_stats(const int32_t* __restrict__ isl, int64_t n,
                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ first,
                                                         int32_t* __restrict__ last) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int32_t b = isl[i];
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t i0 = i - lane;                      // the wave's first row
+    if (i0 >= n) return;                              // the whole wave is past the end
+    const bool ok = i < n;                            // a prefix of the wave's lanes
+    const int32_t b = ok ? isl[i] : -1;
+    const int32_t b0 = __shfl(b, 0);
+    if (__all(!ok || b == b0)) {
+        if (lane == 0) {
+            const int32_t k = (int32_t)(n - i0 < 64 ? n - i0 : 64);
+            atomicAdd(&cnt[b0], k);
+            atomicMin(&first[b0], (int32_t)i0);
+            atomicMax(&last[b0], (int32_t)i0 + k - 1);
+        }
+        return;
+    }
+    if (!ok) return;
     atomicAdd(&cnt[b], 1);
     atomicMin(&first[b], (int32_t)i);
     atomicMax(&last[b], (int32_t)i);
@@ -1227,14 +1243,29 @@ __global__ void __launch_bounds__(BLOCK) k_island_next(const int32_t* __restrict
 }
 
 // Each island's own Gershgorin bound on this level: the largest row bound of
-// its rows (bit patterns of non-negative doubles order like the values).
+// its rows (bit patterns of non-negative doubles order like the values).  A
+// wave whose rows all lie in one island takes its maximum in registers and
+// makes one update.
 __global__ void __launch_bounds__(BLOCK) k_island_rho(const double* __restrict__ rowv,
                                                       const int32_t* __restrict__ isl,
                                                       const int8_t* __restrict__ frz, int64_t n,
                                                       unsigned long long* __restrict__ rho_isl) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n || (frz && frz[i])) return;
-    atomicMax(&rho_isl[isl[i]], (unsigned long long)__double_as_longlong(rowv[i]));
+    const int lane = (int)(threadIdx.x & 63);
+    if (i - lane >= n) return;                        // the whole wave is past the end
+    const bool ok = i < n && !(frz && frz[i]);
+    const int32_t b = ok ? isl[i] : -1;
+    double v = ok ? rowv[i] : 0.0;
+    const unsigned long long m = __ballot(ok);
+    if (m == 0) return;
+    const int lead = __ffsll((long long)m) - 1;       // the first lane with a row
+    const int32_t bl = __shfl(b, lead);
+    if (__all(!ok || b == bl)) {
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if (lane == lead) atomicMax(&rho_isl[bl], (unsigned long long)__double_as_longlong(v));
+        return;
+    }
+    if (ok) atomicMax(&rho_isl[b], (unsigned long long)__double_as_longlong(v));
 }
 
 // The smoothers and the prolongator of a level take omega / d: scaling the
@@ -1288,6 +1319,7 @@ struct ReportArgs {
     const int32_t* p_tot[MAX_LEVELS];
     const int32_t* r_tot[MAX_LEVELS];
     const int32_t* ra_tot[MAX_LEVELS];
+    const int32_t* sell_w[3 * MAX_LEVELS];   // widths of the sliced A, P, A P
     const double* scal;      // 2 * MAX_LEVELS
     const int32_t* counts;   // 3
     const int32_t* stat;     // 4 (SetupStat)
@@ -1295,6 +1327,7 @@ struct ReportArgs {
 
 struct ReportBlock {
     int64_t nnz[4 * MAX_LEVELS];
+    int32_t sell_w[3 * MAX_LEVELS];
     double scal[2 * MAX_LEVELS];
     int32_t counts[3];
     int32_t stat[4];
@@ -1307,6 +1340,7 @@ __global__ void k_report(ReportArgs R, ReportBlock* __restrict__ out) {
         out->nnz[4 * l + 1] = R.p_tot[l] ? *R.p_tot[l] : 0;
         out->nnz[4 * l + 2] = R.r_tot[l] ? *R.r_tot[l] : 0;
         out->nnz[4 * l + 3] = R.ra_tot[l] ? *R.ra_tot[l] : 0;
+        for (int m = 0; m < 3; ++m) out->sell_w[3 * l + m] = R.sell_w[3 * l + m] ? *R.sell_w[3 * l + m] : 0;
     }
     if (l < 2 * MAX_LEVELS) out->scal[l] = R.scal[l];
     if (l < 3) out->counts[l] = R.counts[l];
@@ -1452,25 +1486,22 @@ struct RowSrc {
     __device__ int32_t len(int64_t r) const { return rowptr ? rowptr[r + 1] - rowptr[r] : cnt[r]; }
 };
 
-// entries of each slice: 64 x its longest row (one lane per row, the
-// slice's maximum across its wavefront)
-__global__ void __launch_bounds__(BLOCK) k_sell_width(RowSrc M, int64_t n, int64_t nslices,
-                                                      int32_t* __restrict__ slice_entries) {
+// The longest row (*width pre-set to 0): each wavefront's maximum, then one
+// atomic per wavefront.
+__global__ void __launch_bounds__(BLOCK) k_sell_width(RowSrc M, int64_t n, int32_t* __restrict__ width) {
     const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     int32_t w = r < n ? M.len(r) : 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, WAVE));
-    const int64_t sl = r / 64;
-    if ((threadIdx.x & (WAVE - 1)) == 0 && sl < nslices) slice_entries[sl] = 64 * w;
+    if ((threadIdx.x & (WAVE - 1)) == 0 && w > 0) atomicMax(width, w);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_sell_fill(RowSrc M, int64_t n, const int32_t* __restrict__ sptr,
+__global__ void __launch_bounds__(BLOCK) k_sell_fill(RowSrc M, int64_t n, const int32_t* __restrict__ width,
                                                      int32_t* __restrict__ col, double* __restrict__ val) {
     const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (r >= n) return;
-    const int64_t sl = r / 64;
-    const int32_t base = sptr[sl] + (int32_t)(r % 64);
-    const int32_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+    const int32_t w = *width;
+    const int32_t base = (int32_t)(r / 64) * 64 * w + (int32_t)(r % 64);
     const int32_t f = M.first(r), m = M.len(r);
     int32_t last = 0;
     for (int32_t k = 0; k < w; ++k) {
@@ -1509,7 +1540,8 @@ __global__ void __launch_bounds__(BLOCK) k_trs_fill(RowSrc M, int64_t n, const i
 }
 
 // Sliced ELL copy of an n-row matrix whose rows have at most `bound` entries
-// (storage sized by the bound: no host synchronisation).
+// (storage sized by the bound, the width found on the device: no host
+// synchronisation; the host learns the width from the setup's final report).
 static int build_sell(const RowSrc& M, int64_t n, int64_t bound, Sell* out, hipStream_t s) {
     const int64_t nslices = (n + 63) / 64;
     out->cap = nslices * 64 * (bound > 0 ? bound : 1);
@@ -1517,18 +1549,19 @@ static int build_sell(const RowSrc& M, int64_t n, int64_t bound, Sell* out, hipS
         set_error("a sliced matrix bound exceeds 2^31 entries");
         return EB_ENOSPC;
     }
-    int32_t* ent = nullptr;
-    EB_TRY(dalloc_n(&ent, nslices, s));
-    EB_TRY(dalloc_n(&out->sptr, nslices + 1, s));
+    EB_TRY(dalloc_n(&out->wdev, 1, s));
     EB_TRY(dalloc_n(&out->col, out->cap, s));
     EB_TRY(dalloc_n(&out->val, out->cap, s));
-    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(nslices * 64)), dim3(BLOCK), 0, s, M, n, nslices, ent);
-    EB_LAUNCH_CHECK();
-    EB_TRY(scan_i32_dev(ent, out->sptr, nslices, out->sptr + nslices, s));
-    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, (const int32_t*)out->sptr,
-                       out->col, out->val);
-    EB_LAUNCH_CHECK();
-    EB_TRY(dfree(ent, s));
+    {
+        const FillSpec f[] = {{out->wdev, sizeof(int32_t), 0u}};
+        EB_TRY(fill_words(f, 1, s));
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sell_width, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, out->wdev);
+        hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, (const int32_t*)out->wdev,
+                           out->col, out->val);
+        EB_LAUNCH_CHECK();
+    }
     return EB_OK;
 }
 
@@ -1839,7 +1872,7 @@ static void free_level(Level& L, hipStream_t s) {
                     L.sv, L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
     for (void* p : ptrs) (void)dfree(p, s);
     for (Sell* m : {&L.sa, &L.sp, &L.sap}) {
-        void* q[] = {m->sptr, m->col, m->val, m->val32};
+        void* q[] = {m->wdev, m->col, m->val, m->val32};
         for (void* p : q) (void)dfree(p, s);
     }
     {
@@ -2099,6 +2132,9 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
             R.r_tot[k] = L.r_rowptr + H->lev[k + 1].n;
             if (L.ra_rowptr) R.ra_tot[k] = L.ra_rowptr + H->lev[k + 1].n;
         }
+        R.sell_w[3 * k + 0] = L.sa.wdev;
+        R.sell_w[3 * k + 1] = L.sp.wdev;
+        R.sell_w[3 * k + 2] = L.sap.wdev;
     }
     R.scal = H->dscal;
     R.counts = H->dcount;
@@ -2122,6 +2158,9 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         L.nnz_p = rep.nnz[4 * k + 1];
         L.nnz_r = rep.nnz[4 * k + 2];
         L.nnz_ap = rep.nnz[4 * k + 3];
+        L.sa.width = rep.sell_w[3 * k + 0];
+        L.sp.width = rep.sell_w[3 * k + 1];
+        L.sap.width = rep.sell_w[3 * k + 2];
         if (!L.is_coarsest) {
             L.rho = rep.scal[2 * k];
             L.omega = rep.scal[2 * k + 1];

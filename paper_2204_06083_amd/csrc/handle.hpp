@@ -8,18 +8,21 @@ namespace eb {
 
 constexpr int MAX_LEVELS = 24;
 
-// Sliced ELL copy of a sparse matrix for the V-cycle: slices of 64
-// consecutive rows (one wavefront, one lane per row), each stored slot-major
-// with the width of its longest row: entry k of row r sits at
-// sptr[r / 64] + 64 k + r % 64.  Rows shorter than their slice are padded
-// with value 0 and the row's last column (column 0 for an empty row), so every
-// read is in bounds and adds nothing.
+// ELL copy of a sparse matrix for the V-cycle in slices of 64 consecutive
+// rows (one wavefront, one lane per row), each stored slot-major, every row
+// padded to the width w of the matrix's longest row: entry k of row r sits at
+// 64 (w (r / 64) + k) + r % 64, so a kernel finds it from r and w alone (no
+// offset table to read first).  Padding has value 0 and the row's last column
+// (column 0 for an empty row), so every read is in bounds and adds nothing.
+// On the coarse levels of the box aggregation the widths are nearly uniform
+// (2-D: A 9, P 4, A P 9 on most rows).
 struct Sell {
-    int32_t* sptr = nullptr;   // nslices + 1 entry offsets
+    int32_t* wdev = nullptr;   // w on the device (set by the setup kernels)
     int32_t* col = nullptr;
     double* val = nullptr;
     float* val32 = nullptr;    // single-precision V-cycle copy (made on first use)
-    int64_t cap = 0;           // entries allocated (a bound on sptr[nslices])
+    int64_t cap = 0;           // entries allocated (a bound on 64 w nslices)
+    int width = 0;             // w on the host (read back at the end of setup)
 };
 
 struct Level {

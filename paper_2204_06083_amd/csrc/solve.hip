@@ -324,11 +324,9 @@ __global__ void __launch_bounds__(NT) k_pcg_xr(FineArgs f, double* __restrict__ 
     block_partial(part, part_rr);
 }
 
-// Convergence test on ||r||^2 (partials of the previous kernel); true if the
-// caller must return.  BS is the caller's block size.
-template <int BS = NT>
-__device__ inline bool converged_or_failed(const double* __restrict__ part_rr, int np, PcgScalars* sc) {
-    const double rr = block_total<BS>(part_rr, np);
+// Convergence test on a total ||r||^2 already formed; true if the caller
+// must return.
+__device__ inline bool converged_or_failed_total(double rr, PcgScalars* sc) {
     if (bad_value(rr)) {
         if (lead()) {
             sc->status = EB_ENAN;
@@ -342,6 +340,14 @@ __device__ inline bool converged_or_failed(const double* __restrict__ part_rr, i
         return true;
     }
     return false;
+}
+
+// Convergence test on ||r||^2 (partials of the previous kernel); true if the
+// caller must return.  BS is the caller's block size.
+template <int BS = NT>
+__device__ inline bool converged_or_failed(const double* __restrict__ part_rr, int np, PcgScalars* sc) {
+    const double rr = block_total<BS>(part_rr, np);
+    return converged_or_failed_total(rr, sc);
 }
 
 // ------------------------------------------------------------ fine V-cycle
@@ -765,10 +771,20 @@ __device__ inline TileLane tile_lane(const TileArgs& t) {
     return L;
 }
 
-__device__ inline void tile_origin(const TileArgs& t, int64_t tix, int* x0, int* y0) {
-    const int tid = __builtin_amdgcn_readfirstlane(t.tiles[tix]);
+__device__ inline void tile_origin_of(const TileArgs& t, int tid, int* x0, int* y0) {
+    tid = __builtin_amdgcn_readfirstlane(tid);
     *x0 = (tid % t.ntx) * TX;
     *y0 = (tid / t.ntx) * TY;
+}
+
+__device__ inline void tile_origin(const TileArgs& t, int64_t tix, int* x0, int* y0) {
+    tile_origin_of(t, t.tiles[tix], x0, y0);
+}
+
+// The wavefront's first tile id, read at the kernel's start beside the
+// partial sums it reduces (0 when the wavefront has no tile).
+__device__ inline int first_tile(const TileArgs& t, const TileLane& L) {
+    return L.t0 < L.t1 ? t.tiles[L.t0] : 0;
 }
 
 // p = z + beta p_old on the tile and its halo rows, q = A p on the tile;
@@ -779,10 +795,15 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
                                                   double* __restrict__ q, const double* __restrict__ rz_cur,
                                                   const double* __restrict__ rz_prev, int np,
                                                   double* __restrict__ part_pq, PcgScalars* sc) {
-    if (sc->done) return;
+    // the flag and the first tile are read with the partials (one round trip);
+    // nothing is stored once the solve is done
+    const int32_t done = sc->done;
+    const TileLane L = tile_lane(t);
+    const int tid0 = first_tile(t, L);
     double rho, rho_prev = 0.0;
     if (rz_prev) block_total2<TNT>(rz_cur, rz_prev, np, &rho, &rho_prev);
     else rho = block_total<TNT>(rz_cur, np);
+    if (done) return;
     const double beta = rz_prev ? rho / rho_prev : 0.0;
     if (!(rho > 0.0) || bad_value(rho) || bad_value(beta)) {
         if (lead()) {
@@ -791,11 +812,10 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
         }
         return;
     }
-    const TileLane L = tile_lane(t);
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
         int x0, y0;
-        tile_origin(t, ti, &x0, &y0);
+        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
         const int xc = x0 - 2 + L.lane;
         const bool xin = xc >= 0 && xc < t.nx;
         const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
@@ -857,11 +877,17 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
                                                         double* __restrict__ part_rr, V* __restrict__ rc,
                                                         const V* __restrict__ dg_c, double omega_c,
                                                         V* __restrict__ sv_c, PcgScalars* sc) {
-    if (sc->done) return;
+    // the flag and the first tile are read with the partials (one round trip);
+    // nothing is stored once the solve is done
+    const int32_t done = sc->done;
+    const TileLane L = tile_lane(t);
+    const int tid0 = first_tile(t, L);
     double alpha = 0.0;
+    if (!UPD && done) return;
     if (UPD) {
         double rho, pq;
         block_total2<TNT>(rz_cur, part_pq, np, &rho, &pq);
+        if (done) return;
         if (!(pq > 0.0) || bad_value(pq)) {
             if (lead()) {
                 sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;
@@ -877,7 +903,6 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
     }
     const double sw = omega * t.s;
     const V wV = (V)omega, swV = (V)sw;
-    const TileLane L = tile_lane(t);
     // a box's lead lane is its left column; lanes 2 .. 61 hold the tile's 20 boxes
     const int bl = L.lane - 2;
     const bool box_lead = bl >= 0 && bl < TX && bl % 3 == 0;
@@ -885,7 +910,7 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
         int x0, y0;
-        tile_origin(t, ti, &x0, &y0);
+        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
         const int xc = x0 - 2 + L.lane;
         const bool xin = xc >= 0 && xc < t.nx;
         const bool inner = xin && bl >= 0 && bl < TX;
@@ -1013,15 +1038,23 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
                                                     std::conditional_t<B16, bf16, V>* __restrict__ z,
                                                     double* __restrict__ part_rz,
                                                     const double* __restrict__ part_rr, int np, PcgScalars* sc) {
-    if (sc->done) return;
-    if (part_rr && converged_or_failed<TNT>(part_rr, np, sc)) return;
+    // the flag and the first tile are read with the partials (one round trip);
+    // nothing is stored once the solve is done
+    const int32_t done = sc->done;
+    const TileLane L = tile_lane(t);
+    const int tid0 = first_tile(t, L);
+    if (part_rr) {
+        const double rr = block_total<TNT>(part_rr, np);
+        if (done || converged_or_failed_total(rr, sc)) return;
+    } else if (done) {
+        return;
+    }
     const V* __restrict__ dinv = tdinv<V>(t);
     const V wV = (V)omega, sV = (V)t.s, swV = (V)(omega * t.s);
-    const TileLane L = tile_lane(t);
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
         int x0, y0;
-        tile_origin(t, ti, &x0, &y0);
+        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
         const int xc = x0 - 2 + L.lane;
         const bool xin = xc >= 0 && xc < t.nx;
         const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
@@ -1304,7 +1337,7 @@ __global__ void __launch_bounds__(NT) k_coarse_up(int64_t n, Csr<V> A, Csr<V> P,
 // gathered, then summed in column order.
 template <class V>
 struct SellV {
-    const int32_t* sptr;
+    int w;   // slots per row (the matrix's longest row)
     const int32_t* col;
     const V* val;
 };
@@ -1318,7 +1351,7 @@ __global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA,
                                                 const V* __restrict__ sv, V* __restrict__ rv_c,
                                                 const V* __restrict__ dg_c, V omega_c, V* __restrict__ sv_c,
                                                 const PcgScalars* sc) {
-    if (sc->done) return;
+    const int32_t done = sc->done;   // read beside the row pointers; tested before the stores
     const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= nc) return;
@@ -1329,30 +1362,49 @@ __global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA,
     for (int br = r0 + lane, bq = q0 + lane; br < r1 || bq < q1; br += UR * LPR, bq += UQ * LPR) {
         int kr[UR], kq[UQ];
         V ar[UR], aq[UQ], xr[UR], xq[UQ];
+        // entries past a row's end read entry 0 and are dropped (column -1),
+        // so the reads carry no branch and go out together
 #pragma unroll
         for (int u = 0; u < UR; ++u) {
             const int e = br + u * LPR;
-            kr[u] = e < r1 ? R.col[e] : -1;
-            ar[u] = e < r1 ? R.val[e] : V(0);
+            const int ei = e < r1 ? e : 0;
+            const int k = R.col[ei];
+            const V a = R.val[ei];
+            kr[u] = e < r1 ? k : -1;
+            ar[u] = e < r1 ? a : V(0);
         }
 #pragma unroll
         for (int u = 0; u < UQ; ++u) {
             const int e = bq + u * LPR;
-            kq[u] = e < q1 ? RA.col[e] : -1;
-            aq[u] = e < q1 ? RA.val[e] : V(0);
+            const int ei = e < q1 ? e : 0;
+            const int k = RA.col[ei];
+            const V a = RA.val[ei];
+            kq[u] = e < q1 ? k : -1;
+            aq[u] = e < q1 ? a : V(0);
         }
 #pragma unroll
-        for (int u = 0; u < UR; ++u) xr[u] = kr[u] >= 0 ? rv[kr[u]] : V(0);
+        for (int u = 0; u < UR; ++u) {
+            const V v = rv[kr[u] >= 0 ? kr[u] : 0];
+            xr[u] = kr[u] >= 0 ? v : V(0);
+        }
 #pragma unroll
-        for (int u = 0; u < UQ; ++u) xq[u] = kq[u] >= 0 ? sv[kq[u]] : V(0);
+        for (int u = 0; u < UQ; ++u) {
+            const V v = sv[kq[u] >= 0 ? kq[u] : 0];
+            xq[u] = kq[u] >= 0 ? v : V(0);
+        }
 #pragma unroll
-        for (int u = 0; u < UR; ++u)
-            if (kr[u] >= 0) acc += ar[u] * xr[u];
+        for (int u = 0; u < UR; ++u) {
+            const V t = acc + ar[u] * xr[u];
+            acc = kr[u] >= 0 ? t : acc;
+        }
 #pragma unroll
-        for (int u = 0; u < UQ; ++u)
-            if (kq[u] >= 0) acc -= aq[u] * xq[u];
+        for (int u = 0; u < UQ; ++u) {
+            const V t = acc - aq[u] * xq[u];
+            acc = kq[u] >= 0 ? t : acc;
+        }
     }
     acc = segment_sum<LPR>(acc);
+    if (done) return;
     if (lane == 0) {
         rv_c[row] = acc;
         if (sv_c) sv_c[row] = omega_c * acc / dg_c[row];
@@ -1360,9 +1412,10 @@ __global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA,
 }
 
 // One row of a sliced matrix in chunks of W slots: slot u of the row is
-// entry sptr[slice] + lane + 64 u; a slice's slot count is uniform over its
-// wavefront.  A chunk's column and value reads are issued together, then its
-// gathers, so a row costs one round trip per chunk rather than per entry.
+// entry 64 (w slice + u) + lane, with w the matrix's width (a launch
+// argument, so no offset is read before the entries).  A chunk's column and
+// value reads are issued together, then its gathers, so a row costs one
+// round trip per chunk rather than per entry.
 template <class V, int W>
 struct SellRow {
     int k[W];
@@ -1376,33 +1429,45 @@ struct SellSpan {
 
 template <class V>
 __device__ inline SellSpan sell_span(const SellV<V>& M, int slice, int lane) {
-    const int b = M.sptr[slice];
-    return {b + lane, (M.sptr[slice + 1] - b) >> 6};
+    return {slice * 64 * M.w + lane, M.w};
 }
 
+// A slot past the slice's width reads entry 0 and is dropped (column -1):
+// no branch, so the reads of all matrices of a pass stay in one block and
+// are issued together (a branch per slot let the compiler defer a matrix's
+// slice pointer until the previous matrix's reads were out).
 template <class V, int W>
 __device__ inline void sell_load(const SellV<V>& M, const SellSpan& sp, int u0, SellRow<V, W>& r) {
 #pragma unroll
     for (int u = 0; u < W; ++u) {
         const bool in = u0 + u < sp.slots;
-        const int e = sp.e0 + 64 * (u0 + u);
-        r.k[u] = in ? M.col[e] : -1;
-        r.a[u] = in ? M.val[e] : V(0);
+        const int e = in ? sp.e0 + 64 * (u0 + u) : 0;
+        const int k = M.col[e];
+        const V a = M.val[e];
+        r.k[u] = in ? k : -1;
+        r.a[u] = in ? a : V(0);
     }
 }
 
+// x at the chunk's columns (a dropped slot reads x[0] and takes 0)
 template <class V, int W>
 __device__ inline void sell_gather(const SellRow<V, W>& r, const V* __restrict__ x, V* xv) {
 #pragma unroll
-    for (int u = 0; u < W; ++u) xv[u] = r.k[u] >= 0 ? x[r.k[u]] : V(0);
+    for (int u = 0; u < W; ++u) {
+        const V v = x[r.k[u] >= 0 ? r.k[u] : 0];
+        xv[u] = r.k[u] >= 0 ? v : V(0);
+    }
 }
 
-// acc + the chunk's products, in slot (column) order
+// acc + the chunk's products, in slot (column) order; dropped slots leave acc
+// as it is
 template <class V, int W>
 __device__ inline V sell_acc(V acc, const SellRow<V, W>& r, const V* xv) {
 #pragma unroll
-    for (int u = 0; u < W; ++u)
-        if (r.k[u] >= 0) acc += r.a[u] * xv[u];
+    for (int u = 0; u < W; ++u) {
+        const V t = acc + r.a[u] * xv[u];
+        acc = r.k[u] >= 0 ? t : acc;
+    }
     return acc;
 }
 
@@ -1416,7 +1481,7 @@ __global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> 
                                                 const V* __restrict__ diag, V omega, const V* __restrict__ rv,
                                                 const V* __restrict__ sv, const V* __restrict__ ev_c,
                                                 V* __restrict__ ev, const PcgScalars* sc) {
-    if (sc->done) return;
+    const int32_t done = sc->done;   // read beside the slice pointers; tested before the store
     const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));
     if (row >= n) return;
@@ -1448,6 +1513,7 @@ __global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> 
         sell_gather(rp, ev_c, xp);
         pe = sell_acc(pe, rp, xp);
     }
+    if (done) return;
     ev[row] = svr + pe + omega * (rvr - as - ape) / dr;
 }
 
@@ -1457,13 +1523,14 @@ template <class V>
 __global__ void __launch_bounds__(NT) k_dense_apply(int64_t n, const double* __restrict__ W,
                                                     const V* __restrict__ rv, V* __restrict__ ev,
                                                     const PcgScalars* sc) {
-    if (sc->done) return;
+    const int32_t done = sc->done;   // read beside the first loads; tested before the store
     const int64_t row = (int64_t)blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (row >= n) return;
     double acc = 0.0;
     for (int64_t j = lane; j < n; j += WAVE) acc += W[row * n + j] * (double)rv[j];
     acc = wave_sum(acc);
+    if (done) return;
     if (lane == 0) ev[row] = (V)acc;
 }
 
@@ -1778,14 +1845,14 @@ template <class V> static LevelView<V> view(const Level& L);
 template <> LevelView<double> view<double>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val}, {L.p_rowptr, L.p_col, L.p_val}, {L.r_rowptr, L.r_col, L.r_val},
             L.diag, L.rv, L.ev, L.tmp, L.sv,
-            {L.sa.sptr, L.sa.col, L.sa.val}, {L.sp.sptr, L.sp.col, L.sp.val}, {L.sap.sptr, L.sap.col, L.sap.val},
+            {L.sa.width, L.sa.col, L.sa.val}, {L.sp.width, L.sp.col, L.sp.val}, {L.sap.width, L.sap.col, L.sap.val},
             {L.ra_rowptr, L.ra_col, L.ra_val}};
 }
 template <> LevelView<float> view<float>(const Level& L) {
     return {{L.a_rowptr, L.a_col, L.a_val32}, {L.p_rowptr, L.p_col, L.p_val32}, {L.r_rowptr, L.r_col, L.r_val32},
             L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32,
-            {L.sa.sptr, L.sa.col, L.sa.val32}, {L.sp.sptr, L.sp.col, L.sp.val32},
-            {L.sap.sptr, L.sap.col, L.sap.val32}, {L.ra_rowptr, L.ra_col, L.ra_val32}};
+            {L.sa.width, L.sa.col, L.sa.val32}, {L.sp.width, L.sp.col, L.sp.val32},
+            {L.sap.width, L.sap.col, L.sap.val32}, {L.ra_rowptr, L.ra_col, L.ra_val32}};
 }
 
 template <class V>

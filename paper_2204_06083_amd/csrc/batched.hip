@@ -1425,9 +1425,11 @@ static int batched_run(amg_handle* H, BatchBufs* B, int nrhs, const pcg_params_t
 // Launch shape of the fine kernels, chosen by timing: on the first solve with
 // a new set of batch buffers, before that solve's timed window opens and
 // before its right-hand sides are loaded, each candidate (plane width 8 or 16,
-// planes per block 1, 2 or 4, within the plane count) runs the two largest
-// fine kernels (p-update and x/r update) once untimed and TUNE_REPS times
-// between HIP events on the batch buffers; the median run decides.  Every
+// planes per block 1, 2 or 4, within the plane count) runs the fine kernels
+// that take the shape (p-update, x/r update, prolongation, post-smoothing)
+// once untimed and TUNE_REPS times between HIP events on the batch buffers;
+// the median run decides.  (Timing the first two alone once chose a shape
+// that made the other two, and the whole FP64 batch, 40 % slower.)  Every
 // system is marked active (alpha = beta = 1) for the timing, so the kernels
 // read and write every slot, as in a solve: their traffic does not depend on
 // the values the buffers hold.  The choice is kept with the buffers and in a
@@ -1496,6 +1498,15 @@ static int autotune_batch(amg_handle* H, BatchBufs* B, hipStream_t s) {
                           (const BatchState*)B->st, B->part[0]);
                 BLAUNCH_V(kb_xr_down, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, B->x, B->rr[0], B->rr[1], B->p[0],
                           B->q, (V*)B->res, H->lev[0].omega, (const BatchState*)B->st, B->part[1]);
+                if (H->nlev > 1) {
+                    // the prolongation and post-smoothing passes take the same shape
+                    unsigned gfull = 0;
+                    const BFine ff = bfine(H, B, true, &gfull);
+                    BLAUNCH_V(kb_fine_up, V, npl_of(ff, B), bgrid(gfull, ff, B), ff, H->lev[0].omega, H->agg_p,
+                              (const V*)B->ev[1], B->rr[1], (V*)B->zt);
+                    BLAUNCH_V(kb_fine_post, V, npl_of(fr, B), bgrid(gfix, fr, B), fr, H->lev[0].omega,
+                              (const V*)B->zt, B->rr[1], (V*)B->z, B->part[2]);
+                }
                 if (hipGetLastError() != hipSuccess || hipEventRecord(b, s) != hipSuccess ||
                     hipEventSynchronize(b) != hipSuccess) {
                     rc = EB_EHIP;
@@ -1528,6 +1539,18 @@ static int autotune_batch(amg_handle* H, BatchBufs* B, hipStream_t s) {
     if (rc != EB_OK) {
         set_error("batched launch-shape autotuner: HIP error");
         return rc;
+    }
+    // The fine kernels read neighbours without a guard and rely on zeros off
+    // the unknowns, but where a slot lies depends on the plane width: values
+    // a candidate wrote at its unknowns can sit off the unknowns of another
+    // width.  Every vector the timed kernels wrote goes back to zero.
+    {
+        const int64_t nv = H->npad * B->kp;
+        const size_t vb = B->prec == EB_PREC_FP32 ? sizeof(float) : sizeof(double);
+        double* dv[] = {B->x, B->p[0], B->p[1], B->rr[0], B->rr[1], B->q};
+        for (double* v : dv) EB_HIP(hipMemsetAsync(v, 0, sizeof(double) * nv, s));
+        void* vv[] = {B->zt, B->z, B->res};
+        for (void* v : vv) EB_HIP(hipMemsetAsync(v, 0, vb * (size_t)nv, s));
     }
     B->kbw = best_w;
     B->npb = best_n;

@@ -289,22 +289,25 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 constexpr int64_t SCAN_DIRECT_TILES = 4096;
 
+constexpr int SCAN_WAVES = BLOCK / WAVE;
+
+// Sum over the block (integers: exact in any order): within each wavefront
+// by lane exchanges, then the wavefront totals through LDS (one barrier).
 template <class T>
 __device__ __forceinline__ T block_sum(T v, T* lds) {
-    lds[threadIdx.x] = v;
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = v;
     __syncthreads();
-    for (int off = BLOCK / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < (unsigned)off) lds[threadIdx.x] += lds[threadIdx.x + off];
-        __syncthreads();
-    }
-    const T r = lds[0];
+    T r = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_WAVES; ++w) r += lds[w];
     __syncthreads();
     return r;
 }
 
 template <class TI, class TO>
 __global__ void __launch_bounds__(BLOCK) k_scan_reduce(const TI* __restrict__ in, int64_t n, TO* __restrict__ sums) {
-    __shared__ TO lds[BLOCK];
+    __shared__ TO lds[SCAN_WAVES];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     TO acc = 0;
 #pragma unroll
@@ -322,7 +325,7 @@ template <class TI, class TO, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in, TO* __restrict__ out, int64_t n,
                                                       const TO* __restrict__ tile_val, int64_t ntiles,
                                                       TO* __restrict__ total) {
-    __shared__ TO lds[BLOCK];
+    __shared__ TO lds[SCAN_WAVES];
     TO offset = 0;
     if (MODE == 1) {
         TO acc = 0;
@@ -341,22 +344,30 @@ __global__ void __launch_bounds__(BLOCK) k_scan_tiles(const TI* __restrict__ in,
         v[i] = run;
         run += x;
     }
-    lds[threadIdx.x] = run;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of thread totals
-    for (int off = 1; off < BLOCK; off <<= 1) {
-        const TO t = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : (TO)0;
-        __syncthreads();
-        lds[threadIdx.x] += t;
-        __syncthreads();
+    // inclusive scan of the thread totals within the wavefront (lane
+    // exchanges), then the wavefront totals through LDS
+    const int lane = (int)(threadIdx.x & (WAVE - 1)), wv = (int)(threadIdx.x / WAVE);
+    TO inc = run;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const TO y = __shfl_up(inc, off, WAVE);
+        if (lane >= off) inc += y;
     }
-    const TO prefix = offset + (threadIdx.x > 0 ? lds[threadIdx.x - 1] : (TO)0);
+    if (lane == WAVE - 1) lds[wv] = inc;
+    __syncthreads();
+    TO before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_WAVES; ++w) {
+        if (w < wv) before += lds[w];
+        all += lds[w];
+    }
+    const TO prefix = offset + before + (inc - run);
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         const int64_t idx = base + i;
         if (idx < n) out[idx] = v[i] + prefix;
     }
-    if (threadIdx.x == BLOCK - 1 && (int64_t)blockIdx.x == ntiles - 1) *total = offset + lds[BLOCK - 1];
+    if (threadIdx.x == BLOCK - 1 && (int64_t)blockIdx.x == ntiles - 1) *total = offset + all;
 }
 
 template <class TI, class TO>

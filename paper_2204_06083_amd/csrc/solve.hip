@@ -163,7 +163,8 @@ __device__ inline void block_partial(double v, double* __restrict__ part) {
 // Sum of np partials in a fixed order; every thread of the block gets it.
 // Thread t adds part[t], part[t + BS], ... in that order; the loads of a
 // round of TOT_U of them are issued together (one memory latency per round,
-// not per partial).
+// not per partial), without a branch (an index past np reads part[0] and is
+// not added), so they also go out together with reads issued before them.
 constexpr int TOT_U = 4;
 
 template <int BS>
@@ -174,24 +175,54 @@ __device__ inline double thread_partials(const double* __restrict__ part, int np
 #pragma unroll
         for (int u = 0; u < TOT_U; ++u) {
             const int i = i0 + u * BS + (int)threadIdx.x;
-            v[u] = i < np ? part[i] : 0.0;
+            v[u] = part[i < np ? i : 0];
         }
 #pragma unroll
-        for (int u = 0; u < TOT_U; ++u)
-            if (i0 + u * BS + (int)threadIdx.x < np) a += v[u];
+        for (int u = 0; u < TOT_U; ++u) {
+            const double t = a + v[u];
+            a = i0 + u * BS + (int)threadIdx.x < np ? t : a;
+        }
     }
     return a;
 }
 
+// The same for two arrays of np partials, their reads issued together.
+template <int BS>
+__device__ inline void thread_partials2(const double* __restrict__ pa, const double* __restrict__ pb, int np,
+                                        double* a, double* b) {
+    double sa = 0.0, sb = 0.0;
+    for (int i0 = 0; i0 < np; i0 += BS * TOT_U) {
+        double va[TOT_U], vb[TOT_U];
+#pragma unroll
+        for (int u = 0; u < TOT_U; ++u) {
+            const int i = i0 + u * BS + (int)threadIdx.x;
+            va[u] = pa[i < np ? i : 0];
+            vb[u] = pb[i < np ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < TOT_U; ++u) {
+            const bool in = i0 + u * BS + (int)threadIdx.x < np;
+            const double ta = sa + va[u], tb = sb + vb[u];
+            sa = in ? ta : sa;
+            sb = in ? tb : sb;
+        }
+    }
+    *a = sa;
+    *b = sb;
+}
+
+// The block's total: wavefront sums, then every thread adds the wavefront
+// sums in wavefront order (the same value in every thread, one barrier
+// before and one after).
 template <int BS = NT>
 __device__ inline double block_total(const double* __restrict__ part, int np) {
     __shared__ double lds[BS / WAVE];
-    __shared__ double tot;
-    double a = thread_partials<BS>(part, np);
-    a = block_sum<BS>(a, lds);
-    if (threadIdx.x == 0) tot = a;
+    const double a = wave_sum(thread_partials<BS>(part, np));
+    if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = a;
     __syncthreads();
-    const double r = tot;
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < BS / WAVE; ++i) r += lds[i];
     __syncthreads();
     return r;
 }
@@ -202,32 +233,25 @@ template <int BS = NT>
 __device__ inline void block_total2(const double* __restrict__ pa, const double* __restrict__ pb, int np,
                                     double* ta, double* tb) {
     __shared__ double lds[2][BS / WAVE];
-    __shared__ double tot[2];
-    double a = thread_partials<BS>(pa, np);
-    double b = thread_partials<BS>(pb, np);
+    double a, b;
+    thread_partials2<BS>(pa, pb, np, &a, &b);
     a = wave_sum(a);
     b = wave_sum(b);
-    const int lane = threadIdx.x & (WAVE - 1);
     const int w = threadIdx.x / WAVE;
-    if (lane == 0) {
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
         lds[0][w] = a;
         lds[1][w] = b;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double x = 0.0, y = 0.0;
+    double x = 0.0, y = 0.0;
 #pragma unroll
-        for (int i = 0; i < BS / WAVE; ++i) {
-            x += lds[0][i];
-            y += lds[1][i];
-        }
-        tot[0] = x;
-        tot[1] = y;
+    for (int i = 0; i < BS / WAVE; ++i) {
+        x += lds[0][i];
+        y += lds[1][i];
     }
     __syncthreads();
-    *ta = tot[0];
-    *tb = tot[1];
-    __syncthreads();
+    *ta = x;
+    *tb = y;
 }
 
 __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -795,11 +819,26 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
                                                   double* __restrict__ q, const double* __restrict__ rz_cur,
                                                   const double* __restrict__ rz_prev, int np,
                                                   double* __restrict__ part_pq, PcgScalars* sc) {
-    // the flag and the first tile are read with the partials (one round trip);
-    // nothing is stored once the solve is done
+    // the flag and the first tile are read with the partials; the first
+    // tile's first two rows are read before the partials are reduced, so
+    // their latency overlaps the reduction (a wavefront without a tile reads
+    // tile 0's and drops them); nothing is stored once the solve is done
     const int32_t done = sc->done;
     const TileLane L = tile_lane(t);
-    const int tid0 = first_tile(t, L);
+    int x0, y0;
+    tile_origin_of(t, first_tile(t, L), &x0, &y0);
+    int xc = x0 - 2 + L.lane;
+    bool xin = xc >= 0 && xc < t.nx;
+    auto row = [&](int j, double& d, double& zz, double& pp) {
+        const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY;
+        const uint32_t pn = xc + t.sy * j;
+        d = ldz(t.diag, ok, pn);
+        zz = to_f64(ldz(z, ok, pn));
+        pp = ldz(pold, ok, pn);
+    };
+    double d0, z0, p0, d1, z1, p1;     // rows j, j + 1 (read ahead)
+    row(y0 - 1, d0, z0, p0);
+    row(y0, d1, z1, p1);
     double rho, rho_prev = 0.0;
     if (rz_prev) block_total2<TNT>(rz_cur, rz_prev, np, &rho, &rho_prev);
     else rho = block_total<TNT>(rz_cur, np);
@@ -814,21 +853,14 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
     }
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
-        int x0, y0;
-        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
-        const int xc = x0 - 2 + L.lane;
-        const bool xin = xc >= 0 && xc < t.nx;
+        if (ti > L.t0) {
+            tile_origin(t, ti, &x0, &y0);
+            xc = x0 - 2 + L.lane;
+            xin = xc >= 0 && xc < t.nx;
+            row(y0 - 1, d0, z0, p0);
+            row(y0, d1, z1, p1);
+        }
         const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
-        auto row = [&](int j, double& d, double& zz, double& pp) {
-            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY;
-            const uint32_t pn = xc + t.sy * j;
-            d = ldz(t.diag, ok, pn);
-            zz = to_f64(ldz(z, ok, pn));
-            pp = ldz(pold, ok, pn);
-        };
-        double d0, z0, p0, d1, z1, p1;     // rows j, j + 1 (read ahead)
-        row(y0 - 1, d0, z0, p0);
-        row(y0, d1, z1, p1);
         double pa = 0.0, pb = 0.0, da = 0.0;   // p of rows j - 2, j - 1; d of row j - 1
         // fully unrolled: the rows in flight are never copied between
         // registers, so no read waits before the row that uses it
@@ -877,11 +909,54 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
                                                         double* __restrict__ part_rr, V* __restrict__ rc,
                                                         const V* __restrict__ dg_c, double omega_c,
                                                         V* __restrict__ sv_c, PcgScalars* sc) {
-    // the flag and the first tile are read with the partials (one round trip);
-    // nothing is stored once the solve is done
+    // the flag and the first tile are read with the partials; the first
+    // tile's first rows and box row are read before the partials are
+    // reduced, so their latency overlaps the reduction (a wavefront without a
+    // tile reads tile 0's and drops them); nothing is stored once the solve
+    // is done
     const int32_t done = sc->done;
     const TileLane L = tile_lane(t);
-    const int tid0 = first_tile(t, L);
+    // a box's lead lane is its left column; lanes 2 .. 61 hold the tile's 20 boxes
+    const int bl = L.lane - 2;
+    const bool box_lead = bl >= 0 && bl < TX && bl % 3 == 0;
+    const int ox = bl >= 0 ? bl % 3 : 0;
+    int x0, y0;
+    tile_origin_of(t, first_tile(t, L), &x0, &y0);
+    int xc = x0 - 2 + L.lane;
+    bool xin = xc >= 0 && xc < t.nx;
+    bool inner = xin && bl >= 0 && bl < TX;
+    int bx = xc >= 0 ? xc / 3 : 0;
+    // one row of a lane: 1 / d, r_in, q (UPD); LW: weight, d; the tile's
+    // own rows also x and p (UPD)
+    struct Row { double iv, r, q, w, d, x, p; };
+    auto row = [&](int j, Row& R) {
+        const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
+        const bool own = ok && inner && j >= y0 && j < y0 + TY;
+        const uint32_t pn = xc + t.sy * j;
+        R.iv = ldz(t.dinv, ok, pn);
+        R.r = ldz(rin, ok, pn);
+        R.q = UPD ? ldz(q, ok, pn) : 0.0;
+        R.w = LW ? ldz(t.wf, ok, pn) : 0.0;
+        R.d = LW ? ldz(t.diag, ok, pn) : 0.0;
+        R.x = UPD ? ldz((const double*)x, own, pn) : 0.0;
+        R.p = UPD ? ldz(pv, own, pn) : 0.0;
+    };
+    // box row of the lane's box: aggregate count, first aggregate, node
+    // map and omega_c / d_c of the first aggregate (read a box row ahead)
+    auto boxrow = [&](int by, int& m, int& c0, int& map, V& w0) {
+        const bool ok = inner && by < b.nby && bx < b.nbx;
+        const uint32_t box = by * b.nbx + bx;
+        m = ldz(b.ncomp, ok, box);
+        c0 = ldz(b.cstart, ok, box);
+        map = ldz(b.map, ok, box);
+        w0 = ldz(vbw0<V>(b), ok, box);
+    };
+    Row R0, R1;                          // rows j, j + 1 (read ahead)
+    row(y0 - 2, R0);
+    row(y0 - 1, R1);
+    int bm, bc0, bmap;
+    V bw0;
+    boxrow(y0 / 3, bm, bc0, bmap, bw0);
     double alpha = 0.0;
     if (!UPD && done) return;
     if (UPD) {
@@ -903,49 +978,18 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
     }
     const double sw = omega * t.s;
     const V wV = (V)omega, swV = (V)sw;
-    // a box's lead lane is its left column; lanes 2 .. 61 hold the tile's 20 boxes
-    const int bl = L.lane - 2;
-    const bool box_lead = bl >= 0 && bl < TX && bl % 3 == 0;
-    const int ox = bl >= 0 ? bl % 3 : 0;
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
-        int x0, y0;
-        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
-        const int xc = x0 - 2 + L.lane;
-        const bool xin = xc >= 0 && xc < t.nx;
-        const bool inner = xin && bl >= 0 && bl < TX;
-        const int bx = xc >= 0 ? xc / 3 : 0;
-        // one row of a lane: 1 / d, r_in, q (UPD); LW: weight, d; the tile's
-        // own rows also x and p (UPD)
-        struct Row { double iv, r, q, w, d, x, p; };
-        auto row = [&](int j, Row& R) {
-            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
-            const bool own = ok && inner && j >= y0 && j < y0 + TY;
-            const uint32_t pn = xc + t.sy * j;
-            R.iv = ldz(t.dinv, ok, pn);
-            R.r = ldz(rin, ok, pn);
-            R.q = UPD ? ldz(q, ok, pn) : 0.0;
-            R.w = LW ? ldz(t.wf, ok, pn) : 0.0;
-            R.d = LW ? ldz(t.diag, ok, pn) : 0.0;
-            R.x = UPD ? ldz((const double*)x, own, pn) : 0.0;
-            R.p = UPD ? ldz(pv, own, pn) : 0.0;
-        };
-        // box row of the lane's box: aggregate count, first aggregate, node
-        // map and omega_c / d_c of the first aggregate (read a box row ahead)
-        auto boxrow = [&](int by, int& m, int& c0, int& map, V& w0) {
-            const bool ok = inner && by < b.nby && bx < b.nbx;
-            const uint32_t box = by * b.nbx + bx;
-            m = ldz(b.ncomp, ok, box);
-            c0 = ldz(b.cstart, ok, box);
-            map = ldz(b.map, ok, box);
-            w0 = ldz(vbw0<V>(b), ok, box);
-        };
-        Row R0, R1;                          // rows j, j + 1 (read ahead)
-        row(y0 - 2, R0);
-        row(y0 - 1, R1);
-        int bm, bc0, bmap;
-        V bw0;
-        boxrow(y0 / 3, bm, bc0, bmap, bw0);
+        if (ti > L.t0) {
+            tile_origin(t, ti, &x0, &y0);
+            xc = x0 - 2 + L.lane;
+            xin = xc >= 0 && xc < t.nx;
+            inner = xin && bl >= 0 && bl < TX;
+            bx = xc >= 0 ? xc / 3 : 0;
+            row(y0 - 2, R0);
+            row(y0 - 1, R1);
+            boxrow(y0 / 3, bm, bc0, bmap, bw0);
+        }
         // rolling rows: z1 (j-2, j-1), r (j-1), 1 / d (j-2, j-1), d (j-1),
         // res (j-2), v (j-3, j-2), column sums per aggregate of the box row
         double za = 0.0, zb = 0.0, rb = 0.0, ia = 0.0, ib = 0.0, dbb = 0.0;
@@ -1038,44 +1082,53 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
                                                     std::conditional_t<B16, bf16, V>* __restrict__ z,
                                                     double* __restrict__ part_rz,
                                                     const double* __restrict__ part_rr, int np, PcgScalars* sc) {
-    // the flag and the first tile are read with the partials (one round trip);
-    // nothing is stored once the solve is done
+    // the flag and the first tile are read with the partials; the first
+    // tile's first two rows are read before the partials are reduced, so
+    // their latency overlaps the reduction (a wavefront without a tile reads
+    // tile 0's and drops them); nothing is stored once the solve is done
     const int32_t done = sc->done;
     const TileLane L = tile_lane(t);
-    const int tid0 = first_tile(t, L);
+    const V* __restrict__ dinv = tdinv<V>(t);
+    int x0, y0;
+    tile_origin_of(t, first_tile(t, L), &x0, &y0);
+    int xc = x0 - 2 + L.lane;
+    bool xin = xc >= 0 && xc < t.nx;
+    bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
+    // one row of a lane: aggregate, 1 / d, r; LW: weight, d
+    struct Row { int32_t g; V iv, w, d; double r; };
+    auto row = [&](int j, Row& R) {
+        const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
+        const bool mid = ok && j >= y0 - 1 && j <= y0 + TY;
+        const uint32_t pn = xc + t.sy * j;
+        R.g = ldz(agg, ok, pn, -1);
+        if constexpr (B16) R.iv = (V)bf16_to_f32(ldz(t.dinv16, mid, pn));
+        else R.iv = ldz(dinv, mid, pn);
+        R.r = ldz(r, mid, pn);
+        R.w = LW ? ldz(twf<V>(t), mid, pn) : V(0);
+        R.d = LW ? ldz(tdiag<V>(t), mid, pn) : V(0);
+    };
+    // e_c at a node's aggregate (0 where it has none)
+    auto gather = [&](int32_t g) { return ldz(ec, g >= 0, (uint32_t)g); };
+    Row R0, R1;                          // rows j, j + 1 (read ahead)
+    row(y0 - 2, R0);
+    row(y0 - 1, R1);
     if (part_rr) {
         const double rr = block_total<TNT>(part_rr, np);
         if (done || converged_or_failed_total(rr, sc)) return;
     } else if (done) {
         return;
     }
-    const V* __restrict__ dinv = tdinv<V>(t);
     const V wV = (V)omega, sV = (V)t.s, swV = (V)(omega * t.s);
     double part = 0.0;
     for (int64_t ti = L.t0; ti < L.t1; ++ti) {
-        int x0, y0;
-        tile_origin_of(t, ti == L.t0 ? tid0 : t.tiles[ti], &x0, &y0);
-        const int xc = x0 - 2 + L.lane;
-        const bool xin = xc >= 0 && xc < t.nx;
-        const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
-        // one row of a lane: aggregate, 1 / d, r; LW: weight, d
-        struct Row { int32_t g; V iv, w, d; double r; };
-        auto row = [&](int j, Row& R) {
-            const bool ok = xin && j >= 0 && j < t.ny && j <= y0 + TY + 1;
-            const bool mid = ok && j >= y0 - 1 && j <= y0 + TY;
-            const uint32_t pn = xc + t.sy * j;
-            R.g = ldz(agg, ok, pn, -1);
-            if constexpr (B16) R.iv = (V)bf16_to_f32(ldz(t.dinv16, mid, pn));
-            else R.iv = ldz(dinv, mid, pn);
-            R.r = ldz(r, mid, pn);
-            R.w = LW ? ldz(twf<V>(t), mid, pn) : V(0);
-            R.d = LW ? ldz(tdiag<V>(t), mid, pn) : V(0);
-        };
-        // e_c at a node's aggregate (0 where it has none)
-        auto gather = [&](int32_t g) { return ldz(ec, g >= 0, (uint32_t)g); };
-        Row R0, R1;                          // rows j, j + 1 (read ahead)
-        row(y0 - 2, R0);
-        row(y0 - 1, R1);
+        if (ti > L.t0) {
+            tile_origin(t, ti, &x0, &y0);
+            xc = x0 - 2 + L.lane;
+            xin = xc >= 0 && xc < t.nx;
+            inner = xin && L.lane >= 2 && L.lane < 2 + TX;
+            row(y0 - 2, R0);
+            row(y0 - 1, R1);
+        }
         V t0v = gather(R0.g);                // gathered a row ahead
         // rolling rows: t (j-2, j-1), zt (j-3, j-2), 1 / d and r and LW
         // weights of rows j-2, j-1

@@ -1486,21 +1486,30 @@ struct RowSrc {
     __device__ int32_t len(int64_t r) const { return rowptr ? rowptr[r + 1] - rowptr[r] : cnt[r]; }
 };
 
-// The longest row (*width pre-set to 0): each wavefront's maximum, then one
-// atomic per wavefront.
-__global__ void __launch_bounds__(BLOCK) k_sell_width(RowSrc M, int64_t n, int32_t* __restrict__ width) {
+// The longest row of each of three matrices with the same rows (width[0..2]
+// pre-set to 0): each wavefront's maxima, then an atomic only where a
+// maximum exceeds the width already recorded (rows of a level are nearly
+// uniform, so after the first wavefronts hardly any atomic is left: one
+// address taking an atomic from every wavefront serialises them).
+__global__ void __launch_bounds__(BLOCK) k_sell_width3(RowSrc A, RowSrc B, RowSrc C, int64_t n,
+                                                       int32_t* __restrict__ width) {
     const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    int32_t w = r < n ? M.len(r) : 0;
+    int32_t w[3] = {r < n ? A.len(r) : 0, r < n ? B.len(r) : 0, r < n ? C.len(r) : 0};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, WAVE));
-    if ((threadIdx.x & (WAVE - 1)) == 0 && w > 0) atomicMax(width, w);
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w[m] = max(w[m], __shfl_xor(w[m], off, WAVE));
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            if (w[m] > __atomic_load_n(&width[m], __ATOMIC_RELAXED)) atomicMax(&width[m], w[m]);
+    }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_sell_fill(RowSrc M, int64_t n, const int32_t* __restrict__ width,
-                                                     int32_t* __restrict__ col, double* __restrict__ val) {
-    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= n) return;
-    const int32_t w = *width;
+// Row r of a sliced matrix of width w from its source rows (padding: value 0
+// and the row's last column, column 0 for an empty row).
+__device__ inline void sell_fill_row(const RowSrc& M, int64_t r, int32_t w, int32_t* __restrict__ col,
+                                     double* __restrict__ val) {
     const int32_t base = (int32_t)(r / 64) * 64 * w + (int32_t)(r % 64);
     const int32_t f = M.first(r), m = M.len(r);
     int32_t last = 0;
@@ -1514,6 +1523,19 @@ __global__ void __launch_bounds__(BLOCK) k_sell_fill(RowSrc M, int64_t n, const 
             val[base + 64 * k] = 0.0;
         }
     }
+}
+
+// The three sliced matrices of a level in one pass over its rows.
+__global__ void __launch_bounds__(BLOCK) k_sell_fill3(RowSrc A, RowSrc B, RowSrc C, int64_t n,
+                                                      const int32_t* __restrict__ width, int32_t* __restrict__ ca,
+                                                      double* __restrict__ va, int32_t* __restrict__ cb,
+                                                      double* __restrict__ vb, int32_t* __restrict__ cc,
+                                                      double* __restrict__ vc) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= n) return;
+    sell_fill_row(A, r, width[0], ca, va);
+    sell_fill_row(B, r, width[1], cb, vb);
+    sell_fill_row(C, r, width[2], cc, vc);
 }
 
 // Transpose of a matrix given by rows (CSR or packed), into CSR: counts per
@@ -1539,29 +1561,80 @@ __global__ void __launch_bounds__(BLOCK) k_trs_fill(RowSrc M, int64_t n, const i
     }
 }
 
-// Sliced ELL copy of an n-row matrix whose rows have at most `bound` entries
-// (storage sized by the bound, the width found on the device: no host
-// synchronisation; the host learns the width from the setup's final report).
-static int build_sell(const RowSrc& M, int64_t n, int64_t bound, Sell* out, hipStream_t s) {
+// Sliced ELL copies of the level's A, P and A P (n rows each, at most
+// bound[m] entries per row): storage sized by the bounds, the widths found
+// on the device (no host synchronisation; the host learns them from the
+// setup's final report).  Three launches for the three matrices.
+static int build_sells(Level& L, const RowSrc (&M)[3], int64_t n, const int64_t (&bound)[3], hipStream_t s) {
+    Sell* out[3] = {&L.sa, &L.sp, &L.sap};
     const int64_t nslices = (n + 63) / 64;
-    out->cap = nslices * 64 * (bound > 0 ? bound : 1);
-    if (out->cap >= ((int64_t)1 << 31)) {
-        set_error("a sliced matrix bound exceeds 2^31 entries");
-        return EB_ENOSPC;
+    EB_TRY(dalloc_n(&L.sell_w, 4, s));
+    for (int m = 0; m < 3; ++m) {
+        out[m]->cap = nslices * 64 * (bound[m] > 0 ? bound[m] : 1);
+        if (out[m]->cap >= ((int64_t)1 << 31)) {
+            set_error("a sliced matrix bound exceeds 2^31 entries");
+            return EB_ENOSPC;
+        }
+        out[m]->wdev = L.sell_w + m;
+        EB_TRY(dalloc_n(&out[m]->col, out[m]->cap, s));
+        EB_TRY(dalloc_n(&out[m]->val, out[m]->cap, s));
     }
-    EB_TRY(dalloc_n(&out->wdev, 1, s));
-    EB_TRY(dalloc_n(&out->col, out->cap, s));
-    EB_TRY(dalloc_n(&out->val, out->cap, s));
     {
-        const FillSpec f[] = {{out->wdev, sizeof(int32_t), 0u}};
+        const FillSpec f[] = {{L.sell_w, 4 * sizeof(int32_t), 0u}};
         EB_TRY(fill_words(f, 1, s));
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_sell_width, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, out->wdev);
-        hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, M, n, (const int32_t*)out->wdev,
-                           out->col, out->val);
+        hipLaunchKernelGGL(k_sell_width3, dim3(grid_for(n)), dim3(BLOCK), 0, s, M[0], M[1], M[2], n, L.sell_w);
+        hipLaunchKernelGGL(k_sell_fill3, dim3(grid_for(n)), dim3(BLOCK), 0, s, M[0], M[1], M[2], n,
+                           (const int32_t*)L.sell_w, L.sa.col, L.sa.val, L.sp.col, L.sp.val, L.sap.col, L.sap.val);
         EB_LAUNCH_CHECK();
     }
+    return EB_OK;
+}
+
+// V-cycle copies of level l >= 1 (not the coarsest): sliced A, P and A P for
+// the up pass and R A for the down pass, from the A P kept by build_next.
+// They feed neither the coarsening nor the coarsest inverse, so setup builds
+// them after launching that inverse on the side stream, where they overlap it.
+static int build_cycle_copies(amg_handle* H, int l, hipStream_t s) {
+    Level& L = H->lev[l];
+    if (!L.apk_col) return EB_OK;
+    const int64_t n = L.n, nc = H->lev[l + 1].n;
+    const int slots = L.apk_slots;
+    RowSrc map = {nullptr, L.apk_start, L.apk_cnt, L.apk_col, L.apk_val};
+    // sliced copies of A, P and A P for the coarse V-cycle kernels
+    const RowSrc ms[3] = {{L.a_rowptr, nullptr, nullptr, L.a_col, L.a_val},
+                          {L.p_rowptr, nullptr, nullptr, L.p_col, L.p_val}, map};
+    const int64_t bounds[3] = {L.row_bound, L.apk_pbound, slots};
+    EB_TRY(build_sells(L, ms, n, bounds, s));
+    // R A = P^T A = (A P)^T (A symmetric): rows of level l + 1 over level-l
+    // columns, sorted, for the one-pass residual and restriction
+    L.ra_cap = n * slots;
+    int32_t* tcnt = nullptr;
+    int32_t* tfill = nullptr;
+    EB_TRY(dalloc_n(&tcnt, nc, s));
+    EB_TRY(dalloc_n(&tfill, nc, s));
+    {
+        const FillSpec f[] = {{tcnt, sizeof(int32_t) * nc, 0u}, {tfill, sizeof(int32_t) * nc, 0u}};
+        EB_TRY(fill_words(f, 2, s));
+    }
+    hipLaunchKernelGGL(k_trs_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, tcnt);
+    EB_LAUNCH_CHECK();
+    EB_TRY(rowptr_from_counts(tcnt, nc, &L.ra_rowptr, s));
+    EB_TRY(dalloc_n(&L.ra_col, L.ra_cap, s));
+    EB_TRY(dalloc_n(&L.ra_val, L.ra_cap, s));
+    hipLaunchKernelGGL(k_trs_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, (const int32_t*)L.ra_rowptr,
+                       tfill, L.ra_col, L.ra_val);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sort_rows<BLOCK, 2048>), dim3((unsigned)nc), dim3(BLOCK), 0, s,
+                       (const int32_t*)L.ra_rowptr, L.ra_col, L.ra_val, nc);
+    EB_LAUNCH_CHECK();
+    EB_TRY(dfree(tcnt, s));
+    EB_TRY(dfree(tfill, s));
+    void* q[] = {L.apk_cnt, L.apk_start, L.apk_col, L.apk_val};
+    for (void* p : q) EB_TRY(dfree(p, s));
+    L.apk_cnt = L.apk_start = L.apk_col = nullptr;
+    L.apk_val = nullptr;
     return EB_OK;
 }
 
@@ -1824,40 +1897,17 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, const
     EB_TRY(accumulate_product(ACC_RAP, args, nc, slots, &C.a_rowptr, &C.a_col, &C.a_val, s));
     C.row_bound = slots;
     if (l >= 1) {
-        // sliced copies of A, P and A P for the coarse V-cycle kernels
-        RowSrc ma = {L.a_rowptr, nullptr, nullptr, L.a_col, L.a_val};
-        RowSrc mp = {L.p_rowptr, nullptr, nullptr, L.p_col, L.p_val};
-        RowSrc map = {nullptr, ap.start, ap.cnt, ap.col, ap.val};
-        EB_TRY(build_sell(ma, n, L.row_bound, &L.sa, s));
-        EB_TRY(build_sell(mp, n, p_bound, &L.sp, s));
-        EB_TRY(build_sell(map, n, slots, &L.sap, s));
-        // R A = P^T A = (A P)^T (A symmetric): rows of level l + 1 over level-l
-        // columns, sorted, for the one-pass residual and restriction
-        L.ra_cap = n * slots;
-        int32_t* tcnt = nullptr;
-        int32_t* tfill = nullptr;
-        EB_TRY(dalloc_n(&tcnt, nc, s));
-        EB_TRY(dalloc_n(&tfill, nc, s));
-        {
-            const FillSpec f[] = {{tcnt, sizeof(int32_t) * nc, 0u}, {tfill, sizeof(int32_t) * nc, 0u}};
-            EB_TRY(fill_words(f, 2, s));
-        }
-        hipLaunchKernelGGL(k_trs_count, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, tcnt);
-        EB_LAUNCH_CHECK();
-        EB_TRY(rowptr_from_counts(tcnt, nc, &L.ra_rowptr, s));
-        EB_TRY(dalloc_n(&L.ra_col, L.ra_cap, s));
-        EB_TRY(dalloc_n(&L.ra_val, L.ra_cap, s));
-        hipLaunchKernelGGL(k_trs_fill, dim3(grid_for(n)), dim3(BLOCK), 0, s, map, n, (const int32_t*)L.ra_rowptr,
-                           tfill, L.ra_col, L.ra_val);
-        EB_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sort_rows<BLOCK, 2048>), dim3((unsigned)nc), dim3(BLOCK), 0, s,
-                           (const int32_t*)L.ra_rowptr, L.ra_col,
-                           L.ra_val, nc);
-        EB_LAUNCH_CHECK();
-        EB_TRY(dfree(tcnt, s));
-        EB_TRY(dfree(tfill, s));
+        // kept for the V-cycle copies, built once the coarsest inverse runs
+        L.apk_cnt = ap.cnt;
+        L.apk_start = ap.start;
+        L.apk_col = ap.col;
+        L.apk_val = ap.val;
+        L.apk_slots = slots;
+        L.apk_pbound = p_bound;
+        ap = PackedRows();
+    } else {
+        EB_TRY(free_packed(ap, s));
     }
-    EB_TRY(free_packed(ap, s));
     EB_TRY(dalloc_n(&C.diag, nc, s));
     hipLaunchKernelGGL(k_extract_diag, dim3(grid_for(nc)), dim3(BLOCK), 0, s, C.a_rowptr, C.a_col, C.a_val, nc,
                        C.diag, err);
@@ -1868,11 +1918,11 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, const
 static void free_level(Level& L, hipStream_t s) {
     void* ptrs[] = {L.a_rowptr, L.a_col, L.a_val, L.diag, L.p_rowptr, L.p_col, L.p_val, L.r_rowptr, L.r_col,
                     L.r_val, L.agg, L.coords, L.cinfo, L.box_cstart, L.box_ncomp, L.dense_inv, L.fz_off, L.fz_woff,
-                    L.fz_inv, L.fz_blk, L.rv, L.ev, L.tmp,
+                    L.fz_inv, L.fz_blk, L.sell_w, L.apk_cnt, L.apk_start, L.apk_col, L.apk_val, L.rv, L.ev, L.tmp,
                     L.sv, L.a_val32, L.p_val32, L.r_val32, L.diag32, L.rv32, L.ev32, L.tmp32, L.sv32};
     for (void* p : ptrs) (void)dfree(p, s);
     for (Sell* m : {&L.sa, &L.sp, &L.sap}) {
-        void* q[] = {m->wdev, m->col, m->val, m->val32};
+        void* q[] = {m->col, m->val, m->val32};
         for (void* p : q) (void)dfree(p, s);
     }
     {
@@ -2114,6 +2164,9 @@ static int setup_impl(amg_handle* H, const int8_t* kind, const double* a, hipStr
         ++l;
     }
     H->nlev = l + 1;
+    // V-cycle copies of the middle levels: after the coarsest inverse was
+    // launched on the side stream, so that they run beside it
+    for (int k = 1; k < H->nlev - 1; ++k) EB_TRY(build_cycle_copies(H, k, s));
     EB_TRY(solve_layout_alloc(H, s));
     if (H->join_pending) {      // the coarsest inverse (side stream)
         EB_HIP(hipStreamWaitEvent(s, H->ev_join, 0));

@@ -17,7 +17,7 @@ constexpr int MAX_LEVELS = 24;
 // On the coarse levels of the box aggregation the widths are nearly uniform
 // (2-D: A 9, P 4, A P 9 on most rows).
 struct Sell {
-    int32_t* wdev = nullptr;   // w on the device (set by the setup kernels)
+    int32_t* wdev = nullptr;   // w on the device (set by the setup kernels; in the level's sell_w)
     int32_t* col = nullptr;
     double* val = nullptr;
     float* val32 = nullptr;    // single-precision V-cycle copy (made on first use)
@@ -60,6 +60,15 @@ struct Level {
     // sliced ELL copies of A, P and A P for the V-cycle (levels >= 1 with a
     // coarser level), and R A = (A P)^T in CSR (rows sorted)
     Sell sa, sp, sap;
+    int32_t* sell_w = nullptr;   // widths of sa, sp, sap on the device (one allocation)
+    // the packed A P of the Galerkin step, kept until the V-cycle copies
+    // (sliced A, P, A P and R A) are built at the end of setup
+    int32_t* apk_cnt = nullptr;
+    int32_t* apk_start = nullptr;
+    int32_t* apk_col = nullptr;
+    double* apk_val = nullptr;
+    int apk_slots = 0;
+    int64_t apk_pbound = 0;
     int32_t* ra_rowptr = nullptr; int32_t* ra_col = nullptr; double* ra_val = nullptr; float* ra_val32 = nullptr;
     int64_t ra_cap = 0;
     // solve vectors (levels >= 1); sv = omega rv / diag, written with rv by the

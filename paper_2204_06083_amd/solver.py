@@ -45,12 +45,13 @@ class Assembly:
         return raw.view(L.CUT_DTYPE)
 
     def cut_coordinates(self):
-        """Crossing coordinates as device tensors (x, y[, z]) in record order."""
+        """Crossing coordinates as device tensors (x, y[, z]) in record order:
+        strided views into the records (no copy; read them, do not write)."""
         if self.n_cuts == 0:
             z = torch.zeros(0, dtype=torch.float64, device=self.kind.device)
             return tuple(z for _ in range(self.grid.dim))
         rec = self.cuts[: self.n_cuts * 56].view(torch.float64).view(self.n_cuts, 7)
-        return tuple(rec[:, 4 + p].contiguous() for p in range(self.grid.dim))
+        return tuple(rec[:, 4 + p] for p in range(self.grid.dim))
 
 
 def assemble_diag(grid, psi: torch.Tensor, cuts_cap: Optional[int] = None, mode: str = "line",

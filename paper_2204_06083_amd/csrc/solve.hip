@@ -270,10 +270,11 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_p_spmv(FineArgs f, const V* __res
                                                    double* __restrict__ q, const double* __restrict__ rz_cur,
                                                    const double* __restrict__ rz_prev, int np,
                                                    double* __restrict__ part_pq, PcgScalars* sc) {
-    if (sc->done) return;
+    const int32_t done = sc->done;   // read with the partials; nothing is stored once done
     double rho, rho_prev = 0.0;
     if (rz_prev) block_total2(rz_cur, rz_prev, np, &rho, &rho_prev);
     else rho = block_total(rz_cur, np);
+    if (done) return;
     const double beta = rz_prev ? rho / rho_prev : 0.0;
     if (!(rho > 0.0) || bad_value(rho) || bad_value(beta)) {
         if (lead()) {
@@ -384,8 +385,13 @@ template <class V, bool LW, bool VB = false>
 __global__ void __launch_bounds__(NT) k_fine_down(FineArgs f, double omega, const double* __restrict__ r,
                                                   V* __restrict__ res, PcgScalars* sc, int check,
                                                   const double* __restrict__ part_rr, int np) {
-    if (sc->done) return;
-    if (check && converged_or_failed(part_rr, np, sc)) return;
+    const int32_t done = sc->done;   // read with the partials; nothing is stored once done
+    if (check) {
+        const double rr = block_total(part_rr, np);
+        if (done || converged_or_failed_total(rr, sc)) return;
+    } else if (done) {
+        return;
+    }
     FINE_LOOP(f, p) {
         const double d = f.diag[p];
         if (d != 0.0) {
@@ -489,8 +495,13 @@ __global__ void __launch_bounds__(RNT) k_fine_restrict(FineArgs f, BoxArgs b, do
                                                       const V* __restrict__ dg_c, double omega_c,
                                                       V* __restrict__ sv_c, PcgScalars* sc, int check,
                                                       const double* __restrict__ part_rr, int np) {
-    if (sc->done) return;
-    if (check && converged_or_failed<RNT>(part_rr, np, sc)) return;
+    const int32_t done = sc->done;   // read with the partials; nothing is stored once done
+    if (check) {
+        const double rr = block_total<RNT>(part_rr, np);
+        if (done || converged_or_failed_total(rr, sc)) return;
+    } else if (done) {
+        return;
+    }
     const V* __restrict__ dg = vdiag<V>(f);
     const V omega = (V)omega_d;
     const V sh = (V)f.s;
@@ -574,9 +585,10 @@ __global__ void __launch_bounds__(NT, 8) k_pcg_xr_down(FineArgs f, double* __res
                                                     double omega, const double* __restrict__ rz_cur,
                                                     const double* __restrict__ part_pq, int np,
                                                     double* __restrict__ part_rr, PcgScalars* sc) {
-    if (sc->done) return;
+    const int32_t done = sc->done;   // read with the partials; nothing is stored once done
     double rho, pq;
     block_total2(rz_cur, part_pq, np, &rho, &pq);
+    if (done) return;
     if (!(pq > 0.0) || bad_value(pq)) {
         if (lead()) {
             sc->status = bad_value(pq) ? EB_ENAN : EB_ENOTSPD;

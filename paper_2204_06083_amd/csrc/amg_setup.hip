@@ -510,6 +510,7 @@ struct SlotMap {
 };
 
 enum { ACC_P = 0, ACC_AP = 1, ACC_RAP = 2 };
+constexpr int ACC_XB = 4;   // first-operand entries a lane reads at once
 
 struct AccArgs {
     SlotMap sm;
@@ -581,27 +582,71 @@ __global__ void k_accumulate(AccArgs A, int G) {
                     v[s0] = 1.0;
                 }
             }
-            for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
-                const int j = A.x_col[e];
-                if (A.agg[j] < 0) continue;   // never: no edge joins two islands
-                const int sl = A.sm.slot(A.agg[j], bx, by, bz);
-                if (sl < 0) { bad = true; continue; }
-                fl[sl] = 1;
-                const double w = omega * (A.x_val[e] / dii);
-                v[sl] = v[sl] - w;
-            }
-        } else {
-            for (int e = A.x_rowptr[row] + g; e < A.x_rowptr[row + 1]; e += G) {
-                const int k = A.x_col[e];
-                const double xv = A.x_val[e];
-                const int f0 = A.y_start ? A.y_start[k] : A.y_rowptr[k];
-                const int f1 = A.y_start ? f0 + A.y_cnt[k] : A.y_rowptr[k + 1];
-                for (int f = f0; f < f1; ++f) {
-                    const int sl = A.sm.slot(A.y_col[f], bx, by, bz);
+            // entries in groups of ACC_XB: columns and values, then their
+            // aggregates, read a group at a time; added in entry order
+            const int e0 = A.x_rowptr[row] + g, e1 = A.x_rowptr[row + 1];
+            for (int eb = e0; eb < e1; eb += G * ACC_XB) {
+                int gs[ACC_XB];
+                double xvs[ACC_XB];
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    const int e = eb + u * G;
+                    const int ei = e < e1 ? e : 0;
+                    const int j = A.x_col[ei];
+                    xvs[u] = A.x_val[ei];
+                    gs[u] = j;
+                }
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    const int a = A.agg[gs[u]];
+                    gs[u] = eb + u * G < e1 ? a : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    if (gs[u] < 0) continue;   // past the row; or never: no edge joins two islands
+                    const int sl = A.sm.slot(gs[u], bx, by, bz);
                     if (sl < 0) { bad = true; continue; }
                     fl[sl] = 1;
-                    const double pr = xv * A.y_val[f];
-                    v[sl] = v[sl] + pr;
+                    const double w = omega * (xvs[u] / dii);
+                    v[sl] = v[sl] - w;
+                }
+            }
+        } else {
+            // the lane's first-operand entries in groups of ACC_XB: their
+            // columns and values, then the extents of the second operand's
+            // rows they select, are read a group at a time (two round trips
+            // per group instead of two per entry); the products are then
+            // added in entry order, as one entry at a time would add them.
+            // A slot past the row reads entry 0 / row 0 and is not used.
+            const int e0 = A.x_rowptr[row] + g, e1 = A.x_rowptr[row + 1];
+            for (int eb = e0; eb < e1; eb += G * ACC_XB) {
+                int ks[ACC_XB], f0s[ACC_XB], f1s[ACC_XB];
+                double xvs[ACC_XB];
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    const int e = eb + u * G;
+                    const int ei = e < e1 ? e : 0;
+                    ks[u] = A.x_col[ei];
+                    xvs[u] = A.x_val[ei];
+                }
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    const int k = eb + u * G < e1 ? ks[u] : 0;
+                    const int a = A.y_start ? A.y_start[k] : A.y_rowptr[k];
+                    const int b = A.y_start ? a + A.y_cnt[k] : A.y_rowptr[k + 1];
+                    f0s[u] = a;
+                    f1s[u] = eb + u * G < e1 ? b : a;
+                }
+#pragma unroll
+                for (int u = 0; u < ACC_XB; ++u) {
+                    const double xv = xvs[u];
+                    for (int f = f0s[u]; f < f1s[u]; ++f) {
+                        const int sl = A.sm.slot(A.y_col[f], bx, by, bz);
+                        if (sl < 0) { bad = true; continue; }
+                        fl[sl] = 1;
+                        const double pr = xv * A.y_val[f];
+                        v[sl] = v[sl] + pr;
+                    }
                 }
             }
         }

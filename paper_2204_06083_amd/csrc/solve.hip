@@ -855,6 +855,12 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
     double dq[T2_AHEAD], zq[T2_AHEAD], oq[T2_AHEAD];
 #pragma unroll
     for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 1 + k, dq[k], zq[k], oq[k]);
+    // the tile's last row and its halo row below are the first rows of the
+    // tile below, which reads them at its start: read here at the start too
+    // (so the second read finds them in L2) and taken by the march from here
+    double dt[2], zt2[2], ot[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) row(y0 + TY - 1 + k, dt[k], zt2[k], ot[k]);
     double rho, rho_prev = 0.0;
     if (rz_prev) block_total2<TNT>(rz_cur, rz_prev, np, &rho, &rho_prev);
     else rho = block_total<TNT>(rz_cur, np);
@@ -875,6 +881,8 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
             xin = xc >= 0 && xc < t.nx;
 #pragma unroll
             for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 1 + k, dq[k], zq[k], oq[k]);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) row(y0 + TY - 1 + k, dt[k], zt2[k], ot[k]);
         }
         const bool inner = xin && L.lane >= 2 && L.lane < 2 + TX;
         double pa = 0.0, pb = 0.0, da = 0.0;   // p of rows j - 2, j - 1; d of row j - 1
@@ -884,7 +892,16 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
         for (int jj = 0; jj < TY + 2; ++jj) {
             const int j = y0 - 1 + jj;
             double dn, zn, on;
-            row(j + T2_AHEAD, dn, zn, on);
+            // row y0 - 1 + jj + T2_AHEAD: one of the last two (read at the
+            // start) or a row of the march (jj is a compile-time constant)
+            const int ahead = jj - 1 + T2_AHEAD;
+            if (ahead >= TY - 1 && ahead <= TY) {
+                dn = dt[ahead - (TY - 1)];
+                zn = zt2[ahead - (TY - 1)];
+                on = ot[ahead - (TY - 1)];
+            } else {
+                row(j + T2_AHEAD, dn, zn, on);
+            }
             const double d0 = dq[0];
             const double pc = d0 != 0.0 ? zq[0] + beta * oq[0] : 0.0;
             // row j - 1: q = A p
@@ -978,6 +995,13 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
     Row Rq[T2_AHEAD];                    // rows j .. j + T2_AHEAD - 1 (read ahead)
 #pragma unroll
     for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 2 + k, Rq[k]);
+    // the tile's last two rows and its two halo rows below are the first
+    // rows of the tile below, which reads them at its start: reading them at
+    // the start here too lets the second read find them in L2 (read at the
+    // end of the march, some 15 us later, they were mostly fetched again)
+    Row Rt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) row(y0 + TY - 2 + k, Rt[k]);
     int bm, bc0, bmap;
     V bw0;
     boxrow(y0 / 3, bm, bc0, bmap, bw0);
@@ -1012,6 +1036,8 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
             bx = xc >= 0 ? xc / 3 : 0;
 #pragma unroll
             for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 2 + k, Rq[k]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) row(y0 + TY - 2 + k, Rt[k]);
             boxrow(y0 / 3, bm, bc0, bmap, bw0);
         }
         // rolling rows: z1 (j-2, j-1), r (j-1), 1 / d (j-2, j-1), d (j-1),
@@ -1023,7 +1049,11 @@ __global__ void __launch_bounds__(TNT) k_t2_xr_restrict(TileArgs t, BoxArgs b, d
         for (int jj = 0; jj < TY + 4; ++jj) {
             const int j = y0 - 2 + jj;
             Row Rn;
-            row(j + T2_AHEAD, Rn);
+            // row y0 - 2 + jj + T2_AHEAD: one of the last four (read at the
+            // start) or a row of the march (jj is a compile-time constant)
+            const int ahead = jj - 2 + T2_AHEAD;
+            if (ahead >= TY - 2 && ahead <= TY + 1) Rn = Rt[ahead - (TY - 2)];
+            else row(j + T2_AHEAD, Rn);
             const Row R0 = Rq[0];
             // row j: r, z1 (and the CG update of the tile's own rows)
             double rj = 0.0, zj = 0.0;
@@ -1138,6 +1168,12 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
     Row Rq[T2_AHEAD];                    // rows j .. j + T2_AHEAD - 1 (read ahead)
 #pragma unroll
     for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 2 + k, Rq[k]);
+    // the tile's last two rows and its two halo rows below are the first
+    // rows of the tile below, which reads them at its start: read here at
+    // the start too (so the second read finds them in L2)
+    Row Rt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) row(y0 + TY - 2 + k, Rt[k]);
     if (part_rr) {
         const double rr = block_total<TNT>(part_rr, np);
         if (done || converged_or_failed_total(rr, sc)) return;
@@ -1154,6 +1190,8 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
             inner = xin && L.lane >= 2 && L.lane < 2 + TX;
 #pragma unroll
             for (int k = 0; k < T2_AHEAD; ++k) row(y0 - 2 + k, Rq[k]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) row(y0 + TY - 2 + k, Rt[k]);
         }
         V t0v = gather(Rq[0].g);             // gathered a row ahead
         // rolling rows: t (j-2, j-1), zt (j-3, j-2), 1 / d and r and LW
@@ -1165,7 +1203,11 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
         for (int jj = 0; jj < TY + 4; ++jj) {
             const int j = y0 - 2 + jj;
             Row Rn;
-            row(j + T2_AHEAD, Rn);
+            // row y0 - 2 + jj + T2_AHEAD: one of the last four (read at the
+            // start) or a row of the march (jj is a compile-time constant)
+            const int ahead = jj - 2 + T2_AHEAD;
+            if (ahead >= TY - 2 && ahead <= TY + 1) Rn = Rt[ahead - (TY - 2)];
+            else row(j + T2_AHEAD, Rn);
             const Row R0 = Rq[0];
             const V t1v = gather(Rq[1].g);
             // row j - 1: zt

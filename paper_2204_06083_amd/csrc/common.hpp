@@ -77,6 +77,10 @@ constexpr int BLOCK = 256;
 // the stencil kernels read from adjacent strips, inside one L2.
 constexpr int NUM_XCD = 8;
 
+// A grid rounded up to whole groups of NUM_XCD blocks, so that xcd_block()
+// applies (the extra blocks find no row and return).
+inline unsigned xcd_grid(unsigned g) { return (g + NUM_XCD - 1) / NUM_XCD * NUM_XCD; }
+
 __device__ inline int64_t xcd_block() {
     const int64_t per = gridDim.x / NUM_XCD;
     if (per == 0 || (gridDim.x % NUM_XCD) != 0) return blockIdx.x;

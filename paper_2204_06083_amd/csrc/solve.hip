@@ -1475,7 +1475,9 @@ __global__ void __launch_bounds__(NT) k_down_ra(int64_t nc, Csr<V> R, Csr<V> RA,
                                                 const V* __restrict__ dg_c, V omega_c, V* __restrict__ sv_c,
                                                 const PcgScalars* sc) {
     const int32_t done = sc->done;   // read beside the row pointers; tested before the stores
-    const int64_t row = ((int64_t)blockIdx.x * NT + threadIdx.x) / LPR;
+    // consecutive rows on one XCD (grid a multiple of 8): neighbouring coarse
+    // rows gather overlapping fine entries, which then come from one L2
+    const int64_t row = (xcd_block() * NT + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
     if (row >= nc) return;
     constexpr int UR = 2, UQ = 2;
@@ -1604,8 +1606,8 @@ __global__ void __launch_bounds__(NT) k_sell_up(int64_t n, SellV<V> A, SellV<V> 
                                                 const V* __restrict__ diag, V omega, const V* __restrict__ rv,
                                                 const V* __restrict__ sv, const V* __restrict__ ev_c,
                                                 V* __restrict__ ev, const PcgScalars* sc) {
-    const int32_t done = sc->done;   // read beside the slice pointers; tested before the store
-    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int32_t done = sc->done;   // read beside the first reads; tested before the store
+    const int64_t row = xcd_block() * NT + threadIdx.x;   // consecutive rows on one XCD
     const int slice = __builtin_amdgcn_readfirstlane((int)(row >> 6));
     if (row >= n) return;
     const int lane = (int)(row & 63);
@@ -2039,8 +2041,20 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         V* svc = l + 1 < H->nlev - 1 ? Cv.sv : nullptr;
         (void)lpr_r;
         const int lpr_d = lanes_for((double)(2 * L.nnz_r) / (double)(C.n > 0 ? C.n : 1));
-        EB_LPR_LAUNCH(k_down_ra, V, lpr_d, C.n, C.n, Lv.R, Lv.RA, (const V*)Lv.rv, (const V*)Lv.sv, Cv.rv,
-                      (const V*)Cv.diag, wc, svc, sc);
+        {
+            const unsigned g_ = xcd_grid(grid_for(C.n * (int64_t)lpr_d, NT));
+            const dim3 gd(g_), bd(NT);
+            switch (lpr_d) {
+                case 4: hipLaunchKernelGGL((k_down_ra<4, V>), gd, bd, 0, s, C.n, Lv.R, Lv.RA, (const V*)Lv.rv,
+                                           (const V*)Lv.sv, Cv.rv, (const V*)Cv.diag, wc, svc, sc); break;
+                case 8: hipLaunchKernelGGL((k_down_ra<8, V>), gd, bd, 0, s, C.n, Lv.R, Lv.RA, (const V*)Lv.rv,
+                                           (const V*)Lv.sv, Cv.rv, (const V*)Cv.diag, wc, svc, sc); break;
+                case 16: hipLaunchKernelGGL((k_down_ra<16, V>), gd, bd, 0, s, C.n, Lv.R, Lv.RA, (const V*)Lv.rv,
+                                            (const V*)Lv.sv, Cv.rv, (const V*)Cv.diag, wc, svc, sc); break;
+                default: hipLaunchKernelGGL((k_down_ra<32, V>), gd, bd, 0, s, C.n, Lv.R, Lv.RA, (const V*)Lv.rv,
+                                            (const V*)Lv.sv, Cv.rv, (const V*)Cv.diag, wc, svc, sc); break;
+            }
+        }
     }
     {
         const Level& Lc = H->lev[H->nlev - 1];
@@ -2058,11 +2072,11 @@ static int enqueue_coarse(amg_handle* H, hipStream_t s) {
         const Level& C = H->lev[l + 1];
         const LevelView<V> Lv = view<V>(L), Cv = view<V>(C);
         if (H->d.dim == 2)
-            hipLaunchKernelGGL((k_sell_up<V, 4, 9>), dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
+            hipLaunchKernelGGL((k_sell_up<V, 4, 9>), dim3(xcd_grid(grid_for(L.n, NT))), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
                                Lv.sap, Lv.diag, (V)L.omega, (const V*)Lv.rv, (const V*)Lv.sv, (const V*)Cv.ev, Lv.ev,
                                sc);
         else
-            hipLaunchKernelGGL((k_sell_up<V, 8, 14>), dim3(grid_for(L.n, NT)), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
+            hipLaunchKernelGGL((k_sell_up<V, 8, 14>), dim3(xcd_grid(grid_for(L.n, NT))), dim3(NT), 0, s, L.n, Lv.sa, Lv.sp,
                                Lv.sap, Lv.diag, (V)L.omega, (const V*)Lv.rv, (const V*)Lv.sv, (const V*)Cv.ev, Lv.ev,
                                sc);
         // islands ending on this level: their exact block solve replaces the

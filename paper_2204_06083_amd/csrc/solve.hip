@@ -1193,7 +1193,10 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) row(y0 + TY - 2 + k, Rt[k]);
         }
-        V t0v = gather(Rq[0].g);             // gathered a row ahead
+        // e_c gathered two rows ahead (the aggregate of row j + 2 was read
+        // one march step earlier, so the gather does not wait for it)
+        V t0v = gather(Rq[0].g);
+        V t1v = gather(Rq[1].g);
         // rolling rows: t (j-2, j-1), zt (j-3, j-2), 1 / d and r and LW
         // weights of rows j-2, j-1
         V ta = V(0), tb = V(0), zta = V(0), ztb = V(0);
@@ -1209,7 +1212,7 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
             if (ahead >= TY - 2 && ahead <= TY + 1) Rn = Rt[ahead - (TY - 2)];
             else row(j + T2_AHEAD, Rn);
             const Row R0 = Rq[0];
-            const V t1v = gather(Rq[1].g);
+            const V t2v = gather(Rq[2].g);
             // row j - 1: zt
             const V tlr = from_left(tb) + from_right(tb);
             V ztc = V(0);
@@ -1239,6 +1242,7 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
             wa = wb; wb = R0.w;
             da = db; db = R0.d;
             t0v = t1v;
+            t1v = t2v;
 #pragma unroll
             for (int k = 0; k + 1 < T2_AHEAD; ++k) Rq[k] = Rq[k + 1];
             Rq[T2_AHEAD - 1] = Rn;

@@ -1407,6 +1407,45 @@ struct SetupStat {
     int32_t pad;
 };
 
+// Pinned host copy of the status words for reads that let the device go on
+// working (one per host thread, kept until the process ends); null if pinned
+// memory cannot be had, and the plain read is used.
+static SetupStat* pinned_stat() {
+    thread_local SetupStat* p = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void**)&p, sizeof(SetupStat), hipHostMallocPortable) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+    }
+    return p;
+}
+
+static int read_stat(const int32_t* dstat, SetupStat* h, hipStream_t s);
+
+// The status read of a level with work enqueued behind it: the words are
+// copied to pinned memory and an event is recorded, then `more` enqueues
+// work that does not depend on them, and the host waits for the event only,
+// so the device has that work to do while the host reads the words and
+// issues the next launches.
+template <class F>
+static int read_stat_then(amg_handle* H, const int32_t* dstat, SetupStat* h, hipStream_t s, F&& more) {
+    SetupStat* ps = pinned_stat();
+    if (!ps) {
+        EB_TRY(more());
+        return read_stat(dstat, h, s);
+    }
+    if (!H->ev_stat) EB_HIP(hipEventCreateWithFlags(&H->ev_stat, hipEventDisableTiming));
+    EB_HIP(hipMemcpyAsync(ps, dstat, sizeof(SetupStat), hipMemcpyDeviceToHost, s));
+    EB_HIP(hipEventRecord(H->ev_stat, s));
+    EB_TRY(more());
+    EB_HIP(hipEventSynchronize(H->ev_stat));
+    *h = *ps;
+    return EB_OK;
+}
+
 static int read_stat(const int32_t* dstat, SetupStat* h, hipStream_t s) {
     EB_HIP(hipMemcpyAsync(h, dstat, sizeof(SetupStat), hipMemcpyDeviceToHost, s));
     EB_HIP(hipStreamSynchronize(s));
@@ -1816,7 +1855,9 @@ static int build_next(amg_handle* H, int l, hipStream_t s, int32_t* dstat, const
     EB_TRY(dfree(members, s));
     EB_TRY(dfree(boxid, s));
     SetupStat st;
-    EB_TRY(read_stat(dstat, &st, s));
+    // the V-cycle copies of the level above (they need this level's size,
+    // not these words) keep the device busy while the host reads them
+    EB_TRY(read_stat_then(H, dstat, &st, s, [&]() { return l >= 2 ? build_cycle_copies(H, l - 1, s) : EB_OK; }));
     EB_TRY(err_code(st.err, "aggregation"));
     const int64_t nc = st.count;
     const int maxc = st.maxv;
@@ -2000,6 +2041,7 @@ int free_handle_memory(amg_handle* H) {
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
     if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    if (H->ev_stat) (void)hipEventDestroy(H->ev_stat);
     H->ev_fork = H->ev_join = nullptr;
     return EB_OK;
 }

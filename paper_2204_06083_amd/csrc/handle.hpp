@@ -189,6 +189,7 @@ struct amg_handle {
     // read-back); join_pending while that work may still be in flight
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join = nullptr;
+    hipEvent_t ev_stat = nullptr;   // setup: the per-level status read has arrived
     int join_pending = 0;
     // kernel timing hook (eb_timing_select / eb_timing_read)
     int tim_kernel = -1;

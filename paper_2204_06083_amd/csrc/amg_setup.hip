@@ -1440,8 +1440,11 @@ static int read_stat_then(amg_handle* H, const int32_t* dstat, SetupStat* h, hip
     if (!H->ev_stat) EB_HIP(hipEventCreateWithFlags(&H->ev_stat, hipEventDisableTiming));
     EB_HIP(hipMemcpyAsync(ps, dstat, sizeof(SetupStat), hipMemcpyDeviceToHost, s));
     EB_HIP(hipEventRecord(H->ev_stat, s));
-    EB_TRY(more());
+    const int rc = more();
+    // wait even when `more` failed: the copy into the shared pinned words
+    // must be complete before they are read or written again
     EB_HIP(hipEventSynchronize(H->ev_stat));
+    if (rc != EB_OK) return rc;
     *h = *ps;
     return EB_OK;
 }

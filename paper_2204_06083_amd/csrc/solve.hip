@@ -835,9 +835,10 @@ __global__ void __launch_bounds__(TNT) k_t2_pspmv(TileArgs t, const V* __restric
                                                   const double* __restrict__ rz_prev, int np,
                                                   double* __restrict__ part_pq, PcgScalars* sc) {
     // the flag and the first tile are read with the partials; the first
-    // tile's first two rows are read before the partials are reduced, so
-    // their latency overlaps the reduction (a wavefront without a tile reads
-    // tile 0's and drops them); nothing is stored once the solve is done
+    // tile's first rows (T2_AHEAD of them) are read before the partials are
+    // reduced, so their latency overlaps the reduction (a wavefront without
+    // a tile reads tile 0's and drops them); nothing is stored once the
+    // solve is done
     const int32_t done = sc->done;
     const TileLane L = tile_lane(t);
     int x0, y0;
@@ -1139,9 +1140,10 @@ __global__ void __launch_bounds__(TNT) k_t2_up_post(TileArgs t, double omega, co
                                                     double* __restrict__ part_rz,
                                                     const double* __restrict__ part_rr, int np, PcgScalars* sc) {
     // the flag and the first tile are read with the partials; the first
-    // tile's first two rows are read before the partials are reduced, so
-    // their latency overlaps the reduction (a wavefront without a tile reads
-    // tile 0's and drops them); nothing is stored once the solve is done
+    // tile's first rows (T2_AHEAD of them) are read before the partials are
+    // reduced, so their latency overlaps the reduction (a wavefront without
+    // a tile reads tile 0's and drops them); nothing is stored once the
+    // solve is done
     const int32_t done = sc->done;
     const TileLane L = tile_lane(t);
     const V* __restrict__ dinv = tdinv<V>(t);

@@ -1721,6 +1721,29 @@ __global__ void __launch_bounds__(NT) k_load_field(int64_t n, const int64_t* __r
     if (k < n) dst[pad[k]] = src[nodes[k]];
 }
 
+// Zero initial guess: b goes into the padded layout twice, as b and as
+// r0 = b - A 0 = b, x is cleared at the unknowns (every store to x is guarded
+// by a non-zero diagonal, so the other slots hold the zero set at setup), and
+// each block of the fixed reduction grid leaves its partial of ||b||^2, which
+// is also ||r0||^2.  One pass over b instead of a load, a clear of all of x
+// and two reductions over the strips.
+__global__ void __launch_bounds__(NT) k_init_zero_guess(int64_t n, const int64_t* __restrict__ nodes,
+                                                        const int32_t* __restrict__ pad,
+                                                        const double* __restrict__ src, double* __restrict__ bvec,
+                                                        double* __restrict__ x, double* __restrict__ r0,
+                                                        double* __restrict__ part) {
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+        const int32_t q = pad[k];
+        const double v = src[nodes[k]];
+        bvec[q] = v;
+        r0[q] = v;
+        x[q] = 0.0;
+        acc += v * v;
+    }
+    block_partial(acc, part);
+}
+
 template <class V>
 __global__ void __launch_bounds__(NT) k_store_field(int64_t n, const int64_t* __restrict__ nodes,
                                                     const int32_t* __restrict__ pad, const V* __restrict__ src,
@@ -2422,6 +2445,17 @@ static int enqueue_init(amg_handle* H, double tol, int iters, hipStream_t s) {
     return EB_OK;
 }
 
+// The same for a zero initial guess, b read from the caller's field: one
+// kernel in place of the load of b, the clear of x and both reductions.
+static int enqueue_init_zero_guess(amg_handle* H, const double* b, int64_t nunk, double tol, hipStream_t s) {
+    const int np = H->red.nparts;
+    hipLaunchKernelGGL(k_init_zero_guess, dim3((unsigned)np), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, b,
+                       H->bvec, H->x, H->rr[0], H->red.aux);
+    hipLaunchKernelGGL(k_finalize_init, dim3(1), dim3(NT), 0, s, H->sc, H->red.aux, H->red.aux, np, tol, 0);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+}
+
 // Fine solve layout, part 1 (no synchronisation): padded fields, active
 // strip and box lists sized by their bounds, vectors and partial buffers.
 int solve_layout_alloc(amg_handle* H, hipStream_t s) {
@@ -3003,20 +3037,19 @@ extern "C" int pcg_solve(amg_handle_t* H, const double* b, double* x, const pcg_
     const FineArgs f = fine_args(H);
     const int np = H->red.nparts;
     const unsigned ug = grid_for(nunk, NT);
-    hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, b, H->bvec);
     if (p.x0_given) {
+        hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, b, H->bvec);
         hipLaunchKernelGGL(k_load_field, dim3(ug), dim3(NT), 0, s, nunk, H->fine_nodes, H->fine_pad, x, H->x);
-    } else {
-        EB_HIP(hipMemsetAsync(H->x, 0, sizeof(double) * H->npad, s));
+        EB_LAUNCH_CHECK();
     }
-    EB_LAUNCH_CHECK();
 
     int restarts = 0;
     int enqueued = 0;
     int iter_base = 0;
     int rc = EB_OK;
     while (true) {
-        EB_TRY(enqueue_init(H, p.tol, iter_base, s));
+        if (!p.x0_given && restarts == 0) EB_TRY(enqueue_init_zero_guess(H, b, nunk, p.tol, s));
+        else EB_TRY(enqueue_init(H, p.tol, iter_base, s));
         // V-cycle 0 -> rz[0]
         if (H->nlev == 1) EB_TRY(enqueue_vcycle_one_level(H, H->rr[0], H->z, H->red.rz[0], 0, s));
         else if (b16) EB_TRY((enqueue_vcycle_any<float, true>(H, H->rr[0], (bf16*)H->z16, H->red.rz[0], s)));

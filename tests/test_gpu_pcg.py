@@ -110,6 +110,33 @@ def test_determinism_and_warm_start():
     H.free()
 
 
+@pytest.mark.parametrize("make", [lambda: W.star_poisson(600), lambda: W.ellipsoid_poisson(40)],
+                         ids=["star600", "ell40"])
+def test_zero_guess_start(make):
+    """Without a guess the solve starts in one kernel from r0 = b; an explicit
+    zero guess takes the general start, r0 = b - A 0, which is b bit for bit.
+    alpha and beta do not depend on ||r||^2, so the iteration count and the
+    solution agree exactly.  A zero right-hand side after a solve returns
+    exactly zero (x is cleared at every unknown, not only where the last
+    iterate was small)."""
+    prob = make()
+    asm_o, A, b_o, u = oracle_system(prob)
+    asm_g, b_g = gpu_system(prob, u)
+    H = S.Hierarchy(prob.grid, asm_g.kind, asm_g.a)
+    print(f"[gpu] zero-guess start {prob.name} grid={prob.grid.shape}", flush=True)
+    H.solve(b_g, tol=1e-8, x0=torch.ones_like(b_g))       # leaves a non-zero iterate behind
+    xa, ia = H.solve(b_g, tol=1e-8)
+    xb, ib = H.solve(b_g, tol=1e-8, x0=torch.zeros_like(b_g))
+    assert ia["iterations"] == ib["iterations"] > 0
+    assert torch.equal(xa, xb)
+    x = xa.cpu().numpy().ravel()[asm_o.nodes]
+    assert np.linalg.norm(b_o - A @ x) <= 1e-8 * np.linalg.norm(b_o) * 1.0001
+    xz, iz = H.solve(torch.zeros_like(b_g), tol=1e-8)
+    assert iz["iterations"] == 0 and iz["status"] == 0
+    assert not torch.any(xz)
+    H.free()
+
+
 def test_error_paths():
     prob = W.star_poisson(256)
     asm_o, A, b_o, u = oracle_system(prob)

@@ -81,7 +81,7 @@ BLOCKS = {}
 MALL_BYTES = 256 << 20   # the MI355X Infinity Cache
 
 
-def survey_model_bytes(H):
+def design_model_bytes(H):
     """Whole-solve bytes per PCG iteration by the design model of the hot-path
     scope table: fine level 40 + 48 + (20 + 8 n1/n0) + (28 + 8 n1/n0) B per
     unknown (p-update + SpMV, x/r update, restriction, prolongation +
@@ -279,11 +279,11 @@ def learned_ellipsoid(n=256, n_train=96, steps=120, reps=3):
            "training": {"grid": f"{n_train}^3", "steps": steps, "seconds": train_s,
                         "loss_first": hist[0], "loss_last5_mean": sum(hist[-5:]) / 5,
                         "level_weight_multipliers": {str(k): v for k, v in gl.items()}}}
-    sm, wset = survey_model_bytes(H), working_set_bytes(H, 3)
+    sm, wset = design_model_bytes(H), working_set_bytes(H, 3)
     for prec in ("fp64", "fp32"):
         r = timed(H, b, prec)
         gbs = sm * r["iterations"] / (r["solve_ms"] * 1e-3) / 1e9
-        r["solve_roofline"] = {"bound": "hbm", "model": "survey", "bytes_per_iter": sm, "achieved": gbs,
+        r["solve_roofline"] = {"bound": "hbm", "model": "design", "bytes_per_iter": sm, "achieved": gbs,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                                "mall_resident": wset < MALL_BYTES, "working_set_bytes": wset}
         out[f"plain_{prec}"] = r
@@ -1017,7 +1017,7 @@ def main():
         byt = kernel_bytes(kname, n0, n1, dim)
         kern[kname] = {"avg_launch_us": avg_us, "launches": nl, "algorithmic_bytes_per_launch": byt,
                        "achieved_GBs": byt / (avg_us * 1e-6) / 1e9}
-    models = {"survey": survey_model_bytes(H),
+    models = {"design": design_model_bytes(H),
               "impl_fp64": impl_model_bytes(H, "fp64", dim), "impl_fp32": impl_model_bytes(H, "fp32", dim),
               "impl_bf16": impl_model_bytes(H, "bf16", dim)}
     wset = working_set_bytes(H, dim)
@@ -1037,11 +1037,11 @@ def main():
         per_s = iters / (solve_ms * 1e-3)
         out_ = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "mall_resident": wset < MALL_BYTES, "working_set_bytes": wset}
-        for key, mkey in (("survey_model", "survey"), ("implementation", impl_key)):
+        for key, mkey in (("design_model", "design"), ("implementation", impl_key)):
             gbs = models[mkey] * per_s / 1e9
             out_[key] = {"bytes_per_iter": models[mkey], "achieved": gbs, "frac": gbs / HBM_PEAK_GBS}
-        out_["frac"] = out_["survey_model"]["frac"]
-        out_["achieved"] = out_["survey_model"]["achieved"]
+        out_["frac"] = out_["design_model"]["frac"]
+        out_["achieved"] = out_["design_model"]["achieved"]
         return out_
 
     ktraffic = load_traffic(dom)
